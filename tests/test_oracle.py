@@ -1,0 +1,394 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test checks the oracle against something other than itself: reference vectors of
+the published RNG, hand-worked fixtures, closed forms of the update, exhaustive
+enumeration, planted optima, library routines for special cases and finite differences.
+"""
+import itertools
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_2501_19221_amd import instances as gen
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rows(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return [ln.split() for ln in f if ln.strip() and not ln.startswith("#")]
+
+
+# ---------------------------------------------------------------- counter RNG / init
+def test_splitmix64_reference_vectors(orc):
+    for seed, k, out in _rows("splitmix64_vectors.txt"):
+        assert orc.sm64_output(int(seed), int(k)) == int(out)
+
+
+def test_init_grid_range_and_subset(orc):
+    n, R, seed, s0 = 37, 9, 12345, 0.1
+    x, m = orc.pa_init(n, R, seed, np.float32(s0))
+    assert np.all(m == 0)
+    # x0 = sigma0 * (2u - 1) with u on the 2^-24 grid: recover the integer draw exactly
+    assert np.all(np.abs(x) <= np.float32(s0))
+    for r, i in [(0, 0), (3, 17), (8, 36)]:
+        top = orc.sm64_output(seed, r * n + i + 1) >> 40
+        v = np.float32(2 * top - 2**24) / np.float32(2**24)   # exact: |2 top - 2^24| <= 2^24
+        assert x[r, i] == np.float32(s0) * v
+    # any replica subset is reproducible on its own
+    xs, _ = orc.pa_init(n, 4, seed, np.float32(s0), r0=5)
+    assert np.array_equal(xs, x[5:9])
+
+
+def test_lambda_linear_exact_for_power_of_two_T(orc):
+    T, lam0 = 64, 3.0
+    lam = orc.lambda_linear(T, lam0)
+    for t in range(T):
+        exact = Fraction(3) * (1 - Fraction(t, T))          # t/T and 1 - t/T exact in FP32
+        assert Fraction(float(lam[t])) == Fraction(float(np.float32(float(exact))))
+    assert lam[0] == np.float32(lam0) and np.all(np.diff(lam) < 0) and lam[-1] > 0
+
+
+# ---------------------------------------------------------------- energies / App. A
+def test_sdk_toy_energies_and_ground_state(orc):
+    inst = gen.sdk_toy()
+    rows = _rows("sdk_toy_energies.txt")
+    for s0, s1, s2, H in rows:
+        s = np.array([int(s0), int(s1), int(s2)], np.int8)
+        assert orc.ising_energy_float(inst.dense, inst.lin, s) == float(H)
+    Es = [float(r[3]) for r in rows]
+    assert min(Es) == -3.5 and Es.count(-3.5) == 1
+
+
+def _all_states(n):
+    return np.array(list(itertools.product([-1, 1], repeat=n)), np.int8)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_app_a_identity_by_enumeration(orc, seed):
+    """2 E(x) = H(s) + K for every x, with x = (1+s)/2; E from x^T Q x + c^T x directly."""
+    inst = gen.dense_int_qubo(n=9, lo=-7, hi=7, seed=seed)
+    J, b, K = orc.qubo_to_ising_int(inst.dense, inst.lin)
+    for s in _all_states(inst.n):
+        x = ((s + 1) // 2).astype(np.int8)
+        E = orc.qubo_energy_int(inst.dense, inst.lin, x)
+        H = orc.ising_energy_int(J, b, s)
+        assert 2 * E == H + K
+
+
+def test_app_a_printed_constant_sign(orc):
+    """App. A with c = 0: h_i = sum_j Q_ij, J = offdiag(Q), C = sum_{i<j} Q_ij + tr Q.
+    Enumeration shows Q(x) = H/2 + C/2; the printed relation has -C/2."""
+    inst = gen.dense_int_qubo(n=7, lo=-5, hi=9, seed=11)
+    Q = inst.dense.astype(np.int64)
+    zero = np.zeros(inst.n, np.int64)
+    J, b, K = orc.qubo_to_ising_int(Q, zero)
+    C = int(np.triu(Q, 1).sum() + np.trace(Q))
+    assert K == C and C != 0
+    plus = minus = True
+    for s in _all_states(inst.n):
+        x = ((s + 1) // 2).astype(np.int8)
+        E = orc.qubo_energy_int(Q, zero, x)
+        H = orc.ising_energy_int(J, b, s)
+        plus &= (2 * E == H + C)
+        minus &= (2 * E == H - C)
+    assert plus and not minus
+
+
+def test_float_canonicalisation_matches_int(orc):
+    inst = gen.dense_int_qubo(n=12, seed=5)
+    Ji, bi, Ki = orc.qubo_to_ising_int(inst.dense, inst.lin)
+    Jf, bf, Kf = orc.qubo_to_ising_float(inst.dense.astype(np.float64), inst.lin.astype(np.float64))
+    assert np.array_equal(Ji, Jf) and np.array_equal(bi, bf) and Ki == Kf
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        s = (2 * rng.integers(0, 2, inst.n) - 1).astype(np.int8)
+        assert orc.ising_energy_int(Ji, bi, s) == orc.ising_energy_float(Jf, bf, s)
+        x = ((s + 1) // 2).astype(np.int8)
+        assert orc.qubo_energy_int(inst.dense, inst.lin, x) == orc.qubo_energy_float(
+            inst.dense.astype(np.float64), inst.lin.astype(np.float64), x)
+
+
+def test_csr_energy_equals_dense_energy(orc):
+    inst = gen.chimera_ising(m=3, seed=7)
+    D = inst.csr.to_dense(np.int32)
+    assert np.array_equal(D, D.T) and np.all(np.diag(D) == 0)
+    b = np.arange(inst.n, dtype=np.int64) % 5 - 2
+    rng = np.random.default_rng(1)
+    for _ in range(10):
+        s = (2 * rng.integers(0, 2, inst.n) - 1).astype(np.int8)
+        c = inst.csr
+        assert orc.ising_energy_csr_int(c.rp, c.col, c.w, b, s) == orc.ising_energy_int(D, b, s)
+
+
+def test_matrix_form_energy_from_fields(orc):
+    """App. C matrix form: H(s) = (1/2) s^T (f + b) with f = J s + b the PA field."""
+    inst = gen.dense_int_ising(n=30, seed=3)
+    rng = np.random.default_rng(4)
+    x = rng.uniform(-1, 1, (5, inst.n)).astype(np.float32)
+    m = np.zeros_like(x)
+    s = np.where(x >= 0, 1, -1).astype(np.int8)
+    lam = np.zeros(1, np.float32)
+    h = orc.pa_steps_dense_int(inst.dense, inst.lin, x, m, 0, 1, lam, 0.01, 0.0, want_h=True)
+    for r in range(5):
+        half = (s[r].astype(np.int64) * (h[r].astype(np.int64) + inst.lin)).sum()
+        assert half % 2 == 0
+        assert half // 2 == orc.ising_energy_int(inst.dense, inst.lin, s[r])
+
+
+def test_field_matches_float64_matmul(orc):
+    """The PA field on +-1 spins is a plain matrix product."""
+    inst = gen.sk_ising(n=64, seed=9)
+    rng = np.random.default_rng(2)
+    x = rng.uniform(-1, 1, (4, inst.n)).astype(np.float32)
+    m = np.zeros_like(x)
+    s = np.where(x >= 0, 1.0, -1.0)
+    lam = np.zeros(1, np.float32)
+    h = orc.pa_steps_dense_float(inst.dense, inst.lin, x.copy(), m, 0, 1, lam, 0.01, 0.0,
+                                 want_h=True)
+    ref = s @ inst.dense.astype(np.float64).T + inst.lin.astype(np.float64)
+    bound = 64 * np.finfo(np.float32).eps * (np.abs(inst.dense).sum(1) + np.abs(inst.lin))
+    assert np.all(np.abs(h - ref) <= bound)
+
+
+# ---------------------------------------------------------------- brute force
+def _naive_min(J, b):
+    best = None
+    for s in _all_states(J.shape[0]).tolist():
+        e = sum(int(J[i, j]) * s[i] * s[j] for i in range(len(s)) for j in range(i + 1, len(s)))
+        e += sum(int(bi) * si for bi, si in zip(b, s))
+        best = e if best is None else min(best, e)
+    return best
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_bruteforce_vs_naive_enumeration(orc, seed):
+    inst = gen.dense_int_ising(n=9, seed=seed)
+    e, s = orc.bruteforce_ising_int(inst.dense, inst.lin)
+    assert e == _naive_min(inst.dense, inst.lin)
+    assert orc.ising_energy_int(inst.dense, inst.lin, s) == e
+
+
+def test_bruteforce_planted_optimum(orc):
+    inst = gen.planted_3regular(16, seed=3)
+    c = inst.csr
+    D = c.to_dense(np.int32)
+    b = np.zeros(inst.n, np.int64)
+    e, s = orc.bruteforce_ising_int(D, b)
+    e_star = -int(np.abs(c.w.astype(np.int64)).sum()) // 2      # each edge stored twice
+    assert e == e_star
+    assert orc.ising_energy_csr_int(c.rp, c.col, c.w, b, inst.meta["planted_state"]) == e_star
+
+
+def test_planted_generator_is_simple_3_regular(orc):
+    inst = gen.planted_3regular(1000, seed=8)
+    c = inst.csr
+    assert np.all(np.diff(c.rp) == 3)
+    rows = np.repeat(np.arange(inst.n), 3)
+    assert np.all(c.col != rows)
+    assert np.all(np.diff(c.col.reshape(-1, 3), axis=1) > 0)       # no repeated neighbour
+    D = c.to_dense(np.int32)
+    assert np.array_equal(D, D.T)
+    ss = inst.meta["planted_state"].astype(np.int32)
+    assert np.all(D * np.outer(ss, ss) <= 0)                        # every coupling satisfied
+
+
+# ---------------------------------------------------------------- PA update: closed forms
+def test_two_spin_hand_worked_steps(orc):
+    J = np.array([[0, 2], [2, 0]], np.int32)
+    b = np.zeros(2, np.int64)
+    x = np.array([[0.25, -0.5]], np.float32)
+    m = np.zeros_like(x)
+    lam = np.array([0.5, 0.5], np.float32)
+    for step, h0, h1, m0, m1, x0, x1 in _rows("pa_two_spin.txt"):
+        t = int(step)
+        h = orc.pa_steps_dense_int(J, b, x, m, t, t + 1, lam, 0.125, 0.5, want_h=True)
+        assert h[0].tolist() == [float(h0), float(h1)]
+        assert m[0].tolist() == [float(m0), float(m1)]
+        assert x[0].tolist() == [float(x0), float(x1)]
+
+
+def test_free_decay_closed_form(orc):
+    """J = 0, b = 0, alpha = 0: x_T = x_0 prod_t (1 - eta lambda_t) while inside [-1,1]."""
+    n, T, eta = 50, 40, 0.05
+    rng = np.random.default_rng(3)
+    x = rng.uniform(-0.9, 0.9, (2, n)).astype(np.float32)
+    x0 = x.astype(np.float64)
+    m = np.zeros_like(x)
+    lam = orc.lambda_linear(T, 2.0)
+    orc.pa_steps_dense_int(np.zeros((n, n), np.int32), np.zeros(n, np.int64), x, m, 0, T, lam,
+                           eta, 0.0)
+    factor = np.prod(1.0 - eta * lam.astype(np.float64))
+    np.testing.assert_allclose(x, x0 * factor, rtol=4 * T * 6e-8, atol=1e-12)
+
+
+def test_constant_force_momentum_closed_form(orc):
+    """lambda = 0, J = 0, constant field b: m_t = -eta b (1 - alpha^t)/(1 - alpha) and
+    x_t = x_0 + sum of the momenta (geometric series), until the clip at -sign(b)."""
+    T, eta, alpha = 12, 0.01, 0.75
+    b = np.array([3, -2, 1], np.int64)
+    x = np.zeros((1, 3), np.float32)
+    m = np.zeros_like(x)
+    lam = np.zeros(T, np.float32)
+    orc.pa_steps_dense_int(np.zeros((3, 3), np.int32), b, x, m, 0, T, lam, eta, alpha)
+    mt = -eta * b * (1 - alpha**T) / (1 - alpha)
+    xt = -eta * b * sum((1 - alpha**k) / (1 - alpha) for k in range(1, T + 1))
+    xt = np.clip(xt, -1, 1)
+    np.testing.assert_allclose(m[0], mt, rtol=1e-5)
+    np.testing.assert_allclose(x[0], xt, rtol=1e-5)
+
+
+def test_sign_of_zero_is_plus_one(orc):
+    """sigma0 = 0 puts every x at 0; the first field must then be J 1 + b."""
+    inst = gen.dense_int_ising(n=10, seed=2)
+    x, m = orc.pa_init(inst.n, 1, 7, np.float32(0.0))
+    assert np.all(x == 0)
+    h = orc.pa_steps_dense_int(inst.dense, inst.lin, x, m, 0, 1, np.ones(1, np.float32), 0.01,
+                               0.0, want_h=True)
+    assert np.array_equal(h[0], (inst.dense.sum(1) + inst.lin).astype(np.float32))
+
+
+def test_updates_are_synchronous(orc):
+    """Antiferromagnetic pair from (+,+): a synchronous step flips both spins; a
+    sequential sweep would flip only the first."""
+    J = np.array([[0, 1], [1, 0]], np.int32)
+    x = np.array([[0.1, 0.1]], np.float32)
+    m = np.zeros_like(x)
+    orc.pa_steps_dense_int(J, np.zeros(2, np.int64), x, m, 0, 1, np.zeros(1, np.float32), 0.5,
+                           0.0)
+    assert np.all(x < 0)
+
+
+def test_clip_saturates_at_exactly_one(orc):
+    J = np.zeros((3, 3), np.int32)
+    b = np.array([-100, 100, 0], np.int64)
+    x = np.array([[0.0, 0.0, 0.5]], np.float32)
+    m = np.zeros_like(x)
+    orc.pa_steps_dense_int(J, b, x, m, 0, 3, np.zeros(3, np.float32), 1.0, 0.9)
+    assert x[0, 0] == 1.0 and x[0, 1] == -1.0 and x[0, 2] == 0.5
+    assert m[0, 0] > 1.0        # momentum itself is never clipped
+
+
+def test_csr_and_dense_trajectories_identical(orc):
+    inst = gen.chimera_ising(m=4, seed=1)
+    c = inst.csr
+    D = c.to_dense(np.int32)
+    b = (np.arange(inst.n) % 3 - 1).astype(np.int64)
+    T = 60
+    lam = orc.lambda_linear(T, 1.5)
+    x1, m1 = orc.pa_init(inst.n, 6, 99, np.float32(0.1))
+    x2, m2 = x1.copy(), m1.copy()
+    orc.pa_steps_dense_int(D, b, x1, m1, 0, T, lam, 0.05, 0.8)
+    orc.pa_steps_csr_int(c.rp, c.col, c.w, b, x2, m2, 0, T, lam, 0.05, 0.8)
+    assert np.array_equal(x1, x2) and np.array_equal(m1, m2)
+    # float CSR on integer weights sums exactly too
+    x3, m3 = orc.pa_init(inst.n, 6, 99, np.float32(0.1))
+    orc.pa_steps_csr_float(c.rp, c.col, c.w.astype(np.float32), b.astype(np.float32), x3, m3,
+                           0, T, lam, 0.05, 0.8)
+    assert np.array_equal(x1, x3)
+
+
+def test_step_rows_matches_full_step(orc):
+    inst = gen.planted_3regular(200, seed=4)
+    c = inst.csr
+    b = np.zeros(inst.n, np.int64)
+    x, m = orc.pa_init(inst.n, 1, 5, np.float32(0.1))
+    xf, mf = x.copy(), m.copy()
+    hf = orc.pa_steps_csr_int(c.rp, c.col, c.w, b, xf, mf, 0, 1, np.array([0.7], np.float32),
+                              0.1, 0.5, want_h=True)
+    rows = np.array([0, 5, 77, 199])
+    h, xo, mo = orc.pa_step_rows_csr_int(c.rp, c.col, c.w, b, x[0], m[0], rows, 0.7, 0.1, 0.5)
+    assert np.array_equal(h, hf[0, rows]) and np.array_equal(xo, xf[0, rows])
+    assert np.array_equal(mo, mf[0, rows])
+
+
+def test_pa_reaches_bruteforce_ground_state_small(orc):
+    """Sanity of the whole driver on a tiny instance: best-of-replica equals brute force."""
+    inst = gen.dense_int_qubo(n=12, seed=21)
+    J, b, K = orc.qubo_to_ising_int(inst.dense, inst.lin)
+    Hmin, _ = orc.bruteforce_ising_int(J, b)
+    T = 300
+    lam = orc.lambda_linear(T, 20.0)
+    res = orc.solve_dense_int(inst.dense, inst.lin, "qubo", 64, T, lam, 0.002, 0.8, 1, 0.1)
+    assert res.energy.min() == (Hmin + K) // 2
+    assert res.energy[res.best] == res.energy.min()
+
+
+# ---------------------------------------------------------------- BF16 storage
+def test_bf16_quantise_matches_torch_rne(orc):
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(0)
+    J = (rng.standard_normal(4096) * 0.3).astype(np.float32)
+    J[:4] = [1.0 + 2**-8, 1.0 + 3 * 2**-8, -(1.0 + 2**-8), 0.0]      # ties to even
+    e = orc.bf16_scale_exponent(J)
+    assert 2.0 ** (e - 1) < np.abs(J).max() <= 2.0 ** e
+    q = orc.bf16_quantise(J, e)
+    ref = (torch.from_numpy(J / np.float32(2.0**e)).to(torch.bfloat16).float().numpy()
+           * np.float32(2.0**e))
+    assert np.array_equal(q, ref)
+    assert q[0] == 1.0 and q[1] == 1.0 + 2**-6 and q[2] == -1.0
+
+
+def test_bf16_scale_exponent_edges(orc):
+    assert orc.bf16_scale_exponent(np.array([0.75], np.float32)) == 0
+    assert orc.bf16_scale_exponent(np.array([1.0], np.float32)) == 0
+    assert orc.bf16_scale_exponent(np.array([-1.5], np.float32)) == 1
+    assert orc.bf16_scale_exponent(np.array([4.0, 0.1], np.float32)) == 2
+    assert orc.bf16_scale_exponent(np.zeros(3, np.float32)) == 0
+
+
+# ---------------------------------------------------------------- relaxed adjoint
+def _fd(f, p, eps):
+    return (f(p + eps) - f(p - eps)) / (2 * eps)
+
+
+@pytest.mark.parametrize("fmt", ["dense", "csr"])
+def test_relaxed_adjoint_vs_finite_differences(orc, fmt):
+    inst = gen.chimera_ising(m=2, seed=3)
+    c = inst.csr
+    n = inst.n
+    rng = np.random.default_rng(5)
+    b = rng.normal(0, 0.3, n)
+    x0, _ = orc.pa_init(n, 4, 3, np.float32(0.2))
+    T, eta, alpha, lam0 = 60, 0.05, 0.7, 1.2
+    base = 1.0 - np.arange(T) / T
+
+    def run(eta_, alpha_, lam_, grads=False):
+        if fmt == "dense":
+            return orc.relaxed_grad_dense(c.to_dense(np.float64), b, x0, T, lam_, eta_, alpha_,
+                                          grads=grads)
+        return orc.relaxed_grad_csr(c.rp, c.col, c.w.astype(np.float64), b, x0, T, lam_, eta_,
+                                    alpha_, grads=grads)
+
+    L, de, da, dl = run(eta, alpha, lam0 * base, grads=True)
+    eps = 1e-6
+    fe = _fd(lambda p: run(p, alpha, lam0 * base)[0], eta, eps)
+    fa = _fd(lambda p: run(eta, p, lam0 * base)[0], alpha, eps)
+    fl0 = _fd(lambda p: run(eta, alpha, p * base)[0], lam0, eps)
+    assert abs(de - fe) <= 1e-6 * max(1.0, abs(fe))
+    assert abs(da - fa) <= 1e-6 * max(1.0, abs(fa))
+    assert abs(np.dot(dl, base) - fl0) <= 1e-6 * max(1.0, abs(fl0))
+    for t in [0, 17, T - 1]:
+        def f(p, t=t):
+            lam = lam0 * base.copy()
+            lam[t] = p
+            return run(eta, alpha, lam)[0]
+        ft = _fd(f, lam0 * base[t], eps)
+        assert abs(dl[t] - ft) <= 1e-6 * max(1.0, abs(ft))
+
+
+def test_relaxed_forward_equals_pa_without_couplings(orc):
+    """With J = 0 the relaxed (s := x) and binarised dynamics coincide."""
+    n, T = 16, 30
+    b = np.linspace(-1, 1, n)
+    x0, _ = orc.pa_init(n, 2, 1, np.float32(0.3))
+    lam = orc.lambda_linear(T, 1.0)
+    L, *_ = orc.relaxed_grad_dense(np.zeros((n, n)), b, x0, T, lam.astype(np.float64), 0.05, 0.5,
+                                   grads=False)
+    x, m = x0.copy(), np.zeros_like(x0)
+    orc.pa_steps_dense_float(np.zeros((n, n), np.float32), b.astype(np.float32), x, m, 0, T, lam,
+                             0.05, 0.5)
+    Lpa = np.mean(x.astype(np.float64) @ b)
+    assert abs(L - Lpa) <= 1e-5 * max(1.0, abs(Lpa))
