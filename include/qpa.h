@@ -1,0 +1,198 @@
+/*
+ * qpa.h -- C ABI of the replica-batched Parallel Annealing (PA) engine for AMD MI355X.
+ *
+ * The engine minimises a QUBO objective E(x) = x^T Q x + c^T x over x in {0,1}^n
+ * (symmetric Q; Sec. II, eq. (1) in symmetric-matrix form) or an Ising objective
+ * H(s) = sum_{i<j} J_ij s_i s_j + sum_i b_i s_i over s in {-1,+1}^n (Sec. II, eq. (2))
+ * with the Parallel Annealing dynamics of App. B of arXiv 2501.19221, run on R
+ * independent replicas:
+ *
+ *   s_t   = sign(x_t)                       (sign(0) = +1)
+ *   g_t   = lambda_t x_t + (J s_t + b)      (target part on binarised spins)
+ *   m_t+1 = alpha m_t - eta g_t             (momentum)
+ *   x_t+1 = clip(x_t + m_t+1, -1, 1)        (clipping)
+ *
+ * every operation rounded to FP32 separately in the order written.  A QUBO is first
+ * mapped to Ising form with x = (1+s)/2 (App. A): J = Q without its diagonal,
+ * b = Q 1 + c, and 2 E(x) = H(s) + K with K = (1/2) 1^T Q 1 + (1/2) tr Q + 1^T c; the
+ * dynamics run on that (J, b).  The initial state is x_0[r][i] = sigma0 * (2u - 1) with
+ * u the top 24 bits of the (r*n + i + 1)-th output of SplitMix64(seed), scaled by 2^-24;
+ * m_0 = 0.  The default schedule is lambda_t = lambda0 * (1 - t/T) (App. B asks for a
+ * gradual decrease to zero).  After T steps every replica's final spins sign(x_T) are
+ * scored exactly (int64 for integer couplings, FP64 for float couplings) and the lowest
+ * replica index attaining the minimum is reported.
+ *
+ * Conventions for every entry point:
+ *  - Buffers marked "device" are HIP device pointers on the context's device; buffers
+ *    marked "host" are ordinary host memory read during the call only.  The caller owns
+ *    every buffer (inputs, outputs, workspace).  The library never frees caller memory
+ *    and keeps no pointer to it after the call returns.
+ *  - Work is enqueued on `stream` (a hipStream_t, NULL = default stream).  An entry point
+ *    synchronises that stream once, after validating its inputs on the device, so that
+ *    it can report invalid input through its return value; the remaining work is
+ *    asynchronous, and outputs are ready when the stream is.
+ *  - Errors: every entry point returns a qpa_status; QPA_OK is 0.  A human-readable
+ *    message for the last failure on a context is returned by qpa_last_error().  No C++
+ *    exception crosses this interface.  A context is not thread-safe: use one per host
+ *    thread.  Calls that share a workspace must not overlap.
+ */
+#ifndef QPA_H
+#define QPA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QPA_OK = 0,
+    QPA_E_ARG = 1,          /* null pointer, negative size, unknown enum value        */
+    QPA_E_SHAPE = 2,        /* inconsistent sizes (CSR row pointers, n, nnz)          */
+    QPA_E_ASYM = 3,         /* couplings not symmetric, or Ising diagonal not zero    */
+    QPA_E_RANGE = 4,        /* integer row sum max_i sum_j |J_ij| + |b_i| >= 2^24:    */
+                            /* FP32 fields would no longer be exact                   */
+    QPA_E_WORKSPACE = 5,    /* workspace smaller than qpa_workspace_size()            */
+    QPA_E_DEVICE = 6,       /* a HIP call failed                                      */
+    QPA_E_UNSUPPORTED = 7   /* valid request outside what this build implements       */
+} qpa_status;
+
+typedef enum { QPA_KIND_QUBO = 0, QPA_KIND_ISING = 1 } qpa_kind;
+typedef enum { QPA_FMT_DENSE = 0, QPA_FMT_CSR = 1 } qpa_format;
+typedef enum { QPA_I8 = 0, QPA_I16 = 1, QPA_I32 = 2, QPA_F32 = 3 } qpa_dtype;
+
+/* Field arithmetic of the dense path.  QPA_PREC_FP32: couplings stored and multiplied
+ * in FP32.  QPA_PREC_BF16: couplings stored as bf16(J / 2^e) (round to nearest even,
+ * e the smallest integer with max|J| <= 2^e) on the matrix cores with FP32
+ * accumulation, the sum scaled back by 2^e; spins are exact in BF16.  Integer
+ * couplings with |J| <= 256 are exact in BF16, so both settings give identical
+ * trajectories for them.  CSR problems always use exact FP32 (or integer) sums. */
+typedef enum { QPA_PREC_FP32 = 0, QPA_PREC_BF16 = 1 } qpa_precision;
+
+/* One problem instance.  All array pointers are device pointers.
+ *  dense  : n*n couplings, row-major, symmetric, dtype `coupling_dtype`.
+ *           QUBO: Q (any diagonal, folded into b).  Ising: J (diagonal must be 0).
+ *  CSR    : row_ptr[n+1] (int32, row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz),
+ *           col[nnz] (dtype `index_dtype`: QPA_I32 or QPA_I16, each in [0, n)),
+ *           weights[nnz] (dtype `coupling_dtype`).  Both (i,j) and (j,i) are stored
+ *           with equal weights.  QUBO: entries (i,i) allowed.  Ising: none allowed.
+ *  linear : n entries of dtype `linear_dtype`; c (QUBO) or b (Ising); NULL = zeros. */
+typedef struct {
+    int64_t n;
+    int32_t kind;               /* qpa_kind   */
+    int32_t format;             /* qpa_format */
+    int32_t coupling_dtype;     /* qpa_dtype  */
+    int32_t index_dtype;        /* qpa_dtype, CSR only: QPA_I32 or QPA_I16 */
+    int32_t linear_dtype;       /* qpa_dtype  */
+    int32_t reserved0;
+    const void *dense;
+    int64_t nnz;
+    const int32_t *row_ptr;
+    const void *col;
+    const void *weights;
+    const void *linear;
+} qpa_problem;
+
+/* Dynamics parameters (App. B).  lambda_table (host, `steps` floats) overrides the
+ * default linear schedule when not NULL. */
+typedef struct {
+    int32_t replicas;           /* R >= 1                                       */
+    int32_t steps;              /* T >= 0                                       */
+    float eta;                  /* gradient step ("time step")                  */
+    float alpha;                /* momentum coefficient                         */
+    float lambda0;              /* initial weight of the quadratic H_initial    */
+    float sigma0;               /* amplitude of the initial analog spins        */
+    const float *lambda_table;  /* host, optional                               */
+    uint64_t seed;              /* SplitMix64 seed of the initial state          */
+    int32_t precision;          /* qpa_precision (dense path)                   */
+    int32_t flags;              /* must be 0                                    */
+} qpa_params;
+
+/* Outputs of a solve.  Every pointer is a device pointer and may be NULL except
+ * `energy` and `best`.
+ *  spins      [R*n] int8, final sign(x_T) of each replica, row-major by replica.
+ *  energy     [R] double: the instance's own objective of those spins (E(x) for a
+ *             QUBO with x = (1+s)/2, H(s) for Ising), exact for integer couplings,
+ *             FP64-accumulated for float couplings.
+ *  energy_i64 [R] int64: the same energies as exact integers (integer couplings only;
+ *             left untouched for float couplings).
+ *  best       [1] int32: lowest replica index attaining the minimum energy.
+ *  x, m       [R*n] float: final analog spins and momenta. */
+typedef struct {
+    int8_t *spins;
+    double *energy;
+    int64_t *energy_i64;
+    int32_t *best;
+    float *x;
+    float *m;
+} qpa_outputs;
+
+typedef struct qpa_ctx qpa_ctx;
+
+/* Create a context bound to HIP device `device` (0-based).  *out receives the handle. */
+qpa_status qpa_create(qpa_ctx **out, int device);
+
+/* Destroy a context created by qpa_create (NULL is accepted). */
+void qpa_destroy(qpa_ctx *ctx);
+
+/* Message describing the last failure on `ctx` ("" if none).  Valid until the next
+ * call on the same context.  With ctx == NULL: the last failure of a call made without
+ * a context (qpa_create, qpa_workspace_size(NULL, ...)) on the calling thread. */
+const char *qpa_last_error(const qpa_ctx *ctx);
+
+/* Static name of a status code. */
+const char *qpa_status_string(qpa_status status);
+
+/* Device bytes of workspace that qpa_solve needs for (problem, params).
+ * The workspace must be 256-byte aligned (any hipMalloc'd or torch-allocated buffer
+ * is).  Its content on entry is irrelevant; the library clears what it needs. */
+qpa_status qpa_workspace_size(qpa_ctx *ctx, const qpa_problem *problem,
+                              const qpa_params *params, size_t *bytes);
+
+/* Run the whole solve -- canonicalisation (App. A), initial state, `steps` PA steps
+ * (App. B), exact energies of the final spins, best replica -- for one problem.
+ * workspace: device buffer of at least qpa_workspace_size() bytes. */
+qpa_status qpa_solve(qpa_ctx *ctx, const qpa_problem *problem, const qpa_params *params,
+                     void *workspace, size_t workspace_bytes, void *stream,
+                     const qpa_outputs *out);
+
+/* Advance a caller-held state by PA steps t0 .. t1-1 (0 <= t0 <= t1 <= params->steps)
+ * of the schedule of `params` -- the resume / teacher-forcing entry point.
+ *  x, m    : device [R*n] float, read and overwritten in place (R = params->replicas).
+ *  h_last  : device [R*n] float or NULL; receives the fields J s + b of the last step
+ *            taken (untouched if t0 == t1).
+ * The same kernels as qpa_solve run; the seed and sigma0 are not used.  Trajectories are
+ * identical to an uninterrupted qpa_solve whatever the split points. */
+qpa_status qpa_steps(qpa_ctx *ctx, const qpa_problem *problem, const qpa_params *params,
+                     int32_t t0, int32_t t1, float *x, float *m, float *h_last,
+                     void *workspace, size_t workspace_bytes, void *stream);
+
+/* Batched energies and best-of-replica for given spins: energy[r] = the instance's
+ * objective of spins[r*n .. r*n+n) (as in qpa_outputs), best = lowest argmin.
+ *  spins: device [R*n] int8 in {-1,+1}.  energy: device [R] double (required);
+ *  energy_i64: device [R] int64 or NULL; best: device [1] int32 or NULL.
+ * Uses the workspace of qpa_workspace_size(problem, params) with params->replicas = R. */
+qpa_status qpa_energy(qpa_ctx *ctx, const qpa_problem *problem, const qpa_params *params,
+                      const int8_t *spins, double *energy, int64_t *energy_i64,
+                      int32_t *best, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Measurement of the PA-step kernels.  While enabled (enable != 0), every qpa_solve and
+ * qpa_steps call records one HIP event on its stream right before its first step kernel
+ * and one right after its last, and counts the step kernels it launched.
+ * qpa_profile_read waits for the recorded events and returns the summed elapsed time in
+ * milliseconds and the number of step-kernel launches since the last reset (reset != 0
+ * clears the totals after reading).  The averaged interval includes the gaps between
+ * consecutive step kernels of one call. */
+qpa_status qpa_profile_enable(qpa_ctx *ctx, int32_t enable);
+qpa_status qpa_profile_read(qpa_ctx *ctx, double *step_ms, int64_t *step_launches,
+                            int32_t reset);
+
+/* Library version string. */
+const char *qpa_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QPA_H */

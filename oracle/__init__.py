@@ -369,3 +369,24 @@ def solve_csr_int(rp, col, w, lin, R, T, lam, eta, alpha, seed, sigma0, r0=0):
     s = _sign(x)
     e = np.array([ising_energy_csr_int(rp, col, w, lin, s[r]) for r in range(R)], np.int64)
     return OracleResult(x, m, s, e, _argmin_first(e))
+
+
+def qubo_to_ising_csr_int(rp, col, w, c):
+    """App. A for a CSR QUBO with integer weights: J = the off-diagonal entries,
+    b_i = (sum of row i, diagonal included) + c_i, K = (1/2) 1^T Q 1 + (1/2) tr Q + 1^T c."""
+    rp = np.asarray(rp, np.int64)
+    col = np.asarray(col, np.int64)
+    w = np.asarray(w, np.int64)
+    n = len(rp) - 1
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    rowsum = np.zeros(n, np.int64)
+    np.add.at(rowsum, rows, w)
+    diag = np.zeros(n, np.int64)
+    on = rows == col
+    np.add.at(diag, rows[on], w[on])
+    keep = ~on
+    rp2 = np.zeros(n + 1, np.int64)
+    np.cumsum(np.bincount(rows[keep], minlength=n), out=rp2[1:])
+    b = rowsum + np.asarray(c, np.int64)
+    K = (int(rowsum.sum()) + int(diag.sum())) // 2 + int(np.asarray(c, np.int64).sum())
+    return rp2, col[keep].astype(np.int32), w[keep].astype(np.int32), b, K

@@ -1,0 +1,216 @@
+// Dense PA steps in FP32 (App. B).  Both kernels accumulate every local field
+// sum_j J_ij s_j in ascending j from zero and then add b_i: with s = +-1 every product is
+// exact, so the result is the same FP32 sum whatever the tiling, and trajectories are
+// reproducible bit for bit.
+//
+// The update after the field is, each operation rounded separately:
+//   g = lambda_t * x + h;  m' = alpha * m - eta * g;  x' = clip(x + m', -1, 1).
+#include "qpa_internal.h"
+
+namespace qpa {
+namespace {
+
+__device__ __forceinline__ void pa_update(float h, float lam, float eta, float alpha, float &x,
+                                          float &m) {
+    float g = __fadd_rn(__fmul_rn(lam, x), h);
+    float mn = __fsub_rn(__fmul_rn(alpha, m), __fmul_rn(eta, g));
+    float y = __fadd_rn(x, mn);
+    y = fminf(1.0f, fmaxf(-1.0f, y));
+    m = mn;
+    x = y;
+}
+
+__device__ __forceinline__ float spin_of(float x) { return x >= 0.0f ? 1.0f : -1.0f; }
+
+// ---------------------------------------------------------------- LDS-resident (small n)
+// A block owns RB replicas and all n variables for every step in [t0, t1): couplings,
+// fields and both spin buffers live in LDS, analog state in registers.  Thread p of the
+// block handles pairs p, p + 256, ... of the RB x n (replica, variable) grid.
+constexpr int RES_THREADS = 256;
+constexpr int RES_PAIRS = 2;
+
+__global__ void __launch_bounds__(RES_THREADS) k_dense_resident(
+    int n, int R, int RB, const float *__restrict__ J, const float *__restrict__ b,
+    float *__restrict__ x, float *__restrict__ m, float *__restrict__ h_last, int t0, int t1,
+    const float *__restrict__ lam, float eta, float alpha) {
+    extern __shared__ float sh[];
+    float *sJ = sh;
+    float *sb = sJ + n * n;
+    float *sS = sb + n;   // [2][RB][n]
+    const int tid = threadIdx.x;
+    const int r0 = blockIdx.x * RB;
+    const int nr = min(RB, R - r0);
+    for (int k = tid; k < n * n; k += RES_THREADS) sJ[k] = J[k];
+    for (int k = tid; k < n; k += RES_THREADS) sb[k] = b[k];
+
+    float xr[RES_PAIRS], mr[RES_PAIRS], hr[RES_PAIRS];
+    int rl[RES_PAIRS], iv[RES_PAIRS];
+    bool act[RES_PAIRS];
+#pragma unroll
+    for (int q = 0; q < RES_PAIRS; ++q) {
+        int p = tid + q * RES_THREADS;
+        act[q] = p < nr * n;
+        rl[q] = act[q] ? p / n : 0;
+        iv[q] = act[q] ? p - rl[q] * n : 0;
+        xr[q] = mr[q] = hr[q] = 0.0f;
+        if (act[q]) {
+            int64_t g = (int64_t)(r0 + rl[q]) * n + iv[q];
+            xr[q] = x[g];
+            mr[q] = m[g];
+            sS[rl[q] * n + iv[q]] = spin_of(xr[q]);
+        }
+    }
+    __syncthreads();
+    int cur = 0;
+    for (int t = t0; t < t1; ++t) {
+        const float lt = lam[t];
+        const float *scur = sS + cur * RB * n;
+        float *snxt = sS + (cur ^ 1) * RB * n;
+#pragma unroll
+        for (int q = 0; q < RES_PAIRS; ++q) {
+            if (!act[q]) continue;
+            const float *Jrow = sJ + iv[q] * n;
+            const float *srow = scur + rl[q] * n;
+            float acc = 0.0f;
+            for (int j = 0; j < n; ++j) acc = __fadd_rn(acc, __fmul_rn(Jrow[j], srow[j]));
+            float h = __fadd_rn(acc, sb[iv[q]]);
+            hr[q] = h;
+            pa_update(h, lt, eta, alpha, xr[q], mr[q]);
+            snxt[rl[q] * n + iv[q]] = spin_of(xr[q]);
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+#pragma unroll
+    for (int q = 0; q < RES_PAIRS; ++q) {
+        if (!act[q]) continue;
+        int64_t g = (int64_t)(r0 + rl[q]) * n + iv[q];
+        x[g] = xr[q];
+        m[g] = mr[q];
+        if (h_last && t1 > t0) h_last[g] = hr[q];
+    }
+}
+
+// ---------------------------------------------------------------- tiled, one step
+// Block tile: 64 replicas x 64 variables, 256 threads; thread (ty, tx) owns replicas
+// r0 + 4*ty + q (q < 4) and variables i0 + tx + 16*c (c < 4).  K is walked in chunks of
+// 32 staged through LDS, ascending, with one accumulator per output.
+constexpr int TB = 64, TK = 32;
+
+__global__ void __launch_bounds__(256) k_dense_tiled_step(
+    int64_t n, int64_t R, const float *__restrict__ J, const float *__restrict__ b,
+    const float *__restrict__ s_cur, float *__restrict__ s_nxt, float *__restrict__ x,
+    float *__restrict__ m, float *__restrict__ h_last, int t, const float *__restrict__ lam,
+    float eta, float alpha) {
+    __shared__ float As[TK][TB + 1];   // spins  [k][replica]
+    __shared__ float Bs[TK][TB + 1];   // J      [k][variable]
+    const int tid = threadIdx.x;
+    const int tx = tid % 16, ty = tid / 16;
+    const int64_t r0 = (int64_t)blockIdx.y * TB, i0 = (int64_t)blockIdx.x * TB;
+    float acc[4][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[q][c] = 0.0f;
+
+    for (int64_t k0 = 0; k0 < n; k0 += TK) {
+        // 64 rows x 32 k for both tiles: 2048 elements, 8 per thread.
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            int idx = tid + e * 256;
+            int row = idx / TK, kk = idx % TK;
+            int64_t k = k0 + kk;
+            int64_t r = r0 + row, i = i0 + row;
+            As[kk][row] = (r < R && k < n) ? s_cur[r * n + k] : 0.0f;
+            Bs[kk][row] = (i < n && k < n) ? J[i * n + k] : 0.0f;
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int kk = 0; kk < TK; ++kk) {
+            float a[4], bb[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) a[q] = As[kk][4 * ty + q];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) bb[c] = Bs[kk][tx + 16 * c];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    acc[q][c] = __fadd_rn(acc[q][c], __fmul_rn(a[q], bb[c]));
+        }
+        __syncthreads();
+    }
+    const float lt = lam[t];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        int64_t r = r0 + 4 * ty + q;
+        if (r >= R) continue;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            int64_t i = i0 + tx + 16 * c;
+            if (i >= n) continue;
+            int64_t g = r * n + i;
+            float h = __fadd_rn(acc[q][c], b[i]);
+            float xv = x[g], mv = m[g];
+            pa_update(h, lt, eta, alpha, xv, mv);
+            x[g] = xv;
+            m[g] = mv;
+            s_nxt[g] = spin_of(xv);
+            if (h_last) h_last[g] = h;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_sign_f32(int64_t count, const float *__restrict__ x,
+                                                  float *__restrict__ s) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count;
+         k += (int64_t)gridDim.x * blockDim.x)
+        s[k] = spin_of(x[k]);
+}
+
+int resident_rb(int64_t n) {
+    int rb = (int)((RES_THREADS * RES_PAIRS) / n);
+    return rb < 1 ? 1 : rb;
+}
+
+size_t resident_lds_bytes(int64_t n) {
+    return sizeof(float) * (size_t)(n * n + n + 2 * resident_rb(n) * n);
+}
+
+}  // namespace
+
+bool dense_resident_fits(int64_t n) {
+    return n >= 1 && n <= 128 && resident_lds_bytes(n) <= 64 * 1024;
+}
+
+hipError_t launch_dense_resident(int64_t n, int64_t R, const float *J, const float *b,
+                                 float *x, float *m, float *h_last, int32_t t0, int32_t t1,
+                                 const float *lam, float eta, float alpha, hipStream_t st) {
+    if (!dense_resident_fits(n)) return hipErrorInvalidValue;
+    const int rb = resident_rb(n);
+    const unsigned grid = (unsigned)((R + rb - 1) / rb);
+    const size_t lds = resident_lds_bytes(n);
+    k_dense_resident<<<grid, RES_THREADS, lds, st>>>((int)n, (int)R, rb, J, b, x, m, h_last,
+                                                     t0, t1, lam, eta, alpha);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_tiled_step(int64_t n, int64_t R, const float *J, const float *b,
+                                   const float *s_cur, float *s_nxt, float *x, float *m,
+                                   float *h_last, int32_t t, const float *lam, float eta,
+                                   float alpha, hipStream_t st) {
+    dim3 grid((unsigned)((n + TB - 1) / TB), (unsigned)((R + TB - 1) / TB));
+    k_dense_tiled_step<<<grid, 256, 0, st>>>(n, R, J, b, s_cur, s_nxt, x, m, h_last, t, lam, eta,
+                                             alpha);
+    return hipGetLastError();
+}
+
+hipError_t launch_sign_f32(int64_t count, const float *x, float *s, hipStream_t st) {
+    if (count == 0) return hipSuccess;
+    int64_t g = (count + 255) / 256;
+    if (g > 65536) g = 65536;
+    k_sign_f32<<<(unsigned)g, 256, 0, st>>>(count, x, s);
+    return hipGetLastError();
+}
+
+}  // namespace qpa

@@ -1,0 +1,667 @@
+// Set-up and scoring kernels: canonicalisation (App. A), validation, initial state,
+// state layout copies, exact energies (eq. (1) / eq. (2)) and best-of-replica.
+#include "qpa_internal.h"
+
+#include <math.h>
+
+namespace qpa {
+namespace {
+
+constexpr int WAVE = 64;
+
+template <typename T> __device__ __forceinline__ T ld(const void *p, int64_t k) {
+    return static_cast<const T *>(p)[k];
+}
+
+// Read element k of an array of caller dtype `dt` as double (exact for every dtype here).
+__device__ __forceinline__ double load_as_double(const void *p, int32_t dt, int64_t k) {
+    switch (dt) {
+        case QPA_I8: return (double)ld<int8_t>(p, k);
+        case QPA_I16: return (double)ld<int16_t>(p, k);
+        case QPA_I32: return (double)ld<int32_t>(p, k);
+        default: return (double)ld<float>(p, k);
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+    for (int o = WAVE / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
+    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Round-to-nearest-even of a finite float to bf16 (upper 16 bits).
+__device__ __forceinline__ uint16_t bf16_rne(float v) {
+    uint32_t u = __float_as_uint(v);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// ------------------------------------------------------------------ dense canonicalisation
+// One wave per row i.  Integer values are carried in double, exact below 2^53.
+template <typename TQ>
+__global__ void __launch_bounds__(256) k_dense_rows(int64_t n, const TQ *__restrict__ Q,
+                                                    const void *lin, int32_t lin_dt,
+                                                    int32_t is_qubo, float *__restrict__ J_f32,
+                                                    float *__restrict__ b_f32,
+                                                    int64_t *__restrict__ b_i64,
+                                                    double *__restrict__ b_f64,
+                                                    double *__restrict__ row_abs,
+                                                    double *__restrict__ row_max,
+                                                    double *__restrict__ row_k,
+                                                    CanonScalars *sc) {
+    const int lane = threadIdx.x % WAVE;
+    const int64_t i = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    if (i >= n) return;
+    const TQ *row = Q + i * n;
+    double sum = 0.0, sabs = 0.0, smax = 0.0, diag = 0.0;
+    for (int64_t j = lane; j < n; j += WAVE) {
+        double q = (double)row[j];
+        sum += q;
+        if (j == i) {
+            diag = q;
+        } else {
+            sabs += fabs(q);
+            smax = fmax(smax, fabs(q));
+        }
+        if (J_f32) J_f32[i * n + j] = (j == i) ? 0.0f : (float)row[j];
+    }
+    sum = wave_sum(sum);
+    sabs = wave_sum(sabs);
+    smax = wave_max(smax);
+    diag = wave_sum(diag);
+    if (lane == 0) {
+        double c = lin ? load_as_double(lin, lin_dt, i) : 0.0;
+        if (!is_qubo && diag != 0.0) atomicOr(&sc->flags, (int32_t)FLAG_ASYM);
+        double bx = (is_qubo ? sum : 0.0) + c;
+        b_f32[i] = (float)bx;
+        if (b_i64) b_i64[i] = (int64_t)bx;
+        b_f64[i] = bx;
+        row_abs[i] = sabs + fabs(bx);
+        row_max[i] = smax;
+        // contribution to 2K = 1^T Q 1 + tr Q + 2 1^T c  (QUBO only)
+        row_k[i] = is_qubo ? (sum + diag + 2.0 * c) : 0.0;
+    }
+}
+
+// Symmetry: compare the 32x32 tiles (by, bx) and (bx, by) through LDS.
+template <typename TQ>
+__global__ void __launch_bounds__(256) k_dense_sym(int64_t n, const TQ *__restrict__ Q,
+                                                   CanonScalars *sc) {
+    __shared__ TQ tile[32][33];
+    const int64_t bx = blockIdx.x, by = blockIdx.y;
+    if (bx > by) return;
+    const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;   // 32 x 8
+    // load tile (bx, by) transposed: element (r = by*32 + ..., c = bx*32 + ...)
+    for (int k = ty; k < 32; k += 8) {
+        int64_t r = bx * 32 + k, c = by * 32 + tx;
+        tile[tx][k] = (r < n && c < n) ? Q[r * n + c] : TQ(0);
+    }
+    __syncthreads();
+    int bad = 0;
+    for (int k = ty; k < 32; k += 8) {
+        int64_t r = by * 32 + k, c = bx * 32 + tx;
+        if (r < n && c < n) bad |= (Q[r * n + c] != tile[k][tx]);
+    }
+    if (bad) atomicOr(&sc->flags, (int32_t)FLAG_ASYM);
+}
+
+// Single block: reduce the per-row partials into the scalars.
+__global__ void __launch_bounds__(1024) k_canon_finalize(int64_t n, const double *row_abs,
+                                                         const double *row_max,
+                                                         const double *row_k, int32_t is_int,
+                                                         CanonScalars *sc) {
+    __shared__ double s_abs[1024 / WAVE], s_max[1024 / WAVE], s_k[1024 / WAVE];
+    __shared__ int64_t s_ki[1024 / WAVE];
+    double a = 0.0, mx = 0.0, kf = 0.0;
+    int64_t ki = 0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        a = fmax(a, row_abs[i]);
+        if (row_max) mx = fmax(mx, row_max[i]);
+        kf += row_k[i];
+        ki += (int64_t)row_k[i];
+    }
+    a = wave_max(a);
+    mx = wave_max(mx);
+    kf = wave_sum(kf);
+    ki = wave_sum_i64(ki);
+    const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    if (lane == 0) {
+        s_abs[w] = a;
+        s_max[w] = mx;
+        s_k[w] = kf;
+        s_ki[w] = ki;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double A = 0.0, M = 0.0, Kf = 0.0;
+        int64_t Ki = 0;
+        for (int k = 0; k < (int)(blockDim.x / WAVE); ++k) {
+            A = fmax(A, s_abs[k]);
+            M = fmax(M, s_max[k]);
+            Kf += s_k[k];
+            Ki += s_ki[k];
+        }
+        sc->max_row = A;
+        sc->max_abs = M;
+        sc->K_f64 = 0.5 * Kf;
+        sc->K_i64 = Ki / 2;
+        if (is_int && A >= 16777216.0) atomicOr(&sc->flags, (int32_t)FLAG_RANGE);
+        int e = 0;
+        if (M > 0.0) {
+            e = (int)ceil(log2(M));
+            // guard the rounding of log2 near powers of two
+            while (ldexp(1.0, e) < M) ++e;
+            while (e > -126 && ldexp(1.0, e - 1) >= M) --e;
+        }
+        sc->exp2 = e;
+        sc->scale = ldexpf(1.0f, e);
+        sc->inv_scale = ldexpf(1.0f, -e);
+    }
+}
+
+template <typename TQ>
+__global__ void __launch_bounds__(256) k_dense_bf16(int64_t n, int64_t npad,
+                                                    const TQ *__restrict__ Q,
+                                                    const CanonScalars *sc,
+                                                    uint16_t *__restrict__ Jb) {
+    const float inv = sc->inv_scale;
+    const int64_t total = npad * npad;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        int64_t i = k / npad, j = k - i * npad;
+        uint16_t v = 0;
+        if (i < n && j < n && i != j) v = bf16_rne((float)Q[i * n + j] * inv);
+        Jb[k] = v;
+    }
+}
+
+// ------------------------------------------------------------------ CSR canonicalisation
+template <typename TW, typename TI>
+__global__ void __launch_bounds__(256) k_csr_rows(int64_t n, int64_t nnz,
+                                                  const int32_t *__restrict__ rp,
+                                                  const TI *__restrict__ col,
+                                                  const TW *__restrict__ w, const void *lin,
+                                                  int32_t lin_dt, int32_t is_qubo,
+                                                  float *__restrict__ b_f32,
+                                                  int64_t *__restrict__ b_i64,
+                                                  double *__restrict__ b_f64,
+                                                  double *__restrict__ row_abs,
+                                                  double *__restrict__ row_k,
+                                                  CanonScalars *sc) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t flags = 0;
+    const int64_t k0 = rp[i], k1 = rp[i + 1];
+    if (i == 0 && k0 != 0) flags |= FLAG_SHAPE;
+    if (i == n - 1 && k1 != nnz) flags |= FLAG_SHAPE;
+    double sum = 0.0, sabs = 0.0, diag = 0.0;
+    if (k0 > k1 || k0 < 0 || k1 > nnz) {
+        flags |= FLAG_SHAPE;
+    } else {
+        int64_t prev = -1;
+        for (int64_t k = k0; k < k1; ++k) {
+            int64_t j = (int64_t)col[k];
+            double v = (double)w[k];
+            if (j < 0 || j >= n) {
+                flags |= FLAG_SHAPE;
+                continue;
+            }
+            if (j <= prev) flags |= FLAG_UNSORTED;
+            prev = j;
+            sum += v;
+            if (j == i) {
+                diag += v;
+                if (!is_qubo) flags |= FLAG_ASYM;
+                continue;
+            }
+            sabs += fabs(v);
+            // symmetric partner (j, i) with the same weight: binary search in row j
+            int64_t lo = rp[j], hi = rp[j + 1] - 1;
+            bool found = false;
+            while (lo <= hi && lo >= 0 && hi < nnz) {
+                int64_t mid = (lo + hi) >> 1;
+                int64_t cm = (int64_t)col[mid];
+                if (cm == i) {
+                    found = ((double)w[mid] == v);
+                    break;
+                }
+                if (cm < i) lo = mid + 1;
+                else hi = mid - 1;
+            }
+            if (!found) flags |= FLAG_ASYM;
+        }
+    }
+    double c = lin ? load_as_double(lin, lin_dt, i) : 0.0;
+    double bx = (is_qubo ? sum : 0.0) + c;
+    b_f32[i] = (float)bx;
+    if (b_i64) b_i64[i] = (int64_t)bx;
+    b_f64[i] = bx;
+    row_abs[i] = sabs + fabs(bx);
+    row_k[i] = is_qubo ? (sum + diag + 2.0 * c) : 0.0;
+    if (flags) atomicOr(&sc->flags, flags);
+}
+
+// ------------------------------------------------------------------ initial state
+// Replica r, variable i: u = top 24 bits of SplitMix64 output number r*n + i + 1.
+__device__ __forceinline__ uint64_t splitmix_output(uint64_t seed, uint64_t k) {
+    uint64_t z = seed + k * 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+__global__ void __launch_bounds__(256) k_init_state(int64_t n, int64_t R, uint64_t seed,
+                                                    float sigma0, float *__restrict__ x,
+                                                    float *__restrict__ m, int64_t ld_r,
+                                                    int64_t ld_i, int64_t Rpad, int64_t npad) {
+    const int64_t total = Rpad * npad;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        int64_t r, i;
+        if (ld_i == 1) {          // replica-major: consecutive threads walk variables
+            r = k / npad;
+            i = k - r * npad;
+        } else {                  // variable-major: consecutive threads walk replicas
+            i = k / Rpad;
+            r = k - i * Rpad;
+        }
+        float xv = 0.0f;
+        if (r < R && i < n) {
+            uint64_t top = splitmix_output(seed, (uint64_t)(r * n + i) + 1u) >> 40;
+            float u = __fmul_rn((float)top, 1.0f / 16777216.0f);
+            float v = __fsub_rn(__fmul_rn(2.0f, u), 1.0f);
+            xv = __fmul_rn(sigma0, v);
+        }
+        x[r * ld_r + i * ld_i] = xv;
+        m[r * ld_r + i * ld_i] = 0.0f;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_copy_state(int64_t n, int64_t R, const float *src,
+                                                    int64_t s_ld_r, int64_t s_ld_i,
+                                                    float *dst, int64_t d_ld_r,
+                                                    int64_t d_ld_i) {
+    const int64_t total = R * n;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        int64_t r, i;
+        if (d_ld_i == 1) {
+            r = k / n;
+            i = k - r * n;
+        } else {
+            i = k / R;
+            r = k - i * R;
+        }
+        dst[r * d_ld_r + i * d_ld_i] = src[r * s_ld_r + i * s_ld_i];
+    }
+}
+
+__global__ void __launch_bounds__(256) k_export_spins(int64_t n, int64_t R, const float *x,
+                                                      int64_t ld_r, int64_t ld_i,
+                                                      int8_t *spins) {
+    const int64_t total = R * n;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        int64_t r = k / n, i = k - r * n;
+        spins[k] = (x[r * ld_r + i * ld_i] >= 0.0f) ? (int8_t)1 : (int8_t)-1;
+    }
+}
+
+// ------------------------------------------------------------------ energies
+// H(s) = (1/2) sum_i s_i (sum_{j != i} J_ij s_j) + sum_i b_i s_i, i.e. 2H = sum_i s_i (d_i + 2 b_i)
+// with d_i = sum_{j != i} Q_ij s_j.  For a QUBO the objective is E = (H + K) / 2.
+// Dense: a wave takes one row i and ER replicas; lanes stride over j.  Integer row dots are
+// exact in int32 (validated row bound < 2^24); float dots accumulate in double.
+constexpr int ER = 16;
+
+template <typename TQ, bool INT>
+__global__ void __launch_bounds__(256) k_energy_dense(int64_t n, const TQ *__restrict__ Q,
+                                                      const int64_t *__restrict__ b_i64,
+                                                      const double *__restrict__ b_f64,
+                                                      const int8_t *__restrict__ s, int64_t R,
+                                                      double *__restrict__ partial) {
+    const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+    const int64_t i = (int64_t)blockIdx.x * 4 + wv;
+    const int64_t r0 = (int64_t)blockIdx.y * ER;
+    __shared__ double red[4][ER];
+    double contrib[ER];
+#pragma unroll
+    for (int q = 0; q < ER; ++q) contrib[q] = 0.0;
+    if (i < n) {
+        const TQ *row = Q + i * n;
+        int32_t di[ER];
+        double df[ER];
+#pragma unroll
+        for (int q = 0; q < ER; ++q) {
+            di[q] = 0;
+            df[q] = 0.0;
+        }
+        for (int64_t j = lane; j < n; j += WAVE) {
+            TQ qv = (j == i) ? TQ(0) : row[j];
+#pragma unroll
+            for (int q = 0; q < ER; ++q) {
+                int64_t r = r0 + q;
+                if (r < R) {
+                    int8_t sj = s[r * n + j];
+                    if (INT) di[q] += (sj > 0) ? (int32_t)qv : -(int32_t)qv;
+                    else df[q] += (sj > 0) ? (double)qv : -(double)qv;
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < ER; ++q) {
+            int64_t r = r0 + q;
+            double d;
+            if (INT) {
+                int64_t v = di[q];
+                for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+                d = (double)v;
+            } else {
+                d = wave_sum(df[q]);
+            }
+            if (r < R) {
+                double si = (double)s[r * n + i];
+                if (INT) contrib[q] = si * (d + 2.0 * (double)b_i64[i]);
+                else contrib[q] = si * (0.5 * d + b_f64[i]);
+            }
+        }
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < ER; ++q) red[wv][q] = contrib[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < ER) {
+        int q = threadIdx.x;
+        int64_t r = r0 + q;
+        if (r < R) {
+            double v = red[0][q] + red[1][q] + red[2][q] + red[3][q];
+            partial[(int64_t)blockIdx.x * R + r] = v;
+        }
+    }
+}
+
+// CSR: one thread per row, replicas r0 .. r0+ER.
+template <typename TW, typename TI, bool INT>
+__global__ void __launch_bounds__(256) k_energy_csr(int64_t n, const int32_t *__restrict__ rp,
+                                                    const TI *__restrict__ col,
+                                                    const TW *__restrict__ w,
+                                                    const int64_t *__restrict__ b_i64,
+                                                    const double *__restrict__ b_f64,
+                                                    const int8_t *__restrict__ s, int64_t R,
+                                                    double *__restrict__ partial) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.y * ER;
+    __shared__ double red[256 / WAVE][ER];
+    double contrib[ER];
+#pragma unroll
+    for (int q = 0; q < ER; ++q) contrib[q] = 0.0;
+    if (i < n) {
+        const int64_t k0 = rp[i], k1 = rp[i + 1];
+#pragma unroll
+        for (int q = 0; q < ER; ++q) {
+            int64_t r = r0 + q;
+            if (r >= R) continue;
+            const int8_t *sr = s + r * n;
+            int64_t di = 0;
+            double df = 0.0;
+            for (int64_t k = k0; k < k1; ++k) {
+                int64_t j = (int64_t)col[k];
+                if (j == i) continue;
+                if (INT) di += (sr[j] > 0) ? (int64_t)w[k] : -(int64_t)w[k];
+                else df += (sr[j] > 0) ? (double)w[k] : -(double)w[k];
+            }
+            double si = (double)sr[i];
+            if (INT) contrib[q] = si * ((double)di + 2.0 * (double)b_i64[i]);
+            else contrib[q] = si * (0.5 * df + b_f64[i]);
+        }
+    }
+    const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+#pragma unroll
+    for (int q = 0; q < ER; ++q) {
+        double v = wave_sum(contrib[q]);
+        if (lane == 0) red[wv][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < ER) {
+        int q = threadIdx.x;
+        int64_t r = r0 + q;
+        if (r < R) {
+            double v = 0.0;
+            for (int k = 0; k < (int)(blockDim.x / WAVE); ++k) v += red[k][q];
+            partial[(int64_t)blockIdx.x * R + r] = v;
+        }
+    }
+}
+
+// energy[r] = sum over blocks of partial[b][r] (fixed order), then the QUBO constant.
+// For integer instances the partials are exact integers (< 2^53) and the total is taken
+// in int64.
+__global__ void __launch_bounds__(256) k_energy_finalize(int64_t R, int64_t nblk,
+                                                         const double *__restrict__ partial,
+                                                         int32_t is_int, int32_t is_qubo,
+                                                         const CanonScalars *sc,
+                                                         int64_t *__restrict__ e_i64,
+                                                         double *__restrict__ e_f64) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    if (is_int) {
+        int64_t two_h = 0;
+        for (int64_t b = 0; b < nblk; ++b) two_h += (int64_t)partial[b * R + r];
+        int64_t H = two_h / 2;               // 2H is even: sum_i s_i (d_i + 2 b_i), d = 2 x pairs
+        int64_t E = is_qubo ? (H + sc->K_i64) / 2 : H;
+        if (e_i64) e_i64[r] = E;
+        e_f64[r] = (double)E;
+    } else {
+        double H = 0.0;
+        for (int64_t b = 0; b < nblk; ++b) H += partial[b * R + r];
+        e_f64[r] = is_qubo ? 0.5 * (H + sc->K_f64) : H;
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_argmin(int64_t R, const int64_t *e_i64,
+                                                 const double *e_f64, int32_t *best) {
+    __shared__ double sv[1024];
+    __shared__ int64_t si[1024];
+    __shared__ int64_t sv_i[1024];
+    double bv = INFINITY;
+    int64_t bvi = INT64_MAX;
+    int64_t bi = INT64_MAX;
+    for (int64_t r = threadIdx.x; r < R; r += blockDim.x) {
+        if (e_i64) {
+            int64_t v = e_i64[r];
+            if (v < bvi || (v == bvi && r < bi)) {
+                bvi = v;
+                bi = r;
+            }
+        } else {
+            double v = e_f64[r];
+            if (v < bv || (v == bv && r < bi) || bi == INT64_MAX) {
+                bv = v;
+                bi = r;
+            }
+        }
+    }
+    sv[threadIdx.x] = bv;
+    sv_i[threadIdx.x] = bvi;
+    si[threadIdx.x] = bi;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            int a = threadIdx.x, b = threadIdx.x + o;
+            bool take;
+            if (e_i64) take = sv_i[b] < sv_i[a] || (sv_i[b] == sv_i[a] && si[b] < si[a]);
+            else take = si[b] != INT64_MAX &&
+                        (si[a] == INT64_MAX || sv[b] < sv[a] || (sv[b] == sv[a] && si[b] < si[a]));
+            if (take) {
+                sv[a] = sv[b];
+                sv_i[a] = sv_i[b];
+                si[a] = si[b];
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) best[0] = (int32_t)si[0];
+}
+
+inline unsigned grid1(int64_t total, int block, int64_t cap = 65536) {
+    int64_t g = (total + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+template <typename F> hipError_t dispatch_q(int32_t dt, F &&f) {
+    switch (dt) {
+        case QPA_I8: return f((int8_t)0);
+        case QPA_I16: return f((int16_t)0);
+        case QPA_I32: return f((int32_t)0);
+        case QPA_F32: return f(0.0f);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_canon_dense(const qpa_problem &p, float *J_f32, uint16_t *Jb, int64_t npad,
+                              float *b_f32, int64_t *b_i64, double *b_f64, double *row_abs,
+                              double *row_max, double *row_k, CanonScalars *sc,
+                              hipStream_t st) {
+    const int64_t n = p.n;
+    const int32_t is_qubo = p.kind == QPA_KIND_QUBO;
+    const int32_t is_int = dtype_is_int(p.coupling_dtype) &&
+                           (p.linear == nullptr || dtype_is_int(p.linear_dtype));
+    hipError_t e = hipMemsetAsync(sc, 0, sizeof(CanonScalars), st);
+    if (e != hipSuccess) return e;
+    e = dispatch_q(p.coupling_dtype, [&](auto tag) {
+        using T = decltype(tag);
+        const T *Q = static_cast<const T *>(p.dense);
+        k_dense_rows<T><<<(unsigned)((n + 3) / 4), 256, 0, st>>>(
+            n, Q, p.linear, p.linear_dtype, is_qubo, J_f32, b_f32, b_i64, b_f64, row_abs,
+            row_max, row_k, sc);
+        int64_t nb = (n + 31) / 32;
+        k_dense_sym<T><<<dim3((unsigned)nb, (unsigned)nb), 256, 0, st>>>(n, Q, sc);
+        k_canon_finalize<<<1, 1024, 0, st>>>(n, row_abs, row_max, row_k, is_int, sc);
+        if (Jb) k_dense_bf16<T><<<grid1(npad * npad, 256), 256, 0, st>>>(n, npad, Q, sc, Jb);
+        return hipGetLastError();
+    });
+    return e;
+}
+
+hipError_t launch_canon_csr(const qpa_problem &p, float *b_f32, int64_t *b_i64, double *b_f64,
+                            double *row_abs, double *row_k, CanonScalars *sc, hipStream_t st) {
+    const int64_t n = p.n;
+    const int32_t is_qubo = p.kind == QPA_KIND_QUBO;
+    const int32_t is_int = dtype_is_int(p.coupling_dtype) &&
+                           (p.linear == nullptr || dtype_is_int(p.linear_dtype));
+    hipError_t e = hipMemsetAsync(sc, 0, sizeof(CanonScalars), st);
+    if (e != hipSuccess) return e;
+    auto run = [&](auto wtag, auto itag) {
+        using TW = decltype(wtag);
+        using TI = decltype(itag);
+        k_csr_rows<TW, TI><<<grid1(n, 256, INT64_MAX), 256, 0, st>>>(
+            n, p.nnz, p.row_ptr, static_cast<const TI *>(p.col),
+            static_cast<const TW *>(p.weights), p.linear, p.linear_dtype, is_qubo, b_f32, b_i64,
+            b_f64, row_abs, row_k, sc);
+        k_canon_finalize<<<1, 1024, 0, st>>>(n, row_abs, nullptr, row_k, is_int, sc);
+        return hipGetLastError();
+    };
+    return dispatch_q(p.coupling_dtype, [&](auto wtag) {
+        if (p.index_dtype == QPA_I16) return run(wtag, (int16_t)0);
+        return run(wtag, (int32_t)0);
+    });
+}
+
+hipError_t launch_init_state(int64_t n, int64_t R, uint64_t seed, float sigma0, float *x,
+                             float *m, int64_t ld_r, int64_t ld_i, int64_t Rpad, int64_t npad,
+                             hipStream_t st) {
+    k_init_state<<<grid1(Rpad * npad, 256), 256, 0, st>>>(n, R, seed, sigma0, x, m, ld_r, ld_i,
+                                                          Rpad, npad);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_state(int64_t n, int64_t R, const float *src, int64_t s_ld_r,
+                             int64_t s_ld_i, float *dst, int64_t d_ld_r, int64_t d_ld_i,
+                             hipStream_t st) {
+    if (R * n == 0) return hipSuccess;
+    k_copy_state<<<grid1(R * n, 256), 256, 0, st>>>(n, R, src, s_ld_r, s_ld_i, dst, d_ld_r,
+                                                    d_ld_i);
+    return hipGetLastError();
+}
+
+hipError_t launch_export_spins(int64_t n, int64_t R, const float *x, int64_t ld_r,
+                               int64_t ld_i, int8_t *spins, hipStream_t st) {
+    if (R * n == 0) return hipSuccess;
+    k_export_spins<<<grid1(R * n, 256), 256, 0, st>>>(n, R, x, ld_r, ld_i, spins);
+    return hipGetLastError();
+}
+
+int64_t energy_partial_blocks(const qpa_problem &p) {
+    if (p.format == QPA_FMT_DENSE) return (p.n + 3) / 4;
+    return (p.n + 255) / 256;
+}
+
+hipError_t launch_energy(const qpa_problem &p, const int64_t *b_i64, const double *b_f64,
+                         const CanonScalars *sc, const int8_t *spins, int64_t R,
+                         int64_t *e_i64, double *e_f64, double *partial, int64_t partial_len,
+                         hipStream_t st) {
+    const int64_t n = p.n;
+    const int32_t is_qubo = p.kind == QPA_KIND_QUBO;
+    const bool is_int = dtype_is_int(p.coupling_dtype) &&
+                        (p.linear == nullptr || dtype_is_int(p.linear_dtype));
+    const int64_t nblk = energy_partial_blocks(p);
+    if (nblk * R > partial_len) return hipErrorInvalidValue;
+    const unsigned gy = (unsigned)((R + ER - 1) / ER);
+    hipError_t e;
+    if (p.format == QPA_FMT_DENSE) {
+        e = dispatch_q(p.coupling_dtype, [&](auto tag) {
+            using T = decltype(tag);
+            const T *Q = static_cast<const T *>(p.dense);
+            if (is_int)
+                k_energy_dense<T, true><<<dim3((unsigned)nblk, gy), 256, 0, st>>>(
+                    n, Q, b_i64, b_f64, spins, R, partial);
+            else
+                k_energy_dense<T, false><<<dim3((unsigned)nblk, gy), 256, 0, st>>>(
+                    n, Q, b_i64, b_f64, spins, R, partial);
+            return hipGetLastError();
+        });
+    } else {
+        auto run = [&](auto wtag, auto itag) {
+            using TW = decltype(wtag);
+            using TI = decltype(itag);
+            const TW *w = static_cast<const TW *>(p.weights);
+            const TI *c = static_cast<const TI *>(p.col);
+            if (is_int)
+                k_energy_csr<TW, TI, true><<<dim3((unsigned)nblk, gy), 256, 0, st>>>(
+                    n, p.row_ptr, c, w, b_i64, b_f64, spins, R, partial);
+            else
+                k_energy_csr<TW, TI, false><<<dim3((unsigned)nblk, gy), 256, 0, st>>>(
+                    n, p.row_ptr, c, w, b_i64, b_f64, spins, R, partial);
+            return hipGetLastError();
+        };
+        e = dispatch_q(p.coupling_dtype, [&](auto wtag) {
+            if (p.index_dtype == QPA_I16) return run(wtag, (int16_t)0);
+            return run(wtag, (int32_t)0);
+        });
+    }
+    if (e != hipSuccess) return e;
+    k_energy_finalize<<<grid1(R, 256, INT64_MAX), 256, 0, st>>>(R, nblk, partial, is_int ? 1 : 0,
+                                                                 is_qubo, sc,
+                                                                 is_int ? e_i64 : nullptr, e_f64);
+    return hipGetLastError();
+}
+
+hipError_t launch_argmin(int64_t R, const int64_t *e_i64, const double *e_f64, int32_t *best,
+                         hipStream_t st) {
+    k_argmin<<<1, 1024, 0, st>>>(R, e_i64, e_f64, best);
+    return hipGetLastError();
+}
+
+}  // namespace qpa

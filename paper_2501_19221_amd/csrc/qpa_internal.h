@@ -1,0 +1,134 @@
+// Internal declarations shared by the HIP translation units of libqpa.
+// Nothing here is part of the public C ABI (include/qpa.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/qpa.h"
+
+namespace qpa {
+
+// Validation flags written by the set-up kernels (bit mask in a device int32).
+enum : int32_t {
+    FLAG_ASYM = 1,        // Q or J not symmetric / Ising diagonal non-zero
+    FLAG_RANGE = 2,       // integer row bound >= 2^24
+    FLAG_SHAPE = 4,       // CSR row pointers / column indices inconsistent
+    FLAG_UNSORTED = 8,    // CSR row columns not strictly increasing
+};
+
+// Scalars produced by canonicalisation, kept in device memory.
+struct CanonScalars {
+    int64_t K_i64;        // 2E = H + K for integer QUBO instances (0 for Ising)
+    double K_f64;         // same for float instances
+    float scale;          // 2^e of the BF16 storage
+    float inv_scale;      // 2^-e
+    int32_t flags;        // validation bit mask
+    int32_t exp2;         // e
+    double max_row;       // max_i sum_j |J_ij| + |b_i|
+    double max_abs;       // max |J_ij| (i != j)
+};
+
+// Element types of the caller's arrays.
+inline size_t dtype_size(int32_t dt) {
+    switch (dt) {
+        case QPA_I8: return 1;
+        case QPA_I16: return 2;
+        case QPA_I32: return 4;
+        case QPA_F32: return 4;
+        default: return 0;
+    }
+}
+inline bool dtype_is_int(int32_t dt) { return dt == QPA_I8 || dt == QPA_I16 || dt == QPA_I32; }
+
+// -------------------------------------------------------------------------------------
+// Launchers (each returns hipSuccess or the first HIP error).
+// -------------------------------------------------------------------------------------
+
+// Canonicalisation of a dense problem: J_f32 (n*n, diagonal zero), b_f32 (n),
+// b_i64 / b_f64 (n), per-row partials, then scalars.  Jb (npad*npad bf16) is filled when
+// non-null with bf16(J / 2^e), zero padded.
+hipError_t launch_canon_dense(const qpa_problem &p, float *J_f32, uint16_t *Jb, int64_t npad,
+                              float *b_f32, int64_t *b_i64, double *b_f64, double *row_abs,
+                              double *row_max, double *row_diag, CanonScalars *sc,
+                              hipStream_t st);
+
+// Canonicalisation of a CSR problem: b_f32 / b_i64 / b_f64, validation, scalars.
+hipError_t launch_canon_csr(const qpa_problem &p, float *b_f32, int64_t *b_i64, double *b_f64,
+                            double *row_abs, double *row_diag, CanonScalars *sc, hipStream_t st);
+
+// x0 / m0 from the counter RNG.  Layout: element (r, i) at x[r * ld_r + i * ld_i].
+hipError_t launch_init_state(int64_t n, int64_t R, uint64_t seed, float sigma0, float *x,
+                             float *m, int64_t ld_r, int64_t ld_i, int64_t Rpad, int64_t npad,
+                             hipStream_t st);
+
+// Copy a [R][n] state into / out of a strided internal layout.
+hipError_t launch_copy_state(int64_t n, int64_t R, const float *src, int64_t s_ld_r,
+                             int64_t s_ld_i, float *dst, int64_t d_ld_r, int64_t d_ld_i,
+                             hipStream_t st);
+
+// spins[r*n+i] = sign(x(r,i)) (int8).
+hipError_t launch_export_spins(int64_t n, int64_t R, const float *x, int64_t ld_r,
+                               int64_t ld_i, int8_t *spins, hipStream_t st);
+
+// Exact energies of int8 spins [R][n] from the caller's original couplings.
+// Integer: e_i64[r] = objective (and e_f64 = (double)e_i64).  Float: e_f64 only.
+hipError_t launch_energy(const qpa_problem &p, const int64_t *b_i64, const double *b_f64,
+                         const CanonScalars *sc, const int8_t *spins, int64_t R,
+                         int64_t *e_i64, double *e_f64, double *partial, int64_t partial_len,
+                         hipStream_t st);
+
+// best[0] = lowest r with minimal energy.
+hipError_t launch_argmin(int64_t R, const int64_t *e_i64, const double *e_f64, int32_t *best,
+                         hipStream_t st);
+
+// ---- dense PA steps ------------------------------------------------------------------
+// Small instances: couplings in LDS, all steps of a replica block in one launch.
+bool dense_resident_fits(int64_t n);
+hipError_t launch_dense_resident(int64_t n, int64_t R, const float *J, const float *b,
+                                 float *x, float *m, float *h_last, int32_t t0, int32_t t1,
+                                 const float *lam, float eta, float alpha, hipStream_t st);
+
+// Any size: one launch per step, FP32 sequential sums (same order as the definition).
+// s_cur / s_nxt: float +-1 [R][n]; x, m, h_last: [R][n].
+hipError_t launch_dense_tiled_step(int64_t n, int64_t R, const float *J, const float *b,
+                                   const float *s_cur, float *s_nxt, float *x, float *m,
+                                   float *h_last, int32_t t, const float *lam, float eta,
+                                   float alpha, hipStream_t st);
+hipError_t launch_sign_f32(int64_t count, const float *x, float *s, hipStream_t st);
+
+// BF16 matrix-core path.  Internal padded layout: x, m [Rp][np] FP32, spin bits
+// [Rp][np/32] uint32 (bit set <=> spin -1), Jb [np][np] bf16.
+constexpr int MF_BM = 128;   // replicas per tile
+constexpr int MF_BN = 128;   // variables per tile
+constexpr int MF_BK = 64;    // reduction chunk
+hipError_t launch_mfma_pack_spins(int64_t Rp, int64_t np, const float *x, uint32_t *sbits,
+                                  hipStream_t st);
+hipError_t launch_mfma_step(int64_t Rp, int64_t np, const uint16_t *Jb, const float *b,
+                            const CanonScalars *sc, const uint32_t *s_cur, uint32_t *s_nxt,
+                            float *x, float *m, float *h_last, int32_t t, const float *lam,
+                            float eta, float alpha, hipStream_t st);
+
+// ---- CSR PA steps --------------------------------------------------------------------
+// Internal layout: x, m [np][Rp] (replica fastest, Rp a multiple of the replica group
+// G), spin bits: words of 64 bits, group g, word w = bits of variables
+// w*V .. w*V+V-1 (V = 64/G), G bits per variable, bit set <=> spin -1.
+struct CsrView {
+    int64_t n;
+    const int32_t *rp;
+    const void *col;
+    const void *w;
+    int32_t col_dt, w_dt;
+    bool skip_diag;      // QUBO: diagonal entries are folded into b
+};
+int csr_group_size(int64_t R);
+int64_t csr_words_per_group(int64_t n, int G);
+hipError_t launch_csr_pack_spins(int64_t n, int64_t Rp, int G, const float *x, uint64_t *sbits,
+                                 hipStream_t st);
+hipError_t launch_csr_step(const CsrView &c, int64_t Rp, int G, const float *b_f32,
+                           const uint64_t *s_cur, uint64_t *s_nxt, float *x, float *m,
+                           float *h_last, int32_t t, const float *lam, float eta, float alpha,
+                           bool is_int, hipStream_t st);
+
+}  // namespace qpa

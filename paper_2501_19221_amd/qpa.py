@@ -1,0 +1,329 @@
+"""Thin ctypes binding of libqpa (include/qpa.h).
+
+The functions named like the C entry points (``qpa_solve``, ``qpa_steps``, ...) only
+marshal arguments: torch tensors supply device memory and the current HIP stream, and
+every step of the method runs in the library's kernels.  Importing this module fails
+loudly if the built library is missing -- there is no fallback path.
+
+Convenience layer: ``Problem`` wraps device tensors of one instance and ``solve`` /
+``steps`` / ``energy`` allocate outputs and the workspace with torch and call the C ABI.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqpa.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libqpa.so is not built: run `python -m paper_2501_19221_amd.build` "
+                      "(expected at %s)" % LIB_PATH)
+# torch brings its own HIP runtime; loading it first makes libqpa bind to that same copy
+# (a process must hold a single HIP runtime -- a second one finds no device).
+import torch  # noqa: E402,F401
+_lib = ctypes.CDLL(LIB_PATH)
+
+# ---- enums (mirror include/qpa.h) ---------------------------------------------------
+QPA_OK, QPA_E_ARG, QPA_E_SHAPE, QPA_E_ASYM, QPA_E_RANGE, QPA_E_WORKSPACE, QPA_E_DEVICE, \
+    QPA_E_UNSUPPORTED = range(8)
+QPA_KIND_QUBO, QPA_KIND_ISING = 0, 1
+QPA_FMT_DENSE, QPA_FMT_CSR = 0, 1
+QPA_I8, QPA_I16, QPA_I32, QPA_F32 = 0, 1, 2, 3
+QPA_PREC_FP32, QPA_PREC_BF16 = 0, 1
+
+EXPORTED = ["qpa_create", "qpa_destroy", "qpa_last_error", "qpa_status_string",
+            "qpa_workspace_size", "qpa_solve", "qpa_steps", "qpa_energy", "qpa_version",
+            "qpa_profile_enable", "qpa_profile_read"]
+
+
+class qpa_problem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("kind", ctypes.c_int32), ("format", ctypes.c_int32),
+                ("coupling_dtype", ctypes.c_int32), ("index_dtype", ctypes.c_int32),
+                ("linear_dtype", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("dense", ctypes.c_void_p), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p),
+                ("weights", ctypes.c_void_p), ("linear", ctypes.c_void_p)]
+
+
+class qpa_params(ctypes.Structure):
+    _fields_ = [("replicas", ctypes.c_int32), ("steps", ctypes.c_int32),
+                ("eta", ctypes.c_float), ("alpha", ctypes.c_float),
+                ("lambda0", ctypes.c_float), ("sigma0", ctypes.c_float),
+                ("lambda_table", ctypes.c_void_p), ("seed", ctypes.c_uint64),
+                ("precision", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class qpa_outputs(ctypes.Structure):
+    _fields_ = [("spins", ctypes.c_void_p), ("energy", ctypes.c_void_p),
+                ("energy_i64", ctypes.c_void_p), ("best", ctypes.c_void_p),
+                ("x", ctypes.c_void_p), ("m", ctypes.c_void_p)]
+
+
+_P = ctypes.c_void_p
+_S = ctypes.c_int
+_sig = {
+    "qpa_create": (_S, [ctypes.POINTER(_P), ctypes.c_int]),
+    "qpa_destroy": (None, [_P]),
+    "qpa_last_error": (ctypes.c_char_p, [_P]),
+    "qpa_status_string": (ctypes.c_char_p, [_S]),
+    "qpa_version": (ctypes.c_char_p, []),
+    "qpa_workspace_size": (_S, [_P, ctypes.POINTER(qpa_problem), ctypes.POINTER(qpa_params),
+                                ctypes.POINTER(ctypes.c_size_t)]),
+    "qpa_solve": (_S, [_P, ctypes.POINTER(qpa_problem), ctypes.POINTER(qpa_params), _P,
+                       ctypes.c_size_t, _P, ctypes.POINTER(qpa_outputs)]),
+    "qpa_steps": (_S, [_P, ctypes.POINTER(qpa_problem), ctypes.POINTER(qpa_params),
+                       ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "qpa_energy": (_S, [_P, ctypes.POINTER(qpa_problem), ctypes.POINTER(qpa_params), _P, _P,
+                        _P, _P, _P, ctypes.c_size_t, _P]),
+    "qpa_profile_enable": (_S, [_P, ctypes.c_int32]),
+    "qpa_profile_read": (_S, [_P, ctypes.POINTER(ctypes.c_double),
+                              ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class QpaError(RuntimeError):
+    def __init__(self, status, message):
+        self.status = status
+        name = _lib.qpa_status_string(status).decode()
+        super().__init__("%s: %s" % (name, message))
+
+
+# ---- C entry points under their own names --------------------------------------------
+def qpa_create(device: int = 0):
+    h = _P()
+    st = _lib.qpa_create(ctypes.byref(h), device)
+    if st != QPA_OK:
+        raise QpaError(st, "qpa_create(device=%d) failed: %s" % (device, qpa_last_error(None)))
+    return h
+
+
+def qpa_destroy(ctx):
+    _lib.qpa_destroy(ctx)
+
+
+def qpa_last_error(ctx) -> str:
+    return _lib.qpa_last_error(ctx).decode()
+
+
+def qpa_status_string(status: int) -> str:
+    return _lib.qpa_status_string(status).decode()
+
+
+def qpa_version() -> str:
+    return _lib.qpa_version().decode()
+
+
+def _check(ctx, st):
+    if st != QPA_OK:
+        raise QpaError(st, qpa_last_error(ctx))
+
+
+def qpa_workspace_size(ctx, problem: qpa_problem, params: qpa_params) -> int:
+    nbytes = ctypes.c_size_t()
+    _check(ctx, _lib.qpa_workspace_size(ctx, ctypes.byref(problem), ctypes.byref(params),
+                                        ctypes.byref(nbytes)))
+    return nbytes.value
+
+
+def qpa_solve(ctx, problem, params, workspace, workspace_bytes, stream, outputs):
+    _check(ctx, _lib.qpa_solve(ctx, ctypes.byref(problem), ctypes.byref(params), workspace,
+                               workspace_bytes, stream, ctypes.byref(outputs)))
+
+
+def qpa_steps(ctx, problem, params, t0, t1, x, m, h_last, workspace, workspace_bytes, stream):
+    _check(ctx, _lib.qpa_steps(ctx, ctypes.byref(problem), ctypes.byref(params), t0, t1, x, m,
+                               h_last, workspace, workspace_bytes, stream))
+
+
+def qpa_energy(ctx, problem, params, spins, energy, energy_i64, best, workspace,
+               workspace_bytes, stream):
+    _check(ctx, _lib.qpa_energy(ctx, ctypes.byref(problem), ctypes.byref(params), spins, energy,
+                                energy_i64, best, workspace, workspace_bytes, stream))
+
+
+def qpa_profile_enable(ctx, enable: bool):
+    _check(ctx, _lib.qpa_profile_enable(ctx, 1 if enable else 0))
+
+
+def qpa_profile_read(ctx, reset: bool = True):
+    """Returns (summed step-kernel milliseconds, step-kernel launches)."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(ctx, _lib.qpa_profile_read(ctx, ctypes.byref(ms), ctypes.byref(n), 1 if reset else 0))
+    return ms.value, n.value
+
+
+# ---- convenience layer (torch supplies memory and streams) ---------------------------
+_DT = {"int8": QPA_I8, "int16": QPA_I16, "int32": QPA_I32, "float32": QPA_F32}
+
+
+def _dt_code(t):
+    name = str(t.dtype).replace("torch.", "")
+    if name not in _DT:
+        raise TypeError("unsupported dtype %s" % t.dtype)
+    return _DT[name]
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class Problem:
+    """One instance held in device tensors (kept referenced here while in use)."""
+    kind: int
+    n: int
+    dense: object = None
+    row_ptr: object = None
+    col: object = None
+    weights: object = None
+    linear: object = None
+
+    def struct(self) -> qpa_problem:
+        p = qpa_problem()
+        p.n = self.n
+        p.kind = self.kind
+        if self.dense is not None:
+            p.format = QPA_FMT_DENSE
+            p.coupling_dtype = _dt_code(self.dense)
+            p.dense = self.dense.data_ptr()
+        else:
+            p.format = QPA_FMT_CSR
+            p.coupling_dtype = _dt_code(self.weights)
+            p.index_dtype = _dt_code(self.col)
+            p.nnz = int(self.col.numel())
+            p.row_ptr = self.row_ptr.data_ptr()
+            p.col = self.col.data_ptr() if self.col.numel() else None
+            p.weights = self.weights.data_ptr() if self.weights.numel() else None
+        if self.linear is not None:
+            p.linear_dtype = _dt_code(self.linear)
+            p.linear = self.linear.data_ptr()
+        return p
+
+    @staticmethod
+    def from_instance(inst, device="cuda"):
+        """Upload a paper_2501_19221_amd.instances.Instance to device tensors."""
+        import torch
+        kind = QPA_KIND_QUBO if inst.kind == "qubo" else QPA_KIND_ISING
+        lin = None if inst.lin is None else torch.from_numpy(
+            np.ascontiguousarray(inst.lin)).to(device)
+        if inst.dense is not None:
+            return Problem(kind, inst.n, dense=torch.from_numpy(
+                np.ascontiguousarray(inst.dense)).to(device), linear=lin)
+        c = inst.csr
+        return Problem(kind, inst.n,
+                       row_ptr=torch.from_numpy(c.rp.astype(np.int32)).to(device),
+                       col=torch.from_numpy(np.ascontiguousarray(c.col)).to(device),
+                       weights=torch.from_numpy(np.ascontiguousarray(c.w)).to(device),
+                       linear=lin)
+
+
+def make_params(replicas, steps, eta, alpha, lambda0, sigma0=0.1, seed=1, precision=QPA_PREC_FP32,
+                lambda_table=None):
+    p = qpa_params()
+    p.replicas = replicas
+    p.steps = steps
+    p.eta = eta
+    p.alpha = alpha
+    p.lambda0 = lambda0
+    p.sigma0 = sigma0
+    p.seed = seed & (2**64 - 1)
+    p.precision = precision
+    p.flags = 0
+    keep = None
+    if lambda_table is not None:
+        keep = np.ascontiguousarray(lambda_table, dtype=np.float32)
+        assert keep.shape == (steps,)
+        p.lambda_table = keep.ctypes.data
+    p._keep = keep            # host table must outlive the call
+    return p
+
+
+class Engine:
+    """A context on one device plus a reusable torch workspace."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self.torch = torch
+        self.device = device
+        torch.cuda.init()                 # one HIP runtime per process: let torch set it up
+        torch.cuda.set_device(device)
+        self.ctx = qpa_create(device)
+        self._ws = None
+
+    def close(self):
+        if self.ctx:
+            qpa_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace(self, problem: qpa_problem, params: qpa_params):
+        nbytes = qpa_workspace_size(self.ctx, problem, params)
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = self.torch.empty(max(nbytes, 256), dtype=self.torch.uint8,
+                                        device="cuda:%d" % self.device)
+        return self._ws, nbytes
+
+    def _stream(self):
+        return ctypes.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
+
+    def solve(self, prob: Problem, params: qpa_params, want_state=False):
+        """Returns dict(spins [R,n] int8, energy [R] f64, energy_i64 [R] or None,
+        best int tensor [1], x, m) -- device tensors."""
+        torch = self.torch
+        dev = "cuda:%d" % self.device
+        R, n = params.replicas, prob.n
+        ps = prob.struct()
+        ws, nbytes = self.workspace(ps, params)
+        out = {"spins": torch.empty((R, n), dtype=torch.int8, device=dev),
+               "energy": torch.empty(R, dtype=torch.float64, device=dev),
+               "best": torch.empty(1, dtype=torch.int32, device=dev),
+               "energy_i64": torch.empty(R, dtype=torch.int64, device=dev),
+               "x": torch.empty((R, n), dtype=torch.float32, device=dev) if want_state else None,
+               "m": torch.empty((R, n), dtype=torch.float32, device=dev) if want_state else None}
+        o = qpa_outputs()
+        o.spins = out["spins"].data_ptr()
+        o.energy = out["energy"].data_ptr()
+        o.energy_i64 = out["energy_i64"].data_ptr()
+        o.best = out["best"].data_ptr()
+        o.x = out["x"].data_ptr() if want_state else None
+        o.m = out["m"].data_ptr() if want_state else None
+        qpa_solve(self.ctx, ps, params, ctypes.c_void_p(ws.data_ptr()), nbytes, self._stream(), o)
+        return out
+
+    def steps(self, prob: Problem, params: qpa_params, t0: int, t1: int, x, m, want_h=False):
+        """Advance device tensors x, m ([R,n] float32, contiguous) in place; returns h or None."""
+        torch = self.torch
+        assert x.is_contiguous() and m.is_contiguous() and x.dtype == torch.float32
+        ps = prob.struct()
+        ws, nbytes = self.workspace(ps, params)
+        h = torch.empty_like(x) if want_h else None
+        qpa_steps(self.ctx, ps, params, t0, t1, _ptr(x), _ptr(m), _ptr(h),
+                  ctypes.c_void_p(ws.data_ptr()), nbytes, self._stream())
+        return h
+
+    def energy(self, prob: Problem, params: qpa_params, spins):
+        torch = self.torch
+        R = spins.shape[0]
+        dev = spins.device
+        ps = prob.struct()
+        ws, nbytes = self.workspace(ps, params)
+        e = torch.empty(R, dtype=torch.float64, device=dev)
+        ei = torch.empty(R, dtype=torch.int64, device=dev)
+        best = torch.empty(1, dtype=torch.int32, device=dev)
+        qpa_energy(self.ctx, ps, params, _ptr(spins), _ptr(e), _ptr(ei), _ptr(best),
+                   ctypes.c_void_p(ws.data_ptr()), nbytes, self._stream())
+        return e, ei, best

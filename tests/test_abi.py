@@ -1,0 +1,123 @@
+"""Host-side checks of the C ABI library (no GPU needed): it loads, exports every symbol
+include/qpa.h declares, and its argument validation and workspace planning behave as
+documented.  No compute call is made here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qpa.h")
+
+
+@pytest.fixture(scope="module")
+def q():
+    from paper_2501_19221_amd import build
+    if not os.path.exists(build.LIB):
+        build.build()
+    from paper_2501_19221_amd import qpa
+    return qpa
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(qpa_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for must in ["qpa_create", "qpa_solve", "qpa_steps", "qpa_energy", "qpa_workspace_size"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(q):
+    lib = ctypes.CDLL(q.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(declared_functions()) <= set(q.EXPORTED)
+
+
+def test_status_strings(q):
+    assert q.qpa_status_string(q.QPA_OK) == "QPA_OK"
+    assert q.qpa_status_string(q.QPA_E_ASYM) == "QPA_E_ASYM"
+    assert q.qpa_version().startswith("qpa")
+
+
+def _dense_problem(q, n=10, dt=None):
+    p = q.qpa_problem()
+    p.n = n
+    p.kind = q.QPA_KIND_QUBO
+    p.format = q.QPA_FMT_DENSE
+    p.coupling_dtype = q.QPA_I32 if dt is None else dt
+    p.dense = 0x1000          # never dereferenced by the host-side checks
+    return p
+
+
+def _ws(q, p, a):
+    n = ctypes.c_size_t()
+    st = q._lib.qpa_workspace_size(None, ctypes.byref(p), ctypes.byref(a), ctypes.byref(n))
+    return st, n.value
+
+
+def test_workspace_size_paths(q):
+    a = q.make_params(256, 2000, 0.002, 0.9, 30.0)
+    st, small = _ws(q, _dense_problem(q, 20), a)
+    assert st == q.QPA_OK and small > 0
+    st, tiled = _ws(q, _dense_problem(q, 300), a)
+    assert st == q.QPA_OK and tiled > 300 * 300 * 4
+    a16 = q.make_params(1024, 10, 0.1, 0.8, 4.0, precision=q.QPA_PREC_BF16)
+    st, mf = _ws(q, _dense_problem(q, 4096, q.QPA_F32), a16)
+    assert st == q.QPA_OK and mf >= 4096 * 4096 * 2 + 3 * 1024 * 4096 * 4
+
+
+def test_argument_validation(q):
+    a = q.make_params(4, 10, 0.1, 0.5, 1.0)
+    p = _dense_problem(q)
+    p.n = 0
+    assert _ws(q, p, a)[0] == q.QPA_E_SHAPE
+    p = _dense_problem(q)
+    p.dense = None
+    assert _ws(q, p, a)[0] == q.QPA_E_ARG
+    p = _dense_problem(q)
+    p.kind = 7
+    assert _ws(q, p, a)[0] == q.QPA_E_ARG
+    bad = q.make_params(0, 10, 0.1, 0.5, 1.0)
+    assert _ws(q, _dense_problem(q), bad)[0] == q.QPA_E_ARG
+    bad = q.make_params(4, -1, 0.1, 0.5, 1.0)
+    assert _ws(q, _dense_problem(q), bad)[0] == q.QPA_E_ARG
+    bad = q.make_params(4, 10, 0.1, 0.5, 1.0)
+    bad.flags = 3
+    assert _ws(q, _dense_problem(q), bad)[0] == q.QPA_E_ARG
+    c = q.qpa_problem()
+    c.n = 40000
+    c.format = q.QPA_FMT_CSR
+    c.kind = q.QPA_KIND_ISING
+    c.coupling_dtype = q.QPA_I8
+    c.index_dtype = q.QPA_I16
+    c.row_ptr = 0x1000
+    c.col = 0x1000
+    c.weights = 0x1000
+    c.nnz = 10
+    assert _ws(q, c, a)[0] == q.QPA_E_SHAPE       # int16 indices cannot address 40000 rows
+    c.index_dtype = q.QPA_I32
+    assert _ws(q, c, a)[0] == q.QPA_OK
+    c.nnz = -1
+    assert _ws(q, c, a)[0] == q.QPA_E_SHAPE
+
+
+def test_solve_rejects_null_context_and_bad_workspace(q):
+    a = q.make_params(4, 10, 0.1, 0.5, 1.0)
+    p = _dense_problem(q)
+    o = q.qpa_outputs()
+    st = q._lib.qpa_solve(None, ctypes.byref(p), ctypes.byref(a), None, 0, None, ctypes.byref(o))
+    assert st == q.QPA_E_ARG
+
+
+def test_create_without_device_fails_cleanly(q):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    assert q._lib.qpa_create(ctypes.byref(h), 0) == q.QPA_E_DEVICE

@@ -1,0 +1,368 @@
+"""Parity of the HIP path (called through the C ABI) with the CPU oracle.
+
+Integer couplings, and float couplings on the FP32 paths (which sum every field in
+ascending column order, as the oracle does), must match bit for bit: final analog
+states, momenta, spins, exact energies and the best replica.  The BF16 matrix-core path
+sums in another order, so float couplings there are checked one step at a time from the
+oracle's state (teacher forcing) within 1e-5 relative to each row's magnitude; integer
+couplings small enough to be exact in BF16 must again match bit for bit.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as orc
+from paper_2501_19221_amd import instances as gen
+from paper_2501_19221_amd.configs import WORKLOADS
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print("[gpu-parity] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def q():
+    from paper_2501_19221_amd import qpa
+    return qpa
+
+
+@pytest.fixture(scope="module")
+def eng(q):
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    e = q.Engine(0)
+    yield e
+    e.close()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def _params(q, R, T, eta, alpha, lam0, sigma0=0.1, seed=1, prec="fp32"):
+    return q.make_params(R, T, eta, alpha, lam0, sigma0, seed,
+                         q.QPA_PREC_BF16 if prec == "bf16" else q.QPA_PREC_FP32)
+
+
+def _check_solve_dense_int(q, eng, inst, R, T, eta, alpha, lam0, prec="fp32", seed=1):
+    prob = q.Problem.from_instance(inst)
+    p = _params(q, R, T, eta, alpha, lam0, seed=seed, prec=prec)
+    say("dense int %s n=%d R=%d T=%d prec=%s" % (inst.kind, inst.n, R, T, prec))
+    out = eng.solve(prob, p, want_state=True)
+    lam = orc.lambda_linear(T, lam0)
+    ref = orc.solve_dense_int(inst.dense, inst.lin, inst.kind, R, T, lam, eta, alpha, seed, 0.1)
+    assert np.array_equal(host(out["x"]), ref.x)
+    assert np.array_equal(host(out["m"]), ref.m)
+    assert np.array_equal(host(out["spins"]), ref.spins)
+    assert np.array_equal(host(out["energy_i64"]), ref.energy)
+    assert np.array_equal(host(out["energy"]), ref.energy.astype(np.float64))
+    assert int(host(out["best"])[0]) == ref.best
+    return out, ref
+
+
+# ------------------------------------------------------------------ dense, integer
+def test_dense20_full_workload_bit_exact(q, eng):
+    wl = WORKLOADS["dense20"]
+    inst = wl.make()
+    out, ref = _check_solve_dense_int(q, eng, inst, wl.replicas, wl.steps, wl.eta, wl.alpha,
+                                      wl.lambda0)
+    J, b, K = orc.qubo_to_ising_int(inst.dense, inst.lin)
+    Hmin, _ = orc.bruteforce_ising_int(J, b)
+    assert ref.energy.min() == (Hmin + K) // 2          # best-of-replica reaches the optimum
+
+
+def test_dense20_bf16_path_is_exact_for_small_integers(q, eng):
+    wl = WORKLOADS["dense20"]
+    _check_solve_dense_int(q, eng, wl.make(), wl.replicas, wl.steps, wl.eta, wl.alpha,
+                           wl.lambda0, prec="bf16")
+
+
+@pytest.mark.parametrize("n,R,T", [(300, 70, 50), (129, 3, 30), (1, 1, 5), (2, 1, 0)])
+def test_dense_int_ising_ragged(q, eng, n, R, T):
+    inst = gen.dense_int_ising(n, -9, 9, seed=n)
+    _check_solve_dense_int(q, eng, inst, R, T, 0.01, 0.7, 5.0)
+
+
+def test_dense_int_bf16_ragged_tiles(q, eng):
+    inst = gen.dense_int_ising(200, -50, 50, seed=8)
+    _check_solve_dense_int(q, eng, inst, 130, 40, 0.001, 0.7, 50.0, prec="bf16")
+
+
+# ------------------------------------------------------------------ dense, float
+def _oracle_dense_float(J, b, R, T, lam, eta, alpha, seed=1):
+    x, m = orc.pa_init(J.shape[0], R, seed, np.float32(0.1))
+    orc.pa_steps_dense_float(J, b, x, m, 0, T, lam, eta, alpha)
+    return x, m
+
+
+@pytest.mark.parametrize("n,R,T", [(300, 70, 40), (64, 5, 100)])
+def test_dense_float_fp32_bit_exact(q, eng, n, R, T):
+    inst = gen.sk_ising(n, 0.1, seed=n)
+    prob = q.Problem.from_instance(inst)
+    p = _params(q, R, T, 0.2, 0.8, 4.0)
+    say("dense float fp32 n=%d R=%d T=%d" % (n, R, T))
+    out = eng.solve(prob, p, want_state=True)
+    x, m = _oracle_dense_float(inst.dense, inst.lin, R, T, orc.lambda_linear(T, 4.0), 0.2, 0.8)
+    assert np.array_equal(host(out["x"]), x)
+    assert np.array_equal(host(out["m"]), m)
+    s = np.where(x >= 0, 1, -1).astype(np.int8)
+    e = np.array([orc.ising_energy_float(inst.dense.astype(np.float64),
+                                         inst.lin.astype(np.float64), s[r]) for r in range(R)])
+    np.testing.assert_allclose(host(out["energy"]), e, rtol=1e-12, atol=1e-9)
+    assert int(host(out["best"])[0]) == int(np.argmin(e))
+
+
+def test_mfma_float_teacher_forced(q, eng):
+    n, R, T = 300, 70, 60
+    inst = gen.sk_ising(n, 0.1, seed=5)
+    e = orc.bf16_scale_exponent(inst.dense)
+    Jq = orc.bf16_quantise(inst.dense, e)
+    lam = orc.lambda_linear(T, 4.0)
+    prob = q.Problem.from_instance(inst)
+    p = _params(q, R, T, 0.2, 0.8, 4.0, prec="bf16")
+    x, m = orc.pa_init(n, R, 1, np.float32(0.1))
+    rowmag = np.abs(Jq.astype(np.float64)).sum(1) + np.abs(inst.lin)
+    import torch
+    for t in range(T):
+        x0, m0 = x.copy(), m.copy()
+        h_ref = orc.pa_steps_dense_float(Jq, inst.lin, x0, m0, t, t + 1, lam, 0.2, 0.8,
+                                         want_h=True)
+        if t % 15 == 0 or t == T - 1:
+            say("mfma teacher-forced step %d" % t)
+            xd = torch.from_numpy(x).cuda()
+            md = torch.from_numpy(m).cuda()
+            h = eng.steps(prob, p, t, t + 1, xd, md, want_h=True)
+            dh = np.abs(host(h) - h_ref)
+            assert np.all(dh <= 1e-5 * rowmag[None, :]), dh.max()
+            tol = 1e-5 * np.maximum(np.abs(x0), 1e-3)
+            assert np.all(np.abs(host(xd) - x0) <= tol)
+            assert np.all(np.abs(host(md) - m0) <= 1e-5 * np.maximum(np.abs(m0), 1e-3))
+        x, m = x0, m0
+
+
+# ------------------------------------------------------------------ CSR
+def _oracle_csr(inst, R, T, lam, eta, alpha, r0=0, seed=1):
+    c = inst.csr
+    if inst.kind == "qubo":
+        rp, col, w, b, K = orc.qubo_to_ising_csr_int(c.rp, c.col, c.w, inst.lin)
+    else:
+        rp, col, w, b, K = c.rp, c.col, c.w, inst.lin, 0
+    x, m = orc.pa_init(inst.n, R, seed, np.float32(0.1), r0=r0)
+    if np.issubdtype(np.asarray(w).dtype, np.floating):
+        orc.pa_steps_csr_float(rp, col, w, b, x, m, 0, T, lam, eta, alpha)
+    else:
+        orc.pa_steps_csr_int(rp, col, w, b, x, m, 0, T, lam, eta, alpha)
+    return x, m, (rp, col, w, b, K)
+
+
+def _energies_csr_int(canon, kind, s):
+    rp, col, w, b, K = canon
+    H = np.array([orc.ising_energy_csr_int(rp, col, w, b, s[r]) for r in range(len(s))])
+    return (H + K) // 2 if kind == "qubo" else H
+
+
+@pytest.mark.parametrize("m_,R,T", [(4, 70, 200), (2, 1, 30), (3, 64, 50)])
+def test_csr_chimera_bit_exact(q, eng, m_, R, T):
+    inst = gen.chimera_ising(m_, seed=m_)
+    prob = q.Problem.from_instance(inst)
+    p = _params(q, R, T, 0.2, 0.8, 10.0)
+    say("csr chimera m=%d R=%d T=%d" % (m_, R, T))
+    out = eng.solve(prob, p, want_state=True)
+    x, m, canon = _oracle_csr(inst, R, T, orc.lambda_linear(T, 10.0), 0.2, 0.8)
+    assert np.array_equal(host(out["x"]), x)
+    assert np.array_equal(host(out["m"]), m)
+    s = np.where(x >= 0, 1, -1).astype(np.int8)
+    assert np.array_equal(host(out["spins"]), s)
+    e = _energies_csr_int(canon, "ising", s)
+    assert np.array_equal(host(out["energy_i64"]), e)
+    assert int(host(out["best"])[0]) == int(np.flatnonzero(e == e.min())[0])
+
+
+def test_chimera16_full_workload_replica_subset(q, eng):
+    wl = WORKLOADS["chimera16"]
+    inst = wl.make()
+    prob = q.Problem.from_instance(inst)
+    p = _params(q, wl.replicas, wl.steps, wl.eta, wl.alpha, wl.lambda0)
+    say("chimera16 full workload R=%d T=%d" % (wl.replicas, wl.steps))
+    out = eng.solve(prob, p, want_state=True)
+    gx, gm, gs = host(out["x"]), host(out["m"]), host(out["spins"])
+    lam = orc.lambda_linear(wl.steps, wl.lambda0)
+    for r0 in [0, 1, 511, 1023]:
+        x, m, canon = _oracle_csr(inst, 1, wl.steps, lam, wl.eta, wl.alpha, r0=r0)
+        assert np.array_equal(gx[r0], x[0]) and np.array_equal(gm[r0], m[0])
+    e = _energies_csr_int((inst.csr.rp, inst.csr.col, inst.csr.w, inst.lin, 0), "ising", gs)
+    assert np.array_equal(host(out["energy_i64"]), e)
+    assert int(host(out["best"])[0]) == int(np.flatnonzero(e == e.min())[0])
+
+
+def test_csr_er_qubo_int16(q, eng):
+    rng = np.random.default_rng(3)
+    inst = gen.er_qubo(300, 0.1, 100, rng)
+    # add diagonal terms to exercise the QUBO fold
+    c = inst.csr
+    n = inst.n
+    d = c.to_dense(np.int32)
+    d[np.arange(n), np.arange(n)] = rng.integers(-20, 21, n)
+    rows, cols = np.nonzero(d)
+    rp = np.zeros(n + 1, np.int64)
+    np.cumsum(np.bincount(rows, minlength=n), out=rp[1:])
+    inst.csr = gen.CSR(n, rp.astype(np.int32), cols.astype(np.int16), d[rows, cols].astype(np.int16))
+    R, T = 5, 100
+    prob = q.Problem.from_instance(inst)
+    p = _params(q, R, T, 0.0002, 0.8, 200.0)
+    say("csr ER qubo int16 n=%d R=%d T=%d" % (n, R, T))
+    out = eng.solve(prob, p, want_state=True)
+    x, m, canon = _oracle_csr(inst, R, T, orc.lambda_linear(T, 200.0), 0.0002, 0.8)
+    assert np.array_equal(host(out["x"]), x) and np.array_equal(host(out["m"]), m)
+    s = np.where(x >= 0, 1, -1).astype(np.int8)
+    e = _energies_csr_int(canon, "qubo", s)
+    assert np.array_equal(host(out["energy_i64"]), e)
+    # independent check of the QUBO objective on x = (1+s)/2
+    for r in range(R):
+        xb = ((s[r] + 1) // 2).astype(np.int8)
+        assert e[r] == orc.qubo_energy_int(d, inst.lin, xb)
+
+
+def test_csr_float_weights_bit_exact(q, eng):
+    inst = gen.chimera_ising(3, seed=4)
+    rng = np.random.default_rng(0)
+    c = inst.csr
+    D = c.to_dense(np.int32).astype(np.float32)
+    W = np.triu(rng.standard_normal(D.shape).astype(np.float32) * (D != 0), 1)
+    W = W + W.T
+    rows, cols = np.nonzero(D)
+    inst.csr = gen.CSR(inst.n, c.rp, c.col, W[rows, cols].astype(np.float32))
+    inst.lin = rng.standard_normal(inst.n).astype(np.float32) * 0.3
+    R, T = 3, 80
+    prob = q.Problem.from_instance(inst)
+    p = _params(q, R, T, 0.1, 0.8, 2.0)
+    say("csr float weights n=%d" % inst.n)
+    out = eng.solve(prob, p, want_state=True)
+    x, m, _ = _oracle_csr(inst, R, T, orc.lambda_linear(T, 2.0), 0.1, 0.8)
+    assert np.array_equal(host(out["x"]), x) and np.array_equal(host(out["m"]), m)
+
+
+# ------------------------------------------------------------------ energies, resume, errors
+def test_energy_entry_point(q, eng):
+    import torch
+    rng = np.random.default_rng(11)
+    for inst in [gen.dense_int_qubo(50, seed=3), gen.sk_ising(70, seed=2),
+                 gen.chimera_ising(3, seed=1)]:
+        R = 33
+        s = (2 * rng.integers(0, 2, (R, inst.n)) - 1).astype(np.int8)
+        prob = q.Problem.from_instance(inst)
+        say("energy entry point %s n=%d" % (inst.kind, inst.n))
+        e, ei, best = eng.energy(prob, _params(q, R, 1, 0.1, 0.5, 1.0), torch.from_numpy(s).cuda())
+        if inst.dense is not None and inst.kind == "qubo":
+            ref = np.array([orc.qubo_energy_int(inst.dense, inst.lin, ((s[r] + 1) // 2).astype(np.int8))
+                            for r in range(R)])
+            assert np.array_equal(host(ei), ref)
+        elif inst.dense is not None:
+            ref = np.array([orc.ising_energy_float(inst.dense.astype(np.float64),
+                                                   inst.lin.astype(np.float64), s[r]) for r in range(R)])
+            np.testing.assert_allclose(host(e), ref, rtol=1e-12, atol=1e-9)
+        else:
+            ref = _energies_csr_int((inst.csr.rp, inst.csr.col, inst.csr.w, inst.lin, 0), "ising", s)
+            assert np.array_equal(host(ei), ref)
+        assert int(host(best)[0]) == int(np.flatnonzero(ref == ref.min())[0])
+
+
+@pytest.mark.parametrize("which", ["dense-tiled", "csr", "mfma"])
+def test_resume_split_equals_uninterrupted(q, eng, which):
+    import torch
+    if which == "csr":
+        inst, prec = gen.chimera_ising(4, seed=9), "fp32"
+    elif which == "mfma":
+        inst, prec = gen.dense_int_ising(150, seed=4), "bf16"
+    else:
+        inst, prec = gen.dense_int_ising(150, seed=4), "fp32"
+    R, T = 9, 120
+    prob = q.Problem.from_instance(inst)
+    p = _params(q, R, T, 0.01, 0.8, 5.0, prec=prec)
+    say("resume split %s" % which)
+    full = eng.solve(prob, p, want_state=True)
+    x, m = orc.pa_init(inst.n, R, 1, np.float32(0.1))
+    xd, md = torch.from_numpy(x).cuda(), torch.from_numpy(m).cuda()
+    eng.steps(prob, p, 0, 37, xd, md)
+    eng.steps(prob, p, 37, 37, xd, md)
+    eng.steps(prob, p, 37, T, xd, md)
+    assert torch.equal(xd, full["x"]) and torch.equal(md, full["m"])
+
+
+def _expect_status(q, eng, inst, status, prec="fp32"):
+    prob = q.Problem.from_instance(inst)
+    with pytest.raises(q.QpaError) as ei:
+        eng.solve(prob, _params(q, 4, 3, 0.1, 0.5, 1.0, prec=prec))
+    assert ei.value.status == status, str(ei.value)
+
+
+def test_invalid_inputs_are_rejected(q, eng):
+    say("error paths")
+    a = gen.dense_int_qubo(10, seed=1)
+    a.dense = a.dense.copy()
+    a.dense[2, 3] += 1
+    _expect_status(q, eng, a, q.QPA_E_ASYM)
+    b = gen.dense_int_ising(10, seed=1)
+    b.dense = b.dense.copy()
+    b.dense[4, 4] = 1
+    _expect_status(q, eng, b, q.QPA_E_ASYM)
+    c = gen.dense_int_ising(10, seed=1)
+    c.dense = np.full((10, 10), 2**22, np.int32)
+    np.fill_diagonal(c.dense, 0)
+    _expect_status(q, eng, c, q.QPA_E_RANGE)
+    d = gen.chimera_ising(2, seed=1)
+    col = d.csr.col.copy()
+    col[[0, 1]] = col[[1, 0]]
+    d.csr = gen.CSR(d.n, d.csr.rp, col, d.csr.w)
+    _expect_status(q, eng, d, q.QPA_E_SHAPE)
+    e = gen.chimera_ising(2, seed=1)
+    w = e.csr.w.copy()
+    w[0] = -w[0]
+    e.csr = gen.CSR(e.n, e.csr.rp, e.csr.col, w)
+    _expect_status(q, eng, e, q.QPA_E_ASYM)
+
+
+def test_workspace_too_small(q, eng):
+    import ctypes
+    import torch
+    inst = gen.dense_int_qubo(20, seed=1)
+    prob = q.Problem.from_instance(inst)
+    p = _params(q, 4, 3, 0.1, 0.5, 1.0)
+    ps = prob.struct()
+    need = q.qpa_workspace_size(eng.ctx, ps, p)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    out = {k: torch.empty(4, dtype=dt, device="cuda") for k, dt in
+           [("e", torch.float64), ("b", torch.int32)]}
+    o = q.qpa_outputs()
+    o.energy = out["e"].data_ptr()
+    o.best = out["b"].data_ptr()
+    st = q._lib.qpa_solve(eng.ctx, ctypes.byref(ps), ctypes.byref(p),
+                          ctypes.c_void_p(ws.data_ptr()), need - 1, None, ctypes.byref(o))
+    assert st == q.QPA_E_WORKSPACE
+
+
+def test_zero_steps_scores_initial_state(q, eng):
+    inst = gen.chimera_ising(2, seed=3)
+    prob = q.Problem.from_instance(inst)
+    say("zero steps")
+    out = eng.solve(prob, _params(q, 6, 0, 0.1, 0.5, 1.0), want_state=True)
+    x, m = orc.pa_init(inst.n, 6, 1, np.float32(0.1))
+    assert np.array_equal(host(out["x"]), x)
+    s = np.where(x >= 0, 1, -1).astype(np.int8)
+    e = _energies_csr_int((inst.csr.rp, inst.csr.col, inst.csr.w, inst.lin, 0), "ising", s)
+    assert np.array_equal(host(out["energy_i64"]), e)
+
+
+def test_empty_csr(q, eng):
+    inst = gen.Instance("ising", 5, csr=gen.CSR(5, np.zeros(6, np.int32), np.zeros(0, np.int32),
+                                                np.zeros(0, np.int8)),
+                        lin=np.array([1, -2, 0, 3, -1], np.int8))
+    prob = q.Problem.from_instance(inst)
+    say("empty csr")
+    out = eng.solve(prob, _params(q, 2, 400, 0.05, 0.5, 1.0))
+    # with no couplings each spin settles opposite to its field
+    assert int(host(out["energy_i64"]).min()) == -7
