@@ -56,7 +56,7 @@ def cpu_baseline(inst, wl, prec):
         J = inst.dense
         if prec == "bf16":
             J = orc.bf16_quantise(J, orc.bf16_scale_exponent(J))
-        reps, steps = 2 * cores, 12
+        reps, steps = 2 * cores, 40
         lam = orc.lambda_linear(wl.steps, wl.lambda0)
 
         def work(r0, cnt):

@@ -157,6 +157,21 @@ qpa_status qpa_solve(qpa_ctx *ctx, const qpa_problem *problem, const qpa_params 
                      void *workspace, size_t workspace_bytes, void *stream,
                      const qpa_outputs *out);
 
+/* Solve `count` independent sparse instances in one persistent launch (the batch shares
+ * params).  Instance k is solved exactly as qpa_solve would solve it alone with seed
+ * params->seed + k; its outputs go to out[k].
+ *  problems : host array of `count` CSR problems (format QPA_FMT_CSR, n <= 4096).
+ *  out      : host array of `count` output sets (device pointers as in qpa_outputs).
+ *  workspace: device buffer of at least qpa_workspace_size_batch() bytes.
+ * Work is split into tasks (instance, group of 64 replicas), sorted by stored entries,
+ * largest first, and taken by workgroups from an atomic counter; no workgroup waits on
+ * another.  Errors name the offending instance in qpa_last_error(). */
+qpa_status qpa_workspace_size_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *problems,
+                                    const qpa_params *params, size_t *bytes);
+qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *problems,
+                           const qpa_params *params, void *workspace, size_t workspace_bytes,
+                           void *stream, const qpa_outputs *out);
+
 /* Advance a caller-held state by PA steps t0 .. t1-1 (0 <= t0 <= t1 <= params->steps)
  * of the schedule of `params` -- the resume / teacher-forcing entry point.
  *  x, m    : device [R*n] float, read and overwritten in place (R = params->replicas).
@@ -176,6 +191,25 @@ qpa_status qpa_steps(qpa_ctx *ctx, const qpa_problem *problem, const qpa_params 
 qpa_status qpa_energy(qpa_ctx *ctx, const qpa_problem *problem, const qpa_params *params,
                       const int8_t *spins, double *energy, int64_t *energy_i64,
                       int32_t *best, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Gradient of the relaxed final energy (the dynamics with analog spins in the target
+ * part, s := x; App. B relaxes the binary spins to x in [-1,1]) with respect to the
+ * step size eta, the momentum alpha and every schedule value lambda_t.
+ *   L = scale * sum_r [ (1/2) x_T^T J x_T + b^T x_T ]   over the params->replicas
+ *   replicas started as in qpa_solve (scale = 1/replicas gives the mean), (J, b) the
+ *   Ising form of the problem (App. A for a QUBO).
+ * FP32 state, FP64 accumulation of the gradient sums.  The forward pass keeps (x, m)
+ * every ckpt_every steps; the reverse pass recomputes each segment from its checkpoint.
+ *  loss, d_eta, d_alpha: device [1] double; d_lambda: device [steps] double.
+ *  workspace: device buffer of at least qpa_workspace_size_relaxed() bytes.
+ * Dense problems use FP32 couplings whatever params->precision says. */
+qpa_status qpa_workspace_size_relaxed(qpa_ctx *ctx, const qpa_problem *problem,
+                                      const qpa_params *params, int32_t ckpt_every,
+                                      size_t *bytes);
+qpa_status qpa_relaxed_grad(qpa_ctx *ctx, const qpa_problem *problem, const qpa_params *params,
+                            int32_t ckpt_every, double scale, void *workspace,
+                            size_t workspace_bytes, void *stream, double *loss, double *d_eta,
+                            double *d_alpha, double *d_lambda);
 
 /* Measurement of the PA-step kernels.  While enabled (enable != 0), every qpa_solve and
  * qpa_steps call records one HIP event on its stream right before its first step kernel

@@ -1,16 +1,25 @@
 // Dense PA step on the CDNA4 matrix cores with BF16 couplings (App. B field J s + b,
 // couplings stored as bf16(J / 2^e), FP32 accumulation, result scaled back by 2^e).
 //
-// One launch advances every replica by one step.  Output tile: 128 replicas x 128
-// variables per workgroup (4 waves; wave w owns replicas 32w .. 32w+31 of the tile and all
-// 128 variables, i.e. four 32x32 accumulators).  The reduction dimension walks in chunks
-// of 64:
-//   * the 128 x 64 block of J (bf16) is staged global -> registers -> LDS, double
-//     buffered, rows padded to 144 bytes so that the 16-byte fragment reads of 8
-//     consecutive lanes fall in distinct banks;
-//   * the spins of the wave's 32 replicas arrive as one 64-bit word of sign bits per
-//     replica (bit set <=> spin -1) straight from global memory and are expanded in
-//     registers to bf16 +-1 (0x3F80 / 0xBF80), 8 spins per lane per MFMA.
+// One launch advances every replica by one step.  A workgroup owns an output tile of
+// 128 replicas x 128 variables and splits the reduction dimension over its 4 waves:
+// wave w accumulates the whole tile (4 x 4 accumulators of 32x32 in AGPRs) over
+// k in [w*np/4, (w+1)*np/4), walking it in chunks of 64.
+//   * each wave stages its own chunk -- the 128 x 64 bf16 block of J and the 128 spin
+//     words (sign bits, bit set <=> spin -1, one 64-bit word per 64 variables and replica
+//     row) -- into a wave-private LDS stage (two stages) with direct global->LDS loads:
+//     16 loads of 16 bytes per lane for J, each covering 8 full 128-byte rows, and 4 of
+//     4 bytes for the spin words.  Every operand of the tile is fetched once per
+//     workgroup, coalesced, without passing through registers; the only wait is one
+//     vmcnt(0) per chunk, a whole chunk of MFMAs after the loads were issued.  Inside
+//     a J row the eight 16-byte pieces sit at position (piece ^ (row % 8)), so that the
+//     fragment reads of 8 consecutive lanes (8 consecutive rows) hit distinct banks.
+//   * all 16 B fragments and 4 spin words of a chunk are read from LDS before the next
+//     chunk's loads are issued; the 8 bits of a fragment row are expanded to bf16 +-1
+//     (0x3F80 / 0xBF80) and reused by the 4 MFMAs of that row.
+// After the loop the four partial tiles are summed through LDS so that wave w holds
+// replicas 32w .. 32w+31 of the tile for all 128 variables, then runs the PA update.
+//
 // Matrix instruction: v_mfma_f32_32x32x16_bf16.  Operand layout (64 lanes):
 //   A (32 x 16, rows = replicas): lane l holds row l%32, k = 8*(l/32) .. +7
 //   B (16 x 32, cols = variables): lane l holds col l%32, k = 8*(l/32) .. +7
@@ -26,8 +35,9 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int BM = MF_BM, BN = MF_BN, BK = MF_BK;
-constexpr int LDS_ROW = BK * 2 + 16;   // bytes per staged J row
+constexpr int BM = MF_BM, BN = MF_BN;
+constexpr int JST = BN * 128;                // J bytes of a wave stage: 128 rows x 64 bf16
+constexpr int STG = JST + BM * 8;            // + one 64-bit spin word per replica row
 
 __device__ __forceinline__ void pa_update(float h, float lam, float eta, float alpha, float &x,
                                           float &m) {
@@ -39,95 +49,144 @@ __device__ __forceinline__ void pa_update(float h, float lam, float eta, float a
     x = y;
 }
 
-// 8 sign bits (bit j <=> element j is -1) -> eight bf16 +-1 values.
+// 8 sign bits (bit j <=> element j is -1) -> eight bf16 +-1 values:
+// dword q holds elements 2q (low half) and 2q+1 (high half); a set bit sets the half's
+// sign bit on top of 0x3F80 (= 1.0).
 __device__ __forceinline__ bf16x8 expand_spins(uint32_t byte) {
     u32x4 d;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         uint32_t y = byte >> (2 * q);
-        d[q] = 0x3F803F80u | ((y & 1u) << 15) | ((y & 2u) << 30);
+        uint32_t spread = (y << 15) | (y << 30);
+        d[q] = (spread & 0x80008000u) | 0x3F803F80u;
     }
     return __builtin_bit_cast(bf16x8, d);
 }
 
-__global__ void __launch_bounds__(256) k_mfma_step(
+typedef __attribute__((address_space(3))) void lds_void;
+
+__global__ void __launch_bounds__(256, 1) k_mfma_step(
     int64_t Rp, int64_t np, const uint16_t *__restrict__ Jb, const float *__restrict__ b,
-    const CanonScalars *__restrict__ sc, const uint32_t *__restrict__ s_cur,
+    const CanonScalars *__restrict__ sc, const uint64_t *__restrict__ s_cur,
     uint32_t *__restrict__ s_nxt, float *__restrict__ x, float *__restrict__ m,
     float *__restrict__ h_last, int t, const float *__restrict__ lam, float eta, float alpha) {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[2][BN * LDS_ROW];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    // 4 waves x 2 stages of (J block, spin words); reused after the loop as the
+    // cross-wave reduction buffer [destination fragment][source wave][register][lane]
+    __shared__ __attribute__((aligned(16))) uint8_t lds[4 * 2 * STG];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int half = lane >> 5, l32 = lane & 31;
     const int64_t I0 = (int64_t)blockIdx.x * BN, R0 = (int64_t)blockIdx.y * BM;
-    const int64_t wr0 = R0 + 32 * wv;
-    const int64_t words = np / 32;
-    const int nk = (int)(np / BK);
+    const int64_t kq = np / 4;                 // reduction length of one wave
+    const int64_t kb = (int64_t)w * kq;
+    const int nchunk = (int)(kq / 64);
+    const int64_t wpr = np / 64;               // spin words per replica row
+    uint8_t *mine = lds + w * 2 * STG;
 
-    // J stager: thread -> (row tid/2, 32 consecutive k at offset 32*(tid%2)) = 4 x 16 B
-    const int lrow = tid >> 1, lhalf = tid & 1;
-    const uint4 *gB = reinterpret_cast<const uint4 *>(Jb + (I0 + lrow) * np + lhalf * 32);
-    const int lds_off = lrow * LDS_ROW + lhalf * 64;
-    // spin bits of replica wr0 + lane%32: one 64-bit word per chunk
-    const uint64_t *gA = reinterpret_cast<const uint64_t *>(s_cur + (wr0 + (lane & 31)) * words);
+    // J: load e (0..15) fills rows 8e .. 8e+7 of a stage; lane l covers row 8e + l/8 and
+    // stores at position l%8 the piece (l%8) ^ (row%8) = (l%8) ^ (l/8).
+    const uint16_t *gJ = Jb + (I0 + (lane >> 3)) * np + kb + 8 * ((lane & 7) ^ (lane >> 3));
+    // spin words: load e (0..3) fills rows 32e .. 32e+31; lane l covers row 32e + l/2,
+    // 32-bit half l%2 of that row's 64-bit word, so a row's word is contiguous in LDS.
+    const uint32_t *gS = reinterpret_cast<const uint32_t *>(s_cur + (R0 + (lane >> 1)) * wpr +
+                                                            kb / 64) + (lane & 1);
+    auto stage = [&](int kc, int st) {
+        kc = kc < nchunk ? kc : nchunk - 1;   // past the end: reload the last chunk
+        const uint16_t *srcJ = gJ + (int64_t)kc * 64;
+        const uint32_t *srcS = gS + 2 * (int64_t)kc;
+        uint8_t *dst = mine + st * STG;
+#pragma unroll
+        for (int e = 0; e < 16; ++e)
+            __builtin_amdgcn_global_load_lds(srcJ + (int64_t)8 * e * np,
+                                             (lds_void *)(dst + e * 1024), 16, 0, 0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            __builtin_amdgcn_global_load_lds(srcS + (int64_t)32 * e * 2 * wpr,
+                                             (lds_void *)(dst + JST + e * 256), 4, 0, 0);
+    };
 
-    f32x16 acc[4];
+    f32x16 acc[4][4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int v = 0; v < 16; ++v) acc[c][v] = 0.0f;
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
 
-    uint4 breg[4];
+    stage(0, 0);
+    for (int c = 0; c < nchunk; ++c) {
+        // chunk c was requested one chunk ago: wait for it here, and keep every LDS read
+        // of the chunk below this point
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        const uint8_t *src = mine + (c & 1) * STG;
+        u32x4 bf[4][4];                         // [k step q][variable fragment j]
 #pragma unroll
-    for (int e = 0; e < 4; ++e) breg[e] = gB[e];
-    uint64_t abits = gA[0];
+        for (int q = 0; q < 4; ++q)
 #pragma unroll
-    for (int e = 0; e < 4; ++e)
-        *reinterpret_cast<uint4 *>(&lds[0][lds_off + 16 * e]) = breg[e];
-    __syncthreads();
-
-    const int half = lane >> 5;
-    for (int kc = 0; kc < nk; ++kc) {
-        uint64_t abits_next = 0;
-        if (kc + 1 < nk) {
-            const uint4 *src = gB + (int64_t)(kc + 1) * (BK / 8);
+            for (int j = 0; j < 4; ++j) {
+                const int row = 32 * j + l32;
+                const int pos = (2 * q + half) ^ (row & 7);
+                bf[q][j] = *reinterpret_cast<const u32x4 *>(src + row * 128 + (pos << 4));
+            }
+        uint64_t aw[4];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) breg[e] = src[e];
-            abits_next = gA[kc + 1];
-        }
-        const uint8_t *buf = lds[kc & 1];
+        for (int i = 0; i < 4; ++i)
+            aw[i] = *reinterpret_cast<const uint64_t *>(src + JST + 8 * (32 * i + l32));
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        stage(c + 1, (c + 1) & 1);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            uint32_t byte = (uint32_t)(abits >> (16 * q + 8 * half)) & 0xFFu;
-            bf16x8 a = expand_spins(byte);
+            bf16x8 a[4];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const int row = 32 * c + (lane & 31);
-                u32x4 bd = *reinterpret_cast<const u32x4 *>(buf + row * LDS_ROW + q * 32 +
-                                                            half * 16);
-                acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                    a, __builtin_bit_cast(bf16x8, bd), acc[c], 0, 0, 0);
-            }
-        }
-        if (kc + 1 < nk) {
+            for (int i = 0; i < 4; ++i)
+                a[i] = expand_spins((uint32_t)(aw[i] >> (16 * q + 8 * half)) & 0xFFu);
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-                *reinterpret_cast<uint4 *>(&lds[(kc + 1) & 1][lds_off + 16 * e]) = breg[e];
-            abits = abits_next;
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                        a[i], __builtin_bit_cast(bf16x8, bf[q][j]), acc[i][j], 0, 0, 0);
         }
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // the last (redundant) loads landed
+    __syncthreads();
+
+    // sum the partial tiles: wave w ends up with replica fragment w (all 4 variable
+    // fragments), adding the other waves' partials in ascending wave order.
+    float *red = reinterpret_cast<float *>(lds);
+    f32x16 fin[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (i != w)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) red[((i * 4 + w) * 16 + v) * 64 + lane] = acc[i][j][v];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (i == w) fin[j] = acc[i][j];
+#pragma unroll
+        for (int src = 0; src < 4; ++src)
+            if (src != w)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) fin[j][v] += red[((w * 4 + src) * 16 + v) * 64 + lane];
         __syncthreads();
     }
 
     const float scale = sc->scale;
     const float lt = lam[t];
+    const int64_t wrow = np / 32;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        const int64_t iv = I0 + 32 * c + (lane & 31);
+    for (int j = 0; j < 4; ++j) {
+        const int64_t iv = I0 + 32 * j + l32;
         const float bi = b[iv];
-        const int64_t wcol = (I0 + 32 * c) / 32;
+        const int64_t wcol = (I0 + 32 * j) / 32;
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-            const int64_t r = wr0 + 8 * (v >> 2) + 4 * half + (v & 3);
+            const int64_t r = R0 + 32 * w + 8 * (v >> 2) + 4 * half + (v & 3);
             const int64_t g = r * np + iv;
-            float h = __fadd_rn(__fmul_rn(acc[c][v], scale), bi);
+            float h = __fadd_rn(__fmul_rn(fin[j][v], scale), bi);
             float xv = x[g], mv = m[g];
             pa_update(h, lt, eta, alpha, xv, mv);
             x[g] = xv;
@@ -135,7 +194,7 @@ __global__ void __launch_bounds__(256) k_mfma_step(
             if (h_last) h_last[g] = h;
             uint64_t bal = __ballot(xv < 0.0f);
             uint32_t word = half ? (uint32_t)(bal >> 32) : (uint32_t)bal;
-            if ((lane & 31) == 0) s_nxt[r * words + wcol] = word;
+            if (l32 == 0) s_nxt[r * wrow + wcol] = word;
         }
     }
 }
@@ -148,8 +207,8 @@ __global__ void __launch_bounds__(256) k_mfma_pack(int64_t Rp, int64_t np,
     const int64_t total = Rp * words;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
          k += (int64_t)gridDim.x * blockDim.x) {
-        int64_t r = k / words, w = k - r * words;
-        const float *xr = x + r * np + 32 * w;
+        int64_t r = k / words, wd = k - r * words;
+        const float *xr = x + r * np + 32 * wd;
         uint32_t bits = 0;
         for (int j = 0; j < 32; ++j) bits |= (xr[j] < 0.0f ? 1u : 0u) << j;
         sbits[k] = bits;
@@ -171,10 +230,11 @@ hipError_t launch_mfma_step(int64_t Rp, int64_t np, const uint16_t *Jb, const fl
                             const CanonScalars *sc, const uint32_t *s_cur, uint32_t *s_nxt,
                             float *x, float *m, float *h_last, int32_t t, const float *lam,
                             float eta, float alpha, hipStream_t st) {
-    if (Rp % BM || np % BN || np % BK) return hipErrorInvalidValue;
+    if (Rp % BM || np % MF_NPAD) return hipErrorInvalidValue;
     dim3 grid((unsigned)(np / BN), (unsigned)(Rp / BM));
-    k_mfma_step<<<grid, 256, 0, st>>>(Rp, np, Jb, b, sc, s_cur, s_nxt, x, m, h_last, t, lam, eta,
-                                      alpha);
+    k_mfma_step<<<grid, 256, 0, st>>>(Rp, np, Jb, b, sc,
+                                      reinterpret_cast<const uint64_t *>(s_cur), s_nxt, x, m,
+                                      h_last, t, lam, eta, alpha);
     return hipGetLastError();
 }
 

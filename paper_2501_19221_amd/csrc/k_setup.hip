@@ -315,74 +315,92 @@ __global__ void __launch_bounds__(256) k_export_spins(int64_t n, int64_t R, cons
 }
 
 // ------------------------------------------------------------------ energies
-// H(s) = (1/2) sum_i s_i (sum_{j != i} J_ij s_j) + sum_i b_i s_i, i.e. 2H = sum_i s_i (d_i + 2 b_i)
-// with d_i = sum_{j != i} Q_ij s_j.  For a QUBO the objective is E = (H + K) / 2.
-// Dense: a wave takes one row i and ER replicas; lanes stride over j.  Integer row dots are
-// exact in int32 (validated row bound < 2^24); float dots accumulate in double.
+// H(s) = sum_{i<j} J_ij s_i s_j + sum_i b_i s_i (eq. (2)); for a QUBO the objective is
+// E = (H + K) / 2 with the canonical (J, b, K).
 constexpr int ER = 16;
+
+// Dense: lane = replica.  The spins of 64 replicas at variable j are one 64-bit word
+// (bit set <=> -1) staged in LDS; for row i and every j > i the pair term is
+// J_ij (1 - 2 [s_i != s_j]), so  sum_{j>i} J_ij s_i s_j = U_i - 2 P_i  with
+// U_i = sum_{j>i} J_ij (uniform) and P_i = sum_{j>i} J_ij [bit_i xor bit_j].
+// Integer couplings: exact int32 sums (rows are validated below 2^24); float couplings:
+// FP64 sums.  A block owns 16 rows (4 per wave) of one 64-replica group and walks j in
+// chunks of DW words; per-block, per-replica partials go to `partial`.
+constexpr int DW = 4096;
+
+__global__ void __launch_bounds__(256) k_spin_words(int64_t n, int64_t R,
+                                                    const int8_t *__restrict__ s,
+                                                    uint64_t *__restrict__ words) {
+    // wave per variable j, lane = replica of group blockIdx.y
+    const int lane = threadIdx.x & 63;
+    const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t r = (int64_t)blockIdx.y * 64 + lane;
+    bool neg = false;
+    if (j < n && r < R) neg = s[r * n + j] < 0;
+    const uint64_t bal = __ballot(neg);
+    if (lane == 0 && j < n) words[blockIdx.y * n + j] = bal;
+}
 
 template <typename TQ, bool INT>
 __global__ void __launch_bounds__(256) k_energy_dense(int64_t n, const TQ *__restrict__ Q,
                                                       const int64_t *__restrict__ b_i64,
                                                       const double *__restrict__ b_f64,
-                                                      const int8_t *__restrict__ s, int64_t R,
-                                                      double *__restrict__ partial) {
-    const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
-    const int64_t i = (int64_t)blockIdx.x * 4 + wv;
-    const int64_t r0 = (int64_t)blockIdx.y * ER;
-    __shared__ double red[4][ER];
-    double contrib[ER];
+                                                      const uint64_t *__restrict__ words,
+                                                      int64_t R, double *__restrict__ partial) {
+    __shared__ uint64_t sw[DW];
+    __shared__ double red[4][64];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t g = blockIdx.y;
+    const uint64_t *gw = words + g * n;
+    const int64_t i0 = (int64_t)blockIdx.x * 16 + 4 * wv;
+    int32_t Pi[4] = {0, 0, 0, 0}, Ui[4] = {0, 0, 0, 0};
+    double Pf[4] = {0.0, 0.0, 0.0, 0.0}, Uf[4] = {0.0, 0.0, 0.0, 0.0};
+    uint32_t bit_i[4];
 #pragma unroll
-    for (int q = 0; q < ER; ++q) contrib[q] = 0.0;
-    if (i < n) {
-        const TQ *row = Q + i * n;
-        int32_t di[ER];
-        double df[ER];
+    for (int q = 0; q < 4; ++q)
+        bit_i[q] = (i0 + q < n) ? (uint32_t)((gw[i0 + q] >> lane) & 1u) : 0u;
+    for (int64_t j0 = 0; j0 < n; j0 += DW) {
+        const int64_t cnt = min((int64_t)DW, n - j0);
+        __syncthreads();
+        for (int64_t k = threadIdx.x; k < cnt; k += 256) sw[k] = gw[j0 + k];
+        __syncthreads();
 #pragma unroll
-        for (int q = 0; q < ER; ++q) {
-            di[q] = 0;
-            df[q] = 0.0;
-        }
-        for (int64_t j = lane; j < n; j += WAVE) {
-            TQ qv = (j == i) ? TQ(0) : row[j];
-#pragma unroll
-            for (int q = 0; q < ER; ++q) {
-                int64_t r = r0 + q;
-                if (r < R) {
-                    int8_t sj = s[r * n + j];
-                    if (INT) di[q] += (sj > 0) ? (int32_t)qv : -(int32_t)qv;
-                    else df[q] += (sj > 0) ? (double)qv : -(double)qv;
+        for (int q = 0; q < 4; ++q) {
+            const int64_t i = i0 + q;
+            if (i >= n) continue;
+            const int64_t jb = max(j0, i + 1);
+            const TQ *row = Q + i * n;
+            for (int64_t j = jb; j < j0 + cnt; ++j) {
+                const TQ qv = row[j];
+                const uint32_t x = ((uint32_t)(sw[j - j0] >> lane) ^ bit_i[q]) & 1u;
+                if (INT) {
+                    Ui[q] += (int32_t)qv;
+                    Pi[q] += x ? (int32_t)qv : 0;
+                } else {
+                    const double d = (double)qv;
+                    Uf[q] += d;
+                    Pf[q] += x ? d : 0.0;
                 }
             }
         }
-#pragma unroll
-        for (int q = 0; q < ER; ++q) {
-            int64_t r = r0 + q;
-            double d;
-            if (INT) {
-                int64_t v = di[q];
-                for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
-                d = (double)v;
-            } else {
-                d = wave_sum(df[q]);
-            }
-            if (r < R) {
-                double si = (double)s[r * n + i];
-                if (INT) contrib[q] = si * (d + 2.0 * (double)b_i64[i]);
-                else contrib[q] = si * (0.5 * d + b_f64[i]);
-            }
-        }
     }
-    if (lane == 0) {
+    double contrib = 0.0;
 #pragma unroll
-        for (int q = 0; q < ER; ++q) red[wv][q] = contrib[q];
+    for (int q = 0; q < 4; ++q) {
+        const int64_t i = i0 + q;
+        if (i >= n) continue;
+        const double si = bit_i[q] ? -1.0 : 1.0;
+        if (INT) contrib += (double)((int64_t)Ui[q] - 2 * (int64_t)Pi[q]) + si * (double)b_i64[i];
+        else contrib += (Uf[q] - 2.0 * Pf[q]) + si * b_f64[i];
     }
+    red[wv][lane] = contrib;
     __syncthreads();
-    if (threadIdx.x < ER) {
-        int q = threadIdx.x;
-        int64_t r = r0 + q;
+    if (threadIdx.x < 64) {
+        const int64_t r = g * 64 + threadIdx.x;
         if (r < R) {
-            double v = red[0][q] + red[1][q] + red[2][q] + red[3][q];
+            double v = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
+                       red[3][threadIdx.x];
             partial[(int64_t)blockIdx.x * R + r] = v;
         }
     }
@@ -414,12 +432,12 @@ __global__ void __launch_bounds__(256) k_energy_csr(int64_t n, const int32_t *__
             double df = 0.0;
             for (int64_t k = k0; k < k1; ++k) {
                 int64_t j = (int64_t)col[k];
-                if (j == i) continue;
+                if (INT ? (j <= i) : (j == i)) continue;   // integer: each pair once
                 if (INT) di += (sr[j] > 0) ? (int64_t)w[k] : -(int64_t)w[k];
                 else df += (sr[j] > 0) ? (double)w[k] : -(double)w[k];
             }
             double si = (double)sr[i];
-            if (INT) contrib[q] = si * ((double)di + 2.0 * (double)b_i64[i]);
+            if (INT) contrib[q] = si * ((double)di + (double)b_i64[i]);
             else contrib[q] = si * (0.5 * df + b_f64[i]);
         }
     }
@@ -453,9 +471,8 @@ __global__ void __launch_bounds__(256) k_energy_finalize(int64_t R, int64_t nblk
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= R) return;
     if (is_int) {
-        int64_t two_h = 0;
-        for (int64_t b = 0; b < nblk; ++b) two_h += (int64_t)partial[b * R + r];
-        int64_t H = two_h / 2;               // 2H is even: sum_i s_i (d_i + 2 b_i), d = 2 x pairs
+        int64_t H = 0;
+        for (int64_t b = 0; b < nblk; ++b) H += (int64_t)partial[b * R + r];
         int64_t E = is_qubo ? (H + sc->K_i64) / 2 : H;
         if (e_i64) e_i64[r] = E;
         e_f64[r] = (double)E;
@@ -604,14 +621,14 @@ hipError_t launch_export_spins(int64_t n, int64_t R, const float *x, int64_t ld_
 }
 
 int64_t energy_partial_blocks(const qpa_problem &p) {
-    if (p.format == QPA_FMT_DENSE) return (p.n + 3) / 4;
+    if (p.format == QPA_FMT_DENSE) return (p.n + 15) / 16;
     return (p.n + 255) / 256;
 }
 
 hipError_t launch_energy(const qpa_problem &p, const int64_t *b_i64, const double *b_f64,
                          const CanonScalars *sc, const int8_t *spins, int64_t R,
                          int64_t *e_i64, double *e_f64, double *partial, int64_t partial_len,
-                         hipStream_t st) {
+                         uint64_t *words, hipStream_t st) {
     const int64_t n = p.n;
     const int32_t is_qubo = p.kind == QPA_KIND_QUBO;
     const bool is_int = dtype_is_int(p.coupling_dtype) &&
@@ -621,15 +638,17 @@ hipError_t launch_energy(const qpa_problem &p, const int64_t *b_i64, const doubl
     const unsigned gy = (unsigned)((R + ER - 1) / ER);
     hipError_t e;
     if (p.format == QPA_FMT_DENSE) {
+        const unsigned groups = (unsigned)((R + 63) / 64);
+        k_spin_words<<<dim3((unsigned)((n + 3) / 4), groups), 256, 0, st>>>(n, R, spins, words);
         e = dispatch_q(p.coupling_dtype, [&](auto tag) {
             using T = decltype(tag);
             const T *Q = static_cast<const T *>(p.dense);
             if (is_int)
-                k_energy_dense<T, true><<<dim3((unsigned)nblk, gy), 256, 0, st>>>(
-                    n, Q, b_i64, b_f64, spins, R, partial);
+                k_energy_dense<T, true><<<dim3((unsigned)nblk, groups), 256, 0, st>>>(
+                    n, Q, b_i64, b_f64, words, R, partial);
             else
-                k_energy_dense<T, false><<<dim3((unsigned)nblk, gy), 256, 0, st>>>(
-                    n, Q, b_i64, b_f64, spins, R, partial);
+                k_energy_dense<T, false><<<dim3((unsigned)nblk, groups), 256, 0, st>>>(
+                    n, Q, b_i64, b_f64, words, R, partial);
             return hipGetLastError();
         });
     } else {

@@ -57,14 +57,12 @@ struct Plan {
     int64_t eblk;         // energy partial blocks
     // workspace offsets (bytes)
     size_t o_sc, o_lam, o_bf, o_bi, o_bd, o_rabs, o_rmax, o_rk, o_Jf, o_Jb, o_x, o_m, o_h,
-        o_s0, o_s1, o_part, o_ei, o_ed, o_sp, o_best, total;
+        o_s0, o_s1, o_part, o_ei, o_ed, o_sp, o_best, o_words, total;
 };
 
-int64_t energy_blocks(const qpa_problem &p) {
-    return p.format == QPA_FMT_DENSE ? (p.n + 3) / 4 : (p.n + 255) / 256;
-}
 
-Plan make_plan(const qpa_problem &p, const qpa_params &a) {
+// batch_rp > 0: state for the batch kernel, [batch_rp/64 groups][n][64].
+Plan make_plan(const qpa_problem &p, const qpa_params &a, int64_t batch_rp = 0) {
     Plan pl{};
     pl.n = p.n;
     pl.R = a.replicas;
@@ -78,19 +76,19 @@ Plan make_plan(const qpa_problem &p, const qpa_params &a) {
     pl.nwords = 0;
     if (p.format == QPA_FMT_CSR) {
         pl.path = Path::Csr;
-        pl.G = csr_group_size(pl.R);
-        pl.Rp = round_up(pl.R, pl.G);
+        pl.G = batch_rp > 0 ? 64 : csr_group_size(pl.R);
+        pl.Rp = batch_rp > 0 ? batch_rp : round_up(pl.R, pl.G);
         pl.nwords = csr_words_per_group(pl.n, pl.G);
     } else if (a.precision == QPA_PREC_BF16) {
         pl.path = Path::DenseMfma;
-        pl.np = round_up(pl.n, std::max(MF_BN, MF_BK));
+        pl.np = round_up(pl.n, MF_NPAD);
         pl.Rp = round_up(pl.R, MF_BM);
     } else if (dense_resident_fits(pl.n)) {
         pl.path = Path::DenseResident;
     } else {
         pl.path = Path::DenseTiled;
     }
-    pl.eblk = energy_blocks(p);
+    pl.eblk = energy_partial_blocks(p);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -126,6 +124,8 @@ Plan make_plan(const qpa_problem &p, const qpa_params &a) {
     pl.o_ed = take(sizeof(double) * R);
     pl.o_sp = take(sizeof(int8_t) * R * n);
     pl.o_best = take(sizeof(int32_t) * 4);
+    pl.o_words = p.format == QPA_FMT_DENSE
+                     ? take(sizeof(uint64_t) * (size_t)((R + 63) / 64) * n) : 0;
     pl.total = off;
     return pl;
 }
@@ -358,7 +358,8 @@ qpa_status score(qpa_ctx *ctx, const qpa_problem &p, const Plan &pl, void *ws,
     int64_t *ei = energy_i64 ? energy_i64 : at<int64_t>(ws, pl.o_ei);
     QPA_HIP(launch_energy(p, at<int64_t>(ws, pl.o_bi), at<double>(ws, pl.o_bd),
                           at<CanonScalars>(ws, pl.o_sc), spins, pl.R, ei, energy,
-                          at<double>(ws, pl.o_part), pl.eblk * pl.R, st));
+                          at<double>(ws, pl.o_part), pl.eblk * pl.R,
+                          pl.o_words ? at<uint64_t>(ws, pl.o_words) : nullptr, st));
     if (best) QPA_HIP(launch_argmin(pl.R, pl.is_int ? ei : nullptr, energy, best, st));
     return QPA_OK;
 }
@@ -379,6 +380,94 @@ qpa_status prologue(qpa_ctx *ctx, const qpa_problem *problem, const qpa_params *
         return fail(ctx, QPA_E_WORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes,
                     pl.total);
     QPA_HIP(hipSetDevice(ctx->device));
+    return QPA_OK;
+}
+
+// Relaxed-gradient workspace: the FP32 plan's canonical buffers, then checkpoints and
+// the segment buffer of states (x_t, m_t, f_t = J x_t) and the reverse vectors.
+struct RelPlan {
+    Plan base;
+    int32_t k, nseg, nblk;
+    size_t o_ckpt, o_seg, o_f, o_xbar, o_mu, o_jmu, o_part, o_ploss, total;
+};
+
+qpa_status make_rel_plan(qpa_ctx *ctx, const qpa_problem &p, const qpa_params &a, int32_t k,
+                         RelPlan &rp) {
+    if (k < 1) return fail(ctx, QPA_E_ARG, "ckpt_every must be >= 1");
+    qpa_params a32 = a;
+    a32.precision = QPA_PREC_FP32;
+    rp.base = make_plan(p, a32);
+    rp.k = k;
+    rp.nseg = (int32_t)((a.steps + k - 1) / k);
+    const size_t RN = (size_t)a.replicas * (size_t)p.n;
+    rp.nblk = rel_blocks((int64_t)RN);
+    size_t off = rp.base.total;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align_up(bytes);
+        return o;
+    };
+    rp.o_ckpt = take(sizeof(float) * 2 * RN * (size_t)(rp.nseg + 1));
+    rp.o_seg = take(sizeof(float) * 3 * RN * (size_t)k);
+    rp.o_f = take(sizeof(float) * RN);
+    rp.o_xbar = take(sizeof(float) * RN);
+    rp.o_mu = take(sizeof(float) * RN);
+    rp.o_jmu = take(sizeof(float) * RN);
+    rp.o_part = take(sizeof(double) * 3 * (size_t)rp.nblk * (size_t)std::max(a.steps, 1));
+    rp.o_ploss = take(sizeof(double) * (size_t)rp.nblk);
+    rp.total = off;
+    return QPA_OK;
+}
+
+constexpr int64_t BATCH_MAX_N = 4096;
+
+struct BatchPlan {
+    std::vector<Plan> inst;          // per-instance single-solve plans (canonical buffers)
+    std::vector<size_t> base;        // byte offset of each instance's region
+    size_t o_tasks, o_counter, o_lam, total;
+    int32_t ntasks, max_n;
+};
+
+// Per instance: the canonical buffers, energy scratch and [groups][n][64] state of a CSR
+// plan, laid out one after the other; then the task table, the queue counter and the
+// shared schedule.
+qpa_status make_batch_plan(qpa_ctx *ctx, int32_t count, const qpa_problem *probs,
+                           const qpa_params &a, BatchPlan &bp) {
+    if (count < 1) return fail(ctx, QPA_E_ARG, "count must be >= 1");
+    if (!probs) return fail(ctx, QPA_E_ARG, "problems is NULL");
+    bp.inst.resize(count);
+    bp.base.resize(count);
+    size_t off = 0;
+    bp.ntasks = 0;
+    bp.max_n = 0;
+    const int64_t groups = (a.replicas + 63) / 64;
+    for (int32_t k = 0; k < count; ++k) {
+        qpa_status s = check_problem(ctx, &probs[k]);
+        if (s != QPA_OK) {
+            std::string msg = "instance " + std::to_string(k) + ": " + ctx->err;
+            return fail(ctx, s, "%s", msg.c_str());
+        }
+        if (probs[k].format != QPA_FMT_CSR)
+            return fail(ctx, QPA_E_UNSUPPORTED, "instance %d: batches take CSR problems", k);
+        if (probs[k].n > BATCH_MAX_N)
+            return fail(ctx, QPA_E_UNSUPPORTED, "instance %d: n=%lld exceeds the batch limit %lld",
+                        k, (long long)probs[k].n, (long long)BATCH_MAX_N);
+        Plan pl = make_plan(probs[k], a, groups * 64);
+        bp.base[k] = off;
+        off += align_up(pl.total);
+        bp.inst[k] = pl;
+        bp.ntasks += (int32_t)groups;
+        bp.max_n = std::max<int32_t>(bp.max_n, (int32_t)probs[k].n);
+    }
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align_up(bytes);
+        return o;
+    };
+    bp.o_tasks = take(sizeof(BatchTask) * (size_t)bp.ntasks);
+    bp.o_counter = take(sizeof(int32_t));
+    bp.o_lam = take(sizeof(float) * (size_t)std::max<int32_t>(a.steps, 1));
+    bp.total = off;
     return QPA_OK;
 }
 
@@ -512,6 +601,269 @@ qpa_status qpa_solve(qpa_ctx *ctx, const qpa_problem *problem, const qpa_params 
     if (out->x) QPA_HIP(launch_copy_state(pl.n, pl.R, x, ld_r, ld_i, out->x, pl.n, 1, st));
     if (out->m) QPA_HIP(launch_copy_state(pl.n, pl.R, m, ld_r, ld_i, out->m, pl.n, 1, st));
     return score(ctx, *problem, pl, ws, spins, out->energy, out->energy_i64, out->best, st);
+}
+
+qpa_status qpa_workspace_size_relaxed(qpa_ctx *ctx, const qpa_problem *problem,
+                                      const qpa_params *params, int32_t ckpt_every,
+                                      size_t *bytes) {
+    if (!bytes) return fail(ctx, QPA_E_ARG, "bytes is NULL");
+    qpa_status s = check_problem(ctx, problem);
+    if (s != QPA_OK) return s;
+    s = check_params(ctx, params);
+    if (s != QPA_OK) return s;
+    RelPlan rp;
+    s = make_rel_plan(ctx, *problem, *params, ckpt_every, rp);
+    if (s != QPA_OK) return s;
+    *bytes = rp.total;
+    return QPA_OK;
+}
+
+qpa_status qpa_relaxed_grad(qpa_ctx *ctx, const qpa_problem *problem, const qpa_params *params,
+                            int32_t ckpt_every, double scale, void *workspace,
+                            size_t workspace_bytes, void *stream, double *loss, double *d_eta,
+                            double *d_alpha, double *d_lambda) {
+    if (!ctx) return QPA_E_ARG;
+    ctx->err.clear();
+    qpa_status s = check_problem(ctx, problem);
+    if (s != QPA_OK) return s;
+    s = check_params(ctx, params);
+    if (s != QPA_OK) return s;
+    if (!loss || !d_eta || !d_alpha || (params->steps > 0 && !d_lambda))
+        return fail(ctx, QPA_E_ARG, "loss, d_eta, d_alpha and d_lambda are required");
+    RelPlan rp;
+    s = make_rel_plan(ctx, *problem, *params, ckpt_every, rp);
+    if (s != QPA_OK) return s;
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % ALIGN) != 0)
+        return fail(ctx, QPA_E_ARG, "workspace must be non-NULL and %zu-byte aligned", ALIGN);
+    if (workspace_bytes < rp.total)
+        return fail(ctx, QPA_E_WORKSPACE, "workspace has %zu bytes, %zu needed", workspace_bytes,
+                    rp.total);
+    QPA_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    void *ws = workspace;
+    const Plan &pl = rp.base;
+    const qpa_problem &p = *problem;
+    s = upload_schedule(ctx, *params, at<float>(ws, pl.o_lam), st);
+    if (s != QPA_OK) return s;
+    s = canonicalise(ctx, p, pl, ws, st);
+    if (s != QPA_OK) return s;
+    // the schedule values are needed on the host to pass to the update kernels
+    std::vector<float> lam(params->steps);
+    for (int32_t t = 0; t < params->steps; ++t) lam[t] = ctx->host_lam[t];
+
+    const int64_t n = p.n, R = params->replicas, RN = R * n;
+    const float eta = params->eta, alpha = params->alpha;
+    const float *Jf = pl.o_Jf ? at<float>(ws, pl.o_Jf) : nullptr;
+    const float *bf = at<float>(ws, pl.o_bf);
+    const bool skip = pl.is_qubo;
+    float *ckpt = at<float>(ws, rp.o_ckpt), *seg = at<float>(ws, rp.o_seg);
+    float *f = at<float>(ws, rp.o_f), *xbar = at<float>(ws, rp.o_xbar);
+    float *mu = at<float>(ws, rp.o_mu), *jmu = at<float>(ws, rp.o_jmu);
+    double *part = at<double>(ws, rp.o_part), *ploss = at<double>(ws, rp.o_ploss);
+    float *x = at<float>(ws, pl.o_x), *m = at<float>(ws, pl.o_m);
+    const size_t RNB = sizeof(float) * (size_t)RN;
+    const int32_t T = params->steps, k = rp.k;
+
+    QPA_HIP(launch_init_state(n, R, params->seed, params->sigma0, x, m, n, 1, R, n, st));
+    QPA_HIP(hipMemcpyAsync(ckpt, x, RNB, hipMemcpyDeviceToDevice, st));
+    QPA_HIP(hipMemcpyAsync(ckpt + RN, m, RNB, hipMemcpyDeviceToDevice, st));
+    for (int32_t t = 0; t < T; ++t) {
+        QPA_HIP(launch_rel_apply(p, Jf, skip, R, x, f, st));
+        QPA_HIP(launch_rel_update(n, R, f, bf, lam[t], eta, alpha, x, m, st));
+        if ((t + 1) % k == 0 && (t + 1) < T) {
+            float *c = ckpt + (size_t)2 * RN * (size_t)((t + 1) / k);
+            QPA_HIP(hipMemcpyAsync(c, x, RNB, hipMemcpyDeviceToDevice, st));
+            QPA_HIP(hipMemcpyAsync(c + RN, m, RNB, hipMemcpyDeviceToDevice, st));
+        }
+    }
+    QPA_HIP(launch_rel_apply(p, Jf, skip, R, x, f, st));
+    QPA_HIP(launch_rel_loss(n, R, x, f, bf, scale, xbar, ploss, st));
+    QPA_HIP(hipMemsetAsync(mu, 0, RNB, st));
+    for (int32_t c = rp.nseg - 1; c >= 0; --c) {
+        const int32_t t0 = c * k, t1 = std::min(T, (c + 1) * k);
+        const float *cp = ckpt + (size_t)2 * RN * (size_t)c;
+        QPA_HIP(hipMemcpyAsync(x, cp, RNB, hipMemcpyDeviceToDevice, st));
+        QPA_HIP(hipMemcpyAsync(m, cp + RN, RNB, hipMemcpyDeviceToDevice, st));
+        for (int32_t t = t0; t < t1; ++t) {
+            float *sx = seg + (size_t)3 * RN * (size_t)(t - t0);
+            QPA_HIP(launch_rel_apply(p, Jf, skip, R, x, sx + 2 * RN, st));
+            QPA_HIP(hipMemcpyAsync(sx, x, RNB, hipMemcpyDeviceToDevice, st));
+            QPA_HIP(hipMemcpyAsync(sx + RN, m, RNB, hipMemcpyDeviceToDevice, st));
+            QPA_HIP(launch_rel_update(n, R, sx + 2 * RN, bf, lam[t], eta, alpha, x, m, st));
+        }
+        for (int32_t t = t1 - 1; t >= t0; --t) {
+            const float *sx = seg + (size_t)3 * RN * (size_t)(t - t0);
+            QPA_HIP(launch_rel_rev_a(n, R, sx, sx + RN, sx + 2 * RN, bf, lam[t], eta, alpha, xbar,
+                                     mu, part + (size_t)3 * rp.nblk * (size_t)t, st));
+            QPA_HIP(launch_rel_apply(p, Jf, skip, R, mu, jmu, st));
+            QPA_HIP(launch_rel_rev_b(RN, mu, jmu, lam[t], eta, xbar, st));
+        }
+    }
+    QPA_HIP(launch_rel_finish(T, rp.nblk, part, ploss, loss, d_eta, d_alpha, d_lambda, st));
+    return QPA_OK;
+}
+
+qpa_status qpa_workspace_size_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *problems,
+                                    const qpa_params *params, size_t *bytes) {
+    if (!bytes) return fail(ctx, QPA_E_ARG, "bytes is NULL");
+    qpa_status s = check_params(ctx, params);
+    if (s != QPA_OK) return s;
+    BatchPlan bp;
+    s = make_batch_plan(ctx, count, problems, *params, bp);
+    if (s != QPA_OK) return s;
+    *bytes = bp.total;
+    return QPA_OK;
+}
+
+qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *problems,
+                           const qpa_params *params, void *workspace, size_t workspace_bytes,
+                           void *stream, const qpa_outputs *out) {
+    if (!ctx) return QPA_E_ARG;
+    ctx->err.clear();
+    qpa_status s = check_params(ctx, params);
+    if (s != QPA_OK) return s;
+    BatchPlan bp;
+    s = make_batch_plan(ctx, count, problems, *params, bp);
+    if (s != QPA_OK) return s;
+    if (!workspace) return fail(ctx, QPA_E_ARG, "workspace is NULL");
+    if ((reinterpret_cast<uintptr_t>(workspace) % ALIGN) != 0)
+        return fail(ctx, QPA_E_ARG, "workspace must be %zu-byte aligned", ALIGN);
+    if (workspace_bytes < bp.total)
+        return fail(ctx, QPA_E_WORKSPACE, "workspace has %zu bytes, %zu needed", workspace_bytes,
+                    bp.total);
+    if (!out) return fail(ctx, QPA_E_ARG, "out is NULL");
+    for (int32_t k = 0; k < count; ++k)
+        if (!out[k].energy || !out[k].best)
+            return fail(ctx, QPA_E_ARG, "instance %d: outputs.energy and outputs.best are required",
+                        k);
+    QPA_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char *ws = static_cast<char *>(workspace);
+    s = upload_schedule(ctx, *params, reinterpret_cast<float *>(ws + bp.o_lam), st);
+    if (s != QPA_OK) return s;
+
+    // canonicalise + validate every instance, then one read-back of all the flags
+    std::vector<CanonScalars> hsc(count);
+    for (int32_t k = 0; k < count; ++k) {
+        const Plan &pl = bp.inst[k];
+        void *iw = ws + bp.base[k];
+        QPA_HIP(launch_canon_csr(problems[k], at<float>(iw, pl.o_bf), at<int64_t>(iw, pl.o_bi),
+                                 at<double>(iw, pl.o_bd), at<double>(iw, pl.o_rabs),
+                                 at<double>(iw, pl.o_rk), at<CanonScalars>(iw, pl.o_sc), st));
+    }
+    CanonScalars *pinned = nullptr;
+    QPA_HIP(hipHostMalloc((void **)&pinned, sizeof(CanonScalars) * (size_t)count));
+    for (int32_t k = 0; k < count; ++k) {
+        void *iw = ws + bp.base[k];
+        hipError_t e = hipMemcpyAsync(&pinned[k], at<CanonScalars>(iw, bp.inst[k].o_sc),
+                                      sizeof(CanonScalars), hipMemcpyDeviceToHost, st);
+        if (e != hipSuccess) {
+            (void)hipHostFree(pinned);
+            return fail(ctx, QPA_E_DEVICE, "flag read-back failed: %s", hipGetErrorString(e));
+        }
+    }
+    hipError_t se = hipStreamSynchronize(st);
+    for (int32_t k = 0; k < count; ++k) hsc[k] = pinned[k];
+    (void)hipHostFree(pinned);
+    if (se != hipSuccess)
+        return fail(ctx, QPA_E_DEVICE, "synchronise failed: %s", hipGetErrorString(se));
+    for (int32_t k = 0; k < count; ++k) {
+        const int32_t f = hsc[k].flags;
+        if (f & (FLAG_SHAPE | FLAG_UNSORTED))
+            return fail(ctx, QPA_E_SHAPE, "instance %d: CSR structure invalid", k);
+        if (f & FLAG_ASYM) return fail(ctx, QPA_E_ASYM, "instance %d: couplings not symmetric", k);
+        if (f & FLAG_RANGE)
+            return fail(ctx, QPA_E_RANGE, "instance %d: integer row bound %.0f >= 2^24", k,
+                        hsc[k].max_row);
+    }
+
+    // task table, largest instances (most stored entries) first
+    std::vector<std::pair<int64_t, BatchTask>> order;
+    order.reserve(bp.ntasks);
+    const int64_t R = params->replicas;
+    for (int32_t k = 0; k < count; ++k) {
+        const Plan &pl = bp.inst[k];
+        char *iw = ws + bp.base[k];
+        const qpa_problem &p = problems[k];
+        for (int64_t g = 0; g < pl.Rp / 64; ++g) {
+            BatchTask tk{};
+            tk.n = p.n;
+            tk.rp = p.row_ptr;
+            tk.col = p.col;
+            tk.w = p.weights;
+            tk.col_dt = p.index_dtype;
+            tk.w_dt = p.coupling_dtype;
+            tk.is_int = pl.is_int ? 1 : 0;
+            tk.skip_diag = pl.is_qubo ? 1 : 0;
+            tk.b = at<float>(iw, pl.o_bf);
+            tk.x = at<float>(iw, pl.o_x) + g * p.n * 64;
+            tk.m = at<float>(iw, pl.o_m) + g * p.n * 64;
+            tk.seed = params->seed + (uint64_t)k;
+            tk.group = (int32_t)g;
+            tk.nrep = (int32_t)std::min<int64_t>(64, R - 64 * g);
+            order.push_back({p.nnz + p.n, tk});
+        }
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [](const std::pair<int64_t, BatchTask> &a,
+                        const std::pair<int64_t, BatchTask> &b) { return a.first > b.first; });
+    std::vector<BatchTask> tasks;
+    tasks.reserve(order.size());
+    for (auto &pr : order) tasks.push_back(pr.second);
+    BatchTask *htasks = nullptr;
+    QPA_HIP(hipHostMalloc((void **)&htasks, sizeof(BatchTask) * tasks.size()));
+    std::copy(tasks.begin(), tasks.end(), htasks);
+    hipError_t ce = hipMemcpyAsync(ws + bp.o_tasks, htasks, sizeof(BatchTask) * tasks.size(),
+                                   hipMemcpyHostToDevice, st);
+    if (ce == hipSuccess) ce = hipStreamSynchronize(st);
+    (void)hipHostFree(htasks);
+    if (ce != hipSuccess) return fail(ctx, QPA_E_DEVICE, "task upload: %s", hipGetErrorString(ce));
+
+    int cus = 0;
+    QPA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+    const int32_t blocks = (int32_t)std::min<int64_t>(bp.ntasks, (int64_t)cus * 4);
+    int64_t launches = 0;
+    {
+        qpa_ctx::Span sp{};
+        if (ctx->prof) {
+            QPA_HIP(take_event(ctx, &sp.a));
+            QPA_HIP(take_event(ctx, &sp.b));
+            QPA_HIP(hipEventRecord(sp.a, st));
+        }
+        QPA_HIP(launch_csr_batch(reinterpret_cast<const BatchTask *>(ws + bp.o_tasks), bp.ntasks,
+                                 reinterpret_cast<int32_t *>(ws + bp.o_counter), blocks,
+                                 params->steps, reinterpret_cast<const float *>(ws + bp.o_lam),
+                                 params->eta, params->alpha, params->sigma0, bp.max_n, st));
+        launches = 1;
+        if (ctx->prof) {
+            QPA_HIP(hipEventRecord(sp.b, st));
+            sp.launches = launches;
+            ctx->spans.push_back(sp);
+        }
+    }
+
+    // per instance: spins, optional state, exact energies, best replica
+    for (int32_t k = 0; k < count; ++k) {
+        const Plan &pl = bp.inst[k];
+        char *iw = ws + bp.base[k];
+        const qpa_problem &p = problems[k];
+        const qpa_outputs &o = out[k];
+        int8_t *spins = o.spins ? o.spins : at<int8_t>(iw, pl.o_sp);
+        for (int64_t g = 0; g < pl.Rp / 64; ++g) {
+            const int64_t rg = std::min<int64_t>(64, R - 64 * g);
+            const float *xg = at<float>(iw, pl.o_x) + g * p.n * 64;
+            const float *mg = at<float>(iw, pl.o_m) + g * p.n * 64;
+            QPA_HIP(launch_export_spins(p.n, rg, xg, 1, 64, spins + g * 64 * p.n, st));
+            if (o.x) QPA_HIP(launch_copy_state(p.n, rg, xg, 1, 64, o.x + g * 64 * p.n, p.n, 1, st));
+            if (o.m) QPA_HIP(launch_copy_state(p.n, rg, mg, 1, 64, o.m + g * 64 * p.n, p.n, 1, st));
+        }
+        s = score(ctx, p, pl, iw, spins, o.energy, o.energy_i64, o.best, st);
+        if (s != QPA_OK) {
+            std::string msg = "instance " + std::to_string(k) + ": " + ctx->err;
+            return fail(ctx, s, "%s", msg.c_str());
+        }
+    }
+    return QPA_OK;
 }
 
 qpa_status qpa_steps(qpa_ctx *ctx, const qpa_problem *problem, const qpa_params *params,

@@ -74,10 +74,12 @@ hipError_t launch_export_spins(int64_t n, int64_t R, const float *x, int64_t ld_
 
 // Exact energies of int8 spins [R][n] from the caller's original couplings.
 // Integer: e_i64[r] = objective (and e_f64 = (double)e_i64).  Float: e_f64 only.
+// words: scratch of ceil(R/64) * n uint64 (dense problems only).
+int64_t energy_partial_blocks(const qpa_problem &p);
 hipError_t launch_energy(const qpa_problem &p, const int64_t *b_i64, const double *b_f64,
                          const CanonScalars *sc, const int8_t *spins, int64_t R,
                          int64_t *e_i64, double *e_f64, double *partial, int64_t partial_len,
-                         hipStream_t st);
+                         uint64_t *words, hipStream_t st);
 
 // best[0] = lowest r with minimal energy.
 hipError_t launch_argmin(int64_t R, const int64_t *e_i64, const double *e_f64, int32_t *best,
@@ -99,10 +101,10 @@ hipError_t launch_dense_tiled_step(int64_t n, int64_t R, const float *J, const f
 hipError_t launch_sign_f32(int64_t count, const float *x, float *s, hipStream_t st);
 
 // BF16 matrix-core path.  Internal padded layout: x, m [Rp][np] FP32, spin bits
-// [Rp][np/32] uint32 (bit set <=> spin -1), Jb [np][np] bf16.
+// [Rp][np/32] uint32 (bit j of word w <=> variable 32w + j is -1), Jb [np][np] bf16.
 constexpr int MF_BM = 128;   // replicas per tile
 constexpr int MF_BN = 128;   // variables per tile
-constexpr int MF_BK = 64;    // reduction chunk
+constexpr int MF_NPAD = 256; // np is a multiple of this (4 waves x 64-wide chunks)
 hipError_t launch_mfma_pack_spins(int64_t Rp, int64_t np, const float *x, uint32_t *sbits,
                                   hipStream_t st);
 hipError_t launch_mfma_step(int64_t Rp, int64_t np, const uint16_t *Jb, const float *b,
@@ -130,5 +132,40 @@ hipError_t launch_csr_step(const CsrView &c, int64_t Rp, int G, const float *b_f
                            const uint64_t *s_cur, uint64_t *s_nxt, float *x, float *m,
                            float *h_last, int32_t t, const float *lam, float eta, float alpha,
                            bool is_int, hipStream_t st);
+
+// ---- relaxed PA and its adjoint (FP32 state, FP64 inner products) -------------------
+int32_t rel_blocks(int64_t count);
+hipError_t launch_rel_apply(const qpa_problem &p, const float *Jf, bool skip_diag, int64_t R,
+                            const float *v, float *out, hipStream_t st);
+hipError_t launch_rel_update(int64_t n, int64_t R, const float *f, const float *b, float lam,
+                             float eta, float alpha, float *x, float *m, hipStream_t st);
+hipError_t launch_rel_loss(int64_t n, int64_t R, const float *x, const float *f, const float *b,
+                           double scale, float *xbar, double *part, hipStream_t st);
+hipError_t launch_rel_rev_a(int64_t n, int64_t R, const float *x, const float *m, const float *f,
+                            const float *b, float lam, float eta, float alpha, float *xbar,
+                            float *mu, double *part, hipStream_t st);
+hipError_t launch_rel_rev_b(int64_t count, const float *mu, const float *Jmu, float lam,
+                            float eta, float *xbar, hipStream_t st);
+hipError_t launch_rel_finish(int32_t T, int32_t nblk, const double *part_steps,
+                             const double *part_loss, double *loss, double *d_eta,
+                             double *d_alpha, double *d_lam, hipStream_t st);
+
+// ---- batched CSR instances: one persistent launch ------------------------------------
+struct BatchTask {
+    int64_t n;
+    const int32_t *rp;
+    const void *col;
+    const void *w;
+    int32_t col_dt, w_dt;
+    int32_t is_int, skip_diag;
+    const float *b;          // canonical field bias b (FP32), n entries
+    float *x, *m;            // [n][64] state slice of this replica group
+    uint64_t seed;           // the instance's seed
+    int32_t group, nrep;     // replica group index and live replicas in it (<= 64)
+};
+size_t batch_lds_bytes(int32_t max_n);
+hipError_t launch_csr_batch(const BatchTask *tasks, int32_t ntasks, int32_t *next_task,
+                            int32_t blocks, int32_t T, const float *lam, float eta, float alpha,
+                            float sigma0, int32_t max_n, hipStream_t st);
 
 }  // namespace qpa

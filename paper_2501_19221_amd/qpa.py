@@ -37,7 +37,8 @@ QPA_PREC_FP32, QPA_PREC_BF16 = 0, 1
 
 EXPORTED = ["qpa_create", "qpa_destroy", "qpa_last_error", "qpa_status_string",
             "qpa_workspace_size", "qpa_solve", "qpa_steps", "qpa_energy", "qpa_version",
-            "qpa_profile_enable", "qpa_profile_read"]
+            "qpa_profile_enable", "qpa_profile_read", "qpa_workspace_size_batch",
+            "qpa_solve_batch", "qpa_workspace_size_relaxed", "qpa_relaxed_grad"]
 
 
 class qpa_problem(ctypes.Structure):
@@ -79,6 +80,18 @@ _sig = {
                        ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "qpa_energy": (_S, [_P, ctypes.POINTER(qpa_problem), ctypes.POINTER(qpa_params), _P, _P,
                         _P, _P, _P, ctypes.c_size_t, _P]),
+    "qpa_workspace_size_batch": (_S, [_P, ctypes.c_int32, ctypes.POINTER(qpa_problem),
+                                      ctypes.POINTER(qpa_params),
+                                      ctypes.POINTER(ctypes.c_size_t)]),
+    "qpa_solve_batch": (_S, [_P, ctypes.c_int32, ctypes.POINTER(qpa_problem),
+                             ctypes.POINTER(qpa_params), _P, ctypes.c_size_t, _P,
+                             ctypes.POINTER(qpa_outputs)]),
+    "qpa_workspace_size_relaxed": (_S, [_P, ctypes.POINTER(qpa_problem),
+                                        ctypes.POINTER(qpa_params), ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_size_t)]),
+    "qpa_relaxed_grad": (_S, [_P, ctypes.POINTER(qpa_problem), ctypes.POINTER(qpa_params),
+                              ctypes.c_int32, ctypes.c_double, _P, ctypes.c_size_t, _P, _P, _P,
+                              _P, _P]),
     "qpa_profile_enable": (_S, [_P, ctypes.c_int32]),
     "qpa_profile_read": (_S, [_P, ctypes.POINTER(ctypes.c_double),
                               ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]),
@@ -147,6 +160,34 @@ def qpa_energy(ctx, problem, params, spins, energy, energy_i64, best, workspace,
                workspace_bytes, stream):
     _check(ctx, _lib.qpa_energy(ctx, ctypes.byref(problem), ctypes.byref(params), spins, energy,
                                 energy_i64, best, workspace, workspace_bytes, stream))
+
+
+def qpa_workspace_size_batch(ctx, problems, params) -> int:
+    """problems: a ctypes array of qpa_problem."""
+    nbytes = ctypes.c_size_t()
+    _check(ctx, _lib.qpa_workspace_size_batch(ctx, len(problems), problems, ctypes.byref(params),
+                                              ctypes.byref(nbytes)))
+    return nbytes.value
+
+
+def qpa_solve_batch(ctx, problems, params, workspace, workspace_bytes, stream, outputs):
+    """problems / outputs: ctypes arrays of qpa_problem / qpa_outputs of equal length."""
+    _check(ctx, _lib.qpa_solve_batch(ctx, len(problems), problems, ctypes.byref(params),
+                                     workspace, workspace_bytes, stream, outputs))
+
+
+def qpa_workspace_size_relaxed(ctx, problem, params, ckpt_every) -> int:
+    nbytes = ctypes.c_size_t()
+    _check(ctx, _lib.qpa_workspace_size_relaxed(ctx, ctypes.byref(problem), ctypes.byref(params),
+                                                ckpt_every, ctypes.byref(nbytes)))
+    return nbytes.value
+
+
+def qpa_relaxed_grad(ctx, problem, params, ckpt_every, scale, workspace, workspace_bytes,
+                     stream, loss, d_eta, d_alpha, d_lambda):
+    _check(ctx, _lib.qpa_relaxed_grad(ctx, ctypes.byref(problem), ctypes.byref(params),
+                                      ckpt_every, scale, workspace, workspace_bytes, stream,
+                                      loss, d_eta, d_alpha, d_lambda))
 
 
 def qpa_profile_enable(ctx, enable: bool):
@@ -304,6 +345,52 @@ class Engine:
         qpa_solve(self.ctx, ps, params, ctypes.c_void_p(ws.data_ptr()), nbytes, self._stream(), o)
         return out
 
+    def solve_batch(self, probs, params: qpa_params, want_state=False):
+        """Solve a list of CSR Problems in one launch; returns one output dict per problem."""
+        torch = self.torch
+        dev = "cuda:%d" % self.device
+        R = params.replicas
+        pa = (qpa_problem * len(probs))(*[p.struct() for p in probs])
+        nbytes = qpa_workspace_size_batch(self.ctx, pa, params)
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dev)
+        outs = []
+        oa = (qpa_outputs * len(probs))()
+        for k, p in enumerate(probs):
+            o = {"spins": torch.empty((R, p.n), dtype=torch.int8, device=dev),
+                 "energy": torch.empty(R, dtype=torch.float64, device=dev),
+                 "energy_i64": torch.empty(R, dtype=torch.int64, device=dev),
+                 "best": torch.empty(1, dtype=torch.int32, device=dev),
+                 "x": torch.empty((R, p.n), dtype=torch.float32, device=dev) if want_state else None,
+                 "m": torch.empty((R, p.n), dtype=torch.float32, device=dev) if want_state else None}
+            oa[k].spins = o["spins"].data_ptr()
+            oa[k].energy = o["energy"].data_ptr()
+            oa[k].energy_i64 = o["energy_i64"].data_ptr()
+            oa[k].best = o["best"].data_ptr()
+            oa[k].x = o["x"].data_ptr() if want_state else None
+            oa[k].m = o["m"].data_ptr() if want_state else None
+            outs.append(o)
+        qpa_solve_batch(self.ctx, pa, params, ctypes.c_void_p(self._ws.data_ptr()), nbytes,
+                        self._stream(), oa)
+        return outs
+
+    def relaxed_grad(self, prob: Problem, params: qpa_params, ckpt_every: int, scale=None):
+        """Loss and gradients of the relaxed final energy (device float64 tensors):
+        (loss [1], d_eta [1], d_alpha [1], d_lambda [T])."""
+        torch = self.torch
+        dev = "cuda:%d" % self.device
+        ps = prob.struct()
+        nbytes = qpa_workspace_size_relaxed(self.ctx, ps, params, ckpt_every)
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dev)
+        scale = 1.0 / params.replicas if scale is None else scale
+        out = [torch.empty(1, dtype=torch.float64, device=dev) for _ in range(3)]
+        dl = torch.empty(max(params.steps, 1), dtype=torch.float64, device=dev)
+        qpa_relaxed_grad(self.ctx, ps, params, ckpt_every, scale,
+                         ctypes.c_void_p(self._ws.data_ptr()), nbytes, self._stream(),
+                         _ptr(out[0]), _ptr(out[1]), _ptr(out[2]), _ptr(dl))
+        return out[0], out[1], out[2], dl[:params.steps]
+
     def steps(self, prob: Problem, params: qpa_params, t0: int, t1: int, x, m, want_h=False):
         """Advance device tensors x, m ([R,n] float32, contiguous) in place; returns h or None."""
         torch = self.torch
@@ -327,3 +414,40 @@ class Engine:
         qpa_energy(self.ctx, ps, params, _ptr(spins), _ptr(e), _ptr(ei), _ptr(best),
                    ctypes.c_void_p(ws.data_ptr()), nbytes, self._stream())
         return e, ei, best
+
+
+class RelaxedEnergy:
+    """Mean relaxed final energy as a differentiable function of (eta, alpha, lambda_t).
+
+    ``RelaxedEnergy.apply(eta, alpha, lam, engine, problem, replicas, sigma0, seed,
+    ckpt_every)`` with 0-d float64 tensors eta, alpha and a 1-d float64 tensor lam of
+    length T returns the loss; its backward is the library's hand-written adjoint
+    (qpa_relaxed_grad), so gradients flow into whatever produced eta, alpha and lam
+    (e.g. lam = lambda0 * (1 - t/T))."""
+
+    @staticmethod
+    def _fn():
+        import torch
+
+        class _F(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, eta, alpha, lam, engine, problem, replicas, sigma0, seed, ckpt):
+                T = int(lam.numel())
+                table = lam.detach().cpu().numpy().astype(np.float32)
+                p = make_params(replicas, T, float(eta), float(alpha), 0.0, sigma0, seed,
+                                QPA_PREC_FP32, lambda_table=table)
+                loss, de, da, dl = engine.relaxed_grad(problem, p, ckpt)
+                ctx.save_for_backward(de.to(eta.device), da.to(alpha.device),
+                                      dl.to(lam.device))
+                return loss[0].to(eta.device)
+
+            @staticmethod
+            def backward(ctx, g):
+                de, da, dl = ctx.saved_tensors
+                return (g * de[0], g * da[0], g * dl, None, None, None, None, None, None)
+
+        return _F
+
+    @classmethod
+    def apply(cls, *args):
+        return cls._fn().apply(*args)

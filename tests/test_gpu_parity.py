@@ -126,21 +126,28 @@ def test_mfma_float_teacher_forced(q, eng):
     p = _params(q, R, T, 0.2, 0.8, 4.0, prec="bf16")
     x, m = orc.pa_init(n, R, 1, np.float32(0.1))
     rowmag = np.abs(Jq.astype(np.float64)).sum(1) + np.abs(inst.lin)
+    eta, alpha = 0.2, 0.8
     import torch
     for t in range(T):
         x0, m0 = x.copy(), m.copy()
-        h_ref = orc.pa_steps_dense_float(Jq, inst.lin, x0, m0, t, t + 1, lam, 0.2, 0.8,
+        h_ref = orc.pa_steps_dense_float(Jq, inst.lin, x0, m0, t, t + 1, lam, eta, alpha,
                                          want_h=True)
         if t % 15 == 0 or t == T - 1:
             say("mfma teacher-forced step %d" % t)
             xd = torch.from_numpy(x).cuda()
             md = torch.from_numpy(m).cuda()
             h = eng.steps(prob, p, t, t + 1, xd, md, want_h=True)
+            # field: 1e-5 relative to the row's magnitude sum_j |J_ij| + |b_i|
+            tol_h = 1e-5 * rowmag[None, :]
             dh = np.abs(host(h) - h_ref)
-            assert np.all(dh <= 1e-5 * rowmag[None, :]), dh.max()
-            tol = 1e-5 * np.maximum(np.abs(x0), 1e-3)
-            assert np.all(np.abs(host(xd) - x0) <= tol)
-            assert np.all(np.abs(host(md) - m0) <= 1e-5 * np.maximum(np.abs(m0), 1e-3))
+            assert np.all(dh <= tol_h), dh.max()
+            # states: m' = alpha m - eta (lambda x + h) and x' = clip(x + m') move by eta
+            # times the field difference, plus 1e-5 of the magnitude of the update's terms
+            terms = (np.abs(x) + alpha * np.abs(m)
+                     + eta * (np.abs(lam[t] * x) + np.abs(h_ref)))
+            tol_s = eta * tol_h + 1e-5 * terms
+            assert np.all(np.abs(host(md) - m0) <= tol_s)
+            assert np.all(np.abs(host(xd) - x0) <= tol_s)
         x, m = x0, m0
 
 
@@ -366,3 +373,177 @@ def test_empty_csr(q, eng):
     out = eng.solve(prob, _params(q, 2, 400, 0.05, 0.5, 1.0))
     # with no couplings each spin settles opposite to its field
     assert int(host(out["energy_i64"]).min()) == -7
+
+
+# ------------------------------------------------------------------ batched instances
+def _oracle_instance(inst, R, T, lam, eta, alpha, seed, r0=0):
+    x, m, canon = _oracle_csr(inst, R, T, lam, eta, alpha, r0=r0, seed=seed)
+    return x, m, canon
+
+
+def test_batch_uneven_instances_bit_exact(q, eng):
+    rng = np.random.default_rng(7)
+    insts = [gen.er_qubo(int(n), 0.1, 100, rng) for n in rng.integers(30, 400, size=9)]
+    insts.append(gen.chimera_ising(3, seed=5))          # an Ising instance in the same batch
+    R, T, eta, alpha, lam0 = 70, 60, 0.0002, 0.8, 200.0  # 70 replicas: a full and a partial group
+    probs = [q.Problem.from_instance(i) for i in insts]
+    p = _params(q, R, T, eta, alpha, lam0, seed=11)
+    say("batch of %d uneven instances, R=%d T=%d" % (len(insts), R, T))
+    outs = eng.solve_batch(probs, p, want_state=True)
+    lam = orc.lambda_linear(T, lam0)
+    for k, (inst, out) in enumerate(zip(insts, outs)):
+        x, m, canon = _oracle_instance(inst, R, T, lam, eta, alpha, seed=11 + k)
+        assert np.array_equal(host(out["x"]), x), k
+        assert np.array_equal(host(out["m"]), m), k
+        s = np.where(x >= 0, 1, -1).astype(np.int8)
+        assert np.array_equal(host(out["spins"]), s), k
+        e = _energies_csr_int(canon, inst.kind, s)
+        assert np.array_equal(host(out["energy_i64"]), e), k
+        assert int(host(out["best"])[0]) == int(np.flatnonzero(e == e.min())[0]), k
+
+
+def test_er512_full_workload_sampled(q, eng):
+    wl = WORKLOADS["er512"]
+    say("er512 generation")
+    insts = wl.make()
+    probs = [q.Problem.from_instance(i) for i in insts]
+    p = _params(q, wl.replicas, wl.steps, wl.eta, wl.alpha, wl.lambda0, seed=wl.seed)
+    say("er512 full workload solve")
+    outs = eng.solve_batch(probs, p, want_state=True)
+    lam = orc.lambda_linear(wl.steps, wl.lambda0)
+    sizes = np.array([i.n for i in insts])
+    for k in [int(np.argmin(sizes)), int(np.argmax(sizes)), 137]:
+        inst = insts[k]
+        for r0 in [0, wl.replicas - 1]:
+            x, m, canon = _oracle_instance(inst, 1, wl.steps, lam, wl.eta, wl.alpha,
+                                           seed=wl.seed + k, r0=r0)
+            assert np.array_equal(host(outs[k]["x"])[r0], x[0]), (k, r0)
+        s = host(outs[k]["spins"])
+        e = _energies_csr_int(orc.qubo_to_ising_csr_int(inst.csr.rp, inst.csr.col, inst.csr.w,
+                                                        inst.lin), "qubo", s)
+        assert np.array_equal(host(outs[k]["energy_i64"]), e), k
+
+
+# ------------------------------------------------------------------ relaxed adjoint
+def _rel_case(which):
+    if which == "dense":
+        inst = gen.sk_ising(64, 0.1, seed=21)
+        J = inst.dense.astype(np.float64)
+        return inst, lambda x0, T, lam, eta, alpha, grads: orc.relaxed_grad_dense(
+            J, inst.lin, x0, T, lam, eta, alpha, grads=grads)
+    inst = gen.chimera_ising(3, seed=22)
+    c = inst.csr
+    return inst, lambda x0, T, lam, eta, alpha, grads: orc.relaxed_grad_csr(
+        c.rp, c.col, c.w.astype(np.float64), inst.lin, x0, T, lam, eta, alpha, grads=grads)
+
+
+@pytest.mark.parametrize("which", ["dense", "csr"])
+def test_relaxed_adjoint_matches_fp64_oracle_and_fd(q, eng, which):
+    inst, oracle_fn = _rel_case(which)
+    R, T, eta, alpha, lam0, k = 8, 120, 0.05, 0.7, 1.5, 7
+    prob = q.Problem.from_instance(inst)
+    lam = orc.lambda_linear(T, lam0)
+    p = q.make_params(R, T, eta, alpha, lam0, 0.1, 3, lambda_table=lam)
+    say("relaxed adjoint %s R=%d T=%d k=%d" % (which, R, T, k))
+    L, de, da, dl = [host(v) for v in eng.relaxed_grad(prob, p, k)]
+    x0, _ = orc.pa_init(inst.n, R, 3, np.float32(0.1))
+    Lo, deo, dao, dlo = oracle_fn(x0, T, lam.astype(np.float64), float(np.float32(eta)),
+                                  float(np.float32(alpha)), True)
+    assert abs(L[0] - Lo) <= 1e-4 * max(1.0, abs(Lo))
+    assert abs(de[0] - deo) <= 2e-3 * max(1.0, abs(deo))
+    assert abs(da[0] - dao) <= 2e-3 * max(1.0, abs(dao))
+    assert np.max(np.abs(dl - dlo)) <= 2e-3 * max(1.0, np.max(np.abs(dlo)))
+    # central differences of the GPU loss itself
+    eps = 1e-3
+
+    def loss_at(eta_, alpha_):
+        pp = q.make_params(R, T, eta_, alpha_, lam0, 0.1, 3, lambda_table=lam)
+        return float(host(eng.relaxed_grad(prob, pp, k)[0])[0])
+    fd_e = (loss_at(eta + eps, alpha) - loss_at(eta - eps, alpha)) / (2 * eps)
+    fd_a = (loss_at(eta, alpha + eps) - loss_at(eta, alpha - eps)) / (2 * eps)
+    assert abs(de[0] - fd_e) <= 1e-2 * max(1.0, abs(fd_e))
+    assert abs(da[0] - fd_a) <= 1e-2 * max(1.0, abs(fd_a))
+
+
+def test_relaxed_adjoint_independent_of_checkpoint_interval(q, eng):
+    inst = gen.chimera_ising(2, seed=9)
+    prob = q.Problem.from_instance(inst)
+    R, T = 5, 50
+    p = q.make_params(R, T, 0.05, 0.6, 2.0, 0.1, 4)
+    say("relaxed adjoint checkpoint invariance")
+    ref = [host(v) for v in eng.relaxed_grad(prob, p, 1)]
+    for k in [3, 50, 64]:
+        got = [host(v) for v in eng.relaxed_grad(prob, p, k)]
+        for a_, b_ in zip(ref, got):
+            assert np.array_equal(a_, b_), k
+
+
+def test_relaxed_energy_autograd_function(q, eng):
+    import torch
+    inst = gen.sk_ising(48, 0.1, seed=5)
+    prob = q.Problem.from_instance(inst)
+    T = 40
+    eta = torch.tensor(0.05, dtype=torch.float64, requires_grad=True)
+    alpha = torch.tensor(0.7, dtype=torch.float64, requires_grad=True)
+    lam0 = torch.tensor(1.5, dtype=torch.float64, requires_grad=True)
+    lam = lam0 * (1.0 - torch.arange(T, dtype=torch.float64) / T)
+    say("relaxed energy autograd")
+    L = q.RelaxedEnergy.apply(eta, alpha, lam, eng, prob, 6, 0.1, 2, 10)
+    L.backward()
+    p = q.make_params(6, T, 0.05, 0.7, 1.5, 0.1, 2,
+                      lambda_table=lam.detach().numpy().astype(np.float32))
+    _, de, da, dl = [host(v) for v in eng.relaxed_grad(prob, p, 10)]
+    assert abs(eta.grad.item() - de[0]) <= 1e-12 * max(1.0, abs(de[0]))
+    assert abs(alpha.grad.item() - da[0]) <= 1e-12 * max(1.0, abs(da[0]))
+    dlam0 = float(np.dot(dl, 1.0 - np.arange(T) / T))
+    assert abs(lam0.grad.item() - dlam0) <= 1e-9 * max(1.0, abs(dlam0))
+
+
+# ------------------------------------------------------------------ planted 3-regular, n = 1e8
+def test_planted3r_full_workload_sampled(q, eng):
+    import time
+    import torch
+    wl = WORKLOADS["planted3r"]
+    t0 = time.time()
+    say("planted3r: generating n=1e8 (about a minute)")
+    inst = wl.make()
+    c = inst.csr
+    say("planted3r: generated in %.0f s, nnz=%d" % (time.time() - t0, c.nnz))
+    prob = q.Problem.from_instance(inst)
+    R, n = wl.replicas, inst.n
+    # one-step check from a mid-trajectory state, sampled rows computed one by one
+    p = _params(q, R, wl.steps, wl.eta, wl.alpha, wl.lambda0, seed=wl.seed)
+    x0, m0 = orc.pa_init(n, R, wl.seed, np.float32(wl.sigma0))
+    xd, md = torch.from_numpy(x0).cuda(), torch.from_numpy(m0).cuda()
+    del x0, m0
+    say("planted3r: 40 steps on the GPU")
+    eng.steps(prob, p, 0, 40, xd, md)
+    xs, ms = host(xd), host(md)
+    say("planted3r: step 40 with fields")
+    h = host(eng.steps(prob, p, 40, 41, xd, md, want_h=True))
+    lam = orc.lambda_linear(wl.steps, wl.lambda0)
+    rng = np.random.default_rng(0)
+    rows = np.unique(np.concatenate([[0, n - 1], rng.integers(0, n, 2000)]))
+    b = np.zeros(n, np.int64)
+    gx, gm = host(xd), host(md)
+    for r in range(R):
+        hr, xr, mr = orc.pa_step_rows_csr_int(c.rp, c.col, c.w, b, xs[r], ms[r], rows, lam[40],
+                                              wl.eta, wl.alpha)
+        assert np.array_equal(h[r, rows], hr), r
+        assert np.array_equal(gx[r, rows], xr), r
+        assert np.array_equal(gm[r, rows], mr), r
+    del xs, ms, gx, gm, h, xd, md
+    # the full solve: exact energies of every returned replica, planted optimum as bound
+    say("planted3r: full solve")
+    out = eng.solve(prob, p)
+    spins = host(out["spins"])
+    e_star = -int(np.abs(c.w.astype(np.int64)).sum()) // 2
+    say("planted3r: oracle energies")
+    for r in range(R):
+        e = orc.ising_energy_csr_int(c.rp, c.col, c.w, b, spins[r])
+        assert int(host(out["energy_i64"])[r]) == e
+        assert e >= e_star
+    best = int(host(out["best"])[0])
+    say("planted3r: best energy %d, planted optimum %d, gap %.4f%%"
+        % (int(host(out["energy_i64"])[best]), e_star,
+           100.0 * (int(host(out["energy_i64"])[best]) - e_star) / abs(e_star)))
