@@ -72,14 +72,17 @@ def cpu_baseline(inst, wl, prec):
             orc.pa_steps_dense_int(J, b, x, m, 0, steps, lam, wl.eta, wl.alpha)
     else:
         c = inst.csr
-        rp = c.rp.astype(np.int64)
+        if inst.kind == "qubo":
+            rp, col, w, b, _ = orc.qubo_to_ising_csr_int(c.rp, c.col, c.w, inst.lin)
+        else:
+            rp, col, w, b = c.rp.astype(np.int64), c.col, c.w, inst.lin
         reps = min(wl.replicas, 4 * cores)
-        steps = max(1, min(wl.steps, int(2.0e9 / max(1, c.nnz * reps))))
+        steps = max(1, min(wl.steps, int(2.0e10 / max(1, c.nnz * reps))))
         lam = orc.lambda_linear(wl.steps, wl.lambda0)
 
         def work(r0, cnt):
             x, m = orc.pa_init(n, cnt, wl.seed, np.float32(wl.sigma0), r0=r0)
-            orc.pa_steps_csr_int(rp, c.col, c.w, inst.lin, x, m, 0, steps, lam, wl.eta, wl.alpha)
+            orc.pa_steps_csr_int(rp, col, w, b, x, m, 0, steps, lam, wl.eta, wl.alpha)
     per = [reps // cores + (1 if k < reps % cores else 0) for k in range(cores)]
     starts = np.concatenate([[0], np.cumsum(per)[:-1]])
     threads = [threading.Thread(target=work, args=(int(s), int(c))) for s, c in zip(starts, per) if c]
@@ -95,6 +98,31 @@ def cpu_baseline(inst, wl, prec):
                       % (reps, steps, "bf16-rounded" if prec == "bf16" else "exact", dt)}
 
 
+PEAK_ALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # 32-bit VALU lane-ops/s, no packed math
+PEAK_FP32_TFLOPS = 78.6                          # FP32 FMA without packed math
+
+
+def run_solves(eng, qpa, torch, inst, prob, params, steps, warmup, batch):
+    """Time `steps` whole solves; returns (seconds, last output, step-kernel ms, launches)."""
+    solve = (lambda: eng.solve_batch(prob, params)) if batch else (lambda: eng.solve(prob, params))
+    torch.cuda.synchronize()
+    for w in range(warmup):
+        solve()
+        torch.cuda.synchronize()
+        log("warmup %d done" % w)
+    qpa.qpa_profile_read(eng.ctx, reset=True)
+    qpa.qpa_profile_enable(eng.ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = solve()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    qpa.qpa_profile_enable(eng.ctx, False)
+    ms, launches = qpa.qpa_profile_read(eng.ctx, reset=True)
+    return dt, out, ms, launches
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -108,53 +136,67 @@ def main():
 
     wl = WORKLOADS[a.workload]
     log("generating workload %s" % wl.name)
-    inst = wl.make()
+    made = wl.make()
+    batch = isinstance(made, list)
+    insts = made if batch else [made]
     prec = wl.precision
     eng = qpa.Engine(0)
-    prob = qpa.Problem.from_instance(inst)
+    probs = [qpa.Problem.from_instance(i) for i in insts]
+    prob = probs if batch else probs[0]
     pcode = qpa.QPA_PREC_BF16 if prec == "bf16" else qpa.QPA_PREC_FP32
-    params = qpa.make_params(wl.replicas, wl.steps, wl.eta, wl.alpha, wl.lambda0, wl.sigma0,
-                             wl.seed, pcode)
-    torch.cuda.synchronize()
-    for w in range(a.warmup):
-        out = eng.solve(prob, params)
-        torch.cuda.synchronize()
-        log("warmup %d done" % w)
-    qpa.qpa_profile_read(eng.ctx, reset=True)
-    qpa.qpa_profile_enable(eng.ctx, True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(a.steps):
-        out = eng.solve(prob, params)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    qpa.qpa_profile_enable(eng.ctx, False)
-    step_ms, launches = qpa.qpa_profile_read(eng.ctx, reset=True)
+    R, T = wl.replicas, wl.steps
+    params = qpa.make_params(R, T, wl.eta, wl.alpha, wl.lambda0, wl.sigma0, wl.seed, pcode)
+    dt, out, step_ms, launches = run_solves(eng, qpa, torch, insts, prob, params, a.steps,
+                                            a.warmup, batch)
     log("timed %d solves in %.3f s" % (a.steps, dt))
-    n, R, T = inst.n, wl.replicas, wl.steps
-    su = n * R * T * a.steps / dt
-    energy = out["energy"].cpu().numpy()
-    best = int(out["best"].cpu()[0])
+    n_total = sum(i.n for i in insts)
+    su = n_total * R * T * a.steps / dt
     avg_launch_s = step_ms / 1e3 / max(1, launches)
+    per_solve_launches = launches / max(1, a.steps)
 
-    if inst.dense is not None:
-        flops = 2.0 * R * n * n           # one field product per launch
+    inst0 = insts[0]
+    if batch:
+        nnz = sum(i.csr.nnz for i in insts)
+        ops = float(nnz) * R * T              # one signed coupling add per entry, replica, step
+        achieved = ops / avg_launch_s / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TOPS, "unit": "Tops/s",
+                "kernel": "k_csr_batch",
+                "per_launch": "sum(nnz)*R*T = %.4g signed coupling adds (whole batch, all "
+                              "steps, one launch)" % ops}
+        best = [int(o["best"].cpu()[0]) for o in out]
+        bestE = [float(o["energy"].cpu().numpy()[b]) for o, b in zip(out, best)]
+        extra = {"mean_best_energy": float(np.mean(bestE))}
+    elif inst0.dense is not None:
+        n = inst0.n
+        if per_solve_launches <= 1.0:      # LDS-resident kernel: all steps in one launch
+            flops = 2.0 * R * n * n * T
+            what = "2*R*n^2*T = %.4g flop (all steps of all replicas, one launch)" % flops
+        else:
+            flops = 2.0 * R * n * n
+            what = "2*R*n^2 = %.4g flop (one PA step of every replica)" % flops
         achieved = flops / avg_launch_s / 1e12
-        roof = {"bound": "mfma" if prec == "bf16" else "alu", "achieved": achieved,
-                "peak": PEAK_BF16_TFLOPS if prec == "bf16" else 78.6, "unit": "TFLOP/s"}
-        roof["frac"] = achieved / roof["peak"]
-        roof["kernel"] = "k_mfma_step" if prec == "bf16" else "k_dense_*"
-        roof["per_launch"] = "2*R*n^2 = %.4g flop (one PA step of every replica)" % flops
+        if prec == "bf16":
+            roof = {"bound": "mfma", "peak": PEAK_BF16_TFLOPS, "kernel": "k_mfma_step"}
+        else:
+            roof = {"bound": "alu", "peak": PEAK_FP32_TFLOPS,
+                    "kernel": "k_dense_resident" if per_solve_launches <= 1.0
+                    else "k_dense_tiled_step"}
+        roof.update({"achieved": achieved, "unit": "TFLOP/s", "per_launch": what})
+        e = out["energy"].cpu().numpy()
+        extra = {"best_energy": float(e.min()), "best_replica": int(out["best"].cpu()[0])}
     else:
-        c = inst.csr
-        idx = c.col.dtype.itemsize
-        wbytes = c.w.dtype.itemsize
-        byts = (4 * (n + 1) + c.nnz * (idx + wbytes) + 16 * n * R) * 1.0
+        c = inst0.csr
+        n = inst0.n
+        byts = (4.0 * (n + 1) + c.nnz * (c.col.dtype.itemsize + c.w.dtype.itemsize)
+                + 16.0 * n * R)
         achieved = byts / avg_launch_s / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM_GBS, "kernel": "k_csr_step",
-                "per_launch": "row_ptr + nnz*(index+weight) + 16 B of x,m read+write per "
-                              "(variable, replica) = %.4g B" % byts}
+                "kernel": "k_csr_step",
+                "per_launch": "4(n+1) + nnz*(index+weight) + 16*n*R (x, m read and written) "
+                              "= %.4g B (one PA step of every replica)" % byts}
+        e = out["energy"].cpu().numpy()
+        extra = {"best_energy": float(e.min()), "best_replica": int(out["best"].cpu()[0])}
+    roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = None
     roof["avg_launch_us"] = avg_launch_s * 1e6
     roof["launches"] = launches
@@ -163,30 +205,42 @@ def main():
            "steps": a.steps, "warmup": a.warmup, "ms_per_step": dt / a.steps * 1e3,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": prec, "data": "synthetic",
-           "config": {"workload": wl.name, "description": wl.note, "n": n, "replicas": R,
-                      "pa_steps": T, "precision": prec, "eta": wl.eta, "alpha": wl.alpha,
+           "config": {"workload": wl.name, "description": wl.note, "n": n_total,
+                      "instances": len(insts), "replicas": R, "pa_steps": T,
+                      "precision": prec, "eta": wl.eta, "alpha": wl.alpha,
                       "lambda0": wl.lambda0, "parallelism": "single GPU"},
-           "best_energy": float(energy[best]), "best_replica": best,
            "roofline": roof}
+    res.update(extra)
 
     if prec == "bf16" and not a.no_fp32_form:
+        # the same solve with FP32 couplings; when BF16's best energy is worse, BF16 is
+        # rerun with twice the replicas (and its cost counted) until it matches
         p32 = qpa.make_params(R, T, wl.eta, wl.alpha, wl.lambda0, wl.sigma0, wl.seed,
                               qpa.QPA_PREC_FP32)
         log("FP32 form")
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        o32 = eng.solve(prob, p32)
-        torch.cuda.synchronize()
-        d32 = time.perf_counter() - t1
-        e32 = o32["energy"].cpu().numpy()
-        eb, ef = float(energy.min()), float(e32.min())
-        res["fp32_form"] = {"value": n * R * T / d32, "unit": "spin-updates/s",
-                            "best_energy": ef, "bf16_best_energy": eb,
+        d32, o32, _, _ = run_solves(eng, qpa, torch, insts, prob, p32, 1, 0, False)
+        ef = float(o32["energy"].cpu().numpy().min())
+        eb = float(out["energy"].cpu().numpy().min())
+        t_bf = dt / a.steps
+        reps = R
+        while eb > ef + 1e-6 * abs(ef) and reps < 8 * R:
+            reps *= 2
+            log("BF16 with %d replicas" % reps)
+            pb = qpa.make_params(reps, T, wl.eta, wl.alpha, wl.lambda0, wl.sigma0, wl.seed,
+                                 qpa.QPA_PREC_BF16)
+            tb, ob, _, _ = run_solves(eng, qpa, torch, insts, prob, pb, 1, 0, False)
+            t_bf = tb
+            eb = float(ob["energy"].cpu().numpy().min())
+        res["fp32_form"] = {"value": n_total * R * T / d32, "unit": "spin-updates/s",
+                            "seconds_per_solve": d32, "best_energy": ef,
+                            "bf16_best_energy": eb, "bf16_replicas_to_match": reps,
                             "matched": bool(eb <= ef + 1e-6 * abs(ef)),
-                            "bf16_speedup": (n * R * T * a.steps / dt) / (n * R * T / d32)}
+                            "bf16_speedup_at_matched_energy": d32 / t_bf}
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        res["cpu_baseline"] = cpu_baseline(inst, wl, prec)
+        res["cpu_baseline"] = cpu_baseline(inst0, wl, prec)
+        if batch:
+            res["cpu_baseline"]["sample"] += " (first instance of the batch)"
     eng.close()
     print(json.dumps(res), flush=True)
 

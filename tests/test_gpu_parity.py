@@ -440,7 +440,9 @@ def _rel_case(which):
 @pytest.mark.parametrize("which", ["dense", "csr"])
 def test_relaxed_adjoint_matches_fp64_oracle_and_fd(q, eng, which):
     inst, oracle_fn = _rel_case(which)
-    R, T, eta, alpha, lam0, k = 8, 120, 0.05, 0.7, 1.5, 7
+    # a regime where the relaxed trajectories stay inside [-1, 1] long enough for the loss
+    # to be smooth in (eta, alpha): finite differences are meaningless across clip kinks
+    R, T, eta, alpha, lam0, k = 8, 30, 0.01, 0.5, 4.0, 7
     prob = q.Problem.from_instance(inst)
     lam = orc.lambda_linear(T, lam0)
     p = q.make_params(R, T, eta, alpha, lam0, 0.1, 3, lambda_table=lam)
@@ -449,18 +451,18 @@ def test_relaxed_adjoint_matches_fp64_oracle_and_fd(q, eng, which):
     x0, _ = orc.pa_init(inst.n, R, 3, np.float32(0.1))
     Lo, deo, dao, dlo = oracle_fn(x0, T, lam.astype(np.float64), float(np.float32(eta)),
                                   float(np.float32(alpha)), True)
+    assert abs(deo) > 1.0 and abs(dao) > 0.1          # a non-trivial gradient is checked
     assert abs(L[0] - Lo) <= 1e-4 * max(1.0, abs(Lo))
     assert abs(de[0] - deo) <= 2e-3 * max(1.0, abs(deo))
     assert abs(da[0] - dao) <= 2e-3 * max(1.0, abs(dao))
     assert np.max(np.abs(dl - dlo)) <= 2e-3 * max(1.0, np.max(np.abs(dlo)))
-    # central differences of the GPU loss itself
-    eps = 1e-3
-
+    # central differences of the GPU loss itself (steps of 1% of eta and 0.2% of alpha)
     def loss_at(eta_, alpha_):
         pp = q.make_params(R, T, eta_, alpha_, lam0, 0.1, 3, lambda_table=lam)
         return float(host(eng.relaxed_grad(prob, pp, k)[0])[0])
-    fd_e = (loss_at(eta + eps, alpha) - loss_at(eta - eps, alpha)) / (2 * eps)
-    fd_a = (loss_at(eta, alpha + eps) - loss_at(eta, alpha - eps)) / (2 * eps)
+    he, ha = 1e-2 * eta, 1e-3
+    fd_e = (loss_at(eta + he, alpha) - loss_at(eta - he, alpha)) / (2 * he)
+    fd_a = (loss_at(eta, alpha + ha) - loss_at(eta, alpha - ha)) / (2 * ha)
     assert abs(de[0] - fd_e) <= 1e-2 * max(1.0, abs(fd_e))
     assert abs(da[0] - fd_a) <= 1e-2 * max(1.0, abs(fd_a))
 
