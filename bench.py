@@ -119,8 +119,14 @@ def run_solves(eng, qpa, torch, inst, prob, params, steps, warmup, batch):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     qpa.qpa_profile_enable(eng.ctx, False)
+    per_path = {}
+    for code in (qpa.QPA_PATH_DENSE_RESIDENT, qpa.QPA_PATH_DENSE_TILED, qpa.QPA_PATH_DENSE_MFMA,
+                 qpa.QPA_PATH_CSR, qpa.QPA_PATH_BATCH_SPARSE, qpa.QPA_PATH_BATCH_DENSE):
+        pm, pl = qpa.qpa_profile_read_path(eng.ctx, code)
+        if pl:
+            per_path[code] = (pm, pl)
     ms, launches = qpa.qpa_profile_read(eng.ctx, reset=True)
-    return dt, out, ms, launches
+    return dt, out, ms, launches, per_path
 
 
 def main():
@@ -146,8 +152,8 @@ def main():
     pcode = qpa.QPA_PREC_BF16 if prec == "bf16" else qpa.QPA_PREC_FP32
     R, T = wl.replicas, wl.steps
     params = qpa.make_params(R, T, wl.eta, wl.alpha, wl.lambda0, wl.sigma0, wl.seed, pcode)
-    dt, out, step_ms, launches = run_solves(eng, qpa, torch, insts, prob, params, a.steps,
-                                            a.warmup, batch)
+    dt, out, step_ms, launches, per_path = run_solves(eng, qpa, torch, insts, prob, params,
+                                                      a.steps, a.warmup, batch)
     log("timed %d solves in %.3f s" % (a.steps, dt))
     n_total = sum(i.n for i in insts)
     su = n_total * R * T * a.steps / dt
@@ -156,13 +162,40 @@ def main():
 
     inst0 = insts[0]
     if batch:
-        nnz = sum(i.csr.nnz for i in insts)
-        ops = float(nnz) * R * T              # one signed coupling add per entry, replica, step
-        achieved = ops / avg_launch_s / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_ALU_TOPS, "unit": "Tops/s",
-                "kernel": "k_csr_batch",
-                "per_launch": "sum(nnz)*R*T = %.4g signed coupling adds (whole batch, all "
-                              "steps, one launch)" % ops}
+        paths = qpa.qpa_batch_paths(eng.ctx, len(insts))
+        dense = paths == qpa.QPA_PATH_BATCH_DENSE
+        roofs = {}
+        if qpa.QPA_PATH_BATCH_DENSE in per_path:
+            pm, pl = per_path[qpa.QPA_PATH_BATCH_DENSE]
+            nd = np.array([i.n for i, d in zip(insts, dense) if d], np.float64)
+            # one step: the BF16 coupling matrix read once, x and m read and written
+            byts = float(np.sum(2.0 * nd * nd + 16.0 * R * nd))
+            roofs["dense"] = {
+                "bound": "hbm", "achieved": byts / (pm / 1e3 / pl) / 1e9, "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "kernel": "k_mfma_grouped", "ms": pm, "launches": pl,
+                "instances": int(dense.sum()),
+                "per_launch": "sum over dense instances of 2n^2 (BF16 couplings) + 16nR "
+                              "(x, m read and written) = %.4g B (one PA step of every "
+                              "replica of every dense instance)" % byts}
+        if qpa.QPA_PATH_BATCH_SPARSE in per_path:
+            pm, pl = per_path[qpa.QPA_PATH_BATCH_SPARSE]
+            nnz = sum(i.csr.nnz for i, d in zip(insts, dense) if not d)
+            ops = float(nnz) * R * T          # one signed coupling add per entry, replica, step
+            roofs["sparse"] = {
+                "bound": "alu", "achieved": ops / (pm / 1e3 / pl) / 1e12, "peak": PEAK_ALU_TOPS,
+                "unit": "Tops/s", "kernel": "k_csr_batch", "ms": pm, "launches": pl,
+                "instances": int((~dense).sum()),
+                "per_launch": "sum(nnz)*R*T = %.4g signed coupling adds (sparse instances, "
+                              "all steps, one launch)" % ops}
+        main_path = max(roofs, key=lambda k: roofs[k]["ms"])
+        roof = dict(roofs[main_path])
+        avg_launch_s = roof.pop("ms") / 1e3 / roof["launches"]
+        launches = roof.pop("launches")
+        if len(roofs) > 1:
+            other = [k for k in roofs if k != main_path][0]
+            o = dict(roofs[other])
+            o["frac"] = o["achieved"] / o["peak"]
+            roof["other_path"] = o
         best = [int(o["best"].cpu()[0]) for o in out]
         bestE = [float(o["energy"].cpu().numpy()[b]) for o, b in zip(out, best)]
         extra = {"mean_best_energy": float(np.mean(bestE))}
@@ -218,7 +251,7 @@ def main():
         p32 = qpa.make_params(R, T, wl.eta, wl.alpha, wl.lambda0, wl.sigma0, wl.seed,
                               qpa.QPA_PREC_FP32)
         log("FP32 form")
-        d32, o32, _, _ = run_solves(eng, qpa, torch, insts, prob, p32, 1, 0, False)
+        d32, o32, _, _, _ = run_solves(eng, qpa, torch, insts, prob, p32, 1, 0, False)
         ef = float(o32["energy"].cpu().numpy().min())
         eb = float(out["energy"].cpu().numpy().min())
         t_bf = dt / a.steps
@@ -228,7 +261,7 @@ def main():
             log("BF16 with %d replicas" % reps)
             pb = qpa.make_params(reps, T, wl.eta, wl.alpha, wl.lambda0, wl.sigma0, wl.seed,
                                  qpa.QPA_PREC_BF16)
-            tb, ob, _, _ = run_solves(eng, qpa, torch, insts, prob, pb, 1, 0, False)
+            tb, ob, _, _, _ = run_solves(eng, qpa, torch, insts, prob, pb, 1, 0, False)
             t_bf = tb
             eb = float(ob["energy"].cpu().numpy().min())
         res["fp32_form"] = {"value": n_total * R * T / d32, "unit": "spin-updates/s",

@@ -106,8 +106,17 @@ typedef struct {
     const float *lambda_table;  /* host, optional                               */
     uint64_t seed;              /* SplitMix64 seed of the initial state          */
     int32_t precision;          /* qpa_precision (dense path)                   */
-    int32_t flags;              /* must be 0                                    */
+    int32_t flags;              /* 0, or one qpa_batch_flags value (batch only) */
 } qpa_params;
+
+/* Path choice of qpa_solve_batch (params.flags; qpa_solve requires 0).  By default
+ * every instance whose couplings are exact in BF16 (integer weights with |w| <= 256,
+ * or any weights when precision is QPA_PREC_BF16) runs as dense matrix-core tiles when
+ * a cost model finds that cheaper than the sparse kernel; the others run sparse. */
+typedef enum {
+    QPA_BATCH_SPARSE = 1,       /* every instance on the sparse task kernel      */
+    QPA_BATCH_DENSE = 2         /* every BF16-exact instance as dense tiles      */
+} qpa_batch_flags;
 
 /* Outputs of a solve.  Every pointer is a device pointer and may be NULL except
  * `energy` and `best`.
@@ -157,15 +166,21 @@ qpa_status qpa_solve(qpa_ctx *ctx, const qpa_problem *problem, const qpa_params 
                      void *workspace, size_t workspace_bytes, void *stream,
                      const qpa_outputs *out);
 
-/* Solve `count` independent sparse instances in one persistent launch (the batch shares
- * params).  Instance k is solved exactly as qpa_solve would solve it alone with seed
+/* Solve `count` independent sparse instances together (the batch shares params).
+ * Instance k is solved exactly as qpa_solve would solve it alone with seed
  * params->seed + k; its outputs go to out[k].
  *  problems : host array of `count` CSR problems (format QPA_FMT_CSR, n <= 4096).
  *  out      : host array of `count` output sets (device pointers as in qpa_outputs).
- *  workspace: device buffer of at least qpa_workspace_size_batch() bytes.
- * Work is split into tasks (instance, group of 64 replicas), sorted by stored entries,
- * largest first, and taken by workgroups from an atomic counter; no workgroup waits on
- * another.  Errors name the offending instance in qpa_last_error(). */
+ *  workspace: device buffer of at least qpa_workspace_size_batch() bytes, for the same
+ *             problems and params (flags included).
+ * Two paths, chosen per instance (see qpa_batch_flags):
+ *  - sparse: tasks (instance, group of 64 replicas), sorted by stored entries, largest
+ *    first, taken by the workgroups of one persistent launch from an atomic counter;
+ *    no workgroup waits on another;
+ *  - dense: the couplings are expanded once into a BF16 matrix (exact, see above) and
+ *    every PA step is one grouped matrix-core launch over the 128x128 tiles of all such
+ *    instances.  Integer instances give the same bits on both paths.
+ * Errors name the offending instance in qpa_last_error(). */
 qpa_status qpa_workspace_size_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *problems,
                                     const qpa_params *params, size_t *bytes);
 qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *problems,
@@ -211,16 +226,36 @@ qpa_status qpa_relaxed_grad(qpa_ctx *ctx, const qpa_problem *problem, const qpa_
                             size_t workspace_bytes, void *stream, double *loss, double *d_eta,
                             double *d_alpha, double *d_lambda);
 
-/* Measurement of the PA-step kernels.  While enabled (enable != 0), every qpa_solve and
- * qpa_steps call records one HIP event on its stream right before its first step kernel
- * and one right after its last, and counts the step kernels it launched.
- * qpa_profile_read waits for the recorded events and returns the summed elapsed time in
- * milliseconds and the number of step-kernel launches since the last reset (reset != 0
- * clears the totals after reading).  The averaged interval includes the gaps between
- * consecutive step kernels of one call. */
+/* Step kernels, as named by the profiling calls and qpa_batch_paths. */
+typedef enum {
+    QPA_PATH_ALL = -1,           /* qpa_profile_read_path: every kernel           */
+    QPA_PATH_DENSE_RESIDENT = 0, /* FP32 couplings held in LDS, all steps at once */
+    QPA_PATH_DENSE_TILED = 1,    /* FP32 couplings streamed, one launch per step  */
+    QPA_PATH_DENSE_MFMA = 2,     /* BF16 matrix-core step, one launch per step    */
+    QPA_PATH_CSR = 3,            /* sparse step, one launch per step              */
+    QPA_PATH_BATCH_SPARSE = 4,   /* persistent sparse task kernel (all steps)     */
+    QPA_PATH_BATCH_DENSE = 5     /* grouped matrix-core step over many instances  */
+} qpa_path;
+
+/* Measurement of the PA-step kernels.  While enabled (enable != 0), every qpa_solve,
+ * qpa_solve_batch and qpa_steps call records one HIP event on its stream right before
+ * its first step kernel of a path and one right after its last, and counts the step
+ * kernels it launched.  qpa_profile_read waits for the recorded events and returns the
+ * summed elapsed time in milliseconds and the number of step-kernel launches since the
+ * last reset (reset != 0 clears the totals after reading); qpa_profile_read_path does the
+ * same for the kernels of one qpa_path only (QPA_PATH_ALL: every kernel; reset clears
+ * everything).  The averaged interval includes the gaps between consecutive step kernels
+ * of one call. */
 qpa_status qpa_profile_enable(qpa_ctx *ctx, int32_t enable);
 qpa_status qpa_profile_read(qpa_ctx *ctx, double *step_ms, int64_t *step_launches,
                             int32_t reset);
+qpa_status qpa_profile_read_path(qpa_ctx *ctx, int32_t path, double *step_ms,
+                                 int64_t *step_launches, int32_t reset);
+
+/* The path (QPA_PATH_BATCH_SPARSE or QPA_PATH_BATCH_DENSE) that each instance of the
+ * last successful qpa_solve_batch on this context took; `count` must equal that call's
+ * count.  paths: host array of `count` int32. */
+qpa_status qpa_batch_paths(const qpa_ctx *ctx, int32_t count, int32_t *paths);
 
 /* Library version string. */
 const char *qpa_version(void);

@@ -65,18 +65,17 @@ __device__ __forceinline__ bf16x8 expand_spins(uint32_t byte) {
 
 typedef __attribute__((address_space(3))) void lds_void;
 
-__global__ void __launch_bounds__(256, 1) k_mfma_step(
-    int64_t Rp, int64_t np, const uint16_t *__restrict__ Jb, const float *__restrict__ b,
-    const CanonScalars *__restrict__ sc, const uint64_t *__restrict__ s_cur,
-    uint32_t *__restrict__ s_nxt, float *__restrict__ x, float *__restrict__ m,
-    float *__restrict__ h_last, int t, const float *__restrict__ lam, float eta, float alpha) {
-    // 4 waves x 2 stages of (J block, spin words); reused after the loop as the
-    // cross-wave reduction buffer [destination fragment][source wave][register][lane]
-    __shared__ __attribute__((aligned(16))) uint8_t lds[4 * 2 * STG];
+// One 128 x 128 output tile of one PA step: replicas R0 .. R0+127 (rows at or past
+// `rlive` are padding: no state traffic), variables I0 .. I0+127.  `lds` holds
+// 4 * 2 * STG bytes.
+__device__ __forceinline__ void mfma_tile_step(
+    uint8_t *lds, int64_t np, int64_t I0, int64_t R0, int64_t rlive,
+    const uint16_t *__restrict__ Jb, const float *__restrict__ b, float scale,
+    const uint64_t *__restrict__ s_cur, uint32_t *__restrict__ s_nxt, float *__restrict__ x,
+    float *__restrict__ m, float *__restrict__ h_last, float lt, float eta, float alpha) {
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int half = lane >> 5, l32 = lane & 31;
-    const int64_t I0 = (int64_t)blockIdx.x * BN, R0 = (int64_t)blockIdx.y * BM;
     const int64_t kq = np / 4;                 // reduction length of one wave
     const int64_t kb = (int64_t)w * kq;
     const int nchunk = (int)(kq / 64);
@@ -174,8 +173,6 @@ __global__ void __launch_bounds__(256, 1) k_mfma_step(
         __syncthreads();
     }
 
-    const float scale = sc->scale;
-    const float lt = lam[t];
     const int64_t wrow = np / 32;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -186,17 +183,45 @@ __global__ void __launch_bounds__(256, 1) k_mfma_step(
         for (int v = 0; v < 16; ++v) {
             const int64_t r = R0 + 32 * w + 8 * (v >> 2) + 4 * half + (v & 3);
             const int64_t g = r * np + iv;
-            float h = __fadd_rn(__fmul_rn(fin[j][v], scale), bi);
-            float xv = x[g], mv = m[g];
-            pa_update(h, lt, eta, alpha, xv, mv);
-            x[g] = xv;
-            m[g] = mv;
-            if (h_last) h_last[g] = h;
+            float xv = 0.0f;
+            if (r < rlive) {
+                float h = __fadd_rn(__fmul_rn(fin[j][v], scale), bi);
+                float mv = m[g];
+                xv = x[g];
+                pa_update(h, lt, eta, alpha, xv, mv);
+                x[g] = xv;
+                m[g] = mv;
+                if (h_last) h_last[g] = h;
+            }
             uint64_t bal = __ballot(xv < 0.0f);
             uint32_t word = half ? (uint32_t)(bal >> 32) : (uint32_t)bal;
             if (l32 == 0) s_nxt[r * wrow + wcol] = word;
         }
     }
+}
+
+__global__ void __launch_bounds__(256, 1) k_mfma_step(
+    int64_t Rp, int64_t np, int64_t rlive, const uint16_t *__restrict__ Jb,
+    const float *__restrict__ b, const CanonScalars *__restrict__ sc,
+    const uint64_t *__restrict__ s_cur, uint32_t *__restrict__ s_nxt, float *__restrict__ x,
+    float *__restrict__ m, float *__restrict__ h_last, int t, const float *__restrict__ lam,
+    float eta, float alpha) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds[4 * 2 * STG];
+    mfma_tile_step(lds, np, (int64_t)blockIdx.x * BN, (int64_t)blockIdx.y * BM, rlive, Jb, b,
+                   sc->scale, s_cur, s_nxt, x, m, h_last, lam[t], eta, alpha);
+}
+
+// Many instances in one launch: block k runs tile k of the table.  Each tile points at
+// its instance's couplings, bias, state and the two spin buffers (picked by step parity).
+__global__ void __launch_bounds__(256, 1) k_mfma_grouped(const MfmaTile *__restrict__ tiles,
+                                                         int t, const float *__restrict__ lam,
+                                                         float eta, float alpha) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds[4 * 2 * STG];
+    const MfmaTile tl = tiles[blockIdx.x];
+    const uint64_t *cur = reinterpret_cast<const uint64_t *>((t & 1) ? tl.s1 : tl.s0);
+    uint32_t *nxt = (t & 1) ? tl.s0 : tl.s1;
+    mfma_tile_step(lds, tl.np, tl.I0, tl.R0, tl.rlive, tl.Jb, tl.b, tl.sc->scale, cur, nxt, tl.x,
+                   tl.m, nullptr, lam[t], eta, alpha);
 }
 
 // sbits[r][w] bit j = (x[r][32w + j] < 0)
@@ -226,16 +251,69 @@ hipError_t launch_mfma_pack_spins(int64_t Rp, int64_t np, const float *x, uint32
     return hipGetLastError();
 }
 
-hipError_t launch_mfma_step(int64_t Rp, int64_t np, const uint16_t *Jb, const float *b,
-                            const CanonScalars *sc, const uint32_t *s_cur, uint32_t *s_nxt,
-                            float *x, float *m, float *h_last, int32_t t, const float *lam,
-                            float eta, float alpha, hipStream_t st) {
+hipError_t launch_mfma_step(int64_t Rp, int64_t np, int64_t rlive, const uint16_t *Jb,
+                            const float *b, const CanonScalars *sc, const uint32_t *s_cur,
+                            uint32_t *s_nxt, float *x, float *m, float *h_last, int32_t t,
+                            const float *lam, float eta, float alpha, hipStream_t st) {
     if (Rp % BM || np % MF_NPAD) return hipErrorInvalidValue;
     dim3 grid((unsigned)(np / BN), (unsigned)(Rp / BM));
-    k_mfma_step<<<grid, 256, 0, st>>>(Rp, np, Jb, b, sc,
+    k_mfma_step<<<grid, 256, 0, st>>>(Rp, np, rlive, Jb, b, sc,
                                       reinterpret_cast<const uint64_t *>(s_cur), s_nxt, x, m,
                                       h_last, t, lam, eta, alpha);
     return hipGetLastError();
+}
+
+hipError_t launch_mfma_grouped(const MfmaTile *tiles, int32_t ntiles, int32_t t,
+                               const float *lam, float eta, float alpha, hipStream_t st) {
+    if (ntiles <= 0) return hipSuccess;
+    k_mfma_grouped<<<(unsigned)ntiles, 256, 0, st>>>(tiles, t, lam, eta, alpha);
+    return hipGetLastError();
+}
+
+// Dense BF16 copy of a CSR instance: Jb[i][j] = bf16(w_ij * 2^-e) for the stored
+// off-diagonal entries (zero elsewhere; the caller clears Jb first).
+template <typename TW, typename TI>
+__global__ void __launch_bounds__(256) k_csr_to_bf16(int64_t n, int64_t np,
+                                                     const int32_t *__restrict__ rp,
+                                                     const TI *__restrict__ col,
+                                                     const TW *__restrict__ w,
+                                                     const CanonScalars *__restrict__ sc,
+                                                     uint16_t *__restrict__ Jb) {
+    const float inv = sc->inv_scale;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+            const int64_t j = (int64_t)col[k];
+            if (j == i) continue;
+            uint32_t u = __float_as_uint(__fmul_rn((float)w[k], inv));
+            u += 0x7fffu + ((u >> 16) & 1u);
+            Jb[i * np + j] = (uint16_t)(u >> 16);
+        }
+    }
+}
+
+hipError_t launch_csr_to_bf16(const qpa_problem &p, int64_t np, const CanonScalars *sc,
+                              uint16_t *Jb, hipStream_t st) {
+    hipError_t e = hipMemsetAsync(Jb, 0, sizeof(uint16_t) * (size_t)(np * np), st);
+    if (e != hipSuccess) return e;
+    int64_t g = (p.n + 255) / 256;
+    auto run = [&](auto wtag, auto itag) {
+        using TW = decltype(wtag);
+        using TI = decltype(itag);
+        k_csr_to_bf16<TW, TI><<<(unsigned)g, 256, 0, st>>>(
+            p.n, np, p.row_ptr, static_cast<const TI *>(p.col),
+            static_cast<const TW *>(p.weights), sc, Jb);
+        return hipGetLastError();
+    };
+    auto byw = [&](auto itag) -> hipError_t {
+        switch (p.coupling_dtype) {
+            case QPA_I8: return run((int8_t)0, itag);
+            case QPA_I16: return run((int16_t)0, itag);
+            case QPA_I32: return run((int32_t)0, itag);
+            default: return run(0.0f, itag);
+        }
+    };
+    return p.index_dtype == QPA_I16 ? byw((int16_t)0) : byw((int32_t)0);
 }
 
 }  // namespace qpa

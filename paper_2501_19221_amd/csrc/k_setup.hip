@@ -193,11 +193,13 @@ __global__ void __launch_bounds__(256) k_csr_rows(int64_t n, int64_t nnz,
                                                   int64_t *__restrict__ b_i64,
                                                   double *__restrict__ b_f64,
                                                   double *__restrict__ row_abs,
+                                                  double *__restrict__ row_max,
                                                   double *__restrict__ row_k,
                                                   CanonScalars *sc) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int32_t flags = 0;
+    double smax = 0.0;
     const int64_t k0 = rp[i], k1 = rp[i + 1];
     if (i == 0 && k0 != 0) flags |= FLAG_SHAPE;
     if (i == n - 1 && k1 != nnz) flags |= FLAG_SHAPE;
@@ -222,6 +224,7 @@ __global__ void __launch_bounds__(256) k_csr_rows(int64_t n, int64_t nnz,
                 continue;
             }
             sabs += fabs(v);
+            smax = fmax(smax, fabs(v));
             // symmetric partner (j, i) with the same weight: binary search in row j
             int64_t lo = rp[j], hi = rp[j + 1] - 1;
             bool found = false;
@@ -244,6 +247,7 @@ __global__ void __launch_bounds__(256) k_csr_rows(int64_t n, int64_t nnz,
     if (b_i64) b_i64[i] = (int64_t)bx;
     b_f64[i] = bx;
     row_abs[i] = sabs + fabs(bx);
+    if (row_max) row_max[i] = smax;
     row_k[i] = is_qubo ? (sum + diag + 2.0 * c) : 0.0;
     if (flags) atomicOr(&sc->flags, flags);
 }
@@ -573,7 +577,8 @@ hipError_t launch_canon_dense(const qpa_problem &p, float *J_f32, uint16_t *Jb, 
 }
 
 hipError_t launch_canon_csr(const qpa_problem &p, float *b_f32, int64_t *b_i64, double *b_f64,
-                            double *row_abs, double *row_k, CanonScalars *sc, hipStream_t st) {
+                            double *row_abs, double *row_max, double *row_k, CanonScalars *sc,
+                            hipStream_t st) {
     const int64_t n = p.n;
     const int32_t is_qubo = p.kind == QPA_KIND_QUBO;
     const int32_t is_int = dtype_is_int(p.coupling_dtype) &&
@@ -586,8 +591,8 @@ hipError_t launch_canon_csr(const qpa_problem &p, float *b_f32, int64_t *b_i64, 
         k_csr_rows<TW, TI><<<grid1(n, 256, INT64_MAX), 256, 0, st>>>(
             n, p.nnz, p.row_ptr, static_cast<const TI *>(p.col),
             static_cast<const TW *>(p.weights), p.linear, p.linear_dtype, is_qubo, b_f32, b_i64,
-            b_f64, row_abs, row_k, sc);
-        k_canon_finalize<<<1, 1024, 0, st>>>(n, row_abs, nullptr, row_k, is_int, sc);
+            b_f64, row_abs, row_max, row_k, sc);
+        k_canon_finalize<<<1, 1024, 0, st>>>(n, row_abs, row_max, row_k, is_int, sc);
         return hipGetLastError();
     };
     return dispatch_q(p.coupling_dtype, [&](auto wtag) {

@@ -22,9 +22,11 @@ struct qpa_ctx {
     struct Span {
         hipEvent_t a, b;
         int64_t launches;
+        int32_t path;
     };
     std::vector<Span> spans;
     std::vector<hipEvent_t> free_events;
+    std::vector<int32_t> batch_paths;       // per instance, last qpa_solve_batch
 };
 
 namespace qpa {
@@ -36,6 +38,15 @@ inline size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
 enum class Path { DenseResident, DenseTiled, DenseMfma, Csr };
+
+int32_t path_code(Path p) {
+    switch (p) {
+        case Path::DenseResident: return QPA_PATH_DENSE_RESIDENT;
+        case Path::DenseTiled: return QPA_PATH_DENSE_TILED;
+        case Path::DenseMfma: return QPA_PATH_DENSE_MFMA;
+        default: return QPA_PATH_CSR;
+    }
+}
 
 const char *path_name(Path p) {
     switch (p) {
@@ -202,6 +213,15 @@ qpa_status check_params(qpa_ctx *ctx, const qpa_params *a) {
     return QPA_OK;
 }
 
+qpa_status check_batch_params(qpa_ctx *ctx, const qpa_params *a) {
+    if (!a) return fail(ctx, QPA_E_ARG, "params is NULL");
+    qpa_params b = *a;
+    if (b.flags != 0 && b.flags != QPA_BATCH_SPARSE && b.flags != QPA_BATCH_DENSE)
+        return fail(ctx, QPA_E_ARG, "params.flags must be 0, QPA_BATCH_SPARSE or QPA_BATCH_DENSE");
+    b.flags = 0;
+    return check_params(ctx, &b);
+}
+
 template <typename T> T *at(void *ws, size_t off) {
     return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
 }
@@ -246,7 +266,8 @@ qpa_status canonicalise(qpa_ctx *ctx, const qpa_problem &p, const Plan &pl, void
                                    at<double>(ws, pl.o_rmax), at<double>(ws, pl.o_rk), sc, st));
     } else {
         QPA_HIP(launch_canon_csr(p, bf, at<int64_t>(ws, pl.o_bi), at<double>(ws, pl.o_bd),
-                                 at<double>(ws, pl.o_rabs), at<double>(ws, pl.o_rk), sc, st));
+                                 at<double>(ws, pl.o_rabs), at<double>(ws, pl.o_rmax),
+                                 at<double>(ws, pl.o_rk), sc, st));
     }
     QPA_HIP(hipMemcpyAsync(ctx->host_sc, sc, sizeof(CanonScalars), hipMemcpyDeviceToHost, st));
     QPA_HIP(hipStreamSynchronize(st));
@@ -292,6 +313,7 @@ qpa_status run_steps(qpa_ctx *ctx, const qpa_problem &p, const qpa_params &a, co
     qpa_status s = run_steps_inner(ctx, p, a, pl, ws, t0, t1, want_h, st, launches);
     QPA_HIP(hipEventRecord(sp.b, st));
     sp.launches = launches;
+    sp.path = path_code(pl.path);
     ctx->spans.push_back(sp);
     return s;
 }
@@ -327,9 +349,9 @@ qpa_status run_steps_inner(qpa_ctx *ctx, const qpa_problem &p, const qpa_params 
             launches = t1 - t0;
             const CanonScalars *sc = at<CanonScalars>(ws, pl.o_sc);
             for (int32_t t = t0; t < t1; ++t) {
-                QPA_HIP(launch_mfma_step(pl.Rp, pl.np, at<uint16_t>(ws, pl.o_Jb), bf, sc, s0, s1,
-                                         x, m, (t == t1 - 1) ? h : nullptr, t, lam, a.eta,
-                                         a.alpha, st));
+                QPA_HIP(launch_mfma_step(pl.Rp, pl.np, pl.R, at<uint16_t>(ws, pl.o_Jb), bf, sc,
+                                         s0, s1, x, m, (t == t1 - 1) ? h : nullptr, t, lam,
+                                         a.eta, a.alpha, st));
                 std::swap(s0, s1);
             }
             break;
@@ -421,12 +443,29 @@ qpa_status make_rel_plan(qpa_ctx *ctx, const qpa_problem &p, const qpa_params &a
 
 constexpr int64_t BATCH_MAX_N = 4096;
 
+// Dense matrix-core buffers of a batch instance that may run as BF16 tiles.
+struct DenseSlot {
+    bool cand = false;
+    int64_t np = 0, Rp = 0;
+    size_t o_Jb = 0, o_bfp = 0, o_x = 0, o_m = 0, o_s0 = 0, o_s1 = 0;
+};
+
 struct BatchPlan {
     std::vector<Plan> inst;          // per-instance single-solve plans (canonical buffers)
     std::vector<size_t> base;        // byte offset of each instance's region
-    size_t o_tasks, o_counter, o_lam, total;
-    int32_t ntasks, max_n;
+    std::vector<DenseSlot> dense;
+    size_t o_tasks, o_tiles, o_counter, o_lam, total;
+    int32_t ntasks, ntiles_max, max_n;
 };
+
+// Cost model of one PA step of one instance on the two batch paths, in seconds, with
+// rates measured on MI355X: the CSR task kernel sustains about 0.3e12 signed coupling
+// adds per second; the grouped matrix-core step streams BF16 couplings and FP32 state at
+// about 3e12 bytes per second.
+double csr_step_cost(int64_t nnz, int64_t R) { return (double)nnz * (double)R / 0.3e12; }
+double dense_step_cost(int64_t np, int64_t R) {
+    return ((double)np * (double)np * 2.0 + 16.0 * (double)R * (double)np) / 3.0e12;
+}
 
 // Per instance: the canonical buffers, energy scratch and [groups][n][64] state of a CSR
 // plan, laid out one after the other; then the task table, the queue counter and the
@@ -437,8 +476,10 @@ qpa_status make_batch_plan(qpa_ctx *ctx, int32_t count, const qpa_problem *probs
     if (!probs) return fail(ctx, QPA_E_ARG, "problems is NULL");
     bp.inst.resize(count);
     bp.base.resize(count);
+    bp.dense.clear();
     size_t off = 0;
     bp.ntasks = 0;
+    bp.ntiles_max = 0;
     bp.max_n = 0;
     const int64_t groups = (a.replicas + 63) / 64;
     for (int32_t k = 0; k < count; ++k) {
@@ -458,6 +499,31 @@ qpa_status make_batch_plan(qpa_ctx *ctx, int32_t count, const qpa_problem *probs
         bp.inst[k] = pl;
         bp.ntasks += (int32_t)groups;
         bp.max_n = std::max<int32_t>(bp.max_n, (int32_t)probs[k].n);
+        // dense BF16 candidate: exact couplings (integer weights, checked <= 256 on the
+        // device) or BF16 requested, and cheaper by the cost model
+        DenseSlot ds;
+        const bool exact_ok = pl.is_int || a.precision == QPA_PREC_BF16;
+        const int64_t np = round_up(probs[k].n, MF_NPAD), Rp = round_up(a.replicas, MF_BM);
+        const bool cheaper =
+            dense_step_cost(np, a.replicas) < csr_step_cost(probs[k].nnz, a.replicas);
+        if (exact_ok && a.flags != QPA_BATCH_SPARSE && (cheaper || a.flags == QPA_BATCH_DENSE)) {
+            ds.cand = true;
+            ds.np = np;
+            ds.Rp = Rp;
+            auto tk = [&](size_t bytes) {
+                size_t o = off;
+                off += align_up(bytes);
+                return o;
+            };
+            ds.o_Jb = tk(sizeof(uint16_t) * (size_t)(np * np));
+            ds.o_bfp = tk(sizeof(float) * (size_t)np);
+            ds.o_x = tk(sizeof(float) * (size_t)(Rp * np));
+            ds.o_m = tk(sizeof(float) * (size_t)(Rp * np));
+            ds.o_s0 = tk(sizeof(uint32_t) * (size_t)(Rp * np / 32));
+            ds.o_s1 = tk(sizeof(uint32_t) * (size_t)(Rp * np / 32));
+            bp.ntiles_max += (int32_t)((np / MF_BN) * (Rp / MF_BM));
+        }
+        bp.dense.push_back(ds);
     }
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -465,6 +531,7 @@ qpa_status make_batch_plan(qpa_ctx *ctx, int32_t count, const qpa_problem *probs
         return o;
     };
     bp.o_tasks = take(sizeof(BatchTask) * (size_t)bp.ntasks);
+    bp.o_tiles = take(sizeof(MfmaTile) * (size_t)std::max(bp.ntiles_max, 1));
     bp.o_counter = take(sizeof(int32_t));
     bp.o_lam = take(sizeof(float) * (size_t)std::max<int32_t>(a.steps, 1));
     bp.total = off;
@@ -542,10 +609,25 @@ qpa_status qpa_profile_enable(qpa_ctx *ctx, int32_t enable) {
 
 qpa_status qpa_profile_read(qpa_ctx *ctx, double *step_ms, int64_t *step_launches,
                             int32_t reset) {
+    return qpa_profile_read_path(ctx, QPA_PATH_ALL, step_ms, step_launches, reset);
+}
+
+qpa_status qpa_batch_paths(const qpa_ctx *ctx, int32_t count, int32_t *paths) {
+    if (!ctx || !paths) return QPA_E_ARG;
+    if (count != (int32_t)ctx->batch_paths.size()) return QPA_E_ARG;
+    std::copy(ctx->batch_paths.begin(), ctx->batch_paths.end(), paths);
+    return QPA_OK;
+}
+
+qpa_status qpa_profile_read_path(qpa_ctx *ctx, int32_t path, double *step_ms,
+                                 int64_t *step_launches, int32_t reset) {
     if (!ctx || !step_ms || !step_launches) return QPA_E_ARG;
+    if (path < QPA_PATH_ALL || path > QPA_PATH_BATCH_DENSE)
+        return fail(ctx, QPA_E_ARG, "unknown path %d", path);
     double total = 0.0;
     int64_t n = 0;
     for (auto &sp : ctx->spans) {
+        if (path != QPA_PATH_ALL && sp.path != path) continue;
         QPA_HIP(hipEventSynchronize(sp.b));
         float ms = 0.0f;
         QPA_HIP(hipEventElapsedTime(&ms, sp.a, sp.b));
@@ -706,7 +788,7 @@ qpa_status qpa_relaxed_grad(qpa_ctx *ctx, const qpa_problem *problem, const qpa_
 qpa_status qpa_workspace_size_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *problems,
                                     const qpa_params *params, size_t *bytes) {
     if (!bytes) return fail(ctx, QPA_E_ARG, "bytes is NULL");
-    qpa_status s = check_params(ctx, params);
+    qpa_status s = check_batch_params(ctx, params);
     if (s != QPA_OK) return s;
     BatchPlan bp;
     s = make_batch_plan(ctx, count, problems, *params, bp);
@@ -720,7 +802,8 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
                            void *stream, const qpa_outputs *out) {
     if (!ctx) return QPA_E_ARG;
     ctx->err.clear();
-    qpa_status s = check_params(ctx, params);
+    ctx->batch_paths.clear();
+    qpa_status s = check_batch_params(ctx, params);
     if (s != QPA_OK) return s;
     BatchPlan bp;
     s = make_batch_plan(ctx, count, problems, *params, bp);
@@ -749,7 +832,8 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
         void *iw = ws + bp.base[k];
         QPA_HIP(launch_canon_csr(problems[k], at<float>(iw, pl.o_bf), at<int64_t>(iw, pl.o_bi),
                                  at<double>(iw, pl.o_bd), at<double>(iw, pl.o_rabs),
-                                 at<double>(iw, pl.o_rk), at<CanonScalars>(iw, pl.o_sc), st));
+                                 at<double>(iw, pl.o_rmax), at<double>(iw, pl.o_rk),
+                                 at<CanonScalars>(iw, pl.o_sc), st));
     }
     CanonScalars *pinned = nullptr;
     QPA_HIP(hipHostMalloc((void **)&pinned, sizeof(CanonScalars) * (size_t)count));
@@ -777,11 +861,58 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
                         hsc[k].max_row);
     }
 
-    // task table, largest instances (most stored entries) first
+    // dense BF16 tiles for the candidates whose couplings are exact in BF16
+    const int64_t R = params->replicas;
+    std::vector<char> is_dense(count, 0);
+    std::vector<MfmaTile> tiles;
+    for (int32_t k = 0; k < count; ++k) {
+        const DenseSlot &ds = bp.dense[k];
+        if (!ds.cand) continue;
+        if (bp.inst[k].is_int && hsc[k].max_abs > 256.0) continue;
+        is_dense[k] = 1;
+        const Plan &pl = bp.inst[k];
+        char *iw = ws + bp.base[k];
+        const qpa_problem &p = problems[k];
+        uint16_t *Jb = reinterpret_cast<uint16_t *>(ws + ds.o_Jb);
+        float *bfp = reinterpret_cast<float *>(ws + ds.o_bfp);
+        float *dx = reinterpret_cast<float *>(ws + ds.o_x);
+        float *dm = reinterpret_cast<float *>(ws + ds.o_m);
+        uint32_t *s0 = reinterpret_cast<uint32_t *>(ws + ds.o_s0);
+        uint32_t *s1 = reinterpret_cast<uint32_t *>(ws + ds.o_s1);
+        const CanonScalars *sc = at<CanonScalars>(iw, pl.o_sc);
+        QPA_HIP(launch_csr_to_bf16(p, ds.np, sc, Jb, st));
+        QPA_HIP(hipMemsetAsync(bfp, 0, sizeof(float) * (size_t)ds.np, st));
+        QPA_HIP(hipMemcpyAsync(bfp, at<float>(iw, pl.o_bf), sizeof(float) * (size_t)p.n,
+                               hipMemcpyDeviceToDevice, st));
+        QPA_HIP(launch_init_state(p.n, R, params->seed + (uint64_t)k, params->sigma0, dx, dm,
+                                  ds.np, 1, ds.Rp, ds.np, st));
+        QPA_HIP(launch_mfma_pack_spins(ds.Rp, ds.np, dx, s0, st));
+        for (int64_t rb = 0; rb < ds.Rp / MF_BM; ++rb)
+            for (int64_t ib = 0; ib < ds.np / MF_BN; ++ib) {
+                MfmaTile tl{};
+                tl.Jb = Jb;
+                tl.b = bfp;
+                tl.sc = sc;
+                tl.s0 = s0;
+                tl.s1 = s1;
+                tl.x = dx;
+                tl.m = dm;
+                tl.np = ds.np;
+                tl.I0 = ib * MF_BN;
+                tl.R0 = rb * MF_BM;
+                tl.rlive = R;
+                tiles.push_back(tl);
+            }
+    }
+    // largest instances first so that the tail of each step is made of small tiles
+    std::stable_sort(tiles.begin(), tiles.end(),
+                     [](const MfmaTile &a, const MfmaTile &b) { return a.np > b.np; });
+
+    // task table of the CSR instances, largest (most stored entries) first
     std::vector<std::pair<int64_t, BatchTask>> order;
     order.reserve(bp.ntasks);
-    const int64_t R = params->replicas;
     for (int32_t k = 0; k < count; ++k) {
+        if (is_dense[k]) continue;
         const Plan &pl = bp.inst[k];
         char *iw = ws + bp.base[k];
         const qpa_problem &p = problems[k];
@@ -810,34 +941,58 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
     std::vector<BatchTask> tasks;
     tasks.reserve(order.size());
     for (auto &pr : order) tasks.push_back(pr.second);
-    BatchTask *htasks = nullptr;
-    QPA_HIP(hipHostMalloc((void **)&htasks, sizeof(BatchTask) * tasks.size()));
-    std::copy(tasks.begin(), tasks.end(), htasks);
-    hipError_t ce = hipMemcpyAsync(ws + bp.o_tasks, htasks, sizeof(BatchTask) * tasks.size(),
-                                   hipMemcpyHostToDevice, st);
+    const size_t tbytes = sizeof(BatchTask) * tasks.size();
+    const size_t lbytes = sizeof(MfmaTile) * tiles.size();
+    char *hbuf = nullptr;
+    QPA_HIP(hipHostMalloc((void **)&hbuf, std::max<size_t>(tbytes + lbytes, 16)));
+    std::copy(tasks.begin(), tasks.end(), reinterpret_cast<BatchTask *>(hbuf));
+    std::copy(tiles.begin(), tiles.end(), reinterpret_cast<MfmaTile *>(hbuf + tbytes));
+    hipError_t ce = hipSuccess;
+    if (tbytes) ce = hipMemcpyAsync(ws + bp.o_tasks, hbuf, tbytes, hipMemcpyHostToDevice, st);
+    if (ce == hipSuccess && lbytes)
+        ce = hipMemcpyAsync(ws + bp.o_tiles, hbuf + tbytes, lbytes, hipMemcpyHostToDevice, st);
     if (ce == hipSuccess) ce = hipStreamSynchronize(st);
-    (void)hipHostFree(htasks);
+    (void)hipHostFree(hbuf);
     if (ce != hipSuccess) return fail(ctx, QPA_E_DEVICE, "task upload: %s", hipGetErrorString(ce));
 
-    int cus = 0;
-    QPA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
-    const int32_t blocks = (int32_t)std::min<int64_t>(bp.ntasks, (int64_t)cus * 4);
-    int64_t launches = 0;
-    {
+    const float *dlam = reinterpret_cast<const float *>(ws + bp.o_lam);
+    if (!tiles.empty() && params->steps > 0) {
         qpa_ctx::Span sp{};
         if (ctx->prof) {
             QPA_HIP(take_event(ctx, &sp.a));
             QPA_HIP(take_event(ctx, &sp.b));
             QPA_HIP(hipEventRecord(sp.a, st));
         }
-        QPA_HIP(launch_csr_batch(reinterpret_cast<const BatchTask *>(ws + bp.o_tasks), bp.ntasks,
-                                 reinterpret_cast<int32_t *>(ws + bp.o_counter), blocks,
-                                 params->steps, reinterpret_cast<const float *>(ws + bp.o_lam),
-                                 params->eta, params->alpha, params->sigma0, bp.max_n, st));
-        launches = 1;
+        for (int32_t t = 0; t < params->steps; ++t)
+            QPA_HIP(launch_mfma_grouped(reinterpret_cast<const MfmaTile *>(ws + bp.o_tiles),
+                                        (int32_t)tiles.size(), t, dlam, params->eta,
+                                        params->alpha, st));
         if (ctx->prof) {
             QPA_HIP(hipEventRecord(sp.b, st));
-            sp.launches = launches;
+            sp.launches = params->steps;
+            sp.path = QPA_PATH_BATCH_DENSE;
+            ctx->spans.push_back(sp);
+        }
+    }
+    if (!tasks.empty()) {
+        int cus = 0;
+        QPA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+        const int32_t ntask = (int32_t)tasks.size();
+        const int32_t blocks = (int32_t)std::min<int64_t>(ntask, (int64_t)cus * 4);
+        qpa_ctx::Span sp{};
+        if (ctx->prof) {
+            QPA_HIP(take_event(ctx, &sp.a));
+            QPA_HIP(take_event(ctx, &sp.b));
+            QPA_HIP(hipEventRecord(sp.a, st));
+        }
+        QPA_HIP(launch_csr_batch(reinterpret_cast<const BatchTask *>(ws + bp.o_tasks), ntask,
+                                 reinterpret_cast<int32_t *>(ws + bp.o_counter), blocks,
+                                 params->steps, dlam, params->eta, params->alpha, params->sigma0,
+                                 bp.max_n, st));
+        if (ctx->prof) {
+            QPA_HIP(hipEventRecord(sp.b, st));
+            sp.launches = 1;
+            sp.path = QPA_PATH_BATCH_SPARSE;
             ctx->spans.push_back(sp);
         }
     }
@@ -849,7 +1004,15 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
         const qpa_problem &p = problems[k];
         const qpa_outputs &o = out[k];
         int8_t *spins = o.spins ? o.spins : at<int8_t>(iw, pl.o_sp);
-        for (int64_t g = 0; g < pl.Rp / 64; ++g) {
+        if (is_dense[k]) {
+            const DenseSlot &ds = bp.dense[k];
+            const float *dx = reinterpret_cast<const float *>(ws + ds.o_x);
+            const float *dm = reinterpret_cast<const float *>(ws + ds.o_m);
+            QPA_HIP(launch_export_spins(p.n, R, dx, ds.np, 1, spins, st));
+            if (o.x) QPA_HIP(launch_copy_state(p.n, R, dx, ds.np, 1, o.x, p.n, 1, st));
+            if (o.m) QPA_HIP(launch_copy_state(p.n, R, dm, ds.np, 1, o.m, p.n, 1, st));
+        }
+        for (int64_t g = 0; !is_dense[k] && g < pl.Rp / 64; ++g) {
             const int64_t rg = std::min<int64_t>(64, R - 64 * g);
             const float *xg = at<float>(iw, pl.o_x) + g * p.n * 64;
             const float *mg = at<float>(iw, pl.o_m) + g * p.n * 64;
@@ -863,6 +1026,9 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
             return fail(ctx, s, "%s", msg.c_str());
         }
     }
+    ctx->batch_paths.assign(count, QPA_PATH_BATCH_SPARSE);
+    for (int32_t k = 0; k < count; ++k)
+        if (is_dense[k]) ctx->batch_paths[k] = QPA_PATH_BATCH_DENSE;
     return QPA_OK;
 }
 

@@ -56,7 +56,8 @@ hipError_t launch_canon_dense(const qpa_problem &p, float *J_f32, uint16_t *Jb, 
 
 // Canonicalisation of a CSR problem: b_f32 / b_i64 / b_f64, validation, scalars.
 hipError_t launch_canon_csr(const qpa_problem &p, float *b_f32, int64_t *b_i64, double *b_f64,
-                            double *row_abs, double *row_diag, CanonScalars *sc, hipStream_t st);
+                            double *row_abs, double *row_max, double *row_k, CanonScalars *sc,
+                            hipStream_t st);
 
 // x0 / m0 from the counter RNG.  Layout: element (r, i) at x[r * ld_r + i * ld_i].
 hipError_t launch_init_state(int64_t n, int64_t R, uint64_t seed, float sigma0, float *x,
@@ -107,10 +108,23 @@ constexpr int MF_BN = 128;   // variables per tile
 constexpr int MF_NPAD = 256; // np is a multiple of this (4 waves x 64-wide chunks)
 hipError_t launch_mfma_pack_spins(int64_t Rp, int64_t np, const float *x, uint32_t *sbits,
                                   hipStream_t st);
-hipError_t launch_mfma_step(int64_t Rp, int64_t np, const uint16_t *Jb, const float *b,
-                            const CanonScalars *sc, const uint32_t *s_cur, uint32_t *s_nxt,
-                            float *x, float *m, float *h_last, int32_t t, const float *lam,
-                            float eta, float alpha, hipStream_t st);
+hipError_t launch_mfma_step(int64_t Rp, int64_t np, int64_t rlive, const uint16_t *Jb,
+                            const float *b, const CanonScalars *sc, const uint32_t *s_cur,
+                            uint32_t *s_nxt, float *x, float *m, float *h_last, int32_t t,
+                            const float *lam, float eta, float alpha, hipStream_t st);
+// One tile of a grouped launch (many instances, one PA step each).
+struct MfmaTile {
+    const uint16_t *Jb;
+    const float *b;
+    const CanonScalars *sc;
+    uint32_t *s0, *s1;       // spin-bit buffers: step t reads s0 if t is even, else s1
+    float *x, *m;            // [Rp][np] state of the instance
+    int64_t np, I0, R0, rlive;
+};
+hipError_t launch_mfma_grouped(const MfmaTile *tiles, int32_t ntiles, int32_t t,
+                               const float *lam, float eta, float alpha, hipStream_t st);
+hipError_t launch_csr_to_bf16(const qpa_problem &p, int64_t np, const CanonScalars *sc,
+                              uint16_t *Jb, hipStream_t st);
 
 // ---- CSR PA steps --------------------------------------------------------------------
 // Internal layout: x, m [np][Rp] (replica fastest, Rp a multiple of the replica group

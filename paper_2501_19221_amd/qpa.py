@@ -34,11 +34,15 @@ QPA_KIND_QUBO, QPA_KIND_ISING = 0, 1
 QPA_FMT_DENSE, QPA_FMT_CSR = 0, 1
 QPA_I8, QPA_I16, QPA_I32, QPA_F32 = 0, 1, 2, 3
 QPA_PREC_FP32, QPA_PREC_BF16 = 0, 1
+QPA_BATCH_SPARSE, QPA_BATCH_DENSE = 1, 2
+QPA_PATH_ALL, QPA_PATH_DENSE_RESIDENT, QPA_PATH_DENSE_TILED, QPA_PATH_DENSE_MFMA, QPA_PATH_CSR, \
+    QPA_PATH_BATCH_SPARSE, QPA_PATH_BATCH_DENSE = range(-1, 6)
 
 EXPORTED = ["qpa_create", "qpa_destroy", "qpa_last_error", "qpa_status_string",
             "qpa_workspace_size", "qpa_solve", "qpa_steps", "qpa_energy", "qpa_version",
             "qpa_profile_enable", "qpa_profile_read", "qpa_workspace_size_batch",
-            "qpa_solve_batch", "qpa_workspace_size_relaxed", "qpa_relaxed_grad"]
+            "qpa_solve_batch", "qpa_workspace_size_relaxed", "qpa_relaxed_grad",
+            "qpa_profile_read_path", "qpa_batch_paths"]
 
 
 class qpa_problem(ctypes.Structure):
@@ -95,6 +99,9 @@ _sig = {
     "qpa_profile_enable": (_S, [_P, ctypes.c_int32]),
     "qpa_profile_read": (_S, [_P, ctypes.POINTER(ctypes.c_double),
                               ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]),
+    "qpa_profile_read_path": (_S, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]),
+    "qpa_batch_paths": (_S, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -202,6 +209,22 @@ def qpa_profile_read(ctx, reset: bool = True):
     return ms.value, n.value
 
 
+def qpa_profile_read_path(ctx, path: int, reset: bool = False):
+    """(milliseconds, launches) of the step kernels of one path (QPA_PATH_*)."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(ctx, _lib.qpa_profile_read_path(ctx, path, ctypes.byref(ms), ctypes.byref(n),
+                                           1 if reset else 0))
+    return ms.value, n.value
+
+
+def qpa_batch_paths(ctx, count: int) -> np.ndarray:
+    """Path (QPA_PATH_BATCH_SPARSE / _DENSE) of each instance of the last batch solve."""
+    out = np.zeros(count, np.int32)
+    _check(ctx, _lib.qpa_batch_paths(ctx, count, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+    return out
+
+
 # ---- convenience layer (torch supplies memory and streams) ---------------------------
 _DT = {"int8": QPA_I8, "int16": QPA_I16, "int32": QPA_I32, "float32": QPA_F32}
 
@@ -268,7 +291,7 @@ class Problem:
 
 
 def make_params(replicas, steps, eta, alpha, lambda0, sigma0=0.1, seed=1, precision=QPA_PREC_FP32,
-                lambda_table=None):
+                lambda_table=None, flags=0):
     p = qpa_params()
     p.replicas = replicas
     p.steps = steps
@@ -278,7 +301,7 @@ def make_params(replicas, steps, eta, alpha, lambda0, sigma0=0.1, seed=1, precis
     p.sigma0 = sigma0
     p.seed = seed & (2**64 - 1)
     p.precision = precision
-    p.flags = 0
+    p.flags = flags
     keep = None
     if lambda_table is not None:
         keep = np.ascontiguousarray(lambda_table, dtype=np.float32)

@@ -121,3 +121,44 @@ def test_create_without_device_fails_cleanly(q):
         pytest.skip("a GPU is present")
     h = ctypes.c_void_p()
     assert q._lib.qpa_create(ctypes.byref(h), 0) == q.QPA_E_DEVICE
+
+
+def _fake_csr(q, n, nnz):
+    c = q.qpa_problem()
+    c.n = n
+    c.format = q.QPA_FMT_CSR
+    c.kind = q.QPA_KIND_QUBO
+    c.coupling_dtype = q.QPA_I16
+    c.index_dtype = q.QPA_I16
+    c.linear_dtype = q.QPA_I16
+    c.row_ptr = 0x1000
+    c.col = 0x1000
+    c.weights = 0x1000
+    c.nnz = nnz
+    return c
+
+
+def _ws_batch(q, probs, a):
+    arr = (q.qpa_problem * len(probs))(*probs)
+    n = ctypes.c_size_t(0)
+    st = q._lib.qpa_workspace_size_batch(None, len(probs), arr, ctypes.byref(a), ctypes.byref(n))
+    return st, n.value
+
+
+def test_batch_path_flags(q):
+    # a dense-friendly instance (n=1000, 10% of pairs) and a very sparse one
+    probs = [_fake_csr(q, 1000, 100_000), _fake_csr(q, 1000, 2_000)]
+    sizes = {}
+    for name, fl in [("auto", 0), ("sparse", q.QPA_BATCH_SPARSE), ("dense", q.QPA_BATCH_DENSE)]:
+        a = q.make_params(64, 10, 0.1, 0.8, 4.0, flags=fl)
+        st, sizes[name] = _ws_batch(q, probs, a)
+        assert st == q.QPA_OK, name
+    # the dense path adds a 1024x1024 BF16 matrix per densified instance
+    bf16 = 1024 * 1024 * 2
+    assert sizes["dense"] >= sizes["sparse"] + 2 * bf16
+    assert sizes["sparse"] + bf16 <= sizes["auto"] < sizes["sparse"] + 2 * bf16
+    bad = q.make_params(64, 10, 0.1, 0.8, 4.0, flags=3)
+    assert _ws_batch(q, probs, bad)[0] == q.QPA_E_ARG
+    # single-instance solves take no flags
+    one = q.make_params(4, 10, 0.1, 0.5, 1.0, flags=q.QPA_BATCH_SPARSE)
+    assert _ws(q, _dense_problem(q), one)[0] == q.QPA_E_ARG

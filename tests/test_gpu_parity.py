@@ -43,9 +43,9 @@ def host(t):
     return t.detach().cpu().numpy()
 
 
-def _params(q, R, T, eta, alpha, lam0, sigma0=0.1, seed=1, prec="fp32"):
+def _params(q, R, T, eta, alpha, lam0, sigma0=0.1, seed=1, prec="fp32", flags=0):
     return q.make_params(R, T, eta, alpha, lam0, sigma0, seed,
-                         q.QPA_PREC_BF16 if prec == "bf16" else q.QPA_PREC_FP32)
+                         q.QPA_PREC_BF16 if prec == "bf16" else q.QPA_PREC_FP32, flags=flags)
 
 
 def _check_solve_dense_int(q, eng, inst, R, T, eta, alpha, lam0, prec="fp32", seed=1):
@@ -381,15 +381,28 @@ def _oracle_instance(inst, R, T, lam, eta, alpha, seed, r0=0):
     return x, m, canon
 
 
-def test_batch_uneven_instances_bit_exact(q, eng):
+@pytest.mark.parametrize("path", ["auto", "sparse", "dense"])
+def test_batch_uneven_instances_bit_exact(q, eng, path):
+    # Both batch paths give the oracle's bits on integer instances.  The last instance has
+    # couplings up to 300 (not exact in BF16), so it stays sparse even when dense is forced.
     rng = np.random.default_rng(7)
     insts = [gen.er_qubo(int(n), 0.1, 100, rng) for n in rng.integers(30, 400, size=9)]
     insts.append(gen.chimera_ising(3, seed=5))          # an Ising instance in the same batch
+    insts.append(gen.er_qubo(300, 0.2, 300, rng))
     R, T, eta, alpha, lam0 = 70, 60, 0.0002, 0.8, 200.0  # 70 replicas: a full and a partial group
     probs = [q.Problem.from_instance(i) for i in insts]
-    p = _params(q, R, T, eta, alpha, lam0, seed=11)
-    say("batch of %d uneven instances, R=%d T=%d" % (len(insts), R, T))
+    flags = {"auto": 0, "sparse": q.QPA_BATCH_SPARSE, "dense": q.QPA_BATCH_DENSE}[path]
+    p = _params(q, R, T, eta, alpha, lam0, seed=11, flags=flags)
+    say("batch of %d uneven instances, R=%d T=%d path=%s" % (len(insts), R, T, path))
     outs = eng.solve_batch(probs, p, want_state=True)
+    paths = q.qpa_batch_paths(eng.ctx, len(insts))
+    assert paths[-1] == q.QPA_PATH_BATCH_SPARSE           # |w| up to 300: never densified
+    if path == "sparse":
+        assert (paths == q.QPA_PATH_BATCH_SPARSE).all()
+    elif path == "dense":
+        assert (paths[:-1] == q.QPA_PATH_BATCH_DENSE).all()
+    else:                                                  # the cost model mixes both
+        assert (paths == q.QPA_PATH_BATCH_DENSE).any() and (paths[:-2] != paths[0]).any()
     lam = orc.lambda_linear(T, lam0)
     for k, (inst, out) in enumerate(zip(insts, outs)):
         x, m, canon = _oracle_instance(inst, R, T, lam, eta, alpha, seed=11 + k)
