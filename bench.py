@@ -43,7 +43,45 @@ def parse():
     ap.add_argument("--workload", default="sk4096")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32-form", action="store_true")
+    ap.add_argument("--no-measured-peaks", action="store_true")
     return ap.parse_args()
+
+
+def measured_peaks(torch):
+    """Achievable rates on this GPU, as references for the roofline fractions: a 2 GiB
+    device-to-device copy (HBM read + write) and a 8192^3 BF16 GEMM from the vendor BLAS."""
+    out = {}
+    a = torch.empty(2 ** 29, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(2):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    it = 10
+    e0.record()
+    for _ in range(it):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    out["hbm_copy_GBps"] = 2.0 * a.numel() * 4 * it / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del a, b
+    n = 8192
+    x = torch.randn(n, n, device="cuda").to(torch.bfloat16)
+    y = torch.randn(n, n, device="cuda").to(torch.bfloat16)
+    for _ in range(3):
+        z = x @ y
+    torch.cuda.synchronize()
+    it = 20
+    e0.record()
+    for _ in range(it):
+        z = x @ y
+    e1.record()
+    torch.cuda.synchronize()
+    out["bf16_gemm_TFLOPs"] = 2.0 * n ** 3 * it / (e0.elapsed_time(e1) / 1e3) / 1e12
+    del x, y, z
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(inst, wl, prec):
@@ -121,7 +159,8 @@ def run_solves(eng, qpa, torch, inst, prob, params, steps, warmup, batch):
     qpa.qpa_profile_enable(eng.ctx, False)
     per_path = {}
     for code in (qpa.QPA_PATH_DENSE_RESIDENT, qpa.QPA_PATH_DENSE_TILED, qpa.QPA_PATH_DENSE_MFMA,
-                 qpa.QPA_PATH_CSR, qpa.QPA_PATH_BATCH_SPARSE, qpa.QPA_PATH_BATCH_DENSE):
+                 qpa.QPA_PATH_CSR, qpa.QPA_PATH_BATCH_SPARSE, qpa.QPA_PATH_BATCH_DENSE,
+                 qpa.QPA_PATH_CSR_RESIDENT):
         pm, pl = qpa.qpa_profile_read_path(eng.ctx, code)
         if pl:
             per_path[code] = (pm, pl)
@@ -217,6 +256,15 @@ def main():
         roof.update({"achieved": achieved, "unit": "TFLOP/s", "per_launch": what})
         e = out["energy"].cpu().numpy()
         extra = {"best_energy": float(e.min()), "best_replica": int(out["best"].cpu()[0])}
+    elif qpa.QPA_PATH_CSR_RESIDENT in per_path:
+        c = inst0.csr
+        ops = float(c.nnz) * R * T            # one signed coupling add per entry, replica, step
+        roof = {"bound": "alu", "achieved": ops / avg_launch_s / 1e12, "peak": PEAK_ALU_TOPS,
+                "unit": "Tops/s", "kernel": "k_csr_resident",
+                "per_launch": "nnz*R*T = %.4g signed coupling adds (all steps of all replicas, "
+                              "one launch; state on chip)" % ops}
+        e = out["energy"].cpu().numpy()
+        extra = {"best_energy": float(e.min()), "best_replica": int(out["best"].cpu()[0])}
     else:
         c = inst0.csr
         n = inst0.n
@@ -230,6 +278,15 @@ def main():
         e = out["energy"].cpu().numpy()
         extra = {"best_energy": float(e.min()), "best_replica": int(out["best"].cpu()[0])}
     roof["frac"] = roof["achieved"] / roof["peak"]
+    if not a.no_measured_peaks:
+        log("measured peaks")
+        mp = measured_peaks(torch)
+        res_peaks = mp
+        ref = {"GB/s": mp["hbm_copy_GBps"], "TFLOP/s": mp["bf16_gemm_TFLOPs"]}.get(roof["unit"])
+        if ref is not None and roof["bound"] in ("hbm", "mfma"):
+            roof["frac_of_measured"] = roof["achieved"] / ref
+    else:
+        res_peaks = None
     roof["traffic"] = None
     roof["avg_launch_us"] = avg_launch_s * 1e6
     roof["launches"] = launches
@@ -243,6 +300,8 @@ def main():
                       "precision": prec, "eta": wl.eta, "alpha": wl.alpha,
                       "lambda0": wl.lambda0, "parallelism": "single GPU"},
            "roofline": roof}
+    if res_peaks is not None:
+        res["measured_peak"] = res_peaks
     res.update(extra)
 
     if prec == "bf16" and not a.no_fp32_form:

@@ -106,8 +106,14 @@ typedef struct {
     const float *lambda_table;  /* host, optional                               */
     uint64_t seed;              /* SplitMix64 seed of the initial state          */
     int32_t precision;          /* qpa_precision (dense path)                   */
-    int32_t flags;              /* 0, or one qpa_batch_flags value (batch only) */
+    int32_t flags;              /* 0, QPA_SOLVE_STREAMED (single solves) or one
+                                   qpa_batch_flags value (qpa_solve_batch)      */
 } qpa_params;
+
+/* qpa_solve / qpa_steps: run a sparse instance with the per-step streamed kernel even
+ * when its state fits on chip (the default then keeps it resident for all steps).  Both
+ * kernels give the same bits. */
+#define QPA_SOLVE_STREAMED 4
 
 /* Path choice of qpa_solve_batch (params.flags; qpa_solve requires 0).  By default
  * every instance whose couplings are exact in BF16 (integer weights with |w| <= 256,
@@ -234,7 +240,8 @@ typedef enum {
     QPA_PATH_DENSE_MFMA = 2,     /* BF16 matrix-core step, one launch per step    */
     QPA_PATH_CSR = 3,            /* sparse step, one launch per step              */
     QPA_PATH_BATCH_SPARSE = 4,   /* persistent sparse task kernel (all steps)     */
-    QPA_PATH_BATCH_DENSE = 5     /* grouped matrix-core step over many instances  */
+    QPA_PATH_BATCH_DENSE = 5,    /* grouped matrix-core step over many instances  */
+    QPA_PATH_CSR_RESIDENT = 6    /* sparse, state on chip, all steps at once      */
 } qpa_path;
 
 /* Measurement of the PA-step kernels.  While enabled (enable != 0), every qpa_solve,

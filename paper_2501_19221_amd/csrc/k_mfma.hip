@@ -2,30 +2,32 @@
 // couplings stored as bf16(J / 2^e), FP32 accumulation, result scaled back by 2^e).
 //
 // One launch advances every replica by one step.  A workgroup owns an output tile of
-// 128 replicas x 128 variables and splits the reduction dimension over its 4 waves:
-// wave w accumulates the whole tile (4 x 4 accumulators of 32x32 in AGPRs) over
-// k in [w*np/4, (w+1)*np/4), walking it in chunks of 64.
-//   * each wave stages its own chunk -- the 128 x 64 bf16 block of J and the 128 spin
-//     words (sign bits, bit set <=> spin -1, one 64-bit word per 64 variables and replica
-//     row) -- into a wave-private LDS stage (two stages) with direct global->LDS loads:
-//     16 loads of 16 bytes per lane for J, each covering 8 full 128-byte rows, and 4 of
-//     4 bytes for the spin words.  Every operand of the tile is fetched once per
-//     workgroup, coalesced, without passing through registers; the only wait is one
-//     vmcnt(0) per chunk, a whole chunk of MFMAs after the loads were issued.  Inside
-//     a J row the eight 16-byte pieces sit at position (piece ^ (row % 8)), so that the
-//     fragment reads of 8 consecutive lanes (8 consecutive rows) hit distinct banks.
-//   * all 16 B fragments and 4 spin words of a chunk are read from LDS before the next
-//     chunk's loads are issued; the 8 bits of a fragment row are expanded to bf16 +-1
-//     (0x3F80 / 0xBF80) and reused by the 4 MFMAs of that row.
-// After the loop the four partial tiles are summed through LDS so that wave w holds
-// replicas 32w .. 32w+31 of the tile for all 128 variables, then runs the PA update.
+// 128 replicas x 128 variables and has two kinds of waves:
+//   * 4 matrix waves in a 2 x 2 arrangement: wave (wr, wc) accumulates replicas
+//     64wr .. 64wr+63 against variables 64wc .. 64wc+63 (2 x 2 accumulators of 32 x 32)
+//     over the whole reduction, walked in chunks of 128 variables;
+//   * 4 state waves: they load the tile's x and m into registers when the launch starts,
+//     so that this traffic overlaps the reduction, then wait for the field and run the
+//     PA update and write x, m and the new sign bits.
+// Chunks are staged through LDS with direct global->LDS loads issued by the matrix waves
+// only (NST stages, NST-1 chunks in flight): per chunk the 128 x 128 bf16 block of J
+// (8 loads of 16 bytes per lane and wave, each filling 4 rows of 256 bytes) and the
+// 128 x 128 spin bits of the tile's replicas (2 loads of 4 bytes per lane and wave).
+// Inside a J row the sixteen 16-byte pieces sit at position piece ^ (row % 16), so that
+// the fragment reads of 16 consecutive rows fall on distinct banks.  One barrier per
+// chunk publishes a stage and frees the one that is loaded next; the state waves take
+// part in every barrier and issue no loads in between, so that the matrix waves' waits
+// count their own loads only.  After the loop the raw sums go to the state waves
+// through LDS (128 x 128 FP32, row-major).
+//
+// Spin bits ("chunk-major"): u32 word (kc * Rp + r) * 4 + q holds in bit j the sign of
+// variable 128 kc + 32 q + j of replica r (bit set <=> spin -1), so that the spins of a
+// tile's replicas for one chunk are one contiguous 2 KiB block.
 //
 // Matrix instruction: v_mfma_f32_32x32x16_bf16.  Operand layout (64 lanes):
 //   A (32 x 16, rows = replicas): lane l holds row l%32, k = 8*(l/32) .. +7
 //   B (16 x 32, cols = variables): lane l holds col l%32, k = 8*(l/32) .. +7
 //   D (32 x 32): register v of lane l holds row 8*(v/4) + 4*(l/32) + v%4, col l%32.
-// Epilogue: h = 2^e * acc + b, then the PA update on x, m (FP32, [Rp][np] row-major) and
-// the new sign bits (one ballot per accumulator register -> two 32-bit words).
 #include "qpa_internal.h"
 
 namespace qpa {
@@ -36,8 +38,16 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int BM = MF_BM, BN = MF_BN;
-constexpr int JST = BN * 128;                // J bytes of a wave stage: 128 rows x 64 bf16
-constexpr int STG = JST + BM * 8;            // + one 64-bit spin word per replica row
+constexpr int KC = 128;                      // reduction chunk (variables)
+constexpr int JSTG = BN * KC * 2;            // J block of a stage: 128 rows x 256 bytes
+constexpr int SSTG = BM * KC / 8;            // spin bits of a stage: 128 rows x 16 bytes
+constexpr int STG = JSTG + SSTG;
+constexpr int NST = 3;                       // stages
+constexpr int LDS_BYTES = NST * STG;
+constexpr int THREADS = 512;                 // 4 matrix waves + 4 state waves
+constexpr int MW = 4;                        // matrix waves
+static_assert(LDS_BYTES >= BM * BN * 4, "the field handoff reuses the stages");
+static_assert(MF_NPAD % KC == 0, "np must be a multiple of the chunk");
 
 __device__ __forceinline__ void pa_update(float h, float lam, float eta, float alpha, float &x,
                                           float &m) {
@@ -49,182 +59,220 @@ __device__ __forceinline__ void pa_update(float h, float lam, float eta, float a
     x = y;
 }
 
+typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
+
 // 8 sign bits (bit j <=> element j is -1) -> eight bf16 +-1 values:
 // dword q holds elements 2q (low half) and 2q+1 (high half); a set bit sets the half's
-// sign bit on top of 0x3F80 (= 1.0).
-__device__ __forceinline__ bf16x8 expand_spins(uint32_t byte) {
+// sign bit on top of 0x3F80 (= 1.0).  The byte is paired as 16-bit halves
+// (byte, byte >> 1), so that one packed 16-bit shift by 15 - 2q brings bit 2q to the
+// top of the low half and bit 2q+1 to the top of the high half; a mask keeps the two
+// sign positions.  All full-rate ALU operations.
+__device__ __forceinline__ bf16x8 expand_spins(uint32_t byte, uint32_t sign_mask) {
+    // low half: byte (bit 15 also receives bit 0, which every shift below moves out);
+    // high half: byte >> 1
+    const uint32_t pair = (byte << 15) | byte;
     u32x4 d;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        uint32_t y = byte >> (2 * q);
-        uint32_t spread = (y << 15) | (y << 30);
-        d[q] = (spread & 0x80008000u) | 0x3F803F80u;
+        const uint16_t sh = (uint16_t)(15 - 2 * q);
+        const u16x2 v = __builtin_bit_cast(u16x2, pair) << (u16x2){sh, sh};
+        // (v & 0x80008000) | 0x3F803F80 in one instruction; the mask comes in a VGPR
+        // because one VOP3 instruction can read only one scalar operand here
+        uint32_t r;
+        asm("v_and_or_b32 %0, %1, %2, %3"
+            : "=v"(r)
+            : "v"(__builtin_bit_cast(uint32_t, v)), "v"(sign_mask), "s"(0x3F803F80u));
+        d[q] = r;
     }
     return __builtin_bit_cast(bf16x8, d);
 }
 
 typedef __attribute__((address_space(3))) void lds_void;
 
+// Workgroup barrier without the memory fence of __syncthreads (which would also wait for
+// every load in flight, including the chunks loaded ahead): the callers order their LDS
+// traffic with the explicit waits below.
+__device__ __forceinline__ void barrier() { asm volatile("s_barrier" ::: "memory"); }
+
+// This wave's loads of all but the N youngest are done and its LDS accesses are complete,
+// then the workgroup barrier.
+template <int N> __device__ __forceinline__ void wait_barrier() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(N) : "memory");
+}
+
+constexpr int LOADS_PER_CHUNK = 10;          // per matrix wave: 8 J pieces + 2 spin dwords
+
 // One 128 x 128 output tile of one PA step: replicas R0 .. R0+127 (rows at or past
-// `rlive` are padding: no state traffic), variables I0 .. I0+127.  `lds` holds
-// 4 * 2 * STG bytes.
+// `rlive` are padding: their state is neither read nor written and they report +1
+// spins), variables I0 .. I0+127.  `lds` holds LDS_BYTES bytes.
 __device__ __forceinline__ void mfma_tile_step(
-    uint8_t *lds, int64_t np, int64_t I0, int64_t R0, int64_t rlive,
+    uint8_t *lds, int64_t np, int64_t Rp, int64_t I0, int64_t R0, int64_t rlive,
     const uint16_t *__restrict__ Jb, const float *__restrict__ b, float scale,
-    const uint64_t *__restrict__ s_cur, uint32_t *__restrict__ s_nxt, float *__restrict__ x,
+    const uint32_t *__restrict__ s_cur, uint32_t *__restrict__ s_nxt, float *__restrict__ x,
     float *__restrict__ m, float *__restrict__ h_last, float lt, float eta, float alpha) {
     const int tid = threadIdx.x, lane = tid & 63;
-    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int half = lane >> 5, l32 = lane & 31;
-    const int64_t kq = np / 4;                 // reduction length of one wave
-    const int64_t kb = (int64_t)w * kq;
-    const int nchunk = (int)(kq / 64);
-    const int64_t wpr = np / 64;               // spin words per replica row
-    uint8_t *mine = lds + w * 2 * STG;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nchunk = (int)(np / KC);
+    float *hs = reinterpret_cast<float *>(lds);   // field sums of the tile, after the loop
 
-    // J: load e (0..15) fills rows 8e .. 8e+7 of a stage; lane l covers row 8e + l/8 and
-    // stores at position l%8 the piece (l%8) ^ (row%8) = (l%8) ^ (l/8).
-    const uint16_t *gJ = Jb + (I0 + (lane >> 3)) * np + kb + 8 * ((lane & 7) ^ (lane >> 3));
-    // spin words: load e (0..3) fills rows 32e .. 32e+31; lane l covers row 32e + l/2,
-    // 32-bit half l%2 of that row's 64-bit word, so a row's word is contiguous in LDS.
-    const uint32_t *gS = reinterpret_cast<const uint32_t *>(s_cur + (R0 + (lane >> 1)) * wpr +
-                                                            kb / 64) + (lane & 1);
+    if (wave >= MW) {
+        // ---- state waves: thread t owns column t % 128 of rows 2e + t / 128 ----
+        const int t = tid - MW * 64;
+        const int col = t & (BN - 1);
+        const int rsub = __builtin_amdgcn_readfirstlane(t >> 7);
+        const int64_t iv = I0 + col;
+        const int64_t rmax = rlive - 1;
+        float xv[BM / 2], mv[BM / 2];
+#pragma unroll
+        for (int e = 0; e < BM / 2; ++e) {
+            // padding rows read a live row instead (never written back)
+            const int64_t r = min(R0 + 2 * e + rsub, rmax);
+            xv[e] = x[r * np + iv];
+            mv[e] = m[r * np + iv];
+        }
+        const float bi = b[iv];
+        for (int c = 0; c < nchunk; ++c) barrier();   // the matrix waves' chunks
+        barrier();                                     // stages drained
+        barrier();                                     // field sums in LDS
+        // collect every load here, once, so that the stores below wait for nothing
+#pragma unroll
+        for (int e = 0; e < BM / 2; ++e) asm volatile("" ::"v"(xv[e]), "v"(mv[e]));
+        asm volatile("" ::"v"(bi));
+        const int64_t wbase = (I0 / KC) * Rp * 4 + 2 * ((wave - MW) & 1);
+#pragma unroll
+        for (int e = 0; e < BM / 2; ++e) {
+            const int row = 2 * e + rsub;
+            const int64_t r = R0 + row;
+            const bool live = r < rlive;
+            const float h = __fadd_rn(__fmul_rn(hs[row * BN + col], scale), bi);
+            float xn = xv[e], mn = mv[e];
+            pa_update(h, lt, eta, alpha, xn, mn);
+            // this wave covers 64 consecutive variables of row r: one 64-bit spin word
+            const uint64_t bal = __ballot(live && xn < 0.0f);
+            if (live) {
+                x[r * np + iv] = xn;
+                m[r * np + iv] = mn;
+                if (h_last) h_last[r * np + iv] = h;
+            }
+            if (lane == 0)
+                *reinterpret_cast<uint64_t *>(s_nxt + wbase + r * 4) = bal;
+        }
+        return;
+    }
+
+    // ---- matrix waves ----
+    const int wr = wave >> 1, wc = wave & 1;
+    const int half = lane >> 5, l32 = lane & 31;
+    // J: load u (0..7) of wave w fills LDS rows 32w + 4u + lane/16 at position lane % 16,
+    // which holds piece (lane % 16) ^ (row % 16) of that row.
+    const uint16_t *gJ[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int row = 32 * wave + 4 * u + (lane >> 4);
+        gJ[u] = Jb + (I0 + row) * np + 8 * ((lane & 15) ^ (row & 15));
+    }
+    // spins: load e (0..1) of wave w fills bytes 512w + 256e + 4 lane of the 2 KiB block
+    const uint32_t *gS = s_cur + R0 * 4 + 128 * wave + lane;
+    const int64_t sstride = Rp * 4;                // u32 words between consecutive chunks
     auto stage = [&](int kc, int st) {
-        kc = kc < nchunk ? kc : nchunk - 1;   // past the end: reload the last chunk
-        const uint16_t *srcJ = gJ + (int64_t)kc * 64;
-        const uint32_t *srcS = gS + 2 * (int64_t)kc;
-        uint8_t *dst = mine + st * STG;
+        kc = kc < nchunk ? kc : nchunk - 1;        // past the end: reload the last chunk
+        uint8_t *dst = lds + st * STG;
 #pragma unroll
-        for (int e = 0; e < 16; ++e)
-            __builtin_amdgcn_global_load_lds(srcJ + (int64_t)8 * e * np,
-                                             (lds_void *)(dst + e * 1024), 16, 0, 0);
+        for (int u = 0; u < 8; ++u)
+            __builtin_amdgcn_global_load_lds(gJ[u] + (int64_t)kc * KC,
+                                             (lds_void *)(dst + (8 * wave + u) * 1024), 16, 0, 0);
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-            __builtin_amdgcn_global_load_lds(srcS + (int64_t)32 * e * 2 * wpr,
-                                             (lds_void *)(dst + JST + e * 256), 4, 0, 0);
+        for (int e = 0; e < 2; ++e)
+            __builtin_amdgcn_global_load_lds(gS + (int64_t)kc * sstride + 64 * e,
+                                             (lds_void *)(dst + JSTG + 512 * wave + 256 * e), 4,
+                                             0, 0);
     };
 
-    f32x16 acc[4][4];
+    const uint32_t sign_mask = __builtin_amdgcn_readfirstlane(0x80008000u) + 0u * lane;
+    f32x16 acc[2][2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
 
-    stage(0, 0);
+#pragma unroll
+    for (int s = 0; s < NST - 1; ++s) stage(s, s);
     for (int c = 0; c < nchunk; ++c) {
-        // chunk c was requested one chunk ago: wait for it here, and keep every LDS read
-        // of the chunk below this point
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        const uint8_t *src = mine + (c & 1) * STG;
-        u32x4 bf[4][4];                         // [k step q][variable fragment j]
+        // this wave's loads of chunk c have landed (the NST-2 younger chunks may not);
+        // after the barrier every wave's have, and every wave is done with the stage of
+        // chunk c-1, which is refilled next
+        wait_barrier<(NST - 2) * LOADS_PER_CHUNK>();
+        stage(c + NST - 1, (c + NST - 1) % NST);
+        const uint8_t *src = lds + (c % NST) * STG;
+        u32x4 sw[2];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int i = 0; i < 2; ++i)
+            sw[i] = *reinterpret_cast<const u32x4 *>(src + JSTG + 16 * (64 * wr + 32 * i + l32));
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int row = 32 * j + l32;
-                const int pos = (2 * q + half) ^ (row & 7);
-                bf[q][j] = *reinterpret_cast<const u32x4 *>(src + row * 128 + (pos << 4));
+        for (int q = 0; q < KC / 16; ++q) {
+            u32x4 bq[2];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int row = 64 * wc + 32 * j + l32;
+                const int pos = (2 * q + half) ^ (row & 15);
+                bq[j] = *reinterpret_cast<const u32x4 *>(src + row * 256 + pos * 16);
             }
-        uint64_t aw[4];
+            bf16x8 a[2];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            aw[i] = *reinterpret_cast<const uint64_t *>(src + JST + 8 * (32 * i + l32));
-        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-        stage(c + 1, (c + 1) & 1);
+            for (int i = 0; i < 2; ++i)
+                a[i] = expand_spins((sw[i][q >> 1] >> (16 * (q & 1) + 8 * half)) & 0xFFu,
+                                    sign_mask);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            bf16x8 a[4];
+            for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                a[i] = expand_spins((uint32_t)(aw[i] >> (16 * q + 8 * half)) & 0xFFu);
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
+                for (int j = 0; j < 2; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                        a[i], __builtin_bit_cast(bf16x8, bf[q][j]), acc[i][j], 0, 0, 0);
+                        a[i], __builtin_bit_cast(bf16x8, bq[j]), acc[i][j], 0, 0, 0);
         }
     }
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // the last (redundant) loads landed
-    __syncthreads();
-
-    // sum the partial tiles: wave w ends up with replica fragment w (all 4 variable
-    // fragments), adding the other waves' partials in ascending wave order.
-    float *red = reinterpret_cast<float *>(lds);
-    f32x16 fin[4];
+    wait_barrier<0>();     // the trailing (redundant) loads have landed in every wave and
+                           // every stage read is done: the stages can take the sums
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            if (i != w)
+        for (int j = 0; j < 2; ++j)
 #pragma unroll
-                for (int v = 0; v < 16; ++v) red[((i * 4 + w) * 16 + v) * 64 + lane] = acc[i][j][v];
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            if (i == w) fin[j] = acc[i][j];
-#pragma unroll
-        for (int src = 0; src < 4; ++src)
-            if (src != w)
-#pragma unroll
-                for (int v = 0; v < 16; ++v) fin[j][v] += red[((w * 4 + src) * 16 + v) * 64 + lane];
-        __syncthreads();
-    }
-
-    const int64_t wrow = np / 32;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int64_t iv = I0 + 32 * j + l32;
-        const float bi = b[iv];
-        const int64_t wcol = (I0 + 32 * j) / 32;
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            const int64_t r = R0 + 32 * w + 8 * (v >> 2) + 4 * half + (v & 3);
-            const int64_t g = r * np + iv;
-            float xv = 0.0f;
-            if (r < rlive) {
-                float h = __fadd_rn(__fmul_rn(fin[j][v], scale), bi);
-                float mv = m[g];
-                xv = x[g];
-                pa_update(h, lt, eta, alpha, xv, mv);
-                x[g] = xv;
-                m[g] = mv;
-                if (h_last) h_last[g] = h;
+            for (int v = 0; v < 16; ++v) {
+                const int row = 64 * wr + 32 * i + 8 * (v >> 2) + 4 * half + (v & 3);
+                const int col = 64 * wc + 32 * j + l32;
+                hs[row * BN + col] = acc[i][j][v];
             }
-            uint64_t bal = __ballot(xv < 0.0f);
-            uint32_t word = half ? (uint32_t)(bal >> 32) : (uint32_t)bal;
-            if (l32 == 0) s_nxt[r * wrow + wcol] = word;
-        }
-    }
+    wait_barrier<0>();     // field sums visible to the state waves
 }
 
-__global__ void __launch_bounds__(256, 1) k_mfma_step(
+__global__ void __launch_bounds__(THREADS, 1) k_mfma_step(
     int64_t Rp, int64_t np, int64_t rlive, const uint16_t *__restrict__ Jb,
     const float *__restrict__ b, const CanonScalars *__restrict__ sc,
-    const uint64_t *__restrict__ s_cur, uint32_t *__restrict__ s_nxt, float *__restrict__ x,
+    const uint32_t *__restrict__ s_cur, uint32_t *__restrict__ s_nxt, float *__restrict__ x,
     float *__restrict__ m, float *__restrict__ h_last, int t, const float *__restrict__ lam,
     float eta, float alpha) {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[4 * 2 * STG];
-    mfma_tile_step(lds, np, (int64_t)blockIdx.x * BN, (int64_t)blockIdx.y * BM, rlive, Jb, b,
-                   sc->scale, s_cur, s_nxt, x, m, h_last, lam[t], eta, alpha);
+    __shared__ __attribute__((aligned(16))) uint8_t lds[LDS_BYTES];
+    mfma_tile_step(lds, np, Rp, (int64_t)blockIdx.x * BN, (int64_t)blockIdx.y * BM, rlive, Jb,
+                   b, sc->scale, s_cur, s_nxt, x, m, h_last, lam[t], eta, alpha);
 }
 
 // Many instances in one launch: block k runs tile k of the table.  Each tile points at
 // its instance's couplings, bias, state and the two spin buffers (picked by step parity).
-__global__ void __launch_bounds__(256, 1) k_mfma_grouped(const MfmaTile *__restrict__ tiles,
-                                                         int t, const float *__restrict__ lam,
-                                                         float eta, float alpha) {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[4 * 2 * STG];
+__global__ void __launch_bounds__(THREADS, 1) k_mfma_grouped(const MfmaTile *__restrict__ tiles,
+                                                             int t, const float *__restrict__ lam,
+                                                             float eta, float alpha) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds[LDS_BYTES];
     const MfmaTile tl = tiles[blockIdx.x];
-    const uint64_t *cur = reinterpret_cast<const uint64_t *>((t & 1) ? tl.s1 : tl.s0);
+    const uint32_t *cur = (t & 1) ? tl.s1 : tl.s0;
     uint32_t *nxt = (t & 1) ? tl.s0 : tl.s1;
-    mfma_tile_step(lds, tl.np, tl.I0, tl.R0, tl.rlive, tl.Jb, tl.b, tl.sc->scale, cur, nxt, tl.x,
-                   tl.m, nullptr, lam[t], eta, alpha);
+    mfma_tile_step(lds, tl.np, tl.Rp, tl.I0, tl.R0, tl.rlive, tl.Jb, tl.b, tl.sc->scale, cur, nxt,
+                   tl.x, tl.m, nullptr, lam[t], eta, alpha);
 }
 
-// sbits[r][w] bit j = (x[r][32w + j] < 0)
+// Chunk-major sign bits of x: word (kc * Rp + r) * 4 + q, bit j = (x[r][128kc + 32q + j] < 0)
 __global__ void __launch_bounds__(256) k_mfma_pack(int64_t Rp, int64_t np,
                                                    const float *__restrict__ x,
                                                    uint32_t *__restrict__ sbits) {
@@ -232,11 +280,11 @@ __global__ void __launch_bounds__(256) k_mfma_pack(int64_t Rp, int64_t np,
     const int64_t total = Rp * words;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
          k += (int64_t)gridDim.x * blockDim.x) {
-        int64_t r = k / words, wd = k - r * words;
+        const int64_t r = k / words, wd = k - r * words;
         const float *xr = x + r * np + 32 * wd;
         uint32_t bits = 0;
         for (int j = 0; j < 32; ++j) bits |= (xr[j] < 0.0f ? 1u : 0u) << j;
-        sbits[k] = bits;
+        sbits[((wd >> 2) * Rp + r) * 4 + (wd & 3)] = bits;
     }
 }
 
@@ -255,20 +303,21 @@ hipError_t launch_mfma_step(int64_t Rp, int64_t np, int64_t rlive, const uint16_
                             const float *b, const CanonScalars *sc, const uint32_t *s_cur,
                             uint32_t *s_nxt, float *x, float *m, float *h_last, int32_t t,
                             const float *lam, float eta, float alpha, hipStream_t st) {
-    if (Rp % BM || np % MF_NPAD) return hipErrorInvalidValue;
+    if (Rp % BM || np % MF_NPAD || np <= 0 || rlive < 1 || rlive > Rp)
+        return hipErrorInvalidValue;
     dim3 grid((unsigned)(np / BN), (unsigned)(Rp / BM));
-    k_mfma_step<<<grid, 256, 0, st>>>(Rp, np, rlive, Jb, b, sc,
-                                      reinterpret_cast<const uint64_t *>(s_cur), s_nxt, x, m,
-                                      h_last, t, lam, eta, alpha);
+    k_mfma_step<<<grid, THREADS, 0, st>>>(Rp, np, rlive, Jb, b, sc, s_cur, s_nxt, x, m, h_last,
+                                          t, lam, eta, alpha);
     return hipGetLastError();
 }
 
 hipError_t launch_mfma_grouped(const MfmaTile *tiles, int32_t ntiles, int32_t t,
                                const float *lam, float eta, float alpha, hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
-    k_mfma_grouped<<<(unsigned)ntiles, 256, 0, st>>>(tiles, t, lam, eta, alpha);
+    k_mfma_grouped<<<(unsigned)ntiles, THREADS, 0, st>>>(tiles, t, lam, eta, alpha);
     return hipGetLastError();
 }
+
 
 // Dense BF16 copy of a CSR instance: Jb[i][j] = bf16(w_ij * 2^-e) for the stored
 // off-diagonal entries (zero elsewhere; the caller clears Jb first).

@@ -12,6 +12,7 @@
 
 struct qpa_ctx {
     int device = 0;
+    int cus = 256;                          // compute units of the device
     std::string err;
     int32_t *host_flags = nullptr;          // pinned, for the validation read-back
     qpa::CanonScalars *host_sc = nullptr;   // pinned
@@ -37,13 +38,14 @@ constexpr size_t ALIGN = 256;
 inline size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
-enum class Path { DenseResident, DenseTiled, DenseMfma, Csr };
+enum class Path { DenseResident, DenseTiled, DenseMfma, Csr, CsrResident };
 
 int32_t path_code(Path p) {
     switch (p) {
         case Path::DenseResident: return QPA_PATH_DENSE_RESIDENT;
         case Path::DenseTiled: return QPA_PATH_DENSE_TILED;
         case Path::DenseMfma: return QPA_PATH_DENSE_MFMA;
+        case Path::CsrResident: return QPA_PATH_CSR_RESIDENT;
         default: return QPA_PATH_CSR;
     }
 }
@@ -54,6 +56,7 @@ const char *path_name(Path p) {
         case Path::DenseTiled: return "dense-tiled-fp32";
         case Path::DenseMfma: return "dense-mfma-bf16";
         case Path::Csr: return "csr";
+        case Path::CsrResident: return "csr-resident";
     }
     return "?";
 }
@@ -73,7 +76,9 @@ struct Plan {
 
 
 // batch_rp > 0: state for the batch kernel, [batch_rp/64 groups][n][64].
-Plan make_plan(const qpa_problem &p, const qpa_params &a, int64_t batch_rp = 0) {
+// cus: compute units of the device (chooses the replica group of the resident sparse
+// kernel; the workspace size does not depend on it).
+Plan make_plan(const qpa_problem &p, const qpa_params &a, int64_t batch_rp = 0, int cus = 256) {
     Plan pl{};
     pl.n = p.n;
     pl.R = a.replicas;
@@ -85,7 +90,11 @@ Plan make_plan(const qpa_problem &p, const qpa_params &a, int64_t batch_rp = 0) 
     pl.Rp = pl.R;
     pl.G = 1;
     pl.nwords = 0;
-    if (p.format == QPA_FMT_CSR) {
+    if (p.format == QPA_FMT_CSR && batch_rp == 0 && cus > 0 && a.flags != QPA_SOLVE_STREAMED &&
+        csr_resident_group(pl.n, pl.R, cus) > 0 && csr_resident_lds(pl.n, p.nnz) <= RES_MAX_LDS) {
+        pl.path = Path::CsrResident;
+        pl.G = csr_resident_group(pl.n, pl.R, cus);
+    } else if (p.format == QPA_FMT_CSR) {
         pl.path = Path::Csr;
         pl.G = batch_rp > 0 ? 64 : csr_group_size(pl.R);
         pl.Rp = batch_rp > 0 ? batch_rp : round_up(pl.R, pl.G);
@@ -127,6 +136,7 @@ Plan make_plan(const qpa_problem &p, const qpa_params &a, int64_t batch_rp = 0) 
         case Path::DenseTiled: sbytes = sizeof(float) * R * n; break;
         case Path::DenseMfma: sbytes = sizeof(uint32_t) * Rp * (np / 32); break;
         case Path::Csr: sbytes = sizeof(uint64_t) * (size_t)(Rp / pl.G) * (size_t)pl.nwords; break;
+        case Path::CsrResident: sbytes = 0; break;
     }
     pl.o_s0 = sbytes ? take(sbytes) : 0;
     pl.o_s1 = sbytes ? take(sbytes) : 0;
@@ -143,7 +153,7 @@ Plan make_plan(const qpa_problem &p, const qpa_params &a, int64_t batch_rp = 0) 
 
 // Strides of element (r, i) in the internal state layout of a plan.
 void state_strides(const Plan &pl, int64_t &ld_r, int64_t &ld_i) {
-    if (pl.path == Path::Csr) {
+    if (pl.path == Path::Csr || pl.path == Path::CsrResident) {
         ld_r = 1;
         ld_i = pl.Rp;
     } else {
@@ -209,7 +219,8 @@ qpa_status check_params(qpa_ctx *ctx, const qpa_params *a) {
     if (a->steps < 0) return fail(ctx, QPA_E_ARG, "steps must be >= 0");
     if (a->precision != QPA_PREC_FP32 && a->precision != QPA_PREC_BF16)
         return fail(ctx, QPA_E_ARG, "unknown precision %d", a->precision);
-    if (a->flags != 0) return fail(ctx, QPA_E_ARG, "params.flags must be 0");
+    if (a->flags != 0 && a->flags != QPA_SOLVE_STREAMED)
+        return fail(ctx, QPA_E_ARG, "params.flags must be 0 or QPA_SOLVE_STREAMED");
     return QPA_OK;
 }
 
@@ -356,6 +367,14 @@ qpa_status run_steps_inner(qpa_ctx *ctx, const qpa_problem &p, const qpa_params 
             }
             break;
         }
+        case Path::CsrResident: {
+            CsrView c{pl.n, p.row_ptr, p.col, p.weights, p.index_dtype, p.coupling_dtype,
+                      pl.is_qubo, p.nnz};
+            QPA_HIP(launch_csr_resident(c, pl.G, pl.R, pl.Rp, pl.is_int, bf, x, m, h, t0, t1, lam,
+                                        a.eta, a.alpha, st));
+            launches = 1;
+            break;
+        }
         case Path::Csr: {
             uint64_t *s0 = at<uint64_t>(ws, pl.o_s0), *s1 = at<uint64_t>(ws, pl.o_s1);
             QPA_HIP(launch_csr_pack_spins(pl.n, pl.Rp, pl.G, x, s0, st));
@@ -394,7 +413,7 @@ qpa_status prologue(qpa_ctx *ctx, const qpa_problem *problem, const qpa_params *
     if (s != QPA_OK) return s;
     s = check_params(ctx, params);
     if (s != QPA_OK) return s;
-    pl = make_plan(*problem, *params);
+    pl = make_plan(*problem, *params, 0, ctx->cus);
     if (!ws) return fail(ctx, QPA_E_ARG, "workspace is NULL");
     if ((reinterpret_cast<uintptr_t>(ws) % ALIGN) != 0)
         return fail(ctx, QPA_E_ARG, "workspace must be %zu-byte aligned", ALIGN);
@@ -418,7 +437,7 @@ qpa_status make_rel_plan(qpa_ctx *ctx, const qpa_problem &p, const qpa_params &a
     if (k < 1) return fail(ctx, QPA_E_ARG, "ckpt_every must be >= 1");
     qpa_params a32 = a;
     a32.precision = QPA_PREC_FP32;
-    rp.base = make_plan(p, a32);
+    rp.base = make_plan(p, a32, 0, 0);   // streamed layout: the adjoint kernels use it
     rp.k = k;
     rp.nseg = (int32_t)((a.steps + k - 1) / k);
     const size_t RN = (size_t)a.replicas * (size_t)p.n;
@@ -560,6 +579,8 @@ qpa_status qpa_create(qpa_ctx **out, int device) {
                     hipGetErrorString(e));
     qpa_ctx *c = new qpa_ctx();
     c->device = device;
+    (void)hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, device);
+    if (c->cus < 1) c->cus = 1;
     e = hipHostMalloc((void **)&c->host_sc, sizeof(CanonScalars), hipHostMallocDefault);
     if (e != hipSuccess) {
         delete c;
@@ -622,7 +643,7 @@ qpa_status qpa_batch_paths(const qpa_ctx *ctx, int32_t count, int32_t *paths) {
 qpa_status qpa_profile_read_path(qpa_ctx *ctx, int32_t path, double *step_ms,
                                  int64_t *step_launches, int32_t reset) {
     if (!ctx || !step_ms || !step_launches) return QPA_E_ARG;
-    if (path < QPA_PATH_ALL || path > QPA_PATH_BATCH_DENSE)
+    if (path < QPA_PATH_ALL || path > QPA_PATH_CSR_RESIDENT)
         return fail(ctx, QPA_E_ARG, "unknown path %d", path);
     double total = 0.0;
     int64_t n = 0;
@@ -898,6 +919,7 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
                 tl.x = dx;
                 tl.m = dm;
                 tl.np = ds.np;
+                tl.Rp = ds.Rp;
                 tl.I0 = ib * MF_BN;
                 tl.R0 = rb * MF_BM;
                 tl.rlive = R;

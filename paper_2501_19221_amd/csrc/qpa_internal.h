@@ -101,11 +101,12 @@ hipError_t launch_dense_tiled_step(int64_t n, int64_t R, const float *J, const f
                                    float alpha, hipStream_t st);
 hipError_t launch_sign_f32(int64_t count, const float *x, float *s, hipStream_t st);
 
-// BF16 matrix-core path.  Internal padded layout: x, m [Rp][np] FP32, spin bits
-// [Rp][np/32] uint32 (bit j of word w <=> variable 32w + j is -1), Jb [np][np] bf16.
+// BF16 matrix-core path.  Internal padded layout: x, m [Rp][np] FP32, Jb [np][np] bf16,
+// spin bits Rp * np / 32 uint32 in chunk-major order: word (kc * Rp + r) * 4 + q, bit j
+// <=> variable 128 kc + 32 q + j of replica r is -1.
 constexpr int MF_BM = 128;   // replicas per tile
 constexpr int MF_BN = 128;   // variables per tile
-constexpr int MF_NPAD = 256; // np is a multiple of this (4 waves x 64-wide chunks)
+constexpr int MF_NPAD = 128; // np is a multiple of this (the reduction chunk)
 hipError_t launch_mfma_pack_spins(int64_t Rp, int64_t np, const float *x, uint32_t *sbits,
                                   hipStream_t st);
 hipError_t launch_mfma_step(int64_t Rp, int64_t np, int64_t rlive, const uint16_t *Jb,
@@ -119,7 +120,7 @@ struct MfmaTile {
     const CanonScalars *sc;
     uint32_t *s0, *s1;       // spin-bit buffers: step t reads s0 if t is even, else s1
     float *x, *m;            // [Rp][np] state of the instance
-    int64_t np, I0, R0, rlive;
+    int64_t np, Rp, I0, R0, rlive;
 };
 hipError_t launch_mfma_grouped(const MfmaTile *tiles, int32_t ntiles, int32_t t,
                                const float *lam, float eta, float alpha, hipStream_t st);
@@ -137,7 +138,19 @@ struct CsrView {
     const void *w;
     int32_t col_dt, w_dt;
     bool skip_diag;      // QUBO: diagonal entries are folded into b
+    int64_t nnz = 0;
 };
+// Resident sparse steps: the state of G replicas x all variables stays in registers and
+// the CSR structure in LDS for all steps of one launch (G in {1, 2, 4, 8}).
+constexpr int64_t RES_MAX_N = 8192;
+constexpr size_t RES_MAX_LDS = 160 * 1024;
+size_t csr_resident_lds(int64_t n, int64_t nnz);
+// G for R replicas on `cus` compute units, 0 when the instance does not fit the kernel.
+int csr_resident_group(int64_t n, int64_t R, int cus);
+hipError_t launch_csr_resident(const CsrView &c, int G, int64_t R, int64_t Rp, bool is_int,
+                               const float *b, float *x, float *m, float *h_last, int32_t t0,
+                               int32_t t1, const float *lam, float eta, float alpha,
+                               hipStream_t st);
 int csr_group_size(int64_t R);
 int64_t csr_words_per_group(int64_t n, int G);
 hipError_t launch_csr_pack_spins(int64_t n, int64_t Rp, int G, const float *x, uint64_t *sbits,

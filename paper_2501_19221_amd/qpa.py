@@ -36,7 +36,8 @@ QPA_I8, QPA_I16, QPA_I32, QPA_F32 = 0, 1, 2, 3
 QPA_PREC_FP32, QPA_PREC_BF16 = 0, 1
 QPA_BATCH_SPARSE, QPA_BATCH_DENSE = 1, 2
 QPA_PATH_ALL, QPA_PATH_DENSE_RESIDENT, QPA_PATH_DENSE_TILED, QPA_PATH_DENSE_MFMA, QPA_PATH_CSR, \
-    QPA_PATH_BATCH_SPARSE, QPA_PATH_BATCH_DENSE = range(-1, 6)
+    QPA_PATH_BATCH_SPARSE, QPA_PATH_BATCH_DENSE, QPA_PATH_CSR_RESIDENT = range(-1, 7)
+QPA_SOLVE_STREAMED = 4
 
 EXPORTED = ["qpa_create", "qpa_destroy", "qpa_last_error", "qpa_status_string",
             "qpa_workspace_size", "qpa_solve", "qpa_steps", "qpa_energy", "qpa_version",

@@ -172,13 +172,33 @@ def _energies_csr_int(canon, kind, s):
     return (H + K) // 2 if kind == "qubo" else H
 
 
+def _launches_by_path(q, eng, fn):
+    """Runs fn() with kernel profiling on; returns {path code: step-kernel launches}."""
+    q.qpa_profile_read(eng.ctx, reset=True)
+    q.qpa_profile_enable(eng.ctx, True)
+    try:
+        res = fn()
+    finally:
+        q.qpa_profile_enable(eng.ctx, False)
+    paths = {}
+    for code in range(0, 7):
+        _, n = q.qpa_profile_read_path(eng.ctx, code)
+        if n:
+            paths[code] = n
+    q.qpa_profile_read(eng.ctx, reset=True)
+    return res, paths
+
+
+@pytest.mark.parametrize("streamed", [False, True])
 @pytest.mark.parametrize("m_,R,T", [(4, 70, 200), (2, 1, 30), (3, 64, 50)])
-def test_csr_chimera_bit_exact(q, eng, m_, R, T):
+def test_csr_chimera_bit_exact(q, eng, m_, R, T, streamed):
     inst = gen.chimera_ising(m_, seed=m_)
     prob = q.Problem.from_instance(inst)
-    p = _params(q, R, T, 0.2, 0.8, 10.0)
-    say("csr chimera m=%d R=%d T=%d" % (m_, R, T))
-    out = eng.solve(prob, p, want_state=True)
+    p = _params(q, R, T, 0.2, 0.8, 10.0, flags=q.QPA_SOLVE_STREAMED if streamed else 0)
+    say("csr chimera m=%d R=%d T=%d streamed=%s" % (m_, R, T, streamed))
+    out, paths = _launches_by_path(q, eng, lambda: eng.solve(prob, p, want_state=True))
+    want = q.QPA_PATH_CSR if streamed else q.QPA_PATH_CSR_RESIDENT
+    assert list(paths) == [want], paths
     x, m, canon = _oracle_csr(inst, R, T, orc.lambda_linear(T, 10.0), 0.2, 0.8)
     assert np.array_equal(host(out["x"]), x)
     assert np.array_equal(host(out["m"]), m)
@@ -187,6 +207,31 @@ def test_csr_chimera_bit_exact(q, eng, m_, R, T):
     e = _energies_csr_int(canon, "ising", s)
     assert np.array_equal(host(out["energy_i64"]), e)
     assert int(host(out["best"])[0]) == int(np.flatnonzero(e == e.min())[0])
+
+
+# replica groups G = 8, 4, 2, 1 and 2, 2, 4, 8, 1 variables per thread of the resident
+# kernel, with replica counts that leave a partial group (the n = 6000 graph has degree 3,
+# so that its CSR fits in LDS)
+@pytest.mark.parametrize("graph,R,T", [("chimera14", 2050, 12), ("chimera14", 1100, 15),
+                                       ("chimera19", 515, 10), ("planted6000", 300, 6),
+                                       ("chimera1", 7, 40)])
+def test_csr_resident_groups_bit_exact(q, eng, graph, R, T):
+    if graph.startswith("chimera"):
+        m_ = int(graph[len("chimera"):])
+        inst = gen.chimera_ising(m_, seed=m_ + 1)
+    else:
+        inst = gen.planted_3regular(6000, 1, 7, seed=3)
+    prob = q.Problem.from_instance(inst)
+    p = _params(q, R, T, 0.2, 0.8, 10.0)
+    say("csr resident chimera n=%d R=%d T=%d" % (inst.n, R, T))
+    out, paths = _launches_by_path(q, eng, lambda: eng.solve(prob, p, want_state=True))
+    assert list(paths) == [q.QPA_PATH_CSR_RESIDENT], paths
+    x, m, canon = _oracle_csr(inst, R, T, orc.lambda_linear(T, 10.0), 0.2, 0.8)
+    assert np.array_equal(host(out["x"]), x)
+    assert np.array_equal(host(out["m"]), m)
+    s = np.where(x >= 0, 1, -1).astype(np.int8)
+    e = _energies_csr_int(canon, "ising", s)
+    assert np.array_equal(host(out["energy_i64"]), e)
 
 
 def test_chimera16_full_workload_replica_subset(q, eng):
@@ -206,7 +251,8 @@ def test_chimera16_full_workload_replica_subset(q, eng):
     assert int(host(out["best"])[0]) == int(np.flatnonzero(e == e.min())[0])
 
 
-def test_csr_er_qubo_int16(q, eng):
+@pytest.mark.parametrize("streamed", [False, True])
+def test_csr_er_qubo_int16(q, eng, streamed):
     rng = np.random.default_rng(3)
     inst = gen.er_qubo(300, 0.1, 100, rng)
     # add diagonal terms to exercise the QUBO fold
@@ -220,8 +266,8 @@ def test_csr_er_qubo_int16(q, eng):
     inst.csr = gen.CSR(n, rp.astype(np.int32), cols.astype(np.int16), d[rows, cols].astype(np.int16))
     R, T = 5, 100
     prob = q.Problem.from_instance(inst)
-    p = _params(q, R, T, 0.0002, 0.8, 200.0)
-    say("csr ER qubo int16 n=%d R=%d T=%d" % (n, R, T))
+    p = _params(q, R, T, 0.0002, 0.8, 200.0, flags=q.QPA_SOLVE_STREAMED if streamed else 0)
+    say("csr ER qubo int16 n=%d R=%d T=%d streamed=%s" % (n, R, T, streamed))
     out = eng.solve(prob, p, want_state=True)
     x, m, canon = _oracle_csr(inst, R, T, orc.lambda_linear(T, 200.0), 0.0002, 0.8)
     assert np.array_equal(host(out["x"]), x) and np.array_equal(host(out["m"]), m)
@@ -234,7 +280,8 @@ def test_csr_er_qubo_int16(q, eng):
         assert e[r] == orc.qubo_energy_int(d, inst.lin, xb)
 
 
-def test_csr_float_weights_bit_exact(q, eng):
+@pytest.mark.parametrize("streamed", [False, True])
+def test_csr_float_weights_bit_exact(q, eng, streamed):
     inst = gen.chimera_ising(3, seed=4)
     rng = np.random.default_rng(0)
     c = inst.csr
@@ -246,8 +293,8 @@ def test_csr_float_weights_bit_exact(q, eng):
     inst.lin = rng.standard_normal(inst.n).astype(np.float32) * 0.3
     R, T = 3, 80
     prob = q.Problem.from_instance(inst)
-    p = _params(q, R, T, 0.1, 0.8, 2.0)
-    say("csr float weights n=%d" % inst.n)
+    p = _params(q, R, T, 0.1, 0.8, 2.0, flags=q.QPA_SOLVE_STREAMED if streamed else 0)
+    say("csr float weights n=%d streamed=%s" % (inst.n, streamed))
     out = eng.solve(prob, p, want_state=True)
     x, m, _ = _oracle_csr(inst, R, T, orc.lambda_linear(T, 2.0), 0.1, 0.8)
     assert np.array_equal(host(out["x"]), x) and np.array_equal(host(out["m"]), m)
@@ -278,18 +325,20 @@ def test_energy_entry_point(q, eng):
         assert int(host(best)[0]) == int(np.flatnonzero(ref == ref.min())[0])
 
 
-@pytest.mark.parametrize("which", ["dense-tiled", "csr", "mfma"])
+@pytest.mark.parametrize("which", ["dense-tiled", "csr", "csr-streamed", "mfma"])
 def test_resume_split_equals_uninterrupted(q, eng, which):
     import torch
-    if which == "csr":
+    flags = 0
+    if which.startswith("csr"):
         inst, prec = gen.chimera_ising(4, seed=9), "fp32"
+        flags = q.QPA_SOLVE_STREAMED if which == "csr-streamed" else 0
     elif which == "mfma":
         inst, prec = gen.dense_int_ising(150, seed=4), "bf16"
     else:
         inst, prec = gen.dense_int_ising(150, seed=4), "fp32"
     R, T = 9, 120
     prob = q.Problem.from_instance(inst)
-    p = _params(q, R, T, 0.01, 0.8, 5.0, prec=prec)
+    p = _params(q, R, T, 0.01, 0.8, 5.0, prec=prec, flags=flags)
     say("resume split %s" % which)
     full = eng.solve(prob, p, want_state=True)
     x, m = orc.pa_init(inst.n, R, 1, np.float32(0.1))
@@ -388,6 +437,7 @@ def test_batch_uneven_instances_bit_exact(q, eng, path):
     rng = np.random.default_rng(7)
     insts = [gen.er_qubo(int(n), 0.1, 100, rng) for n in rng.integers(30, 400, size=9)]
     insts.append(gen.chimera_ising(3, seed=5))          # an Ising instance in the same batch
+    insts.append(gen.er_qubo(400, 0.005, 100, rng))     # sparse enough for the sparse kernel
     insts.append(gen.er_qubo(300, 0.2, 300, rng))
     R, T, eta, alpha, lam0 = 70, 60, 0.0002, 0.8, 200.0  # 70 replicas: a full and a partial group
     probs = [q.Problem.from_instance(i) for i in insts]
@@ -402,7 +452,8 @@ def test_batch_uneven_instances_bit_exact(q, eng, path):
     elif path == "dense":
         assert (paths[:-1] == q.QPA_PATH_BATCH_DENSE).all()
     else:                                                  # the cost model mixes both
-        assert (paths == q.QPA_PATH_BATCH_DENSE).any() and (paths[:-2] != paths[0]).any()
+        assert paths[0] == q.QPA_PATH_BATCH_DENSE           # n=379, 10% of pairs
+        assert paths[-2] == q.QPA_PATH_BATCH_SPARSE         # n=400, 0.5% of pairs
     lam = orc.lambda_linear(T, lam0)
     for k, (inst, out) in enumerate(zip(insts, outs)):
         x, m, canon = _oracle_instance(inst, R, T, lam, eta, alpha, seed=11 + k)
