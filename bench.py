@@ -240,7 +240,7 @@ def main():
         extra = {"mean_best_energy": float(np.mean(bestE))}
     elif inst0.dense is not None:
         n = inst0.n
-        if per_solve_launches <= 1.0:      # LDS-resident kernel: all steps in one launch
+        if per_solve_launches <= 1.0:      # resident kernels: all steps in one launch
             flops = 2.0 * R * n * n * T
             what = "2*R*n^2*T = %.4g flop (all steps of all replicas, one launch)" % flops
         else:

@@ -11,18 +11,25 @@
 //     PA update and write x, m and the new sign bits.
 // Chunks are staged through LDS with direct global->LDS loads issued by the matrix waves
 // only (NST stages, NST-1 chunks in flight): per chunk the 128 x 128 bf16 block of J
-// (8 loads of 16 bytes per lane and wave, each filling 4 rows of 256 bytes) and the
-// 128 x 128 spin bits of the tile's replicas (2 loads of 4 bytes per lane and wave).
-// Inside a J row the sixteen 16-byte pieces sit at position piece ^ (row % 16), so that
-// the fragment reads of 16 consecutive rows fall on distinct banks.  One barrier per
+// (8 loads of 16 bytes per lane and wave, each filling 4 rows of 256 bytes) and the spins
+// of the tile's 128 replicas for those 128 variables (2 loads of 16 bytes per lane and
+// wave, 64 bytes per replica).
+// Inside a J row the sixteen 16-byte pieces sit at position piece ^ (row % 16), and inside
+// a replica's 64 spin bytes the four 16-byte pieces at (piece + row / 4) % 4, so that the
+// fragment reads of 16 consecutive rows fall on distinct banks.  One barrier per
 // chunk publishes a stage and frees the one that is loaded next; the state waves take
 // part in every barrier and issue no loads in between, so that the matrix waves' waits
 // count their own loads only.  After the loop the raw sums go to the state waves
-// through LDS (128 x 128 FP32, row-major).
+// through LDS (128 x 128 FP32, rows padded to 136 so that the two halves of a wave's
+// stores use different banks).
 //
-// Spin bits ("chunk-major"): u32 word (kc * Rp + r) * 4 + q holds in bit j the sign of
-// variable 128 kc + 32 q + j of replica r (bit set <=> spin -1), so that the spins of a
-// tile's replicas for one chunk are one contiguous 2 KiB block.
+// Spins ("pair words", chunk-major): for replica r and chunk kc (variables 128 kc ..
+// 128 kc + 127) there are 16 u32 words at (kc * Rp + r) * 16.  Word 8 h + q covers the
+// eight variables 128 kc + 16 q + 8 h + j (j = 0..7) -- exactly the k values of one lane
+// half h of the matrix instruction's operand at k step q -- as the byte B (bit j set <=>
+// spin -1) in its low half and B >> 1 in its high half, the form the sign expansion
+// starts from.  The state waves write this form once per step; each word is expanded by
+// every tile of its replicas' row, so work moved into the writer is saved many times.
 //
 // Matrix instruction: v_mfma_f32_32x32x16_bf16.  Operand layout (64 lanes):
 //   A (32 x 16, rows = replicas): lane l holds row l%32, k = 8*(l/32) .. +7
@@ -40,13 +47,15 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 constexpr int BM = MF_BM, BN = MF_BN;
 constexpr int KC = 128;                      // reduction chunk (variables)
 constexpr int JSTG = BN * KC * 2;            // J block of a stage: 128 rows x 256 bytes
-constexpr int SSTG = BM * KC / 8;            // spin bits of a stage: 128 rows x 16 bytes
+constexpr int SSTG = BM * 64;                // spin words of a stage: 128 rows x 64 bytes
 constexpr int STG = JSTG + SSTG;
-constexpr int NST = 3;                       // stages
+constexpr int NST = 4;                       // stages
 constexpr int LDS_BYTES = NST * STG;
+constexpr int HS = BN + 8;                   // row stride of the field handoff (floats)
 constexpr int THREADS = 512;                 // 4 matrix waves + 4 state waves
 constexpr int MW = 4;                        // matrix waves
-static_assert(LDS_BYTES >= BM * BN * 4, "the field handoff reuses the stages");
+static_assert(LDS_BYTES >= BM * HS * 4, "the field handoff reuses the stages");
+static_assert(LDS_BYTES <= 160 * 1024, "LDS of one workgroup");
 static_assert(MF_NPAD % KC == 0, "np must be a multiple of the chunk");
 
 __device__ __forceinline__ void pa_update(float h, float lam, float eta, float alpha, float &x,
@@ -61,16 +70,14 @@ __device__ __forceinline__ void pa_update(float h, float lam, float eta, float a
 
 typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
 
-// 8 sign bits (bit j <=> element j is -1) -> eight bf16 +-1 values:
-// dword q holds elements 2q (low half) and 2q+1 (high half); a set bit sets the half's
-// sign bit on top of 0x3F80 (= 1.0).  The byte is paired as 16-bit halves
-// (byte, byte >> 1), so that one packed 16-bit shift by 15 - 2q brings bit 2q to the
-// top of the low half and bit 2q+1 to the top of the high half; a mask keeps the two
-// sign positions.  All full-rate ALU operations.
-__device__ __forceinline__ bf16x8 expand_spins(uint32_t byte, uint32_t sign_mask) {
-    // low half: byte (bit 15 also receives bit 0, which every shift below moves out);
-    // high half: byte >> 1
-    const uint32_t pair = (byte << 15) | byte;
+// Pair word (low half: byte B of 8 sign bits, bit j <=> element j is -1; high half:
+// B >> 1) -> eight bf16 +-1 values: dword q holds elements 2q (low half) and 2q+1 (high
+// half); a set bit sets the half's sign bit on top of 0x3F80 (= 1.0).  One packed 16-bit
+// shift by 15 - 2q brings bit 2q to the top of the low half and bit 2q+1 to the top of
+// the high half; a mask keeps the two sign positions.  Two full-rate operations per dword.
+__device__ __forceinline__ uint32_t spin_pair(uint32_t byte) { return byte | ((byte >> 1) << 16); }
+
+__device__ __forceinline__ bf16x8 expand_spins(uint32_t pair, uint32_t sign_mask) {
     u32x4 d;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -103,65 +110,25 @@ template <int N> __device__ __forceinline__ void wait_barrier() {
 
 constexpr int LOADS_PER_CHUNK = 10;          // per matrix wave: 8 J pieces + 2 spin dwords
 
-// One 128 x 128 output tile of one PA step: replicas R0 .. R0+127 (rows at or past
-// `rlive` are padding: their state is neither read nor written and they report +1
-// spins), variables I0 .. I0+127.  `lds` holds LDS_BYTES bytes.
-__device__ __forceinline__ void mfma_tile_step(
-    uint8_t *lds, int64_t np, int64_t Rp, int64_t I0, int64_t R0, int64_t rlive,
-    const uint16_t *__restrict__ Jb, const float *__restrict__ b, float scale,
-    const uint32_t *__restrict__ s_cur, uint32_t *__restrict__ s_nxt, float *__restrict__ x,
-    float *__restrict__ m, float *__restrict__ h_last, float lt, float eta, float alpha) {
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int nchunk = (int)(np / KC);
-    float *hs = reinterpret_cast<float *>(lds);   // field sums of the tile, after the loop
+// The tile of a workgroup: replicas R0 .. R0+127 (rows at or past `rlive` are padding:
+// their state is neither read nor written and they report +1 spins), variables
+// I0 .. I0+127 of an instance with np padded variables and Rp padded replicas.
+struct Tile {
+    int64_t np, Rp, I0, R0, rlive;
+    const uint16_t *Jb;
+    const float *b;
+    float scale;
+    float *x, *m;
+};
 
-    if (wave >= MW) {
-        // ---- state waves: thread t owns column t % 128 of rows 2e + t / 128 ----
-        const int t = tid - MW * 64;
-        const int col = t & (BN - 1);
-        const int rsub = __builtin_amdgcn_readfirstlane(t >> 7);
-        const int64_t iv = I0 + col;
-        const int64_t rmax = rlive - 1;
-        float xv[BM / 2], mv[BM / 2];
-#pragma unroll
-        for (int e = 0; e < BM / 2; ++e) {
-            // padding rows read a live row instead (never written back)
-            const int64_t r = min(R0 + 2 * e + rsub, rmax);
-            xv[e] = x[r * np + iv];
-            mv[e] = m[r * np + iv];
-        }
-        const float bi = b[iv];
-        for (int c = 0; c < nchunk; ++c) barrier();   // the matrix waves' chunks
-        barrier();                                     // stages drained
-        barrier();                                     // field sums in LDS
-        // collect every load here, once, so that the stores below wait for nothing
-#pragma unroll
-        for (int e = 0; e < BM / 2; ++e) asm volatile("" ::"v"(xv[e]), "v"(mv[e]));
-        asm volatile("" ::"v"(bi));
-        const int64_t wbase = (I0 / KC) * Rp * 4 + 2 * ((wave - MW) & 1);
-#pragma unroll
-        for (int e = 0; e < BM / 2; ++e) {
-            const int row = 2 * e + rsub;
-            const int64_t r = R0 + row;
-            const bool live = r < rlive;
-            const float h = __fadd_rn(__fmul_rn(hs[row * BN + col], scale), bi);
-            float xn = xv[e], mn = mv[e];
-            pa_update(h, lt, eta, alpha, xn, mn);
-            // this wave covers 64 consecutive variables of row r: one 64-bit spin word
-            const uint64_t bal = __ballot(live && xn < 0.0f);
-            if (live) {
-                x[r * np + iv] = xn;
-                m[r * np + iv] = mn;
-                if (h_last) h_last[r * np + iv] = h;
-            }
-            if (lane == 0)
-                *reinterpret_cast<uint64_t *>(s_nxt + wbase + r * 4) = bal;
-        }
-        return;
-    }
-
-    // ---- matrix waves ----
+// ---- matrix waves: the reduction of one step, left in LDS as raw sums --------------
+// Executes nchunk + 2 workgroup barriers (the state waves execute as many).
+__device__ __forceinline__ void matrix_step(uint8_t *lds, const Tile &tl, int nchunk,
+                                            const uint32_t *__restrict__ s_cur, int wave,
+                                            int lane) {
+    const int64_t np = tl.np, I0 = tl.I0, R0 = tl.R0;
+    const uint16_t *__restrict__ Jb = tl.Jb;
+    float *hs = reinterpret_cast<float *>(lds);
     const int wr = wave >> 1, wc = wave & 1;
     const int half = lane >> 5, l32 = lane & 31;
     // J: load u (0..7) of wave w fills LDS rows 32w + 4u + lane/16 at position lane % 16,
@@ -172,9 +139,14 @@ __device__ __forceinline__ void mfma_tile_step(
         const int row = 32 * wave + 4 * u + (lane >> 4);
         gJ[u] = Jb + (I0 + row) * np + 8 * ((lane & 15) ^ (row & 15));
     }
-    // spins: load e (0..1) of wave w fills bytes 512w + 256e + 4 lane of the 2 KiB block
-    const uint32_t *gS = s_cur + R0 * 4 + 128 * wave + lane;
-    const int64_t sstride = Rp * 4;                // u32 words between consecutive chunks
+    // spins: load e (0..1) of wave w fills bytes 2048w + 1024e + 16 lane of the 8 KiB
+    // block of the tile's replicas (64 bytes per replica, in replica order): row
+    // 32w + 16e + lane/4, position lane % 4, which holds piece (lane - row / 4) % 4
+    const int srow0 = 32 * wave + (lane >> 2);      // row for e = 0; e adds 16 (4 to row/4)
+    const uint32_t *gS = s_cur + (R0 + srow0) * 16 + 4 * (((lane & 3) - (srow0 >> 2)) & 3);
+    const uint32_t *gS1 = s_cur + (R0 + srow0 + 16) * 16 +
+                          4 * (((lane & 3) - ((srow0 + 16) >> 2)) & 3);
+    const int64_t sstride = tl.Rp * 16;            // u32 words between consecutive chunks
     auto stage = [&](int kc, int st) {
         kc = kc < nchunk ? kc : nchunk - 1;        // past the end: reload the last chunk
         uint8_t *dst = lds + st * STG;
@@ -182,11 +154,11 @@ __device__ __forceinline__ void mfma_tile_step(
         for (int u = 0; u < 8; ++u)
             __builtin_amdgcn_global_load_lds(gJ[u] + (int64_t)kc * KC,
                                              (lds_void *)(dst + (8 * wave + u) * 1024), 16, 0, 0);
-#pragma unroll
-        for (int e = 0; e < 2; ++e)
-            __builtin_amdgcn_global_load_lds(gS + (int64_t)kc * sstride + 64 * e,
-                                             (lds_void *)(dst + JSTG + 512 * wave + 256 * e), 4,
-                                             0, 0);
+        __builtin_amdgcn_global_load_lds(gS + (int64_t)kc * sstride,
+                                         (lds_void *)(dst + JSTG + 2048 * wave), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(gS1 + (int64_t)kc * sstride,
+                                         (lds_void *)(dst + JSTG + 2048 * wave + 1024), 16, 0,
+                                         0);
     };
 
     const uint32_t sign_mask = __builtin_amdgcn_readfirstlane(0x80008000u) + 0u * lane;
@@ -207,10 +179,16 @@ __device__ __forceinline__ void mfma_tile_step(
         wait_barrier<(NST - 2) * LOADS_PER_CHUNK>();
         stage(c + NST - 1, (c + NST - 1) % NST);
         const uint8_t *src = lds + (c % NST) * STG;
-        u32x4 sw[2];
+        // this lane's 8 pair words (k steps 0..7 of its half) for each replica fragment
+        u32x4 sw[2][2];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
-            sw[i] = *reinterpret_cast<const u32x4 *>(src + JSTG + 16 * (64 * wr + 32 * i + l32));
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+                const int row = 64 * wr + 32 * i + l32;
+                const int pos = (2 * half + hh + (row >> 2)) & 3;
+                sw[i][hh] = *reinterpret_cast<const u32x4 *>(src + JSTG + 64 * row + 16 * pos);
+            }
 #pragma unroll
         for (int q = 0; q < KC / 16; ++q) {
             u32x4 bq[2];
@@ -223,8 +201,7 @@ __device__ __forceinline__ void mfma_tile_step(
             bf16x8 a[2];
 #pragma unroll
             for (int i = 0; i < 2; ++i)
-                a[i] = expand_spins((sw[i][q >> 1] >> (16 * (q & 1) + 8 * half)) & 0xFFu,
-                                    sign_mask);
+                a[i] = expand_spins(sw[i][q >> 2][q & 3], sign_mask);
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -243,9 +220,157 @@ __device__ __forceinline__ void mfma_tile_step(
             for (int v = 0; v < 16; ++v) {
                 const int row = 64 * wr + 32 * i + 8 * (v >> 2) + 4 * half + (v & 3);
                 const int col = 64 * wc + 32 * j + l32;
-                hs[row * BN + col] = acc[i][j][v];
+                hs[row * HS + col] = acc[i][j][v];
             }
     wait_barrier<0>();     // field sums visible to the state waves
+}
+
+// ---- state waves: thread t (0..255) owns column t % 128 of rows 2e + t / 128 ---------
+// Row pointers are wave-uniform and advanced one row pair at a time through an opaque
+// step, so that the compiler computes each address when it is used instead of holding
+// all 64 in scalar registers.
+template <typename P> __device__ __forceinline__ P *next_rows(P *p, int64_t stride) {
+    P *q = p + stride;
+    asm volatile("" : "+s"(q));
+    return q;
+}
+
+struct StateRegs {
+    float xv[BM / 2], mv[BM / 2];
+    float bi;
+};
+
+// Loads the tile's x, m and b, spread over the matrix waves' nchunk chunk barriers (a
+// few elements before each), so that this traffic shares the memory system with the
+// chunk loads instead of delaying the first chunks.  Rows past rlive are padding rows of
+// the [Rp][np] state: they are read (zeros, never written back) like the others.  Row
+// pointers are wave-uniform, so that each load is a scalar base plus the lane's column.
+// Executes nchunk barriers.
+__device__ __forceinline__ void state_load(StateRegs &st, const Tile &tl, int nchunk, int t) {
+    const int col = t & (BN - 1);
+    const int rsub = __builtin_amdgcn_readfirstlane(t >> 7);
+    const int per = (BM / 2 + nchunk - 1) / nchunk;
+    const float *xr = tl.x + (tl.R0 + rsub) * tl.np + tl.I0;
+    const float *mr = tl.m + (tl.R0 + rsub) * tl.np + tl.I0;
+    int passed = 0;
+#pragma unroll
+    for (int e = 0; e < BM / 2; ++e) {
+        if (e > 0 && e % per == 0 && passed < nchunk) {
+            barrier();
+            ++passed;
+        }
+        st.xv[e] = xr[col];
+        st.mv[e] = mr[col];
+        xr = next_rows(xr, 2 * tl.np);
+        mr = next_rows(mr, 2 * tl.np);
+    }
+    st.bi = tl.b[tl.I0 + col];
+    for (; passed < nchunk; ++passed) barrier();   // the remaining chunks
+}
+
+// Waits for the loads of state_load, once, so that later stores wait for nothing.
+__device__ __forceinline__ void state_collect(StateRegs &st) {
+#pragma unroll
+    for (int e = 0; e < BM / 2; ++e) asm volatile("" ::"v"(st.xv[e]), "v"(st.mv[e]));
+    asm volatile("" ::"v"(st.bi));
+}
+
+// The PA update of the tile from the field sums in LDS, then the new spins as pair words.
+// Rows are taken in groups of 8 with no branch inside the loop (the field reads of a group
+// are issued together); lane 2g + ln keeps the ballot of row g of each group, and after
+// the loop lanes 0..15 turn them into 16-byte stores (the even (ln = 0) or odd (ln = 1)
+// bytes of their row).  With h_last the fields are stored by a second pass.  Executes no
+// barrier.
+__device__ __forceinline__ void state_update(StateRegs &st, const Tile &tl, const float *hs,
+                                             uint32_t *__restrict__ s_nxt,
+                                             float *__restrict__ h_last, int t, int wave,
+                                             int lane, float lt, float eta, float alpha) {
+    const int col = t & (BN - 1);
+    const int rsub = __builtin_amdgcn_readfirstlane(t >> 7);
+    const int u_mine = (lane >> 1) & 7;
+    uint64_t mine[BM / 16];
+#pragma unroll
+    for (int g = 0; g < BM / 16; ++g) {
+        float hv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) hv[u] = hs[(2 * (8 * g + u) + rsub) * HS + col];
+        uint64_t bal[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = 8 * g + u;
+            const bool live = tl.R0 + 2 * e + rsub < tl.rlive;      // uniform per wave
+            const float h = __fadd_rn(__fmul_rn(hv[u], tl.scale), st.bi);
+            pa_update(h, lt, eta, alpha, st.xv[e], st.mv[e]);
+            bal[u] = __ballot(live && st.xv[e] < 0.0f);
+        }
+        mine[g] = bal[0];
+#pragma unroll
+        for (int k = 1; k < 8; ++k) mine[g] = u_mine == k ? bal[k] : mine[g];
+    }
+    // this wave covers variables 64 c2 .. 64 c2 + 63 of the chunk: ballot byte k of a row
+    // is word 8 (k & 1) + 4 c2 + k / 2 of the replica's 16 pair words
+    if (lane < 16) {
+        const int c2 = (wave - MW) & 1;
+        const int ln = lane & 1;
+        uint32_t *wrow = s_nxt + ((tl.I0 / KC) * tl.Rp + tl.R0 + rsub) * 16 + 4 * c2 + 8 * ln;
+#pragma unroll
+        for (int g = 0; g < BM / 16; ++g) {
+            u32x4 wq;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                wq[k] = spin_pair((uint32_t)(mine[g] >> (8 * (2 * k + ln))) & 0xFFu);
+            *reinterpret_cast<u32x4 *>(wrow + 32 * (8 * g + u_mine)) = wq;
+        }
+    }
+    if (h_last) {
+        float *hr = h_last + (tl.R0 + rsub) * tl.np + tl.I0;
+#pragma unroll
+        for (int e = 0; e < BM / 2; ++e) {
+            if (tl.R0 + 2 * e + rsub < tl.rlive)
+                hr[col] = __fadd_rn(__fmul_rn(hs[(2 * e + rsub) * HS + col], tl.scale), st.bi);
+            hr = next_rows(hr, 2 * tl.np);
+        }
+    }
+}
+
+__device__ __forceinline__ void state_store(const StateRegs &st, const Tile &tl, int t) {
+    const int col = t & (BN - 1);
+    const int rsub = __builtin_amdgcn_readfirstlane(t >> 7);
+    float *xr = tl.x + (tl.R0 + rsub) * tl.np + tl.I0;
+    float *mr = tl.m + (tl.R0 + rsub) * tl.np + tl.I0;
+#pragma unroll
+    for (int e = 0; e < BM / 2; ++e) {
+        if (tl.R0 + 2 * e + rsub < tl.rlive) {
+            xr[col] = st.xv[e];
+            mr[col] = st.mv[e];
+        }
+        xr = next_rows(xr, 2 * tl.np);
+        mr = next_rows(mr, 2 * tl.np);
+    }
+}
+
+// One PA step of one tile: matrix and state waves side by side.
+__device__ __forceinline__ void mfma_tile_step(uint8_t *lds, const Tile &tl,
+                                               const uint32_t *__restrict__ s_cur,
+                                               uint32_t *__restrict__ s_nxt,
+                                               float *__restrict__ h_last, float lt, float eta,
+                                               float alpha) {
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nchunk = (int)(tl.np / KC);
+    if (wave >= MW) {
+        const int t = tid - MW * 64;
+        StateRegs st;
+        state_load(st, tl, nchunk, t);
+        barrier();                                     // stages drained
+        barrier();                                     // field sums in LDS
+        state_collect(st);
+        state_update(st, tl, reinterpret_cast<const float *>(lds), s_nxt, h_last, t,
+                            wave, lane, lt, eta, alpha);
+        state_store(st, tl, t);
+        return;
+    }
+    matrix_step(lds, tl, nchunk, s_cur, wave, lane);
 }
 
 __global__ void __launch_bounds__(THREADS, 1) k_mfma_step(
@@ -255,8 +380,9 @@ __global__ void __launch_bounds__(THREADS, 1) k_mfma_step(
     float *__restrict__ m, float *__restrict__ h_last, int t, const float *__restrict__ lam,
     float eta, float alpha) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[LDS_BYTES];
-    mfma_tile_step(lds, np, Rp, (int64_t)blockIdx.x * BN, (int64_t)blockIdx.y * BM, rlive, Jb,
-                   b, sc->scale, s_cur, s_nxt, x, m, h_last, lam[t], eta, alpha);
+    const Tile tl{np, Rp, (int64_t)blockIdx.x * BN, (int64_t)blockIdx.y * BM, rlive, Jb, b,
+                  sc->scale, x, m};
+    mfma_tile_step(lds, tl, s_cur, s_nxt, h_last, lam[t], eta, alpha);
 }
 
 // Many instances in one launch: block k runs tile k of the table.  Each tile points at
@@ -265,26 +391,27 @@ __global__ void __launch_bounds__(THREADS, 1) k_mfma_grouped(const MfmaTile *__r
                                                              int t, const float *__restrict__ lam,
                                                              float eta, float alpha) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[LDS_BYTES];
-    const MfmaTile tl = tiles[blockIdx.x];
-    const uint32_t *cur = (t & 1) ? tl.s1 : tl.s0;
-    uint32_t *nxt = (t & 1) ? tl.s0 : tl.s1;
-    mfma_tile_step(lds, tl.np, tl.Rp, tl.I0, tl.R0, tl.rlive, tl.Jb, tl.b, tl.sc->scale, cur, nxt,
-                   tl.x, tl.m, nullptr, lam[t], eta, alpha);
+    const MfmaTile mt = tiles[blockIdx.x];
+    const uint32_t *cur = (t & 1) ? mt.s1 : mt.s0;
+    uint32_t *nxt = (t & 1) ? mt.s0 : mt.s1;
+    const Tile tl{mt.np, mt.Rp, mt.I0, mt.R0, mt.rlive, mt.Jb, mt.b, mt.sc->scale, mt.x, mt.m};
+    mfma_tile_step(lds, tl, cur, nxt, nullptr, lam[t], eta, alpha);
 }
 
-// Chunk-major sign bits of x: word (kc * Rp + r) * 4 + q, bit j = (x[r][128kc + 32q + j] < 0)
+// Pair words of the signs of x (layout above): one thread per word.
 __global__ void __launch_bounds__(256) k_mfma_pack(int64_t Rp, int64_t np,
                                                    const float *__restrict__ x,
-                                                   uint32_t *__restrict__ sbits) {
-    const int64_t words = np / 32;
-    const int64_t total = Rp * words;
+                                                   uint32_t *__restrict__ sw) {
+    const int64_t total = Rp * (np / 8);
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
          k += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = k / words, wd = k - r * words;
-        const float *xr = x + r * np + 32 * wd;
-        uint32_t bits = 0;
-        for (int j = 0; j < 32; ++j) bits |= (xr[j] < 0.0f ? 1u : 0u) << j;
-        sbits[((wd >> 2) * Rp + r) * 4 + (wd & 3)] = bits;
+        const int64_t kc = k / (Rp * 16), rem = k - kc * Rp * 16;
+        const int64_t r = rem / 16, wd = rem - r * 16;
+        const int64_t h = wd >> 3, q = wd & 7;
+        const float *xr = x + r * np + KC * kc + 16 * q + 8 * h;
+        uint32_t byte = 0;
+        for (int j = 0; j < 8; ++j) byte |= (xr[j] < 0.0f ? 1u : 0u) << j;
+        sw[k] = spin_pair(byte);
     }
 }
 
@@ -292,7 +419,7 @@ __global__ void __launch_bounds__(256) k_mfma_pack(int64_t Rp, int64_t np,
 
 hipError_t launch_mfma_pack_spins(int64_t Rp, int64_t np, const float *x, uint32_t *sbits,
                                   hipStream_t st) {
-    int64_t total = Rp * (np / 32);
+    int64_t total = Rp * (np / 8);
     int64_t g = (total + 255) / 256;
     if (g > 65536) g = 65536;
     k_mfma_pack<<<(unsigned)g, 256, 0, st>>>(Rp, np, x, sbits);
@@ -320,7 +447,8 @@ hipError_t launch_mfma_grouped(const MfmaTile *tiles, int32_t ntiles, int32_t t,
 
 
 // Dense BF16 copy of a CSR instance: Jb[i][j] = bf16(w_ij * 2^-e) for the stored
-// off-diagonal entries (zero elsewhere; the caller clears Jb first).
+// off-diagonal entries (zero elsewhere; the caller clears Jb first).  One wave per row,
+// the row's entries split over the lanes.
 template <typename TW, typename TI>
 __global__ void __launch_bounds__(256) k_csr_to_bf16(int64_t n, int64_t np,
                                                      const int32_t *__restrict__ rp,
@@ -329,15 +457,15 @@ __global__ void __launch_bounds__(256) k_csr_to_bf16(int64_t n, int64_t np,
                                                      const CanonScalars *__restrict__ sc,
                                                      uint16_t *__restrict__ Jb) {
     const float inv = sc->inv_scale;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
-            const int64_t j = (int64_t)col[k];
-            if (j == i) continue;
-            uint32_t u = __float_as_uint(__fmul_rn((float)w[k], inv));
-            u += 0x7fffu + ((u >> 16) & 1u);
-            Jb[i * np + j] = (uint16_t)(u >> 16);
-        }
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= n) return;
+    for (int64_t k = rp[i] + lane; k < rp[i + 1]; k += 64) {
+        const int64_t j = (int64_t)col[k];
+        if (j == i) continue;
+        uint32_t u = __float_as_uint(__fmul_rn((float)w[k], inv));
+        u += 0x7fffu + ((u >> 16) & 1u);
+        Jb[i * np + j] = (uint16_t)(u >> 16);
     }
 }
 
@@ -345,7 +473,7 @@ hipError_t launch_csr_to_bf16(const qpa_problem &p, int64_t np, const CanonScala
                               uint16_t *Jb, hipStream_t st) {
     hipError_t e = hipMemsetAsync(Jb, 0, sizeof(uint16_t) * (size_t)(np * np), st);
     if (e != hipSuccess) return e;
-    int64_t g = (p.n + 255) / 256;
+    const int64_t g = (p.n + 3) / 4;
     auto run = [&](auto wtag, auto itag) {
         using TW = decltype(wtag);
         using TI = decltype(itag);

@@ -2,6 +2,8 @@
 // state layout copies, exact energies (eq. (1) / eq. (2)) and best-of-replica.
 #include "qpa_internal.h"
 
+#include <type_traits>
+
 #include <math.h>
 
 namespace qpa {
@@ -252,6 +254,85 @@ __global__ void __launch_bounds__(256) k_csr_rows(int64_t n, int64_t nnz,
     if (flags) atomicOr(&sc->flags, flags);
 }
 
+// Integer CSR rows with many entries: one wave per row, the row's entries split over the
+// lanes (the symmetric-partner searches run in parallel).  Outputs as k_csr_rows; every
+// sum is an exact integer, so the order of the reduction does not matter.
+template <typename TW, typename TI>
+__global__ void __launch_bounds__(256) k_csr_rows_wave(int64_t n, int64_t nnz,
+                                                       const int32_t *__restrict__ rp,
+                                                       const TI *__restrict__ col,
+                                                       const TW *__restrict__ w, const void *lin,
+                                                       int32_t lin_dt, int32_t is_qubo,
+                                                       float *__restrict__ b_f32,
+                                                       int64_t *__restrict__ b_i64,
+                                                       double *__restrict__ b_f64,
+                                                       double *__restrict__ row_abs,
+                                                       double *__restrict__ row_max,
+                                                       double *__restrict__ row_k,
+                                                       CanonScalars *sc) {
+    const int lane = threadIdx.x % WAVE;
+    const int64_t i = (int64_t)blockIdx.x * (256 / WAVE) + threadIdx.x / WAVE;
+    if (i >= n) return;                        // uniform per wave
+    int32_t flags = 0;
+    const int64_t k0 = rp[i], k1 = rp[i + 1];
+    if (i == 0 && k0 != 0) flags |= FLAG_SHAPE;
+    if (i == n - 1 && k1 != nnz) flags |= FLAG_SHAPE;
+    int64_t sum = 0, sabs = 0, diag = 0, smax = 0;
+    if (k0 > k1 || k0 < 0 || k1 > nnz) {
+        flags |= FLAG_SHAPE;
+    } else {
+        for (int64_t k = k0 + lane; k < k1; k += WAVE) {
+            const int64_t j = (int64_t)col[k];
+            const int64_t v = (int64_t)w[k];
+            if (j < 0 || j >= n) {
+                flags |= FLAG_SHAPE;
+                continue;
+            }
+            if (k > k0 && (int64_t)col[k - 1] >= j) flags |= FLAG_UNSORTED;
+            sum += v;
+            if (j == i) {
+                diag += v;
+                if (!is_qubo) flags |= FLAG_ASYM;
+                continue;
+            }
+            const int64_t av = v < 0 ? -v : v;
+            sabs += av;
+            smax = av > smax ? av : smax;
+            int64_t lo = rp[j], hi = rp[j + 1] - 1;
+            bool found = false;
+            while (lo <= hi && lo >= 0 && hi < nnz) {
+                const int64_t mid = (lo + hi) >> 1;
+                const int64_t cm = (int64_t)col[mid];
+                if (cm == i) {
+                    found = ((int64_t)w[mid] == v);
+                    break;
+                }
+                if (cm < i) lo = mid + 1;
+                else hi = mid - 1;
+            }
+            if (!found) flags |= FLAG_ASYM;
+        }
+    }
+    sum = wave_sum_i64(sum);
+    sabs = wave_sum_i64(sabs);
+    diag = wave_sum_i64(diag);
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+        const int64_t other = __shfl_xor(smax, o);
+        smax = other > smax ? other : smax;
+        flags |= __shfl_xor(flags, o);
+    }
+    if (lane != 0) return;
+    const double c = lin ? load_as_double(lin, lin_dt, i) : 0.0;
+    const double bx = (is_qubo ? (double)sum : 0.0) + c;
+    b_f32[i] = (float)bx;
+    if (b_i64) b_i64[i] = (int64_t)bx;
+    b_f64[i] = bx;
+    row_abs[i] = (double)sabs + fabs(bx);
+    if (row_max) row_max[i] = (double)smax;
+    row_k[i] = is_qubo ? ((double)sum + (double)diag + 2.0 * c) : 0.0;
+    if (flags) atomicOr(&sc->flags, flags);
+}
+
 // ------------------------------------------------------------------ initial state
 // Replica r, variable i: u = top 24 bits of SplitMix64 output number r*n + i + 1.
 __device__ __forceinline__ uint64_t splitmix_output(uint64_t seed, uint64_t k) {
@@ -463,6 +544,59 @@ __global__ void __launch_bounds__(256) k_energy_csr(int64_t n, const int32_t *__
     }
 }
 
+// CSR, integer couplings, rows with many entries: one wave per row, the row's entries
+// split over the lanes; replicas r0 .. r0+ER.  Same partial sums as k_energy_csr (each
+// pair once, exact integers), with 4 rows per block.
+template <typename TW, typename TI>
+__global__ void __launch_bounds__(256) k_energy_csr_wave(int64_t n,
+                                                         const int32_t *__restrict__ rp,
+                                                         const TI *__restrict__ col,
+                                                         const TW *__restrict__ w,
+                                                         const int64_t *__restrict__ b_i64,
+                                                         const int8_t *__restrict__ s, int64_t R,
+                                                         double *__restrict__ partial) {
+    const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+    const int64_t i = (int64_t)blockIdx.x * (256 / WAVE) + wv;
+    const int64_t r0 = (int64_t)blockIdx.y * ER;
+    __shared__ double red[256 / WAVE][ER];
+    int64_t di[ER];
+#pragma unroll
+    for (int q = 0; q < ER; ++q) di[q] = 0;
+    if (i < n) {
+        const int64_t k1 = rp[i + 1];
+        for (int64_t k = rp[i] + lane; k < k1; k += WAVE) {
+            const int64_t j = (int64_t)col[k];
+            if (j <= i) continue;                 // each pair once
+            const int64_t wk = (int64_t)w[k];
+#pragma unroll
+            for (int q = 0; q < ER; ++q) {
+                const int64_t r = r0 + q < R ? r0 + q : R - 1;
+                di[q] += (s[r * n + j] > 0) ? wk : -wk;
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < ER; ++q) {
+        const int64_t d = wave_sum_i64(di[q]);
+        if (lane == 0) {
+            double v = 0.0;
+            const int64_t r = r0 + q;
+            if (i < n && r < R) v = (double)s[r * n + i] * ((double)d + (double)b_i64[i]);
+            red[wv][q] = v;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < ER) {
+        const int q = threadIdx.x;
+        const int64_t r = r0 + q;
+        if (r < R) {
+            double v = 0.0;
+            for (int k = 0; k < 256 / WAVE; ++k) v += red[k][q];
+            partial[(int64_t)blockIdx.x * R + r] = v;
+        }
+    }
+}
+
 // energy[r] = sum over blocks of partial[b][r] (fixed order), then the QUBO constant.
 // For integer instances the partials are exact integers (< 2^53) and the total is taken
 // in int64.
@@ -588,10 +722,16 @@ hipError_t launch_canon_csr(const qpa_problem &p, float *b_f32, int64_t *b_i64, 
     auto run = [&](auto wtag, auto itag) {
         using TW = decltype(wtag);
         using TI = decltype(itag);
-        k_csr_rows<TW, TI><<<grid1(n, 256, INT64_MAX), 256, 0, st>>>(
-            n, p.nnz, p.row_ptr, static_cast<const TI *>(p.col),
-            static_cast<const TW *>(p.weights), p.linear, p.linear_dtype, is_qubo, b_f32, b_i64,
-            b_f64, row_abs, row_max, row_k, sc);
+        if (csr_rows_by_wave(p) && !std::is_floating_point<TW>::value)
+            k_csr_rows_wave<TW, TI><<<(unsigned)((n + 3) / 4), 256, 0, st>>>(
+                n, p.nnz, p.row_ptr, static_cast<const TI *>(p.col),
+                static_cast<const TW *>(p.weights), p.linear, p.linear_dtype, is_qubo, b_f32,
+                b_i64, b_f64, row_abs, row_max, row_k, sc);
+        else
+            k_csr_rows<TW, TI><<<grid1(n, 256, INT64_MAX), 256, 0, st>>>(
+                n, p.nnz, p.row_ptr, static_cast<const TI *>(p.col),
+                static_cast<const TW *>(p.weights), p.linear, p.linear_dtype, is_qubo, b_f32,
+                b_i64, b_f64, row_abs, row_max, row_k, sc);
         k_canon_finalize<<<1, 1024, 0, st>>>(n, row_abs, row_max, row_k, is_int, sc);
         return hipGetLastError();
     };
@@ -625,8 +765,17 @@ hipError_t launch_export_spins(int64_t n, int64_t R, const float *x, int64_t ld_
     return hipGetLastError();
 }
 
+// Integer CSR instances averaging 16 or more entries per row take the wave-per-row
+// kernels.
+bool csr_rows_by_wave(const qpa_problem &p) {
+    const bool is_int = dtype_is_int(p.coupling_dtype) &&
+                        (p.linear == nullptr || dtype_is_int(p.linear_dtype));
+    return p.format == QPA_FMT_CSR && is_int && p.nnz >= 16 * p.n;
+}
+
 int64_t energy_partial_blocks(const qpa_problem &p) {
     if (p.format == QPA_FMT_DENSE) return (p.n + 15) / 16;
+    if (csr_rows_by_wave(p)) return (p.n + 3) / 4;
     return (p.n + 255) / 256;
 }
 
@@ -662,7 +811,10 @@ hipError_t launch_energy(const qpa_problem &p, const int64_t *b_i64, const doubl
             using TI = decltype(itag);
             const TW *w = static_cast<const TW *>(p.weights);
             const TI *c = static_cast<const TI *>(p.col);
-            if (is_int)
+            if (csr_rows_by_wave(p))
+                k_energy_csr_wave<TW, TI><<<dim3((unsigned)nblk, gy), 256, 0, st>>>(
+                    n, p.row_ptr, c, w, b_i64, spins, R, partial);
+            else if (is_int)
                 k_energy_csr<TW, TI, true><<<dim3((unsigned)nblk, gy), 256, 0, st>>>(
                     n, p.row_ptr, c, w, b_i64, b_f64, spins, R, partial);
             else

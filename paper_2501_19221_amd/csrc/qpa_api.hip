@@ -14,7 +14,7 @@ struct qpa_ctx {
     int device = 0;
     int cus = 256;                          // compute units of the device
     std::string err;
-    int32_t *host_flags = nullptr;          // pinned, for the validation read-back
+    int32_t *host_flags = nullptr;          // pinned, for device status read-backs
     qpa::CanonScalars *host_sc = nullptr;   // pinned
     float *host_lam = nullptr;              // pinned schedule staging
     size_t host_lam_cap = 0;
@@ -134,7 +134,7 @@ Plan make_plan(const qpa_problem &p, const qpa_params &a, int64_t batch_rp = 0, 
     switch (pl.path) {
         case Path::DenseResident: sbytes = 0; break;
         case Path::DenseTiled: sbytes = sizeof(float) * R * n; break;
-        case Path::DenseMfma: sbytes = sizeof(uint32_t) * Rp * (np / 32); break;
+        case Path::DenseMfma: sbytes = sizeof(uint32_t) * Rp * (np / 8); break;
         case Path::Csr: sbytes = sizeof(uint64_t) * (size_t)(Rp / pl.G) * (size_t)pl.nwords; break;
         case Path::CsrResident: sbytes = 0; break;
     }
@@ -309,29 +309,30 @@ hipError_t take_event(qpa_ctx *ctx, hipEvent_t *ev) {
 
 qpa_status run_steps_inner(qpa_ctx *ctx, const qpa_problem &p, const qpa_params &a,
                            const Plan &pl, void *ws, int32_t t0, int32_t t1, bool want_h,
-                           hipStream_t st, int64_t &launches);
+                           hipStream_t st, int64_t &launches, int32_t &ran);
 
 // Run steps t0 .. t1-1 on the internal state of the plan (timed when profiling).
 qpa_status run_steps(qpa_ctx *ctx, const qpa_problem &p, const qpa_params &a, const Plan &pl,
                      void *ws, int32_t t0, int32_t t1, bool want_h, hipStream_t st) {
     if (t1 <= t0) return QPA_OK;
     int64_t launches = 0;
-    if (!ctx->prof) return run_steps_inner(ctx, p, a, pl, ws, t0, t1, want_h, st, launches);
+    int32_t ran = path_code(pl.path);
+    if (!ctx->prof) return run_steps_inner(ctx, p, a, pl, ws, t0, t1, want_h, st, launches, ran);
     qpa_ctx::Span sp{};
     QPA_HIP(take_event(ctx, &sp.a));
     QPA_HIP(take_event(ctx, &sp.b));
     QPA_HIP(hipEventRecord(sp.a, st));
-    qpa_status s = run_steps_inner(ctx, p, a, pl, ws, t0, t1, want_h, st, launches);
+    qpa_status s = run_steps_inner(ctx, p, a, pl, ws, t0, t1, want_h, st, launches, ran);
     QPA_HIP(hipEventRecord(sp.b, st));
     sp.launches = launches;
-    sp.path = path_code(pl.path);
+    sp.path = ran;
     ctx->spans.push_back(sp);
     return s;
 }
 
 qpa_status run_steps_inner(qpa_ctx *ctx, const qpa_problem &p, const qpa_params &a,
                            const Plan &pl, void *ws, int32_t t0, int32_t t1, bool want_h,
-                           hipStream_t st, int64_t &launches) {
+                           hipStream_t st, int64_t &launches, int32_t &ran) {
     float *x = at<float>(ws, pl.o_x), *m = at<float>(ws, pl.o_m);
     float *h = want_h ? at<float>(ws, pl.o_h) : nullptr;
     const float *lam = at<float>(ws, pl.o_lam);
@@ -358,6 +359,7 @@ qpa_status run_steps_inner(qpa_ctx *ctx, const qpa_problem &p, const qpa_params 
             uint32_t *s0 = at<uint32_t>(ws, pl.o_s0), *s1 = at<uint32_t>(ws, pl.o_s1);
             QPA_HIP(launch_mfma_pack_spins(pl.Rp, pl.np, x, s0, st));
             launches = t1 - t0;
+            ran = QPA_PATH_DENSE_MFMA;
             const CanonScalars *sc = at<CanonScalars>(ws, pl.o_sc);
             for (int32_t t = t0; t < t1; ++t) {
                 QPA_HIP(launch_mfma_step(pl.Rp, pl.np, pl.R, at<uint16_t>(ws, pl.o_Jb), bf, sc,
@@ -538,8 +540,8 @@ qpa_status make_batch_plan(qpa_ctx *ctx, int32_t count, const qpa_problem *probs
             ds.o_bfp = tk(sizeof(float) * (size_t)np);
             ds.o_x = tk(sizeof(float) * (size_t)(Rp * np));
             ds.o_m = tk(sizeof(float) * (size_t)(Rp * np));
-            ds.o_s0 = tk(sizeof(uint32_t) * (size_t)(Rp * np / 32));
-            ds.o_s1 = tk(sizeof(uint32_t) * (size_t)(Rp * np / 32));
+            ds.o_s0 = tk(sizeof(uint32_t) * (size_t)(Rp * np / 8));
+            ds.o_s1 = tk(sizeof(uint32_t) * (size_t)(Rp * np / 8));
             bp.ntiles_max += (int32_t)((np / MF_BN) * (Rp / MF_BM));
         }
         bp.dense.push_back(ds);
@@ -582,7 +584,10 @@ qpa_status qpa_create(qpa_ctx **out, int device) {
     (void)hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, device);
     if (c->cus < 1) c->cus = 1;
     e = hipHostMalloc((void **)&c->host_sc, sizeof(CanonScalars), hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&c->host_flags, sizeof(int32_t) * 4, hipHostMallocDefault);
     if (e != hipSuccess) {
+        if (c->host_sc) (void)hipHostFree(c->host_sc);
         delete c;
         return fail(nullptr, QPA_E_DEVICE, "hipHostMalloc failed: %s", hipGetErrorString(e));
     }
@@ -593,6 +598,7 @@ qpa_status qpa_create(qpa_ctx **out, int device) {
 void qpa_destroy(qpa_ctx *ctx) {
     if (!ctx) return;
     if (ctx->host_sc) (void)hipHostFree(ctx->host_sc);
+    if (ctx->host_flags) (void)hipHostFree(ctx->host_flags);
     if (ctx->host_lam) (void)hipHostFree(ctx->host_lam);
     for (auto &sp : ctx->spans) {
         (void)hipEventDestroy(sp.a);

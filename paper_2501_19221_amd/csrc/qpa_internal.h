@@ -77,6 +77,9 @@ hipError_t launch_export_spins(int64_t n, int64_t R, const float *x, int64_t ld_
 // Integer: e_i64[r] = objective (and e_f64 = (double)e_i64).  Float: e_f64 only.
 // words: scratch of ceil(R/64) * n uint64 (dense problems only).
 int64_t energy_partial_blocks(const qpa_problem &p);
+// Integer CSR instances with many entries per row run their row scan and energies with
+// one wave per row.
+bool csr_rows_by_wave(const qpa_problem &p);
 hipError_t launch_energy(const qpa_problem &p, const int64_t *b_i64, const double *b_f64,
                          const CanonScalars *sc, const int8_t *spins, int64_t R,
                          int64_t *e_i64, double *e_f64, double *partial, int64_t partial_len,
@@ -102,8 +105,7 @@ hipError_t launch_dense_tiled_step(int64_t n, int64_t R, const float *J, const f
 hipError_t launch_sign_f32(int64_t count, const float *x, float *s, hipStream_t st);
 
 // BF16 matrix-core path.  Internal padded layout: x, m [Rp][np] FP32, Jb [np][np] bf16,
-// spin bits Rp * np / 32 uint32 in chunk-major order: word (kc * Rp + r) * 4 + q, bit j
-// <=> variable 128 kc + 32 q + j of replica r is -1.
+// spins Rp * np / 8 uint32 "pair words" (see the step kernel), chunk-major.
 constexpr int MF_BM = 128;   // replicas per tile
 constexpr int MF_BN = 128;   // variables per tile
 constexpr int MF_NPAD = 128; // np is a multiple of this (the reduction chunk)
