@@ -2,17 +2,18 @@
 // couplings stored as bf16(J / 2^e), FP32 accumulation, result scaled back by 2^e).
 //
 // One launch advances every replica by one step.  A workgroup owns an output tile of
-// 128 replicas x 128 variables and has two kinds of waves:
-//   * 4 matrix waves in a 2 x 2 arrangement: wave (wr, wc) accumulates replicas
-//     64wr .. 64wr+63 against variables 64wc .. 64wc+63 (2 x 2 accumulators of 32 x 32)
-//     over the whole reduction, walked in chunks of 128 variables;
-//   * 4 state waves: they load the tile's x and m into registers when the launch starts,
-//     so that this traffic overlaps the reduction, then wait for the field and run the
-//     PA update and write x, m and the new sign bits.
+// 128 replicas x 128 variables and has 16 waves, four per SIMD:
+//   * 8 matrix waves: a 2 x 2 arrangement of 64 x 64 sub-tiles, each worked on by two
+//     waves that split every chunk's eight k steps between them (steps 0..3 and 4..7),
+//     so that every SIMD runs two matrix waves whose instruction streams interleave (one
+//     wave alone cannot issue its operand expansion while its matrix ops run); each wave
+//     keeps 2 x 2 accumulators of 32 x 32 and the two halves are summed in LDS at the end;
+//   * 8 state waves: they load the tile's x and m into registers while the reduction
+//     runs, then wait for the field and run the PA update and write x, m and the spins.
 // Chunks are staged through LDS with direct global->LDS loads issued by the matrix waves
 // only (NST stages, NST-1 chunks in flight): per chunk the 128 x 128 bf16 block of J
-// (8 loads of 16 bytes per lane and wave, each filling 4 rows of 256 bytes) and the spins
-// of the tile's 128 replicas for those 128 variables (2 loads of 16 bytes per lane and
+// (4 loads of 16 bytes per lane and wave, each filling 4 rows of 256 bytes) and the spins
+// of the tile's 128 replicas for those 128 variables (1 load of 16 bytes per lane and
 // wave, 64 bytes per replica).
 // Inside a J row the sixteen 16-byte pieces sit at position piece ^ (row % 16), and inside
 // a replica's 64 spin bytes the four 16-byte pieces at (piece + row / 4) % 4, so that the
@@ -52,8 +53,9 @@ constexpr int STG = JSTG + SSTG;
 constexpr int NST = 4;                       // stages
 constexpr int LDS_BYTES = NST * STG;
 constexpr int HS = BN + 8;                   // row stride of the field handoff (floats)
-constexpr int THREADS = 512;                 // 4 matrix waves + 4 state waves
-constexpr int MW = 4;                        // matrix waves
+constexpr int THREADS = 1024;                // 8 matrix waves + 8 state waves
+constexpr int MW = 8;                        // matrix waves
+constexpr int SR = BM / 4;                   // rows per state thread
 static_assert(LDS_BYTES >= BM * HS * 4, "the field handoff reuses the stages");
 static_assert(LDS_BYTES <= 160 * 1024, "LDS of one workgroup");
 static_assert(MF_NPAD % KC == 0, "np must be a multiple of the chunk");
@@ -108,7 +110,7 @@ template <int N> __device__ __forceinline__ void wait_barrier() {
     asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(N) : "memory");
 }
 
-constexpr int LOADS_PER_CHUNK = 10;          // per matrix wave: 8 J pieces + 2 spin dwords
+constexpr int LOADS_PER_CHUNK = 5;           // per matrix wave: 4 J pieces + 1 spin piece
 
 // The tile of a workgroup: replicas R0 .. R0+127 (rows at or past `rlive` are padding:
 // their state is neither read nor written and they report +1 spins), variables
@@ -129,36 +131,32 @@ __device__ __forceinline__ void matrix_step(uint8_t *lds, const Tile &tl, int nc
     const int64_t np = tl.np, I0 = tl.I0, R0 = tl.R0;
     const uint16_t *__restrict__ Jb = tl.Jb;
     float *hs = reinterpret_cast<float *>(lds);
-    const int wr = wave >> 1, wc = wave & 1;
+    const int kh = wave >> 2;                      // k steps 4 kh .. 4 kh + 3 of a chunk
+    const int wr = (wave >> 1) & 1, wc = wave & 1;
     const int half = lane >> 5, l32 = lane & 31;
-    // J: load u (0..7) of wave w fills LDS rows 32w + 4u + lane/16 at position lane % 16,
+    // J: load u (0..3) of wave w fills LDS rows 16w + 4u + lane/16 at position lane % 16,
     // which holds piece (lane % 16) ^ (row % 16) of that row.
-    const uint16_t *gJ[8];
+    const uint16_t *gJ[4];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        const int row = 32 * wave + 4 * u + (lane >> 4);
+    for (int u = 0; u < 4; ++u) {
+        const int row = 16 * wave + 4 * u + (lane >> 4);
         gJ[u] = Jb + (I0 + row) * np + 8 * ((lane & 15) ^ (row & 15));
     }
-    // spins: load e (0..1) of wave w fills bytes 2048w + 1024e + 16 lane of the 8 KiB
-    // block of the tile's replicas (64 bytes per replica, in replica order): row
-    // 32w + 16e + lane/4, position lane % 4, which holds piece (lane - row / 4) % 4
-    const int srow0 = 32 * wave + (lane >> 2);      // row for e = 0; e adds 16 (4 to row/4)
-    const uint32_t *gS = s_cur + (R0 + srow0) * 16 + 4 * (((lane & 3) - (srow0 >> 2)) & 3);
-    const uint32_t *gS1 = s_cur + (R0 + srow0 + 16) * 16 +
-                          4 * (((lane & 3) - ((srow0 + 16) >> 2)) & 3);
+    // spins: the load of wave w fills bytes 1024w + 16 lane of the 8 KiB block of the
+    // tile's replicas (64 bytes per replica, in replica order): row 16w + lane/4,
+    // position lane % 4, which holds piece (lane - row / 4) % 4
+    const int srow = 16 * wave + (lane >> 2);
+    const uint32_t *gS = s_cur + (R0 + srow) * 16 + 4 * (((lane & 3) - (srow >> 2)) & 3);
     const int64_t sstride = tl.Rp * 16;            // u32 words between consecutive chunks
     auto stage = [&](int kc, int st) {
         kc = kc < nchunk ? kc : nchunk - 1;        // past the end: reload the last chunk
         uint8_t *dst = lds + st * STG;
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+        for (int u = 0; u < 4; ++u)
             __builtin_amdgcn_global_load_lds(gJ[u] + (int64_t)kc * KC,
-                                             (lds_void *)(dst + (8 * wave + u) * 1024), 16, 0, 0);
+                                             (lds_void *)(dst + (4 * wave + u) * 1024), 16, 0, 0);
         __builtin_amdgcn_global_load_lds(gS + (int64_t)kc * sstride,
-                                         (lds_void *)(dst + JSTG + 2048 * wave), 16, 0, 0);
-        __builtin_amdgcn_global_load_lds(gS1 + (int64_t)kc * sstride,
-                                         (lds_void *)(dst + JSTG + 2048 * wave + 1024), 16, 0,
-                                         0);
+                                         (lds_void *)(dst + JSTG + 1024 * wave), 16, 0, 0);
     };
 
     const uint32_t sign_mask = __builtin_amdgcn_readfirstlane(0x80008000u) + 0u * lane;
@@ -179,18 +177,18 @@ __device__ __forceinline__ void matrix_step(uint8_t *lds, const Tile &tl, int nc
         wait_barrier<(NST - 2) * LOADS_PER_CHUNK>();
         stage(c + NST - 1, (c + NST - 1) % NST);
         const uint8_t *src = lds + (c % NST) * STG;
-        // this lane's 8 pair words (k steps 0..7 of its half) for each replica fragment
-        u32x4 sw[2][2];
+        // this lane's 4 pair words (k steps 4 kh .. 4 kh + 3 of its half) per replica
+        // fragment: piece 2 half + kh of the replica's 64 bytes
+        u32x4 sw[2];
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 2; ++i) {
+            const int row = 64 * wr + 32 * i + l32;
+            const int pos = (2 * half + kh + (row >> 2)) & 3;
+            sw[i] = *reinterpret_cast<const u32x4 *>(src + JSTG + 64 * row + 16 * pos);
+        }
 #pragma unroll
-            for (int hh = 0; hh < 2; ++hh) {
-                const int row = 64 * wr + 32 * i + l32;
-                const int pos = (2 * half + hh + (row >> 2)) & 3;
-                sw[i][hh] = *reinterpret_cast<const u32x4 *>(src + JSTG + 64 * row + 16 * pos);
-            }
-#pragma unroll
-        for (int q = 0; q < KC / 16; ++q) {
+        for (int qq = 0; qq < 4; ++qq) {
+            const int q = 4 * kh + qq;
             u32x4 bq[2];
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
@@ -200,8 +198,7 @@ __device__ __forceinline__ void matrix_step(uint8_t *lds, const Tile &tl, int nc
             }
             bf16x8 a[2];
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
-                a[i] = expand_spins(sw[i][q >> 2][q & 3], sign_mask);
+            for (int i = 0; i < 2; ++i) a[i] = expand_spins(sw[i][qq], sign_mask);
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -212,20 +209,27 @@ __device__ __forceinline__ void matrix_step(uint8_t *lds, const Tile &tl, int nc
     }
     wait_barrier<0>();     // the trailing (redundant) loads have landed in every wave and
                            // every stage read is done: the stages can take the sums
+    // the first k half stores its sums, the second adds its own
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int pass = 0; pass < 2; ++pass) {
+        if (kh == pass) {
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+            for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int row = 64 * wr + 32 * i + 8 * (v >> 2) + 4 * half + (v & 3);
-                const int col = 64 * wc + 32 * j + l32;
-                hs[row * HS + col] = acc[i][j][v];
-            }
-    wait_barrier<0>();     // field sums visible to the state waves
+                for (int j = 0; j < 2; ++j)
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) {
+                        const int row = 64 * wr + 32 * i + 8 * (v >> 2) + 4 * half + (v & 3);
+                        const int col = 64 * wc + 32 * j + l32;
+                        float *hp = hs + row * HS + col;
+                        *hp = pass == 0 ? acc[i][j][v] : *hp + acc[i][j][v];
+                    }
+        }
+        wait_barrier<0>();  // pass 0: partial sums stored; pass 1: field sums complete
+    }
 }
 
-// ---- state waves: thread t (0..255) owns column t % 128 of rows 2e + t / 128 ---------
+// ---- state waves: thread t (0..511) owns column t % 128 of rows 4e + t / 128 ---------
 // Row pointers are wave-uniform and advanced one row pair at a time through an opaque
 // step, so that the compiler computes each address when it is used instead of holding
 // all 64 in scalar registers.
@@ -236,7 +240,7 @@ template <typename P> __device__ __forceinline__ P *next_rows(P *p, int64_t stri
 }
 
 struct StateRegs {
-    float xv[BM / 2], mv[BM / 2];
+    float xv[SR], mv[SR];
     float bi;
 };
 
@@ -249,20 +253,20 @@ struct StateRegs {
 __device__ __forceinline__ void state_load(StateRegs &st, const Tile &tl, int nchunk, int t) {
     const int col = t & (BN - 1);
     const int rsub = __builtin_amdgcn_readfirstlane(t >> 7);
-    const int per = (BM / 2 + nchunk - 1) / nchunk;
+    const int per = (SR + nchunk - 1) / nchunk;
     const float *xr = tl.x + (tl.R0 + rsub) * tl.np + tl.I0;
     const float *mr = tl.m + (tl.R0 + rsub) * tl.np + tl.I0;
     int passed = 0;
 #pragma unroll
-    for (int e = 0; e < BM / 2; ++e) {
+    for (int e = 0; e < SR; ++e) {
         if (e > 0 && e % per == 0 && passed < nchunk) {
             barrier();
             ++passed;
         }
         st.xv[e] = xr[col];
         st.mv[e] = mr[col];
-        xr = next_rows(xr, 2 * tl.np);
-        mr = next_rows(mr, 2 * tl.np);
+        xr = next_rows(xr, 4 * tl.np);
+        mr = next_rows(mr, 4 * tl.np);
     }
     st.bi = tl.b[tl.I0 + col];
     for (; passed < nchunk; ++passed) barrier();   // the remaining chunks
@@ -271,7 +275,7 @@ __device__ __forceinline__ void state_load(StateRegs &st, const Tile &tl, int nc
 // Waits for the loads of state_load, once, so that later stores wait for nothing.
 __device__ __forceinline__ void state_collect(StateRegs &st) {
 #pragma unroll
-    for (int e = 0; e < BM / 2; ++e) asm volatile("" ::"v"(st.xv[e]), "v"(st.mv[e]));
+    for (int e = 0; e < SR; ++e) asm volatile("" ::"v"(st.xv[e]), "v"(st.mv[e]));
     asm volatile("" ::"v"(st.bi));
 }
 
@@ -288,17 +292,17 @@ __device__ __forceinline__ void state_update(StateRegs &st, const Tile &tl, cons
     const int col = t & (BN - 1);
     const int rsub = __builtin_amdgcn_readfirstlane(t >> 7);
     const int u_mine = (lane >> 1) & 7;
-    uint64_t mine[BM / 16];
+    uint64_t mine[SR / 8];
 #pragma unroll
-    for (int g = 0; g < BM / 16; ++g) {
+    for (int g = 0; g < SR / 8; ++g) {
         float hv[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) hv[u] = hs[(2 * (8 * g + u) + rsub) * HS + col];
+        for (int u = 0; u < 8; ++u) hv[u] = hs[(4 * (8 * g + u) + rsub) * HS + col];
         uint64_t bal[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int e = 8 * g + u;
-            const bool live = tl.R0 + 2 * e + rsub < tl.rlive;      // uniform per wave
+            const bool live = tl.R0 + 4 * e + rsub < tl.rlive;      // uniform per wave
             const float h = __fadd_rn(__fmul_rn(hv[u], tl.scale), st.bi);
             pa_update(h, lt, eta, alpha, st.xv[e], st.mv[e]);
             bal[u] = __ballot(live && st.xv[e] < 0.0f);
@@ -314,21 +318,21 @@ __device__ __forceinline__ void state_update(StateRegs &st, const Tile &tl, cons
         const int ln = lane & 1;
         uint32_t *wrow = s_nxt + ((tl.I0 / KC) * tl.Rp + tl.R0 + rsub) * 16 + 4 * c2 + 8 * ln;
 #pragma unroll
-        for (int g = 0; g < BM / 16; ++g) {
+        for (int g = 0; g < SR / 8; ++g) {
             u32x4 wq;
 #pragma unroll
             for (int k = 0; k < 4; ++k)
                 wq[k] = spin_pair((uint32_t)(mine[g] >> (8 * (2 * k + ln))) & 0xFFu);
-            *reinterpret_cast<u32x4 *>(wrow + 32 * (8 * g + u_mine)) = wq;
+            *reinterpret_cast<u32x4 *>(wrow + 64 * (8 * g + u_mine)) = wq;
         }
     }
     if (h_last) {
         float *hr = h_last + (tl.R0 + rsub) * tl.np + tl.I0;
 #pragma unroll
-        for (int e = 0; e < BM / 2; ++e) {
-            if (tl.R0 + 2 * e + rsub < tl.rlive)
-                hr[col] = __fadd_rn(__fmul_rn(hs[(2 * e + rsub) * HS + col], tl.scale), st.bi);
-            hr = next_rows(hr, 2 * tl.np);
+        for (int e = 0; e < SR; ++e) {
+            if (tl.R0 + 4 * e + rsub < tl.rlive)
+                hr[col] = __fadd_rn(__fmul_rn(hs[(4 * e + rsub) * HS + col], tl.scale), st.bi);
+            hr = next_rows(hr, 4 * tl.np);
         }
     }
 }
@@ -339,13 +343,13 @@ __device__ __forceinline__ void state_store(const StateRegs &st, const Tile &tl,
     float *xr = tl.x + (tl.R0 + rsub) * tl.np + tl.I0;
     float *mr = tl.m + (tl.R0 + rsub) * tl.np + tl.I0;
 #pragma unroll
-    for (int e = 0; e < BM / 2; ++e) {
-        if (tl.R0 + 2 * e + rsub < tl.rlive) {
+    for (int e = 0; e < SR; ++e) {
+        if (tl.R0 + 4 * e + rsub < tl.rlive) {
             xr[col] = st.xv[e];
             mr[col] = st.mv[e];
         }
-        xr = next_rows(xr, 2 * tl.np);
-        mr = next_rows(mr, 2 * tl.np);
+        xr = next_rows(xr, 4 * tl.np);
+        mr = next_rows(mr, 4 * tl.np);
     }
 }
 
@@ -363,6 +367,7 @@ __device__ __forceinline__ void mfma_tile_step(uint8_t *lds, const Tile &tl,
         StateRegs st;
         state_load(st, tl, nchunk, t);
         barrier();                                     // stages drained
+        barrier();                                     // partial sums stored
         barrier();                                     // field sums in LDS
         state_collect(st);
         state_update(st, tl, reinterpret_cast<const float *>(lds), s_nxt, h_last, t,
