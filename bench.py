@@ -44,7 +44,43 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32-form", action="store_true")
     ap.add_argument("--no-measured-peaks", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy 1 GiB device to device 4 times (the reference kernel for "
+                         "scaling the HBM byte counters) and exit")
     return ap.parse_args()
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of the dominant kernel, from the committed rocprofv3 counter
+    table (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when the table has no
+    entry for it or the kernel's sources changed since the counters were taken."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    try:
+        with open(os.path.join(root, "profiles", "hbm_traffic.json")) as f:
+            entry = json.load(f)["kernels"][workload]
+    except (OSError, KeyError, ValueError):
+        return None
+    if entry.get("kernel") != kernel:
+        return None
+    h = hashlib.sha256()
+    for rel in entry["source"]:
+        with open(os.path.join(root, "paper_2501_19221_amd", rel), "rb") as f:
+            h.update(f.read())
+    return entry["hbm_bytes_per_dispatch"] if h.hexdigest() == entry["source_sha256"] else None
+
+
+def calibrate_copy(torch):
+    """A plain device-to-device copy of 1 GiB, four times: under rocprofv3 --pmc its
+    FETCH_SIZE and WRITE_SIZE per dispatch, against the 1 GiB moved, give the factors that
+    turn those counters into HBM bytes."""
+    a = torch.ones(2 ** 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(4):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": a.numel() * 4, "copies": 4}), flush=True)
 
 
 def measured_peaks(torch):
@@ -176,6 +212,9 @@ def main():
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     import torch
+    if a.calibrate_copy:
+        calibrate_copy(torch)
+        return
     from paper_2501_19221_amd import qpa
     from paper_2501_19221_amd.configs import WORKLOADS
 
@@ -287,7 +326,7 @@ def main():
             roof["frac_of_measured"] = roof["achieved"] / ref
     else:
         res_peaks = None
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(wl.name, roof["kernel"])
     roof["avg_launch_us"] = avg_launch_s * 1e6
     roof["launches"] = launches
 

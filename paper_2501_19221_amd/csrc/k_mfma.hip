@@ -246,10 +246,9 @@ struct StateRegs {
 
 // Loads the tile's x, m and b, spread over the matrix waves' nchunk chunk barriers (a
 // few elements before each), so that this traffic shares the memory system with the
-// chunk loads instead of delaying the first chunks.  Rows past rlive are padding rows of
-// the [Rp][np] state: they are read (zeros, never written back) like the others.  Row
-// pointers are wave-uniform, so that each load is a scalar base plus the lane's column.
-// Executes nchunk barriers.
+// chunk loads instead of delaying the first chunks.  Rows past rlive are padding: they
+// are not read and take zeros.  Row pointers are wave-uniform, so that each load is a
+// scalar base plus the lane's column.  Executes nchunk barriers.
 __device__ __forceinline__ void state_load(StateRegs &st, const Tile &tl, int nchunk, int t) {
     const int col = t & (BN - 1);
     const int rsub = __builtin_amdgcn_readfirstlane(t >> 7);
@@ -263,8 +262,10 @@ __device__ __forceinline__ void state_load(StateRegs &st, const Tile &tl, int nc
             barrier();
             ++passed;
         }
-        st.xv[e] = xr[col];
-        st.mv[e] = mr[col];
+        // padding rows (uniform per wave) are not read: they start from zero each step
+        const bool live = tl.R0 + 4 * e + rsub < tl.rlive;
+        st.xv[e] = live ? xr[col] : 0.0f;
+        st.mv[e] = live ? mr[col] : 0.0f;
         xr = next_rows(xr, 4 * tl.np);
         mr = next_rows(mr, 4 * tl.np);
     }

@@ -6,8 +6,10 @@
 // copied once into LDS (row pointers int32, columns uint16, weights int32 or FP32), next
 // to two byte arrays of spins: byte j holds in bit g the sign of variable j in replica g
 // of the workgroup (bit set <=> spin -1).  A step is, for every owned variable, a walk of
-// its row in LDS -- one spin byte serves all G replicas -- followed by the fused update
-// and one byte store; a workgroup barrier separates the steps.  Nothing is written to
+// its row -- one spin byte serves all G replicas -- followed by the fused update and one
+// byte store; a workgroup barrier separates the steps.  The first CACHE off-diagonal
+// entries of each owned row (CACHE = min(8, 16 / VPT)) are held in registers, so that a
+// step issues their spin-byte reads together; longer rows continue from LDS in order.  Nothing is written to
 // memory until the last step, when x and m go back to the workspace state ([n][Rp],
 // replica fastest) and, if asked, the last field.
 // The field sums follow the entry order of the row: int32 (exact; rows are validated
@@ -64,6 +66,13 @@ __global__ void __launch_bounds__(RT) k_csr_resident(
         else wf[k] = ld_as<float>(w_g, w_dt, k);
     }
 
+    constexpr int CACHE = (16 / VPT) < 8 ? (16 / VPT) : 8;
+    // cached entries of each owned row (diagonal entries of a QUBO left out), then the
+    // LDS position where the rest of the row continues
+    int32_t cj[VPT][CACHE];
+    int32_t cwi[VPT][CACHE];
+    float cwf[VPT][CACHE];
+    int32_t ccount[VPT], crest[VPT];
     float xs[VPT][G], ms[VPT][G], bi[VPT];
 #pragma unroll
     for (int u = 0; u < VPT; ++u) {
@@ -89,6 +98,36 @@ __global__ void __launch_bounds__(RT) k_csr_resident(
         }
     }
     __syncthreads();
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+        const int32_t i = tid + u * RT;
+        int32_t cnt = 0, k = 0, k1 = 0;
+        if (i < n) {
+            k = rp[i];
+            k1 = rp[i + 1];
+        }
+#pragma unroll
+        for (int c = 0; c < CACHE; ++c) {
+            cj[u][c] = 0;
+            cwi[u][c] = 0;
+            cwf[u][c] = 0.0f;
+        }
+        // take entries in row order until CACHE of them are held
+        for (; k < k1 && cnt < CACHE; ++k) {
+            const int32_t j = col[k];
+            if (skip_diag && j == i) continue;
+#pragma unroll
+            for (int c = 0; c < CACHE; ++c)
+                if (c == cnt) {
+                    cj[u][c] = j;
+                    if (INT) cwi[u][c] = wi[k];
+                    else cwf[u][c] = wf[k];
+                }
+            ++cnt;
+        }
+        ccount[u] = cnt;
+        crest[u] = k;
+    }
 
     uint8_t *cur = sp0, *nxt = sp1;
     for (int32_t t = t0; t < t1; ++t) {
@@ -105,8 +144,27 @@ __global__ void __launch_bounds__(RT) k_csr_resident(
                 ai[g] = 0;
                 af[g] = 0.0f;
             }
+            // cached entries: their spin bytes are read together, then summed in order
+            uint32_t cb[CACHE];
+#pragma unroll
+            for (int c = 0; c < CACHE; ++c) cb[c] = c < ccount[u] ? cur[cj[u][c]] : 0u;
+#pragma unroll
+            for (int c = 0; c < CACHE; ++c) {
+                if (c < ccount[u]) {
+                    if (INT) {
+                        const int32_t wk = cwi[u][c];
+#pragma unroll
+                        for (int g = 0; g < G; ++g) ai[g] += ((cb[c] >> g) & 1u) ? -wk : wk;
+                    } else {
+                        const float wk = cwf[u][c];
+#pragma unroll
+                        for (int g = 0; g < G; ++g)
+                            af[g] = __fadd_rn(af[g], ((cb[c] >> g) & 1u) ? -wk : wk);
+                    }
+                }
+            }
             const int32_t k1 = rp[i + 1];
-            for (int32_t k = rp[i]; k < k1; ++k) {
+            for (int32_t k = crest[u]; k < k1; ++k) {
                 const int32_t j = col[k];
                 if (skip_diag && j == i) continue;
                 const uint32_t byte = cur[j];
