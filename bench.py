@@ -120,56 +120,72 @@ def measured_peaks(torch):
     return out
 
 
-def cpu_baseline(inst, wl, prec):
-    """The CPU oracle (untuned) on a bounded replica x step sample of the same workload,
-    replicas split over host threads (the oracle releases the GIL)."""
+def cpu_baseline(inst, wl, prec, target_s=15.0):
+    """The CPU oracle (untuned) on a bounded sample of the same workload: a set of replicas
+    split over host threads (the oracle releases the GIL), initialised outside the timing,
+    run for a number of PA steps chosen from a short probe so that the timed part takes
+    about target_s (steps beyond the schedule's T continue from the state, restarting the
+    schedule)."""
     import oracle as orc
     cores = max(1, min(16, os.cpu_count() or 1))
     n = inst.n
+    lam = orc.lambda_linear(wl.steps, wl.lambda0)
     if inst.dense is not None and not np.issubdtype(inst.dense.dtype, np.integer):
         J = inst.dense
         if prec == "bf16":
             J = orc.bf16_quantise(J, orc.bf16_scale_exponent(J))
-        reps, steps = 2 * cores, 40
-        lam = orc.lambda_linear(wl.steps, wl.lambda0)
+        kind = "bf16-rounded" if prec == "bf16" else "exact"
 
-        def work(r0, cnt):
-            x, m = orc.pa_init(n, cnt, wl.seed, np.float32(wl.sigma0), r0=r0)
-            orc.pa_steps_dense_float(J, inst.lin, x, m, 0, steps, lam, wl.eta, wl.alpha)
+        def steps_fn(x, m, t0, t1):
+            orc.pa_steps_dense_float(J, inst.lin, x, m, t0, t1, lam, wl.eta, wl.alpha)
     elif inst.dense is not None:
         J, b, _ = orc.qubo_to_ising_int(inst.dense, inst.lin)
-        reps, steps = wl.replicas, wl.steps
-        lam = orc.lambda_linear(wl.steps, wl.lambda0)
+        kind = "exact"
 
-        def work(r0, cnt):
-            x, m = orc.pa_init(n, cnt, wl.seed, np.float32(wl.sigma0), r0=r0)
-            orc.pa_steps_dense_int(J, b, x, m, 0, steps, lam, wl.eta, wl.alpha)
+        def steps_fn(x, m, t0, t1):
+            orc.pa_steps_dense_int(J, b, x, m, t0, t1, lam, wl.eta, wl.alpha)
     else:
         c = inst.csr
         if inst.kind == "qubo":
             rp, col, w, b, _ = orc.qubo_to_ising_csr_int(c.rp, c.col, c.w, inst.lin)
         else:
             rp, col, w, b = c.rp.astype(np.int64), c.col, c.w, inst.lin
-        reps = min(wl.replicas, 4 * cores)
-        steps = max(1, min(wl.steps, int(2.0e10 / max(1, c.nnz * reps))))
-        lam = orc.lambda_linear(wl.steps, wl.lambda0)
+        kind = "exact"
 
-        def work(r0, cnt):
-            x, m = orc.pa_init(n, cnt, wl.seed, np.float32(wl.sigma0), r0=r0)
-            orc.pa_steps_csr_int(rp, col, w, b, x, m, 0, steps, lam, wl.eta, wl.alpha)
+        def steps_fn(x, m, t0, t1):
+            orc.pa_steps_csr_int(rp, col, w, b, x, m, t0, t1, lam, wl.eta, wl.alpha)
+    reps = min(wl.replicas, 4 * cores)
     per = [reps // cores + (1 if k < reps % cores else 0) for k in range(cores)]
     starts = np.concatenate([[0], np.cumsum(per)[:-1]])
-    threads = [threading.Thread(target=work, args=(int(s), int(c))) for s, c in zip(starts, per) if c]
-    t0 = time.perf_counter()
-    for th in threads:
-        th.start()
-    for th in threads:
-        th.join()
-    dt = time.perf_counter() - t0
-    return {"value": n * reps * steps / dt, "unit": "spin-updates/s", "cores": len(threads),
+    chunks = [(int(s0), int(cnt)) for s0, cnt in zip(starts, per) if cnt]
+    states = [orc.pa_init(n, cnt, wl.seed, np.float32(wl.sigma0), r0=s0) for s0, cnt in chunks]
+
+    def timed(steps):
+        def work(k):
+            x, m = states[k]
+            done = 0
+            while done < steps:                   # whole schedules, then the remainder
+                t1 = min(wl.steps, steps - done)
+                steps_fn(x, m, 0, t1)
+                done += t1
+        threads = [threading.Thread(target=work, args=(k,)) for k in range(len(chunks))]
+        t0 = time.perf_counter()
+        for th in threads:
+            th.start()
+        for th in threads:
+            th.join()
+        return time.perf_counter() - t0
+
+    probe_steps, probe = 1, timed(1)
+    while probe < 0.25:                       # grow the probe until it measures work
+        probe_steps *= 4
+        probe = timed(probe_steps)
+    steps = max(1, int(probe_steps * target_s / probe))
+    dt = timed(steps)
+    return {"value": n * reps * steps / dt, "unit": "spin-updates/s", "cores": len(chunks),
             "kind": "oracle",
-            "sample": "%d replicas x %d PA steps of the same instance (%s couplings), %.1f s wall"
-                      % (reps, steps, "bf16-rounded" if prec == "bf16" else "exact", dt)}
+            "sample": "%d replicas x %d PA steps of the same instance (%s couplings), "
+                      "%.1f s wall on %d threads" % (reps, steps, kind, dt, len(chunks))}
 
 
 PEAK_ALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # 32-bit VALU lane-ops/s, no packed math
