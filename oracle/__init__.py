@@ -5,6 +5,8 @@ import this package.  It wraps the plain C reference in ``qpa_oracle.c`` (compil
 gcc, no FMA contraction) with numpy-friendly functions and adds the end-to-end
 ``solve_*`` drivers that string the primitives together in the order of App. B of the
 paper (initialise, T synchronous PA steps, binarise, exact energies, best replica).
+It also holds the Simulated Bifurcation steps of App. B and a float64 power method for
+the spectral radius that sets SBM's c0.
 It shares no code with the HIP library and never imports it.
 """
 from __future__ import annotations
@@ -73,6 +75,10 @@ def _load():
                                                   _F64, _F64, _P, _P, _P, _P]),
             "orc_relaxed_grad_csr_f64": (_F64, [_I64, _P, _P, _P, _P, _I64, _P, _P, _I64, _P,
                                                 _F64, _F64, _F64, _P, _P, _P, _P]),
+            "orc_sbm_steps_dense_f32": (None, [_I64, _P, _P, _I64, _P, _P, _I64, _I64, _I64,
+                                               _F32, _F32, _F32, _P]),
+            "orc_sbm_steps_csr_f32": (None, [_I64, _P, _P, _P, _P, _I64, _P, _P, _I64, _I64,
+                                             _I64, _F32, _F32, _F32, _P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -390,3 +396,48 @@ def qubo_to_ising_csr_int(rp, col, w, c):
     b = rowsum + np.asarray(c, np.int64)
     K = (int(rowsum.sum()) + int(diag.sum())) // 2 + int(np.asarray(c, np.int64).sum())
     return rp2, col[keep].astype(np.int32), w[keep].astype(np.int32), b, K
+
+
+# ---- Simulated Bifurcation Machine (App. B, SBM) ---------------------------------------
+def sbm_steps_dense(J, b, q, p, t0, t1, T, a0, c0, dt, want_g=False):
+    """Symplectic-Euler SBM steps t0..t1-1 on float32 q, p [R][n] in place (problem in
+    the PA convention; see orc_sbm_steps_dense_f32).  Returns the last step's g = J q + b
+    when want_g."""
+    J = _c(J, np.float32)
+    n = J.shape[0]
+    assert q.dtype == np.float32 and q.flags.c_contiguous and p.flags.c_contiguous
+    g = np.empty_like(q) if want_g else None
+    _load().orc_sbm_steps_dense_f32(n, _ptr(J), _ptr(_c(b, np.float32)), q.shape[0], _ptr(q),
+                                    _ptr(p), t0, t1, T, a0, c0, dt, _ptr(g))
+    return g
+
+
+def sbm_steps_csr(rp, col, w, b, q, p, t0, t1, T, a0, c0, dt, want_g=False):
+    """As sbm_steps_dense for CSR couplings (any numeric weights, used as float32)."""
+    rp = _c(rp, np.int64)
+    assert q.dtype == np.float32 and q.flags.c_contiguous and p.flags.c_contiguous
+    g = np.empty_like(q) if want_g else None
+    _load().orc_sbm_steps_csr_f32(len(rp) - 1, _ptr(rp), _ptr(_c(col, np.int32)),
+                                  _ptr(_c(w, np.float32)), _ptr(_c(b, np.float32)), q.shape[0],
+                                  _ptr(q), _ptr(p), t0, t1, T, a0, c0, dt, _ptr(g))
+    return g
+
+
+def power_start_vector(n, seed):
+    """Start vector of the power method: v_i = 2u - 1, u the top 24 bits of SplitMix64
+    output number i + 1 of `seed` (the draw of the initial state, replica 0)."""
+    k = np.arange(1, n + 1, dtype=np.uint64)
+    return np.array([2.0 * (sm64_output(seed, int(i)) >> 40) / 16777216.0 - 1.0 for i in k])
+
+
+def spectral_radius_power(J, iters, seed):
+    """Power method in float64 on the symmetric matrix J (dense): v <- J v / ||J v|| from
+    power_start_vector; returns ||J v|| after `iters` normalised iterations, which tends
+    to the spectral radius max |lambda| (also when +-lambda_max both occur)."""
+    J = np.asarray(J, np.float64)
+    v = power_start_vector(J.shape[0], seed)
+    v = v / np.linalg.norm(v)
+    for _ in range(iters):
+        w = J @ v
+        v = w / np.linalg.norm(w)
+    return float(np.linalg.norm(J @ v))

@@ -26,6 +26,8 @@
  *     lambda_t, derived by hand from the same update rule.
  *   - Exhaustive ground-state search for small n (Sec. VII.A uses brute force as the
  *     exact reference).
+ *   - The adiabatic Simulated Bifurcation Machine (App. B, Hamilton's equations of the
+ *     oscillator network) integrated with symplectic Euler, on the same (J, b).
  *
  * Arithmetic contract of the dynamics: FP32, every operation rounded separately in the
  * order written (this file is compiled with -ffp-contract=off), integer couplings summed
@@ -35,7 +37,8 @@
  *
  * Parity pins live in tests/ (brute force vs naive enumeration, App. A identities,
  * closed forms of the update, planted optima, finite differences for the adjoint,
- * SplitMix64 reference vectors).
+ * SplitMix64 reference vectors; for SBM a hand-worked two-spin fixture, first-order
+ * convergence to a library ODE solution, bounded energy error, sign conventions).
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -558,4 +561,74 @@ double orc_relaxed_grad_csr_f64(int64_t n, const int64_t *rp, const int32_t *col
 {
     return relaxed_grad(1, n, NULL, rp, col, w, b, nrep, x0, m0, T, lam, eta, alpha, norm,
                         d_eta, d_alpha, d_lam, xT);
+}
+
+/* ---------------------------------------------------------------------------------------
+ * Simulated Bifurcation Machine (App. B, SBM): Hamilton's equations of the oscillator
+ * network, dq/dt = a0 p, dp/dt = -(q^2 + a0 - a(t)) q + c0 (J' q + h'), integrated by
+ * symplectic Euler with step dt: every p is advanced from the positions of the step,
+ * then every q from its new p.  The problem is given in the PA convention (minimise
+ * H = 1/2 s^T J s + b^T s); SBM maximises 1/2 q^T J' q + h'^T q, so it runs on
+ * (J', h') = (-J, -b), i.e. its force is -c0 (J q + b).  a(t) = a0 * t / T rises
+ * linearly.  Every operation is one FP32 rounding, in this order:
+ *   g = (sum_j J_ij q_j, products rounded, added in ascending j) + b_i
+ *   w = ((q q + a0) - a) q;   F = -w - c0 g;   p = p + dt F;   q = q + (dt a0) p
+ * (dt a0 rounded once).  g_out, when given, receives g of the last step.
+ * ------------------------------------------------------------------------------------- */
+static void sbm_update_row(int64_t n, const float *g, float a, float a0, float c0, float dt,
+                           float *q, float *p)
+{
+    const float adt = dt * a0;
+    for (int64_t i = 0; i < n; ++i) {
+        float qq = q[i] * q[i];
+        float w = ((qq + a0) - a) * q[i];
+        float cg = c0 * g[i];
+        float force = -w - cg;
+        float pn = p[i] + dt * force;
+        p[i] = pn;
+        q[i] = q[i] + adt * pn;
+    }
+}
+
+void orc_sbm_steps_dense_f32(int64_t n, const float *J, const float *b, int64_t nrep,
+                             float *q, float *p, int64_t t0, int64_t t1, int64_t T, float a0,
+                             float c0, float dt, float *g_out)
+{
+    float *g = (float *)malloc(sizeof(float) * (size_t)n);
+    for (int64_t r = 0; r < nrep; ++r) {
+        float *qr = q + r * n, *pr = p + r * n;
+        for (int64_t t = t0; t < t1; ++t) {
+            const float a = a0 * ((float)t / (float)T);
+            for (int64_t i = 0; i < n; ++i) {
+                float acc = 0.0f;
+                for (int64_t j = 0; j < n; ++j) acc += J[i * n + j] * qr[j];
+                g[i] = acc + b[i];
+            }
+            sbm_update_row(n, g, a, a0, c0, dt, qr, pr);
+        }
+        if (g_out && t1 > t0) memcpy(g_out + r * n, g, sizeof(float) * (size_t)n);
+    }
+    free(g);
+}
+
+/* CSR couplings (weights converted to float, entries in row order, no diagonal). */
+void orc_sbm_steps_csr_f32(int64_t n, const int64_t *rp, const int32_t *col, const float *w,
+                           const float *b, int64_t nrep, float *q, float *p, int64_t t0,
+                           int64_t t1, int64_t T, float a0, float c0, float dt, float *g_out)
+{
+    float *g = (float *)malloc(sizeof(float) * (size_t)n);
+    for (int64_t r = 0; r < nrep; ++r) {
+        float *qr = q + r * n, *pr = p + r * n;
+        for (int64_t t = t0; t < t1; ++t) {
+            const float a = a0 * ((float)t / (float)T);
+            for (int64_t i = 0; i < n; ++i) {
+                float acc = 0.0f;
+                for (int64_t k = rp[i]; k < rp[i + 1]; ++k) acc += w[k] * qr[col[k]];
+                g[i] = acc + b[i];
+            }
+            sbm_update_row(n, g, a, a0, c0, dt, qr, pr);
+        }
+        if (g_out && t1 > t0) memcpy(g_out + r * n, g, sizeof(float) * (size_t)n);
+    }
+    free(g);
 }

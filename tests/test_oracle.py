@@ -392,3 +392,137 @@ def test_relaxed_forward_equals_pa_without_couplings(orc):
                              0.05, 0.5)
     Lpa = np.mean(x.astype(np.float64) @ b)
     assert abs(L - Lpa) <= 1e-5 * max(1.0, abs(Lpa))
+
+
+# ---------------------------------------------------------------- SBM (App. B)
+def _sbm_H(J, b, q, p, a, a0, c0):
+    """Hamiltonian of App. B with (J', h') = (-J, -b): kinetic + quartic/quadratic
+    single-particle potential - c0 (h'.q + q J' q / 2), in float64."""
+    q = q.astype(np.float64)
+    p = p.astype(np.float64)
+    Jq = q @ J.T
+    return (0.5 * a0 * np.sum(p * p, axis=-1)
+            + np.sum(q**4 / 4 + (a0 - a) / 2 * q * q, axis=-1)
+            + c0 * (np.sum(q * b, axis=-1) + 0.5 * np.sum(q * Jq, axis=-1)))
+
+
+def test_sbm_two_spin_hand_worked_steps(orc):
+    J = np.array([[0, 1], [1, 0]], np.float32)
+    b = np.array([0.25, 0.0], np.float32)
+    q = np.array([[0.5, -0.5]], np.float32)
+    p = np.zeros_like(q)
+    for step, g0, g1, p0, p1, q0, q1 in _rows("sbm_two_spin.txt"):
+        t = int(step)
+        g = orc.sbm_steps_dense(J, b, q, p, t, t + 1, 2, 1.0, 0.5, 0.5, want_g=True)
+        assert g[0].tolist() == [float(g0), float(g1)]
+        assert p[0].tolist() == [float(p0), float(p1)]
+        assert q[0].tolist() == [float(q0), float(q1)]
+
+
+def test_sbm_first_order_convergence_to_ode(orc):
+    """Symplectic Euler is a first-order integrator of Hamilton's equations: against a
+    tight scipy solution of the same ODE (a(tau) = a0 tau / (T dt)), the error at a
+    fixed time halves when dt halves."""
+    from scipy.integrate import solve_ivp
+    n, a0, c0, tau = 6, 0.7, 0.3, 3.0
+    rng = np.random.default_rng(11)
+    J = rng.normal(size=(n, n))
+    J = np.triu(J, 1)
+    J = (J + J.T).astype(np.float32)
+    b = rng.normal(size=n).astype(np.float32) * 0.5
+    q0 = rng.uniform(-0.5, 0.5, n).astype(np.float32)
+    Jd, bd = J.astype(np.float64), b.astype(np.float64)
+
+    def rhs(t, y):
+        q, p = y[:n], y[n:]
+        a = a0 * t / tau
+        return np.concatenate([a0 * p, -(q * q + a0 - a) * q - c0 * (Jd @ q + bd)])
+
+    ref = solve_ivp(rhs, (0.0, tau), np.concatenate([q0, np.zeros(n)]), method="DOP853",
+                    rtol=1e-12, atol=1e-12).y[:, -1]
+    errs = []
+    for T in (300, 600, 1200):
+        q = q0[None].copy()
+        p = np.zeros_like(q)
+        orc.sbm_steps_dense(J, b, q, p, 0, T, T, a0, c0, tau / T)
+        errs.append(np.max(np.abs(np.concatenate([q[0], p[0]]) - ref)))
+    assert errs[0] < 0.05
+    for e1, e2 in zip(errs, errs[1:]):
+        assert 1.7 < e1 / e2 < 2.3
+
+
+def test_sbm_energy_bounded_without_drift(orc):
+    """With a(t) held at 0 (T huge) the Hamiltonian is autonomous and symplectic Euler
+    keeps it within O(dt) of its start for long times (no drift): the largest deviation
+    over the run stays below a fixed multiple of dt and shrinks as dt does."""
+    n, a0, c0 = 8, 1.3, 0.2
+    inst = gen.dense_int_ising(n=n, seed=4)
+    J = inst.dense.astype(np.float32) / 10
+    b = inst.lin.astype(np.float32) / 10
+    rng = np.random.default_rng(5)
+    q0 = rng.uniform(-0.8, 0.8, (1, n)).astype(np.float32)
+    devs = []
+    for dt in (0.04, 0.02, 0.01):
+        q, p = q0.copy(), np.zeros_like(q0)
+        H0 = _sbm_H(J, b, q, p, 0.0, a0, c0)[0]
+        dev = 0.0
+        steps = int(round(20.0 / dt))
+        for k in range(0, steps, 50):
+            orc.sbm_steps_dense(J, b, q, p, k, k + 50, 1 << 40, a0, c0, dt)
+            dev = max(dev, abs(_sbm_H(J, b, q, p, 0.0, a0, c0)[0] - H0))
+        devs.append(dev)
+    for dt, dev in zip((0.04, 0.02, 0.01), devs):
+        assert dev < 1.0 * dt * max(1.0, abs(H0))
+    assert devs[2] < 0.5 * devs[0]
+
+
+@pytest.mark.parametrize("sign", [1, -1])
+def test_sbm_sign_convention_two_spins(orc, sign):
+    """The machine minimises the paper's objective: a positive coupling (J_01 s_0 s_1
+    penalises equal signs) ends anti-aligned, a negative one aligned; a field b pushes
+    s toward -sign(b)."""
+    J = np.array([[0, sign], [sign, 0]], np.float32)
+    b = np.zeros(2, np.float32)
+    q = np.array([[0.01, 0.02], [-0.03, 0.01], [0.02, -0.01]], np.float32)
+    p = np.zeros_like(q)
+    T = 400
+    orc.sbm_steps_dense(J, b, q, p, 0, T, T, 1.0, 1.0, 0.05)
+    s = np.where(q >= 0, 1, -1)
+    assert np.all(s[:, 0] * s[:, 1] == -sign)
+    bb = np.array([sign * 0.5, -sign * 0.5], np.float32)
+    q = np.array([[0.01, 0.02]], np.float32)
+    p = np.zeros_like(q)
+    orc.sbm_steps_dense(np.zeros((2, 2), np.float32), bb, q, p, 0, T, T, 1.0, 1.0, 0.05)
+    assert np.sign(q[0]).tolist() == [-sign, sign]
+
+
+def test_sbm_csr_and_dense_trajectories_identical(orc):
+    n = 60
+    rng = np.random.default_rng(8)
+    D = np.where(rng.random((n, n)) < 0.1, rng.normal(size=(n, n)), 0.0)
+    D = np.triu(D, 1)
+    D = (D + D.T).astype(np.float32)
+    rp = np.r_[0, np.cumsum(np.count_nonzero(D, axis=1))]
+    col = np.nonzero(D)[1].astype(np.int32)
+    w = D[np.nonzero(D)]
+    b = rng.normal(size=n).astype(np.float32)
+    q1 = orc.pa_init(n, 3, 5, 0.1)[0]
+    p1 = np.zeros_like(q1)
+    q2, p2 = q1.copy(), p1.copy()
+    g1 = orc.sbm_steps_dense(D, b, q1, p1, 0, 50, 50, 1.0, 0.1, 0.25, want_g=True)
+    g2 = orc.sbm_steps_csr(rp, col, w, b, q2, p2, 0, 50, 50, 1.0, 0.1, 0.25, want_g=True)
+    np.testing.assert_array_equal(q1, q2)
+    np.testing.assert_array_equal(p1, p2)
+    np.testing.assert_array_equal(g1, g2)
+
+
+def test_power_method_matches_eigvalsh(orc):
+    """The power method tends to the spectral radius max |lambda| of J, also when the
+    dominant eigenvalue is negative (antiferromagnetic-like spectra)."""
+    rng = np.random.default_rng(2)
+    A = rng.normal(size=(40, 40))
+    A = A + A.T
+    for M in (A, -A, np.diag(np.r_[-7.0, np.ones(9)])):
+        ev = np.linalg.eigvalsh(M)
+        rho = max(abs(ev[0]), abs(ev[-1]))
+        assert orc.spectral_radius_power(M, 3000, 1) == pytest.approx(rho, rel=1e-6)
