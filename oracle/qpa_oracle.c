@@ -571,7 +571,7 @@ double orc_relaxed_grad_csr_f64(int64_t n, const int64_t *rp, const int32_t *col
  * H = 1/2 s^T J s + b^T s); SBM maximises 1/2 q^T J' q + h'^T q, so it runs on
  * (J', h') = (-J, -b), i.e. its force is -c0 (J q + b).  a(t) = a0 * t / T rises
  * linearly.  Every operation is one FP32 rounding, in this order:
- *   g = (sum_j J_ij q_j, products rounded, added in ascending j) + b_i
+ *   g = (sum_j J_ij q_j, one fused multiply-add per term, in ascending j) + b_i
  *   w = ((q q + a0) - a) q;   F = -w - c0 g;   p = p + dt F;   q = q + (dt a0) p
  * (dt a0 rounded once).  g_out, when given, receives g of the last step.
  * ------------------------------------------------------------------------------------- */
@@ -601,7 +601,7 @@ void orc_sbm_steps_dense_f32(int64_t n, const float *J, const float *b, int64_t 
             const float a = a0 * ((float)t / (float)T);
             for (int64_t i = 0; i < n; ++i) {
                 float acc = 0.0f;
-                for (int64_t j = 0; j < n; ++j) acc += J[i * n + j] * qr[j];
+                for (int64_t j = 0; j < n; ++j) acc = fmaf(J[i * n + j], qr[j], acc);
                 g[i] = acc + b[i];
             }
             sbm_update_row(n, g, a, a0, c0, dt, qr, pr);
@@ -623,7 +623,7 @@ void orc_sbm_steps_csr_f32(int64_t n, const int64_t *rp, const int32_t *col, con
             const float a = a0 * ((float)t / (float)T);
             for (int64_t i = 0; i < n; ++i) {
                 float acc = 0.0f;
-                for (int64_t k = rp[i]; k < rp[i + 1]; ++k) acc += w[k] * qr[col[k]];
+                for (int64_t k = rp[i]; k < rp[i + 1]; ++k) acc = fmaf(w[k], qr[col[k]], acc);
                 g[i] = acc + b[i];
             }
             sbm_update_row(n, g, a, a0, c0, dt, qr, pr);

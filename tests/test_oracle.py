@@ -526,3 +526,25 @@ def test_power_method_matches_eigvalsh(orc):
         ev = np.linalg.eigvalsh(M)
         rho = max(abs(ev[0]), abs(ev[-1]))
         assert orc.spectral_radius_power(M, 3000, 1) == pytest.approx(rho, rel=1e-6)
+
+
+def test_sbm_field_terms_are_fused_multiply_adds(orc):
+    """The SBM field sums J_ij q_j with one rounding per term (fused multiply-add), in
+    ascending j: with J_01 = -1, J_02 = 1 + 2^-12 and q = (0, 1, 1 + 2^-12) the exact
+    field 2^-11 + 2^-24 is representable, whereas rounding the product first would
+    lose the 2^-24."""
+    e = np.float32(1 + 2.0**-12)
+    J = np.array([[0, -1, e], [-1, 0, 0], [e, 0, 0]], np.float32)
+    q = np.array([[0.0, 1.0, e]], np.float32)
+    p = np.zeros_like(q)
+    g = orc.sbm_steps_dense(J, np.zeros(3, np.float32), q, p, 0, 1, 4, 1.0, 1.0, 0.1,
+                            want_g=True)
+    assert g[0, 0] == np.float32(2.0**-11 + 2.0**-24)
+    rp = np.array([0, 2, 3, 4])
+    col = np.array([1, 2, 0, 0], np.int32)
+    w = np.array([-1, e, -1, e], np.float32)
+    q = np.array([[0.0, 1.0, e]], np.float32)
+    p = np.zeros_like(q)
+    g = orc.sbm_steps_csr(rp, col, w, np.zeros(3, np.float32), q, p, 0, 1, 4, 1.0, 1.0, 0.1,
+                          want_g=True)
+    assert g[0, 0] == np.float32(2.0**-11 + 2.0**-24)
