@@ -241,7 +241,9 @@ typedef enum {
     QPA_PATH_CSR = 3,            /* sparse step, one launch per step              */
     QPA_PATH_BATCH_SPARSE = 4,   /* persistent sparse task kernel (all steps)     */
     QPA_PATH_BATCH_DENSE = 5,    /* grouped matrix-core step over many instances  */
-    QPA_PATH_CSR_RESIDENT = 6    /* sparse, state on chip, all steps at once      */
+    QPA_PATH_CSR_RESIDENT = 6,   /* sparse, state on chip, all steps at once      */
+    QPA_PATH_SBM_DENSE = 7,      /* SBM step, dense FP32 couplings                */
+    QPA_PATH_SBM_CSR = 8         /* SBM step, sparse couplings                    */
 } qpa_path;
 
 /* Measurement of the PA-step kernels.  While enabled (enable != 0), every qpa_solve,
@@ -263,6 +265,64 @@ qpa_status qpa_profile_read_path(qpa_ctx *ctx, int32_t path, double *step_ms,
  * last successful qpa_solve_batch on this context took; `count` must equal that call's
  * count.  paths: host array of `count` int32. */
 qpa_status qpa_batch_paths(const qpa_ctx *ctx, int32_t count, int32_t *paths);
+
+/* ---------------------------------------------------------------------------------
+ * Simulated Bifurcation Machine (App. B): the adiabatic oscillator network
+ *   dq_i/dt = a0 p_i,
+ *   dp_i/dt = -(q_i^2 + a0 - a(t)) q_i + c0 (sum_j J'_ij q_j + h'_i),
+ * on R independent replicas, with a(t) = a0 t / T over T steps of symplectic Euler with
+ * step dt (p first, from the positions of the step; then q from the new p).  The
+ * machine maximises (1/2) q^T J' q + h'^T q, so it is driven with (J', h') = (-J, -b),
+ * (J, b) the Ising form of the problem (App. A for a QUBO); the spins read out at the
+ * end are s = sign(q) (sign(0) = +1) and are scored as in qpa_solve.  Per element, in
+ * FP32 with one rounding per operation in this order:
+ *   g = (sum_j J_ij q_j, one fused multiply-add per term, ascending j) + b_i
+ *   w = ((q q + a0) - a) q;  F = -w - c0 g;  p = p + dt F;  q = q + (dt a0) p
+ * with a = a0 * ((float)t / (float)T) and dt a0 rounded once.  Initial positions as the
+ * PA initial state (q_0 = sigma0 (2u - 1), same counter RNG and seed use); p_0 = 0.
+ * c0 = 0 asks for c0 = 1 / rho, rho the spectral radius max |lambda(J)| estimated in
+ * FP64 by power_iters iterations of the power method from v_0 = 2u - 1 (u the top 24
+ * bits of SplitMix64 output i + 1 of `seed`) -- App. B sets c0 from the largest
+ * eigenvalue of the couplings; rho bounds both signs of the spectrum.
+ * Dense couplings are used in FP32 (exact for integer |J| < 2^24); params of the PA
+ * path (precision, schedule) do not apply. */
+typedef struct {
+    int32_t replicas;           /* R >= 1                                          */
+    int32_t steps;              /* T >= 0                                          */
+    float a0;                   /* > 0: inverse mass and final pump level          */
+    float c0;                   /* > 0: coupling scale; 0: 1 / (power-method rho)  */
+    float dt;                   /* > 0: integration step                           */
+    float sigma0;               /* amplitude of the initial positions              */
+    uint64_t seed;              /* SplitMix64 seed (initial positions, power start) */
+    int32_t power_iters;        /* >= 0, power-method iterations when c0 == 0      */
+    int32_t flags;              /* must be 0                                       */
+} qpa_sbm_params;
+
+/* Device bytes of workspace for qpa_sbm_solve / qpa_sbm_steps / qpa_spectral_radius
+ * (same alignment and ownership rules as qpa_workspace_size). */
+qpa_status qpa_workspace_size_sbm(qpa_ctx *ctx, const qpa_problem *problem,
+                                  const qpa_sbm_params *params, size_t *bytes);
+
+/* Whole SBM solve: canonicalisation, initial state, c0, T steps, exact energies of
+ * sign(q_T), best replica.  Outputs as qpa_outputs, with x <- q_T and m <- p_T. */
+qpa_status qpa_sbm_solve(qpa_ctx *ctx, const qpa_problem *problem, const qpa_sbm_params *params,
+                         void *workspace, size_t workspace_bytes, void *stream,
+                         const qpa_outputs *out);
+
+/* Advance a caller-held SBM state by steps t0 .. t1-1 (0 <= t0 <= t1 <= steps) of the
+ * schedule a(t) of `params`.  q, p: device [R*n] float, replica-major, read and
+ * overwritten in place.  g_last: device [R*n] float or NULL, receives J q + b of the last
+ * step taken.  c0 is resolved as in qpa_sbm_solve.  Split runs give the same bits as an
+ * uninterrupted one. */
+qpa_status qpa_sbm_steps(qpa_ctx *ctx, const qpa_problem *problem, const qpa_sbm_params *params,
+                         int32_t t0, int32_t t1, float *q, float *p, float *g_last,
+                         void *workspace, size_t workspace_bytes, void *stream);
+
+/* Spectral radius estimate of the canonical couplings J by the power method of
+ * qpa_sbm_params (power_iters, seed), in FP64.  rho: device [1] double. */
+qpa_status qpa_spectral_radius(qpa_ctx *ctx, const qpa_problem *problem,
+                               const qpa_sbm_params *params, void *workspace,
+                               size_t workspace_bytes, void *stream, double *rho);
 
 /* Library version string. */
 const char *qpa_version(void);

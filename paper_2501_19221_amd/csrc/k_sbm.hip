@@ -1,0 +1,418 @@
+// Simulated Bifurcation Machine steps (App. B) and the power method that sets its c0.
+//
+// Hamilton's equations of the oscillator network, dq/dt = a0 p and
+// dp/dt = -(q^2 + a0 - a(t)) q + c0 (J' q + h'), advanced by symplectic Euler with step
+// dt: p from the positions of the step, then q from the new p.  The problem arrives in
+// the minimisation convention of the PA path (canonical J, b), and the machine runs on
+// (J', h') = (-J, -b), so its force is -c0 (J q + b).  Per element, FP32, one rounding
+// per operation in this order:
+//   g = (sum_j J_ij q_j, one fused multiply-add per term, ascending j) + b_i
+//   w = ((q q + a0) - a) q;  F = -w - c0 g;  p = p + dt F;  q = q + (dt a0) p
+//
+// State layout: q, p [n][Rp] FP32, replica fastest.  Every step reads q_in and writes
+// q_out (the update is synchronous), p in place.
+//
+// Dense couplings: an LDS-tiled FP32 product on the vector units.  A workgroup owns a
+// 128 (replicas) x 128 (variables) output tile; each of its 256 threads holds 8 x 8
+// sums and adds one term per reduction index with a fused multiply-add, in ascending
+// order, so every sum is bit-identical to the sequential definition.  Chunks of 16
+// reduction indices of q (from [n][Rp]: contiguous in replicas) and J (symmetric, so row
+// k of J gives column k: contiguous in variables) are double-buffered in LDS; the next
+// chunk is prefetched into registers while the current one is multiplied.  The update
+// runs in the epilogue on the tile's 16384 elements.
+//
+// CSR couplings: one lane per (row, replica); the G lanes of a row (G = replicas per
+// row group, a power of two <= 64) read the row's entries once per wave and gather
+// q_in of the neighbours from [n][Rp] rows, contiguous in replicas.
+//
+// Power method (FP64): v_0 = 2u - 1 (u the top 24 bits of SplitMix64 output i + 1 of the
+// seed), normalised; then iters times w = J v, v = w / ||w||; the estimate is ||J v||.
+// Each product writes per-workgroup partial sums of w^2 and one small launch reduces
+// them in a fixed order, so the result is deterministic.
+#include "qpa_internal.h"
+
+namespace qpa {
+namespace {
+
+constexpr int SB_BR = 128;   // replicas per dense tile
+constexpr int SB_BI = 128;   // variables per dense tile
+constexpr int SB_KC = 16;    // reduction indices per LDS chunk
+
+__device__ __forceinline__ void sbm_point(float f, float bi, float a, float a0, float c0,
+                                          float dt, float adt, float &q, float &p, float &g) {
+    g = __fadd_rn(f, bi);
+    const float qq = __fmul_rn(q, q);
+    const float w = __fmul_rn(__fsub_rn(__fadd_rn(qq, a0), a), q);
+    const float cg = __fmul_rn(c0, g);
+    const float force = __fsub_rn(-w, cg);
+    const float pn = __fadd_rn(p, __fmul_rn(dt, force));
+    p = pn;
+    q = __fadd_rn(q, __fmul_rn(adt, pn));
+}
+
+// VEC: n % 4 == 0, so rows of J can be read as float4.
+template <bool VEC>
+__global__ void __launch_bounds__(256) k_sbm_dense_step(int64_t n, int64_t Rp,
+                                                        const float *__restrict__ J,
+                                                        const float *__restrict__ b,
+                                                        const float *__restrict__ c0p, float a,
+                                                        float a0, float dt,
+                                                        const float *__restrict__ qi,
+                                                        float *__restrict__ qo,
+                                                        float *__restrict__ p,
+                                                        float *__restrict__ gout) {
+    __shared__ float4 As[2][SB_KC][SB_BR / 4];
+    __shared__ float4 Bs[2][SB_KC][SB_BI / 4];
+    const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+    const int64_t i0 = (int64_t)blockIdx.x * SB_BI, r0 = (int64_t)blockIdx.y * SB_BR;
+    float acc[8][8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int v = 0; v < 8; ++v) acc[u][v] = 0.0f;
+    float4 ra[2], rb[2];
+    const float4 zero4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    auto fetch = [&](int64_t k0) {
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int idx = t + 256 * e, kk = idx >> 5, c4 = idx & 31;
+            const int64_t k = k0 + kk;
+            ra[e] = k < n ? *reinterpret_cast<const float4 *>(qi + k * Rp + r0 + 4 * c4)
+                          : zero4;
+            const int64_t i = i0 + 4 * c4;
+            if (VEC) {
+                rb[e] = (k < n && i < n) ? *reinterpret_cast<const float4 *>(J + k * n + i)
+                                         : zero4;
+            } else {
+                const float *row = J + k * n;
+                const bool kin = k < n;
+                rb[e].x = (kin && i < n) ? row[i] : 0.0f;
+                rb[e].y = (kin && i + 1 < n) ? row[i + 1] : 0.0f;
+                rb[e].z = (kin && i + 2 < n) ? row[i + 2] : 0.0f;
+                rb[e].w = (kin && i + 3 < n) ? row[i + 3] : 0.0f;
+            }
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int idx = t + 256 * e, kk = idx >> 5, c4 = idx & 31;
+            As[buf][kk][c4] = ra[e];
+            Bs[buf][kk][c4] = rb[e];
+        }
+    };
+    const int64_t nch = (n + SB_KC - 1) / SB_KC;
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    for (int64_t c = 0; c < nch; ++c) {
+        const int buf = (int)(c & 1);
+        if (c + 1 < nch) fetch((c + 1) * SB_KC);
+#pragma unroll 4
+        for (int kk = 0; kk < SB_KC; ++kk) {
+            const float4 a0v = As[buf][kk][ty], a1v = As[buf][kk][16 + ty];
+            const float4 b0v = Bs[buf][kk][tx], b1v = Bs[buf][kk][16 + tx];
+            const float av[8] = {a0v.x, a0v.y, a0v.z, a0v.w, a1v.x, a1v.y, a1v.z, a1v.w};
+            const float bv[8] = {b0v.x, b0v.y, b0v.z, b0v.w, b1v.x, b1v.y, b1v.z, b1v.w};
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int v = 0; v < 8; ++v) acc[u][v] = __fmaf_rn(av[u], bv[v], acc[u][v]);
+        }
+        if (c + 1 < nch) stash(buf ^ 1);
+        __syncthreads();
+    }
+    // epilogue: thread holds replicas r0 + 64h + 4ty + e (h, e < 2, 4) and variables
+    // i0 + 64(v/4) + 4tx + v%4
+    const float c0 = *c0p;
+    const float adt = __fmul_rn(dt, a0);
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        const int64_t i = i0 + 64 * (v >> 2) + 4 * tx + (v & 3);
+        if (i >= n) continue;
+        const float bi = b[i];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int64_t idx = i * Rp + r0 + 64 * h + 4 * ty;
+            float4 qv = *reinterpret_cast<const float4 *>(qi + idx);
+            float4 pv = *reinterpret_cast<const float4 *>(p + idx);
+            float4 gv;
+            sbm_point(acc[4 * h + 0][v], bi, a, a0, c0, dt, adt, qv.x, pv.x, gv.x);
+            sbm_point(acc[4 * h + 1][v], bi, a, a0, c0, dt, adt, qv.y, pv.y, gv.y);
+            sbm_point(acc[4 * h + 2][v], bi, a, a0, c0, dt, adt, qv.z, pv.z, gv.z);
+            sbm_point(acc[4 * h + 3][v], bi, a, a0, c0, dt, adt, qv.w, pv.w, gv.w);
+            *reinterpret_cast<float4 *>(qo + idx) = qv;
+            *reinterpret_cast<float4 *>(p + idx) = pv;
+            if (gout) *reinterpret_cast<float4 *>(gout + idx) = gv;
+        }
+    }
+}
+
+// CSR step: lane -> (row, replica).  Wave w covers replica chunk w % (Rp / G) and rows
+// (w / (Rp / G)) * (64 / G) + lane / G.
+template <typename TW, typename TI>
+__global__ void __launch_bounds__(256) k_sbm_csr_step(int64_t n, int64_t Rp, int G,
+                                                      const int32_t *__restrict__ rp,
+                                                      const TI *__restrict__ col,
+                                                      const TW *__restrict__ w, int skip_diag,
+                                                      const float *__restrict__ b,
+                                                      const float *__restrict__ c0p, float a,
+                                                      float a0, float dt,
+                                                      const float *__restrict__ qi,
+                                                      float *__restrict__ qo,
+                                                      float *__restrict__ p,
+                                                      float *__restrict__ gout) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t chunks = Rp / G;
+    const int64_t chunk = wave % chunks;
+    const int64_t row = (wave / chunks) * (64 / G) + lane / G;
+    if (row >= n) return;
+    const int64_t r = chunk * G + (lane & (G - 1));
+    const int32_t k0 = rp[row], k1 = rp[row + 1];
+    float acc = 0.0f;
+    for (int32_t k = k0; k < k1; ++k) {
+        const int64_t j = (int64_t)col[k];
+        if (skip_diag && j == row) continue;
+        acc = __fmaf_rn((float)w[k], qi[j * Rp + r], acc);
+    }
+    const int64_t idx = row * Rp + r;
+    float q = qi[idx], pv = p[idx], g;
+    sbm_point(acc, b[row], a, a0, *c0p, dt, __fmul_rn(dt, a0), q, pv, g);
+    qo[idx] = q;
+    p[idx] = pv;
+    if (gout) gout[idx] = g;
+}
+
+__global__ void k_set_f32(float *dst, float v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) dst[0] = v;
+}
+
+// ------------------------------------------------------------------ power method
+__device__ __forceinline__ uint64_t pw_splitmix(uint64_t seed, uint64_t k) {
+    uint64_t z = seed + k * 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// sum over the workgroup (256 threads); result valid in thread 0
+__device__ __forceinline__ double group_sum(double v, double *sh) {
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) s = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    __syncthreads();
+    return s;
+}
+
+__global__ void __launch_bounds__(256) k_pw_start(int64_t n, uint64_t seed,
+                                                  double *__restrict__ v,
+                                                  double *__restrict__ part) {
+    __shared__ double sh[4];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double x = 0.0;
+    if (i < n) {
+        const uint64_t top = pw_splitmix(seed, (uint64_t)i + 1u) >> 40;
+        x = 2.0 * (double)top / 16777216.0 - 1.0;
+        v[i] = x;
+    }
+    const double s = group_sum(x * x, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// w_i = inv * sum_j J_ij v_j with one wave per row (dense, caller's dtype, QUBO diagonal
+// skipped); part[block] = sum of w_i^2 over the block's 4 rows.
+template <typename T>
+__global__ void __launch_bounds__(256) k_pw_dense(int64_t n, const T *__restrict__ Q,
+                                                  int skip_diag, const double *__restrict__ v,
+                                                  const double *__restrict__ nrm,
+                                                  double *__restrict__ w,
+                                                  double *__restrict__ part) {
+    __shared__ double sh[4];
+    const int lane = threadIdx.x & 63;
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    double s = 0.0;
+    if (row < n) {
+        const T *qr = Q + row * n;
+        for (int64_t j = lane; j < n; j += 64)
+            if (!(skip_diag && j == row)) s += (double)qr[j] * v[j];
+    }
+    s = wave_sum(s);
+    double y = 0.0;
+    if (row < n) {
+        y = s * nrm[1];
+        if (lane == 0) w[row] = y;
+    }
+    const double tot = group_sum(lane == 0 ? y * y : 0.0, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// The same for CSR couplings, one thread per row.
+template <typename TW, typename TI>
+__global__ void __launch_bounds__(256) k_pw_csr(int64_t n, const int32_t *__restrict__ rp,
+                                                const TI *__restrict__ col,
+                                                const TW *__restrict__ wt, int skip_diag,
+                                                const double *__restrict__ v,
+                                                const double *__restrict__ nrm,
+                                                double *__restrict__ w,
+                                                double *__restrict__ part) {
+    __shared__ double sh[4];
+    const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double y = 0.0;
+    if (row < n) {
+        double s = 0.0;
+        for (int32_t k = rp[row]; k < rp[row + 1]; ++k) {
+            const int64_t j = (int64_t)col[k];
+            if (!(skip_diag && j == row)) s += (double)wt[k] * v[j];
+        }
+        y = s * nrm[1];
+        w[row] = y;
+    }
+    const double tot = group_sum(y * y, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// nrm[0] = sqrt(sum part), nrm[1] = 1 / nrm[0]; optionally rho = nrm[0] and
+// c0 = (float)(1 / nrm[0]).
+__global__ void __launch_bounds__(256) k_pw_finish(int64_t nb, const double *__restrict__ part,
+                                                   double *__restrict__ nrm,
+                                                   double *__restrict__ rho,
+                                                   float *__restrict__ c0) {
+    __shared__ double sh[4];
+    double s = 0.0;
+    for (int64_t k = threadIdx.x; k < nb; k += 256) s += part[k];
+    s = group_sum(s, sh);
+    if (threadIdx.x == 0) {
+        const double r = sqrt(s);
+        nrm[0] = r;
+        nrm[1] = r > 0.0 ? 1.0 / r : 0.0;
+        if (rho) rho[0] = r;
+        if (c0) c0[0] = r > 0.0 ? (float)(1.0 / r) : 0.0f;
+    }
+}
+
+template <typename F>
+hipError_t by_dtypes(const qpa_problem &p, F &&f) {
+    auto byw = [&](auto itag) -> hipError_t {
+        switch (p.coupling_dtype) {
+            case QPA_I8: return f((int8_t)0, itag);
+            case QPA_I16: return f((int16_t)0, itag);
+            case QPA_I32: return f((int32_t)0, itag);
+            default: return f(0.0f, itag);
+        }
+    };
+    return p.index_dtype == QPA_I16 ? byw((int16_t)0) : byw((int32_t)0);
+}
+
+}  // namespace
+
+int sbm_csr_group(int64_t R) {
+    int G = 1;
+    while (G < 64 && G < R) G <<= 1;
+    return G;
+}
+
+int64_t sbm_rpad(const qpa_problem &p, int64_t R) {
+    if (p.format == QPA_FMT_DENSE) return (R + SB_BR - 1) / SB_BR * SB_BR;
+    const int G = sbm_csr_group(R);
+    return (R + G - 1) / G * G;
+}
+
+int64_t pw_blocks(const qpa_problem &p) {
+    const int64_t a = (p.n + 255) / 256;
+    const int64_t d = p.format == QPA_FMT_DENSE ? (p.n + 3) / 4 : a;
+    return a > d ? a : d;
+}
+
+hipError_t launch_sbm_step(const qpa_problem &p, const float *Jf, int64_t Rp, const float *b,
+                           const float *c0p, float a, float a0, float dt, const float *q_in,
+                           float *q_out, float *pm, float *g_out, hipStream_t st) {
+    const int64_t n = p.n;
+    if (p.format == QPA_FMT_DENSE) {
+        dim3 grid((unsigned)((n + SB_BI - 1) / SB_BI), (unsigned)(Rp / SB_BR));
+        if (n % 4 == 0)
+            k_sbm_dense_step<true><<<grid, 256, 0, st>>>(n, Rp, Jf, b, c0p, a, a0, dt, q_in,
+                                                         q_out, pm, g_out);
+        else
+            k_sbm_dense_step<false><<<grid, 256, 0, st>>>(n, Rp, Jf, b, c0p, a, a0, dt, q_in,
+                                                          q_out, pm, g_out);
+        return hipGetLastError();
+    }
+    const int G = sbm_csr_group(Rp);
+    const int64_t waves = ((n + (64 / G) - 1) / (64 / G)) * (Rp / G);
+    const unsigned blocks = (unsigned)((waves + 3) / 4);
+    const int skip = p.kind == QPA_KIND_QUBO ? 1 : 0;
+    return by_dtypes(p, [&](auto wtag, auto itag) {
+        using TW = decltype(wtag);
+        using TI = decltype(itag);
+        k_sbm_csr_step<TW, TI><<<blocks, 256, 0, st>>>(
+            n, Rp, G, p.row_ptr, static_cast<const TI *>(p.col),
+            static_cast<const TW *>(p.weights), skip, b, c0p, a, a0, dt, q_in, q_out, pm, g_out);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_set_f32(float *dst, float v, hipStream_t st) {
+    k_set_f32<<<1, 64, 0, st>>>(dst, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_power_method(const qpa_problem &p, int32_t iters, uint64_t seed, double *v,
+                               double *w, double *part, double *nrm, double *rho, float *c0,
+                               hipStream_t st) {
+    const int64_t n = p.n;
+    const int skip = p.kind == QPA_KIND_QUBO ? 1 : 0;
+    const unsigned nb0 = (unsigned)((n + 255) / 256);
+    k_pw_start<<<nb0, 256, 0, st>>>(n, seed, v, part);
+    k_pw_finish<<<1, 256, 0, st>>>(nb0, part, nrm, nullptr, nullptr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    for (int32_t it = 0; it <= iters; ++it) {
+        const bool last = it == iters;
+        unsigned nb;
+        if (p.format == QPA_FMT_DENSE) {
+            nb = (unsigned)((n + 3) / 4);
+            auto run = [&](auto tag) {
+                using T = decltype(tag);
+                k_pw_dense<T><<<nb, 256, 0, st>>>(n, static_cast<const T *>(p.dense), skip, v,
+                                                  nrm, w, part);
+                return hipGetLastError();
+            };
+            switch (p.coupling_dtype) {
+                case QPA_I8: e = run((int8_t)0); break;
+                case QPA_I16: e = run((int16_t)0); break;
+                case QPA_I32: e = run((int32_t)0); break;
+                default: e = run(0.0f); break;
+            }
+        } else {
+            nb = nb0;
+            e = by_dtypes(p, [&](auto wtag, auto itag) {
+                using TW = decltype(wtag);
+                using TI = decltype(itag);
+                k_pw_csr<TW, TI><<<nb, 256, 0, st>>>(n, p.row_ptr,
+                                                     static_cast<const TI *>(p.col),
+                                                     static_cast<const TW *>(p.weights), skip,
+                                                     v, nrm, w, part);
+                return hipGetLastError();
+            });
+        }
+        if (e != hipSuccess) return e;
+        k_pw_finish<<<1, 256, 0, st>>>(nb, part, nrm, last ? rho : nullptr,
+                                       last ? c0 : nullptr);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        double *tmp = v;
+        v = w;
+        w = tmp;
+    }
+    return hipSuccess;
+}
+
+}  // namespace qpa

@@ -6,6 +6,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <cmath>
+
 #include <algorithm>
 #include <string>
 #include <vector>
@@ -78,7 +80,9 @@ struct Plan {
 // batch_rp > 0: state for the batch kernel, [batch_rp/64 groups][n][64].
 // cus: compute units of the device (chooses the replica group of the resident sparse
 // kernel; the workspace size does not depend on it).
-Plan make_plan(const qpa_problem &p, const qpa_params &a, int64_t batch_rp = 0, int cus = 256) {
+// state = false: no PA state buffers (callers that keep their own, such as SBM).
+Plan make_plan(const qpa_problem &p, const qpa_params &a, int64_t batch_rp = 0, int cus = 256,
+               bool state = true) {
     Plan pl{};
     pl.n = p.n;
     pl.R = a.replicas;
@@ -127,9 +131,9 @@ Plan make_plan(const qpa_problem &p, const qpa_params &a, int64_t batch_rp = 0, 
     pl.o_Jf = (pl.path == Path::DenseResident || pl.path == Path::DenseTiled)
                   ? take(sizeof(float) * n * n) : 0;
     pl.o_Jb = pl.path == Path::DenseMfma ? take(sizeof(uint16_t) * np * np) : 0;
-    pl.o_x = take(sizeof(float) * Rp * np);
-    pl.o_m = take(sizeof(float) * Rp * np);
-    pl.o_h = take(sizeof(float) * Rp * np);
+    pl.o_x = state ? take(sizeof(float) * Rp * np) : 0;
+    pl.o_m = state ? take(sizeof(float) * Rp * np) : 0;
+    pl.o_h = state ? take(sizeof(float) * Rp * np) : 0;
     size_t sbytes = 0;
     switch (pl.path) {
         case Path::DenseResident: sbytes = 0; break;
@@ -138,6 +142,7 @@ Plan make_plan(const qpa_problem &p, const qpa_params &a, int64_t batch_rp = 0, 
         case Path::Csr: sbytes = sizeof(uint64_t) * (size_t)(Rp / pl.G) * (size_t)pl.nwords; break;
         case Path::CsrResident: sbytes = 0; break;
     }
+    if (!state) sbytes = 0;
     pl.o_s0 = sbytes ? take(sbytes) : 0;
     pl.o_s1 = sbytes ? take(sbytes) : 0;
     pl.o_part = take(sizeof(double) * (size_t)pl.eblk * R);
@@ -559,6 +564,58 @@ qpa_status make_batch_plan(qpa_ctx *ctx, int32_t count, const qpa_problem *probs
     return QPA_OK;
 }
 
+// SBM workspace: the FP32 plan's canonical and scoring buffers (no PA state), then the
+// double-buffered positions, momenta, fields, c0 and the power method's vectors.
+struct SbmPlan {
+    Plan base;
+    int64_t Rp, pblk;
+    size_t o_q0, o_q1, o_p, o_g, o_c0, o_pv, o_pw, o_pp, o_nrm, total;
+};
+
+qpa_status check_sbm_params(qpa_ctx *ctx, const qpa_sbm_params *s) {
+    if (!s) return fail(ctx, QPA_E_ARG, "params is NULL");
+    if (s->replicas < 1) return fail(ctx, QPA_E_ARG, "replicas must be >= 1");
+    if (s->steps < 0) return fail(ctx, QPA_E_ARG, "steps must be >= 0");
+    if (!(s->a0 > 0.0f) || !std::isfinite(s->a0)) return fail(ctx, QPA_E_ARG, "a0 must be > 0");
+    if (!(s->dt > 0.0f) || !std::isfinite(s->dt)) return fail(ctx, QPA_E_ARG, "dt must be > 0");
+    if (!(s->c0 >= 0.0f) || !std::isfinite(s->c0))
+        return fail(ctx, QPA_E_ARG, "c0 must be >= 0 (0: from the power method)");
+    if (!std::isfinite(s->sigma0)) return fail(ctx, QPA_E_ARG, "sigma0 must be finite");
+    if (s->power_iters < 0) return fail(ctx, QPA_E_ARG, "power_iters must be >= 0");
+    if (s->flags != 0) return fail(ctx, QPA_E_ARG, "params.flags must be 0");
+    return QPA_OK;
+}
+
+SbmPlan make_sbm_plan(const qpa_problem &p, const qpa_sbm_params &s) {
+    qpa_params a{};
+    a.replicas = s.replicas;
+    a.steps = 0;
+    a.precision = QPA_PREC_FP32;
+    a.flags = QPA_SOLVE_STREAMED;
+    SbmPlan sp;
+    sp.base = make_plan(p, a, 0, 0, false);
+    sp.Rp = sbm_rpad(p, s.replicas);
+    sp.pblk = pw_blocks(p);
+    size_t off = sp.base.total;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align_up(bytes);
+        return o;
+    };
+    const size_t RN = (size_t)sp.Rp * (size_t)p.n;
+    sp.o_q0 = take(sizeof(float) * RN);
+    sp.o_q1 = take(sizeof(float) * RN);
+    sp.o_p = take(sizeof(float) * RN);
+    sp.o_g = take(sizeof(float) * RN);
+    sp.o_c0 = take(sizeof(float));
+    sp.o_pv = take(sizeof(double) * (size_t)p.n);
+    sp.o_pw = take(sizeof(double) * (size_t)p.n);
+    sp.o_pp = take(sizeof(double) * (size_t)sp.pblk);
+    sp.o_nrm = take(sizeof(double) * 2);
+    sp.total = off;
+    return sp;
+}
+
 }  // namespace
 }  // namespace qpa
 
@@ -649,7 +706,7 @@ qpa_status qpa_batch_paths(const qpa_ctx *ctx, int32_t count, int32_t *paths) {
 qpa_status qpa_profile_read_path(qpa_ctx *ctx, int32_t path, double *step_ms,
                                  int64_t *step_launches, int32_t reset) {
     if (!ctx || !step_ms || !step_launches) return QPA_E_ARG;
-    if (path < QPA_PATH_ALL || path > QPA_PATH_CSR_RESIDENT)
+    if (path < QPA_PATH_ALL || path > QPA_PATH_SBM_CSR)
         return fail(ctx, QPA_E_ARG, "unknown path %d", path);
     double total = 0.0;
     int64_t n = 0;
@@ -1107,6 +1164,167 @@ qpa_status qpa_energy(qpa_ctx *ctx, const qpa_problem *problem, const qpa_params
     s = canonicalise(ctx, *problem, pl, workspace, st);
     if (s != QPA_OK) return s;
     return score(ctx, *problem, pl, workspace, spins, energy, energy_i64, best, st);
+}
+
+// ---------------------------------------------------------------- SBM (App. B)
+namespace {
+
+qpa_status sbm_prologue(qpa_ctx *ctx, const qpa_problem *problem, const qpa_sbm_params *params,
+                        void *ws, size_t ws_bytes, SbmPlan &sp) {
+    if (!ctx) return QPA_E_ARG;
+    ctx->err.clear();
+    qpa_status s = check_problem(ctx, problem);
+    if (s != QPA_OK) return s;
+    s = check_sbm_params(ctx, params);
+    if (s != QPA_OK) return s;
+    sp = make_sbm_plan(*problem, *params);
+    if (!ws) return fail(ctx, QPA_E_ARG, "workspace is NULL");
+    if ((reinterpret_cast<uintptr_t>(ws) % ALIGN) != 0)
+        return fail(ctx, QPA_E_ARG, "workspace must be %zu-byte aligned", ALIGN);
+    if (ws_bytes < sp.total)
+        return fail(ctx, QPA_E_WORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes,
+                    sp.total);
+    QPA_HIP(hipSetDevice(ctx->device));
+    return QPA_OK;
+}
+
+// c0 into the workspace: the caller's value, or 1 / rho from the power method.
+qpa_status sbm_set_c0(qpa_ctx *ctx, const qpa_problem &p, const qpa_sbm_params &s,
+                      const SbmPlan &sp, void *ws, double *rho, hipStream_t st) {
+    float *c0 = at<float>(ws, sp.o_c0);
+    if (s.c0 > 0.0f && !rho) {
+        QPA_HIP(launch_set_f32(c0, s.c0, st));
+        return QPA_OK;
+    }
+    QPA_HIP(launch_power_method(p, s.power_iters, s.seed, at<double>(ws, sp.o_pv),
+                                at<double>(ws, sp.o_pw), at<double>(ws, sp.o_pp),
+                                at<double>(ws, sp.o_nrm), rho, s.c0 > 0.0f ? nullptr : c0, st));
+    if (s.c0 > 0.0f) QPA_HIP(launch_set_f32(c0, s.c0, st));
+    return QPA_OK;
+}
+
+// Steps t0 .. t1-1 from the positions in q0; returns the buffer holding the last ones.
+qpa_status sbm_run(qpa_ctx *ctx, const qpa_problem &p, const qpa_sbm_params &s,
+                   const SbmPlan &sp, void *ws, int32_t t0, int32_t t1, bool want_g,
+                   hipStream_t st, float **q_last) {
+    float *qa = at<float>(ws, sp.o_q0), *qb = at<float>(ws, sp.o_q1);
+    *q_last = qa;
+    if (t1 <= t0) return QPA_OK;
+    qpa_ctx::Span sp_ev{};
+    if (ctx->prof) {
+        QPA_HIP(take_event(ctx, &sp_ev.a));
+        QPA_HIP(take_event(ctx, &sp_ev.b));
+        QPA_HIP(hipEventRecord(sp_ev.a, st));
+    }
+    const float *Jf = sp.base.o_Jf ? at<float>(ws, sp.base.o_Jf) : nullptr;
+    const float *bf = at<float>(ws, sp.base.o_bf);
+    const float *c0 = at<float>(ws, sp.o_c0);
+    float *pm = at<float>(ws, sp.o_p), *g = at<float>(ws, sp.o_g);
+    for (int32_t t = t0; t < t1; ++t) {
+        volatile float frac = (float)t / (float)s.steps;
+        const float a = s.a0 * frac;
+        QPA_HIP(launch_sbm_step(p, Jf, sp.Rp, bf, c0, a, s.a0, s.dt, qa, qb, pm,
+                                (want_g && t == t1 - 1) ? g : nullptr, st));
+        std::swap(qa, qb);
+    }
+    *q_last = qa;
+    if (ctx->prof) {
+        QPA_HIP(hipEventRecord(sp_ev.b, st));
+        sp_ev.launches = t1 - t0;
+        sp_ev.path = p.format == QPA_FMT_DENSE ? QPA_PATH_SBM_DENSE : QPA_PATH_SBM_CSR;
+        ctx->spans.push_back(sp_ev);
+    }
+    return QPA_OK;
+}
+
+}  // namespace
+
+qpa_status qpa_workspace_size_sbm(qpa_ctx *ctx, const qpa_problem *problem,
+                                  const qpa_sbm_params *params, size_t *bytes) {
+    if (!bytes) return fail(ctx, QPA_E_ARG, "bytes is NULL");
+    qpa_status s = check_problem(ctx, problem);
+    if (s != QPA_OK) return s;
+    s = check_sbm_params(ctx, params);
+    if (s != QPA_OK) return s;
+    *bytes = make_sbm_plan(*problem, *params).total;
+    return QPA_OK;
+}
+
+qpa_status qpa_sbm_solve(qpa_ctx *ctx, const qpa_problem *problem, const qpa_sbm_params *params,
+                         void *workspace, size_t workspace_bytes, void *stream,
+                         const qpa_outputs *out) {
+    SbmPlan sp;
+    qpa_status s = sbm_prologue(ctx, problem, params, workspace, workspace_bytes, sp);
+    if (s != QPA_OK) return s;
+    if (!out || !out->energy || !out->best)
+        return fail(ctx, QPA_E_ARG, "outputs.energy and outputs.best are required");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    void *ws = workspace;
+    const Plan &pl = sp.base;
+    s = canonicalise(ctx, *problem, pl, ws, st);
+    if (s != QPA_OK) return s;
+    const int64_t n = problem->n, R = params->replicas;
+    float *q0 = at<float>(ws, sp.o_q0), *pm = at<float>(ws, sp.o_p);
+    QPA_HIP(launch_init_state(n, R, params->seed, params->sigma0, q0, pm, 1, sp.Rp, sp.Rp, n,
+                              st));
+    s = sbm_set_c0(ctx, *problem, *params, sp, ws, nullptr, st);
+    if (s != QPA_OK) return s;
+    float *q = nullptr;
+    s = sbm_run(ctx, *problem, *params, sp, ws, 0, params->steps, false, st, &q);
+    if (s != QPA_OK) return s;
+    int8_t *spins = out->spins ? out->spins : at<int8_t>(ws, pl.o_sp);
+    QPA_HIP(launch_export_spins(n, R, q, 1, sp.Rp, spins, st));
+    if (out->x) QPA_HIP(launch_copy_state(n, R, q, 1, sp.Rp, out->x, n, 1, st));
+    if (out->m) QPA_HIP(launch_copy_state(n, R, pm, 1, sp.Rp, out->m, n, 1, st));
+    return score(ctx, *problem, pl, ws, spins, out->energy, out->energy_i64, out->best, st);
+}
+
+qpa_status qpa_sbm_steps(qpa_ctx *ctx, const qpa_problem *problem, const qpa_sbm_params *params,
+                         int32_t t0, int32_t t1, float *q_io, float *p_io, float *g_last,
+                         void *workspace, size_t workspace_bytes, void *stream) {
+    SbmPlan sp;
+    qpa_status s = sbm_prologue(ctx, problem, params, workspace, workspace_bytes, sp);
+    if (s != QPA_OK) return s;
+    if (!q_io || !p_io) return fail(ctx, QPA_E_ARG, "q and p are required");
+    if (t0 < 0 || t1 < t0 || t1 > params->steps)
+        return fail(ctx, QPA_E_ARG, "need 0 <= t0 <= t1 <= steps (got %d, %d, %d)", t0, t1,
+                    params->steps);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    void *ws = workspace;
+    s = canonicalise(ctx, *problem, sp.base, ws, st);
+    if (s != QPA_OK) return s;
+    const int64_t n = problem->n, R = params->replicas;
+    float *q0 = at<float>(ws, sp.o_q0), *pm = at<float>(ws, sp.o_p);
+    if (sp.Rp != R) {
+        // padding replicas start at zero; they never feed a live replica
+        QPA_HIP(hipMemsetAsync(q0, 0, sizeof(float) * (size_t)(sp.Rp * n), st));
+        QPA_HIP(hipMemsetAsync(pm, 0, sizeof(float) * (size_t)(sp.Rp * n), st));
+    }
+    QPA_HIP(launch_copy_state(n, R, q_io, n, 1, q0, 1, sp.Rp, st));
+    QPA_HIP(launch_copy_state(n, R, p_io, n, 1, pm, 1, sp.Rp, st));
+    s = sbm_set_c0(ctx, *problem, *params, sp, ws, nullptr, st);
+    if (s != QPA_OK) return s;
+    float *q = nullptr;
+    s = sbm_run(ctx, *problem, *params, sp, ws, t0, t1, g_last != nullptr, st, &q);
+    if (s != QPA_OK) return s;
+    QPA_HIP(launch_copy_state(n, R, q, 1, sp.Rp, q_io, n, 1, st));
+    QPA_HIP(launch_copy_state(n, R, pm, 1, sp.Rp, p_io, n, 1, st));
+    if (g_last && t1 > t0)
+        QPA_HIP(launch_copy_state(n, R, at<float>(ws, sp.o_g), 1, sp.Rp, g_last, n, 1, st));
+    return QPA_OK;
+}
+
+qpa_status qpa_spectral_radius(qpa_ctx *ctx, const qpa_problem *problem,
+                               const qpa_sbm_params *params, void *workspace,
+                               size_t workspace_bytes, void *stream, double *rho) {
+    SbmPlan sp;
+    qpa_status s = sbm_prologue(ctx, problem, params, workspace, workspace_bytes, sp);
+    if (s != QPA_OK) return s;
+    if (!rho) return fail(ctx, QPA_E_ARG, "rho is NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    s = canonicalise(ctx, *problem, sp.base, workspace, st);
+    if (s != QPA_OK) return s;
+    return sbm_set_c0(ctx, *problem, *params, sp, workspace, rho, st);
 }
 
 }  // extern "C"

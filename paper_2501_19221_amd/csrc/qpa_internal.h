@@ -179,6 +179,26 @@ hipError_t launch_rel_finish(int32_t T, int32_t nblk, const double *part_steps,
                              const double *part_loss, double *loss, double *d_eta,
                              double *d_alpha, double *d_lam, hipStream_t st);
 
+// ---- Simulated Bifurcation Machine (App. B) -----------------------------------------
+// State q, p [n][Rp] FP32 (replica fastest).  Rp: replicas padded to the dense tile (128)
+// or to the CSR replica group (a power of two <= 64).
+int sbm_csr_group(int64_t R);
+int64_t sbm_rpad(const qpa_problem &p, int64_t R);
+// One symplectic-Euler step: q_out, p from q_in, p (p in place); g_out (or NULL) receives
+// the fields J q + b.  Dense problems use the canonical FP32 couplings Jf; CSR problems
+// the caller's arrays (QUBO diagonal skipped).  c0 is read from device memory.
+hipError_t launch_sbm_step(const qpa_problem &p, const float *Jf, int64_t Rp, const float *b,
+                           const float *c0p, float a, float a0, float dt, const float *q_in,
+                           float *q_out, float *pm, float *g_out, hipStream_t st);
+hipError_t launch_set_f32(float *dst, float v, hipStream_t st);
+// FP64 power method on the canonical couplings.  v, w: n doubles each; part: pw_blocks
+// doubles; nrm: 2 doubles.  rho (or NULL) receives the estimate of max |lambda|, c0 (or
+// NULL) the float of its reciprocal.
+int64_t pw_blocks(const qpa_problem &p);
+hipError_t launch_power_method(const qpa_problem &p, int32_t iters, uint64_t seed, double *v,
+                               double *w, double *part, double *nrm, double *rho, float *c0,
+                               hipStream_t st);
+
 // ---- batched CSR instances: one persistent launch ------------------------------------
 struct BatchTask {
     int64_t n;

@@ -36,14 +36,16 @@ QPA_I8, QPA_I16, QPA_I32, QPA_F32 = 0, 1, 2, 3
 QPA_PREC_FP32, QPA_PREC_BF16 = 0, 1
 QPA_BATCH_SPARSE, QPA_BATCH_DENSE = 1, 2
 QPA_PATH_ALL, QPA_PATH_DENSE_RESIDENT, QPA_PATH_DENSE_TILED, QPA_PATH_DENSE_MFMA, QPA_PATH_CSR, \
-    QPA_PATH_BATCH_SPARSE, QPA_PATH_BATCH_DENSE, QPA_PATH_CSR_RESIDENT = range(-1, 7)
+    QPA_PATH_BATCH_SPARSE, QPA_PATH_BATCH_DENSE, QPA_PATH_CSR_RESIDENT, QPA_PATH_SBM_DENSE, \
+    QPA_PATH_SBM_CSR = range(-1, 9)
 QPA_SOLVE_STREAMED = 4
 
 EXPORTED = ["qpa_create", "qpa_destroy", "qpa_last_error", "qpa_status_string",
             "qpa_workspace_size", "qpa_solve", "qpa_steps", "qpa_energy", "qpa_version",
             "qpa_profile_enable", "qpa_profile_read", "qpa_workspace_size_batch",
             "qpa_solve_batch", "qpa_workspace_size_relaxed", "qpa_relaxed_grad",
-            "qpa_profile_read_path", "qpa_batch_paths"]
+            "qpa_profile_read_path", "qpa_batch_paths", "qpa_workspace_size_sbm",
+            "qpa_sbm_solve", "qpa_sbm_steps", "qpa_spectral_radius"]
 
 
 class qpa_problem(ctypes.Structure):
@@ -67,6 +69,13 @@ class qpa_outputs(ctypes.Structure):
     _fields_ = [("spins", ctypes.c_void_p), ("energy", ctypes.c_void_p),
                 ("energy_i64", ctypes.c_void_p), ("best", ctypes.c_void_p),
                 ("x", ctypes.c_void_p), ("m", ctypes.c_void_p)]
+
+
+class qpa_sbm_params(ctypes.Structure):
+    _fields_ = [("replicas", ctypes.c_int32), ("steps", ctypes.c_int32),
+                ("a0", ctypes.c_float), ("c0", ctypes.c_float), ("dt", ctypes.c_float),
+                ("sigma0", ctypes.c_float), ("seed", ctypes.c_uint64),
+                ("power_iters", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -103,6 +112,16 @@ _sig = {
     "qpa_profile_read_path": (_S, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]),
     "qpa_batch_paths": (_S, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "qpa_workspace_size_sbm": (_S, [_P, ctypes.POINTER(qpa_problem),
+                                    ctypes.POINTER(qpa_sbm_params),
+                                    ctypes.POINTER(ctypes.c_size_t)]),
+    "qpa_sbm_solve": (_S, [_P, ctypes.POINTER(qpa_problem), ctypes.POINTER(qpa_sbm_params), _P,
+                           ctypes.c_size_t, _P, ctypes.POINTER(qpa_outputs)]),
+    "qpa_sbm_steps": (_S, [_P, ctypes.POINTER(qpa_problem), ctypes.POINTER(qpa_sbm_params),
+                           ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, ctypes.c_size_t,
+                           _P]),
+    "qpa_spectral_radius": (_S, [_P, ctypes.POINTER(qpa_problem),
+                                 ctypes.POINTER(qpa_sbm_params), _P, ctypes.c_size_t, _P, _P]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -226,6 +245,29 @@ def qpa_batch_paths(ctx, count: int) -> np.ndarray:
     return out
 
 
+def qpa_workspace_size_sbm(ctx, problem, params) -> int:
+    nbytes = ctypes.c_size_t()
+    _check(ctx, _lib.qpa_workspace_size_sbm(ctx, ctypes.byref(problem), ctypes.byref(params),
+                                            ctypes.byref(nbytes)))
+    return nbytes.value
+
+
+def qpa_sbm_solve(ctx, problem, params, workspace, workspace_bytes, stream, outputs):
+    _check(ctx, _lib.qpa_sbm_solve(ctx, ctypes.byref(problem), ctypes.byref(params), workspace,
+                                   workspace_bytes, stream, ctypes.byref(outputs)))
+
+
+def qpa_sbm_steps(ctx, problem, params, t0, t1, q, p, g_last, workspace, workspace_bytes,
+                  stream):
+    _check(ctx, _lib.qpa_sbm_steps(ctx, ctypes.byref(problem), ctypes.byref(params), t0, t1, q,
+                                   p, g_last, workspace, workspace_bytes, stream))
+
+
+def qpa_spectral_radius(ctx, problem, params, workspace, workspace_bytes, stream, rho):
+    _check(ctx, _lib.qpa_spectral_radius(ctx, ctypes.byref(problem), ctypes.byref(params),
+                                         workspace, workspace_bytes, stream, rho))
+
+
 # ---- convenience layer (torch supplies memory and streams) ---------------------------
 _DT = {"int8": QPA_I8, "int16": QPA_I16, "int32": QPA_I32, "float32": QPA_F32}
 
@@ -309,6 +351,21 @@ def make_params(replicas, steps, eta, alpha, lambda0, sigma0=0.1, seed=1, precis
         assert keep.shape == (steps,)
         p.lambda_table = keep.ctypes.data
     p._keep = keep            # host table must outlive the call
+    return p
+
+
+def make_sbm_params(replicas, steps, dt, a0=1.0, c0=0.0, sigma0=0.1, seed=1, power_iters=100,
+                    flags=0):
+    p = qpa_sbm_params()
+    p.replicas = replicas
+    p.steps = steps
+    p.a0 = a0
+    p.c0 = c0
+    p.dt = dt
+    p.sigma0 = sigma0
+    p.seed = seed & (2**64 - 1)
+    p.power_iters = power_iters
+    p.flags = flags
     return p
 
 
@@ -425,6 +482,61 @@ class Engine:
         qpa_steps(self.ctx, ps, params, t0, t1, _ptr(x), _ptr(m), _ptr(h),
                   ctypes.c_void_p(ws.data_ptr()), nbytes, self._stream())
         return h
+
+    def _grow(self, nbytes):
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = self.torch.empty(max(nbytes, 256), dtype=self.torch.uint8,
+                                        device="cuda:%d" % self.device)
+        return self._ws
+
+    def sbm_solve(self, prob: Problem, params: qpa_sbm_params, want_state=False):
+        """SBM solve; returns the dict of solve() with x = q_T and m = p_T."""
+        torch = self.torch
+        dev = "cuda:%d" % self.device
+        R, n = params.replicas, prob.n
+        ps = prob.struct()
+        nbytes = qpa_workspace_size_sbm(self.ctx, ps, params)
+        ws = self._grow(nbytes)
+        out = {"spins": torch.empty((R, n), dtype=torch.int8, device=dev),
+               "energy": torch.empty(R, dtype=torch.float64, device=dev),
+               "best": torch.empty(1, dtype=torch.int32, device=dev),
+               "energy_i64": torch.empty(R, dtype=torch.int64, device=dev),
+               "x": torch.empty((R, n), dtype=torch.float32, device=dev) if want_state else None,
+               "m": torch.empty((R, n), dtype=torch.float32, device=dev) if want_state else None}
+        o = qpa_outputs()
+        o.spins = out["spins"].data_ptr()
+        o.energy = out["energy"].data_ptr()
+        o.energy_i64 = out["energy_i64"].data_ptr()
+        o.best = out["best"].data_ptr()
+        o.x = out["x"].data_ptr() if want_state else None
+        o.m = out["m"].data_ptr() if want_state else None
+        qpa_sbm_solve(self.ctx, ps, params, ctypes.c_void_p(ws.data_ptr()), nbytes,
+                      self._stream(), o)
+        return out
+
+    def sbm_steps(self, prob: Problem, params: qpa_sbm_params, t0: int, t1: int, q, p,
+                  want_g=False):
+        """Advance device tensors q, p ([R,n] float32) in place; returns g or None."""
+        torch = self.torch
+        assert q.is_contiguous() and p.is_contiguous() and q.dtype == torch.float32
+        ps = prob.struct()
+        nbytes = qpa_workspace_size_sbm(self.ctx, ps, params)
+        ws = self._grow(nbytes)
+        g = torch.empty_like(q) if want_g else None
+        qpa_sbm_steps(self.ctx, ps, params, t0, t1, _ptr(q), _ptr(p), _ptr(g),
+                      ctypes.c_void_p(ws.data_ptr()), nbytes, self._stream())
+        return g
+
+    def spectral_radius(self, prob: Problem, params: qpa_sbm_params):
+        """Power-method estimate of max |lambda(J)| (device float64 tensor [1])."""
+        torch = self.torch
+        ps = prob.struct()
+        nbytes = qpa_workspace_size_sbm(self.ctx, ps, params)
+        ws = self._grow(nbytes)
+        rho = torch.empty(1, dtype=torch.float64, device="cuda:%d" % self.device)
+        qpa_spectral_radius(self.ctx, ps, params, ctypes.c_void_p(ws.data_ptr()), nbytes,
+                            self._stream(), _ptr(rho))
+        return rho
 
     def energy(self, prob: Problem, params: qpa_params, spins):
         torch = self.torch

@@ -162,3 +162,28 @@ def test_batch_path_flags(q):
     # single-instance solves take no flags
     one = q.make_params(4, 10, 0.1, 0.5, 1.0, flags=q.QPA_BATCH_SPARSE)
     assert _ws(q, _dense_problem(q), one)[0] == q.QPA_E_ARG
+
+
+def _ws_sbm(q, p, s):
+    n = ctypes.c_size_t()
+    st = q._lib.qpa_workspace_size_sbm(None, ctypes.byref(p), ctypes.byref(s), ctypes.byref(n))
+    return st, n.value
+
+
+def test_sbm_workspace_and_validation(q):
+    s = q.make_sbm_params(1024, 1000, 0.5)
+    st, dense = _ws_sbm(q, _dense_problem(q, 4096, q.QPA_F32), s)
+    # canonical FP32 couplings + q0, q1, p, g of [n][1024]
+    assert st == q.QPA_OK and dense >= 4096 * 4096 * 4 + 4 * 1024 * 4096 * 4
+    s3 = q.make_sbm_params(3, 10, 0.5)
+    st, small = _ws_sbm(q, _dense_problem(q, 100), s3)
+    assert st == q.QPA_OK and small >= 4 * 128 * 100 * 4       # replicas padded to the tile
+    for kw in ({"a0": 0.0}, {"a0": float("nan")}, {"c0": -0.5}, {"flags": 2},
+               {"power_iters": -3}):
+        args = dict(a0=1.0, c0=0.0, flags=0, power_iters=10)
+        args.update(kw)
+        bad = q.make_sbm_params(4, 10, 0.5, **args)
+        assert _ws_sbm(q, _dense_problem(q), bad)[0] == q.QPA_E_ARG
+    assert _ws_sbm(q, _dense_problem(q), q.make_sbm_params(4, 10, 0.0))[0] == q.QPA_E_ARG
+    assert _ws_sbm(q, _dense_problem(q), q.make_sbm_params(0, 10, 0.5))[0] == q.QPA_E_ARG
+    assert _ws_sbm(q, _dense_problem(q), q.make_sbm_params(4, -1, 0.5))[0] == q.QPA_E_ARG
