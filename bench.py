@@ -10,7 +10,10 @@ the matrix cores (FP32 accumulation).  The same solve with FP32 couplings on the
 path is timed once beside it, and both best energies are compared in FP64 ("BF16 vs FP32
 form at matched best energy").
 
-    python bench.py [--steps K] [--warmup W] [--workload sk4096|chimera16|dense20|planted3r]
+    python bench.py [--steps K] [--warmup W]
+                    [--workload sk4096|chimera16|dense20|er512|planted3r|sbm_sk4096|sbm_chimera16]
+
+The sbm_* workloads time whole Simulated Bifurcation Machine solves (App. B) instead.
 """
 from __future__ import annotations
 
@@ -154,18 +157,31 @@ def cpu_baseline(inst, wl, prec, target_s=15.0):
 
         def steps_fn(x, m, t0, t1):
             orc.pa_steps_csr_int(rp, col, w, b, x, m, t0, t1, lam, wl.eta, wl.alpha)
-    reps = min(wl.replicas, 4 * cores)
+    r = _oracle_rate(n, wl.replicas, wl.steps, wl.seed, wl.sigma0, steps_fn, cores, target_s)
+    r["sample"] = "%d replicas x %d PA steps of the same instance (%s couplings), " \
+                  "%.1f s wall on %d threads" % (r.pop("reps"), r.pop("steps"), kind,
+                                                 r.pop("seconds"), r["cores"])
+    return r
+
+
+def _oracle_rate(n, R, T, seed, sigma0, steps_fn, cores, target_s):
+    """Time steps_fn(x, m, t0, t1) (an oracle stepper, which releases the GIL) on a set of
+    replicas split over host threads, initialised outside the timing; the number of steps
+    comes from a short probe so that the timed part takes about target_s (steps beyond the
+    schedule's T continue from the state, restarting the schedule)."""
+    import oracle as orc
+    reps = min(R, 4 * cores)
     per = [reps // cores + (1 if k < reps % cores else 0) for k in range(cores)]
     starts = np.concatenate([[0], np.cumsum(per)[:-1]])
     chunks = [(int(s0), int(cnt)) for s0, cnt in zip(starts, per) if cnt]
-    states = [orc.pa_init(n, cnt, wl.seed, np.float32(wl.sigma0), r0=s0) for s0, cnt in chunks]
+    states = [orc.pa_init(n, cnt, seed, np.float32(sigma0), r0=s0) for s0, cnt in chunks]
 
     def timed(steps):
         def work(k):
             x, m = states[k]
             done = 0
             while done < steps:                   # whole schedules, then the remainder
-                t1 = min(wl.steps, steps - done)
+                t1 = min(T, steps - done)
                 steps_fn(x, m, 0, t1)
                 done += t1
         threads = [threading.Thread(target=work, args=(k,)) for k in range(len(chunks))]
@@ -183,9 +199,37 @@ def cpu_baseline(inst, wl, prec, target_s=15.0):
     steps = max(1, int(probe_steps * target_s / probe))
     dt = timed(steps)
     return {"value": n * reps * steps / dt, "unit": "spin-updates/s", "cores": len(chunks),
-            "kind": "oracle",
-            "sample": "%d replicas x %d PA steps of the same instance (%s couplings), "
-                      "%.1f s wall on %d threads" % (reps, steps, kind, dt, len(chunks))}
+            "kind": "oracle", "reps": reps, "steps": steps, "seconds": dt}
+
+
+def cpu_baseline_sbm(inst, swl, target_s=15.0):
+    """The CPU oracle's SBM steps on a bounded sample of the same workload (see
+    _oracle_rate); c0 = 1 / rho from the oracle's own power method when the workload asks
+    for it."""
+    import oracle as orc
+    cores = max(1, min(16, os.cpu_count() or 1))
+    n = inst.n
+    if inst.dense is not None:
+        J = np.asarray(inst.dense, np.float32)
+        b = np.asarray(inst.lin, np.float32)
+        D = J.astype(np.float64)
+    else:
+        c = inst.csr
+        rp, col, w = c.rp.astype(np.int64), c.col, c.w.astype(np.float32)
+        b = np.zeros(n, np.float32) if inst.lin is None else np.asarray(inst.lin, np.float32)
+        D = c.to_dense(np.float64)
+    c0 = swl.c0 if swl.c0 > 0 else float(np.float32(
+        1.0 / orc.spectral_radius_power(D, swl.power_iters, swl.seed)))
+    if inst.dense is not None:
+        def steps_fn(q, p, t0, t1):
+            orc.sbm_steps_dense(J, b, q, p, t0, t1, swl.steps, swl.a0, c0, swl.dt)
+    else:
+        def steps_fn(q, p, t0, t1):
+            orc.sbm_steps_csr(rp, col, w, b, q, p, t0, t1, swl.steps, swl.a0, c0, swl.dt)
+    r = _oracle_rate(n, swl.replicas, swl.steps, swl.seed, swl.sigma0, steps_fn, cores, target_s)
+    r["sample"] = "%d replicas x %d SBM steps of the same instance, %.1f s wall on %d " \
+                  "threads" % (r.pop("reps"), r.pop("steps"), r.pop("seconds"), r["cores"])
+    return r
 
 
 PEAK_ALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # 32-bit VALU lane-ops/s, no packed math
@@ -220,6 +264,71 @@ def run_solves(eng, qpa, torch, inst, prob, params, steps, warmup, batch):
     return dt, out, ms, launches, per_path
 
 
+def bench_sbm(a, torch, qpa, swl):
+    """One benchmark step = one whole SBM solve (canonicalisation, initial state, power
+    method for c0, all steps, exact energies, best replica)."""
+    log("generating SBM workload %s" % swl.name)
+    inst = swl.make()
+    eng = qpa.Engine(0)
+    prob = qpa.Problem.from_instance(inst)
+    R, T, n = swl.replicas, swl.steps, inst.n
+    sp = qpa.make_sbm_params(R, T, swl.dt, swl.a0, swl.c0, swl.sigma0, swl.seed,
+                             swl.power_iters)
+    torch.cuda.synchronize()
+    for w in range(a.warmup):
+        eng.sbm_solve(prob, sp)
+        torch.cuda.synchronize()
+        log("warmup %d done" % w)
+    qpa.qpa_profile_read(eng.ctx, reset=True)
+    qpa.qpa_profile_enable(eng.ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        out = eng.sbm_solve(prob, sp)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    qpa.qpa_profile_enable(eng.ctx, False)
+    dense = inst.dense is not None
+    code = qpa.QPA_PATH_SBM_DENSE if dense else qpa.QPA_PATH_SBM_CSR
+    step_ms, launches = qpa.qpa_profile_read_path(eng.ctx, code, reset=True)
+    avg_s = step_ms / 1e3 / max(1, launches)
+    if dense:
+        flops = 2.0 * R * n * n
+        roof = {"bound": "alu", "achieved": flops / avg_s / 1e12, "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "kernel": "k_sbm_dense_step",
+                "per_launch": "2*R*n^2 = %.4g flop (one FMA per coupling, replica; one SBM "
+                              "step of every replica)" % flops}
+    else:
+        c = inst.csr
+        byts = (4.0 * (n + 1) + c.nnz * (c.col.dtype.itemsize + c.w.dtype.itemsize)
+                + 16.0 * n * R)
+        roof = {"bound": "hbm", "achieved": byts / avg_s / 1e9, "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "kernel": "k_sbm_csr_step",
+                "per_launch": "4(n+1) + nnz*(index+weight) + 16*n*R (q read and written, p "
+                              "read and written) = %.4g B (one SBM step of every replica)"
+                              % byts}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = measured_traffic(swl.name, roof["kernel"])
+    roof["avg_launch_us"] = avg_s * 1e6
+    roof["launches"] = launches
+    e = out["energy"].cpu().numpy()
+    res = {"metric": METRIC, "value": n * R * T * a.steps / dt, "unit": "spin-updates/s",
+           "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+           "ms_per_step": dt / a.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": swl.name, "description": swl.note, "n": n, "replicas": R,
+                      "sbm_steps": T, "dt": swl.dt, "a0": swl.a0,
+                      "c0": "1/rho (power method)" if swl.c0 == 0 else swl.c0,
+                      "parallelism": "single GPU"},
+           "roofline": roof, "best_energy": float(e.min()),
+           "best_replica": int(out["best"].cpu()[0])}
+    if not a.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        res["cpu_baseline"] = cpu_baseline_sbm(inst, swl)
+    eng.close()
+    print(json.dumps(res), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -232,8 +341,11 @@ def main():
         calibrate_copy(torch)
         return
     from paper_2501_19221_amd import qpa
-    from paper_2501_19221_amd.configs import WORKLOADS
+    from paper_2501_19221_amd.configs import SBM_WORKLOADS, WORKLOADS
 
+    if a.workload in SBM_WORKLOADS:
+        bench_sbm(a, torch, qpa, SBM_WORKLOADS[a.workload])
+        return
     wl = WORKLOADS[a.workload]
     log("generating workload %s" % wl.name)
     made = wl.make()

@@ -52,3 +52,36 @@ WORKLOADS = {
         "planted random 3-regular Ising graph, n=1e8, |w| in [1,7], CSR int32 indices + int8 "
         "weights, 4 replicas, 1000 steps"),
 }
+
+
+@dataclass(frozen=True)
+class SbmWorkload:
+    """A Simulated Bifurcation Machine run (App. B).  c0 = 0 takes c0 = 1 / rho from
+    `power_iters` power-method iterations, the prescription App. B gives; a0 = 1 as it
+    suggests.  dt was chosen once by a small sweep on the CPU oracle (dt = 1 diverges
+    on SK couplings, dt = 0.25 and 0.5 reach similar energies)."""
+    name: str
+    replicas: int
+    steps: int
+    dt: float
+    a0: float
+    c0: float
+    sigma0: float
+    seed: int
+    power_iters: int
+    make: object
+    note: str
+
+
+SBM_WORKLOADS = {
+    "sbm_sk4096": SbmWorkload(
+        "sbm_sk4096", 1024, 1000, 0.5, 1.0, 0.0, 0.1, 1, 100,
+        lambda: gen.sk_ising(4096, 0.1, seed=3),
+        "SBM on dense SK n=4096 (the sk4096 instance), FP32 couplings, 1024 replicas, "
+        "1000 symplectic-Euler steps, dt=0.5, a0=1, c0=1/rho"),
+    "sbm_chimera16": SbmWorkload(
+        "sbm_chimera16", 1024, 2000, 0.5, 1.0, 0.0, 0.1, 1, 100,
+        lambda: gen.chimera_ising(16, seed=2),
+        "SBM on Chimera C16 (the chimera16 instance), CSR int8, 1024 replicas, 2000 steps, "
+        "dt=0.5, a0=1, c0=1/rho"),
+}

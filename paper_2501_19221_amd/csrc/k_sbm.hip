@@ -15,7 +15,7 @@
 // Dense couplings: an LDS-tiled FP32 product on the vector units.  A workgroup owns a
 // 128 (replicas) x 128 (variables) output tile; each of its 256 threads holds 8 x 8
 // sums and adds one term per reduction index with a fused multiply-add, in ascending
-// order, so every sum is bit-identical to the sequential definition.  Chunks of 16
+// order, so every sum is bit-identical to the sequential definition.  Chunks of 32
 // reduction indices of q (from [n][Rp]: contiguous in replicas) and J (symmetric, so row
 // k of J gives column k: contiguous in variables) are double-buffered in LDS; the next
 // chunk is prefetched into registers while the current one is multiplied.  The update
@@ -36,7 +36,7 @@ namespace {
 
 constexpr int SB_BR = 128;   // replicas per dense tile
 constexpr int SB_BI = 128;   // variables per dense tile
-constexpr int SB_KC = 16;    // reduction indices per LDS chunk
+constexpr int SB_KC = 32;    // reduction indices per LDS chunk
 
 __device__ __forceinline__ void sbm_point(float f, float bi, float a, float a0, float c0,
                                           float dt, float adt, float &q, float &p, float &g) {
@@ -50,7 +50,74 @@ __device__ __forceinline__ void sbm_point(float f, float bi, float a, float a0, 
     q = __fadd_rn(q, __fmul_rn(adt, pn));
 }
 
+__device__ __forceinline__ float4 sb_load_q(const float *__restrict__ qi, int64_t k, int64_t n,
+                                           int64_t Rp, int64_t col) {
+    if (k < n) return *reinterpret_cast<const float4 *>(qi + k * Rp + col);
+    return make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
 // VEC: n % 4 == 0, so rows of J can be read as float4.
+template <bool VEC>
+__device__ __forceinline__ float4 sb_load_j(const float *__restrict__ J, int64_t k, int64_t n,
+                                           int64_t i) {
+    float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (k >= n) return v;
+    const float *row = J + k * n;
+    if (VEC) {
+        if (i < n) v = *reinterpret_cast<const float4 *>(row + i);
+    } else {
+        if (i < n) v.x = row[i];
+        if (i + 1 < n) v.y = row[i + 1];
+        if (i + 2 < n) v.z = row[i + 2];
+        if (i + 3 < n) v.w = row[i + 3];
+    }
+    return v;
+}
+
+typedef __attribute__((address_space(3))) const void sb_lds_t;
+typedef float sb_f4 __attribute__((ext_vector_type(4)));
+
+// LDS byte address of a shared-memory pointer.
+__device__ __forceinline__ uint32_t sb_lds(const float4 *p) {
+    return (uint32_t)(uintptr_t)(sb_lds_t *)p;
+}
+
+// Issue the four fragment reads of one reduction index: A columns at la + off and
+// la + off + 256 (replicas 4ty.. and 64+4ty..), B at lb + off and lb + off + 256.
+__device__ __forceinline__ void sb_rd4(sb_f4 &a0, sb_f4 &a1, sb_f4 &b0, sb_f4 &b1,
+                                       uint32_t la, uint32_t lb, int off_tag) {
+    if (off_tag == 0) {
+        asm volatile("ds_read_b128 %0, %4\n\tds_read_b128 %1, %4 offset:256\n\t"
+                     "ds_read_b128 %2, %5\n\tds_read_b128 %3, %5 offset:256"
+                     : "=v"(a0), "=v"(a1), "=v"(b0), "=v"(b1) : "v"(la), "v"(lb));
+    } else if (off_tag == 512) {
+        asm volatile("ds_read_b128 %0, %4 offset:512\n\tds_read_b128 %1, %4 offset:768\n\t"
+                     "ds_read_b128 %2, %5 offset:512\n\tds_read_b128 %3, %5 offset:768"
+                     : "=v"(a0), "=v"(a1), "=v"(b0), "=v"(b1) : "v"(la), "v"(lb));
+    } else {
+        asm volatile("ds_read_b128 %0, %4 offset:1024\n\tds_read_b128 %1, %4 offset:1280\n\t"
+                     "ds_read_b128 %2, %5 offset:1024\n\tds_read_b128 %3, %5 offset:1280"
+                     : "=v"(a0), "=v"(a1), "=v"(b0), "=v"(b1) : "v"(la), "v"(lb));
+    }
+}
+
+// Wait until at most N LDS reads of this wave are outstanding; the registers are tied to
+// the wait so that no use is scheduled before it.
+template <int N>
+__device__ __forceinline__ void sb_wait4(sb_f4 &a0, sb_f4 &a1, sb_f4 &b0, sb_f4 &b1) {
+    asm volatile("s_waitcnt lgkmcnt(%4)" : "+v"(a0), "+v"(a1), "+v"(b0), "+v"(b1) : "n"(N));
+}
+
+#define SB_FMA_ROW(u, av)                                                               \
+    acc[u][0] = __fmaf_rn(av, fb0.x, acc[u][0]);                                         \
+    acc[u][1] = __fmaf_rn(av, fb0.y, acc[u][1]);                                         \
+    acc[u][2] = __fmaf_rn(av, fb0.z, acc[u][2]);                                         \
+    acc[u][3] = __fmaf_rn(av, fb0.w, acc[u][3]);                                         \
+    acc[u][4] = __fmaf_rn(av, fb1.x, acc[u][4]);                                         \
+    acc[u][5] = __fmaf_rn(av, fb1.y, acc[u][5]);                                         \
+    acc[u][6] = __fmaf_rn(av, fb1.z, acc[u][6]);                                         \
+    acc[u][7] = __fmaf_rn(av, fb1.w, acc[u][7]);
+
 template <bool VEC>
 __global__ void __launch_bounds__(256) k_sbm_dense_step(int64_t n, int64_t Rp,
                                                         const float *__restrict__ J,
@@ -61,8 +128,8 @@ __global__ void __launch_bounds__(256) k_sbm_dense_step(int64_t n, int64_t Rp,
                                                         float *__restrict__ qo,
                                                         float *__restrict__ p,
                                                         float *__restrict__ gout) {
-    __shared__ float4 As[2][SB_KC][SB_BR / 4];
-    __shared__ float4 Bs[2][SB_KC][SB_BI / 4];
+    __shared__ float4 As[2][SB_KC + 1][SB_BR / 4];
+    __shared__ float4 Bs[2][SB_KC + 1][SB_BI / 4];
     const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
     const int64_t i0 = (int64_t)blockIdx.x * SB_BI, r0 = (int64_t)blockIdx.y * SB_BR;
     float acc[8][8];
@@ -70,58 +137,84 @@ __global__ void __launch_bounds__(256) k_sbm_dense_step(int64_t n, int64_t Rp,
     for (int u = 0; u < 8; ++u)
 #pragma unroll
         for (int v = 0; v < 8; ++v) acc[u][v] = 0.0f;
-    float4 ra[2], rb[2];
-    const float4 zero4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    auto fetch = [&](int64_t k0) {
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            const int idx = t + 256 * e, kk = idx >> 5, c4 = idx & 31;
-            const int64_t k = k0 + kk;
-            ra[e] = k < n ? *reinterpret_cast<const float4 *>(qi + k * Rp + r0 + 4 * c4)
-                          : zero4;
-            const int64_t i = i0 + 4 * c4;
-            if (VEC) {
-                rb[e] = (k < n && i < n) ? *reinterpret_cast<const float4 *>(J + k * n + i)
-                                         : zero4;
-            } else {
-                const float *row = J + k * n;
-                const bool kin = k < n;
-                rb[e].x = (kin && i < n) ? row[i] : 0.0f;
-                rb[e].y = (kin && i + 1 < n) ? row[i + 1] : 0.0f;
-                rb[e].z = (kin && i + 2 < n) ? row[i + 2] : 0.0f;
-                rb[e].w = (kin && i + 3 < n) ? row[i + 3] : 0.0f;
-            }
-        }
-    };
-    auto stash = [&](int buf) {
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            const int idx = t + 256 * e, kk = idx >> 5, c4 = idx & 31;
-            As[buf][kk][c4] = ra[e];
-            Bs[buf][kk][c4] = rb[e];
-        }
-    };
+    // load slots of this thread in a chunk: rows kk = t/32 + 8e (e < 4), float4 column t%32
+    const int lk = t >> 5, lc = t & 31;
+    const int64_t qcol = r0 + 4 * lc, jcol = i0 + 4 * lc;
+    float4 pa0, pa1, pa2, pa3, pb0, pb1, pb2, pb3;
+#define SB_FETCH(k0)                                                                     \
+    pa0 = sb_load_q(qi, (k0) + lk, n, Rp, qcol);                                         \
+    pa1 = sb_load_q(qi, (k0) + lk + 8, n, Rp, qcol);                                     \
+    pa2 = sb_load_q(qi, (k0) + lk + 16, n, Rp, qcol);                                    \
+    pa3 = sb_load_q(qi, (k0) + lk + 24, n, Rp, qcol);                                    \
+    pb0 = sb_load_j<VEC>(J, (k0) + lk, n, jcol);                                         \
+    pb1 = sb_load_j<VEC>(J, (k0) + lk + 8, n, jcol);                                     \
+    pb2 = sb_load_j<VEC>(J, (k0) + lk + 16, n, jcol);                                    \
+    pb3 = sb_load_j<VEC>(J, (k0) + lk + 24, n, jcol);
+#define SB_STASH(buf)                                                                    \
+    As[buf][lk][lc] = pa0;                                                               \
+    As[buf][lk + 8][lc] = pa1;                                                           \
+    As[buf][lk + 16][lc] = pa2;                                                          \
+    As[buf][lk + 24][lc] = pa3;                                                          \
+    Bs[buf][lk][lc] = pb0;                                                               \
+    Bs[buf][lk + 8][lc] = pb1;                                                           \
+    Bs[buf][lk + 16][lc] = pb2;                                                          \
+    Bs[buf][lk + 24][lc] = pb3;
     const int64_t nch = (n + SB_KC - 1) / SB_KC;
-    fetch(0);
-    stash(0);
+    SB_FETCH(0)
+    SB_STASH(0)
     __syncthreads();
     for (int64_t c = 0; c < nch; ++c) {
         const int buf = (int)(c & 1);
-        if (c + 1 < nch) fetch((c + 1) * SB_KC);
-#pragma unroll 4
-        for (int kk = 0; kk < SB_KC; ++kk) {
-            const float4 a0v = As[buf][kk][ty], a1v = As[buf][kk][16 + ty];
-            const float4 b0v = Bs[buf][kk][tx], b1v = Bs[buf][kk][16 + tx];
-            const float av[8] = {a0v.x, a0v.y, a0v.z, a0v.w, a1v.x, a1v.y, a1v.z, a1v.w};
-            const float bv[8] = {b0v.x, b0v.y, b0v.z, b0v.w, b1v.x, b1v.y, b1v.z, b1v.w};
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-#pragma unroll
-                for (int v = 0; v < 8; ++v) acc[u][v] = __fmaf_rn(av[u], bv[v], acc[u][v]);
+        const bool more = c + 1 < nch;
+        if (more) {
+            SB_FETCH((c + 1) * SB_KC)
         }
-        if (c + 1 < nch) stash(buf ^ 1);
+        // Two fragment sets: while one reduction index is multiplied, the next one's
+        // fragments are read.  The reads are issued by inline assembly (the compiler would
+        // otherwise move them next to their use) and their completion is awaited by
+        // explicit waits that also mark the registers as written.  Row SB_KC of each
+        // buffer is padding: read, never used.
+        const uint32_t la = sb_lds(&As[buf][0][ty]), lb = sb_lds(&Bs[buf][0][tx]);
+        sb_f4 xa0, xa1, xb0, xb1, ya0, ya1, yb0, yb1;
+        sb_rd4(xa0, xa1, xb0, xb1, la, lb, 0);
+#pragma unroll 1
+        for (int kk = 0; kk < SB_KC; kk += 2) {
+            const uint32_t o = (uint32_t)kk * 512u;
+            sb_rd4(ya0, ya1, yb0, yb1, la + o, lb + o, 512);
+            sb_wait4<4>(xa0, xa1, xb0, xb1);
+            {
+                const sb_f4 fb0 = xb0, fb1 = xb1;
+                SB_FMA_ROW(0, xa0.x)
+                SB_FMA_ROW(1, xa0.y)
+                SB_FMA_ROW(2, xa0.z)
+                SB_FMA_ROW(3, xa0.w)
+                SB_FMA_ROW(4, xa1.x)
+                SB_FMA_ROW(5, xa1.y)
+                SB_FMA_ROW(6, xa1.z)
+                SB_FMA_ROW(7, xa1.w)
+            }
+            sb_rd4(xa0, xa1, xb0, xb1, la + o, lb + o, 1024);
+            sb_wait4<4>(ya0, ya1, yb0, yb1);
+            {
+                const sb_f4 fb0 = yb0, fb1 = yb1;
+                SB_FMA_ROW(0, ya0.x)
+                SB_FMA_ROW(1, ya0.y)
+                SB_FMA_ROW(2, ya0.z)
+                SB_FMA_ROW(3, ya0.w)
+                SB_FMA_ROW(4, ya1.x)
+                SB_FMA_ROW(5, ya1.y)
+                SB_FMA_ROW(6, ya1.z)
+                SB_FMA_ROW(7, ya1.w)
+            }
+        }
+        sb_wait4<0>(xa0, xa1, xb0, xb1);     // the padding row's reads land before reuse
+        if (more) {
+            SB_STASH(buf ^ 1)
+        }
         __syncthreads();
     }
+#undef SB_FETCH
+#undef SB_STASH
     // epilogue: thread holds replicas r0 + 64h + 4ty + e (h, e < 2, 4) and variables
     // i0 + 64(v/4) + 4tx + v%4
     const float c0 = *c0p;
@@ -147,6 +240,7 @@ __global__ void __launch_bounds__(256) k_sbm_dense_step(int64_t n, int64_t Rp,
         }
     }
 }
+#undef SB_FMA_ROW
 
 // CSR step: lane -> (row, replica).  Wave w covers replica chunk w % (Rp / G) and rows
 // (w / (Rp / G)) * (64 / G) + lane / G.

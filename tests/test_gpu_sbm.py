@@ -196,6 +196,9 @@ def test_spectral_radius_matches_oracle(q, eng, which):
 
 
 def test_sbm_c0_from_power_method(q, eng):
+    """c0 = 0 runs the power method and uses float32(1 / rho).  The oracle's own power
+    method gives the same float32 c0 (FP64 reduction-order differences are far below its
+    rounding), so the trajectories match the oracle's bit for bit."""
     inst = gen.sk_ising(256, 0.1, seed=8)
     R, T = 4, 40
     prob = q.Problem.from_instance(inst)
@@ -203,10 +206,12 @@ def test_sbm_c0_from_power_method(q, eng):
     say("sbm c0 from power method")
     rho = float(host(eng.spectral_radius(prob, sp0))[0])
     out0 = eng.sbm_solve(prob, sp0, want_state=True)
-    c0 = float(np.float32(1.0 / rho))
-    out1 = eng.sbm_solve(prob, q.make_sbm_params(R, T, 0.5, c0=c0, seed=2), want_state=True)
+    out1 = eng.sbm_solve(prob, q.make_sbm_params(R, T, 0.5, c0=float(np.float32(1.0 / rho)),
+                                                 seed=2), want_state=True)
     assert np.array_equal(host(out0["x"]), host(out1["x"]))
-    qv, _, _ = _oracle_run(inst, R, T, 1.0, c0, 0.5, 2, 0.1)
+    c0 = np.float32(1.0 / orc.spectral_radius_power(inst.dense, 80, 2))
+    assert c0 == np.float32(1.0 / rho)
+    qv, _, _ = _oracle_run(inst, R, T, 1.0, float(c0), 0.5, 2, 0.1)
     assert np.array_equal(host(out0["x"]), qv)
 
 
@@ -226,3 +231,60 @@ def test_sbm_invalid_params_rejected(q, eng):
         with pytest.raises(q.QpaError) as ei:
             eng.sbm_solve(prob, sp)
         assert ei.value.status == q.QPA_E_ARG
+
+
+# ------------------------------------------------------------------ full-size workloads
+def test_sbm_sk4096_full_workload_sampled(q, eng):
+    """The benchmark's dense SBM workload at full size (n = 4096, 1024 replicas, schedule of
+    1000 steps): the first 120 steps of every replica on the GPU, replicas 0 and 1023
+    (first and last of the padded tiles) against the oracle."""
+    import torch
+    from paper_2501_19221_amd.configs import SBM_WORKLOADS
+    wl = SBM_WORKLOADS["sbm_sk4096"]
+    inst = wl.make()
+    c0 = float(np.float32(1.0 / orc.spectral_radius_power(inst.dense, wl.power_iters,
+                                                           wl.seed)))
+    prob = q.Problem.from_instance(inst)
+    sp = q.make_sbm_params(wl.replicas, wl.steps, wl.dt, wl.a0, c0, wl.sigma0, wl.seed)
+    x0, _ = orc.pa_init(inst.n, wl.replicas, wl.seed, np.float32(wl.sigma0))
+    qd = torch.from_numpy(x0).cuda()
+    pd = torch.zeros_like(qd)
+    say("sbm sk4096 full size, 120 steps")
+    eng.sbm_steps(prob, sp, 0, 120, qd, pd)
+    qg, pg = host(qd), host(pd)
+    J, b = inst.dense.astype(np.float32), inst.lin.astype(np.float32)
+    for r in (0, wl.replicas - 1):
+        qv, _ = orc.pa_init(inst.n, 1, wl.seed, np.float32(wl.sigma0), r0=r)
+        p = np.zeros_like(qv)
+        orc.sbm_steps_dense(J, b, qv, p, 0, 120, wl.steps, wl.a0, c0, wl.dt)
+        assert np.array_equal(qg[r], qv[0]) and np.array_equal(pg[r], p[0])
+
+
+def test_sbm_chimera16_full_workload_sampled(q, eng):
+    """The benchmark's sparse SBM workload, whole solve: replicas 0, 517 and 1023 against
+    the oracle's full trajectories; every replica's energy against the oracle's energy of
+    the spins it returned; the best replica is the first minimum."""
+    from paper_2501_19221_amd.configs import SBM_WORKLOADS
+    wl = SBM_WORKLOADS["sbm_chimera16"]
+    inst = wl.make()
+    c = inst.csr
+    c0 = float(np.float32(1.0 / orc.spectral_radius_power(c.to_dense(np.float64),
+                                                           wl.power_iters, wl.seed)))
+    prob = q.Problem.from_instance(inst)
+    sp = q.make_sbm_params(wl.replicas, wl.steps, wl.dt, wl.a0, c0, wl.sigma0, wl.seed)
+    say("sbm chimera16 full solve")
+    out = eng.sbm_solve(prob, sp, want_state=True)
+    qg = host(out["x"])
+    b = np.zeros(inst.n, np.float32)
+    for r in (0, 517, wl.replicas - 1):
+        qv, _ = orc.pa_init(inst.n, 1, wl.seed, np.float32(wl.sigma0), r0=r)
+        p = np.zeros_like(qv)
+        orc.sbm_steps_csr(c.rp, c.col, c.w.astype(np.float32), b, qv, p, 0, wl.steps, wl.steps,
+                          wl.a0, c0, wl.dt)
+        assert np.array_equal(qg[r], qv[0])
+    s = host(out["spins"])
+    assert np.array_equal(s, np.where(qg >= 0, 1, -1))
+    e = np.array([orc.ising_energy_csr_int(c.rp, c.col, c.w, np.zeros(inst.n, np.int64), s[r])
+                  for r in range(wl.replicas)])
+    assert np.array_equal(host(out["energy_i64"]), e)
+    assert int(host(out["best"])[0]) == int(np.flatnonzero(e == e.min())[0])
