@@ -17,6 +17,10 @@ Families (paper sections they stand in for):
   * ``planted_3regular``  -- gauge-transformed random 3-regular Ising graph with a planted
                              ground state (planted families of Sec. VIII; size of the
                              largest sparse instances the paper solves, ~1e8 variables).
+  * ``wishart_planted``   -- dense Wishart-planted instances (Sec. VIII.C).
+  * ``tile_planted``      -- tile-planted square lattices (Sec. VIII.B).
+  * ``xorsat_3r3x``       -- 3-regular 3-XORSAT, planted, reduced to two-body form
+                             (Sec. VIII.A with the cubic reduction of Sec. VI.A).
   * ``sdk_toy``           -- the four-term spin model of the SDK listing in Sec. V.C.
 """
 from __future__ import annotations
@@ -213,6 +217,147 @@ def planted_3regular(n: int, wmin: int = 1, wmax: int = 7, seed: int = 5) -> Ins
     csr = CSR(n, rp, nb.reshape(-1).astype(np.int32), w.reshape(-1))
     return Instance("ising", n, csr=csr, lin=np.zeros(n, np.int8),
                     meta={"planted_state": s_star})
+
+
+def _csr_from_pairs(n, u, v, w, dtype=np.int8):
+    """Symmetric CSR from unordered pairs (u < v or u > v) with weights; repeated pairs
+    are summed, zero sums dropped."""
+    a = np.minimum(u, v).astype(np.int64)
+    b = np.maximum(u, v).astype(np.int64)
+    key = a * n + b
+    uk, inv = np.unique(key, return_inverse=True)
+    ws = np.zeros(len(uk), np.int64)
+    np.add.at(ws, inv, np.asarray(w, np.int64))
+    keep = ws != 0
+    uk, ws = uk[keep], ws[keep]
+    return _csr_from_edges(n, uk // n, uk % n, ws.astype(dtype))
+
+
+def wishart_planted(n: int, alpha: float, seed: int = 7) -> Instance:
+    """Wishart planting (Sec. VIII.C).  M = max(1, round(alpha n)) columns w of W are
+    drawn from N(0, Sigma), Sigma = n/(n-1) (I - t t^T / n) with t = (1, ..., 1), as
+    sqrt(n/(n-1)) (z - mean(z)) with z ~ N(0, I) (so W^T t = 0 up to rounding).  With
+    J~ = -(1/n) W W^T, the section's Hamiltonian -(1/2) sum_ij J_ij s_i s_j on
+    J = J~ - diag(J~) is, in the convention of eq. (2), the dense float32 coupling matrix
+    (1/n) W W^T with its diagonal removed, gauged by a random planted state s*
+    (J_ij -> J_ij s*_i s*_j).  s* is a ground state with energy (1/2) Tr J~ (exactly so
+    for the float64 matrix; the float32 couplings move it by rounding only).  Zero fields.
+    meta: planted_state, alpha, M, planted_energy = (1/2) Tr J~ (float64)."""
+    rng = np.random.default_rng(seed)
+    M = max(1, int(round(alpha * n)))
+    z = rng.standard_normal((n, M))
+    W = np.sqrt(n / (n - 1.0)) * (z - z.mean(axis=0, keepdims=True))
+    J = (W @ W.T) / n
+    np.fill_diagonal(J, 0.0)
+    E0 = -0.5 * float(np.sum(W * W)) / n           # (1/2) Tr J~
+    s_star = (2 * rng.integers(0, 2, size=n) - 1).astype(np.int8)
+    J = J * np.outer(s_star, s_star)
+    J = (J + J.T) / 2
+    return Instance("ising", n, dense=np.ascontiguousarray(J, np.float32),
+                    lin=np.zeros(n, np.float32),
+                    meta={"planted_state": s_star, "alpha": alpha, "M": M,
+                          "planted_energy": E0})
+
+
+# Tiles of the tile-planted square lattice: |J| of the four plaquette edges in cyclic
+# order, the last one antiferromagnetic.  With H_tile = -sum J_e s_a s_b, the all-up state
+# leaves only the negative edge unsatisfied; type k has exactly k ground-state pairs
+# (the unsatisfied edge may be the negative one or any of the k - 1 unit positive ones).
+TILE_TYPES = {1: (2, 2, 2, -1), 2: (2, 2, 1, -1), 3: (2, 1, 1, -1), 4: (1, 1, 1, -1)}
+
+
+def tile_planted(L: int, probs=(0.0, 0.2, 0.0, 0.8), seed: int = 8) -> Instance:
+    """Tile planting on an L x L square lattice with periodic boundaries (Sec. VIII.B).
+    Vertex (x, y) has index y L + x.  The tiles are the plaquettes with lower-left corner
+    (x, y), x + y even (a checkerboard: every edge lies in exactly one tile, every vertex
+    in two); each draws its type k from `probs` = (p1, p2, p3, p4) and the edge weights
+    TILE_TYPES[k] in a random rotation around its edges (bottom, right, top, left).  The
+    all-up state minimises every tile, hence the sum; a random planted state s* gauges the
+    couplings.  Stored in the convention of eq. (2): J'_ab = -J_e s*_a s*_b (int8), zero
+    fields; the planted energy is -sum_e J_e.  meta: planted_state, tile_types."""
+    if L % 2 or L < 4:
+        raise ValueError("L must be even and >= 4")
+    rng = np.random.default_rng(seed)
+    xs, ys = np.meshgrid(np.arange(L), np.arange(L), indexing="xy")
+    black = ((xs + ys) % 2 == 0)
+    x0, y0 = xs[black].ravel(), ys[black].ravel()
+    T = len(x0)
+    v00 = y0 * L + x0
+    v10 = y0 * L + (x0 + 1) % L
+    v11 = ((y0 + 1) % L) * L + (x0 + 1) % L
+    v01 = ((y0 + 1) % L) * L + x0
+    eu = np.stack([v00, v10, v01, v00], axis=1)       # bottom, right, top, left
+    ev = np.stack([v10, v11, v11, v01], axis=1)
+    p = np.asarray(probs, np.float64)
+    kinds = rng.choice(4, size=T, p=p / p.sum()) + 1
+    table = np.array([TILE_TYPES[k] for k in (1, 2, 3, 4)], np.int64)
+    rot = rng.integers(0, 4, size=T)
+    idx = (np.arange(4)[None, :] - rot[:, None]) % 4
+    Je = np.take_along_axis(table[kinds - 1], idx, axis=1)
+    s_star = (2 * rng.integers(0, 2, size=L * L) - 1).astype(np.int8)
+    u, v, je = eu.ravel(), ev.ravel(), Je.ravel()
+    w = -je * s_star[u].astype(np.int64) * s_star[v].astype(np.int64)
+    csr = _csr_from_pairs(L * L, u, v, w, np.int8)
+    return Instance("ising", L * L, csr=csr, lin=np.zeros(L * L, np.int8),
+                    meta={"planted_state": s_star, "tile_types": kinds,
+                          "planted_energy": int(-je.sum())})
+
+
+def xorsat_3r3x(n: int, seed: int = 9) -> Instance:
+    """3-regular 3-XORSAT with a planted solution (Sec. VIII.A), reduced to two-body form.
+    m = n equations over GF(2), each on three distinct variables, each variable in three
+    equations (configuration model; triples with a repeated variable are repaired by
+    random swaps).  A random x* fixes the right-hand sides b = A x* mod 2, so the Ising
+    cost -sum_e (-1)^{b_e} s_i s_j s_k (s = (-1)^x) has minimum -m at s* = (-1)^{x*}.
+    Every cubic term sigma s_i s_j s_k (sigma = -(-1)^{b_e}) is replaced by the two-body
+    form of the cubic-term reduction of Sec. VI.A, with its own auxiliary spin a_e
+    (variable n + e):
+        3 + sigma (s_i + s_j + s_k + 2 a) + 2 a (s_i + s_j + s_k) + s_i s_j + s_j s_k + s_i s_k,
+    whose minimum over a equals the cubic term.  The stored Ising instance (int8 couplings
+    and fields) drops the constant 3 per equation, so its minimum is -4m.
+    meta: planted_state (n + m spins: s* and the minimising a), equations, rhs."""
+    if n < 3:
+        raise ValueError("n must be >= 3")
+    rng = np.random.default_rng(seed)
+    m = n
+    stubs = rng.permutation(np.repeat(np.arange(n), 3)).reshape(m, 3)
+    for _ in range(10000):
+        bad = np.flatnonzero((stubs[:, 0] == stubs[:, 1]) | (stubs[:, 1] == stubs[:, 2])
+                             | (stubs[:, 0] == stubs[:, 2]))
+        if len(bad) == 0:
+            break
+        for e in bad:
+            f = int(rng.integers(0, m))
+            c1, c2 = int(rng.integers(0, 3)), int(rng.integers(0, 3))
+            stubs[e, c1], stubs[f, c2] = stubs[f, c2], stubs[e, c1]
+    else:
+        raise RuntimeError("3-regular repair did not converge")
+    eqs = np.sort(stubs, axis=1)
+    x_star = rng.integers(0, 2, size=n)
+    rhs = x_star[eqs].sum(axis=1) % 2
+    s = (1 - 2 * x_star).astype(np.int64)
+    sigma = -(1 - 2 * rhs)                       # -(-1)^b
+    i, j, k = eqs[:, 0], eqs[:, 1], eqs[:, 2]
+    aux = n + np.arange(m)
+    S = s[i] + s[j] + s[k]
+    # minimising auxiliary spin of each equation at the planted state (ties: +1)
+    f_up = sigma * (S + 2) + 2 * S
+    f_dn = sigma * (S - 2) - 2 * S
+    a_star = np.where(f_up <= f_dn, 1, -1)
+    u = np.concatenate([i, j, i, aux, aux, aux])
+    v = np.concatenate([j, k, k, i, j, k])
+    w = np.concatenate([np.ones(3 * m, np.int64), np.full(3 * m, 2, np.int64)])
+    N = n + m
+    csr = _csr_from_pairs(N, u, v, w, np.int8)
+    lin = np.zeros(N, np.int64)
+    np.add.at(lin, i, sigma)
+    np.add.at(lin, j, sigma)
+    np.add.at(lin, k, sigma)
+    lin[aux] += 2 * sigma
+    planted = np.concatenate([s, a_star]).astype(np.int8)
+    return Instance("ising", N, csr=csr, lin=lin.astype(np.int8),
+                    meta={"planted_state": planted, "equations": eqs, "rhs": rhs,
+                          "planted_energy": -4 * m})
 
 
 def sdk_toy() -> Instance:
