@@ -5,8 +5,9 @@ import this package.  It wraps the plain C reference in ``qpa_oracle.c`` (compil
 gcc, no FMA contraction) with numpy-friendly functions and adds the end-to-end
 ``solve_*`` drivers that string the primitives together in the order of App. B of the
 paper (initialise, T synchronous PA steps, binarise, exact energies, best replica).
-It also holds the Simulated Bifurcation steps of App. B and a float64 power method for
-the spectral radius that sets SBM's c0.
+It also holds the Simulated Bifurcation steps of App. B, a float64 power method for
+the spectral radius that sets SBM's c0, and the low-energy spectrum of a sample set
+(distinct states by energy, Sec. V.A).
 It shares no code with the HIP library and never imports it.
 """
 from __future__ import annotations
@@ -441,3 +442,20 @@ def spectral_radius_power(J, iters, seed):
         w = J @ v
         v = w / np.linalg.norm(w)
     return float(np.linalg.norm(J @ v))
+
+
+# ---- low-energy spectrum (Sec. V.A: the sample set of many low-energy states) ----------
+def spectrum(spins, energy, k):
+    """Distinct states among the R samples, ordered by energy and then by the lowest
+    replica index holding the state; the first k of them.  Returns (states [m][n] int8,
+    energies [m], counts [m] (replicas holding the state), first [m] (lowest such
+    replica index), distinct (number of distinct states)), m = min(k, distinct).  Each
+    state's energy is the energy its first replica reports (equal states have equal
+    energies)."""
+    spins = np.asarray(spins, np.int8)
+    energy = np.asarray(energy)
+    uniq, first, counts = np.unique(spins, axis=0, return_index=True, return_counts=True)
+    E = energy[first]
+    order = np.lexsort((first, E))[:k]
+    return uniq[order], E[order], counts[order].astype(np.int32), \
+        first[order].astype(np.int32), len(uniq)

@@ -548,3 +548,47 @@ def test_sbm_field_terms_are_fused_multiply_adds(orc):
     g = orc.sbm_steps_csr(rp, col, w, np.zeros(3, np.float32), q, p, 0, 1, 4, 1.0, 1.0, 0.1,
                           want_g=True)
     assert g[0, 0] == np.float32(2.0**-11 + 2.0**-24)
+
+
+# ---------------------------------------------------------------- low-energy spectrum
+def _spectrum_by_dict(spins, energy, k):
+    """Brute force: walk the replicas in order, keep a dict of states seen."""
+    seen = {}
+    for r in range(len(spins)):
+        key = bytes(spins[r].astype(np.int8))
+        if key in seen:
+            seen[key][2] += 1
+        else:
+            seen[key] = [float(energy[r]), r, 1]
+    items = sorted(seen.items(), key=lambda kv: (kv[1][0], kv[1][1]))
+    return items[:k], len(seen)
+
+
+@pytest.mark.parametrize("seed,k", [(0, 5), (1, 100), (2, 1)])
+def test_spectrum_matches_brute_force(orc, seed, k):
+    rng = np.random.default_rng(seed)
+    n, R = 9, 300                      # 512 possible states: many repeats
+    J = rng.integers(-3, 4, (n, n))
+    J = np.triu(J, 1)
+    J = J + J.T
+    b = rng.integers(-2, 3, n)
+    s = (2 * rng.integers(0, 2, (R, n)) - 1).astype(np.int8)
+    e = np.array([orc.ising_energy_int(J.astype(np.int32), b, s[r]) for r in range(R)],
+                 np.float64)
+    st, E, cnt, first, distinct = orc.spectrum(s, e, k)
+    ref, ref_distinct = _spectrum_by_dict(s, e, k)
+    assert distinct == ref_distinct
+    assert len(st) == len(ref) == min(k, distinct)
+    for m, (key, (ev, r0, c)) in enumerate(ref):
+        assert bytes(st[m]) == key and E[m] == ev and first[m] == r0 and cnt[m] == c
+
+
+def test_spectrum_invariants_and_ties(orc):
+    # three distinct states, two of them with equal energy: tie broken by first replica
+    s = np.array([[1, 1], [-1, 1], [1, -1], [-1, 1], [1, 1], [1, -1]], np.int8)
+    e = np.array([0.0, -2.0, -2.0, -2.0, 0.0, -2.0])
+    st, E, cnt, first, distinct = orc.spectrum(s, e, 10)
+    assert distinct == 3
+    assert st.tolist() == [[-1, 1], [1, -1], [1, 1]]
+    assert E.tolist() == [-2.0, -2.0, 0.0] and cnt.tolist() == [2, 2, 2]
+    assert first.tolist() == [1, 2, 0]
