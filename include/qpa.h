@@ -324,6 +324,30 @@ qpa_status qpa_spectral_radius(qpa_ctx *ctx, const qpa_problem *problem,
                                const qpa_sbm_params *params, void *workspace,
                                size_t workspace_bytes, void *stream, double *rho);
 
+/* ---------------------------------------------------------------------------------
+ * Low-energy spectrum of a sample set (Sec. V.A: a run returns many low-energy states,
+ * not only the best).  Among the R samples spins[r*n .. r*n+n) (int8 in {-1,+1}) with
+ * energies energy[r], the distinct states ordered by energy and then by the lowest
+ * replica index holding them; the first m = min(k, distinct) are written:
+ *   out_spins  [m*n] int8 (device, may be NULL): the states,
+ *   out_energy [m] double, out_count [m] int32 (replicas holding the state),
+ *   out_first  [m] int32 (lowest such replica), out_distinct [1] int32 (distinct states).
+ * All pointers are device pointers; entries past m are left untouched.  Equal states
+ * must carry equal energies (as every scoring call of this library returns them).
+ * States are told apart by a 64-bit hash and confirmed by exact comparison, so the
+ * result does not depend on the hash.  R <= QPA_SPECTRUM_MAX_R (one workgroup sorts the
+ * samples on chip); larger R returns QPA_E_UNSUPPORTED.
+ * flags: 0, or QPA_SPECTRUM_EXACT_ONLY to group equal-energy samples by exact
+ * comparison alone (diagnostic; same result, slower). */
+#define QPA_SPECTRUM_MAX_R 4096
+#define QPA_SPECTRUM_EXACT_ONLY 1
+qpa_status qpa_workspace_size_spectrum(qpa_ctx *ctx, int64_t n, int32_t R, size_t *bytes);
+qpa_status qpa_spectrum(qpa_ctx *ctx, int64_t n, int32_t R, const int8_t *spins,
+                        const double *energy, int32_t k, int32_t flags, void *workspace,
+                        size_t workspace_bytes, void *stream, int8_t *out_spins,
+                        double *out_energy, int32_t *out_count, int32_t *out_first,
+                        int32_t *out_distinct);
+
 /* Library version string. */
 const char *qpa_version(void);
 

@@ -1327,4 +1327,61 @@ qpa_status qpa_spectral_radius(qpa_ctx *ctx, const qpa_problem *problem,
     return sbm_set_c0(ctx, *problem, *params, sp, workspace, rho, st);
 }
 
+// ---------------------------------------------------------------- spectrum
+namespace {
+
+qpa_status check_spectrum(qpa_ctx *ctx, int64_t n, int32_t R) {
+    if (n < 1) return fail(ctx, QPA_E_SHAPE, "n must be >= 1");
+    if (R < 1) return fail(ctx, QPA_E_ARG, "R must be >= 1");
+    if (R > SPECTRUM_MAX_R)
+        return fail(ctx, QPA_E_UNSUPPORTED, "spectrum of more than %d replicas", SPECTRUM_MAX_R);
+    return QPA_OK;
+}
+
+size_t spectrum_ws(int64_t n, int32_t R) {
+    const size_t nw = (size_t)((n + 63) / 64);
+    return align_up(sizeof(uint64_t) * nw * (size_t)R) + align_up(sizeof(uint64_t) * (size_t)R);
+}
+
+}  // namespace
+
+qpa_status qpa_workspace_size_spectrum(qpa_ctx *ctx, int64_t n, int32_t R, size_t *bytes) {
+    if (!bytes) return fail(ctx, QPA_E_ARG, "bytes is NULL");
+    qpa_status s = check_spectrum(ctx, n, R);
+    if (s != QPA_OK) return s;
+    *bytes = spectrum_ws(n, R);
+    return QPA_OK;
+}
+
+qpa_status qpa_spectrum(qpa_ctx *ctx, int64_t n, int32_t R, const int8_t *spins,
+                        const double *energy, int32_t k, int32_t flags, void *workspace,
+                        size_t workspace_bytes, void *stream, int8_t *out_spins,
+                        double *out_energy, int32_t *out_count, int32_t *out_first,
+                        int32_t *out_distinct) {
+    if (!ctx) return QPA_E_ARG;
+    ctx->err.clear();
+    qpa_status s = check_spectrum(ctx, n, R);
+    if (s != QPA_OK) return s;
+    if (k < 0) return fail(ctx, QPA_E_ARG, "k must be >= 0");
+    if (flags != 0 && flags != QPA_SPECTRUM_EXACT_ONLY)
+        return fail(ctx, QPA_E_ARG, "flags must be 0 or QPA_SPECTRUM_EXACT_ONLY");
+    if (!spins || !energy || !out_distinct || (k > 0 && (!out_energy || !out_count || !out_first)))
+        return fail(ctx, QPA_E_ARG, "spins, energy, out_distinct and (k > 0) out_energy, "
+                                    "out_count, out_first are required");
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % ALIGN) != 0)
+        return fail(ctx, QPA_E_ARG, "workspace must be non-NULL and %zu-byte aligned", ALIGN);
+    if (workspace_bytes < spectrum_ws(n, R))
+        return fail(ctx, QPA_E_WORKSPACE, "workspace has %zu bytes, %zu needed", workspace_bytes,
+                    spectrum_ws(n, R));
+    QPA_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t nw = (size_t)((n + 63) / 64);
+    uint64_t *bits = static_cast<uint64_t *>(workspace);
+    uint64_t *hash = at<uint64_t>(workspace, align_up(sizeof(uint64_t) * nw * (size_t)R));
+    QPA_HIP(launch_spectrum(n, R, spins, energy, k, flags == QPA_SPECTRUM_EXACT_ONLY, bits,
+                            hash, out_spins, out_energy, out_count, out_first, out_distinct,
+                            st));
+    return QPA_OK;
+}
+
 }  // extern "C"

@@ -199,6 +199,15 @@ hipError_t launch_power_method(const qpa_problem &p, int32_t iters, uint64_t see
                                double *w, double *part, double *nrm, double *rho, float *c0,
                                hipStream_t st);
 
+// ---- low-energy spectrum of a sample set -------------------------------------------
+constexpr int32_t SPECTRUM_MAX_R = 4096;
+size_t spectrum_lds_bytes(int32_t RP);
+// bits: R * ceil(n/64) uint64, hash: R uint64 (workspace).
+hipError_t launch_spectrum(int64_t n, int32_t R, const int8_t *spins, const double *energy,
+                           int32_t k, int32_t no_hash, uint64_t *bits, uint64_t *hash,
+                           int8_t *out_spins, double *out_energy, int32_t *out_count,
+                           int32_t *out_first, int32_t *out_distinct, hipStream_t st);
+
 // ---- batched CSR instances: one persistent launch ------------------------------------
 struct BatchTask {
     int64_t n;

@@ -39,13 +39,16 @@ QPA_PATH_ALL, QPA_PATH_DENSE_RESIDENT, QPA_PATH_DENSE_TILED, QPA_PATH_DENSE_MFMA
     QPA_PATH_BATCH_SPARSE, QPA_PATH_BATCH_DENSE, QPA_PATH_CSR_RESIDENT, QPA_PATH_SBM_DENSE, \
     QPA_PATH_SBM_CSR = range(-1, 9)
 QPA_SOLVE_STREAMED = 4
+QPA_SPECTRUM_MAX_R = 4096
+QPA_SPECTRUM_EXACT_ONLY = 1
 
 EXPORTED = ["qpa_create", "qpa_destroy", "qpa_last_error", "qpa_status_string",
             "qpa_workspace_size", "qpa_solve", "qpa_steps", "qpa_energy", "qpa_version",
             "qpa_profile_enable", "qpa_profile_read", "qpa_workspace_size_batch",
             "qpa_solve_batch", "qpa_workspace_size_relaxed", "qpa_relaxed_grad",
             "qpa_profile_read_path", "qpa_batch_paths", "qpa_workspace_size_sbm",
-            "qpa_sbm_solve", "qpa_sbm_steps", "qpa_spectral_radius"]
+            "qpa_sbm_solve", "qpa_sbm_steps", "qpa_spectral_radius",
+            "qpa_workspace_size_spectrum", "qpa_spectrum"]
 
 
 class qpa_problem(ctypes.Structure):
@@ -122,6 +125,10 @@ _sig = {
                            _P]),
     "qpa_spectral_radius": (_S, [_P, ctypes.POINTER(qpa_problem),
                                  ctypes.POINTER(qpa_sbm_params), _P, ctypes.c_size_t, _P, _P]),
+    "qpa_workspace_size_spectrum": (_S, [_P, ctypes.c_int64, ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_size_t)]),
+    "qpa_spectrum": (_S, [_P, ctypes.c_int64, ctypes.c_int32, _P, _P, ctypes.c_int32,
+                          ctypes.c_int32, _P, ctypes.c_size_t, _P, _P, _P, _P, _P, _P]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -266,6 +273,19 @@ def qpa_sbm_steps(ctx, problem, params, t0, t1, q, p, g_last, workspace, workspa
 def qpa_spectral_radius(ctx, problem, params, workspace, workspace_bytes, stream, rho):
     _check(ctx, _lib.qpa_spectral_radius(ctx, ctypes.byref(problem), ctypes.byref(params),
                                          workspace, workspace_bytes, stream, rho))
+
+
+def qpa_workspace_size_spectrum(ctx, n, R) -> int:
+    nbytes = ctypes.c_size_t()
+    _check(ctx, _lib.qpa_workspace_size_spectrum(ctx, n, R, ctypes.byref(nbytes)))
+    return nbytes.value
+
+
+def qpa_spectrum(ctx, n, R, spins, energy, k, flags, workspace, workspace_bytes, stream,
+                 out_spins, out_energy, out_count, out_first, out_distinct):
+    _check(ctx, _lib.qpa_spectrum(ctx, n, R, spins, energy, k, flags, workspace,
+                                  workspace_bytes, stream, out_spins, out_energy, out_count,
+                                  out_first, out_distinct))
 
 
 # ---- convenience layer (torch supplies memory and streams) ---------------------------
@@ -537,6 +557,31 @@ class Engine:
         qpa_spectral_radius(self.ctx, ps, params, ctypes.c_void_p(ws.data_ptr()), nbytes,
                             self._stream(), _ptr(rho))
         return rho
+
+    def spectrum(self, spins, energy, k, flags=0):
+        """Low-energy spectrum of device samples spins [R,n] int8 / energy [R] float64:
+        dict(spins [m,n], energy [m], count [m], first [m], distinct), m = min(k, distinct)."""
+        torch = self.torch
+        R, n = spins.shape
+        dev = spins.device
+        assert spins.dtype == torch.int8 and energy.dtype == torch.float64
+        spins, energy = spins.contiguous(), energy.contiguous()
+        nbytes = qpa_workspace_size_spectrum(self.ctx, n, R)
+        ws = self._grow(nbytes)
+        kk = max(1, min(k, R))
+        out = {"spins": torch.empty((kk, n), dtype=torch.int8, device=dev),
+               "energy": torch.empty(kk, dtype=torch.float64, device=dev),
+               "count": torch.empty(kk, dtype=torch.int32, device=dev),
+               "first": torch.empty(kk, dtype=torch.int32, device=dev)}
+        nd = torch.empty(1, dtype=torch.int32, device=dev)
+        qpa_spectrum(self.ctx, n, R, _ptr(spins), _ptr(energy), k, flags,
+                     ctypes.c_void_p(ws.data_ptr()), nbytes, self._stream(),
+                     _ptr(out["spins"]), _ptr(out["energy"]), _ptr(out["count"]),
+                     _ptr(out["first"]), _ptr(nd))
+        m = min(k, int(nd.cpu()[0]))
+        res = {key: v[:m] for key, v in out.items()}
+        res["distinct"] = int(nd.cpu()[0])
+        return res
 
     def energy(self, prob: Problem, params: qpa_params, spins):
         torch = self.torch

@@ -187,3 +187,13 @@ def test_sbm_workspace_and_validation(q):
     assert _ws_sbm(q, _dense_problem(q), q.make_sbm_params(4, 10, 0.0))[0] == q.QPA_E_ARG
     assert _ws_sbm(q, _dense_problem(q), q.make_sbm_params(0, 10, 0.5))[0] == q.QPA_E_ARG
     assert _ws_sbm(q, _dense_problem(q), q.make_sbm_params(4, -1, 0.5))[0] == q.QPA_E_ARG
+
+
+def test_spectrum_workspace_and_limits(q):
+    n = ctypes.c_size_t()
+    assert q._lib.qpa_workspace_size_spectrum(None, 130, 1024, ctypes.byref(n)) == q.QPA_OK
+    assert n.value >= 1024 * 3 * 8 + 1024 * 8
+    assert q._lib.qpa_workspace_size_spectrum(None, 10, q.QPA_SPECTRUM_MAX_R + 1,
+                                              ctypes.byref(n)) == q.QPA_E_UNSUPPORTED
+    assert q._lib.qpa_workspace_size_spectrum(None, 0, 10, ctypes.byref(n)) == q.QPA_E_SHAPE
+    assert q._lib.qpa_workspace_size_spectrum(None, 10, 0, ctypes.byref(n)) == q.QPA_E_ARG
