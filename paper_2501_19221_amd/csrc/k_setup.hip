@@ -404,90 +404,91 @@ __global__ void __launch_bounds__(256) k_export_spins(int64_t n, int64_t R, cons
 // E = (H + K) / 2 with the canonical (J, b, K).
 constexpr int ER = 16;
 
-// Dense: lane = replica.  The spins of 64 replicas at variable j are one 64-bit word
-// (bit set <=> -1) staged in LDS; for row i and every j > i the pair term is
-// J_ij (1 - 2 [s_i != s_j]), so  sum_{j>i} J_ij s_i s_j = U_i - 2 P_i  with
-// U_i = sum_{j>i} J_ij (uniform) and P_i = sum_{j>i} J_ij [bit_i xor bit_j].
-// Integer couplings: exact int32 sums (rows are validated below 2^24); float couplings:
-// FP64 sums.  A block owns 16 rows (4 per wave) of one 64-replica group and walks j in
-// chunks of DW words; per-block, per-replica partials go to `partial`.
-constexpr int DW = 4096;
+// Dense: thread = replica.  A workgroup owns EROWS rows i and walks the columns in
+// chunks of 8.  For each row and chunk it builds the table of all 256 signed sums
+//   T_i[B] = sum_{k<8} J_{i,8c+k} (bit k of B ? -1 : +1)     (diagonal excluded)
+// (from two 16-entry half tables), after which replica r's row sum over the chunk is one
+// lookup T_i[B_r] with B_r its 8 sign bits there.  Per replica it accumulates
+//   sum_i s_i (J s)_i + 2 sum_i s_i b_i = 2 H(s)
+// over its rows; the tables are FP64 (exact for integer couplings, whose rows are
+// validated below 2^24).  Spins arrive bit-packed per replica (k_spin_rowbits).
+constexpr int EROWS = 16;
 
-__global__ void __launch_bounds__(256) k_spin_words(int64_t n, int64_t R,
-                                                    const int8_t *__restrict__ s,
-                                                    uint64_t *__restrict__ words) {
-    // wave per variable j, lane = replica of group blockIdx.y
+__global__ void __launch_bounds__(256) k_spin_rowbits(int64_t n, int64_t R, int64_t nw,
+                                                      const int8_t *__restrict__ s,
+                                                      uint64_t *__restrict__ bits) {
+    // one wave per replica; bit i%64 of word i/64 set <=> spin i is -1
     const int lane = threadIdx.x & 63;
-    const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int64_t r = (int64_t)blockIdx.y * 64 + lane;
-    bool neg = false;
-    if (j < n && r < R) neg = s[r * n + j] < 0;
-    const uint64_t bal = __ballot(neg);
-    if (lane == 0 && j < n) words[blockIdx.y * n + j] = bal;
+    const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (r >= R) return;
+    for (int64_t w = 0; w < nw; ++w) {
+        const int64_t i = 64 * w + lane;
+        const uint64_t word = __ballot(i < n && s[r * n + i] < 0);
+        if (lane == 0) bits[r * nw + w] = word;
+    }
 }
 
-template <typename TQ, bool INT>
-__global__ void __launch_bounds__(256) k_energy_dense(int64_t n, const TQ *__restrict__ Q,
-                                                      const int64_t *__restrict__ b_i64,
-                                                      const double *__restrict__ b_f64,
-                                                      const uint64_t *__restrict__ words,
-                                                      int64_t R, double *__restrict__ partial) {
-    __shared__ uint64_t sw[DW];
-    __shared__ double red[4][64];
-    const int lane = threadIdx.x & 63;
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t g = blockIdx.y;
-    const uint64_t *gw = words + g * n;
-    const int64_t i0 = (int64_t)blockIdx.x * 16 + 4 * wv;
-    int32_t Pi[4] = {0, 0, 0, 0}, Ui[4] = {0, 0, 0, 0};
-    double Pf[4] = {0.0, 0.0, 0.0, 0.0}, Uf[4] = {0.0, 0.0, 0.0, 0.0};
-    uint32_t bit_i[4];
+template <typename TQ>
+__global__ void __launch_bounds__(1024) k_energy_dense(int64_t n, int64_t nw,
+                                                       const TQ *__restrict__ Q,
+                                                       const int64_t *__restrict__ b_i64,
+                                                       const double *__restrict__ b_f64,
+                                                       const uint64_t *__restrict__ bits,
+                                                       int64_t R, double *__restrict__ partial) {
+    __shared__ double T[EROWS][256];
+    __shared__ double N[EROWS][2][16];
+    const int t = threadIdx.x;
+    const int64_t i0 = (int64_t)blockIdx.x * EROWS;
+    for (int64_t r0 = 0; r0 < R; r0 += 1024) {
+        const int64_t r = r0 + t;
+        const bool live = r < R;
+        const uint64_t *br = bits + (live ? r : 0) * nw;
+        double h[EROWS];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-        bit_i[q] = (i0 + q < n) ? (uint32_t)((gw[i0 + q] >> lane) & 1u) : 0u;
-    for (int64_t j0 = 0; j0 < n; j0 += DW) {
-        const int64_t cnt = min((int64_t)DW, n - j0);
-        __syncthreads();
-        for (int64_t k = threadIdx.x; k < cnt; k += 256) sw[k] = gw[j0 + k];
-        __syncthreads();
+        for (int k = 0; k < EROWS; ++k) h[k] = 0.0;
+        uint64_t word = 0;
+        for (int64_t c = 0; c < n; c += 8) {
+            if (t < EROWS * 32) {                 // half tables: 4 columns each
+                const int row = t >> 5, half = (t >> 4) & 1, e = t & 15;
+                const int64_t i = i0 + row;
+                double v = 0.0;
+                if (i < n) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int64_t i = i0 + q;
-            if (i >= n) continue;
-            const int64_t jb = max(j0, i + 1);
-            const TQ *row = Q + i * n;
-            for (int64_t j = jb; j < j0 + cnt; ++j) {
-                const TQ qv = row[j];
-                const uint32_t x = ((uint32_t)(sw[j - j0] >> lane) ^ bit_i[q]) & 1u;
-                if (INT) {
-                    Ui[q] += (int32_t)qv;
-                    Pi[q] += x ? (int32_t)qv : 0;
-                } else {
-                    const double d = (double)qv;
-                    Uf[q] += d;
-                    Pf[q] += x ? d : 0.0;
+                    for (int k = 0; k < 4; ++k) {
+                        const int64_t j = c + 4 * half + k;
+                        const double q = (j < n && j != i) ? (double)Q[i * n + j] : 0.0;
+                        v += ((e >> k) & 1) ? -q : q;
+                    }
+                }
+                N[row][half][e] = v;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < EROWS / 4; ++u) {
+                const int idx = t + 1024 * u, row = idx >> 8, e = idx & 255;
+                T[row][e] = N[row][0][e & 15] + N[row][1][e >> 4];
+            }
+            __syncthreads();
+            if ((c & 63) == 0 && live) word = br[c >> 6];
+            const int B = (int)((word >> (c & 63)) & 0xFFu);
+#pragma unroll
+            for (int k = 0; k < EROWS; ++k) h[k] += T[k][B];
+        }
+        if (live) {
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 0; k < EROWS; ++k) {
+                const int64_t i = i0 + k;
+                if (i < n) {
+                    const bool neg = (br[i >> 6] >> (i & 63)) & 1u;
+                    const double bi = b_i64 ? (double)b_i64[i] : b_f64[i];
+                    const double term = h[k] + 2.0 * bi;
+                    acc += neg ? -term : term;
                 }
             }
+            partial[(int64_t)blockIdx.x * R + r] = acc;
         }
-    }
-    double contrib = 0.0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int64_t i = i0 + q;
-        if (i >= n) continue;
-        const double si = bit_i[q] ? -1.0 : 1.0;
-        if (INT) contrib += (double)((int64_t)Ui[q] - 2 * (int64_t)Pi[q]) + si * (double)b_i64[i];
-        else contrib += (Uf[q] - 2.0 * Pf[q]) + si * b_f64[i];
-    }
-    red[wv][lane] = contrib;
-    __syncthreads();
-    if (threadIdx.x < 64) {
-        const int64_t r = g * 64 + threadIdx.x;
-        if (r < R) {
-            double v = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
-                       red[3][threadIdx.x];
-            partial[(int64_t)blockIdx.x * R + r] = v;
-        }
+        __syncthreads();
     }
 }
 
@@ -600,10 +601,11 @@ __global__ void __launch_bounds__(256) k_energy_csr_wave(int64_t n,
 // energy[r] = sum over blocks of partial[b][r] (fixed order), then the QUBO constant.
 // For integer instances the partials are exact integers (< 2^53) and the total is taken
 // in int64.
+// twice: the partials sum to 2 H (dense kernel) instead of H.
 __global__ void __launch_bounds__(256) k_energy_finalize(int64_t R, int64_t nblk,
                                                          const double *__restrict__ partial,
                                                          int32_t is_int, int32_t is_qubo,
-                                                         const CanonScalars *sc,
+                                                         int32_t twice, const CanonScalars *sc,
                                                          int64_t *__restrict__ e_i64,
                                                          double *__restrict__ e_f64) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -611,12 +613,14 @@ __global__ void __launch_bounds__(256) k_energy_finalize(int64_t R, int64_t nblk
     if (is_int) {
         int64_t H = 0;
         for (int64_t b = 0; b < nblk; ++b) H += (int64_t)partial[b * R + r];
+        if (twice) H /= 2;
         int64_t E = is_qubo ? (H + sc->K_i64) / 2 : H;
         if (e_i64) e_i64[r] = E;
         e_f64[r] = (double)E;
     } else {
         double H = 0.0;
         for (int64_t b = 0; b < nblk; ++b) H += partial[b * R + r];
+        if (twice) H *= 0.5;
         e_f64[r] = is_qubo ? 0.5 * (H + sc->K_f64) : H;
     }
 }
@@ -792,17 +796,13 @@ hipError_t launch_energy(const qpa_problem &p, const int64_t *b_i64, const doubl
     const unsigned gy = (unsigned)((R + ER - 1) / ER);
     hipError_t e;
     if (p.format == QPA_FMT_DENSE) {
-        const unsigned groups = (unsigned)((R + 63) / 64);
-        k_spin_words<<<dim3((unsigned)((n + 3) / 4), groups), 256, 0, st>>>(n, R, spins, words);
+        const int64_t nw = (n + 63) / 64;
+        k_spin_rowbits<<<(unsigned)((R + 3) / 4), 256, 0, st>>>(n, R, nw, spins, words);
         e = dispatch_q(p.coupling_dtype, [&](auto tag) {
             using T = decltype(tag);
             const T *Q = static_cast<const T *>(p.dense);
-            if (is_int)
-                k_energy_dense<T, true><<<dim3((unsigned)nblk, groups), 256, 0, st>>>(
-                    n, Q, b_i64, b_f64, words, R, partial);
-            else
-                k_energy_dense<T, false><<<dim3((unsigned)nblk, groups), 256, 0, st>>>(
-                    n, Q, b_i64, b_f64, words, R, partial);
+            k_energy_dense<T><<<(unsigned)nblk, 1024, 0, st>>>(n, nw, Q, is_int ? b_i64 : nullptr,
+                                                               b_f64, words, R, partial);
             return hipGetLastError();
         });
     } else {
@@ -828,9 +828,9 @@ hipError_t launch_energy(const qpa_problem &p, const int64_t *b_i64, const doubl
         });
     }
     if (e != hipSuccess) return e;
-    k_energy_finalize<<<grid1(R, 256, INT64_MAX), 256, 0, st>>>(R, nblk, partial, is_int ? 1 : 0,
-                                                                 is_qubo, sc,
-                                                                 is_int ? e_i64 : nullptr, e_f64);
+    k_energy_finalize<<<grid1(R, 256, INT64_MAX), 256, 0, st>>>(
+        R, nblk, partial, is_int ? 1 : 0, is_qubo, p.format == QPA_FMT_DENSE ? 1 : 0, sc,
+        is_int ? e_i64 : nullptr, e_f64);
     return hipGetLastError();
 }
 

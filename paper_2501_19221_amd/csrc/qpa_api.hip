@@ -151,7 +151,7 @@ Plan make_plan(const qpa_problem &p, const qpa_params &a, int64_t batch_rp = 0, 
     pl.o_sp = take(sizeof(int8_t) * R * n);
     pl.o_best = take(sizeof(int32_t) * 4);
     pl.o_words = p.format == QPA_FMT_DENSE
-                     ? take(sizeof(uint64_t) * (size_t)((R + 63) / 64) * n) : 0;
+                     ? take(sizeof(uint64_t) * R * (size_t)((n + 63) / 64)) : 0;
     pl.total = off;
     return pl;
 }

@@ -75,7 +75,7 @@ hipError_t launch_export_spins(int64_t n, int64_t R, const float *x, int64_t ld_
 
 // Exact energies of int8 spins [R][n] from the caller's original couplings.
 // Integer: e_i64[r] = objective (and e_f64 = (double)e_i64).  Float: e_f64 only.
-// words: scratch of ceil(R/64) * n uint64 (dense problems only).
+// words: scratch of R * ceil(n/64) uint64 (dense problems only).
 int64_t energy_partial_blocks(const qpa_problem &p);
 // Integer CSR instances with many entries per row run their row scan and energies with
 // one wave per row.
