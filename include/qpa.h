@@ -106,14 +106,22 @@ typedef struct {
     const float *lambda_table;  /* host, optional                               */
     uint64_t seed;              /* SplitMix64 seed of the initial state          */
     int32_t precision;          /* qpa_precision (dense path)                   */
-    int32_t flags;              /* 0, QPA_SOLVE_STREAMED (single solves) or one
-                                   qpa_batch_flags value (qpa_solve_batch)      */
+    int32_t flags;              /* single solves: 0 or QPA_SOLVE_STREAMED and/or
+                                   QPA_SOLVE_GRAPH; qpa_solve_batch: 0 or one
+                                   qpa_batch_flags value                        */
 } qpa_params;
 
 /* qpa_solve / qpa_steps: run a sparse instance with the per-step streamed kernel even
  * when its state fits on chip (the default then keeps it resident for all steps).  Both
  * kernels give the same bits. */
 #define QPA_SOLVE_STREAMED 4
+/* qpa_solve / qpa_steps / qpa_sbm_solve / qpa_sbm_steps (may be or-ed with
+ * QPA_SOLVE_STREAMED): launch a step loop that takes one kernel per step as a HIP graph.
+ * The graph is captured on a private stream of the context the first time a call's
+ * launch sequence is seen (same problem arrays, workspace, sizes and step range) and
+ * replayed afterwards; a context keeps the 8 most recent graphs.  Results are identical
+ * to the plain launches.  Paths that run all steps in one launch ignore the flag. */
+#define QPA_SOLVE_GRAPH 8
 
 /* Path choice of qpa_solve_batch (params.flags; qpa_solve requires 0).  By default
  * every instance whose couplings are exact in BF16 (integer weights with |w| <= 256,
@@ -295,7 +303,7 @@ typedef struct {
     float sigma0;               /* amplitude of the initial positions              */
     uint64_t seed;              /* SplitMix64 seed (initial positions, power start) */
     int32_t power_iters;        /* >= 0, power-method iterations when c0 == 0      */
-    int32_t flags;              /* must be 0                                       */
+    int32_t flags;              /* 0 or QPA_SOLVE_GRAPH                            */
 } qpa_sbm_params;
 
 /* Device bytes of workspace for qpa_sbm_solve / qpa_sbm_steps / qpa_spectral_radius

@@ -30,6 +30,14 @@ struct qpa_ctx {
     std::vector<Span> spans;
     std::vector<hipEvent_t> free_events;
     std::vector<int32_t> batch_paths;       // per instance, last qpa_solve_batch
+    // step loops captured as HIP graphs (QPA_SOLVE_GRAPH), keyed by every argument the
+    // captured launches read; captured on a private stream of default priority
+    hipStream_t cap = nullptr;
+    struct Graph {
+        std::vector<uint8_t> key;
+        hipGraphExec_t exec;
+    };
+    std::vector<Graph> graphs;              // most recently used last
 };
 
 namespace qpa {
@@ -94,7 +102,7 @@ Plan make_plan(const qpa_problem &p, const qpa_params &a, int64_t batch_rp = 0, 
     pl.Rp = pl.R;
     pl.G = 1;
     pl.nwords = 0;
-    if (p.format == QPA_FMT_CSR && batch_rp == 0 && cus > 0 && a.flags != QPA_SOLVE_STREAMED &&
+    if (p.format == QPA_FMT_CSR && batch_rp == 0 && cus > 0 && !(a.flags & QPA_SOLVE_STREAMED) &&
         csr_resident_group(pl.n, pl.R, cus) > 0 && csr_resident_lds(pl.n, p.nnz) <= RES_MAX_LDS) {
         pl.path = Path::CsrResident;
         pl.G = csr_resident_group(pl.n, pl.R, cus);
@@ -224,8 +232,8 @@ qpa_status check_params(qpa_ctx *ctx, const qpa_params *a) {
     if (a->steps < 0) return fail(ctx, QPA_E_ARG, "steps must be >= 0");
     if (a->precision != QPA_PREC_FP32 && a->precision != QPA_PREC_BF16)
         return fail(ctx, QPA_E_ARG, "unknown precision %d", a->precision);
-    if (a->flags != 0 && a->flags != QPA_SOLVE_STREAMED)
-        return fail(ctx, QPA_E_ARG, "params.flags must be 0 or QPA_SOLVE_STREAMED");
+    if ((a->flags & ~(QPA_SOLVE_STREAMED | QPA_SOLVE_GRAPH)) != 0)
+        return fail(ctx, QPA_E_ARG, "params.flags: only QPA_SOLVE_STREAMED and QPA_SOLVE_GRAPH");
     return QPA_OK;
 }
 
@@ -316,18 +324,94 @@ qpa_status run_steps_inner(qpa_ctx *ctx, const qpa_problem &p, const qpa_params 
                            const Plan &pl, void *ws, int32_t t0, int32_t t1, bool want_h,
                            hipStream_t st, int64_t &launches, int32_t &ran);
 
+template <typename T> void key_add(std::vector<uint8_t> &k, const T &v) {
+    const uint8_t *b = reinterpret_cast<const uint8_t *>(&v);
+    k.insert(k.end(), b, b + sizeof(T));
+}
+
+constexpr size_t GRAPH_CACHE = 8;
+
+// Launch the step loop `body(stream)` as a HIP graph: captured on the context's private
+// stream the first time a key is seen, then replayed on `st`.  The key holds every value
+// the captured launches read from the host, so a replay is the same launch sequence.
+template <typename F>
+qpa_status run_graph(qpa_ctx *ctx, std::vector<uint8_t> key, hipStream_t st, F &&body) {
+    for (size_t g = 0; g < ctx->graphs.size(); ++g) {
+        if (ctx->graphs[g].key == key) {
+            qpa_ctx::Graph hit = ctx->graphs[g];
+            ctx->graphs.erase(ctx->graphs.begin() + (std::ptrdiff_t)g);
+            ctx->graphs.push_back(hit);
+            QPA_HIP(hipGraphLaunch(hit.exec, st));
+            return QPA_OK;
+        }
+    }
+    if (!ctx->cap) QPA_HIP(hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
+    QPA_HIP(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
+    qpa_status s = body(ctx->cap);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(ctx->cap, &graph);
+    if (s != QPA_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return s;
+    }
+    if (e != hipSuccess) return fail(ctx, QPA_E_DEVICE, "graph capture: %s", hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess)
+        return fail(ctx, QPA_E_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
+    if (ctx->graphs.size() >= GRAPH_CACHE) {
+        (void)hipGraphExecDestroy(ctx->graphs.front().exec);
+        ctx->graphs.erase(ctx->graphs.begin());
+    }
+    ctx->graphs.push_back({std::move(key), exec});
+    QPA_HIP(hipGraphLaunch(exec, st));
+    return QPA_OK;
+}
+
+bool per_step_path(Path p) {
+    return p == Path::DenseTiled || p == Path::DenseMfma || p == Path::Csr;
+}
+
 // Run steps t0 .. t1-1 on the internal state of the plan (timed when profiling).
 qpa_status run_steps(qpa_ctx *ctx, const qpa_problem &p, const qpa_params &a, const Plan &pl,
                      void *ws, int32_t t0, int32_t t1, bool want_h, hipStream_t st) {
     if (t1 <= t0) return QPA_OK;
     int64_t launches = 0;
     int32_t ran = path_code(pl.path);
-    if (!ctx->prof) return run_steps_inner(ctx, p, a, pl, ws, t0, t1, want_h, st, launches, ran);
+    const bool graph = (a.flags & QPA_SOLVE_GRAPH) && per_step_path(pl.path);
+    auto inner = [&](hipStream_t s_) {
+        return run_steps_inner(ctx, p, a, pl, ws, t0, t1, want_h, s_, launches, ran);
+    };
+    auto run = [&]() -> qpa_status {
+        if (!graph) return inner(st);
+        std::vector<uint8_t> key;
+        key_add(key, (int32_t)1);
+        key_add(key, p);
+        key_add(key, (int32_t)pl.path);
+        key_add(key, pl.n);
+        key_add(key, pl.R);
+        key_add(key, pl.np);
+        key_add(key, pl.Rp);
+        key_add(key, pl.G);
+        key_add(key, pl.total);
+        key_add(key, ws);
+        key_add(key, a.eta);
+        key_add(key, a.alpha);
+        key_add(key, a.steps);
+        key_add(key, t0);
+        key_add(key, t1);
+        key_add(key, want_h);
+        qpa_status s_ = run_graph(ctx, std::move(key), st, inner);
+        launches = t1 - t0;
+        return s_;
+    };
+    if (!ctx->prof) return run();
     qpa_ctx::Span sp{};
     QPA_HIP(take_event(ctx, &sp.a));
     QPA_HIP(take_event(ctx, &sp.b));
     QPA_HIP(hipEventRecord(sp.a, st));
-    qpa_status s = run_steps_inner(ctx, p, a, pl, ws, t0, t1, want_h, st, launches, ran);
+    qpa_status s = run();
     QPA_HIP(hipEventRecord(sp.b, st));
     sp.launches = launches;
     sp.path = ran;
@@ -582,7 +666,8 @@ qpa_status check_sbm_params(qpa_ctx *ctx, const qpa_sbm_params *s) {
         return fail(ctx, QPA_E_ARG, "c0 must be >= 0 (0: from the power method)");
     if (!std::isfinite(s->sigma0)) return fail(ctx, QPA_E_ARG, "sigma0 must be finite");
     if (s->power_iters < 0) return fail(ctx, QPA_E_ARG, "power_iters must be >= 0");
-    if (s->flags != 0) return fail(ctx, QPA_E_ARG, "params.flags must be 0");
+    if (s->flags != 0 && s->flags != QPA_SOLVE_GRAPH)
+        return fail(ctx, QPA_E_ARG, "params.flags must be 0 or QPA_SOLVE_GRAPH");
     return QPA_OK;
 }
 
@@ -654,6 +739,8 @@ qpa_status qpa_create(qpa_ctx **out, int device) {
 
 void qpa_destroy(qpa_ctx *ctx) {
     if (!ctx) return;
+    for (auto &g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
+    if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
     if (ctx->host_sc) (void)hipHostFree(ctx->host_sc);
     if (ctx->host_flags) (void)hipHostFree(ctx->host_flags);
     if (ctx->host_lam) (void)hipHostFree(ctx->host_lam);
@@ -1220,13 +1307,37 @@ qpa_status sbm_run(qpa_ctx *ctx, const qpa_problem &p, const qpa_sbm_params &s,
     const float *bf = at<float>(ws, sp.base.o_bf);
     const float *c0 = at<float>(ws, sp.o_c0);
     float *pm = at<float>(ws, sp.o_p), *g = at<float>(ws, sp.o_g);
-    for (int32_t t = t0; t < t1; ++t) {
-        volatile float frac = (float)t / (float)s.steps;
-        const float a = s.a0 * frac;
-        QPA_HIP(launch_sbm_step(p, Jf, sp.Rp, bf, c0, a, s.a0, s.dt, qa, qb, pm,
-                                (want_g && t == t1 - 1) ? g : nullptr, st));
-        std::swap(qa, qb);
+    auto loop = [&](hipStream_t s_) -> qpa_status {
+        float *q_in = qa, *q_out = qb;
+        for (int32_t t = t0; t < t1; ++t) {
+            volatile float frac = (float)t / (float)s.steps;
+            const float a = s.a0 * frac;
+            QPA_HIP(launch_sbm_step(p, Jf, sp.Rp, bf, c0, a, s.a0, s.dt, q_in, q_out, pm,
+                                    (want_g && t == t1 - 1) ? g : nullptr, s_));
+            std::swap(q_in, q_out);
+        }
+        return QPA_OK;
+    };
+    qpa_status rs;
+    if (s.flags & QPA_SOLVE_GRAPH) {
+        std::vector<uint8_t> key;
+        key_add(key, (int32_t)2);
+        key_add(key, p);
+        key_add(key, sp.Rp);
+        key_add(key, sp.total);
+        key_add(key, ws);
+        key_add(key, s.a0);
+        key_add(key, s.dt);
+        key_add(key, s.steps);
+        key_add(key, t0);
+        key_add(key, t1);
+        key_add(key, want_g);
+        rs = run_graph(ctx, std::move(key), st, loop);
+    } else {
+        rs = loop(st);
     }
+    if (rs != QPA_OK) return rs;
+    if ((t1 - t0) & 1) std::swap(qa, qb);
     *q_last = qa;
     if (ctx->prof) {
         QPA_HIP(hipEventRecord(sp_ev.b, st));

@@ -613,3 +613,46 @@ def test_planted3r_full_workload_sampled(q, eng):
     say("planted3r: best energy %d, planted optimum %d, gap %.4f%%"
         % (int(host(out["energy_i64"])[best]), e_star,
            100.0 * (int(host(out["energy_i64"])[best]) - e_star) / abs(e_star)))
+
+
+# ------------------------------------------------------------------ HIP-graph step loops
+@pytest.mark.parametrize("which", ["mfma", "dense-tiled", "csr-streamed"])
+def test_graph_step_loop_matches_plain_launches(q, eng, which):
+    """QPA_SOLVE_GRAPH replays a captured step loop: every replay, with other work on
+    the stream in between, gives the bits of the plain launches."""
+    import torch
+    if which == "csr-streamed":
+        inst, prec, flags = gen.chimera_ising(4, seed=3), "fp32", q.QPA_SOLVE_STREAMED
+    else:
+        inst, prec, flags = gen.dense_int_ising(300, seed=4), \
+            ("bf16" if which == "mfma" else "fp32"), 0
+    prob = q.Problem.from_instance(inst)
+    R, T = 70, 40
+    say("graph step loop %s" % which)
+    ref = eng.solve(prob, _params(q, R, T, 0.05, 0.8, 3.0, prec=prec, flags=flags),
+                    want_state=True)
+    pg = _params(q, R, T, 0.05, 0.8, 3.0, prec=prec, flags=flags | q.QPA_SOLVE_GRAPH)
+    for rep in range(3):
+        out = eng.solve(prob, pg, want_state=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(out["x"]), host(ref["x"]))
+        assert np.array_equal(host(out["m"]), host(ref["m"]))
+        assert np.array_equal(host(out["energy"]), host(ref["energy"]))
+        # eager work between the replays
+        eng.energy(prob, _params(q, R, T, 0.05, 0.8, 3.0, prec=prec), out["spins"])
+        torch.cuda.synchronize()
+
+
+def test_graph_steps_split_equals_oracle(q, eng):
+    import torch
+    inst = gen.chimera_ising(3, seed=5)
+    R, T = 5, 30
+    prob = q.Problem.from_instance(inst)
+    p = _params(q, R, T, 0.2, 0.8, 5.0, flags=q.QPA_SOLVE_STREAMED | q.QPA_SOLVE_GRAPH)
+    x0, _ = orc.pa_init(inst.n, R, 1, np.float32(0.1))
+    xd = torch.from_numpy(x0.copy()).cuda()
+    md = torch.zeros_like(xd)
+    for t0, t1 in [(0, 11), (11, 30)]:
+        eng.steps(prob, p, t0, t1, xd, md)
+    x, m, _ = _oracle_csr(inst, R, T, orc.lambda_linear(T, 5.0), 0.2, 0.8)
+    assert np.array_equal(host(xd), x) and np.array_equal(host(md), m)

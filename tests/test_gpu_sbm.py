@@ -288,3 +288,20 @@ def test_sbm_chimera16_full_workload_sampled(q, eng):
                   for r in range(wl.replicas)])
     assert np.array_equal(host(out["energy_i64"]), e)
     assert int(host(out["best"])[0]) == int(np.flatnonzero(e == e.min())[0])
+
+
+@pytest.mark.parametrize("which", ["dense", "csr"])
+def test_sbm_graph_matches_plain(q, eng, which):
+    import torch
+    inst = gen.sk_ising(200, 0.1, seed=2) if which == "dense" else gen.chimera_ising(3, seed=2)
+    prob = q.Problem.from_instance(inst)
+    say("sbm graph %s" % which)
+    ref = eng.sbm_solve(prob, q.make_sbm_params(9, 31, 0.5, c0=0.1, seed=4), want_state=True)
+    pg = q.make_sbm_params(9, 31, 0.5, c0=0.1, seed=4, flags=q.QPA_SOLVE_GRAPH)
+    for rep in range(3):
+        out = eng.sbm_solve(prob, pg, want_state=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(out["x"]), host(ref["x"]))
+        assert np.array_equal(host(out["m"]), host(ref["m"]))
+        eng.spectral_radius(prob, pg)
+        torch.cuda.synchronize()
