@@ -358,6 +358,14 @@ def main():
     pcode = qpa.QPA_PREC_BF16 if prec == "bf16" else qpa.QPA_PREC_FP32
     R, T = wl.replicas, wl.steps
     params = qpa.make_params(R, T, wl.eta, wl.alpha, wl.lambda0, wl.sigma0, wl.seed, pcode)
+    tuned = None
+    if not batch and insts[0].csr is not None and insts[0].n <= 8192:
+        # sparse kernel configuration by the library's autotuner (set-up, not timed)
+        choice, ms = eng.autotune(prob, params, 100)
+        tuned = {"choice": "streamed" if choice == 0 else "resident G=%d" % choice,
+                 "probe_ms": dict(zip(["streamed", "G1", "G2", "G4", "G8"], ms)),
+                 "probe_steps": 100}
+        log("autotune: %s" % tuned["choice"])
     dt, out, step_ms, launches, per_path = run_solves(eng, qpa, torch, insts, prob, params,
                                                       a.steps, a.warmup, batch)
     log("timed %d solves in %.3f s" % (a.steps, dt))
@@ -469,6 +477,8 @@ def main():
            "roofline": roof}
     if res_peaks is not None:
         res["measured_peak"] = res_peaks
+    if tuned is not None:
+        res["autotune"] = tuned
     res.update(extra)
 
     if prec == "bf16" and not a.no_fp32_form:

@@ -356,6 +356,28 @@ qpa_status qpa_spectrum(qpa_ctx *ctx, int64_t n, int32_t R, const int8_t *spins,
                         double *out_energy, int32_t *out_count, int32_t *out_first,
                         int32_t *out_distinct);
 
+/* Autotuning of the sparse step kernel (CSR problems).  Times `probe_steps` PA steps
+ * (at most params->steps) of every applicable kernel configuration -- the streamed
+ * per-step kernel and the resident kernel with 1, 2, 4 or 8 replicas per workgroup
+ * where the instance fits on chip -- each from the initial state of `params`, warmed up
+ * once, and records the fastest for this shape (n, nnz, kind, dtypes, replicas) in the
+ * context: later qpa_solve / qpa_steps / qpa_energy calls on the context with the same
+ * shape use it (unless params->flags holds QPA_SOLVE_STREAMED).  Every configuration
+ * gives the same bits.
+ *  workspace: as for qpa_solve (its size does not depend on the choice);
+ *  choice (host, required): 0 = streamed kernel, G = resident kernel with G replicas;
+ *  ms (host, optional, 5 doubles): probe milliseconds of [streamed, G=1, 2, 4, 8], -1
+ *  where a configuration does not apply.
+ * Dense problems return QPA_E_UNSUPPORTED. */
+qpa_status qpa_autotune(qpa_ctx *ctx, const qpa_problem *problem, const qpa_params *params,
+                        int32_t probe_steps, void *workspace, size_t workspace_bytes,
+                        void *stream, int32_t *choice, double *ms);
+
+/* Record a sparse kernel choice for this shape by hand (0 = streamed, or the resident
+ * kernel's replica group 1, 2, 4 or 8 where it applies), as qpa_autotune would. */
+qpa_status qpa_tune_set(qpa_ctx *ctx, const qpa_problem *problem, const qpa_params *params,
+                        int32_t choice);
+
 /* Library version string. */
 const char *qpa_version(void);
 

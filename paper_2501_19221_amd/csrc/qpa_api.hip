@@ -38,6 +38,9 @@ struct qpa_ctx {
         hipGraphExec_t exec;
     };
     std::vector<Graph> graphs;              // most recently used last
+    // sparse kernel choices found by qpa_autotune: shape key -> 0 (streamed kernel) or
+    // the resident kernel's replica group
+    std::vector<std::pair<std::vector<uint8_t>, int32_t>> tuned;
 };
 
 namespace qpa {
@@ -75,8 +78,9 @@ struct Plan {
     Path path;
     int64_t n, R, T;
     int64_t np, Rp;       // padded sizes of the internal state
-    int G;                // CSR replica group
-    int64_t nwords;       // CSR spin words per group
+    int G;                // CSR replica group of the chosen kernel
+    int Gs;               // CSR replica group of the streamed kernel (state / spin layout)
+    int64_t nwords;       // CSR spin words per group (streamed layout)
     bool is_int, is_qubo;
     int64_t eblk;         // energy partial blocks
     // workspace offsets (bytes)
@@ -102,15 +106,21 @@ Plan make_plan(const qpa_problem &p, const qpa_params &a, int64_t batch_rp = 0, 
     pl.Rp = pl.R;
     pl.G = 1;
     pl.nwords = 0;
-    if (p.format == QPA_FMT_CSR && batch_rp == 0 && cus > 0 && !(a.flags & QPA_SOLVE_STREAMED) &&
-        csr_resident_group(pl.n, pl.R, cus) > 0 && csr_resident_lds(pl.n, p.nnz) <= RES_MAX_LDS) {
-        pl.path = Path::CsrResident;
-        pl.G = csr_resident_group(pl.n, pl.R, cus);
-    } else if (p.format == QPA_FMT_CSR) {
+    pl.Gs = 1;
+    if (p.format == QPA_FMT_CSR) {
+        // one workspace layout for both sparse kernels (the streamed kernel's), so that
+        // the choice between them can change without a new workspace
         pl.path = Path::Csr;
-        pl.G = batch_rp > 0 ? 64 : csr_group_size(pl.R);
-        pl.Rp = batch_rp > 0 ? batch_rp : round_up(pl.R, pl.G);
-        pl.nwords = csr_words_per_group(pl.n, pl.G);
+        pl.Gs = batch_rp > 0 ? 64 : csr_group_size(pl.R);
+        pl.G = pl.Gs;
+        pl.Rp = batch_rp > 0 ? batch_rp : round_up(pl.R, pl.Gs);
+        pl.nwords = csr_words_per_group(pl.n, pl.Gs);
+        if (batch_rp == 0 && cus > 0 && !(a.flags & QPA_SOLVE_STREAMED) &&
+            csr_resident_group(pl.n, pl.R, cus) > 0 &&
+            csr_resident_lds(pl.n, p.nnz) <= RES_MAX_LDS) {
+            pl.path = Path::CsrResident;
+            pl.G = csr_resident_group(pl.n, pl.R, cus);
+        }
     } else if (a.precision == QPA_PREC_BF16) {
         pl.path = Path::DenseMfma;
         pl.np = round_up(pl.n, MF_NPAD);
@@ -147,8 +157,10 @@ Plan make_plan(const qpa_problem &p, const qpa_params &a, int64_t batch_rp = 0, 
         case Path::DenseResident: sbytes = 0; break;
         case Path::DenseTiled: sbytes = sizeof(float) * R * n; break;
         case Path::DenseMfma: sbytes = sizeof(uint32_t) * Rp * (np / 8); break;
-        case Path::Csr: sbytes = sizeof(uint64_t) * (size_t)(Rp / pl.G) * (size_t)pl.nwords; break;
-        case Path::CsrResident: sbytes = 0; break;
+        case Path::Csr:
+        case Path::CsrResident:
+            sbytes = sizeof(uint64_t) * (size_t)(Rp / pl.Gs) * (size_t)pl.nwords;
+            break;
     }
     if (!state) sbytes = 0;
     pl.o_s0 = sbytes ? take(sbytes) : 0;
@@ -496,6 +508,43 @@ qpa_status score(qpa_ctx *ctx, const qpa_problem &p, const Plan &pl, void *ws,
     return QPA_OK;
 }
 
+// Key of a sparse instance's shape for the tuned-choice table.
+std::vector<uint8_t> tune_key(const qpa_problem &p, const qpa_params &a) {
+    std::vector<uint8_t> k;
+    key_add(k, p.n);
+    key_add(k, p.nnz);
+    key_add(k, p.kind);
+    key_add(k, p.coupling_dtype);
+    key_add(k, p.index_dtype);
+    key_add(k, a.replicas);
+    return k;
+}
+
+bool resident_ok(const qpa_problem &p, int G) {
+    if (p.n > RES_MAX_N || csr_resident_lds(p.n, p.nnz) > RES_MAX_LDS) return false;
+    const int64_t v = (p.n + 1023) / 1024;
+    const int64_t vp = v <= 1 ? 1 : v <= 2 ? 2 : v <= 4 ? 4 : 8;
+    return v <= 8 && vp * G <= 16;
+}
+
+// Use the kernel qpa_autotune chose for this shape (unless the caller forced the
+// streamed kernel).  Both sparse kernels share the workspace layout.
+void apply_tuning(qpa_ctx *ctx, const qpa_problem &p, const qpa_params &a, Plan &pl) {
+    if (p.format != QPA_FMT_CSR || (a.flags & QPA_SOLVE_STREAMED) || ctx->tuned.empty()) return;
+    const std::vector<uint8_t> k = tune_key(p, a);
+    for (const auto &e : ctx->tuned) {
+        if (e.first != k) continue;
+        if (e.second == 0) {
+            pl.path = Path::Csr;
+            pl.G = pl.Gs;
+        } else if (resident_ok(p, e.second)) {
+            pl.path = Path::CsrResident;
+            pl.G = e.second;
+        }
+        return;
+    }
+}
+
 qpa_status prologue(qpa_ctx *ctx, const qpa_problem *problem, const qpa_params *params,
                     void *ws, size_t ws_bytes, Plan &pl) {
     if (!ctx) return QPA_E_ARG;
@@ -505,6 +554,7 @@ qpa_status prologue(qpa_ctx *ctx, const qpa_problem *problem, const qpa_params *
     s = check_params(ctx, params);
     if (s != QPA_OK) return s;
     pl = make_plan(*problem, *params, 0, ctx->cus);
+    apply_tuning(ctx, *problem, *params, pl);
     if (!ws) return fail(ctx, QPA_E_ARG, "workspace is NULL");
     if ((reinterpret_cast<uintptr_t>(ws) % ALIGN) != 0)
         return fail(ctx, QPA_E_ARG, "workspace must be %zu-byte aligned", ALIGN);
@@ -1436,6 +1486,110 @@ qpa_status qpa_spectral_radius(qpa_ctx *ctx, const qpa_problem *problem,
     s = canonicalise(ctx, *problem, sp.base, workspace, st);
     if (s != QPA_OK) return s;
     return sbm_set_c0(ctx, *problem, *params, sp, workspace, rho, st);
+}
+
+// ---------------------------------------------------------------- autotuning
+namespace {
+void record_choice(qpa_ctx *ctx, const qpa_problem &p, const qpa_params &a, int32_t choice) {
+    std::vector<uint8_t> k = tune_key(p, a);
+    for (auto &e : ctx->tuned)
+        if (e.first == k) {
+            e.second = choice;
+            return;
+        }
+    ctx->tuned.emplace_back(std::move(k), choice);
+}
+}  // namespace
+
+qpa_status qpa_autotune(qpa_ctx *ctx, const qpa_problem *problem, const qpa_params *params,
+                        int32_t probe_steps, void *workspace, size_t workspace_bytes,
+                        void *stream, int32_t *choice, double *ms) {
+    Plan pl;
+    qpa_status s = prologue(ctx, problem, params, workspace, workspace_bytes, pl);
+    if (s != QPA_OK) return s;
+    if (problem->format != QPA_FMT_CSR)
+        return fail(ctx, QPA_E_UNSUPPORTED, "autotuning covers sparse (CSR) problems");
+    if (params->flags & QPA_SOLVE_STREAMED)
+        return fail(ctx, QPA_E_ARG, "QPA_SOLVE_STREAMED leaves nothing to choose");
+    if (probe_steps < 1) return fail(ctx, QPA_E_ARG, "probe_steps must be >= 1");
+    if (!choice) return fail(ctx, QPA_E_ARG, "choice is NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    void *ws = workspace;
+    s = upload_schedule(ctx, *params, at<float>(ws, pl.o_lam), st);
+    if (s != QPA_OK) return s;
+    s = canonicalise(ctx, *problem, pl, ws, st);
+    if (s != QPA_OK) return s;
+    const int32_t t1 = params->steps < probe_steps ? params->steps : probe_steps;
+    float *x = at<float>(ws, pl.o_x), *m = at<float>(ws, pl.o_m);
+    int64_t ld_r, ld_i;
+    state_strides(pl, ld_r, ld_i);
+    hipEvent_t e0, e1;
+    QPA_HIP(hipEventCreate(&e0));
+    QPA_HIP(hipEventCreate(&e1));
+    const int cand[5] = {0, 1, 2, 4, 8};
+    double best = -1.0;
+    int32_t pick = 0;
+    qpa_params a = *params;
+    a.flags &= ~QPA_SOLVE_GRAPH;
+    for (int c = 0; c < 5 && s == QPA_OK; ++c) {
+        if (ms) ms[c] = -1.0;
+        Plan q = pl;
+        if (cand[c] == 0) {
+            q.path = Path::Csr;
+            q.G = q.Gs;
+        } else {
+            if (!resident_ok(*problem, cand[c])) continue;
+            q.path = Path::CsrResident;
+            q.G = cand[c];
+        }
+        float took = 0.0f;
+        for (int rep = 0; rep < 2 && s == QPA_OK; ++rep) {      // first run warms up
+            hipError_t e = launch_init_state(q.n, q.R, params->seed, params->sigma0, x, m, ld_r,
+                                             ld_i, q.Rp, q.np, st);
+            if (e == hipSuccess) e = hipEventRecord(e0, st);
+            if (e != hipSuccess) {
+                s = fail(ctx, QPA_E_DEVICE, "autotune: %s", hipGetErrorString(e));
+                break;
+            }
+            int64_t launches = 0;
+            int32_t ran = 0;
+            if (t1 > 0) s = run_steps_inner(ctx, *problem, a, q, ws, 0, t1, false, st, launches, ran);
+            if (s != QPA_OK) break;
+            e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            if (e == hipSuccess) e = hipEventElapsedTime(&took, e0, e1);
+            if (e != hipSuccess) s = fail(ctx, QPA_E_DEVICE, "autotune: %s", hipGetErrorString(e));
+        }
+        if (s != QPA_OK) break;
+        if (ms) ms[c] = took;
+        if (best < 0.0 || took < best) {
+            best = took;
+            pick = cand[c];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s != QPA_OK) return s;
+    record_choice(ctx, *problem, *params, pick);
+    *choice = pick;
+    return QPA_OK;
+}
+
+qpa_status qpa_tune_set(qpa_ctx *ctx, const qpa_problem *problem, const qpa_params *params,
+                        int32_t choice) {
+    if (!ctx) return QPA_E_ARG;
+    ctx->err.clear();
+    qpa_status s = check_problem(ctx, problem);
+    if (s != QPA_OK) return s;
+    s = check_params(ctx, params);
+    if (s != QPA_OK) return s;
+    if (problem->format != QPA_FMT_CSR)
+        return fail(ctx, QPA_E_UNSUPPORTED, "kernel choices exist for sparse (CSR) problems");
+    if (choice != 0 && !((choice == 1 || choice == 2 || choice == 4 || choice == 8) &&
+                         resident_ok(*problem, choice)))
+        return fail(ctx, QPA_E_ARG, "choice %d does not apply to this instance", choice);
+    record_choice(ctx, *problem, *params, choice);
+    return QPA_OK;
 }
 
 // ---------------------------------------------------------------- spectrum

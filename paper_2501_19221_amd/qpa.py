@@ -49,7 +49,7 @@ EXPORTED = ["qpa_create", "qpa_destroy", "qpa_last_error", "qpa_status_string",
             "qpa_solve_batch", "qpa_workspace_size_relaxed", "qpa_relaxed_grad",
             "qpa_profile_read_path", "qpa_batch_paths", "qpa_workspace_size_sbm",
             "qpa_sbm_solve", "qpa_sbm_steps", "qpa_spectral_radius",
-            "qpa_workspace_size_spectrum", "qpa_spectrum"]
+            "qpa_workspace_size_spectrum", "qpa_spectrum", "qpa_autotune", "qpa_tune_set"]
 
 
 class qpa_problem(ctypes.Structure):
@@ -126,6 +126,11 @@ _sig = {
                            _P]),
     "qpa_spectral_radius": (_S, [_P, ctypes.POINTER(qpa_problem),
                                  ctypes.POINTER(qpa_sbm_params), _P, ctypes.c_size_t, _P, _P]),
+    "qpa_autotune": (_S, [_P, ctypes.POINTER(qpa_problem), ctypes.POINTER(qpa_params),
+                          ctypes.c_int32, _P, ctypes.c_size_t, _P,
+                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
+    "qpa_tune_set": (_S, [_P, ctypes.POINTER(qpa_problem), ctypes.POINTER(qpa_params),
+                          ctypes.c_int32]),
     "qpa_workspace_size_spectrum": (_S, [_P, ctypes.c_int64, ctypes.c_int32,
                                          ctypes.POINTER(ctypes.c_size_t)]),
     "qpa_spectrum": (_S, [_P, ctypes.c_int64, ctypes.c_int32, _P, _P, ctypes.c_int32,
@@ -274,6 +279,19 @@ def qpa_sbm_steps(ctx, problem, params, t0, t1, q, p, g_last, workspace, workspa
 def qpa_spectral_radius(ctx, problem, params, workspace, workspace_bytes, stream, rho):
     _check(ctx, _lib.qpa_spectral_radius(ctx, ctypes.byref(problem), ctypes.byref(params),
                                          workspace, workspace_bytes, stream, rho))
+
+
+def qpa_autotune(ctx, problem, params, probe_steps, workspace, workspace_bytes, stream):
+    """Returns (choice, [ms of streamed, G=1, 2, 4, 8] with -1 where not applicable)."""
+    choice = ctypes.c_int32()
+    ms = (ctypes.c_double * 5)()
+    _check(ctx, _lib.qpa_autotune(ctx, ctypes.byref(problem), ctypes.byref(params), probe_steps,
+                                  workspace, workspace_bytes, stream, ctypes.byref(choice), ms))
+    return choice.value, list(ms)
+
+
+def qpa_tune_set(ctx, problem, params, choice):
+    _check(ctx, _lib.qpa_tune_set(ctx, ctypes.byref(problem), ctypes.byref(params), choice))
 
 
 def qpa_workspace_size_spectrum(ctx, n, R) -> int:
@@ -558,6 +576,16 @@ class Engine:
         qpa_spectral_radius(self.ctx, ps, params, ctypes.c_void_p(ws.data_ptr()), nbytes,
                             self._stream(), _ptr(rho))
         return rho
+
+    def autotune(self, prob: Problem, params: qpa_params, probe_steps=50):
+        """Time the sparse kernel configurations and record the fastest on the context."""
+        ps = prob.struct()
+        ws, nbytes = self.workspace(ps, params)
+        return qpa_autotune(self.ctx, ps, params, probe_steps, ctypes.c_void_p(ws.data_ptr()),
+                            nbytes, self._stream())
+
+    def tune_set(self, prob: Problem, params: qpa_params, choice):
+        qpa_tune_set(self.ctx, prob.struct(), params, choice)
 
     def spectrum(self, spins, energy, k, flags=0):
         """Low-energy spectrum of device samples spins [R,n] int8 / energy [R] float64:

@@ -656,3 +656,30 @@ def test_graph_steps_split_equals_oracle(q, eng):
         eng.steps(prob, p, t0, t1, xd, md)
     x, m, _ = _oracle_csr(inst, R, T, orc.lambda_linear(T, 5.0), 0.2, 0.8)
     assert np.array_equal(host(xd), x) and np.array_equal(host(md), m)
+
+
+# ------------------------------------------------------------------ sparse kernel choice
+def test_sparse_kernel_choices_and_autotune_give_identical_bits(q, eng):
+    inst = gen.chimera_ising(6, seed=7)
+    R, T = 100, 60
+    prob = q.Problem.from_instance(inst)
+    p = _params(q, R, T, 0.2, 0.8, 5.0)
+    x, m, _ = _oracle_csr(inst, R, T, orc.lambda_linear(T, 5.0), 0.2, 0.8)
+    for choice in (0, 1, 2, 4, 8):
+        say("sparse kernel choice %d" % choice)
+        eng.tune_set(prob, p, choice)
+        out = eng.solve(prob, p, want_state=True)
+        assert np.array_equal(host(out["x"]), x) and np.array_equal(host(out["m"]), m)
+    choice, ms = eng.autotune(prob, p, 30)
+    say("autotune choice %d, ms %s" % (choice, ms))
+    assert choice in (0, 1, 2, 4, 8)
+    assert ms[0] > 0 and ms[[0, 1, 2, 4, 8].index(choice)] == min(v for v in ms if v >= 0)
+    out = eng.solve(prob, p, want_state=True)
+    assert np.array_equal(host(out["x"]), x) and np.array_equal(host(out["m"]), m)
+    with pytest.raises(q.QpaError) as ei:
+        eng.tune_set(prob, p, 3)
+    assert ei.value.status == q.QPA_E_ARG
+    dense = q.Problem.from_instance(gen.dense_int_ising(20, seed=1))
+    with pytest.raises(q.QpaError) as ei:
+        eng.autotune(dense, p, 10)
+    assert ei.value.status == q.QPA_E_UNSUPPORTED
