@@ -290,9 +290,22 @@ def bench_sbm(a, torch, qpa, swl):
     qpa.qpa_profile_enable(eng.ctx, False)
     dense = inst.dense is not None
     code = qpa.QPA_PATH_SBM_DENSE if dense else qpa.QPA_PATH_SBM_CSR
-    step_ms, launches = qpa.qpa_profile_read_path(eng.ctx, code, reset=True)
+    step_ms, launches = qpa.qpa_profile_read_path(eng.ctx, code)
+    resident = False
+    if not dense and launches == 0:
+        code = qpa.QPA_PATH_SBM_CSR_RESIDENT
+        step_ms, launches = qpa.qpa_profile_read_path(eng.ctx, code)
+        resident = True
+    qpa.qpa_profile_read(eng.ctx, reset=True)
     avg_s = step_ms / 1e3 / max(1, launches)
-    if dense:
+    if resident:
+        c = inst.csr
+        flops = 2.0 * c.nnz * R * T
+        roof = {"bound": "alu", "achieved": flops / avg_s / 1e12, "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "kernel": "k_sbm_csr_resident",
+                "per_launch": "2*nnz*R*T = %.4g flop (one FMA per stored entry, replica and "
+                              "step; all steps in one launch, state on chip)" % flops}
+    elif dense:
         flops = 2.0 * R * n * n
         roof = {"bound": "alu", "achieved": flops / avg_s / 1e12, "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "kernel": "k_sbm_dense_step",

@@ -251,7 +251,8 @@ typedef enum {
     QPA_PATH_BATCH_DENSE = 5,    /* grouped matrix-core step over many instances  */
     QPA_PATH_CSR_RESIDENT = 6,   /* sparse, state on chip, all steps at once      */
     QPA_PATH_SBM_DENSE = 7,      /* SBM step, dense FP32 couplings                */
-    QPA_PATH_SBM_CSR = 8         /* SBM step, sparse couplings                    */
+    QPA_PATH_SBM_CSR = 8,        /* SBM step, sparse couplings                    */
+    QPA_PATH_SBM_CSR_RESIDENT = 9 /* SBM, sparse, state on chip, all steps at once */
 } qpa_path;
 
 /* Measurement of the PA-step kernels.  While enabled (enable != 0), every qpa_solve,
@@ -303,7 +304,9 @@ typedef struct {
     float sigma0;               /* amplitude of the initial positions              */
     uint64_t seed;              /* SplitMix64 seed (initial positions, power start) */
     int32_t power_iters;        /* >= 0, power-method iterations when c0 == 0      */
-    int32_t flags;              /* 0 or QPA_SOLVE_GRAPH                            */
+    int32_t flags;              /* 0, QPA_SOLVE_STREAMED (sparse: per-step kernel
+                                   even where the state fits on chip) and/or
+                                   QPA_SOLVE_GRAPH                               */
 } qpa_sbm_params;
 
 /* Device bytes of workspace for qpa_sbm_solve / qpa_sbm_steps / qpa_spectral_radius

@@ -278,6 +278,141 @@ __global__ void __launch_bounds__(256) k_sbm_csr_step(int64_t n, int64_t Rp, int
     if (gout) gout[idx] = g;
 }
 
+// Resident CSR steps: one launch runs every step.  A workgroup owns G replicas and every
+// variable; thread t owns variables t, t + 1024, ... (VPT of them) and keeps their q, p in
+// registers for all steps.  The CSR structure (row pointers int32, columns uint16,
+// weights FP32) and the positions of the G replicas ([n][G] FP32) live in LDS.  A step
+// computes every owned field from LDS (one fused multiply-add per entry and replica, in
+// row order, as the streamed kernel), a barrier, the update and the new positions into
+// LDS, a barrier.  a(t) comes from a table the host fills with the same FP32 expression
+// as the per-step launches.
+constexpr int SRT = 1024;
+
+// the G positions of variable j (row j of the [n][G] LDS array)
+template <int G>
+__device__ __forceinline__ void sbm_lds_read(const float *qv, int32_t j, float (&out)[G]) {
+    if constexpr (G == 8) {
+        const float4 lo = reinterpret_cast<const float4 *>(qv)[2 * j];
+        const float4 hi = reinterpret_cast<const float4 *>(qv)[2 * j + 1];
+        out[0] = lo.x; out[1] = lo.y; out[2] = lo.z; out[3] = lo.w;
+        out[4] = hi.x; out[5] = hi.y; out[6] = hi.z; out[7] = hi.w;
+    } else if constexpr (G == 4) {
+        const float4 v = reinterpret_cast<const float4 *>(qv)[j];
+        out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
+    } else if constexpr (G == 2) {
+        const float2 v = reinterpret_cast<const float2 *>(qv)[j];
+        out[0] = v.x; out[1] = v.y;
+    } else {
+        out[0] = qv[j];
+    }
+}
+
+template <int G, int VPT>
+__global__ void __launch_bounds__(SRT) k_sbm_csr_resident(
+    int32_t n, int32_t nnz, int64_t R, int64_t Rp, const int32_t *__restrict__ rp_g,
+    const void *__restrict__ col_g, int32_t col_dt, const void *__restrict__ w_g, int32_t w_dt,
+    int32_t skip_diag, const float *__restrict__ b, const float *__restrict__ c0p,
+    const float *__restrict__ atab, float a0, float dt, float *__restrict__ q,
+    float *__restrict__ p, float *__restrict__ gout, int32_t t0, int32_t t1) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+    int32_t *rp = reinterpret_cast<int32_t *>(lds);
+    float *wf = reinterpret_cast<float *>(rp + (n + 1));
+    uint16_t *col = reinterpret_cast<uint16_t *>(wf + nnz);
+    const size_t qoff = ((size_t)(n + 1) * 4 + (size_t)nnz * 6 + 15) & ~(size_t)15;
+    float *qv = reinterpret_cast<float *>(lds + qoff);
+    const int tid = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * G;
+
+    for (int32_t k = tid; k <= n; k += SRT) rp[k] = rp_g[k];
+    for (int32_t k = tid; k < nnz; k += SRT) {
+        col[k] = (uint16_t)(col_dt == QPA_I16 ? (int32_t) static_cast<const int16_t *>(col_g)[k]
+                                              : static_cast<const int32_t *>(col_g)[k]);
+        switch (w_dt) {
+            case QPA_I8: wf[k] = (float)static_cast<const int8_t *>(w_g)[k]; break;
+            case QPA_I16: wf[k] = (float)static_cast<const int16_t *>(w_g)[k]; break;
+            case QPA_I32: wf[k] = (float)static_cast<const int32_t *>(w_g)[k]; break;
+            default: wf[k] = static_cast<const float *>(w_g)[k]; break;
+        }
+    }
+    float qs[VPT][G], ps[VPT][G], gs[VPT][G], bi[VPT];
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+        const int32_t i = tid + u * SRT;
+        bi[u] = 0.0f;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            qs[u][g] = 0.0f;
+            ps[u][g] = 0.0f;
+            gs[u][g] = 0.0f;
+        }
+        if (i < n) {
+            bi[u] = b[i];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                if (r0 + g < R) {
+                    qs[u][g] = q[(int64_t)i * Rp + r0 + g];
+                    ps[u][g] = p[(int64_t)i * Rp + r0 + g];
+                }
+                qv[i * G + g] = qs[u][g];
+            }
+        }
+    }
+    const float c0 = *c0p;
+    const float adt = __fmul_rn(dt, a0);
+    __syncthreads();
+    for (int32_t t = t0; t < t1; ++t) {
+        const float a = atab[t];
+#pragma unroll
+        for (int u = 0; u < VPT; ++u) {
+            const int32_t i = tid + u * SRT;
+            float acc[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) acc[g] = 0.0f;
+            if (i < n) {
+                const int32_t k1 = rp[i + 1];
+                for (int32_t k = rp[i]; k < k1; ++k) {
+                    const int32_t j = col[k];
+                    if (skip_diag && j == i) continue;
+                    const float w = wf[k];
+                    float qj[G];
+                    sbm_lds_read<G>(qv, j, qj);
+#pragma unroll
+                    for (int g = 0; g < G; ++g) acc[g] = __fmaf_rn(w, qj[g], acc[g]);
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g) gs[u][g] = acc[g];
+        }
+        __syncthreads();                    // every read of this step's positions is done
+#pragma unroll
+        for (int u = 0; u < VPT; ++u) {
+            const int32_t i = tid + u * SRT;
+            if (i < n) {
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    float gv;
+                    sbm_point(gs[u][g], bi[u], a, a0, c0, dt, adt, qs[u][g], ps[u][g], gv);
+                    gs[u][g] = gv;
+                    qv[i * G + g] = qs[u][g];
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+        const int32_t i = tid + u * SRT;
+        if (i >= n) continue;
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+            if (r0 + g < R) {
+                q[(int64_t)i * Rp + r0 + g] = qs[u][g];
+                p[(int64_t)i * Rp + r0 + g] = ps[u][g];
+                if (gout && t1 > t0) gout[(int64_t)i * Rp + r0 + g] = gs[u][g];
+            }
+    }
+}
+
 __global__ void k_set_f32(float *dst, float v) {
     if (threadIdx.x == 0 && blockIdx.x == 0) dst[0] = v;
 }
@@ -451,6 +586,73 @@ hipError_t launch_sbm_step(const qpa_problem &p, const float *Jf, int64_t Rp, co
             static_cast<const TW *>(p.weights), skip, b, c0p, a, a0, dt, q_in, q_out, pm, g_out);
         return hipGetLastError();
     });
+}
+
+size_t sbm_resident_lds(int64_t n, int64_t nnz, int G) {
+    return (((size_t)(n + 1) * 4 + (size_t)nnz * 6 + 15) & ~(size_t)15) + (size_t)n * G * 4;
+}
+
+static int sbm_vpt(int64_t n) {
+    const int64_t v = (n + SRT - 1) / SRT;
+    return v <= 1 ? 1 : v <= 2 ? 2 : v <= 4 ? 4 : v <= 8 ? 8 : 0;
+}
+
+int sbm_resident_group(const qpa_problem &p, int64_t R, int cus) {
+    if (p.format != QPA_FMT_CSR || p.n < 1 || p.n > RES_MAX_N || p.nnz > INT32_MAX) return 0;
+    const int v = sbm_vpt(p.n);
+    if (v == 0) return 0;
+    for (int G = 8; G >= 1; G >>= 1) {
+        if (v * G > 16 || sbm_resident_lds(p.n, p.nnz, G) > RES_MAX_LDS) continue;
+        if (G > 1 && (R + G - 1) / G < cus) continue;
+        return G;
+    }
+    return 0;
+}
+
+template <int G, int VPT>
+static hipError_t launch_sbm_res_gv(const qpa_problem &pr, int64_t R, int64_t Rp, const float *b,
+                                    const float *c0p, const float *atab, float a0, float dt,
+                                    float *q, float *pm, float *g_out, int32_t t0, int32_t t1,
+                                    hipStream_t st) {
+    const size_t lds = sbm_resident_lds(pr.n, pr.nnz, G);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sbm_csr_resident<G, VPT>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipGetLastError();
+    const unsigned blocks = (unsigned)((R + G - 1) / G);
+    k_sbm_csr_resident<G, VPT><<<blocks, SRT, lds, st>>>(
+        (int32_t)pr.n, (int32_t)pr.nnz, R, Rp, pr.row_ptr, pr.col, pr.index_dtype, pr.weights,
+        pr.coupling_dtype, pr.kind == QPA_KIND_QUBO ? 1 : 0, b, c0p, atab, a0, dt, q, pm, g_out,
+        t0, t1);
+    return hipGetLastError();
+}
+
+hipError_t launch_sbm_resident(const qpa_problem &pr, int G, int64_t R, int64_t Rp,
+                               const float *b, const float *c0p, const float *atab, float a0,
+                               float dt, float *q, float *pm, float *g_out, int32_t t0,
+                               int32_t t1, hipStream_t st) {
+    if (t1 <= t0) return hipSuccess;
+    const int v = sbm_vpt(pr.n);
+    if (v == 0 || v * G > 16 || sbm_resident_lds(pr.n, pr.nnz, G) > RES_MAX_LDS)
+        return hipErrorInvalidValue;
+#define QPA_SBM_RES(GG, VV)                                                                   \
+    if (G == GG && v == VV)                                                                   \
+        return launch_sbm_res_gv<GG, VV>(pr, R, Rp, b, c0p, atab, a0, dt, q, pm, g_out, t0, t1, \
+                                         st);
+    QPA_SBM_RES(8, 1)
+    QPA_SBM_RES(8, 2)
+    QPA_SBM_RES(4, 1)
+    QPA_SBM_RES(4, 2)
+    QPA_SBM_RES(4, 4)
+    QPA_SBM_RES(2, 1)
+    QPA_SBM_RES(2, 2)
+    QPA_SBM_RES(2, 4)
+    QPA_SBM_RES(2, 8)
+    QPA_SBM_RES(1, 1)
+    QPA_SBM_RES(1, 2)
+    QPA_SBM_RES(1, 4)
+    QPA_SBM_RES(1, 8)
+#undef QPA_SBM_RES
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_set_f32(float *dst, float v, hipStream_t st) {

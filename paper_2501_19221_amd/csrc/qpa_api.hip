@@ -703,7 +703,8 @@ qpa_status make_batch_plan(qpa_ctx *ctx, int32_t count, const qpa_problem *probs
 struct SbmPlan {
     Plan base;
     int64_t Rp, pblk;
-    size_t o_q0, o_q1, o_p, o_g, o_c0, o_pv, o_pw, o_pp, o_nrm, total;
+    int Gres;                 // replicas per workgroup of the resident sparse kernel, 0: none
+    size_t o_q0, o_q1, o_p, o_g, o_c0, o_pv, o_pw, o_pp, o_nrm, o_atab, total;
 };
 
 qpa_status check_sbm_params(qpa_ctx *ctx, const qpa_sbm_params *s) {
@@ -716,12 +717,12 @@ qpa_status check_sbm_params(qpa_ctx *ctx, const qpa_sbm_params *s) {
         return fail(ctx, QPA_E_ARG, "c0 must be >= 0 (0: from the power method)");
     if (!std::isfinite(s->sigma0)) return fail(ctx, QPA_E_ARG, "sigma0 must be finite");
     if (s->power_iters < 0) return fail(ctx, QPA_E_ARG, "power_iters must be >= 0");
-    if (s->flags != 0 && s->flags != QPA_SOLVE_GRAPH)
-        return fail(ctx, QPA_E_ARG, "params.flags must be 0 or QPA_SOLVE_GRAPH");
+    if ((s->flags & ~(QPA_SOLVE_GRAPH | QPA_SOLVE_STREAMED)) != 0)
+        return fail(ctx, QPA_E_ARG, "params.flags: only QPA_SOLVE_STREAMED and QPA_SOLVE_GRAPH");
     return QPA_OK;
 }
 
-SbmPlan make_sbm_plan(const qpa_problem &p, const qpa_sbm_params &s) {
+SbmPlan make_sbm_plan(const qpa_problem &p, const qpa_sbm_params &s, int cus = 256) {
     qpa_params a{};
     a.replicas = s.replicas;
     a.steps = 0;
@@ -731,6 +732,7 @@ SbmPlan make_sbm_plan(const qpa_problem &p, const qpa_sbm_params &s) {
     sp.base = make_plan(p, a, 0, 0, false);
     sp.Rp = sbm_rpad(p, s.replicas);
     sp.pblk = pw_blocks(p);
+    sp.Gres = (s.flags & QPA_SOLVE_STREAMED) ? 0 : sbm_resident_group(p, s.replicas, cus);
     size_t off = sp.base.total;
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -747,6 +749,7 @@ SbmPlan make_sbm_plan(const qpa_problem &p, const qpa_sbm_params &s) {
     sp.o_pw = take(sizeof(double) * (size_t)p.n);
     sp.o_pp = take(sizeof(double) * (size_t)sp.pblk);
     sp.o_nrm = take(sizeof(double) * 2);
+    sp.o_atab = take(sizeof(float) * (size_t)std::max<int32_t>(s.steps, 1));
     sp.total = off;
     return sp;
 }
@@ -843,7 +846,7 @@ qpa_status qpa_batch_paths(const qpa_ctx *ctx, int32_t count, int32_t *paths) {
 qpa_status qpa_profile_read_path(qpa_ctx *ctx, int32_t path, double *step_ms,
                                  int64_t *step_launches, int32_t reset) {
     if (!ctx || !step_ms || !step_launches) return QPA_E_ARG;
-    if (path < QPA_PATH_ALL || path > QPA_PATH_SBM_CSR)
+    if (path < QPA_PATH_ALL || path > QPA_PATH_SBM_CSR_RESIDENT)
         return fail(ctx, QPA_E_ARG, "unknown path %d", path);
     double total = 0.0;
     int64_t n = 0;
@@ -1314,7 +1317,7 @@ qpa_status sbm_prologue(qpa_ctx *ctx, const qpa_problem *problem, const qpa_sbm_
     if (s != QPA_OK) return s;
     s = check_sbm_params(ctx, params);
     if (s != QPA_OK) return s;
-    sp = make_sbm_plan(*problem, *params);
+    sp = make_sbm_plan(*problem, *params, ctx->cus);
     if (!ws) return fail(ctx, QPA_E_ARG, "workspace is NULL");
     if ((reinterpret_cast<uintptr_t>(ws) % ALIGN) != 0)
         return fail(ctx, QPA_E_ARG, "workspace must be %zu-byte aligned", ALIGN);
@@ -1340,6 +1343,28 @@ qpa_status sbm_set_c0(qpa_ctx *ctx, const qpa_problem &p, const qpa_sbm_params &
     return QPA_OK;
 }
 
+// a(t) = a0 * ((float)t / (float)T) for every step, the expression the per-step launches
+// evaluate, staged through the pinned schedule buffer.
+qpa_status upload_sbm_schedule(qpa_ctx *ctx, const qpa_sbm_params &s, float *d_a,
+                               hipStream_t st) {
+    const int64_t T = s.steps;
+    if (T == 0) return QPA_OK;
+    if (ctx->host_lam_cap < (size_t)T) {
+        if (ctx->host_lam) (void)hipHostFree(ctx->host_lam);
+        ctx->host_lam = nullptr;
+        QPA_HIP(hipHostMalloc((void **)&ctx->host_lam, sizeof(float) * (size_t)T));
+        ctx->host_lam_cap = (size_t)T;
+    }
+    QPA_HIP(hipStreamSynchronize(st));
+    for (int64_t t = 0; t < T; ++t) {
+        volatile float frac = (float)t / (float)T;
+        ctx->host_lam[t] = s.a0 * frac;
+    }
+    QPA_HIP(hipMemcpyAsync(d_a, ctx->host_lam, sizeof(float) * (size_t)T, hipMemcpyHostToDevice,
+                           st));
+    return QPA_OK;
+}
+
 // Steps t0 .. t1-1 from the positions in q0; returns the buffer holding the last ones.
 qpa_status sbm_run(qpa_ctx *ctx, const qpa_problem &p, const qpa_sbm_params &s,
                    const SbmPlan &sp, void *ws, int32_t t0, int32_t t1, bool want_g,
@@ -1347,16 +1372,33 @@ qpa_status sbm_run(qpa_ctx *ctx, const qpa_problem &p, const qpa_sbm_params &s,
     float *qa = at<float>(ws, sp.o_q0), *qb = at<float>(ws, sp.o_q1);
     *q_last = qa;
     if (t1 <= t0) return QPA_OK;
+    const float *Jf = sp.base.o_Jf ? at<float>(ws, sp.base.o_Jf) : nullptr;
+    const float *bf = at<float>(ws, sp.base.o_bf);
+    const float *c0 = at<float>(ws, sp.o_c0);
+    float *pm = at<float>(ws, sp.o_p), *g = at<float>(ws, sp.o_g);
+    const bool resident = p.format == QPA_FMT_CSR && sp.Gres > 0;
+    if (resident) {
+        qpa_status us = upload_sbm_schedule(ctx, s, at<float>(ws, sp.o_atab), st);
+        if (us != QPA_OK) return us;
+    }
     qpa_ctx::Span sp_ev{};
     if (ctx->prof) {
         QPA_HIP(take_event(ctx, &sp_ev.a));
         QPA_HIP(take_event(ctx, &sp_ev.b));
         QPA_HIP(hipEventRecord(sp_ev.a, st));
     }
-    const float *Jf = sp.base.o_Jf ? at<float>(ws, sp.base.o_Jf) : nullptr;
-    const float *bf = at<float>(ws, sp.base.o_bf);
-    const float *c0 = at<float>(ws, sp.o_c0);
-    float *pm = at<float>(ws, sp.o_p), *g = at<float>(ws, sp.o_g);
+    if (resident) {
+        QPA_HIP(launch_sbm_resident(p, sp.Gres, s.replicas, sp.Rp, bf, c0,
+                                    at<float>(ws, sp.o_atab), s.a0, s.dt, qa, pm,
+                                    want_g ? g : nullptr, t0, t1, st));
+        if (ctx->prof) {
+            QPA_HIP(hipEventRecord(sp_ev.b, st));
+            sp_ev.launches = 1;
+            sp_ev.path = QPA_PATH_SBM_CSR_RESIDENT;
+            ctx->spans.push_back(sp_ev);
+        }
+        return QPA_OK;
+    }
     auto loop = [&](hipStream_t s_) -> qpa_status {
         float *q_in = qa, *q_out = qb;
         for (int32_t t = t0; t < t1; ++t) {
@@ -1407,7 +1449,7 @@ qpa_status qpa_workspace_size_sbm(qpa_ctx *ctx, const qpa_problem *problem,
     if (s != QPA_OK) return s;
     s = check_sbm_params(ctx, params);
     if (s != QPA_OK) return s;
-    *bytes = make_sbm_plan(*problem, *params).total;
+    *bytes = make_sbm_plan(*problem, *params, 256).total;
     return QPA_OK;
 }
 

@@ -191,6 +191,13 @@ hipError_t launch_sbm_step(const qpa_problem &p, const float *Jf, int64_t Rp, co
                            const float *c0p, float a, float a0, float dt, const float *q_in,
                            float *q_out, float *pm, float *g_out, hipStream_t st);
 hipError_t launch_set_f32(float *dst, float v, hipStream_t st);
+// Resident CSR SBM steps (n <= RES_MAX_N): all steps in one launch, G replicas per
+// workgroup; atab[t] = a(t).  0 when the instance does not fit.
+int sbm_resident_group(const qpa_problem &p, int64_t R, int cus);
+hipError_t launch_sbm_resident(const qpa_problem &p, int G, int64_t R, int64_t Rp,
+                               const float *b, const float *c0p, const float *atab, float a0,
+                               float dt, float *q, float *pm, float *g_out, int32_t t0,
+                               int32_t t1, hipStream_t st);
 // FP64 power method on the canonical couplings.  v, w: n doubles each; part: pw_blocks
 // doubles; nrm: 2 doubles.  rho (or NULL) receives the estimate of max |lambda|, c0 (or
 // NULL) the float of its reciprocal.

@@ -305,3 +305,43 @@ def test_sbm_graph_matches_plain(q, eng, which):
         assert np.array_equal(host(out["m"]), host(ref["m"]))
         eng.spectral_radius(prob, pg)
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("R", [512, 1024, 2048, 3])
+def test_sbm_resident_groups_match_streamed_and_oracle(q, eng, R):
+    """The resident sparse SBM kernel (replica groups 2, 4, 8 at these sizes, 1 for small
+    R) gives the bits of the per-step kernel and of the oracle."""
+    inst = gen.chimera_ising(16, seed=2)
+    c = inst.csr
+    T, c0, dt = 60, 0.2, 0.5
+    prob = q.Problem.from_instance(inst)
+    say("sbm resident R=%d" % R)
+    out = eng.sbm_solve(prob, q.make_sbm_params(R, T, dt, c0=c0, seed=5), want_state=True)
+    ref = eng.sbm_solve(prob, q.make_sbm_params(R, T, dt, c0=c0, seed=5,
+                                                flags=q.QPA_SOLVE_STREAMED), want_state=True)
+    assert np.array_equal(host(out["x"]), host(ref["x"]))
+    assert np.array_equal(host(out["m"]), host(ref["m"]))
+    qg = host(out["x"])
+    for r in sorted({0, R // 2, R - 1}):
+        qv, _ = orc.pa_init(inst.n, 1, 5, np.float32(0.1), r0=r)
+        p = np.zeros_like(qv)
+        orc.sbm_steps_csr(c.rp, c.col, c.w.astype(np.float32), np.zeros(inst.n, np.float32), qv,
+                          p, 0, T, T, 1.0, c0, dt)
+        assert np.array_equal(qg[r], qv[0])
+
+
+def test_sbm_resident_split_steps_and_fields(q, eng):
+    import torch
+    inst = gen.chimera_ising(5, seed=9)
+    R, T, c0, dt, seed = 300, 40, 0.2, 0.5, 3
+    prob = q.Problem.from_instance(inst)
+    sp = q.make_sbm_params(R, T, dt, c0=c0, seed=seed)
+    x0, _ = orc.pa_init(inst.n, R, seed, np.float32(0.1))
+    qd = torch.from_numpy(x0.copy()).cuda()
+    pd = torch.zeros_like(qd)
+    say("sbm resident split")
+    for t0, t1 in [(0, 13), (13, 13), (13, 40)]:
+        g = eng.sbm_steps(prob, sp, t0, t1, qd, pd, want_g=True)
+    qv, p, gref = _oracle_run(inst, R, T, 1.0, c0, dt, seed, 0.1, want_g=True)
+    assert np.array_equal(host(qd), qv) and np.array_equal(host(pd), p)
+    assert np.array_equal(host(g), gref)
