@@ -465,6 +465,12 @@ def main():
                               "= %.4g B (one PA step of every replica)" % byts}
         e = out["energy"].cpu().numpy()
         extra = {"best_energy": float(e.min()), "best_replica": int(out["best"].cpu()[0])}
+    if not batch and "planted_state" in inst0.meta and inst0.csr is not None:
+        # planted optimum E* = -sum over edges of |w| (every coupling satisfied by s*)
+        c = inst0.csr
+        e_star = -float(np.abs(c.w.astype(np.int64)).sum()) / 2.0
+        extra["planted_energy"] = e_star
+        extra["optimality_gap"] = (extra["best_energy"] - e_star) / abs(e_star)
     roof["frac"] = roof["achieved"] / roof["peak"]
     if not a.no_measured_peaks:
         log("measured peaks")
