@@ -683,3 +683,28 @@ def test_sparse_kernel_choices_and_autotune_give_identical_bits(q, eng):
     with pytest.raises(q.QpaError) as ei:
         eng.autotune(dense, p, 10)
     assert ei.value.status == q.QPA_E_UNSUPPORTED
+
+
+def test_schedule_tuning_lowers_the_relaxed_energy(q, eng):
+    """A few Adam steps on (eta, alpha, lambda) through the adjoint lower the relaxed
+    final energy (the adjoint used to tune schedules)."""
+    import torch
+    rng = np.random.default_rng(4)
+    inst = gen.er_qubo(150, 0.1, 100, rng)
+    prob = q.Problem.from_instance(inst)
+    T, R = 100, 16
+    log_eta = torch.tensor(np.log(2e-4), dtype=torch.float64, requires_grad=True)
+    log_lam0 = torch.tensor(np.log(200.0), dtype=torch.float64, requires_grad=True)
+    alpha = torch.tensor(0.8, dtype=torch.float64)
+    frac = 1.0 - torch.arange(T, dtype=torch.float64) / T
+    opt = torch.optim.Adam([log_eta, log_lam0], lr=0.1)
+    losses = []
+    say("schedule tuning")
+    for _ in range(8):
+        L = q.RelaxedEnergy.apply(torch.exp(log_eta), alpha, torch.exp(log_lam0) * frac, eng,
+                                  prob, R, 0.1, 3, 10)
+        opt.zero_grad()
+        L.backward()
+        opt.step()
+        losses.append(float(L))
+    assert losses[-1] < losses[0]
