@@ -601,6 +601,8 @@ __global__ void __launch_bounds__(256) k_energy_csr_wave(int64_t n,
 // energy[r] = sum over blocks of partial[b][r] (fixed order), then the QUBO constant.
 // For integer instances the partials are exact integers (< 2^53) and the total is taken
 // in int64.
+// One wave per replica: lane l sums partials l, l + 64, ... in order, then a fixed
+// shuffle tree (deterministic; exact int64 sums for integer couplings).
 // twice: the partials sum to 2 H (dense kernel) instead of H.
 __global__ void __launch_bounds__(256) k_energy_finalize(int64_t R, int64_t nblk,
                                                          const double *__restrict__ partial,
@@ -608,18 +610,23 @@ __global__ void __launch_bounds__(256) k_energy_finalize(int64_t R, int64_t nblk
                                                          int32_t twice, const CanonScalars *sc,
                                                          int64_t *__restrict__ e_i64,
                                                          double *__restrict__ e_f64) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (r >= R) return;
     if (is_int) {
         int64_t H = 0;
-        for (int64_t b = 0; b < nblk; ++b) H += (int64_t)partial[b * R + r];
+        for (int64_t b = lane; b < nblk; b += 64) H += (int64_t)partial[b * R + r];
+        for (int o = 32; o > 0; o >>= 1) H += __shfl_xor(H, o);
+        if (lane) return;
         if (twice) H /= 2;
         int64_t E = is_qubo ? (H + sc->K_i64) / 2 : H;
         if (e_i64) e_i64[r] = E;
         e_f64[r] = (double)E;
     } else {
         double H = 0.0;
-        for (int64_t b = 0; b < nblk; ++b) H += partial[b * R + r];
+        for (int64_t b = lane; b < nblk; b += 64) H += partial[b * R + r];
+        for (int o = 32; o > 0; o >>= 1) H += __shfl_xor(H, o);
+        if (lane) return;
         if (twice) H *= 0.5;
         e_f64[r] = is_qubo ? 0.5 * (H + sc->K_f64) : H;
     }
@@ -828,7 +835,7 @@ hipError_t launch_energy(const qpa_problem &p, const int64_t *b_i64, const doubl
         });
     }
     if (e != hipSuccess) return e;
-    k_energy_finalize<<<grid1(R, 256, INT64_MAX), 256, 0, st>>>(
+    k_energy_finalize<<<grid1(R * 64, 256, INT64_MAX), 256, 0, st>>>(
         R, nblk, partial, is_int ? 1 : 0, is_qubo, p.format == QPA_FMT_DENSE ? 1 : 0, sc,
         is_int ? e_i64 : nullptr, e_f64);
     return hipGetLastError();
