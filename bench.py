@@ -390,20 +390,26 @@ def main():
     inst0 = insts[0]
     if batch:
         paths = qpa.qpa_batch_paths(eng.ctx, len(insts))
-        dense = paths == qpa.QPA_PATH_BATCH_DENSE
+        dense = (paths == qpa.QPA_PATH_BATCH_DENSE) | (paths == qpa.QPA_PATH_BATCH_DENSE_I8)
         roofs = {}
         if qpa.QPA_PATH_BATCH_DENSE in per_path:
             pm, pl = per_path[qpa.QPA_PATH_BATCH_DENSE]
             nd = np.array([i.n for i, d in zip(insts, dense) if d], np.float64)
-            # one step: the BF16 coupling matrix read once, x and m read and written
-            byts = float(np.sum(2.0 * nd * nd + 16.0 * R * nd))
+            esz = np.array([1.0 if pth == qpa.QPA_PATH_BATCH_DENSE_I8 else 2.0
+                            for pth, d in zip(paths, dense) if d])
+            # one step: the coupling matrix (int8 or BF16) read once, x and m read and written
+            byts = float(np.sum(esz * nd * nd + 16.0 * R * nd))
+            # launches per step: one per element type present
+            pl = pl / max(1, int(np.any(esz == 1.0)) + int(np.any(esz == 2.0)))
             roofs["dense"] = {
                 "bound": "hbm", "achieved": byts / (pm / 1e3 / pl) / 1e9, "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "kernel": "k_mfma_grouped", "ms": pm, "launches": pl,
                 "instances": int(dense.sum()),
-                "per_launch": "sum over dense instances of 2n^2 (BF16 couplings) + 16nR "
-                              "(x, m read and written) = %.4g B (one PA step of every "
-                              "replica of every dense instance)" % byts}
+                "per_launch": "sum over dense instances of n^2 (int8 couplings) or 2n^2 "
+                              "(BF16) + 16nR (x, m read and written) = %.4g B (one PA step "
+                              "of every replica of every dense instance; 'launch' = the "
+                              "grouped launches of one step)" % byts,
+                "int8_instances": int(np.sum(paths == qpa.QPA_PATH_BATCH_DENSE_I8))}
         if qpa.QPA_PATH_BATCH_SPARSE in per_path:
             pm, pl = per_path[qpa.QPA_PATH_BATCH_SPARSE]
             nnz = sum(i.csr.nnz for i, d in zip(insts, dense) if not d)

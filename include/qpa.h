@@ -191,9 +191,11 @@ qpa_status qpa_solve(qpa_ctx *ctx, const qpa_problem *problem, const qpa_params 
  *  - sparse: tasks (instance, group of 64 replicas), sorted by stored entries, largest
  *    first, taken by the workgroups of one persistent launch from an atomic counter;
  *    no workgroup waits on another;
- *  - dense: the couplings are expanded once into a BF16 matrix (exact, see above) and
- *    every PA step is one grouped matrix-core launch over the 128x128 tiles of all such
- *    instances.  Integer instances give the same bits on both paths.
+ *  - dense: the couplings are expanded once into a BF16 matrix (exact, see above), or an
+ *    int8 matrix for integer weights with |w| <= 127 (v_mfma_i32_32x32x32_i8, exact int32
+ *    sums, half the coupling bytes), and every PA step is one grouped matrix-core launch
+ *    over the 128x128 tiles of all such instances (one per element type).  Integer
+ *    instances give the same bits on every path.
  * Errors name the offending instance in qpa_last_error(). */
 qpa_status qpa_workspace_size_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *problems,
                                     const qpa_params *params, size_t *bytes);
@@ -252,7 +254,10 @@ typedef enum {
     QPA_PATH_CSR_RESIDENT = 6,   /* sparse, state on chip, all steps at once      */
     QPA_PATH_SBM_DENSE = 7,      /* SBM step, dense FP32 couplings                */
     QPA_PATH_SBM_CSR = 8,        /* SBM step, sparse couplings                    */
-    QPA_PATH_SBM_CSR_RESIDENT = 9 /* SBM, sparse, state on chip, all steps at once */
+    QPA_PATH_SBM_CSR_RESIDENT = 9, /* SBM, sparse, state on chip, all steps at once */
+    QPA_PATH_BATCH_DENSE_I8 = 10 /* qpa_batch_paths: grouped matrix-core step with int8
+                                    couplings (integer |w| <= 127); timed under
+                                    QPA_PATH_BATCH_DENSE                           */
 } qpa_path;
 
 /* Measurement of the PA-step kernels.  While enabled (enable != 0), every qpa_solve,
@@ -270,9 +275,9 @@ qpa_status qpa_profile_read(qpa_ctx *ctx, double *step_ms, int64_t *step_launche
 qpa_status qpa_profile_read_path(qpa_ctx *ctx, int32_t path, double *step_ms,
                                  int64_t *step_launches, int32_t reset);
 
-/* The path (QPA_PATH_BATCH_SPARSE or QPA_PATH_BATCH_DENSE) that each instance of the
- * last successful qpa_solve_batch on this context took; `count` must equal that call's
- * count.  paths: host array of `count` int32. */
+/* The path (QPA_PATH_BATCH_SPARSE, QPA_PATH_BATCH_DENSE or QPA_PATH_BATCH_DENSE_I8) that
+ * each instance of the last successful qpa_solve_batch on this context took; `count` must
+ * equal that call's count.  paths: host array of `count` int32. */
 qpa_status qpa_batch_paths(const qpa_ctx *ctx, int32_t count, int32_t *paths);
 
 /* ---------------------------------------------------------------------------------

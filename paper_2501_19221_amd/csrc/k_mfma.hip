@@ -42,6 +42,8 @@ namespace qpa {
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
@@ -52,6 +54,15 @@ constexpr int SSTG = BM * 64;                // spin words of a stage: 128 rows 
 constexpr int STG = JSTG + SSTG;
 constexpr int NST = 4;                       // stages
 constexpr int LDS_BYTES = NST * STG;
+// Integer couplings with |J| <= 127 (exact in int8): J rows of 128 bytes, spins one byte
+// per (replica, variable) (+1 = 0x01, -1 = 0xFF), chunk-major like the pair words (128
+// bytes per replica and chunk), v_mfma_i32_32x32x32_i8 with exact int32 sums.
+constexpr int JSTG8 = BN * KC;               // 128 rows x 128 bytes
+constexpr int SSTG8 = BM * KC;               // 128 replicas x 128 bytes
+constexpr int STG8 = JSTG8 + SSTG8;
+constexpr int NST8 = 5;
+static_assert(NST8 * STG8 <= LDS_BYTES, "int8 stages fit the same LDS");
+constexpr int LOADS_PER_CHUNK8 = 4;          // per matrix wave: 2 J pieces + 2 spin pieces
 constexpr int HS = BN + 8;                   // row stride of the field handoff (floats)
 constexpr int THREADS = 1024;                // 8 matrix waves + 8 state waves
 constexpr int MW = 8;                        // matrix waves
@@ -229,6 +240,101 @@ __device__ __forceinline__ void matrix_step(uint8_t *lds, const Tile &tl, int nc
     }
 }
 
+// ---- matrix waves, int8 couplings ---------------------------------------------------
+// As matrix_step with J and spins as bytes: per chunk two 1 KiB loads of J (rows
+// 16w + 8u + lane/8, position lane % 8 holding piece (lane % 8) ^ (row % 8)) and two of
+// spins (replica rows likewise) per wave; four k steps of 32 (wave kh takes 2 kh and
+// 2 kh + 1); the operand of k step q and lane half h is piece 2 q + h of the row.
+__device__ __forceinline__ void matrix_step_i8(uint8_t *lds, const Tile &tl, int nchunk,
+                                               const uint8_t *__restrict__ s_cur, int wave,
+                                               int lane) {
+    const int64_t np = tl.np, I0 = tl.I0, R0 = tl.R0;
+    const uint8_t *__restrict__ J8 = reinterpret_cast<const uint8_t *>(tl.Jb);
+    float *hs = reinterpret_cast<float *>(lds);
+    const int kh = wave >> 2;                      // k steps 2 kh, 2 kh + 1 of a chunk
+    const int wr = (wave >> 1) & 1, wc = wave & 1;
+    const int half = lane >> 5, l32 = lane & 31;
+    const uint8_t *gJ[2], *gS[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int row = 16 * wave + 8 * u + (lane >> 3);
+        const int piece = (lane & 7) ^ (row & 7);
+        gJ[u] = J8 + (I0 + row) * np + 16 * piece;
+        gS[u] = s_cur + (R0 + row) * KC + 16 * piece;
+    }
+    const int64_t sstride = tl.Rp * KC;            // bytes between consecutive spin chunks
+    auto stage = [&](int kc, int st) {
+        kc = kc < nchunk ? kc : nchunk - 1;        // past the end: reload the last chunk
+        uint8_t *dst = lds + st * STG8;
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+            __builtin_amdgcn_global_load_lds(gJ[u] + (int64_t)kc * KC,
+                                             (lds_void *)(dst + (2 * wave + u) * 1024), 16, 0, 0);
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+            __builtin_amdgcn_global_load_lds(gS[u] + (int64_t)kc * sstride,
+                                             (lds_void *)(dst + JSTG8 + (2 * wave + u) * 1024),
+                                             16, 0, 0);
+    };
+    i32x16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[i][j][v] = 0;
+
+#pragma unroll
+    for (int s = 0; s < NST8 - 1; ++s) stage(s, s);
+    for (int c = 0; c < nchunk; ++c) {
+        wait_barrier<(NST8 - 2) * LOADS_PER_CHUNK8>();
+        stage(c + NST8 - 1, (c + NST8 - 1) % NST8);
+        const uint8_t *src = lds + (c % NST8) * STG8;
+#pragma unroll
+        for (int qq = 0; qq < 2; ++qq) {
+            const int piece = 2 * (2 * kh + qq) + half;
+            i32x4 a[2], bq[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int row = 64 * wr + 32 * i + l32;
+                a[i] = *reinterpret_cast<const i32x4 *>(src + JSTG8 + row * KC +
+                                                        16 * (piece ^ (row & 7)));
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int row = 64 * wc + 32 * j + l32;
+                bq[j] = *reinterpret_cast<const i32x4 *>(src + row * KC + 16 * (piece ^ (row & 7)));
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], bq[j], acc[i][j], 0,
+                                                                      0, 0);
+        }
+    }
+    wait_barrier<0>();
+    // exact integer sums (rows are validated below 2^24) go to the state waves as floats
+#pragma unroll
+    for (int pass = 0; pass < 2; ++pass) {
+        if (kh == pass) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) {
+                        const int row = 64 * wr + 32 * i + 8 * (v >> 2) + 4 * half + (v & 3);
+                        const int col = 64 * wc + 32 * j + l32;
+                        float *hp = hs + row * HS + col;
+                        const float f = (float)acc[i][j][v];
+                        *hp = pass == 0 ? f : *hp + f;
+                    }
+        }
+        wait_barrier<0>();
+    }
+}
+
 // ---- state waves: thread t (0..511) owns column t % 128 of rows 4e + t / 128 ---------
 // Row pointers are wave-uniform and advanced one row pair at a time through an opaque
 // step, so that the compiler computes each address when it is used instead of holding
@@ -286,12 +392,32 @@ __device__ __forceinline__ void state_collect(StateRegs &st) {
 // the loop lanes 0..15 turn them into 16-byte stores (the even (ln = 0) or odd (ln = 1)
 // bytes of their row).  With h_last the fields are stored by a second pass.  Executes no
 // barrier.
+template <bool I8>
 __device__ __forceinline__ void state_update(StateRegs &st, const Tile &tl, const float *hs,
                                              uint32_t *__restrict__ s_nxt,
                                              float *__restrict__ h_last, int t, int wave,
                                              int lane, float lt, float eta, float alpha) {
     const int col = t & (BN - 1);
     const int rsub = __builtin_amdgcn_readfirstlane(t >> 7);
+    if (I8) {
+        // spins as bytes: row r of chunk I0/128 at (chunk * Rp + r) * 128 + col
+        uint8_t *srow = reinterpret_cast<uint8_t *>(s_nxt) +
+                        ((tl.I0 / KC) * tl.Rp + tl.R0 + rsub) * KC + col;
+#pragma unroll
+        for (int g = 0; g < SR / 8; ++g) {
+            float hv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) hv[u] = hs[(4 * (8 * g + u) + rsub) * HS + col];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = 8 * g + u;
+                const bool live = tl.R0 + 4 * e + rsub < tl.rlive;
+                const float h = __fadd_rn(__fmul_rn(hv[u], tl.scale), st.bi);
+                pa_update(h, lt, eta, alpha, st.xv[e], st.mv[e]);
+                srow[(int64_t)4 * e * KC] = (live && st.xv[e] < 0.0f) ? (uint8_t)0xFF : (uint8_t)0x01;
+            }
+        }
+    } else {
     const int u_mine = (lane >> 1) & 7;
     uint64_t mine[SR / 8];
 #pragma unroll
@@ -327,6 +453,7 @@ __device__ __forceinline__ void state_update(StateRegs &st, const Tile &tl, cons
             *reinterpret_cast<u32x4 *>(wrow + 64 * (8 * g + u_mine)) = wq;
         }
     }
+    }
     if (h_last) {
         float *hr = h_last + (tl.R0 + rsub) * tl.np + tl.I0;
 #pragma unroll
@@ -355,6 +482,7 @@ __device__ __forceinline__ void state_store(const StateRegs &st, const Tile &tl,
 }
 
 // One PA step of one tile: matrix and state waves side by side.
+template <bool I8>
 __device__ __forceinline__ void mfma_tile_step(uint8_t *lds, const Tile &tl,
                                                const uint32_t *__restrict__ s_cur,
                                                uint32_t *__restrict__ s_nxt,
@@ -371,12 +499,15 @@ __device__ __forceinline__ void mfma_tile_step(uint8_t *lds, const Tile &tl,
         barrier();                                     // partial sums stored
         barrier();                                     // field sums in LDS
         state_collect(st);
-        state_update(st, tl, reinterpret_cast<const float *>(lds), s_nxt, h_last, t,
+        state_update<I8>(st, tl, reinterpret_cast<const float *>(lds), s_nxt, h_last, t,
                             wave, lane, lt, eta, alpha);
         state_store(st, tl, t);
         return;
     }
-    matrix_step(lds, tl, nchunk, s_cur, wave, lane);
+    if (I8)
+        matrix_step_i8(lds, tl, nchunk, reinterpret_cast<const uint8_t *>(s_cur), wave, lane);
+    else
+        matrix_step(lds, tl, nchunk, s_cur, wave, lane);
 }
 
 __global__ void __launch_bounds__(THREADS, 1) k_mfma_step(
@@ -388,11 +519,13 @@ __global__ void __launch_bounds__(THREADS, 1) k_mfma_step(
     __shared__ __attribute__((aligned(16))) uint8_t lds[LDS_BYTES];
     const Tile tl{np, Rp, (int64_t)blockIdx.x * BN, (int64_t)blockIdx.y * BM, rlive, Jb, b,
                   sc->scale, x, m};
-    mfma_tile_step(lds, tl, s_cur, s_nxt, h_last, lam[t], eta, alpha);
+    mfma_tile_step<false>(lds, tl, s_cur, s_nxt, h_last, lam[t], eta, alpha);
 }
 
 // Many instances in one launch: block k runs tile k of the table.  Each tile points at
 // its instance's couplings, bias, state and the two spin buffers (picked by step parity).
+// I8: int8 couplings and byte spins (unscaled sums).
+template <bool I8>
 __global__ void __launch_bounds__(THREADS, 1) k_mfma_grouped(const MfmaTile *__restrict__ tiles,
                                                              int t, const float *__restrict__ lam,
                                                              float eta, float alpha) {
@@ -400,8 +533,22 @@ __global__ void __launch_bounds__(THREADS, 1) k_mfma_grouped(const MfmaTile *__r
     const MfmaTile mt = tiles[blockIdx.x];
     const uint32_t *cur = (t & 1) ? mt.s1 : mt.s0;
     uint32_t *nxt = (t & 1) ? mt.s0 : mt.s1;
-    const Tile tl{mt.np, mt.Rp, mt.I0, mt.R0, mt.rlive, mt.Jb, mt.b, mt.sc->scale, mt.x, mt.m};
-    mfma_tile_step(lds, tl, cur, nxt, nullptr, lam[t], eta, alpha);
+    const Tile tl{mt.np, mt.Rp, mt.I0, mt.R0, mt.rlive, mt.Jb, mt.b,
+                  I8 ? 1.0f : mt.sc->scale, mt.x, mt.m};
+    mfma_tile_step<I8>(lds, tl, cur, nxt, nullptr, lam[t], eta, alpha);
+}
+
+// Byte spins of the signs of x (chunk-major, 128 bytes per replica and chunk).
+__global__ void __launch_bounds__(256) k_mfma_pack_i8(int64_t Rp, int64_t np,
+                                                      const float *__restrict__ x,
+                                                      uint8_t *__restrict__ s8) {
+    const int64_t total = Rp * np;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t kc = k / (Rp * KC), rem = k - kc * Rp * KC;
+        const int64_t r = rem / KC, j = rem - r * KC;
+        s8[k] = x[r * np + KC * kc + j] < 0.0f ? (uint8_t)0xFF : (uint8_t)0x01;
+    }
 }
 
 // Pair words of the signs of x (layout above): one thread per word.
@@ -445,10 +592,64 @@ hipError_t launch_mfma_step(int64_t Rp, int64_t np, int64_t rlive, const uint16_
 }
 
 hipError_t launch_mfma_grouped(const MfmaTile *tiles, int32_t ntiles, int32_t t,
-                               const float *lam, float eta, float alpha, hipStream_t st) {
+                               const float *lam, float eta, float alpha, bool i8,
+                               hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
-    k_mfma_grouped<<<(unsigned)ntiles, THREADS, 0, st>>>(tiles, t, lam, eta, alpha);
+    if (i8)
+        k_mfma_grouped<true><<<(unsigned)ntiles, THREADS, 0, st>>>(tiles, t, lam, eta, alpha);
+    else
+        k_mfma_grouped<false><<<(unsigned)ntiles, THREADS, 0, st>>>(tiles, t, lam, eta, alpha);
     return hipGetLastError();
+}
+
+hipError_t launch_mfma_pack_spins_i8(int64_t Rp, int64_t np, const float *x, uint8_t *s8,
+                                     hipStream_t st) {
+    int64_t g = (Rp * np + 255) / 256;
+    if (g > 65536) g = 65536;
+    k_mfma_pack_i8<<<(unsigned)g, 256, 0, st>>>(Rp, np, x, s8);
+    return hipGetLastError();
+}
+
+// Dense int8 copy of a CSR instance (integer weights with |w| <= 127, checked by the
+// caller): J8[i][j] = w_ij for the stored off-diagonal entries, zero elsewhere (the caller
+// clears J8 first).  One wave per row.
+template <typename TW, typename TI>
+__global__ void __launch_bounds__(256) k_csr_to_i8(int64_t n, int64_t np,
+                                                   const int32_t *__restrict__ rp,
+                                                   const TI *__restrict__ col,
+                                                   const TW *__restrict__ w,
+                                                   int8_t *__restrict__ J8) {
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= n) return;
+    for (int64_t k = rp[i] + lane; k < rp[i + 1]; k += 64) {
+        const int64_t j = (int64_t)col[k];
+        if (j == i) continue;
+        J8[i * np + j] = (int8_t)w[k];
+    }
+}
+
+hipError_t launch_csr_to_i8(const qpa_problem &p, int64_t np, int8_t *J8, hipStream_t st) {
+    hipError_t e = hipMemsetAsync(J8, 0, (size_t)(np * np), st);
+    if (e != hipSuccess) return e;
+    const int64_t g = (p.n + 3) / 4;
+    auto run = [&](auto wtag, auto itag) {
+        using TW = decltype(wtag);
+        using TI = decltype(itag);
+        k_csr_to_i8<TW, TI><<<(unsigned)g, 256, 0, st>>>(
+            p.n, np, p.row_ptr, static_cast<const TI *>(p.col),
+            static_cast<const TW *>(p.weights), J8);
+        return hipGetLastError();
+    };
+    auto byw = [&](auto itag) -> hipError_t {
+        switch (p.coupling_dtype) {
+            case QPA_I8: return run((int8_t)0, itag);
+            case QPA_I16: return run((int16_t)0, itag);
+            case QPA_I32: return run((int32_t)0, itag);
+            default: return hipErrorInvalidValue;
+        }
+    };
+    return p.index_dtype == QPA_I16 ? byw((int16_t)0) : byw((int32_t)0);
 }
 
 

@@ -679,8 +679,9 @@ qpa_status make_batch_plan(qpa_ctx *ctx, int32_t count, const qpa_problem *probs
             ds.o_bfp = tk(sizeof(float) * (size_t)np);
             ds.o_x = tk(sizeof(float) * (size_t)(Rp * np));
             ds.o_m = tk(sizeof(float) * (size_t)(Rp * np));
-            ds.o_s0 = tk(sizeof(uint32_t) * (size_t)(Rp * np / 8));
-            ds.o_s1 = tk(sizeof(uint32_t) * (size_t)(Rp * np / 8));
+            // room for byte spins (int8 tiles), twice the pair words of BF16 tiles
+            ds.o_s0 = tk((size_t)(Rp * np));
+            ds.o_s1 = tk((size_t)(Rp * np));
             bp.ntiles_max += (int32_t)((np / MF_BN) * (Rp / MF_BM));
         }
         bp.dense.push_back(ds);
@@ -846,7 +847,7 @@ qpa_status qpa_batch_paths(const qpa_ctx *ctx, int32_t count, int32_t *paths) {
 qpa_status qpa_profile_read_path(qpa_ctx *ctx, int32_t path, double *step_ms,
                                  int64_t *step_launches, int32_t reset) {
     if (!ctx || !step_ms || !step_launches) return QPA_E_ARG;
-    if (path < QPA_PATH_ALL || path > QPA_PATH_SBM_CSR_RESIDENT)
+    if (path < QPA_PATH_ALL || path > QPA_PATH_BATCH_DENSE_I8)
         return fail(ctx, QPA_E_ARG, "unknown path %d", path);
     double total = 0.0;
     int64_t n = 0;
@@ -1085,15 +1086,18 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
                         hsc[k].max_row);
     }
 
-    // dense BF16 tiles for the candidates whose couplings are exact in BF16
+    // dense tiles for the candidates whose couplings are exact in BF16: int8 tiles for
+    // integer weights with |w| <= 127 (exact int32 sums), BF16 tiles otherwise
     const int64_t R = params->replicas;
     std::vector<char> is_dense(count, 0);
-    std::vector<MfmaTile> tiles;
+    std::vector<MfmaTile> tiles, tiles8;
     for (int32_t k = 0; k < count; ++k) {
         const DenseSlot &ds = bp.dense[k];
         if (!ds.cand) continue;
         if (bp.inst[k].is_int && hsc[k].max_abs > 256.0) continue;
-        is_dense[k] = 1;
+        const bool i8 = bp.inst[k].is_int && hsc[k].max_abs <= 127.0 &&
+                        problems[k].coupling_dtype != QPA_F32;
+        is_dense[k] = i8 ? 2 : 1;
         const Plan &pl = bp.inst[k];
         char *iw = ws + bp.base[k];
         const qpa_problem &p = problems[k];
@@ -1104,13 +1108,20 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
         uint32_t *s0 = reinterpret_cast<uint32_t *>(ws + ds.o_s0);
         uint32_t *s1 = reinterpret_cast<uint32_t *>(ws + ds.o_s1);
         const CanonScalars *sc = at<CanonScalars>(iw, pl.o_sc);
-        QPA_HIP(launch_csr_to_bf16(p, ds.np, sc, Jb, st));
+        if (i8)
+            QPA_HIP(launch_csr_to_i8(p, ds.np, reinterpret_cast<int8_t *>(Jb), st));
+        else
+            QPA_HIP(launch_csr_to_bf16(p, ds.np, sc, Jb, st));
         QPA_HIP(hipMemsetAsync(bfp, 0, sizeof(float) * (size_t)ds.np, st));
         QPA_HIP(hipMemcpyAsync(bfp, at<float>(iw, pl.o_bf), sizeof(float) * (size_t)p.n,
                                hipMemcpyDeviceToDevice, st));
         QPA_HIP(launch_init_state(p.n, R, params->seed + (uint64_t)k, params->sigma0, dx, dm,
                                   ds.np, 1, ds.Rp, ds.np, st));
-        QPA_HIP(launch_mfma_pack_spins(ds.Rp, ds.np, dx, s0, st));
+        if (i8)
+            QPA_HIP(launch_mfma_pack_spins_i8(ds.Rp, ds.np, dx, reinterpret_cast<uint8_t *>(s0),
+                                              st));
+        else
+            QPA_HIP(launch_mfma_pack_spins(ds.Rp, ds.np, dx, s0, st));
         for (int64_t rb = 0; rb < ds.Rp / MF_BM; ++rb)
             for (int64_t ib = 0; ib < ds.np / MF_BN; ++ib) {
                 MfmaTile tl{};
@@ -1126,12 +1137,16 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
                 tl.I0 = ib * MF_BN;
                 tl.R0 = rb * MF_BM;
                 tl.rlive = R;
-                tiles.push_back(tl);
+                (i8 ? tiles8 : tiles).push_back(tl);
             }
     }
-    // largest instances first so that the tail of each step is made of small tiles
-    std::stable_sort(tiles.begin(), tiles.end(),
-                     [](const MfmaTile &a, const MfmaTile &b) { return a.np > b.np; });
+    // largest instances first so that the tail of each step is made of small tiles; the
+    // int8 tiles follow the BF16 ones in the uploaded table
+    auto by_size = [](const MfmaTile &a, const MfmaTile &b) { return a.np > b.np; };
+    std::stable_sort(tiles.begin(), tiles.end(), by_size);
+    std::stable_sort(tiles8.begin(), tiles8.end(), by_size);
+    const int32_t ntiles16 = (int32_t)tiles.size(), ntiles8 = (int32_t)tiles8.size();
+    tiles.insert(tiles.end(), tiles8.begin(), tiles8.end());
 
     // task table of the CSR instances, largest (most stored entries) first
     std::vector<std::pair<int64_t, BatchTask>> order;
@@ -1188,13 +1203,16 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
             QPA_HIP(take_event(ctx, &sp.b));
             QPA_HIP(hipEventRecord(sp.a, st));
         }
-        for (int32_t t = 0; t < params->steps; ++t)
-            QPA_HIP(launch_mfma_grouped(reinterpret_cast<const MfmaTile *>(ws + bp.o_tiles),
-                                        (int32_t)tiles.size(), t, dlam, params->eta,
-                                        params->alpha, st));
+        const MfmaTile *dt16 = reinterpret_cast<const MfmaTile *>(ws + bp.o_tiles);
+        for (int32_t t = 0; t < params->steps; ++t) {
+            QPA_HIP(launch_mfma_grouped(dt16, ntiles16, t, dlam, params->eta, params->alpha,
+                                        false, st));
+            QPA_HIP(launch_mfma_grouped(dt16 + ntiles16, ntiles8, t, dlam, params->eta,
+                                        params->alpha, true, st));
+        }
         if (ctx->prof) {
             QPA_HIP(hipEventRecord(sp.b, st));
-            sp.launches = params->steps;
+            sp.launches = (int64_t)params->steps * ((ntiles16 > 0) + (ntiles8 > 0));
             sp.path = QPA_PATH_BATCH_DENSE;
             ctx->spans.push_back(sp);
         }
@@ -1253,7 +1271,8 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
     }
     ctx->batch_paths.assign(count, QPA_PATH_BATCH_SPARSE);
     for (int32_t k = 0; k < count; ++k)
-        if (is_dense[k]) ctx->batch_paths[k] = QPA_PATH_BATCH_DENSE;
+        if (is_dense[k])
+            ctx->batch_paths[k] = is_dense[k] == 2 ? QPA_PATH_BATCH_DENSE_I8 : QPA_PATH_BATCH_DENSE;
     return QPA_OK;
 }
 

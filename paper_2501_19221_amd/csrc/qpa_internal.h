@@ -124,8 +124,14 @@ struct MfmaTile {
     float *x, *m;            // [Rp][np] state of the instance
     int64_t np, Rp, I0, R0, rlive;
 };
+// i8: tiles of integer instances with |J| <= 127 (int8 couplings, byte spins).
 hipError_t launch_mfma_grouped(const MfmaTile *tiles, int32_t ntiles, int32_t t,
-                               const float *lam, float eta, float alpha, hipStream_t st);
+                               const float *lam, float eta, float alpha, bool i8,
+                               hipStream_t st);
+// Byte spins (chunk-major, Rp * np bytes) and the int8 couplings of a CSR instance.
+hipError_t launch_mfma_pack_spins_i8(int64_t Rp, int64_t np, const float *x, uint8_t *s8,
+                                     hipStream_t st);
+hipError_t launch_csr_to_i8(const qpa_problem &p, int64_t np, int8_t *J8, hipStream_t st);
 hipError_t launch_csr_to_bf16(const qpa_problem &p, int64_t np, const CanonScalars *sc,
                               uint16_t *Jb, hipStream_t st);
 

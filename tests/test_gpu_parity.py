@@ -438,6 +438,7 @@ def test_batch_uneven_instances_bit_exact(q, eng, path):
     insts = [gen.er_qubo(int(n), 0.1, 100, rng) for n in rng.integers(30, 400, size=9)]
     insts.append(gen.chimera_ising(3, seed=5))          # an Ising instance in the same batch
     insts.append(gen.er_qubo(400, 0.005, 100, rng))     # sparse enough for the sparse kernel
+    insts.append(gen.er_qubo(250, 0.1, 200, rng))       # |w| up to 200: BF16 tiles, not int8
     insts.append(gen.er_qubo(300, 0.2, 300, rng))
     R, T, eta, alpha, lam0 = 70, 60, 0.0002, 0.8, 200.0  # 70 replicas: a full and a partial group
     probs = [q.Problem.from_instance(i) for i in insts]
@@ -450,10 +451,11 @@ def test_batch_uneven_instances_bit_exact(q, eng, path):
     if path == "sparse":
         assert (paths == q.QPA_PATH_BATCH_SPARSE).all()
     elif path == "dense":
-        assert (paths[:-1] == q.QPA_PATH_BATCH_DENSE).all()
+        assert (paths[:-2] == q.QPA_PATH_BATCH_DENSE_I8).all()   # |w| <= 127: int8 tiles
+        assert paths[-2] == q.QPA_PATH_BATCH_DENSE               # |w| <= 200: BF16 tiles
     else:                                                  # the cost model mixes both
-        assert paths[0] == q.QPA_PATH_BATCH_DENSE           # n=379, 10% of pairs
-        assert paths[-2] == q.QPA_PATH_BATCH_SPARSE         # n=400, 0.5% of pairs
+        assert paths[0] == q.QPA_PATH_BATCH_DENSE_I8        # n=379, 10% of pairs
+        assert paths[-3] == q.QPA_PATH_BATCH_SPARSE         # n=400, 0.5% of pairs
     lam = orc.lambda_linear(T, lam0)
     for k, (inst, out) in enumerate(zip(insts, outs)):
         x, m, canon = _oracle_instance(inst, R, T, lam, eta, alpha, seed=11 + k)
