@@ -106,9 +106,9 @@ typedef struct {
     const float *lambda_table;  /* host, optional                               */
     uint64_t seed;              /* SplitMix64 seed of the initial state          */
     int32_t precision;          /* qpa_precision (dense path)                   */
-    int32_t flags;              /* single solves: 0 or QPA_SOLVE_STREAMED and/or
-                                   QPA_SOLVE_GRAPH; qpa_solve_batch: 0 or one
-                                   qpa_batch_flags value                        */
+    int32_t flags;              /* single solves: 0, QPA_SOLVE_STREAMED or
+                                   QPA_SOLVE_BINNED, and/or QPA_SOLVE_GRAPH;
+                                   qpa_solve_batch: 0 or one qpa_batch_flags value */
 } qpa_params;
 
 /* qpa_solve / qpa_steps: run a sparse instance with the per-step streamed kernel even
@@ -122,6 +122,17 @@ typedef struct {
  * replayed afterwards; a context keeps the 8 most recent graphs.  Results are identical
  * to the plain launches.  Paths that run all steps in one launch ignore the flag. */
 #define QPA_SOLVE_GRAPH 8
+/* qpa_solve / qpa_steps: run a sparse instance with the binned step (two streaming
+ * passes per step over an entry order built at the start of the call: the spin bits of
+ * every coupling's column gathered chunk by chunk from LDS, then the fields summed bin
+ * by bin in LDS and the update fused).  Applies to CSR problems with int8 or int16
+ * couplings, integer fields and at most 8 replicas; other problems fail with
+ * QPA_E_UNSUPPORTED.  Without a flag such instances take it when their spin words
+ * (n x replicas rounded up to a power of two, one bit each) exceed 4 MiB, where the
+ * per-row gather of the streamed kernel misses the cache on nearly every coupling.  The
+ * bits equal the streamed kernel's (integer sums are exact in any order).  Excludes
+ * QPA_SOLVE_STREAMED. */
+#define QPA_SOLVE_BINNED 16
 
 /* Path choice of qpa_solve_batch (params.flags; qpa_solve requires 0).  By default
  * every instance whose couplings are exact in BF16 (integer weights with |w| <= 256,
@@ -255,9 +266,10 @@ typedef enum {
     QPA_PATH_SBM_DENSE = 7,      /* SBM step, dense FP32 couplings                */
     QPA_PATH_SBM_CSR = 8,        /* SBM step, sparse couplings                    */
     QPA_PATH_SBM_CSR_RESIDENT = 9, /* SBM, sparse, state on chip, all steps at once */
-    QPA_PATH_BATCH_DENSE_I8 = 10 /* qpa_batch_paths: grouped matrix-core step with int8
+    QPA_PATH_BATCH_DENSE_I8 = 10, /* qpa_batch_paths: grouped matrix-core step with int8
                                     couplings (integer |w| <= 127); timed under
                                     QPA_PATH_BATCH_DENSE                           */
+    QPA_PATH_CSR_BINNED = 11     /* sparse, two streaming passes per step (binned)  */
 } qpa_path;
 
 /* Measurement of the PA-step kernels.  While enabled (enable != 0), every qpa_solve,
@@ -366,23 +378,28 @@ qpa_status qpa_spectrum(qpa_ctx *ctx, int64_t n, int32_t R, const int8_t *spins,
 
 /* Autotuning of the sparse step kernel (CSR problems).  Times `probe_steps` PA steps
  * (at most params->steps) of every applicable kernel configuration -- the streamed
- * per-step kernel and the resident kernel with 1, 2, 4 or 8 replicas per workgroup
- * where the instance fits on chip -- each from the initial state of `params`, warmed up
+ * per-step kernel, the resident kernel with 1, 2, 4 or 8 replicas per workgroup where
+ * the instance fits on chip, and the binned step where it applies (QPA_SOLVE_BINNED)
+ * -- each from the initial state of `params`, warmed up
  * once, and records the fastest for this shape (n, nnz, kind, dtypes, replicas) in the
  * context: later qpa_solve / qpa_steps / qpa_energy calls on the context with the same
- * shape use it (unless params->flags holds QPA_SOLVE_STREAMED).  Every configuration
+ * shape use it (unless params->flags holds QPA_SOLVE_STREAMED or QPA_SOLVE_BINNED).
+ * Every configuration
  * gives the same bits.
  *  workspace: as for qpa_solve (its size does not depend on the choice);
- *  choice (host, required): 0 = streamed kernel, G = resident kernel with G replicas;
- *  ms (host, optional, 5 doubles): probe milliseconds of [streamed, G=1, 2, 4, 8], -1
- *  where a configuration does not apply.
+ *  choice (host, required): 0 = streamed kernel, G = resident kernel with G replicas,
+ *  QPA_TUNE_BINNED = binned step;
+ *  ms (host, optional, 6 doubles): probe milliseconds of [streamed, G=1, 2, 4, 8,
+ *  binned], -1 where a configuration does not apply.
  * Dense problems return QPA_E_UNSUPPORTED. */
 qpa_status qpa_autotune(qpa_ctx *ctx, const qpa_problem *problem, const qpa_params *params,
                         int32_t probe_steps, void *workspace, size_t workspace_bytes,
                         void *stream, int32_t *choice, double *ms);
 
-/* Record a sparse kernel choice for this shape by hand (0 = streamed, or the resident
- * kernel's replica group 1, 2, 4 or 8 where it applies), as qpa_autotune would. */
+/* Record a sparse kernel choice for this shape by hand (0 = streamed, the resident
+ * kernel's replica group 1, 2, 4 or 8, or QPA_TUNE_BINNED, where it applies), as
+ * qpa_autotune would. */
+#define QPA_TUNE_BINNED (-1)
 qpa_status qpa_tune_set(qpa_ctx *ctx, const qpa_problem *problem, const qpa_params *params,
                         int32_t choice);
 

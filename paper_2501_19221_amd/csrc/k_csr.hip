@@ -26,6 +26,8 @@ __device__ __forceinline__ void pa_update(float h, float lam, float eta, float a
     x = y;
 }
 
+constexpr int CSR_BATCH = 4;   // row entries whose loads are issued together
+
 template <typename TW, typename TI, bool INT>
 __global__ void __launch_bounds__(256) k_csr_step(
     int64_t n, int64_t Rp, int G, int shiftG, int64_t nwords, const int32_t *__restrict__ rp,
@@ -41,27 +43,50 @@ __global__ void __launch_bounds__(256) k_csr_step(
     const int64_t i = w * V + vsub;
     const int64_t r = g * G + rl;
     const uint64_t *sg = s_cur + g * nwords;
+    const int wsh = 6 - shiftG;
     bool neg = false;
     if (w < nwords && i < n) {
+        // every load that does not depend on a gathered value is issued up front; the
+        // entries of the row follow in batches of CSR_BATCH (column and weight loads, then
+        // all spin-word gathers, then the sums in entry order), so a wave waits for three
+        // memory round trips per batch instead of two per entry
+        const int64_t gi = i * Rp + r;
         const int64_t k0 = rp[i], k1 = rp[i + 1];
+        float xv = x[gi], mv = m[gi];
+        const float bi = b[i];
         int32_t ai = 0;
         float af = 0.0f;
-        for (int64_t k = k0; k < k1; ++k) {
-            const int64_t j = (int64_t)col[k];
-            if (skip_diag && j == i) continue;
-            const uint64_t word = sg[j >> (6 - shiftG)];
-            const int bit = (int)((word >> (((j & (V - 1)) << shiftG) + rl)) & 1u);
-            if (INT) {
-                const int32_t wk = (int32_t)wts[k];
-                ai += bit ? -wk : wk;
-            } else {
-                const float wk = (float)wts[k];
-                af = __fadd_rn(af, bit ? -wk : wk);
+        auto batch = [&](int64_t kb) {
+            int64_t j[CSR_BATCH];
+            TW wk[CSR_BATCH];
+            uint64_t word[CSR_BATCH];
+#pragma unroll
+            for (int d = 0; d < CSR_BATCH; ++d) {
+                const int64_t k = kb + d < k1 ? kb + d : k1 - 1;   // in bounds: kb < k1
+                j[d] = (int64_t)col[k];
+                wk[d] = wts[k];
             }
-        }
-        const float h = INT ? __fadd_rn((float)ai, b[i]) : __fadd_rn(af, b[i]);
-        const int64_t gi = i * Rp + r;
-        float xv = x[gi], mv = m[gi];
+#pragma unroll
+            for (int d = 0; d < CSR_BATCH; ++d) {
+                word[d] = 0;
+                if (kb + d < k1) word[d] = sg[j[d] >> wsh];
+            }
+#pragma unroll
+            for (int d = 0; d < CSR_BATCH; ++d) {
+                if (kb + d >= k1 || (skip_diag && j[d] == i)) continue;
+                const int bit = (int)((word[d] >> (((j[d] & (V - 1)) << shiftG) + rl)) & 1u);
+                if (INT) {
+                    const int32_t v = (int32_t)wk[d];
+                    ai += bit ? -v : v;
+                } else {
+                    const float v = (float)wk[d];
+                    af = __fadd_rn(af, bit ? -v : v);
+                }
+            }
+        };
+        if (k0 < k1) batch(k0);   // the first batch outside the loop: most rows end in it
+        for (int64_t kb = k0 + CSR_BATCH; kb < k1; kb += CSR_BATCH) batch(kb);
+        const float h = INT ? __fadd_rn((float)ai, bi) : __fadd_rn(af, bi);
         pa_update(h, lam[t], eta, alpha, xv, mv);
         x[gi] = xv;
         m[gi] = mv;

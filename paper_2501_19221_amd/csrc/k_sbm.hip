@@ -244,6 +244,8 @@ __global__ void __launch_bounds__(256) k_sbm_dense_step(int64_t n, int64_t Rp,
 
 // CSR step: lane -> (row, replica).  Wave w covers replica chunk w % (Rp / G) and rows
 // (w / (Rp / G)) * (64 / G) + lane / G.
+constexpr int SBM_BATCH = 4;   // row entries whose loads are issued together
+
 template <typename TW, typename TI>
 __global__ void __launch_bounds__(256) k_sbm_csr_step(int64_t n, int64_t Rp, int G,
                                                       const int32_t *__restrict__ rp,
@@ -263,16 +265,37 @@ __global__ void __launch_bounds__(256) k_sbm_csr_step(int64_t n, int64_t Rp, int
     const int64_t row = (wave / chunks) * (64 / G) + lane / G;
     if (row >= n) return;
     const int64_t r = chunk * G + (lane & (G - 1));
+    // loads that do not depend on a gathered value first, then the row in batches of
+    // SBM_BATCH entries (columns and weights, then the gathers, then the fused
+    // multiply-adds in entry order)
     const int32_t k0 = rp[row], k1 = rp[row + 1];
-    float acc = 0.0f;
-    for (int32_t k = k0; k < k1; ++k) {
-        const int64_t j = (int64_t)col[k];
-        if (skip_diag && j == row) continue;
-        acc = __fmaf_rn((float)w[k], qi[j * Rp + r], acc);
-    }
     const int64_t idx = row * Rp + r;
     float q = qi[idx], pv = p[idx], g;
-    sbm_point(acc, b[row], a, a0, *c0p, dt, __fmul_rn(dt, a0), q, pv, g);
+    const float brow = b[row];
+    float acc = 0.0f;
+    auto batch = [&](int32_t kb) {
+        int64_t j[SBM_BATCH];
+        float wk[SBM_BATCH], qj[SBM_BATCH];
+#pragma unroll
+        for (int d = 0; d < SBM_BATCH; ++d) {
+            const int32_t k = kb + d < k1 ? kb + d : k1 - 1;   // in bounds: kb < k1
+            j[d] = (int64_t)col[k];
+            wk[d] = (float)w[k];
+        }
+#pragma unroll
+        for (int d = 0; d < SBM_BATCH; ++d) {
+            qj[d] = 0.0f;
+            if (kb + d < k1) qj[d] = qi[j[d] * Rp + r];
+        }
+#pragma unroll
+        for (int d = 0; d < SBM_BATCH; ++d) {
+            if (kb + d >= k1 || (skip_diag && j[d] == row)) continue;
+            acc = __fmaf_rn(wk[d], qj[d], acc);
+        }
+    };
+    if (k0 < k1) batch(k0);
+    for (int32_t kb = k0 + SBM_BATCH; kb < k1; kb += SBM_BATCH) batch(kb);
+    sbm_point(acc, brow, a, a0, *c0p, dt, __fmul_rn(dt, a0), q, pv, g);
     qo[idx] = q;
     p[idx] = pv;
     if (gout) gout[idx] = g;

@@ -51,7 +51,7 @@ constexpr size_t ALIGN = 256;
 inline size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
-enum class Path { DenseResident, DenseTiled, DenseMfma, Csr, CsrResident };
+enum class Path { DenseResident, DenseTiled, DenseMfma, Csr, CsrResident, CsrBinned };
 
 int32_t path_code(Path p) {
     switch (p) {
@@ -59,6 +59,7 @@ int32_t path_code(Path p) {
         case Path::DenseTiled: return QPA_PATH_DENSE_TILED;
         case Path::DenseMfma: return QPA_PATH_DENSE_MFMA;
         case Path::CsrResident: return QPA_PATH_CSR_RESIDENT;
+        case Path::CsrBinned: return QPA_PATH_CSR_BINNED;
         default: return QPA_PATH_CSR;
     }
 }
@@ -70,6 +71,7 @@ const char *path_name(Path p) {
         case Path::DenseMfma: return "dense-mfma-bf16";
         case Path::Csr: return "csr";
         case Path::CsrResident: return "csr-resident";
+        case Path::CsrBinned: return "csr-binned";
     }
     return "?";
 }
@@ -82,11 +84,18 @@ struct Plan {
     int Gs;               // CSR replica group of the streamed kernel (state / spin layout)
     int64_t nwords;       // CSR spin words per group (streamed layout)
     bool is_int, is_qubo;
+    bool bin_ok;          // the binned sparse kernels apply (their arrays are allocated)
+    BinGeom bg;
     int64_t eblk;         // energy partial blocks
     // workspace offsets (bytes)
     size_t o_sc, o_lam, o_bf, o_bi, o_bd, o_rabs, o_rmax, o_rk, o_Jf, o_Jb, o_x, o_m, o_h,
-        o_s0, o_s1, o_part, o_ei, o_ed, o_sp, o_best, o_words, total;
+        o_s0, o_s1, o_part, o_ei, o_ed, o_sp, o_best, o_words, o_boff, o_bcur, o_btsum,
+        o_bsrc, o_bdrec, o_bbits, total;
 };
+
+// Spin words of the streamed layout above which the binned kernels run by default: the
+// per-row gather then misses the L2 on nearly every coupling.
+constexpr int64_t BIN_AUTO_BYTES = (int64_t)4 << 20;
 
 
 // batch_rp > 0: state for the batch kernel, [batch_rp/64 groups][n][64].
@@ -120,6 +129,16 @@ Plan make_plan(const qpa_problem &p, const qpa_params &a, int64_t batch_rp = 0, 
             csr_resident_lds(pl.n, p.nnz) <= RES_MAX_LDS) {
             pl.path = Path::CsrResident;
             pl.G = csr_resident_group(pl.n, pl.R, cus);
+        }
+        // binned kernels: int8 / int16 couplings, integer fields, one group of <= 8 lanes
+        pl.bin_ok = batch_rp == 0 && cus > 0 && state && pl.is_int &&
+                    (p.coupling_dtype == QPA_I8 || p.coupling_dtype == QPA_I16) &&
+                    pl.Rp == pl.Gs && pl.Gs <= 8 && bin_geometry(pl.n, pl.Gs, pl.bg);
+        if (pl.bin_ok && ((a.flags & QPA_SOLVE_BINNED) ||
+                          (!(a.flags & QPA_SOLVE_STREAMED) && pl.path == Path::Csr &&
+                           8 * pl.nwords > BIN_AUTO_BYTES))) {
+            pl.path = Path::CsrBinned;
+            pl.G = pl.Gs;
         }
     } else if (a.precision == QPA_PREC_BF16) {
         pl.path = Path::DenseMfma;
@@ -159,6 +178,7 @@ Plan make_plan(const qpa_problem &p, const qpa_params &a, int64_t batch_rp = 0, 
         case Path::DenseMfma: sbytes = sizeof(uint32_t) * Rp * (np / 8); break;
         case Path::Csr:
         case Path::CsrResident:
+        case Path::CsrBinned:
             sbytes = sizeof(uint64_t) * (size_t)(Rp / pl.Gs) * (size_t)pl.nwords;
             break;
     }
@@ -172,13 +192,22 @@ Plan make_plan(const qpa_problem &p, const qpa_params &a, int64_t batch_rp = 0, 
     pl.o_best = take(sizeof(int32_t) * 4);
     pl.o_words = p.format == QPA_FMT_DENSE
                      ? take(sizeof(uint64_t) * R * (size_t)((n + 63) / 64)) : 0;
+    if (pl.bin_ok) {
+        const size_t nnz = (size_t)std::max<int64_t>(p.nnz, 0), M = (size_t)pl.bg.M;
+        pl.o_boff = take(sizeof(int32_t) * (M + 1));
+        pl.o_bcur = take(sizeof(int32_t) * M);
+        pl.o_btsum = take(sizeof(int32_t) * ((size_t)bin_scan_tiles(pl.bg) + 1));
+        pl.o_bsrc = take(sizeof(uint32_t) * nnz);
+        pl.o_bdrec = take(sizeof(uint32_t) * nnz);
+        pl.o_bbits = take(nnz);
+    }
     pl.total = off;
     return pl;
 }
 
 // Strides of element (r, i) in the internal state layout of a plan.
 void state_strides(const Plan &pl, int64_t &ld_r, int64_t &ld_i) {
-    if (pl.path == Path::Csr || pl.path == Path::CsrResident) {
+    if (pl.path == Path::Csr || pl.path == Path::CsrResident || pl.path == Path::CsrBinned) {
         ld_r = 1;
         ld_i = pl.Rp;
     } else {
@@ -244,8 +273,11 @@ qpa_status check_params(qpa_ctx *ctx, const qpa_params *a) {
     if (a->steps < 0) return fail(ctx, QPA_E_ARG, "steps must be >= 0");
     if (a->precision != QPA_PREC_FP32 && a->precision != QPA_PREC_BF16)
         return fail(ctx, QPA_E_ARG, "unknown precision %d", a->precision);
-    if ((a->flags & ~(QPA_SOLVE_STREAMED | QPA_SOLVE_GRAPH)) != 0)
-        return fail(ctx, QPA_E_ARG, "params.flags: only QPA_SOLVE_STREAMED and QPA_SOLVE_GRAPH");
+    if ((a->flags & ~(QPA_SOLVE_STREAMED | QPA_SOLVE_GRAPH | QPA_SOLVE_BINNED)) != 0)
+        return fail(ctx, QPA_E_ARG,
+                    "params.flags: only QPA_SOLVE_STREAMED, QPA_SOLVE_BINNED and QPA_SOLVE_GRAPH");
+    if ((a->flags & QPA_SOLVE_STREAMED) && (a->flags & QPA_SOLVE_BINNED))
+        return fail(ctx, QPA_E_ARG, "QPA_SOLVE_STREAMED and QPA_SOLVE_BINNED exclude each other");
     return QPA_OK;
 }
 
@@ -381,14 +413,30 @@ qpa_status run_graph(qpa_ctx *ctx, std::vector<uint8_t> key, hipStream_t st, F &
     return QPA_OK;
 }
 
+// Entry order of the binned kernels (once per call, before the step loop).
+qpa_status bin_build(qpa_ctx *ctx, const qpa_problem &p, const Plan &pl, void *ws,
+                     hipStream_t st) {
+    CsrView c{pl.n, p.row_ptr, p.col, p.weights, p.index_dtype, p.coupling_dtype, pl.is_qubo,
+              p.nnz};
+    QPA_HIP(launch_bin_build(c, pl.bg, at<int32_t>(ws, pl.o_boff), at<int32_t>(ws, pl.o_bcur),
+                             at<int32_t>(ws, pl.o_btsum), at<uint32_t>(ws, pl.o_bsrc),
+                             at<uint32_t>(ws, pl.o_bdrec), st));
+    return QPA_OK;
+}
+
 bool per_step_path(Path p) {
-    return p == Path::DenseTiled || p == Path::DenseMfma || p == Path::Csr;
+    return p == Path::DenseTiled || p == Path::DenseMfma || p == Path::Csr ||
+           p == Path::CsrBinned;
 }
 
 // Run steps t0 .. t1-1 on the internal state of the plan (timed when profiling).
 qpa_status run_steps(qpa_ctx *ctx, const qpa_problem &p, const qpa_params &a, const Plan &pl,
                      void *ws, int32_t t0, int32_t t1, bool want_h, hipStream_t st) {
     if (t1 <= t0) return QPA_OK;
+    if (pl.path == Path::CsrBinned) {
+        qpa_status sb = bin_build(ctx, p, pl, ws, st);
+        if (sb != QPA_OK) return sb;
+    }
     int64_t launches = 0;
     int32_t ran = path_code(pl.path);
     const bool graph = (a.flags & QPA_SOLVE_GRAPH) && per_step_path(pl.path);
@@ -478,6 +526,21 @@ qpa_status run_steps_inner(qpa_ctx *ctx, const qpa_problem &p, const qpa_params 
             launches = 1;
             break;
         }
+        case Path::CsrBinned: {
+            uint64_t *s0 = at<uint64_t>(ws, pl.o_s0), *s1 = at<uint64_t>(ws, pl.o_s1);
+            QPA_HIP(launch_csr_pack_spins(pl.n, pl.Rp, pl.Gs, x, s0, st));
+            const int32_t *off = at<int32_t>(ws, pl.o_boff);
+            const uint32_t *src = at<uint32_t>(ws, pl.o_bsrc), *drec = at<uint32_t>(ws, pl.o_bdrec);
+            launches = 2 * (int64_t)(t1 - t0);
+            for (int32_t t = t0; t < t1; ++t) {
+                QPA_HIP(launch_bin_step(pl.bg, pl.n, pl.nwords, off, src, drec,
+                                        at<uint8_t>(ws, pl.o_bbits), bf, s0, s1, x, m,
+                                        (t == t1 - 1) ? h : nullptr, t, lam, a.eta, a.alpha,
+                                        ctx->cus, st));
+                std::swap(s0, s1);
+            }
+            break;
+        }
         case Path::Csr: {
             uint64_t *s0 = at<uint64_t>(ws, pl.o_s0), *s1 = at<uint64_t>(ws, pl.o_s1);
             QPA_HIP(launch_csr_pack_spins(pl.n, pl.Rp, pl.G, x, s0, st));
@@ -520,6 +583,8 @@ std::vector<uint8_t> tune_key(const qpa_problem &p, const qpa_params &a) {
     return k;
 }
 
+constexpr int32_t TUNE_BINNED = QPA_TUNE_BINNED;
+
 bool resident_ok(const qpa_problem &p, int G) {
     if (p.n > RES_MAX_N || csr_resident_lds(p.n, p.nnz) > RES_MAX_LDS) return false;
     const int64_t v = (p.n + 1023) / 1024;
@@ -530,13 +595,20 @@ bool resident_ok(const qpa_problem &p, int G) {
 // Use the kernel qpa_autotune chose for this shape (unless the caller forced the
 // streamed kernel).  Both sparse kernels share the workspace layout.
 void apply_tuning(qpa_ctx *ctx, const qpa_problem &p, const qpa_params &a, Plan &pl) {
-    if (p.format != QPA_FMT_CSR || (a.flags & QPA_SOLVE_STREAMED) || ctx->tuned.empty()) return;
+    if (p.format != QPA_FMT_CSR || (a.flags & (QPA_SOLVE_STREAMED | QPA_SOLVE_BINNED)) ||
+        ctx->tuned.empty())
+        return;
     const std::vector<uint8_t> k = tune_key(p, a);
     for (const auto &e : ctx->tuned) {
         if (e.first != k) continue;
         if (e.second == 0) {
             pl.path = Path::Csr;
             pl.G = pl.Gs;
+        } else if (e.second == TUNE_BINNED) {
+            if (pl.bin_ok) {
+                pl.path = Path::CsrBinned;
+                pl.G = pl.Gs;
+            }
         } else if (resident_ok(p, e.second)) {
             pl.path = Path::CsrResident;
             pl.G = e.second;
@@ -555,6 +627,10 @@ qpa_status prologue(qpa_ctx *ctx, const qpa_problem *problem, const qpa_params *
     if (s != QPA_OK) return s;
     pl = make_plan(*problem, *params, 0, ctx->cus);
     apply_tuning(ctx, *problem, *params, pl);
+    if ((params->flags & QPA_SOLVE_BINNED) && pl.path != Path::CsrBinned)
+        return fail(ctx, QPA_E_UNSUPPORTED,
+                    "QPA_SOLVE_BINNED needs a CSR problem with int8 or int16 couplings, "
+                    "integer fields and at most 8 replicas");
     if (!ws) return fail(ctx, QPA_E_ARG, "workspace is NULL");
     if ((reinterpret_cast<uintptr_t>(ws) % ALIGN) != 0)
         return fail(ctx, QPA_E_ARG, "workspace must be %zu-byte aligned", ALIGN);
@@ -847,7 +923,7 @@ qpa_status qpa_batch_paths(const qpa_ctx *ctx, int32_t count, int32_t *paths) {
 qpa_status qpa_profile_read_path(qpa_ctx *ctx, int32_t path, double *step_ms,
                                  int64_t *step_launches, int32_t reset) {
     if (!ctx || !step_ms || !step_launches) return QPA_E_ARG;
-    if (path < QPA_PATH_ALL || path > QPA_PATH_BATCH_DENSE_I8)
+    if (path < QPA_PATH_ALL || path > QPA_PATH_CSR_BINNED)
         return fail(ctx, QPA_E_ARG, "unknown path %d", path);
     double total = 0.0;
     int64_t n = 0;
@@ -1570,8 +1646,8 @@ qpa_status qpa_autotune(qpa_ctx *ctx, const qpa_problem *problem, const qpa_para
     if (s != QPA_OK) return s;
     if (problem->format != QPA_FMT_CSR)
         return fail(ctx, QPA_E_UNSUPPORTED, "autotuning covers sparse (CSR) problems");
-    if (params->flags & QPA_SOLVE_STREAMED)
-        return fail(ctx, QPA_E_ARG, "QPA_SOLVE_STREAMED leaves nothing to choose");
+    if (params->flags & (QPA_SOLVE_STREAMED | QPA_SOLVE_BINNED))
+        return fail(ctx, QPA_E_ARG, "QPA_SOLVE_STREAMED or QPA_SOLVE_BINNED leaves nothing to choose");
     if (probe_steps < 1) return fail(ctx, QPA_E_ARG, "probe_steps must be >= 1");
     if (!choice) return fail(ctx, QPA_E_ARG, "choice is NULL");
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1587,17 +1663,23 @@ qpa_status qpa_autotune(qpa_ctx *ctx, const qpa_problem *problem, const qpa_para
     hipEvent_t e0, e1;
     QPA_HIP(hipEventCreate(&e0));
     QPA_HIP(hipEventCreate(&e1));
-    const int cand[5] = {0, 1, 2, 4, 8};
+    const int cand[6] = {0, 1, 2, 4, 8, TUNE_BINNED};
     double best = -1.0;
     int32_t pick = 0;
     qpa_params a = *params;
     a.flags &= ~QPA_SOLVE_GRAPH;
-    for (int c = 0; c < 5 && s == QPA_OK; ++c) {
+    for (int c = 0; c < 6 && s == QPA_OK; ++c) {
         if (ms) ms[c] = -1.0;
         Plan q = pl;
         if (cand[c] == 0) {
             q.path = Path::Csr;
             q.G = q.Gs;
+        } else if (cand[c] == TUNE_BINNED) {
+            if (!pl.bin_ok) continue;
+            q.path = Path::CsrBinned;
+            q.G = q.Gs;
+            s = bin_build(ctx, *problem, q, ws, st);
+            if (s != QPA_OK) break;
         } else {
             if (!resident_ok(*problem, cand[c])) continue;
             q.path = Path::CsrResident;
@@ -1646,9 +1728,11 @@ qpa_status qpa_tune_set(qpa_ctx *ctx, const qpa_problem *problem, const qpa_para
     if (s != QPA_OK) return s;
     if (problem->format != QPA_FMT_CSR)
         return fail(ctx, QPA_E_UNSUPPORTED, "kernel choices exist for sparse (CSR) problems");
-    if (choice != 0 && !((choice == 1 || choice == 2 || choice == 4 || choice == 8) &&
-                         resident_ok(*problem, choice)))
-        return fail(ctx, QPA_E_ARG, "choice %d does not apply to this instance", choice);
+    bool ok = choice == 0 ||
+              ((choice == 1 || choice == 2 || choice == 4 || choice == 8) &&
+               resident_ok(*problem, choice));
+    if (choice == TUNE_BINNED) ok = make_plan(*problem, *params, 0, ctx->cus).bin_ok;
+    if (!ok) return fail(ctx, QPA_E_ARG, "choice %d does not apply to this instance", choice);
     record_choice(ctx, *problem, *params, choice);
     return QPA_OK;
 }

@@ -37,9 +37,12 @@ QPA_PREC_FP32, QPA_PREC_BF16 = 0, 1
 QPA_BATCH_SPARSE, QPA_BATCH_DENSE = 1, 2
 QPA_PATH_ALL, QPA_PATH_DENSE_RESIDENT, QPA_PATH_DENSE_TILED, QPA_PATH_DENSE_MFMA, QPA_PATH_CSR, \
     QPA_PATH_BATCH_SPARSE, QPA_PATH_BATCH_DENSE, QPA_PATH_CSR_RESIDENT, QPA_PATH_SBM_DENSE, \
-    QPA_PATH_SBM_CSR, QPA_PATH_SBM_CSR_RESIDENT, QPA_PATH_BATCH_DENSE_I8 = range(-1, 11)
+    QPA_PATH_SBM_CSR, QPA_PATH_SBM_CSR_RESIDENT, QPA_PATH_BATCH_DENSE_I8, \
+    QPA_PATH_CSR_BINNED = range(-1, 12)
 QPA_SOLVE_STREAMED = 4
 QPA_SOLVE_GRAPH = 8
+QPA_SOLVE_BINNED = 16
+QPA_TUNE_BINNED = -1
 QPA_SPECTRUM_MAX_R = 4096
 QPA_SPECTRUM_EXACT_ONLY = 1
 
@@ -282,9 +285,9 @@ def qpa_spectral_radius(ctx, problem, params, workspace, workspace_bytes, stream
 
 
 def qpa_autotune(ctx, problem, params, probe_steps, workspace, workspace_bytes, stream):
-    """Returns (choice, [ms of streamed, G=1, 2, 4, 8] with -1 where not applicable)."""
+    """Returns (choice, [ms of streamed, G=1, 2, 4, 8, binned], -1 where not applicable)."""
     choice = ctypes.c_int32()
-    ms = (ctypes.c_double * 5)()
+    ms = (ctypes.c_double * 6)()
     _check(ctx, _lib.qpa_autotune(ctx, ctypes.byref(problem), ctypes.byref(params), probe_steps,
                                   workspace, workspace_bytes, stream, ctypes.byref(choice), ms))
     return choice.value, list(ms)

@@ -107,6 +107,39 @@ def test_argument_validation(q):
     assert _ws(q, c, a)[0] == q.QPA_E_SHAPE
 
 
+def _csr_problem(q, n, nnz, wdt):
+    c = q.qpa_problem()
+    c.n = n
+    c.format = q.QPA_FMT_CSR
+    c.kind = q.QPA_KIND_ISING
+    c.coupling_dtype = wdt
+    c.index_dtype = q.QPA_I32
+    c.row_ptr = 0x1000
+    c.col = 0x1000
+    c.weights = 0x1000
+    c.nnz = nnz
+    return c
+
+
+def test_binned_workspace_and_flags(q):
+    """Integer CSR problems with at most 8 replicas carry the binned entry arrays (block
+    offsets, 9 bytes per entry); other problems do not; flag mixes are refused."""
+    n, nnz = 3_000_000, 9_000_000
+    ws = {}
+    for R in (4, 9):
+        for wdt in (q.QPA_I8, q.QPA_F32):
+            st, ws[R, wdt] = _ws(q, _csr_problem(q, n, nnz, wdt), q.make_params(R, 10, 0.1, 0.8, 4.0))
+            assert st == q.QPA_OK
+    # G = 4: chunks of 2^18 variables, bins of 2^12 rows
+    blocks = ((n + 2**18 - 1) // 2**18) * ((n + 2**12 - 1) // 2**12)
+    assert ws[4, q.QPA_I8] - ws[4, q.QPA_F32] >= 9 * nnz + 8 * blocks
+    assert ws[9, q.QPA_I8] - ws[9, q.QPA_F32] < 9 * nnz
+    both = q.make_params(4, 10, 0.1, 0.8, 4.0, flags=q.QPA_SOLVE_BINNED | q.QPA_SOLVE_STREAMED)
+    assert _ws(q, _csr_problem(q, n, nnz, q.QPA_I8), both)[0] == q.QPA_E_ARG
+    one = q.make_params(4, 10, 0.1, 0.8, 4.0, flags=q.QPA_SOLVE_BINNED | q.QPA_SOLVE_GRAPH)
+    assert _ws(q, _csr_problem(q, n, nnz, q.QPA_I8), one)[0] == q.QPA_OK
+
+
 def test_solve_rejects_null_context_and_bad_workspace(q):
     a = q.make_params(4, 10, 0.1, 0.5, 1.0)
     p = _dense_problem(q)
