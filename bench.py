@@ -256,7 +256,7 @@ def run_solves(eng, qpa, torch, inst, prob, params, steps, warmup, batch):
     per_path = {}
     for code in (qpa.QPA_PATH_DENSE_RESIDENT, qpa.QPA_PATH_DENSE_TILED, qpa.QPA_PATH_DENSE_MFMA,
                  qpa.QPA_PATH_CSR, qpa.QPA_PATH_BATCH_SPARSE, qpa.QPA_PATH_BATCH_DENSE,
-                 qpa.QPA_PATH_CSR_RESIDENT):
+                 qpa.QPA_PATH_CSR_RESIDENT, qpa.QPA_PATH_CSR_BINNED):
         pm, pl = qpa.qpa_profile_read_path(eng.ctx, code)
         if pl:
             per_path[code] = (pm, pl)
