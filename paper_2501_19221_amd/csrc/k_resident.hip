@@ -14,6 +14,12 @@
 // replica fastest) and, if asked, the last field.
 // The field sums follow the entry order of the row: int32 (exact; rows are validated
 // below 2^24) for integer couplings, FP32 for float couplings, as in the streamed kernel.
+// Integer rows whose sum of |w| stays below 2^16 (SW) take a packed form instead: with
+// b' = b XOR [w < 0] a term is w (1 - 2b) = |w| (1 - 2b'), so the field is
+// sum |w| - 2 sum |w| b'; the second sum of two replicas shares one 32-bit word (16-bit
+// lanes, no carry since each lane stays below 2^16) and one 24-bit multiply-add per
+// entry and replica pair.  The cached entries are padded with zero weights, so the
+// integer walk has no per-entry branch.
 #include "qpa_internal.h"
 
 namespace qpa {
@@ -41,7 +47,7 @@ template <typename T> __device__ __forceinline__ T ld_as(const void *p, int32_t 
 }
 
 // LDS: rp [n+1] int32 | w [nnz] int32 or float | col [nnz] uint16 | spins [2][n] bytes
-template <int G, int VPT, bool INT>
+template <int G, int VPT, bool INT, bool SW>
 __global__ void __launch_bounds__(RT) k_csr_resident(
     int32_t n, int32_t nnz, int64_t R, int64_t Rp, const int32_t *__restrict__ rp_g,
     const void *__restrict__ col_g, int32_t col_dt, const void *__restrict__ w_g, int32_t w_dt,
@@ -70,9 +76,12 @@ __global__ void __launch_bounds__(RT) k_csr_resident(
     // cached entries of each owned row (diagonal entries of a QUBO left out), then the
     // LDS position where the rest of the row continues
     int32_t cj[VPT][CACHE];
-    int32_t cwi[VPT][CACHE];
+    int32_t cwi[VPT][CACHE];      // SW: |w|
     float cwf[VPT][CACHE];
+    uint32_t cfl[VPT][CACHE];     // SW: replica mask where w < 0
     int32_t ccount[VPT], crest[VPT];
+    int32_t wabs[VPT];            // SW: sum of |w| over the row (diagonal excluded)
+    constexpr uint32_t GMASK = (1u << G) - 1;
     float xs[VPT][G], ms[VPT][G], bi[VPT];
 #pragma unroll
     for (int u = 0; u < VPT; ++u) {
@@ -111,7 +120,12 @@ __global__ void __launch_bounds__(RT) k_csr_resident(
             cj[u][c] = 0;
             cwi[u][c] = 0;
             cwf[u][c] = 0.0f;
+            cfl[u][c] = 0u;
         }
+        wabs[u] = 0;
+        if (SW)
+            for (int32_t kk = k; kk < k1; ++kk)
+                if (!(skip_diag && col[kk] == i)) wabs[u] += wi[kk] < 0 ? -wi[kk] : wi[kk];
         // take entries in row order until CACHE of them are held
         for (; k < k1 && cnt < CACHE; ++k) {
             const int32_t j = col[k];
@@ -120,8 +134,14 @@ __global__ void __launch_bounds__(RT) k_csr_resident(
             for (int c = 0; c < CACHE; ++c)
                 if (c == cnt) {
                     cj[u][c] = j;
-                    if (INT) cwi[u][c] = wi[k];
-                    else cwf[u][c] = wf[k];
+                    if (SW) {
+                        cwi[u][c] = wi[k] < 0 ? -wi[k] : wi[k];
+                        cfl[u][c] = wi[k] < 0 ? GMASK : 0u;
+                    } else if (INT) {
+                        cwi[u][c] = wi[k];
+                    } else {
+                        cwf[u][c] = wf[k];
+                    }
                 }
             ++cnt;
         }
@@ -144,6 +164,38 @@ __global__ void __launch_bounds__(RT) k_csr_resident(
                 ai[g] = 0;
                 af[g] = 0.0f;
             }
+            if (SW) {
+                constexpr int NP = (G + 1) / 2;     // replica pairs, one 32-bit word each
+                uint32_t acc[NP];
+#pragma unroll
+                for (int p = 0; p < NP; ++p) acc[p] = 0u;
+                uint32_t cb[CACHE];
+#pragma unroll
+                for (int c = 0; c < CACHE; ++c) cb[c] = (uint32_t)cur[cj[u][c]] ^ cfl[u][c];
+#pragma unroll
+                for (int c = 0; c < CACHE; ++c)
+#pragma unroll
+                    for (int p = 0; p < NP; ++p) {
+                        const uint32_t two = (cb[c] >> (2 * p)) & 3u;
+                        acc[p] += __umul24((uint32_t)cwi[u][c], __umul24(two, 0x8001u) & 0x10001u);
+                    }
+                const int32_t k1 = rp[i + 1];
+                for (int32_t k = crest[u]; k < k1; ++k) {
+                    const int32_t j = col[k];
+                    if (skip_diag && j == i) continue;
+                    const int32_t wk = wi[k];
+                    const uint32_t byte = (uint32_t)cur[j] ^ (wk < 0 ? GMASK : 0u);
+                    const uint32_t aw = (uint32_t)(wk < 0 ? -wk : wk);
+#pragma unroll
+                    for (int p = 0; p < NP; ++p) {
+                        const uint32_t two = (byte >> (2 * p)) & 3u;
+                        acc[p] += __umul24(aw, __umul24(two, 0x8001u) & 0x10001u);
+                    }
+                }
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+                    ai[g] = wabs[u] - 2 * (int32_t)((acc[g >> 1] >> (16 * (g & 1))) & 0xffffu);
+            } else {
             // cached entries: their spin bytes are read together, then summed in order
             uint32_t cb[CACHE];
 #pragma unroll
@@ -179,6 +231,7 @@ __global__ void __launch_bounds__(RT) k_csr_resident(
                         af[g] = __fadd_rn(af[g], ((byte >> g) & 1u) ? -wk : wk);
                 }
             }
+            }
             uint32_t byte = 0;
 #pragma unroll
             for (int g = 0; g < G; ++g) {
@@ -208,28 +261,34 @@ __global__ void __launch_bounds__(RT) k_csr_resident(
     }
 }
 
-template <int G, int VPT>
-hipError_t launch_g_v(const CsrView &c, int64_t R, int64_t Rp, bool is_int, const float *b,
-                      float *x, float *m, float *h_last, int32_t t0, int32_t t1,
-                      const float *lam, float eta, float alpha, size_t lds, hipStream_t st) {
+template <int G, int VPT, bool INT, bool SW>
+hipError_t launch_one(const CsrView &c, int64_t R, int64_t Rp, const float *b, float *x,
+                      float *m, float *h_last, int32_t t0, int32_t t1, const float *lam,
+                      float eta, float alpha, size_t lds, hipStream_t st) {
     const unsigned blocks = (unsigned)((R + G - 1) / G);
-    const int32_t nnz = (int32_t)c.nnz;
     // allow more than the default dynamic LDS; a runtime without the attribute leaves the
     // launch to report a real limit
-    (void)hipFuncSetAttribute(
-        is_int ? reinterpret_cast<const void *>(&k_csr_resident<G, VPT, true>)
-               : reinterpret_cast<const void *>(&k_csr_resident<G, VPT, false>),
-        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_csr_resident<G, VPT, INT, SW>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     (void)hipGetLastError();
-    if (is_int)
-        k_csr_resident<G, VPT, true><<<blocks, RT, lds, st>>>(
-            (int32_t)c.n, nnz, R, Rp, c.rp, c.col, c.col_dt, c.w, c.w_dt, c.skip_diag ? 1 : 0, b,
-            x, m, h_last, t0, t1, lam, eta, alpha);
-    else
-        k_csr_resident<G, VPT, false><<<blocks, RT, lds, st>>>(
-            (int32_t)c.n, nnz, R, Rp, c.rp, c.col, c.col_dt, c.w, c.w_dt, c.skip_diag ? 1 : 0, b,
-            x, m, h_last, t0, t1, lam, eta, alpha);
+    k_csr_resident<G, VPT, INT, SW><<<blocks, RT, lds, st>>>(
+        (int32_t)c.n, (int32_t)c.nnz, R, Rp, c.rp, c.col, c.col_dt, c.w, c.w_dt,
+        c.skip_diag ? 1 : 0, b, x, m, h_last, t0, t1, lam, eta, alpha);
     return hipGetLastError();
+}
+
+template <int G, int VPT>
+hipError_t launch_g_v(const CsrView &c, int64_t R, int64_t Rp, bool is_int, bool small_w,
+                      const float *b, float *x, float *m, float *h_last, int32_t t0, int32_t t1,
+                      const float *lam, float eta, float alpha, size_t lds, hipStream_t st) {
+    if (is_int && small_w)
+        return launch_one<G, VPT, true, true>(c, R, Rp, b, x, m, h_last, t0, t1, lam, eta,
+                                              alpha, lds, st);
+    if (is_int)
+        return launch_one<G, VPT, true, false>(c, R, Rp, b, x, m, h_last, t0, t1, lam, eta,
+                                               alpha, lds, st);
+    return launch_one<G, VPT, false, false>(c, R, Rp, b, x, m, h_last, t0, t1, lam, eta, alpha,
+                                            lds, st);
 }
 
 }  // namespace
@@ -258,8 +317,8 @@ int csr_resident_group(int64_t n, int64_t R, int cus) {
 }
 
 hipError_t launch_csr_resident(const CsrView &c, int G, int64_t R, int64_t Rp, bool is_int,
-                               const float *b, float *x, float *m, float *h_last, int32_t t0,
-                               int32_t t1, const float *lam, float eta, float alpha,
+                               bool small_w, const float *b, float *x, float *m, float *h_last,
+                               int32_t t0, int32_t t1, const float *lam, float eta, float alpha,
                                hipStream_t st) {
     if (t1 <= t0) return hipSuccess;
     const size_t lds = csr_resident_lds(c.n, c.nnz);
@@ -268,8 +327,8 @@ hipError_t launch_csr_resident(const CsrView &c, int G, int64_t R, int64_t Rp, b
     if (v * G > 16) return hipErrorInvalidValue;
 #define QPA_RES_CASE(GG, VV)                                                                   \
     if (G == GG && v == VV)                                                                    \
-        return launch_g_v<GG, VV>(c, R, Rp, is_int, b, x, m, h_last, t0, t1, lam, eta, alpha, \
-                                  lds, st);
+        return launch_g_v<GG, VV>(c, R, Rp, is_int, small_w, b, x, m, h_last, t0, t1, lam, eta, \
+                                  alpha, lds, st);
     QPA_RES_CASE(8, 1)
     QPA_RES_CASE(8, 2)
     QPA_RES_CASE(4, 1)

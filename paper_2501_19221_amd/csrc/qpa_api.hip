@@ -521,8 +521,11 @@ qpa_status run_steps_inner(qpa_ctx *ctx, const qpa_problem &p, const qpa_params 
         case Path::CsrResident: {
             CsrView c{pl.n, p.row_ptr, p.col, p.weights, p.index_dtype, p.coupling_dtype,
                       pl.is_qubo, p.nnz};
-            QPA_HIP(launch_csr_resident(c, pl.G, pl.R, pl.Rp, pl.is_int, bf, x, m, h, t0, t1, lam,
-                                        a.eta, a.alpha, st));
+            // the canonical row bound (sum of |w| plus |b|, read back by canonicalise)
+            // bounds every row's sum of |w|
+            const bool small_w = pl.is_int && ctx->host_sc->max_row < 65536.0;
+            QPA_HIP(launch_csr_resident(c, pl.G, pl.R, pl.Rp, pl.is_int, small_w, bf, x, m, h, t0,
+                                        t1, lam, a.eta, a.alpha, st));
             launches = 1;
             break;
         }

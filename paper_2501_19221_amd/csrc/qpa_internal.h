@@ -155,9 +155,11 @@ constexpr size_t RES_MAX_LDS = 160 * 1024;
 size_t csr_resident_lds(int64_t n, int64_t nnz);
 // G for R replicas on `cus` compute units, 0 when the instance does not fit the kernel.
 int csr_resident_group(int64_t n, int64_t R, int cus);
+// small_w (integer couplings only): every row's sum of |w| is below 2^16, which selects
+// the packed two-replicas-per-word field sums.
 hipError_t launch_csr_resident(const CsrView &c, int G, int64_t R, int64_t Rp, bool is_int,
-                               const float *b, float *x, float *m, float *h_last, int32_t t0,
-                               int32_t t1, const float *lam, float eta, float alpha,
+                               bool small_w, const float *b, float *x, float *m, float *h_last,
+                               int32_t t0, int32_t t1, const float *lam, float eta, float alpha,
                                hipStream_t st);
 int csr_group_size(int64_t R);
 int64_t csr_words_per_group(int64_t n, int G);

@@ -209,6 +209,37 @@ def test_csr_chimera_bit_exact(q, eng, m_, R, T, streamed):
     assert int(host(out["best"])[0]) == int(np.flatnonzero(e == e.min())[0])
 
 
+@pytest.mark.parametrize("scale,G", [(10900, 4), (10900, 8), (11000, 2), (20000, 4)])
+def test_csr_resident_weight_bound(q, eng, scale, G):
+    """Resident kernel on either side of its packed-sum bound: rows with a sum of |w|
+    below 2^16 (6 x 10900 = 65400 plus a field) take two replicas per 32-bit word,
+    6 x 11000 and 6 x 20000 the general int32 sums; both equal the oracle bit for bit."""
+    base = gen.chimera_ising(4, seed=9)
+    rng = np.random.default_rng(scale)
+    c = base.csr
+    w = c.w.astype(np.int32) * scale
+    # symmetric magnitudes in [scale - 100, scale]: perturb the upper triangle, mirror it
+    rows = np.repeat(np.arange(base.n), np.diff(c.rp)).astype(np.int64)
+    cols = c.col.astype(np.int64)
+    pair = np.minimum(rows, cols) * base.n + np.maximum(rows, cols)
+    uniq, inv = np.unique(pair, return_inverse=True)
+    d = rng.integers(0, 101, size=len(uniq))[inv]
+    w = (np.sign(w) * (np.abs(w) - d)).astype(np.int16)
+    lin = rng.integers(-50, 51, size=base.n).astype(np.int16)
+    inst = gen.Instance("ising", base.n, csr=gen.CSR(base.n, c.rp, c.col, w), lin=lin, meta={})
+    prob = q.Problem.from_instance(inst)
+    R, T = 4 * G, 25
+    eng.tune_set(prob, _params(q, R, T, 0.0002, 0.8, 20000.0), G)
+    p = _params(q, R, T, 0.0002, 0.8, 20000.0)
+    say("resident weight bound scale=%d G=%d" % (scale, G))
+    out, paths = _launches_by_path(q, eng, lambda: eng.solve(prob, p, want_state=True))
+    assert paths == {q.QPA_PATH_CSR_RESIDENT: 1}, paths
+    x, m, canon = _oracle_csr(inst, R, T, orc.lambda_linear(T, 20000.0), 0.0002, 0.8)
+    assert np.array_equal(host(out["x"]), x) and np.array_equal(host(out["m"]), m)
+    s = np.where(x >= 0, 1, -1).astype(np.int8)
+    assert np.array_equal(host(out["energy_i64"]), _energies_csr_int(canon, "ising", s))
+
+
 # replica groups G = 8, 4, 2, 1 and 2, 2, 4, 8, 1 variables per thread of the resident
 # kernel, with replica counts that leave a partial group (the n = 6000 graph has degree 3,
 # so that its CSR fits in LDS)
