@@ -16,10 +16,13 @@
 // below 2^24) for integer couplings, FP32 for float couplings, as in the streamed kernel.
 // Integer rows whose sum of |w| stays below 2^16 (SW) take a packed form instead: with
 // b' = b XOR [w < 0] a term is w (1 - 2b) = |w| (1 - 2b'), so the field is
-// sum |w| - 2 sum |w| b'; the second sum of two replicas shares one 32-bit word (16-bit
-// lanes, no carry since each lane stays below 2^16) and one 24-bit multiply-add per
-// entry and replica pair.  The cached entries are padded with zero weights, so the
-// integer walk has no per-entry branch.
+// sum |w| - 2 A with A = sum |w| b' < 2^16.  The A of two replicas share one 32-bit word
+// (16-bit lanes), summed modulo 2^32 as a row constant sum_{w<0} |w| (1 + 2^16) plus, per
+// entry, w times the spread spin bits (bit of the first replica at 0, second at 16, from
+// a 256-entry LDS table indexed by the spin byte): one signed 24-bit multiply-add per
+// entry and replica pair.  The total is A_0 + 2^16 A_1 exactly, whatever the signs of the
+// partial sums.  The cached entries are padded with zero weights, so the integer walk has
+// no per-entry branch.
 #include "qpa_internal.h"
 
 namespace qpa {
@@ -46,7 +49,24 @@ template <typename T> __device__ __forceinline__ T ld_as(const void *p, int32_t 
     }
 }
 
-// LDS: rp [n+1] int32 | w [nnz] int32 or float | col [nnz] uint16 | spins [2][n] bytes
+// Spread words of spin byte b (NP of them) from the LDS table.
+template <int NP>
+__device__ __forceinline__ void lut_read(const uint32_t *lut, uint32_t b, uint32_t (&sp)[NP]) {
+    if constexpr (NP == 4) {
+        const uint4 v = reinterpret_cast<const uint4 *>(lut)[b];
+        sp[0] = v.x; sp[1] = v.y; sp[2] = v.z; sp[3] = v.w;
+    } else if constexpr (NP == 2) {
+        const uint2 v = reinterpret_cast<const uint2 *>(lut)[b];
+        sp[0] = v.x; sp[1] = v.y;
+    } else {
+        sp[0] = lut[b];
+    }
+}
+
+constexpr size_t RES_LUT_BYTES = 256 * 4 * sizeof(uint32_t);
+
+// LDS: spread table [256][4] uint32 | rp [n+1] int32 | w [nnz] int32 or float |
+//      col [nnz] uint16 | spins [2][n] bytes
 template <int G, int VPT, bool INT, bool SW>
 __global__ void __launch_bounds__(RT) k_csr_resident(
     int32_t n, int32_t nnz, int64_t R, int64_t Rp, const int32_t *__restrict__ rp_g,
@@ -55,7 +75,8 @@ __global__ void __launch_bounds__(RT) k_csr_resident(
     float *__restrict__ m, float *__restrict__ h_last, int32_t t0, int32_t t1,
     const float *__restrict__ lam, float eta, float alpha) {
     extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
-    int32_t *rp = reinterpret_cast<int32_t *>(lds);
+    uint32_t *lut = reinterpret_cast<uint32_t *>(lds);
+    int32_t *rp = reinterpret_cast<int32_t *>(lds + RES_LUT_BYTES);
     int32_t *wi = rp + (n + 1);
     float *wf = reinterpret_cast<float *>(wi);
     uint16_t *col = reinterpret_cast<uint16_t *>(wi + nnz);
@@ -64,6 +85,12 @@ __global__ void __launch_bounds__(RT) k_csr_resident(
     const int tid = threadIdx.x;
     const int64_t r0 = (int64_t)blockIdx.x * G;
 
+    constexpr int NP = (G + 1) / 2;     // replica pairs, one 32-bit word each (SW)
+    if (SW)
+        for (int e = tid; e < 256 * NP; e += RT) {
+            const uint32_t byte = (uint32_t)(e / NP), p = (uint32_t)(e % NP);
+            lut[e] = ((byte >> (2 * p)) & 1u) | (((byte >> (2 * p + 1)) & 1u) << 16);
+        }
     for (int32_t k = tid; k <= n; k += RT) rp[k] = rp_g[k];
     for (int32_t k = tid; k < nnz; k += RT) {
         col[k] = (uint16_t)(col_dt == QPA_I16 ? (int32_t) static_cast<const int16_t *>(col_g)[k]
@@ -76,12 +103,11 @@ __global__ void __launch_bounds__(RT) k_csr_resident(
     // cached entries of each owned row (diagonal entries of a QUBO left out), then the
     // LDS position where the rest of the row continues
     int32_t cj[VPT][CACHE];
-    int32_t cwi[VPT][CACHE];      // SW: |w|
+    int32_t cwi[VPT][CACHE];
     float cwf[VPT][CACHE];
-    uint32_t cfl[VPT][CACHE];     // SW: replica mask where w < 0
     int32_t ccount[VPT], crest[VPT];
     int32_t wabs[VPT];            // SW: sum of |w| over the row (diagonal excluded)
-    constexpr uint32_t GMASK = (1u << G) - 1;
+    uint32_t cneg[VPT];           // SW: sum over w < 0 of |w| (1 + 2^16), modulo 2^32
     float xs[VPT][G], ms[VPT][G], bi[VPT];
 #pragma unroll
     for (int u = 0; u < VPT; ++u) {
@@ -120,12 +146,16 @@ __global__ void __launch_bounds__(RT) k_csr_resident(
             cj[u][c] = 0;
             cwi[u][c] = 0;
             cwf[u][c] = 0.0f;
-            cfl[u][c] = 0u;
         }
         wabs[u] = 0;
+        cneg[u] = 0u;
         if (SW)
             for (int32_t kk = k; kk < k1; ++kk)
-                if (!(skip_diag && col[kk] == i)) wabs[u] += wi[kk] < 0 ? -wi[kk] : wi[kk];
+                if (!(skip_diag && col[kk] == i)) {
+                    const int32_t a = wi[kk] < 0 ? -wi[kk] : wi[kk];
+                    wabs[u] += a;
+                    if (wi[kk] < 0) cneg[u] += (uint32_t)a * 0x10001u;
+                }
         // take entries in row order until CACHE of them are held
         for (; k < k1 && cnt < CACHE; ++k) {
             const int32_t j = col[k];
@@ -134,10 +164,7 @@ __global__ void __launch_bounds__(RT) k_csr_resident(
             for (int c = 0; c < CACHE; ++c)
                 if (c == cnt) {
                     cj[u][c] = j;
-                    if (SW) {
-                        cwi[u][c] = wi[k] < 0 ? -wi[k] : wi[k];
-                        cfl[u][c] = wi[k] < 0 ? GMASK : 0u;
-                    } else if (INT) {
+                    if (INT) {
                         cwi[u][c] = wi[k];
                     } else {
                         cwf[u][c] = wf[k];
@@ -165,32 +192,28 @@ __global__ void __launch_bounds__(RT) k_csr_resident(
                 af[g] = 0.0f;
             }
             if (SW) {
-                constexpr int NP = (G + 1) / 2;     // replica pairs, one 32-bit word each
                 uint32_t acc[NP];
 #pragma unroll
-                for (int p = 0; p < NP; ++p) acc[p] = 0u;
+                for (int p = 0; p < NP; ++p) acc[p] = cneg[u];
                 uint32_t cb[CACHE];
 #pragma unroll
-                for (int c = 0; c < CACHE; ++c) cb[c] = (uint32_t)cur[cj[u][c]] ^ cfl[u][c];
+                for (int c = 0; c < CACHE; ++c) cb[c] = cur[cj[u][c]];
 #pragma unroll
-                for (int c = 0; c < CACHE; ++c)
+                for (int c = 0; c < CACHE; ++c) {
+                    uint32_t sp[NP];
+                    lut_read<NP>(lut, cb[c], sp);
 #pragma unroll
-                    for (int p = 0; p < NP; ++p) {
-                        const uint32_t two = (cb[c] >> (2 * p)) & 3u;
-                        acc[p] += __umul24((uint32_t)cwi[u][c], __umul24(two, 0x8001u) & 0x10001u);
-                    }
+                    for (int p = 0; p < NP; ++p)
+                        acc[p] += (uint32_t)__mul24(cwi[u][c], (int32_t)sp[p]);
+                }
                 const int32_t k1 = rp[i + 1];
                 for (int32_t k = crest[u]; k < k1; ++k) {
                     const int32_t j = col[k];
                     if (skip_diag && j == i) continue;
-                    const int32_t wk = wi[k];
-                    const uint32_t byte = (uint32_t)cur[j] ^ (wk < 0 ? GMASK : 0u);
-                    const uint32_t aw = (uint32_t)(wk < 0 ? -wk : wk);
+                    uint32_t sp[NP];
+                    lut_read<NP>(lut, cur[j], sp);
 #pragma unroll
-                    for (int p = 0; p < NP; ++p) {
-                        const uint32_t two = (byte >> (2 * p)) & 3u;
-                        acc[p] += __umul24(aw, __umul24(two, 0x8001u) & 0x10001u);
-                    }
+                    for (int p = 0; p < NP; ++p) acc[p] += (uint32_t)__mul24(wi[k], (int32_t)sp[p]);
                 }
 #pragma unroll
                 for (int g = 0; g < G; ++g)
@@ -294,8 +317,8 @@ hipError_t launch_g_v(const CsrView &c, int64_t R, int64_t Rp, bool is_int, bool
 }  // namespace
 
 size_t csr_resident_lds(int64_t n, int64_t nnz) {
-    return sizeof(int32_t) * (size_t)(n + 1) + (sizeof(int32_t) + sizeof(uint16_t)) * (size_t)nnz +
-           2 * (size_t)n + 16;
+    return RES_LUT_BYTES + sizeof(int32_t) * (size_t)(n + 1) +
+           (sizeof(int32_t) + sizeof(uint16_t)) * (size_t)nnz + 2 * (size_t)n + 16;
 }
 
 namespace {
