@@ -531,6 +531,7 @@ __global__ void __launch_bounds__(THREADS, 1) k_mfma_grouped(const MfmaTile *__r
                                                              float eta, float alpha) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[LDS_BYTES];
     const MfmaTile mt = tiles[blockIdx.x];
+    if (mt.np == 0) return;      // filler entry of the compute-die-ordered table
     const uint32_t *cur = (t & 1) ? mt.s1 : mt.s0;
     uint32_t *nxt = (t & 1) ? mt.s0 : mt.s1;
     const Tile tl{mt.np, mt.Rp, mt.I0, mt.R0, mt.rlive, mt.Jb, mt.b,

@@ -695,7 +695,34 @@ struct BatchPlan {
     std::vector<DenseSlot> dense;
     size_t o_tasks, o_tiles, o_counter, o_lam, total;
     int32_t ntasks, ntiles_max, max_n;
+    int32_t inst_tiles_max;   // most tiles of one dense candidate
 };
+
+// Workgroup i of a launch runs on compute die (XCD) i mod XCDS, each with its own L2.
+constexpr int32_t XCDS = 8;
+
+// Lay a tile list (tiles of one instance consecutive) out so that every instance's tiles
+// run on one compute die: instances go, in list order, to the die with the fewest tiles so
+// far, and entry XCDS * s + d of the table is die d's s-th tile; shorter dies are filled
+// with np = 0 entries, which the kernel skips.  The tiles of an instance then share that
+// die's L2 copy of its spins, which each tile reads whole.
+std::vector<MfmaTile> by_compute_die(const std::vector<MfmaTile> &in) {
+    std::vector<std::vector<MfmaTile>> q(XCDS);
+    std::vector<size_t> load(XCDS, 0);
+    for (size_t a = 0; a < in.size();) {
+        size_t b = a + 1;
+        while (b < in.size() && in[b].s0 == in[a].s0) ++b;
+        const size_t d = (size_t)(std::min_element(load.begin(), load.end()) - load.begin());
+        q[d].insert(q[d].end(), in.begin() + (std::ptrdiff_t)a, in.begin() + (std::ptrdiff_t)b);
+        load[d] += b - a;
+        a = b;
+    }
+    const size_t L = *std::max_element(load.begin(), load.end());
+    std::vector<MfmaTile> out(XCDS * L, MfmaTile{});
+    for (size_t d = 0; d < (size_t)XCDS; ++d)
+        for (size_t s = 0; s < q[d].size(); ++s) out[XCDS * s + d] = q[d][s];
+    return out;
+}
 
 // Cost model of one PA step of one instance on the two batch paths, in seconds, with
 // rates measured on MI355X: the CSR task kernel sustains about 0.3e12 signed coupling
@@ -719,6 +746,7 @@ qpa_status make_batch_plan(qpa_ctx *ctx, int32_t count, const qpa_problem *probs
     size_t off = 0;
     bp.ntasks = 0;
     bp.ntiles_max = 0;
+    bp.inst_tiles_max = 0;
     bp.max_n = 0;
     const int64_t groups = (a.replicas + 63) / 64;
     for (int32_t k = 0; k < count; ++k) {
@@ -761,7 +789,9 @@ qpa_status make_batch_plan(qpa_ctx *ctx, int32_t count, const qpa_problem *probs
             // room for byte spins (int8 tiles), twice the pair words of BF16 tiles
             ds.o_s0 = tk((size_t)(Rp * np));
             ds.o_s1 = tk((size_t)(Rp * np));
-            bp.ntiles_max += (int32_t)((np / MF_BN) * (Rp / MF_BM));
+            const int32_t it = (int32_t)((np / MF_BN) * (Rp / MF_BM));
+            bp.ntiles_max += it;
+            bp.inst_tiles_max = std::max(bp.inst_tiles_max, it);
         }
         bp.dense.push_back(ds);
     }
@@ -771,7 +801,10 @@ qpa_status make_batch_plan(qpa_ctx *ctx, int32_t count, const qpa_problem *probs
         return o;
     };
     bp.o_tasks = take(sizeof(BatchTask) * (size_t)bp.ntasks);
-    bp.o_tiles = take(sizeof(MfmaTile) * (size_t)std::max(bp.ntiles_max, 1));
+    // each of the two tile lists (BF16, int8) may gain up to XCDS * inst_tiles_max
+    // filler entries when it is laid out by compute die
+    bp.o_tiles = take(sizeof(MfmaTile) *
+                      (size_t)std::max(bp.ntiles_max + 2 * XCDS * bp.inst_tiles_max, 1));
     bp.o_counter = take(sizeof(int32_t));
     bp.o_lam = take(sizeof(float) * (size_t)std::max<int32_t>(a.steps, 1));
     bp.total = off;
@@ -1224,6 +1257,8 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
     auto by_size = [](const MfmaTile &a, const MfmaTile &b) { return a.np > b.np; };
     std::stable_sort(tiles.begin(), tiles.end(), by_size);
     std::stable_sort(tiles8.begin(), tiles8.end(), by_size);
+    tiles = by_compute_die(tiles);
+    tiles8 = by_compute_die(tiles8);
     const int32_t ntiles16 = (int32_t)tiles.size(), ntiles8 = (int32_t)tiles8.size();
     tiles.insert(tiles.end(), tiles8.begin(), tiles8.end());
 
