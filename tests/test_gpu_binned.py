@@ -214,3 +214,37 @@ def test_binned_graph_replays_match_plain_launches(q, eng):
         assert np.array_equal(host(out["energy_i64"]), host(ref["energy_i64"]))
         eng.energy(prob, _params(q, R, T, 0.1, 0.8, 6.0, 0), out["spins"])
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("kind", ["no-edges", "diagonal-only-qubo"])
+def test_binned_without_entries(q, eng, kind):
+    """An instance with no off-diagonal couplings leaves the binned entry order empty;
+    the fields are the linear terms alone, as in the oracle."""
+    n = 70_000
+    rng = np.random.default_rng(21)
+    if kind == "no-edges":
+        csr = gen.CSR(n, np.zeros(n + 1, np.int32), np.zeros(0, np.int32), np.zeros(0, np.int8))
+        inst = gen.Instance("ising", n, csr=csr,
+                            lin=rng.integers(-5, 6, size=n).astype(np.int8), meta={})
+    else:
+        d = np.flatnonzero(rng.random(n) < 0.5)
+        rp = np.zeros(n + 1, np.int64)
+        rp[1:] = np.cumsum(np.isin(np.arange(n), d))
+        csr = gen.CSR(n, rp.astype(np.int32), d.astype(np.int32),
+                      rng.integers(-9, 10, size=len(d)).astype(np.int16))
+        inst = gen.Instance("qubo", n, csr=csr,
+                            lin=rng.integers(-9, 10, size=n).astype(np.int16), meta={})
+    prob = q.Problem.from_instance(inst)
+    R, T = 6, 7
+    say("binned without entries: " + kind)
+    out, paths = _paths(q, eng, lambda: eng.solve(
+        prob, _params(q, R, T, 0.1, 0.8, 3.0, q.QPA_SOLVE_BINNED), want_state=True))
+    assert paths == {q.QPA_PATH_CSR_BINNED: 2 * T}, paths
+    x, m, canon = _oracle(inst, R, T, orc.lambda_linear(T, 3.0), 0.1, 0.8)
+    assert np.array_equal(host(out["x"]), x) and np.array_equal(host(out["m"]), m)
+    rp, col, w, b, K = canon
+    spins = host(out["spins"])
+    for r in range(R):
+        H = orc.ising_energy_csr_int(rp, col, w, b, spins[r])
+        e = (H + K) // 2 if inst.kind == "qubo" else H
+        assert int(host(out["energy_i64"])[r]) == e, r
