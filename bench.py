@@ -445,8 +445,8 @@ def main():
             roof = {"bound": "mfma", "peak": PEAK_BF16_TFLOPS, "kernel": "k_mfma_step"}
         else:
             roof = {"bound": "alu", "peak": PEAK_FP32_TFLOPS,
-                    "kernel": "k_dense_resident" if per_solve_launches <= 1.0
-                    else "k_dense_tiled_step"}
+                    "kernel": ("k_dense_wave" if n <= 64 else "k_dense_resident")
+                    if per_solve_launches <= 1.0 else "k_dense_tiled_step"}
         roof.update({"achieved": achieved, "unit": "TFLOP/s", "per_launch": what})
         e = out["energy"].cpu().numpy()
         extra = {"best_energy": float(e.min()), "best_replica": int(out["best"].cpu()[0])}

@@ -91,6 +91,57 @@ __global__ void __launch_bounds__(RES_THREADS) k_dense_resident(
     }
 }
 
+// ---------------------------------------------------------------- one wave per replica
+// n <= 64: lane i holds row i of J (NW >= n registers), x_i and m_i.  The spins of a step
+// are one 64-bit ballot (bit j set <=> x_j < 0), so the sign of term j is the same in every
+// lane, and J_ij * s_j is J_ij with its sign bit flipped where s_j = -1 (the FP32 product,
+// exactly).  The sums ascend in j from zero as in the block kernel; no LDS, no barrier.
+// The schedule is read 64 steps at a time, one value per lane.
+template <int NW>
+__global__ void __launch_bounds__(64) k_dense_wave(int n, const float *__restrict__ J,
+                                                   const float *__restrict__ b,
+                                                   float *__restrict__ x, float *__restrict__ m,
+                                                   float *__restrict__ h_last, int t0, int t1,
+                                                   const float *__restrict__ lam, float eta,
+                                                   float alpha) {
+    const int i = threadIdx.x;
+    const bool act = i < n;
+    const int64_t g = (int64_t)blockIdx.x * n + i;
+    float Jr[NW];
+#pragma unroll
+    for (int j = 0; j < NW; ++j) Jr[j] = (act && j < n) ? J[(int64_t)i * n + j] : 0.0f;
+    float xi = 0.0f, mi = 0.0f, bi = 0.0f, hi = 0.0f;
+    if (act) {
+        xi = x[g];
+        mi = m[g];
+        bi = b[i];
+    }
+    uint64_t neg = __ballot(act && xi < 0.0f);
+    for (int tb = t0; tb < t1; tb += 64) {
+        const float lv = tb + i < t1 ? lam[tb + i] : 0.0f;
+        const int te = t1 - tb < 64 ? t1 - tb : 64;
+        for (int k = 0; k < te; ++k) {
+            const float lt = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lv), k));
+            float acc = 0.0f;
+            // terms j >= n are +0.0 (zero coupling, spin bit clear): a sum that starts at
+            // +0.0 never becomes -0.0 under round-to-nearest, so adding them changes no bit
+#pragma unroll
+            for (int j = 0; j < NW; ++j) {
+                const uint32_t sgn = (uint32_t)((neg >> j) & 1u) << 31;
+                acc = __fadd_rn(acc, __uint_as_float(__float_as_uint(Jr[j]) ^ sgn));
+            }
+            hi = __fadd_rn(acc, bi);
+            pa_update(hi, lt, eta, alpha, xi, mi);
+            neg = __ballot(act && xi < 0.0f);
+        }
+    }
+    if (act) {
+        x[g] = xi;
+        m[g] = mi;
+        if (h_last && t1 > t0) h_last[g] = hi;
+    }
+}
+
 // ---------------------------------------------------------------- tiled, one step
 // Block tile: 64 replicas x 64 variables, 256 threads; thread (ty, tx) owns replicas
 // r0 + 4*ty + q (q < 4) and variables i0 + tx + 16*c (c < 4).  K is walked in chunks of
@@ -187,6 +238,19 @@ hipError_t launch_dense_resident(int64_t n, int64_t R, const float *J, const flo
                                  float *x, float *m, float *h_last, int32_t t0, int32_t t1,
                                  const float *lam, float eta, float alpha, hipStream_t st) {
     if (!dense_resident_fits(n)) return hipErrorInvalidValue;
+    if (n <= 64 && R <= INT32_MAX) {
+        const unsigned grid = (unsigned)R;
+        if (n <= 16)
+            k_dense_wave<16><<<grid, 64, 0, st>>>((int)n, J, b, x, m, h_last, t0, t1, lam, eta,
+                                                  alpha);
+        else if (n <= 32)
+            k_dense_wave<32><<<grid, 64, 0, st>>>((int)n, J, b, x, m, h_last, t0, t1, lam, eta,
+                                                  alpha);
+        else
+            k_dense_wave<64><<<grid, 64, 0, st>>>((int)n, J, b, x, m, h_last, t0, t1, lam, eta,
+                                                  alpha);
+        return hipGetLastError();
+    }
     const int rb = resident_rb(n);
     const unsigned grid = (unsigned)((R + rb - 1) / rb);
     const size_t lds = resident_lds_bytes(n);

@@ -87,6 +87,28 @@ def test_dense_int_ising_ragged(q, eng, n, R, T):
     _check_solve_dense_int(q, eng, inst, R, T, 0.01, 0.7, 5.0)
 
 
+@pytest.mark.parametrize("n", [17, 33, 63, 64, 65, 100, 128])
+def test_dense_resident_sizes(q, eng, n):
+    """Small dense instances run all steps in one launch: one wave per replica for n <= 64
+    (row of J in registers, spins as a ballot), a workgroup of replicas above; both equal
+    the oracle bit for bit, fields of the last step included."""
+    import torch
+    inst = gen.dense_int_ising(n, -9, 9, seed=100 + n)
+    _check_solve_dense_int(q, eng, inst, 7, 40, 0.01, 0.7, 5.0)
+    prob = q.Problem.from_instance(inst)
+    R, T = 5, 23
+    p = _params(q, R, T, 0.02, 0.8, 6.0)
+    x0, _ = orc.pa_init(n, R, 1, np.float32(0.1))
+    xd = torch.from_numpy(x0.copy()).cuda()
+    md = torch.zeros_like(xd)
+    h = eng.steps(prob, p, 0, T, xd, md, want_h=True)
+    x, m = x0.copy(), np.zeros_like(x0)
+    hr = orc.pa_steps_dense_int(inst.dense, inst.lin, x, m, 0, T, orc.lambda_linear(T, 6.0),
+                                0.02, 0.8, want_h=True)
+    assert np.array_equal(host(xd), x) and np.array_equal(host(md), m)
+    assert np.array_equal(host(h), hr)
+
+
 def test_dense_int_bf16_ragged_tiles(q, eng):
     inst = gen.dense_int_ising(200, -50, 50, seed=8)
     _check_solve_dense_int(q, eng, inst, 130, 40, 0.001, 0.7, 50.0, prec="bf16")
@@ -99,7 +121,7 @@ def _oracle_dense_float(J, b, R, T, lam, eta, alpha, seed=1):
     return x, m
 
 
-@pytest.mark.parametrize("n,R,T", [(300, 70, 40), (64, 5, 100)])
+@pytest.mark.parametrize("n,R,T", [(300, 70, 40), (64, 5, 100), (20, 9, 50), (45, 3, 60), (100, 4, 30)])
 def test_dense_float_fp32_bit_exact(q, eng, n, R, T):
     inst = gen.sk_ising(n, 0.1, seed=n)
     prob = q.Problem.from_instance(inst)
