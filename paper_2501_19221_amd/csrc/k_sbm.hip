@@ -383,6 +383,41 @@ __global__ void __launch_bounds__(SRT) k_sbm_csr_resident(
     const float c0 = *c0p;
     const float adt = __fmul_rn(dt, a0);
     __syncthreads();
+    // the first CACHE off-diagonal entries of each owned row in registers, unused slots
+    // with weight 0: a multiply-add chain that starts at +0.0 never reaches -0.0 under
+    // round-to-nearest, so adding a zero product changes no bit; the step then issues the
+    // position reads of the cached entries together
+    // at most 32 cached positions and, with 8 variables per thread, one entry per row
+    constexpr int CA = VPT >= 8 ? 1 : (16 / VPT) < 8 ? (16 / VPT) : 8;
+    constexpr int CACHE = CA * G > 32 ? 32 / G : CA;
+    int32_t cj[VPT][CACHE], crest[VPT];
+    float cw[VPT][CACHE];
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+        const int32_t i = tid + u * SRT;
+        int32_t k = 0, k1 = 0, cnt = 0;
+        if (i < n) {
+            k = rp[i];
+            k1 = rp[i + 1];
+        }
+#pragma unroll
+        for (int c = 0; c < CACHE; ++c) {
+            cj[u][c] = 0;
+            cw[u][c] = 0.0f;
+        }
+        for (; k < k1 && cnt < CACHE; ++k) {
+            const int32_t j = col[k];
+            if (skip_diag && j == i) continue;
+#pragma unroll
+            for (int c = 0; c < CACHE; ++c)
+                if (c == cnt) {
+                    cj[u][c] = j;
+                    cw[u][c] = wf[k];
+                }
+            ++cnt;
+        }
+        crest[u] = k;
+    }
     for (int32_t t = t0; t < t1; ++t) {
         const float a = atab[t];
 #pragma unroll
@@ -392,8 +427,15 @@ __global__ void __launch_bounds__(SRT) k_sbm_csr_resident(
 #pragma unroll
             for (int g = 0; g < G; ++g) acc[g] = 0.0f;
             if (i < n) {
+                float qc[CACHE][G];
+#pragma unroll
+                for (int c = 0; c < CACHE; ++c) sbm_lds_read<G>(qv, cj[u][c], qc[c]);
+#pragma unroll
+                for (int c = 0; c < CACHE; ++c)
+#pragma unroll
+                    for (int g = 0; g < G; ++g) acc[g] = __fmaf_rn(cw[u][c], qc[c][g], acc[g]);
                 const int32_t k1 = rp[i + 1];
-                for (int32_t k = rp[i]; k < k1; ++k) {
+                for (int32_t k = crest[u]; k < k1; ++k) {
                     const int32_t j = col[k];
                     if (skip_diag && j == i) continue;
                     const float w = wf[k];
