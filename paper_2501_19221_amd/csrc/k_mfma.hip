@@ -465,6 +465,9 @@ __device__ __forceinline__ void state_update(StateRegs &st, const Tile &tl, cons
     }
 }
 
+// NT: non-temporal stores (measured: 1.6 % faster for the single-instance step, 1.5 %
+// slower for the grouped batch step, whose next step finds more of x, m in the caches).
+template <bool NT>
 __device__ __forceinline__ void state_store(const StateRegs &st, const Tile &tl, int t) {
     const int col = t & (BN - 1);
     const int rsub = __builtin_amdgcn_readfirstlane(t >> 7);
@@ -473,8 +476,13 @@ __device__ __forceinline__ void state_store(const StateRegs &st, const Tile &tl,
 #pragma unroll
     for (int e = 0; e < SR; ++e) {
         if (tl.R0 + 4 * e + rsub < tl.rlive) {
-            xr[col] = st.xv[e];
-            mr[col] = st.mv[e];
+            if (NT) {
+                __builtin_nontemporal_store(st.xv[e], &xr[col]);
+                __builtin_nontemporal_store(st.mv[e], &mr[col]);
+            } else {
+                xr[col] = st.xv[e];
+                mr[col] = st.mv[e];
+            }
         }
         xr = next_rows(xr, 4 * tl.np);
         mr = next_rows(mr, 4 * tl.np);
@@ -482,7 +490,7 @@ __device__ __forceinline__ void state_store(const StateRegs &st, const Tile &tl,
 }
 
 // One PA step of one tile: matrix and state waves side by side.
-template <bool I8>
+template <bool I8, bool NT>
 __device__ __forceinline__ void mfma_tile_step(uint8_t *lds, const Tile &tl,
                                                const uint32_t *__restrict__ s_cur,
                                                uint32_t *__restrict__ s_nxt,
@@ -501,7 +509,7 @@ __device__ __forceinline__ void mfma_tile_step(uint8_t *lds, const Tile &tl,
         state_collect(st);
         state_update<I8>(st, tl, reinterpret_cast<const float *>(lds), s_nxt, h_last, t,
                             wave, lane, lt, eta, alpha);
-        state_store(st, tl, t);
+        state_store<NT>(st, tl, t);
         return;
     }
     if (I8)
@@ -519,7 +527,7 @@ __global__ void __launch_bounds__(THREADS, 1) k_mfma_step(
     __shared__ __attribute__((aligned(16))) uint8_t lds[LDS_BYTES];
     const Tile tl{np, Rp, (int64_t)blockIdx.x * BN, (int64_t)blockIdx.y * BM, rlive, Jb, b,
                   sc->scale, x, m};
-    mfma_tile_step<false>(lds, tl, s_cur, s_nxt, h_last, lam[t], eta, alpha);
+    mfma_tile_step<false, true>(lds, tl, s_cur, s_nxt, h_last, lam[t], eta, alpha);
 }
 
 // Many instances in one launch: block k runs tile k of the table.  Each tile points at
@@ -536,7 +544,7 @@ __global__ void __launch_bounds__(THREADS, 1) k_mfma_grouped(const MfmaTile *__r
     uint32_t *nxt = (t & 1) ? mt.s0 : mt.s1;
     const Tile tl{mt.np, mt.Rp, mt.I0, mt.R0, mt.rlive, mt.Jb, mt.b,
                   I8 ? 1.0f : mt.sc->scale, mt.x, mt.m};
-    mfma_tile_step<I8>(lds, tl, cur, nxt, nullptr, lam[t], eta, alpha);
+    mfma_tile_step<I8, false>(lds, tl, cur, nxt, nullptr, lam[t], eta, alpha);
 }
 
 // Byte spins of the signs of x (chunk-major, 128 bytes per replica and chunk).
