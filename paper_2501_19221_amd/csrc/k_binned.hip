@@ -6,17 +6,22 @@
 // it serves.  Here the gather is split into two streaming passes over an entry order
 // fixed once per run (propagation blocking):
 //   source chunks: C = 2^20 / G variables, whose spin words (128 KiB) fit in LDS;
-//   destination bins: B = 2^14 / G rows, whose int32 field sums (64 KiB) fit in LDS;
+//   destination bins: B = 2^14 L / G rows, whose field sums fit in 2^14 words of LDS,
+//     L = 4, 2 or 1 sums per word (8-, 16- or 32-bit lanes, chosen from the row bound);
 //   entries (diagonal excluded for QUBO) ordered by (chunk, bin), any order inside a block.
 //   pass 1, k_bin_gather: a workgroup loads the spin words of one chunk into LDS and, for
 //     a contiguous share of the chunk's entries, writes the G spin bits of each entry's
 //     column to bits[p];
-//   pass 2, k_bin_update: a workgroup clears B x G int32 sums in LDS, adds +-w of every
-//     entry of its bin to the sums of each replica (LDS atomics), then runs the fused
-//     update of its rows (x, m, spin words), the same arithmetic as the streamed kernel.
+//   pass 2, k_bin_update: a workgroup clears its sums in LDS and adds, for every entry of
+//     its bin, |w| b' per replica with b' = b XOR [w < 0] (one LDS atomic per word of L
+//     lanes); the field is then h = c - 2 A with A the replica's sum and c = sum |w| + b
+//     per row (built once per call), since a term w (1 - 2b) equals |w| (1 - 2b').  Then
+//     the fused update of its rows (x, m, spin words), the arithmetic of the streamed
+//     kernel.  A lane of W bits never carries into the next: A <= sum |w| < 2^W.
 // Integer sums are exact, so the order of the entries inside a block does not change a
-// bit of the result.  Entries carry the column's offset in its chunk (uint32) and the
-// row's offset in its bin with the weight (low / high 16 bits of a uint32).
+// bit of the result, and (float)(c - 2A) equals the streamed kernel's (float)sum + b.
+// Entries carry the column's offset in its chunk (uint32) and the row's offset in its bin
+// with the weight (low / high 16 bits of a uint32).
 #include "qpa_internal.h"
 
 namespace qpa {
@@ -24,7 +29,7 @@ namespace {
 
 constexpr int BT = 1024;                 // threads per workgroup of every kernel here
 constexpr int CHUNK_WORDS = 1 << 14;     // spin words (uint64) of one source chunk
-constexpr int BIN_SUMS = 1 << 14;        // int32 sums (rows x replicas) of one bin
+constexpr int BIN_WORDS = 1 << 14;       // LDS words of field sums of one bin
 constexpr int SCAN_TILE = 4 * BT;        // elements per workgroup of the offset scan
 
 __device__ __forceinline__ void pa_update(float h, float lam, float eta, float alpha, float &x,
@@ -170,6 +175,25 @@ __global__ void __launch_bounds__(256) k_bin_scatter(int64_t n, const int32_t *_
     }
 }
 
+// Row constants c_i = sum over off-diagonal entries of |w| + b_i (exact integers).
+template <typename TI, typename TW>
+__global__ void __launch_bounds__(256) k_bin_rowconst(int64_t n, const int32_t *__restrict__ rp,
+                                                      const TI *__restrict__ col,
+                                                      const TW *__restrict__ w, int skip_diag,
+                                                      const int64_t *__restrict__ b_i64,
+                                                      int32_t *__restrict__ crow) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t c = b_i64[i];
+    const int32_t k1 = rp[i + 1];
+    for (int32_t k = rp[i]; k < k1; ++k) {
+        if (skip_diag && (int64_t)col[k] == i) continue;
+        const int64_t v = (int64_t)w[k];
+        c += v < 0 ? -v : v;
+    }
+    crow[i] = (int32_t)c;
+}
+
 // Pass 1.  Grid (Nc, S): chunk c, share s of its entries.
 __global__ void __launch_bounds__(BT) k_bin_gather(int shiftG, int64_t nwords, int64_t Nb,
                                                    const int32_t *__restrict__ off,
@@ -211,16 +235,22 @@ __global__ void __launch_bounds__(BT) k_bin_gather(int shiftG, int64_t nwords, i
     }
 }
 
-// Pass 2.  One workgroup per bin of B = BIN_SUMS / G rows; dynamic LDS holds the run
+// Pass 2.  One workgroup per bin of B = BIN_WORDS L / G rows; dynamic LDS holds the run
 // starts and prefix lengths of the bin's Nc runs (2 (Nc + 1) int32), so that two
-// workgroups share a compute unit and one's loads overlap the other's arithmetic.
+// workgroups share a compute unit and one's loads overlap the other's arithmetic.  For
+// L > 1 a table in LDS spreads a (flipped) spin byte into the G / L words of its lanes.
+template <int L>
 __global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(8))) k_bin_update(
     int64_t n, int shiftG, int64_t Nb, int64_t Nc, int64_t nwords,
     const int32_t *__restrict__ off, const uint8_t *__restrict__ bits,
-    const uint32_t *__restrict__ drec, const float *__restrict__ b,
+    const uint32_t *__restrict__ drec, const int32_t *__restrict__ crow,
     uint64_t *__restrict__ s_nxt, float *__restrict__ x, float *__restrict__ m,
     float *__restrict__ h_last, int t, const float *__restrict__ lam, float eta, float alpha) {
-    __shared__ int32_t acc[BIN_SUMS];
+    constexpr int LW = 32 / L;                          // lane width in bits
+    constexpr uint32_t LMASK = L == 1 ? 0xffffffffu : (1u << LW) - 1;
+    constexpr int SUMS = BIN_WORDS * L;                 // (row, replica) sums of a bin
+    __shared__ uint32_t acc[BIN_WORDS];
+    __shared__ uint32_t spread[L > 1 ? 256 * 8 / L : 1];
     __shared__ int32_t wsum[BT / 64];
     extern __shared__ int32_t runs[];
     int32_t *st = runs;               // start of the run of chunk c
@@ -228,7 +258,16 @@ __global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(8))) k_
     const int64_t bin = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63;
     const int G = 1 << shiftG;
-    for (int q = tid; q < BIN_SUMS; q += BT) acc[q] = 0;
+    const int WPE = G / L;            // words of one entry (L <= G)
+    const uint32_t gmask = (1u << G) - 1;
+    for (int q = tid; q < BIN_WORDS; q += BT) acc[q] = 0u;
+    if (L > 1)
+        for (int e = tid; e < 256 * WPE; e += BT) {
+            const uint32_t byte = (uint32_t)(e / WPE), k = (uint32_t)(e % WPE);
+            uint32_t v = 0u;
+            for (int l = 0; l < L; ++l) v |= ((byte >> (k * L + l)) & 1u) << (LW * l);
+            spread[e] = v;
+        }
     // run of chunk c in this bin: [off[c*Nb + bin], off[c*Nb + bin + 1])
     int32_t v[2];
 #pragma unroll
@@ -273,29 +312,38 @@ __global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(8))) k_
         for (int u = 0; u < U; ++u) {
             if (e0 + u * BT >= total) continue;
             const int32_t wv = (int32_t)rec[u] >> 16;
-            int32_t *a = acc + ((rec[u] & 0xffffu) << shiftG);
-            for (int r = 0; r < G; ++r) atomicAdd(a + r, ((bv[u] >> r) & 1u) ? -wv : wv);
+            const uint32_t aw = (uint32_t)(wv < 0 ? -wv : wv);
+            const uint32_t fb = bv[u] ^ (wv < 0 ? gmask : 0u);        // b' of each replica
+            uint32_t *a = acc + ((rec[u] & 0xffffu) << shiftG) / L;
+            if (L == 1) {
+                for (int r = 0; r < G; ++r)
+                    if ((fb >> r) & 1u) atomicAdd(a + r, aw);
+            } else {
+                for (int k = 0; k < WPE; ++k) atomicAdd(a + k, aw * spread[fb * WPE + k]);
+            }
         }
     }
     __syncthreads();
     // fused update of the bin's (row, replica) pairs; state index = row * G + replica.
     // UQ pairs per thread per round: every load of a round is issued before its stores.
     constexpr int UQ = 4;
-    static_assert((BIN_SUMS / BT) % UQ == 0, "rounds must cover the bin exactly");
-    const int64_t q0 = bin * BIN_SUMS;
+    static_assert((BIN_WORDS / BT) % UQ == 0, "rounds must cover the bin exactly");
+    const int64_t q0 = bin * SUMS;
     const float lt = lam[t];
-    for (int qb = tid; qb < BIN_SUMS; qb += UQ * BT) {
-        float xv[UQ], mv[UQ], bb[UQ];
+    for (int qb = tid; qb < SUMS; qb += UQ * BT) {
+        float xv[UQ], mv[UQ];
+        int32_t cr[UQ];
         bool live[UQ];
 #pragma unroll
         for (int u = 0; u < UQ; ++u) {
             const int64_t gi = q0 + qb + u * BT;
             live[u] = (gi >> shiftG) < n;
-            xv[u] = mv[u] = bb[u] = 0.0f;
+            xv[u] = mv[u] = 0.0f;
+            cr[u] = 0;
             if (live[u]) {
                 xv[u] = x[gi];
                 mv[u] = m[gi];
-                bb[u] = b[gi >> shiftG];
+                cr[u] = crow[gi >> shiftG];
             }
         }
 #pragma unroll
@@ -304,7 +352,8 @@ __global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(8))) k_
             const int64_t gi = q0 + q;
             bool neg = false;
             if (live[u]) {
-                const float h = __fadd_rn((float)acc[q], bb[u]);
+                const int32_t A = (int32_t)((acc[q / L] >> (LW * (q % L))) & LMASK);
+                const float h = (float)(cr[u] - 2 * A);
                 pa_update(h, lt, eta, alpha, xv[u], mv[u]);
                 x[gi] = xv[u];
                 m[gi] = mv[u];
@@ -326,12 +375,15 @@ int ilog2(int64_t v) {
 
 }  // namespace
 
-bool bin_geometry(int64_t n, int G, BinGeom &g) {
+bool bin_geometry(int64_t n, int G, int lanes, BinGeom &g) {
     if (G < 1 || G > 8 || (G & (G - 1)) != 0 || n < 1) return false;
+    if (lanes != 1 && lanes != 2 && lanes != 4) return false;
+    if (lanes > G) return false;
     g.G = G;
+    g.lanes = lanes;
     g.shiftG = ilog2(G);
-    g.cshift = 20 - g.shiftG;          // C * G / 64 = CHUNK_WORDS
-    g.bshift = 14 - g.shiftG;          // B * G = BIN_SUMS
+    g.cshift = 20 - g.shiftG;                    // C * G / 64 = CHUNK_WORDS
+    g.bshift = 14 + ilog2(lanes) - g.shiftG;     // B * G = BIN_WORDS * lanes
     g.Nc = (n + ((int64_t)1 << g.cshift) - 1) >> g.cshift;
     g.Nb = (n + ((int64_t)1 << g.bshift) - 1) >> g.bshift;
     g.M = g.Nc * g.Nb;
@@ -340,8 +392,9 @@ bool bin_geometry(int64_t n, int G, BinGeom &g) {
 
 int64_t bin_scan_tiles(const BinGeom &g) { return (g.M + SCAN_TILE - 1) / SCAN_TILE; }
 
-hipError_t launch_bin_build(const CsrView &c, const BinGeom &g, int32_t *off, int32_t *cur,
-                            int32_t *tsum, uint32_t *src, uint32_t *drec, hipStream_t st) {
+hipError_t launch_bin_build(const CsrView &c, const BinGeom &g, const int64_t *b_i64,
+                            int32_t *off, int32_t *cur, int32_t *tsum, uint32_t *src,
+                            uint32_t *drec, int32_t *crow, hipStream_t st) {
     const unsigned rows = (unsigned)((c.n + 255) / 256);
     int64_t fg = (g.M + 255) / 256;
     if (fg > 65536) fg = 65536;
@@ -361,14 +414,21 @@ hipError_t launch_bin_build(const CsrView &c, const BinGeom &g, int32_t *off, in
         k_bin_offsets<<<(unsigned)nt, BT, 0, st>>>(cur, g.M, tsum, off, cur);
         e2 = hipGetLastError();
         if (e2 != hipSuccess) return e2;
-        if (c.w_dt == QPA_I8)
-            k_bin_scatter<TI, int8_t><<<rows, 256, 0, st>>>(
-                c.n, c.rp, col, static_cast<const int8_t *>(c.w), c.skip_diag, g.cshift,
-                g.bshift, g.Nb, cur, src, drec);
-        else
-            k_bin_scatter<TI, int16_t><<<rows, 256, 0, st>>>(
-                c.n, c.rp, col, static_cast<const int16_t *>(c.w), c.skip_diag, g.cshift,
-                g.bshift, g.Nb, cur, src, drec);
+        if (c.w_dt == QPA_I8) {
+            const int8_t *w = static_cast<const int8_t *>(c.w);
+            k_bin_scatter<TI, int8_t><<<rows, 256, 0, st>>>(c.n, c.rp, col, w, c.skip_diag,
+                                                            g.cshift, g.bshift, g.Nb, cur, src,
+                                                            drec);
+            k_bin_rowconst<TI, int8_t><<<rows, 256, 0, st>>>(c.n, c.rp, col, w, c.skip_diag,
+                                                             b_i64, crow);
+        } else {
+            const int16_t *w = static_cast<const int16_t *>(c.w);
+            k_bin_scatter<TI, int16_t><<<rows, 256, 0, st>>>(c.n, c.rp, col, w, c.skip_diag,
+                                                             g.cshift, g.bshift, g.Nb, cur, src,
+                                                             drec);
+            k_bin_rowconst<TI, int16_t><<<rows, 256, 0, st>>>(c.n, c.rp, col, w, c.skip_diag,
+                                                              b_i64, crow);
+        }
         return hipGetLastError();
     };
     if (c.w_dt != QPA_I8 && c.w_dt != QPA_I16) return hipErrorInvalidValue;
@@ -377,7 +437,7 @@ hipError_t launch_bin_build(const CsrView &c, const BinGeom &g, int32_t *off, in
 
 hipError_t launch_bin_step(const BinGeom &g, int64_t n, int64_t nwords, const int32_t *off,
                            const uint32_t *src, const uint32_t *drec, uint8_t *bits,
-                           const float *b_f32, const uint64_t *s_cur, uint64_t *s_nxt, float *x,
+                           const int32_t *crow, const uint64_t *s_cur, uint64_t *s_nxt, float *x,
                            float *m, float *h_last, int32_t t, const float *lam, float eta,
                            float alpha, int cus, hipStream_t st) {
     int64_t S = (4 * (int64_t)cus + g.Nc - 1) / g.Nc;
@@ -388,9 +448,16 @@ hipError_t launch_bin_step(const BinGeom &g, int64_t n, int64_t nwords, const in
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t lds = sizeof(int32_t) * 2 * (size_t)(g.Nc + 1);
-    k_bin_update<<<(unsigned)g.Nb, BT, lds, st>>>(n, g.shiftG, g.Nb, g.Nc, nwords, off, bits,
-                                                  drec, b_f32, s_nxt, x, m, h_last, t, lam, eta,
-                                                  alpha);
+    const unsigned nb = (unsigned)g.Nb;
+    if (g.lanes == 4)
+        k_bin_update<4><<<nb, BT, lds, st>>>(n, g.shiftG, g.Nb, g.Nc, nwords, off, bits, drec,
+                                             crow, s_nxt, x, m, h_last, t, lam, eta, alpha);
+    else if (g.lanes == 2)
+        k_bin_update<2><<<nb, BT, lds, st>>>(n, g.shiftG, g.Nb, g.Nc, nwords, off, bits, drec,
+                                             crow, s_nxt, x, m, h_last, t, lam, eta, alpha);
+    else
+        k_bin_update<1><<<nb, BT, lds, st>>>(n, g.shiftG, g.Nb, g.Nc, nwords, off, bits, drec,
+                                             crow, s_nxt, x, m, h_last, t, lam, eta, alpha);
     return hipGetLastError();
 }
 

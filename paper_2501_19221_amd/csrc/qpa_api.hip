@@ -85,12 +85,12 @@ struct Plan {
     int64_t nwords;       // CSR spin words per group (streamed layout)
     bool is_int, is_qubo;
     bool bin_ok;          // the binned sparse kernels apply (their arrays are allocated)
-    BinGeom bg;
+    BinGeom bg;           // their geometry with one sum per word (the most blocks)
     int64_t eblk;         // energy partial blocks
     // workspace offsets (bytes)
     size_t o_sc, o_lam, o_bf, o_bi, o_bd, o_rabs, o_rmax, o_rk, o_Jf, o_Jb, o_x, o_m, o_h,
         o_s0, o_s1, o_part, o_ei, o_ed, o_sp, o_best, o_words, o_boff, o_bcur, o_btsum,
-        o_bsrc, o_bdrec, o_bbits, total;
+        o_bsrc, o_bdrec, o_bbits, o_bcrow, total;
 };
 
 // Spin words of the streamed layout above which the binned kernels run by default: the
@@ -133,7 +133,7 @@ Plan make_plan(const qpa_problem &p, const qpa_params &a, int64_t batch_rp = 0, 
         // binned kernels: int8 / int16 couplings, integer fields, one group of <= 8 lanes
         pl.bin_ok = batch_rp == 0 && cus > 0 && state && pl.is_int &&
                     (p.coupling_dtype == QPA_I8 || p.coupling_dtype == QPA_I16) &&
-                    pl.Rp == pl.Gs && pl.Gs <= 8 && bin_geometry(pl.n, pl.Gs, pl.bg);
+                    pl.Rp == pl.Gs && pl.Gs <= 8 && bin_geometry(pl.n, pl.Gs, 1, pl.bg);
         if (pl.bin_ok && ((a.flags & QPA_SOLVE_BINNED) ||
                           (!(a.flags & QPA_SOLVE_STREAMED) && pl.path == Path::Csr &&
                            8 * pl.nwords > BIN_AUTO_BYTES))) {
@@ -200,6 +200,7 @@ Plan make_plan(const qpa_problem &p, const qpa_params &a, int64_t batch_rp = 0, 
         pl.o_bsrc = take(sizeof(uint32_t) * nnz);
         pl.o_bdrec = take(sizeof(uint32_t) * nnz);
         pl.o_bbits = take(nnz);
+        pl.o_bcrow = take(sizeof(int32_t) * n);
     }
     pl.total = off;
     return pl;
@@ -413,14 +414,26 @@ qpa_status run_graph(qpa_ctx *ctx, std::vector<uint8_t> key, hipStream_t st, F &
     return QPA_OK;
 }
 
+// Geometry of the binned kernels for this call: as many field sums per LDS word as the
+// canonical row bound (sum of |w| plus |b|, read back by canonicalise) allows, hence as few
+// blocks as possible.  Never more blocks than the plan's workspace holds.
+BinGeom bin_run_geometry(const qpa_ctx *ctx, const Plan &pl) {
+    const double bound = ctx->host_sc->max_row;
+    const int lanes = (pl.Gs >= 4 && bound < 256.0) ? 4 : (pl.Gs >= 2 && bound < 65536.0) ? 2 : 1;
+    BinGeom g;
+    if (!bin_geometry(pl.n, pl.Gs, lanes, g)) return pl.bg;
+    return g;
+}
+
 // Entry order of the binned kernels (once per call, before the step loop).
 qpa_status bin_build(qpa_ctx *ctx, const qpa_problem &p, const Plan &pl, void *ws,
                      hipStream_t st) {
     CsrView c{pl.n, p.row_ptr, p.col, p.weights, p.index_dtype, p.coupling_dtype, pl.is_qubo,
               p.nnz};
-    QPA_HIP(launch_bin_build(c, pl.bg, at<int32_t>(ws, pl.o_boff), at<int32_t>(ws, pl.o_bcur),
+    QPA_HIP(launch_bin_build(c, bin_run_geometry(ctx, pl), at<int64_t>(ws, pl.o_bi),
+                             at<int32_t>(ws, pl.o_boff), at<int32_t>(ws, pl.o_bcur),
                              at<int32_t>(ws, pl.o_btsum), at<uint32_t>(ws, pl.o_bsrc),
-                             at<uint32_t>(ws, pl.o_bdrec), st));
+                             at<uint32_t>(ws, pl.o_bdrec), at<int32_t>(ws, pl.o_bcrow), st));
     return QPA_OK;
 }
 
@@ -462,6 +475,9 @@ qpa_status run_steps(qpa_ctx *ctx, const qpa_problem &p, const qpa_params &a, co
         key_add(key, t0);
         key_add(key, t1);
         key_add(key, want_h);
+        // the binned kernels' geometry follows the data (row bound), and the entry order
+        // built eagerly before the replay must match the captured launches
+        key_add(key, pl.path == Path::CsrBinned ? bin_run_geometry(ctx, pl).lanes : 0);
         qpa_status s_ = run_graph(ctx, std::move(key), st, inner);
         launches = t1 - t0;
         return s_;
@@ -534,12 +550,13 @@ qpa_status run_steps_inner(qpa_ctx *ctx, const qpa_problem &p, const qpa_params 
             QPA_HIP(launch_csr_pack_spins(pl.n, pl.Rp, pl.Gs, x, s0, st));
             const int32_t *off = at<int32_t>(ws, pl.o_boff);
             const uint32_t *src = at<uint32_t>(ws, pl.o_bsrc), *drec = at<uint32_t>(ws, pl.o_bdrec);
+            const BinGeom g = bin_run_geometry(ctx, pl);
             launches = 2 * (int64_t)(t1 - t0);
             for (int32_t t = t0; t < t1; ++t) {
-                QPA_HIP(launch_bin_step(pl.bg, pl.n, pl.nwords, off, src, drec,
-                                        at<uint8_t>(ws, pl.o_bbits), bf, s0, s1, x, m,
-                                        (t == t1 - 1) ? h : nullptr, t, lam, a.eta, a.alpha,
-                                        ctx->cus, st));
+                QPA_HIP(launch_bin_step(g, pl.n, pl.nwords, off, src, drec,
+                                        at<uint8_t>(ws, pl.o_bbits), at<int32_t>(ws, pl.o_bcrow),
+                                        s0, s1, x, m, (t == t1 - 1) ? h : nullptr, t, lam, a.eta,
+                                        a.alpha, ctx->cus, st));
                 std::swap(s0, s1);
             }
             break;

@@ -172,23 +172,27 @@ hipError_t launch_csr_step(const CsrView &c, int64_t Rp, int G, const float *b_f
 
 // Binned sparse steps (int8 / int16 couplings, one replica group of G <= 8 lanes, the
 // streamed kernel's state and spin-word layout).  Source chunks of 2^20 / G variables,
-// destination bins of 2^14 / G rows, M = chunks x bins blocks of entries.
+// destination bins of 2^14 L / G rows with L field sums per 32-bit LDS word (L = 1, 2 or
+// 4, L <= G; every row's sum of |w| must stay below 2^(32 / L)), M = chunks x bins blocks
+// of entries.
 constexpr int BIN_MAX_CHUNKS = 2048;
 struct BinGeom {
-    int G = 0, shiftG = 0, cshift = 0, bshift = 0;
+    int G = 0, lanes = 1, shiftG = 0, cshift = 0, bshift = 0;
     int64_t Nc = 0, Nb = 0, M = 0;
 };
 // Fills g; false when the instance has too many chunks or blocks for the kernels.
-bool bin_geometry(int64_t n, int G, BinGeom &g);
+bool bin_geometry(int64_t n, int G, int lanes, BinGeom &g);
 int64_t bin_scan_tiles(const BinGeom &g);
 // Entry order of the binned kernels: off (M + 1 int32: block offsets, off[M] = entries),
-// cur (M int32 scratch), tsum (bin_scan_tiles int32 scratch), src / drec (nnz uint32).
-hipError_t launch_bin_build(const CsrView &c, const BinGeom &g, int32_t *off, int32_t *cur,
-                            int32_t *tsum, uint32_t *src, uint32_t *drec, hipStream_t st);
+// cur (M int32 scratch), tsum (bin_scan_tiles int32 scratch), src / drec (nnz uint32),
+// crow (n int32: sum over the row of |w| plus the canonical integer field b_i64).
+hipError_t launch_bin_build(const CsrView &c, const BinGeom &g, const int64_t *b_i64,
+                            int32_t *off, int32_t *cur, int32_t *tsum, uint32_t *src,
+                            uint32_t *drec, int32_t *crow, hipStream_t st);
 // One PA step: s_cur -> bits (nnz bytes) -> fields, update, s_nxt.
 hipError_t launch_bin_step(const BinGeom &g, int64_t n, int64_t nwords, const int32_t *off,
                            const uint32_t *src, const uint32_t *drec, uint8_t *bits,
-                           const float *b_f32, const uint64_t *s_cur, uint64_t *s_nxt, float *x,
+                           const int32_t *crow, const uint64_t *s_cur, uint64_t *s_nxt, float *x,
                            float *m, float *h_last, int32_t t, const float *lam, float eta,
                            float alpha, int cus, hipStream_t st);
 
