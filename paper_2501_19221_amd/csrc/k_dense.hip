@@ -1,7 +1,8 @@
-// Dense PA steps in FP32 (App. B).  Both kernels accumulate every local field
-// sum_j J_ij s_j in ascending j from zero and then add b_i: with s = +-1 every product is
+// Dense PA steps in FP32 (App. B).  Every kernel accumulates each local field
+// sum_j J_ij s_j in ascending j from zero and then adds b_i: with s = +-1 every product is
 // exact, so the result is the same FP32 sum whatever the tiling, and trajectories are
-// reproducible bit for bit.
+// reproducible bit for bit.  For the same reason a fused multiply-add s_j J_ij + acc,
+// rounded once, equals the separately rounded product and sum, in one instruction.
 //
 // The update after the field is, each operation rounded separately:
 //   g = lambda_t * x + h;  m' = alpha * m - eta * g;  x' = clip(x + m', -1, 1).
@@ -72,7 +73,7 @@ __global__ void __launch_bounds__(RES_THREADS) k_dense_resident(
             const float *Jrow = sJ + iv[q] * n;
             const float *srow = scur + rl[q] * n;
             float acc = 0.0f;
-            for (int j = 0; j < n; ++j) acc = __fadd_rn(acc, __fmul_rn(Jrow[j], srow[j]));
+            for (int j = 0; j < n; ++j) acc = __fmaf_rn(Jrow[j], srow[j], acc);
             float h = __fadd_rn(acc, sb[iv[q]]);
             hr[q] = h;
             pa_update(h, lt, eta, alpha, xr[q], mr[q]);
@@ -187,7 +188,7 @@ __global__ void __launch_bounds__(256) k_dense_tiled_step(
             for (int q = 0; q < 4; ++q)
 #pragma unroll
                 for (int c = 0; c < 4; ++c)
-                    acc[q][c] = __fadd_rn(acc[q][c], __fmul_rn(a[q], bb[c]));
+                    acc[q][c] = __fmaf_rn(a[q], bb[c], acc[q][c]);
         }
         __syncthreads();
     }
