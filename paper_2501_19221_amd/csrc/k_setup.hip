@@ -114,20 +114,80 @@ __global__ void __launch_bounds__(256) k_dense_sym(int64_t n, const TQ *__restri
     if (bad) atomicOr(&sc->flags, (int32_t)FLAG_ASYM);
 }
 
-// Single block: reduce the per-row partials into the scalars.
+// Large instances reduce the per-row partials in two launches: k_canon_part gives each of
+// P workgroups a contiguous range of rows and writes (max |row|, max |J|, sum K as double,
+// sum K as int64) to parts[4 p ..]; k_canon_finalize then reduces those P values (both in
+// a fixed order, so the scalars are reproducible).
+constexpr int64_t CANON_ROWS_PER_PART = 65536;
+
+__global__ void __launch_bounds__(1024) k_canon_part(int64_t n, int64_t rows,
+                                                     const double *row_abs,
+                                                     const double *row_max,
+                                                     const double *row_k, double *parts) {
+    __shared__ double s_abs[1024 / WAVE], s_max[1024 / WAVE], s_k[1024 / WAVE];
+    __shared__ int64_t s_ki[1024 / WAVE];
+    const int64_t i0 = (int64_t)blockIdx.x * rows;
+    const int64_t i1 = i0 + rows < n ? i0 + rows : n;
+    double a = 0.0, mx = 0.0, kf = 0.0;
+    int64_t ki = 0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+        a = fmax(a, row_abs[i]);
+        if (row_max) mx = fmax(mx, row_max[i]);
+        kf += row_k[i];
+        ki += (int64_t)row_k[i];
+    }
+    a = wave_max(a);
+    mx = wave_max(mx);
+    kf = wave_sum(kf);
+    ki = wave_sum_i64(ki);
+    const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    if (lane == 0) {
+        s_abs[w] = a;
+        s_max[w] = mx;
+        s_k[w] = kf;
+        s_ki[w] = ki;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double A = 0.0, M = 0.0, Kf = 0.0;
+        int64_t Ki = 0;
+        for (int k = 0; k < (int)(blockDim.x / WAVE); ++k) {
+            A = fmax(A, s_abs[k]);
+            M = fmax(M, s_max[k]);
+            Kf += s_k[k];
+            Ki += s_ki[k];
+        }
+        double *pp = parts + 4 * blockIdx.x;
+        pp[0] = A;
+        pp[1] = M;
+        pp[2] = Kf;
+        pp[3] = __longlong_as_double(Ki);
+    }
+}
+
+// Single block: reduce the per-row partials (or, with `parts`, the P partials of
+// k_canon_part) into the scalars.
 __global__ void __launch_bounds__(1024) k_canon_finalize(int64_t n, const double *row_abs,
                                                          const double *row_max,
-                                                         const double *row_k, int32_t is_int,
+                                                         const double *row_k,
+                                                         const double *parts, int32_t is_int,
                                                          CanonScalars *sc) {
     __shared__ double s_abs[1024 / WAVE], s_max[1024 / WAVE], s_k[1024 / WAVE];
     __shared__ int64_t s_ki[1024 / WAVE];
     double a = 0.0, mx = 0.0, kf = 0.0;
     int64_t ki = 0;
     for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-        a = fmax(a, row_abs[i]);
-        if (row_max) mx = fmax(mx, row_max[i]);
-        kf += row_k[i];
-        ki += (int64_t)row_k[i];
+        if (parts) {
+            a = fmax(a, parts[4 * i]);
+            mx = fmax(mx, parts[4 * i + 1]);
+            kf += parts[4 * i + 2];
+            ki += __double_as_longlong(parts[4 * i + 3]);
+        } else {
+            a = fmax(a, row_abs[i]);
+            if (row_max) mx = fmax(mx, row_max[i]);
+            kf += row_k[i];
+            ki += (int64_t)row_k[i];
+        }
     }
     a = wave_max(a);
     mx = wave_max(mx);
@@ -694,11 +754,26 @@ template <typename F> hipError_t dispatch_q(int32_t dt, F &&f) {
     }
 }
 
+// One launch for small instances; above CANON_ROWS_PER_PART rows, P <= CANON_PARTS
+// workgroups of rows and a single-workgroup reduction of their partials.
+void canon_reduce(int64_t n, const double *row_abs, const double *row_max, const double *row_k,
+                  double *parts, int32_t is_int, CanonScalars *sc, hipStream_t st) {
+    if (n <= CANON_ROWS_PER_PART || parts == nullptr) {
+        k_canon_finalize<<<1, 1024, 0, st>>>(n, row_abs, row_max, row_k, nullptr, is_int, sc);
+        return;
+    }
+    int64_t P = (n + CANON_ROWS_PER_PART - 1) / CANON_ROWS_PER_PART;
+    if (P > CANON_PARTS) P = CANON_PARTS;
+    const int64_t rows = (n + P - 1) / P;
+    k_canon_part<<<(unsigned)P, 1024, 0, st>>>(n, rows, row_abs, row_max, row_k, parts);
+    k_canon_finalize<<<1, 1024, 0, st>>>(P, nullptr, nullptr, nullptr, parts, is_int, sc);
+}
+
 }  // namespace
 
 hipError_t launch_canon_dense(const qpa_problem &p, float *J_f32, uint16_t *Jb, int64_t npad,
                               float *b_f32, int64_t *b_i64, double *b_f64, double *row_abs,
-                              double *row_max, double *row_k, CanonScalars *sc,
+                              double *row_max, double *row_k, double *parts, CanonScalars *sc,
                               hipStream_t st) {
     const int64_t n = p.n;
     const int32_t is_qubo = p.kind == QPA_KIND_QUBO;
@@ -714,7 +789,7 @@ hipError_t launch_canon_dense(const qpa_problem &p, float *J_f32, uint16_t *Jb, 
             row_max, row_k, sc);
         int64_t nb = (n + 31) / 32;
         k_dense_sym<T><<<dim3((unsigned)nb, (unsigned)nb), 256, 0, st>>>(n, Q, sc);
-        k_canon_finalize<<<1, 1024, 0, st>>>(n, row_abs, row_max, row_k, is_int, sc);
+        canon_reduce(n, row_abs, row_max, row_k, parts, is_int, sc, st);
         if (Jb) k_dense_bf16<T><<<grid1(npad * npad, 256), 256, 0, st>>>(n, npad, Q, sc, Jb);
         return hipGetLastError();
     });
@@ -722,8 +797,8 @@ hipError_t launch_canon_dense(const qpa_problem &p, float *J_f32, uint16_t *Jb, 
 }
 
 hipError_t launch_canon_csr(const qpa_problem &p, float *b_f32, int64_t *b_i64, double *b_f64,
-                            double *row_abs, double *row_max, double *row_k, CanonScalars *sc,
-                            hipStream_t st) {
+                            double *row_abs, double *row_max, double *row_k, double *parts,
+                            CanonScalars *sc, hipStream_t st) {
     const int64_t n = p.n;
     const int32_t is_qubo = p.kind == QPA_KIND_QUBO;
     const int32_t is_int = dtype_is_int(p.coupling_dtype) &&
@@ -743,7 +818,7 @@ hipError_t launch_canon_csr(const qpa_problem &p, float *b_f32, int64_t *b_i64, 
                 n, p.nnz, p.row_ptr, static_cast<const TI *>(p.col),
                 static_cast<const TW *>(p.weights), p.linear, p.linear_dtype, is_qubo, b_f32,
                 b_i64, b_f64, row_abs, row_max, row_k, sc);
-        k_canon_finalize<<<1, 1024, 0, st>>>(n, row_abs, row_max, row_k, is_int, sc);
+        canon_reduce(n, row_abs, row_max, row_k, parts, is_int, sc, st);
         return hipGetLastError();
     };
     return dispatch_q(p.coupling_dtype, [&](auto wtag) {

@@ -88,7 +88,7 @@ struct Plan {
     BinGeom bg;           // their geometry with one sum per word (the most blocks)
     int64_t eblk;         // energy partial blocks
     // workspace offsets (bytes)
-    size_t o_sc, o_lam, o_bf, o_bi, o_bd, o_rabs, o_rmax, o_rk, o_Jf, o_Jb, o_x, o_m, o_h,
+    size_t o_sc, o_cpart, o_lam, o_bf, o_bi, o_bd, o_rabs, o_rmax, o_rk, o_Jf, o_Jb, o_x, o_m, o_h,
         o_s0, o_s1, o_part, o_ei, o_ed, o_sp, o_best, o_words, o_boff, o_bcur, o_btsum,
         o_bsrc, o_bdrec, o_bbits, o_bcrow, total;
 };
@@ -165,6 +165,7 @@ Plan make_plan(const qpa_problem &p, const qpa_params &a, int64_t batch_rp = 0, 
     pl.o_rabs = take(sizeof(double) * n);
     pl.o_rmax = take(sizeof(double) * n);
     pl.o_rk = take(sizeof(double) * n);
+    pl.o_cpart = take(sizeof(double) * 4 * (size_t)CANON_PARTS);
     pl.o_Jf = (pl.path == Path::DenseResident || pl.path == Path::DenseTiled)
                   ? take(sizeof(float) * n * n) : 0;
     pl.o_Jb = pl.path == Path::DenseMfma ? take(sizeof(uint16_t) * np * np) : 0;
@@ -332,11 +333,12 @@ qpa_status canonicalise(qpa_ctx *ctx, const qpa_problem &p, const Plan &pl, void
         uint16_t *Jb = pl.o_Jb ? at<uint16_t>(ws, pl.o_Jb) : nullptr;
         QPA_HIP(launch_canon_dense(p, Jf, Jb, pl.np, bf, at<int64_t>(ws, pl.o_bi),
                                    at<double>(ws, pl.o_bd), at<double>(ws, pl.o_rabs),
-                                   at<double>(ws, pl.o_rmax), at<double>(ws, pl.o_rk), sc, st));
+                                   at<double>(ws, pl.o_rmax), at<double>(ws, pl.o_rk),
+                                   at<double>(ws, pl.o_cpart), sc, st));
     } else {
         QPA_HIP(launch_canon_csr(p, bf, at<int64_t>(ws, pl.o_bi), at<double>(ws, pl.o_bd),
                                  at<double>(ws, pl.o_rabs), at<double>(ws, pl.o_rmax),
-                                 at<double>(ws, pl.o_rk), sc, st));
+                                 at<double>(ws, pl.o_rk), at<double>(ws, pl.o_cpart), sc, st));
     }
     QPA_HIP(hipMemcpyAsync(ctx->host_sc, sc, sizeof(CanonScalars), hipMemcpyDeviceToHost, st));
     QPA_HIP(hipStreamSynchronize(st));
@@ -1187,7 +1189,7 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
         QPA_HIP(launch_canon_csr(problems[k], at<float>(iw, pl.o_bf), at<int64_t>(iw, pl.o_bi),
                                  at<double>(iw, pl.o_bd), at<double>(iw, pl.o_rabs),
                                  at<double>(iw, pl.o_rmax), at<double>(iw, pl.o_rk),
-                                 at<CanonScalars>(iw, pl.o_sc), st));
+                                 at<double>(iw, pl.o_cpart), at<CanonScalars>(iw, pl.o_sc), st));
     }
     CanonScalars *pinned = nullptr;
     QPA_HIP(hipHostMalloc((void **)&pinned, sizeof(CanonScalars) * (size_t)count));

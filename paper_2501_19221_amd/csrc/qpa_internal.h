@@ -49,15 +49,18 @@ inline bool dtype_is_int(int32_t dt) { return dt == QPA_I8 || dt == QPA_I16 || d
 // Canonicalisation of a dense problem: J_f32 (n*n, diagonal zero), b_f32 (n),
 // b_i64 / b_f64 (n), per-row partials, then scalars.  Jb (npad*npad bf16) is filled when
 // non-null with bf16(J / 2^e), zero padded.
+// parts: scratch of 4 * CANON_PARTS doubles for the two-launch reduction of large
+// instances (nullptr: one launch whatever n).
+constexpr int64_t CANON_PARTS = 1024;
 hipError_t launch_canon_dense(const qpa_problem &p, float *J_f32, uint16_t *Jb, int64_t npad,
                               float *b_f32, int64_t *b_i64, double *b_f64, double *row_abs,
-                              double *row_max, double *row_diag, CanonScalars *sc,
-                              hipStream_t st);
+                              double *row_max, double *row_diag, double *parts,
+                              CanonScalars *sc, hipStream_t st);
 
 // Canonicalisation of a CSR problem: b_f32 / b_i64 / b_f64, validation, scalars.
 hipError_t launch_canon_csr(const qpa_problem &p, float *b_f32, int64_t *b_i64, double *b_f64,
-                            double *row_abs, double *row_max, double *row_k, CanonScalars *sc,
-                            hipStream_t st);
+                            double *row_abs, double *row_max, double *row_k, double *parts,
+                            CanonScalars *sc, hipStream_t st);
 
 // x0 / m0 from the counter RNG.  Layout: element (r, i) at x[r * ld_r + i * ld_i].
 hipError_t launch_init_state(int64_t n, int64_t R, uint64_t seed, float sigma0, float *x,
