@@ -308,7 +308,7 @@ def bench_sbm(a, torch, qpa, swl):
     elif dense:
         flops = 2.0 * R * n * n
         roof = {"bound": "alu", "achieved": flops / avg_s / 1e12, "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "kernel": "k_sbm_dense_step",
+                "unit": "TFLOP/s", "kernel": "k_fp32_tiled_step",
                 "per_launch": "2*R*n^2 = %.4g flop (one FMA per coupling, replica; one SBM "
                               "step of every replica)" % flops}
     else:

@@ -143,75 +143,6 @@ __global__ void __launch_bounds__(64) k_dense_wave(int n, const float *__restric
     }
 }
 
-// ---------------------------------------------------------------- tiled, one step
-// Block tile: 64 replicas x 64 variables, 256 threads; thread (ty, tx) owns replicas
-// r0 + 4*ty + q (q < 4) and variables i0 + tx + 16*c (c < 4).  K is walked in chunks of
-// 32 staged through LDS, ascending, with one accumulator per output.
-constexpr int TB = 64, TK = 32;
-
-__global__ void __launch_bounds__(256) k_dense_tiled_step(
-    int64_t n, int64_t R, const float *__restrict__ J, const float *__restrict__ b,
-    const float *__restrict__ s_cur, float *__restrict__ s_nxt, float *__restrict__ x,
-    float *__restrict__ m, float *__restrict__ h_last, int t, const float *__restrict__ lam,
-    float eta, float alpha) {
-    __shared__ float As[TK][TB + 1];   // spins  [k][replica]
-    __shared__ float Bs[TK][TB + 1];   // J      [k][variable]
-    const int tid = threadIdx.x;
-    const int tx = tid % 16, ty = tid / 16;
-    const int64_t r0 = (int64_t)blockIdx.y * TB, i0 = (int64_t)blockIdx.x * TB;
-    float acc[4][4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[q][c] = 0.0f;
-
-    for (int64_t k0 = 0; k0 < n; k0 += TK) {
-        // 64 rows x 32 k for both tiles: 2048 elements, 8 per thread.
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            int idx = tid + e * 256;
-            int row = idx / TK, kk = idx % TK;
-            int64_t k = k0 + kk;
-            int64_t r = r0 + row, i = i0 + row;
-            As[kk][row] = (r < R && k < n) ? s_cur[r * n + k] : 0.0f;
-            Bs[kk][row] = (i < n && k < n) ? J[i * n + k] : 0.0f;
-        }
-        __syncthreads();
-#pragma unroll 8
-        for (int kk = 0; kk < TK; ++kk) {
-            float a[4], bb[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) a[q] = As[kk][4 * ty + q];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) bb[c] = Bs[kk][tx + 16 * c];
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    acc[q][c] = __fmaf_rn(a[q], bb[c], acc[q][c]);
-        }
-        __syncthreads();
-    }
-    const float lt = lam[t];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        int64_t r = r0 + 4 * ty + q;
-        if (r >= R) continue;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            int64_t i = i0 + tx + 16 * c;
-            if (i >= n) continue;
-            int64_t g = r * n + i;
-            float h = __fadd_rn(acc[q][c], b[i]);
-            float xv = x[g], mv = m[g];
-            pa_update(h, lt, eta, alpha, xv, mv);
-            x[g] = xv;
-            m[g] = mv;
-            s_nxt[g] = spin_of(xv);
-            if (h_last) h_last[g] = h;
-        }
-    }
-}
 
 __global__ void __launch_bounds__(256) k_sign_f32(int64_t count, const float *__restrict__ x,
                                                   float *__restrict__ s) {
@@ -257,16 +188,6 @@ hipError_t launch_dense_resident(int64_t n, int64_t R, const float *J, const flo
     const size_t lds = resident_lds_bytes(n);
     k_dense_resident<<<grid, RES_THREADS, lds, st>>>((int)n, (int)R, rb, J, b, x, m, h_last,
                                                      t0, t1, lam, eta, alpha);
-    return hipGetLastError();
-}
-
-hipError_t launch_dense_tiled_step(int64_t n, int64_t R, const float *J, const float *b,
-                                   const float *s_cur, float *s_nxt, float *x, float *m,
-                                   float *h_last, int32_t t, const float *lam, float eta,
-                                   float alpha, hipStream_t st) {
-    dim3 grid((unsigned)((n + TB - 1) / TB), (unsigned)((R + TB - 1) / TB));
-    k_dense_tiled_step<<<grid, 256, 0, st>>>(n, R, J, b, s_cur, s_nxt, x, m, h_last, t, lam, eta,
-                                             alpha);
     return hipGetLastError();
 }
 

@@ -118,16 +118,94 @@ __device__ __forceinline__ void sb_wait4(sb_f4 &a0, sb_f4 &a1, sb_f4 &b0, sb_f4 
     acc[u][6] = __fmaf_rn(av, fb1.z, acc[u][6]);                                         \
     acc[u][7] = __fmaf_rn(av, fb1.w, acc[u][7]);
 
-template <bool VEC>
-__global__ void __launch_bounds__(256) k_sbm_dense_step(int64_t n, int64_t Rp,
-                                                        const float *__restrict__ J,
-                                                        const float *__restrict__ b,
-                                                        const float *__restrict__ c0p, float a,
-                                                        float a0, float dt,
-                                                        const float *__restrict__ qi,
-                                                        float *__restrict__ qo,
-                                                        float *__restrict__ p,
-                                                        float *__restrict__ gout) {
+// SBM epilogue: the symplectic step of every (variable, replica) of the tile.
+struct SbmEpilogue {
+    const float *b, *c0p;
+    float a, a0, dt;
+    const float *qi;
+    float *qo, *p, *gout;
+    // thread holds replicas r0 + 64h + 4ty + e (h, e < 2, 4) and variables
+    // i0 + 64(v/4) + 4tx + v%4
+    __device__ __forceinline__ void operator()(float (&acc)[8][8], int64_t n, int64_t Rp,
+                                               int64_t i0, int64_t r0, int tx, int ty) const {
+        const float c0 = *c0p;
+        const float adt = __fmul_rn(dt, a0);
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const int64_t i = i0 + 64 * (v >> 2) + 4 * tx + (v & 3);
+            if (i >= n) continue;
+            const float bi = b[i];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int64_t idx = i * Rp + r0 + 64 * h + 4 * ty;
+                float4 qv = *reinterpret_cast<const float4 *>(qi + idx);
+                float4 pv = *reinterpret_cast<const float4 *>(p + idx);
+                float4 gv;
+                sbm_point(acc[4 * h + 0][v], bi, a, a0, c0, dt, adt, qv.x, pv.x, gv.x);
+                sbm_point(acc[4 * h + 1][v], bi, a, a0, c0, dt, adt, qv.y, pv.y, gv.y);
+                sbm_point(acc[4 * h + 2][v], bi, a, a0, c0, dt, adt, qv.z, pv.z, gv.z);
+                sbm_point(acc[4 * h + 3][v], bi, a, a0, c0, dt, adt, qv.w, pv.w, gv.w);
+                *reinterpret_cast<float4 *>(qo + idx) = qv;
+                *reinterpret_cast<float4 *>(p + idx) = pv;
+                if (gout) *reinterpret_cast<float4 *>(gout + idx) = gv;
+            }
+        }
+    }
+};
+
+__device__ __forceinline__ void pa_point(float acc, float bi, float lt, float eta, float alpha,
+                                         float &x, float &m, float &s, float &h) {
+    h = __fadd_rn(acc, bi);
+    const float g = __fadd_rn(__fmul_rn(lt, x), h);
+    const float mn = __fsub_rn(__fmul_rn(alpha, m), __fmul_rn(eta, g));
+    x = fminf(1.0f, fmaxf(-1.0f, __fadd_rn(x, mn)));
+    m = mn;
+    s = x >= 0.0f ? 1.0f : -1.0f;
+}
+
+// PA epilogue (App. B): h = J s + b, the momentum update and clipping, and the next
+// step's spins s' = sign(x') as +-1 floats.  With s = +-1 every product of the tiled sum
+// is exact and a fused multiply-add rounds once, so the field equals the ascending sum.
+struct PaEpilogue {
+    const float *b, *lam;
+    int t;
+    float eta, alpha;
+    float *x, *m, *s_nxt, *h_last;
+    __device__ __forceinline__ void operator()(float (&acc)[8][8], int64_t n, int64_t Rp,
+                                               int64_t i0, int64_t r0, int tx, int ty) const {
+        const float lt = lam[t];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const int64_t i = i0 + 64 * (v >> 2) + 4 * tx + (v & 3);
+            if (i >= n) continue;
+            const float bi = b[i];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int64_t idx = i * Rp + r0 + 64 * h + 4 * ty;
+                float4 xv = *reinterpret_cast<const float4 *>(x + idx);
+                float4 mv = *reinterpret_cast<const float4 *>(m + idx);
+                float4 sv, hv;
+                pa_point(acc[4 * h + 0][v], bi, lt, eta, alpha, xv.x, mv.x, sv.x, hv.x);
+                pa_point(acc[4 * h + 1][v], bi, lt, eta, alpha, xv.y, mv.y, sv.y, hv.y);
+                pa_point(acc[4 * h + 2][v], bi, lt, eta, alpha, xv.z, mv.z, sv.z, hv.z);
+                pa_point(acc[4 * h + 3][v], bi, lt, eta, alpha, xv.w, mv.w, sv.w, hv.w);
+                *reinterpret_cast<float4 *>(x + idx) = xv;
+                *reinterpret_cast<float4 *>(m + idx) = mv;
+                *reinterpret_cast<float4 *>(s_nxt + idx) = sv;
+                if (h_last) *reinterpret_cast<float4 *>(h_last + idx) = hv;
+            }
+        }
+    }
+};
+
+// FP32 tiled product G = J Q ([n][n] x [n][Rp], both read row by row: J is symmetric, so
+// its row k is column k) with a per-step epilogue: the SBM step (Q = positions) or the PA
+// step (Q = spins as +-1 floats).
+template <bool VEC, class Epi>
+__global__ void __launch_bounds__(256) k_fp32_tiled_step(int64_t n, int64_t Rp,
+                                                         const float *__restrict__ J,
+                                                         const float *__restrict__ qi,
+                                                         const Epi epi) {
     __shared__ float4 As[2][SB_KC + 1][SB_BR / 4];
     __shared__ float4 Bs[2][SB_KC + 1][SB_BI / 4];
     const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
@@ -215,30 +293,7 @@ __global__ void __launch_bounds__(256) k_sbm_dense_step(int64_t n, int64_t Rp,
     }
 #undef SB_FETCH
 #undef SB_STASH
-    // epilogue: thread holds replicas r0 + 64h + 4ty + e (h, e < 2, 4) and variables
-    // i0 + 64(v/4) + 4tx + v%4
-    const float c0 = *c0p;
-    const float adt = __fmul_rn(dt, a0);
-#pragma unroll
-    for (int v = 0; v < 8; ++v) {
-        const int64_t i = i0 + 64 * (v >> 2) + 4 * tx + (v & 3);
-        if (i >= n) continue;
-        const float bi = b[i];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int64_t idx = i * Rp + r0 + 64 * h + 4 * ty;
-            float4 qv = *reinterpret_cast<const float4 *>(qi + idx);
-            float4 pv = *reinterpret_cast<const float4 *>(p + idx);
-            float4 gv;
-            sbm_point(acc[4 * h + 0][v], bi, a, a0, c0, dt, adt, qv.x, pv.x, gv.x);
-            sbm_point(acc[4 * h + 1][v], bi, a, a0, c0, dt, adt, qv.y, pv.y, gv.y);
-            sbm_point(acc[4 * h + 2][v], bi, a, a0, c0, dt, adt, qv.z, pv.z, gv.z);
-            sbm_point(acc[4 * h + 3][v], bi, a, a0, c0, dt, adt, qv.w, pv.w, gv.w);
-            *reinterpret_cast<float4 *>(qo + idx) = qv;
-            *reinterpret_cast<float4 *>(p + idx) = pv;
-            if (gout) *reinterpret_cast<float4 *>(gout + idx) = gv;
-        }
-    }
+    epi(acc, n, Rp, i0, r0, tx, ty);
 }
 #undef SB_FMA_ROW
 
@@ -619,6 +674,22 @@ int64_t sbm_rpad(const qpa_problem &p, int64_t R) {
     return (R + G - 1) / G * G;
 }
 
+int64_t dense_fp32_rpad(int64_t R) { return (R + SB_BR - 1) / SB_BR * SB_BR; }
+
+hipError_t launch_dense_fp32_step(int64_t n, int64_t Rp, const float *J, const float *b,
+                                  const float *s_cur, float *s_nxt, float *x, float *m,
+                                  float *h_last, int32_t t, const float *lam, float eta,
+                                  float alpha, hipStream_t st) {
+    if (Rp % SB_BR || n < 1) return hipErrorInvalidValue;
+    dim3 grid((unsigned)((n + SB_BI - 1) / SB_BI), (unsigned)(Rp / SB_BR));
+    const PaEpilogue epi{b, lam, t, eta, alpha, x, m, s_nxt, h_last};
+    if (n % 4 == 0)
+        k_fp32_tiled_step<true, PaEpilogue><<<grid, 256, 0, st>>>(n, Rp, J, s_cur, epi);
+    else
+        k_fp32_tiled_step<false, PaEpilogue><<<grid, 256, 0, st>>>(n, Rp, J, s_cur, epi);
+    return hipGetLastError();
+}
+
 int64_t pw_blocks(const qpa_problem &p) {
     const int64_t a = (p.n + 255) / 256;
     const int64_t d = p.format == QPA_FMT_DENSE ? (p.n + 3) / 4 : a;
@@ -631,12 +702,11 @@ hipError_t launch_sbm_step(const qpa_problem &p, const float *Jf, int64_t Rp, co
     const int64_t n = p.n;
     if (p.format == QPA_FMT_DENSE) {
         dim3 grid((unsigned)((n + SB_BI - 1) / SB_BI), (unsigned)(Rp / SB_BR));
+        const SbmEpilogue epi{b, c0p, a, a0, dt, q_in, q_out, pm, g_out};
         if (n % 4 == 0)
-            k_sbm_dense_step<true><<<grid, 256, 0, st>>>(n, Rp, Jf, b, c0p, a, a0, dt, q_in,
-                                                         q_out, pm, g_out);
+            k_fp32_tiled_step<true, SbmEpilogue><<<grid, 256, 0, st>>>(n, Rp, Jf, q_in, epi);
         else
-            k_sbm_dense_step<false><<<grid, 256, 0, st>>>(n, Rp, Jf, b, c0p, a, a0, dt, q_in,
-                                                          q_out, pm, g_out);
+            k_fp32_tiled_step<false, SbmEpilogue><<<grid, 256, 0, st>>>(n, Rp, Jf, q_in, epi);
         return hipGetLastError();
     }
     const int G = sbm_csr_group(Rp);

@@ -148,6 +148,7 @@ Plan make_plan(const qpa_problem &p, const qpa_params &a, int64_t batch_rp = 0, 
         pl.path = Path::DenseResident;
     } else {
         pl.path = Path::DenseTiled;
+        pl.Rp = dense_fp32_rpad(pl.R);
     }
     pl.eblk = energy_partial_blocks(p);
     size_t off = 0;
@@ -175,7 +176,7 @@ Plan make_plan(const qpa_problem &p, const qpa_params &a, int64_t batch_rp = 0, 
     size_t sbytes = 0;
     switch (pl.path) {
         case Path::DenseResident: sbytes = 0; break;
-        case Path::DenseTiled: sbytes = sizeof(float) * R * n; break;
+        case Path::DenseTiled: sbytes = sizeof(float) * Rp * n; break;
         case Path::DenseMfma: sbytes = sizeof(uint32_t) * Rp * (np / 8); break;
         case Path::Csr:
         case Path::CsrResident:
@@ -209,7 +210,8 @@ Plan make_plan(const qpa_problem &p, const qpa_params &a, int64_t batch_rp = 0, 
 
 // Strides of element (r, i) in the internal state layout of a plan.
 void state_strides(const Plan &pl, int64_t &ld_r, int64_t &ld_i) {
-    if (pl.path == Path::Csr || pl.path == Path::CsrResident || pl.path == Path::CsrBinned) {
+    if (pl.path == Path::Csr || pl.path == Path::CsrResident || pl.path == Path::CsrBinned ||
+        pl.path == Path::DenseTiled) {
         ld_r = 1;
         ld_i = pl.Rp;
     } else {
@@ -512,12 +514,12 @@ qpa_status run_steps_inner(qpa_ctx *ctx, const qpa_problem &p, const qpa_params 
             break;
         case Path::DenseTiled: {
             float *s0 = at<float>(ws, pl.o_s0), *s1 = at<float>(ws, pl.o_s1);
-            QPA_HIP(launch_sign_f32(pl.R * pl.n, x, s0, st));
+            QPA_HIP(launch_sign_f32(pl.Rp * pl.n, x, s0, st));
             launches = t1 - t0;
             for (int32_t t = t0; t < t1; ++t) {
-                QPA_HIP(launch_dense_tiled_step(pl.n, pl.R, at<float>(ws, pl.o_Jf), bf, s0, s1,
-                                                x, m, (t == t1 - 1) ? h : nullptr, t, lam,
-                                                a.eta, a.alpha, st));
+                QPA_HIP(launch_dense_fp32_step(pl.n, pl.Rp, at<float>(ws, pl.o_Jf), bf, s0, s1,
+                                               x, m, (t == t1 - 1) ? h : nullptr, t, lam,
+                                               a.eta, a.alpha, st));
                 std::swap(s0, s1);
             }
             break;

@@ -99,12 +99,15 @@ hipError_t launch_dense_resident(int64_t n, int64_t R, const float *J, const flo
                                  float *x, float *m, float *h_last, int32_t t0, int32_t t1,
                                  const float *lam, float eta, float alpha, hipStream_t st);
 
-// Any size: one launch per step, FP32 sequential sums (same order as the definition).
-// s_cur / s_nxt: float +-1 [R][n]; x, m, h_last: [R][n].
-hipError_t launch_dense_tiled_step(int64_t n, int64_t R, const float *J, const float *b,
-                                   const float *s_cur, float *s_nxt, float *x, float *m,
-                                   float *h_last, int32_t t, const float *lam, float eta,
-                                   float alpha, hipStream_t st);
+// Any size: one launch per step of the FP32 tiled product shared with the SBM step (128 x
+// 128 tiles, 8 x 8 sums per thread, pipelined LDS reads), fused multiply-adds in ascending
+// order (exact products with s = +-1, so the same sums as the definition).  Layout
+// [n][Rp], Rp = dense_fp32_rpad(R): s_cur / s_nxt float +-1, x, m, h_last.
+int64_t dense_fp32_rpad(int64_t R);
+hipError_t launch_dense_fp32_step(int64_t n, int64_t Rp, const float *J, const float *b,
+                                  const float *s_cur, float *s_nxt, float *x, float *m,
+                                  float *h_last, int32_t t, const float *lam, float eta,
+                                  float alpha, hipStream_t st);
 hipError_t launch_sign_f32(int64_t count, const float *x, float *s, hipStream_t st);
 
 // BF16 matrix-core path.  Internal padded layout: x, m [Rp][np] FP32, Jb [np][np] bf16,
