@@ -435,13 +435,14 @@ __global__ void __launch_bounds__(SRT) k_sbm_csr_resident(
             }
         }
     }
+    if (tid < G) qv[n * G + tid] = 0.0f;       // row n: the +0.0 of unused cache slots
     const float c0 = *c0p;
     const float adt = __fmul_rn(dt, a0);
     __syncthreads();
-    // the first CACHE off-diagonal entries of each owned row in registers, unused slots
-    // with weight 0: a multiply-add chain that starts at +0.0 never reaches -0.0 under
-    // round-to-nearest, so adding a zero product changes no bit; the step then issues the
-    // position reads of the cached entries together
+    // the first CACHE off-diagonal entries of each owned row in registers; the step issues
+    // their position reads together.  Unused slots carry weight -0.0 and read row n of the
+    // positions, which holds +0.0: the product is exactly -0.0, and adding -0.0 leaves
+    // every value unchanged (also -0.0, which a product w q that underflows can leave)
     // at most 32 cached positions and, with 8 variables per thread, one entry per row
     constexpr int CA = VPT >= 8 ? 1 : (16 / VPT) < 8 ? (16 / VPT) : 8;
     constexpr int CACHE = CA * G > 32 ? 32 / G : CA;
@@ -457,8 +458,8 @@ __global__ void __launch_bounds__(SRT) k_sbm_csr_resident(
         }
 #pragma unroll
         for (int c = 0; c < CACHE; ++c) {
-            cj[u][c] = 0;
-            cw[u][c] = 0.0f;
+            cj[u][c] = n;
+            cw[u][c] = -0.0f;
         }
         for (; k < k1 && cnt < CACHE; ++k) {
             const int32_t j = col[k];
@@ -724,7 +725,9 @@ hipError_t launch_sbm_step(const qpa_problem &p, const float *Jf, int64_t Rp, co
 }
 
 size_t sbm_resident_lds(int64_t n, int64_t nnz, int G) {
-    return (((size_t)(n + 1) * 4 + (size_t)nnz * 6 + 15) & ~(size_t)15) + (size_t)n * G * 4;
+    // positions of rows 0 .. n (row n: zeros for unused cache slots)
+    return (((size_t)(n + 1) * 4 + (size_t)nnz * 6 + 15) & ~(size_t)15) +
+           (size_t)(n + 1) * G * 4;
 }
 
 static int sbm_vpt(int64_t n) {
