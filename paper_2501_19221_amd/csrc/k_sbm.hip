@@ -53,7 +53,9 @@ __device__ __forceinline__ void sbm_point(float f, float bi, float a, float a0, 
 __device__ __forceinline__ float4 sb_load_q(const float *__restrict__ qi, int64_t k, int64_t n,
                                            int64_t Rp, int64_t col) {
     if (k < n) return *reinterpret_cast<const float4 *>(qi + k * Rp + col);
-    return make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    // past the last row: -0.0 times the padding's zero couplings is exactly -0.0, which
+    // leaves every sum unchanged (also a -0.0 left by an underflowing product)
+    return make_float4(-0.0f, -0.0f, -0.0f, -0.0f);
 }
 
 // VEC: n % 4 == 0, so rows of J can be read as float4.
