@@ -41,6 +41,10 @@ struct qpa_ctx {
     // sparse kernel choices found by qpa_autotune: shape key -> 0 (streamed kernel) or
     // the resident kernel's replica group
     std::vector<std::pair<std::vector<uint8_t>, int32_t>> tuned;
+    // streams of default priority for the independent per-instance work of a batch, and
+    // the events that order them after and join them back into the caller's stream
+    std::vector<hipStream_t> aux;
+    std::vector<hipEvent_t> aux_ev;         // [0]: fork, [1 + i]: join of aux[i]
 };
 
 namespace qpa {
@@ -936,6 +940,8 @@ void qpa_destroy(qpa_ctx *ctx) {
         (void)hipEventDestroy(sp.b);
     }
     for (auto ev : ctx->free_events) (void)hipEventDestroy(ev);
+    for (auto a : ctx->aux) (void)hipStreamDestroy(a);
+    for (auto ev : ctx->aux_ev) (void)hipEventDestroy(ev);
     delete ctx;
 }
 
@@ -1155,6 +1161,56 @@ qpa_status qpa_workspace_size_batch(qpa_ctx *ctx, int32_t count, const qpa_probl
     return QPA_OK;
 }
 
+namespace {
+constexpr int AUX_STREAMS = 4;
+
+// Work enqueued on ctx->aux after this starts after everything already on `st`.
+qpa_status aux_fork(qpa_ctx *ctx, hipStream_t st) {
+    if (ctx->aux.empty()) {
+        for (int i = 0; i < AUX_STREAMS; ++i) {
+            hipStream_t a = nullptr;
+            QPA_HIP(hipStreamCreateWithFlags(&a, hipStreamNonBlocking));
+            ctx->aux.push_back(a);
+        }
+        for (int i = 0; i <= AUX_STREAMS; ++i) {
+            hipEvent_t ev = nullptr;
+            QPA_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+            ctx->aux_ev.push_back(ev);
+        }
+    }
+    QPA_HIP(hipEventRecord(ctx->aux_ev[0], st));
+    for (auto a : ctx->aux) QPA_HIP(hipStreamWaitEvent(a, ctx->aux_ev[0], 0));
+    return QPA_OK;
+}
+
+// Work enqueued on `st` after this starts after everything enqueued on ctx->aux.
+qpa_status aux_join(qpa_ctx *ctx, hipStream_t st) {
+    for (size_t i = 0; i < ctx->aux.size(); ++i) {
+        QPA_HIP(hipEventRecord(ctx->aux_ev[1 + i], ctx->aux[i]));
+        QPA_HIP(hipStreamWaitEvent(st, ctx->aux_ev[1 + i], 0));
+    }
+    return QPA_OK;
+}
+
+// Joins the auxiliary streams into `st` when a forked section is left early (an error
+// return), so that nothing the caller orders after the call can overtake their work.
+struct AuxGuard {
+    qpa_ctx *ctx;
+    hipStream_t st;
+    bool open = true;
+    ~AuxGuard() {
+        if (!open) return;
+        const std::string keep = ctx->err;     // the join must not replace the message
+        (void)aux_join(ctx, st);
+        ctx->err = keep;
+    }
+    qpa_status close() {
+        open = false;
+        return aux_join(ctx, st);
+    }
+};
+}  // namespace
+
 qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *problems,
                            const qpa_params *params, void *workspace, size_t workspace_bytes,
                            void *stream, const qpa_outputs *out) {
@@ -1183,28 +1239,40 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
     s = upload_schedule(ctx, *params, reinterpret_cast<float *>(ws + bp.o_lam), st);
     if (s != QPA_OK) return s;
 
-    // canonicalise + validate every instance, then one read-back of all the flags
+    // canonicalise + validate every instance (instances spread over the context's
+    // auxiliary streams: their launches are small and independent), then one read-back of
+    // all the flags
     std::vector<CanonScalars> hsc(count);
-    for (int32_t k = 0; k < count; ++k) {
-        const Plan &pl = bp.inst[k];
-        void *iw = ws + bp.base[k];
-        QPA_HIP(launch_canon_csr(problems[k], at<float>(iw, pl.o_bf), at<int64_t>(iw, pl.o_bi),
-                                 at<double>(iw, pl.o_bd), at<double>(iw, pl.o_rabs),
-                                 at<double>(iw, pl.o_rmax), at<double>(iw, pl.o_rk),
-                                 at<double>(iw, pl.o_cpart), at<CanonScalars>(iw, pl.o_sc), st));
-    }
     CanonScalars *pinned = nullptr;
     QPA_HIP(hipHostMalloc((void **)&pinned, sizeof(CanonScalars) * (size_t)count));
-    for (int32_t k = 0; k < count; ++k) {
-        void *iw = ws + bp.base[k];
-        hipError_t e = hipMemcpyAsync(&pinned[k], at<CanonScalars>(iw, bp.inst[k].o_sc),
-                                      sizeof(CanonScalars), hipMemcpyDeviceToHost, st);
-        if (e != hipSuccess) {
-            (void)hipHostFree(pinned);
-            return fail(ctx, QPA_E_DEVICE, "flag read-back failed: %s", hipGetErrorString(e));
-        }
+    s = aux_fork(ctx, st);
+    if (s != QPA_OK) {
+        (void)hipHostFree(pinned);
+        return s;
     }
+    AuxGuard g0{ctx, st};
+    for (int32_t k = 0; k < count && s == QPA_OK; ++k) {
+        const Plan &pl = bp.inst[k];
+        void *iw = ws + bp.base[k];
+        hipStream_t ak = ctx->aux[(size_t)k % ctx->aux.size()];
+        hipError_t e = launch_canon_csr(problems[k], at<float>(iw, pl.o_bf),
+                                        at<int64_t>(iw, pl.o_bi), at<double>(iw, pl.o_bd),
+                                        at<double>(iw, pl.o_rabs), at<double>(iw, pl.o_rmax),
+                                        at<double>(iw, pl.o_rk), at<double>(iw, pl.o_cpart),
+                                        at<CanonScalars>(iw, pl.o_sc), ak);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&pinned[k], at<CanonScalars>(iw, pl.o_sc), sizeof(CanonScalars),
+                               hipMemcpyDeviceToHost, ak);
+        if (e != hipSuccess)
+            s = fail(ctx, QPA_E_DEVICE, "canonicalisation: %s", hipGetErrorString(e));
+    }
+    const qpa_status sj = g0.close();
+    if (s == QPA_OK) s = sj;
     hipError_t se = hipStreamSynchronize(st);
+    if (s != QPA_OK) {
+        (void)hipHostFree(pinned);
+        return s;
+    }
     for (int32_t k = 0; k < count; ++k) hsc[k] = pinned[k];
     (void)hipHostFree(pinned);
     if (se != hipSuccess)
@@ -1224,9 +1292,13 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
     const int64_t R = params->replicas;
     std::vector<char> is_dense(count, 0);
     std::vector<MfmaTile> tiles, tiles8;
+    s = aux_fork(ctx, st);
+    if (s != QPA_OK) return s;
+    AuxGuard g1{ctx, st};
     for (int32_t k = 0; k < count; ++k) {
         const DenseSlot &ds = bp.dense[k];
         if (!ds.cand) continue;
+        hipStream_t ak = ctx->aux[(size_t)k % ctx->aux.size()];
         if (bp.inst[k].is_int && hsc[k].max_abs > 256.0) continue;
         const bool i8 = bp.inst[k].is_int && hsc[k].max_abs <= 127.0 &&
                         problems[k].coupling_dtype != QPA_F32;
@@ -1242,19 +1314,19 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
         uint32_t *s1 = reinterpret_cast<uint32_t *>(ws + ds.o_s1);
         const CanonScalars *sc = at<CanonScalars>(iw, pl.o_sc);
         if (i8)
-            QPA_HIP(launch_csr_to_i8(p, ds.np, reinterpret_cast<int8_t *>(Jb), st));
+            QPA_HIP(launch_csr_to_i8(p, ds.np, reinterpret_cast<int8_t *>(Jb), ak));
         else
-            QPA_HIP(launch_csr_to_bf16(p, ds.np, sc, Jb, st));
-        QPA_HIP(hipMemsetAsync(bfp, 0, sizeof(float) * (size_t)ds.np, st));
+            QPA_HIP(launch_csr_to_bf16(p, ds.np, sc, Jb, ak));
+        QPA_HIP(hipMemsetAsync(bfp, 0, sizeof(float) * (size_t)ds.np, ak));
         QPA_HIP(hipMemcpyAsync(bfp, at<float>(iw, pl.o_bf), sizeof(float) * (size_t)p.n,
-                               hipMemcpyDeviceToDevice, st));
+                               hipMemcpyDeviceToDevice, ak));
         QPA_HIP(launch_init_state(p.n, R, params->seed + (uint64_t)k, params->sigma0, dx, dm,
-                                  ds.np, 1, ds.Rp, ds.np, st));
+                                  ds.np, 1, ds.Rp, ds.np, ak));
         if (i8)
             QPA_HIP(launch_mfma_pack_spins_i8(ds.Rp, ds.np, dx, reinterpret_cast<uint8_t *>(s0),
-                                              st));
+                                              ak));
         else
-            QPA_HIP(launch_mfma_pack_spins(ds.Rp, ds.np, dx, s0, st));
+            QPA_HIP(launch_mfma_pack_spins(ds.Rp, ds.np, dx, s0, ak));
         for (int64_t rb = 0; rb < ds.Rp / MF_BM; ++rb)
             for (int64_t ib = 0; ib < ds.np / MF_BN; ++ib) {
                 MfmaTile tl{};
@@ -1273,6 +1345,8 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
                 (i8 ? tiles8 : tiles).push_back(tl);
             }
     }
+    s = g1.close();
+    if (s != QPA_OK) return s;
     // largest instances first so that the tail of each step is made of small tiles; the
     // int8 tiles follow the BF16 ones in the uploaded table
     auto by_size = [](const MfmaTile &a, const MfmaTile &b) { return a.np > b.np; };
@@ -1375,8 +1449,13 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
         }
     }
 
-    // per instance: spins, optional state, exact energies, best replica
+    // per instance: spins, optional state, exact energies, best replica (instances spread
+    // over the auxiliary streams, joined back into the caller's stream at the end)
+    s = aux_fork(ctx, st);
+    if (s != QPA_OK) return s;
+    AuxGuard g2{ctx, st};
     for (int32_t k = 0; k < count; ++k) {
+        hipStream_t ak = ctx->aux[(size_t)k % ctx->aux.size()];
         const Plan &pl = bp.inst[k];
         char *iw = ws + bp.base[k];
         const qpa_problem &p = problems[k];
@@ -1386,24 +1465,26 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
             const DenseSlot &ds = bp.dense[k];
             const float *dx = reinterpret_cast<const float *>(ws + ds.o_x);
             const float *dm = reinterpret_cast<const float *>(ws + ds.o_m);
-            QPA_HIP(launch_export_spins(p.n, R, dx, ds.np, 1, spins, st));
-            if (o.x) QPA_HIP(launch_copy_state(p.n, R, dx, ds.np, 1, o.x, p.n, 1, st));
-            if (o.m) QPA_HIP(launch_copy_state(p.n, R, dm, ds.np, 1, o.m, p.n, 1, st));
+            QPA_HIP(launch_export_spins(p.n, R, dx, ds.np, 1, spins, ak));
+            if (o.x) QPA_HIP(launch_copy_state(p.n, R, dx, ds.np, 1, o.x, p.n, 1, ak));
+            if (o.m) QPA_HIP(launch_copy_state(p.n, R, dm, ds.np, 1, o.m, p.n, 1, ak));
         }
         for (int64_t g = 0; !is_dense[k] && g < pl.Rp / 64; ++g) {
             const int64_t rg = std::min<int64_t>(64, R - 64 * g);
             const float *xg = at<float>(iw, pl.o_x) + g * p.n * 64;
             const float *mg = at<float>(iw, pl.o_m) + g * p.n * 64;
-            QPA_HIP(launch_export_spins(p.n, rg, xg, 1, 64, spins + g * 64 * p.n, st));
-            if (o.x) QPA_HIP(launch_copy_state(p.n, rg, xg, 1, 64, o.x + g * 64 * p.n, p.n, 1, st));
-            if (o.m) QPA_HIP(launch_copy_state(p.n, rg, mg, 1, 64, o.m + g * 64 * p.n, p.n, 1, st));
+            QPA_HIP(launch_export_spins(p.n, rg, xg, 1, 64, spins + g * 64 * p.n, ak));
+            if (o.x) QPA_HIP(launch_copy_state(p.n, rg, xg, 1, 64, o.x + g * 64 * p.n, p.n, 1, ak));
+            if (o.m) QPA_HIP(launch_copy_state(p.n, rg, mg, 1, 64, o.m + g * 64 * p.n, p.n, 1, ak));
         }
-        s = score(ctx, p, pl, iw, spins, o.energy, o.energy_i64, o.best, st);
+        s = score(ctx, p, pl, iw, spins, o.energy, o.energy_i64, o.best, ak);
         if (s != QPA_OK) {
             std::string msg = "instance " + std::to_string(k) + ": " + ctx->err;
             return fail(ctx, s, "%s", msg.c_str());
         }
     }
+    s = g2.close();
+    if (s != QPA_OK) return s;
     ctx->batch_paths.assign(count, QPA_PATH_BATCH_SPARSE);
     for (int32_t k = 0; k < count; ++k)
         if (is_dense[k])
