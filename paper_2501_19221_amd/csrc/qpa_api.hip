@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <string>
+#include <thread>
 #include <vector>
 
 struct qpa_ctx {
@@ -1209,6 +1210,47 @@ struct AuxGuard {
         return aux_join(ctx, st);
     }
 };
+
+// Issues body(k, stream) for instances 0 .. count-1 between aux_fork and aux_join:
+// instance k goes to auxiliary stream k mod (number of streams), and each stream's
+// instances are issued in order from a host thread of its own (the calling thread takes
+// the first stream), since the host-side cost of the many small launches, not the GPU,
+// bounds these sections.  body returns the first HIP error of its instance; a failing
+// thread stops issuing, and the error of the lowest failing instance is reported.  body
+// touches no shared state of the context.
+extern "C++" {
+template <class F>
+qpa_status aux_issue(qpa_ctx *ctx, int32_t count, const char *what, F &&body) {
+    const int32_t A = std::max<int32_t>(1, std::min<int32_t>((int32_t)ctx->aux.size(), count));
+    std::vector<int32_t> bad_k(A, INT32_MAX);
+    std::vector<hipError_t> bad_e(A, hipSuccess);
+    auto share = [&](int32_t a) {
+        hipError_t e = a == 0 ? hipSuccess : hipSetDevice(ctx->device);
+        for (int32_t k = a; k < count && e == hipSuccess; k += A) {
+            e = body(k, ctx->aux[a]);
+            if (e != hipSuccess) bad_k[a] = k;
+        }
+        if (e != hipSuccess && bad_k[a] == INT32_MAX) bad_k[a] = a;
+        bad_e[a] = e;
+    };
+    std::vector<std::thread> th;
+    int32_t started = 1;
+    try {
+        for (; started < A; ++started) th.emplace_back(share, started);
+    } catch (...) {
+        // no thread for the remaining shares: the calling thread issues them
+    }
+    share(0);
+    for (int32_t a = started; a < A; ++a) share(a);
+    for (auto &t : th) t.join();
+    int32_t worst = -1;
+    for (int32_t a = 0; a < A; ++a)
+        if (bad_e[a] != hipSuccess && (worst < 0 || bad_k[a] < bad_k[worst])) worst = a;
+    if (worst < 0) return QPA_OK;
+    return fail(ctx, QPA_E_DEVICE, "instance %d: %s: %s", bad_k[worst], what,
+                hipGetErrorString(bad_e[worst]));
+}
+}  // extern "C++"
 }  // namespace
 
 qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *problems,
@@ -1251,10 +1293,9 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
         return s;
     }
     AuxGuard g0{ctx, st};
-    for (int32_t k = 0; k < count && s == QPA_OK; ++k) {
+    s = aux_issue(ctx, count, "canonicalisation", [&](int32_t k, hipStream_t ak) {
         const Plan &pl = bp.inst[k];
         void *iw = ws + bp.base[k];
-        hipStream_t ak = ctx->aux[(size_t)k % ctx->aux.size()];
         hipError_t e = launch_canon_csr(problems[k], at<float>(iw, pl.o_bf),
                                         at<int64_t>(iw, pl.o_bi), at<double>(iw, pl.o_bd),
                                         at<double>(iw, pl.o_rabs), at<double>(iw, pl.o_rmax),
@@ -1263,9 +1304,8 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
         if (e == hipSuccess)
             e = hipMemcpyAsync(&pinned[k], at<CanonScalars>(iw, pl.o_sc), sizeof(CanonScalars),
                                hipMemcpyDeviceToHost, ak);
-        if (e != hipSuccess)
-            s = fail(ctx, QPA_E_DEVICE, "canonicalisation: %s", hipGetErrorString(e));
-    }
+        return e;
+    });
     const qpa_status sj = g0.close();
     if (s == QPA_OK) s = sj;
     hipError_t se = hipStreamSynchronize(st);
@@ -1292,14 +1332,14 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
     const int64_t R = params->replicas;
     std::vector<char> is_dense(count, 0);
     std::vector<MfmaTile> tiles, tiles8;
+    std::vector<std::vector<MfmaTile>> itiles(count);
     s = aux_fork(ctx, st);
     if (s != QPA_OK) return s;
     AuxGuard g1{ctx, st};
-    for (int32_t k = 0; k < count; ++k) {
+    s = aux_issue(ctx, count, "tile set-up", [&](int32_t k, hipStream_t ak) -> hipError_t {
         const DenseSlot &ds = bp.dense[k];
-        if (!ds.cand) continue;
-        hipStream_t ak = ctx->aux[(size_t)k % ctx->aux.size()];
-        if (bp.inst[k].is_int && hsc[k].max_abs > 256.0) continue;
+        if (!ds.cand) return hipSuccess;
+        if (bp.inst[k].is_int && hsc[k].max_abs > 256.0) return hipSuccess;
         const bool i8 = bp.inst[k].is_int && hsc[k].max_abs <= 127.0 &&
                         problems[k].coupling_dtype != QPA_F32;
         is_dense[k] = i8 ? 2 : 1;
@@ -1313,20 +1353,22 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
         uint32_t *s0 = reinterpret_cast<uint32_t *>(ws + ds.o_s0);
         uint32_t *s1 = reinterpret_cast<uint32_t *>(ws + ds.o_s1);
         const CanonScalars *sc = at<CanonScalars>(iw, pl.o_sc);
-        if (i8)
-            QPA_HIP(launch_csr_to_i8(p, ds.np, reinterpret_cast<int8_t *>(Jb), ak));
-        else
-            QPA_HIP(launch_csr_to_bf16(p, ds.np, sc, Jb, ak));
-        QPA_HIP(hipMemsetAsync(bfp, 0, sizeof(float) * (size_t)ds.np, ak));
-        QPA_HIP(hipMemcpyAsync(bfp, at<float>(iw, pl.o_bf), sizeof(float) * (size_t)p.n,
-                               hipMemcpyDeviceToDevice, ak));
-        QPA_HIP(launch_init_state(p.n, R, params->seed + (uint64_t)k, params->sigma0, dx, dm,
-                                  ds.np, 1, ds.Rp, ds.np, ak));
-        if (i8)
-            QPA_HIP(launch_mfma_pack_spins_i8(ds.Rp, ds.np, dx, reinterpret_cast<uint8_t *>(s0),
-                                              ak));
-        else
-            QPA_HIP(launch_mfma_pack_spins(ds.Rp, ds.np, dx, s0, ak));
+        hipError_t e = i8 ? launch_csr_to_i8(p, ds.np, reinterpret_cast<int8_t *>(Jb), ak)
+                          : launch_csr_to_bf16(p, ds.np, sc, Jb, ak);
+        if (e == hipSuccess) e = hipMemsetAsync(bfp, 0, sizeof(float) * (size_t)ds.np, ak);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(bfp, at<float>(iw, pl.o_bf), sizeof(float) * (size_t)p.n,
+                               hipMemcpyDeviceToDevice, ak);
+        if (e == hipSuccess)
+            e = launch_init_state(p.n, R, params->seed + (uint64_t)k, params->sigma0, dx, dm,
+                                  ds.np, 1, ds.Rp, ds.np, ak);
+        if (e == hipSuccess)
+            e = i8 ? launch_mfma_pack_spins_i8(ds.Rp, ds.np, dx,
+                                               reinterpret_cast<uint8_t *>(s0), ak)
+                   : launch_mfma_pack_spins(ds.Rp, ds.np, dx, s0, ak);
+        if (e != hipSuccess) return e;
+        std::vector<MfmaTile> &tv = itiles[k];
+        tv.reserve((size_t)(ds.Rp / MF_BM) * (size_t)(ds.np / MF_BN));
         for (int64_t rb = 0; rb < ds.Rp / MF_BM; ++rb)
             for (int64_t ib = 0; ib < ds.np / MF_BN; ++ib) {
                 MfmaTile tl{};
@@ -1342,10 +1384,16 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
                 tl.I0 = ib * MF_BN;
                 tl.R0 = rb * MF_BM;
                 tl.rlive = R;
-                (i8 ? tiles8 : tiles).push_back(tl);
+                tv.push_back(tl);
             }
+        return hipSuccess;
+    });
+    for (int32_t k = 0; k < count && s == QPA_OK; ++k) {
+        std::vector<MfmaTile> &dst = is_dense[k] == 2 ? tiles8 : tiles;
+        dst.insert(dst.end(), itiles[k].begin(), itiles[k].end());
     }
-    s = g1.close();
+    const qpa_status sj1 = g1.close();
+    if (s == QPA_OK) s = sj1;
     if (s != QPA_OK) return s;
     // largest instances first so that the tail of each step is made of small tiles; the
     // int8 tiles follow the BF16 ones in the uploaded table

@@ -521,6 +521,31 @@ def test_batch_uneven_instances_bit_exact(q, eng, path):
         assert int(host(out["best"])[0]) == int(np.flatnonzero(e == e.min())[0]), k
 
 
+def test_batch_reports_the_failing_instance(q, eng):
+    # An asymmetric instance in the middle of a batch is named in the error; the context
+    # then solves a valid batch to the oracle's bits.
+    rng = np.random.default_rng(5)
+    insts = [gen.er_qubo(int(n), 0.1, 100, rng) for n in (60, 90, 130, 70, 110, 80, 50)]
+    bad = insts[4]
+    k0 = int(np.flatnonzero(bad.csr.col[bad.csr.rp[0]:bad.csr.rp[1]] != 0)[0])
+    w = bad.csr.w.copy()
+    w[k0] += 1
+    bad.csr = gen.CSR(bad.n, bad.csr.rp, bad.csr.col, w)
+    R, T, eta, alpha, lam0 = 8, 5, 0.0002, 0.8, 200.0
+    p = _params(q, R, T, eta, alpha, lam0, seed=3)
+    say("batch with an asymmetric instance")
+    with pytest.raises(q.QpaError) as ei:
+        eng.solve_batch([q.Problem.from_instance(i) for i in insts], p)
+    assert ei.value.status == q.QPA_E_ASYM and "instance 4" in str(ei.value), str(ei.value)
+    good = insts[:4] + insts[5:]
+    say("valid batch after the error")
+    outs = eng.solve_batch([q.Problem.from_instance(i) for i in good], p, want_state=True)
+    lam = orc.lambda_linear(T, lam0)
+    for k, (inst, out) in enumerate(zip(good, outs)):
+        x, m, _ = _oracle_instance(inst, R, T, lam, eta, alpha, seed=3 + k)
+        assert np.array_equal(host(out["x"]), x) and np.array_equal(host(out["m"]), m), k
+
+
 def test_er512_full_workload_sampled(q, eng):
     wl = WORKLOADS["er512"]
     say("er512 generation")
