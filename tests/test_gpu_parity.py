@@ -786,5 +786,5 @@ def test_schedule_tuning_lowers_the_relaxed_energy(q, eng):
         opt.zero_grad()
         L.backward()
         opt.step()
-        losses.append(float(L))
+        losses.append(float(L.detach()))
     assert losses[-1] < losses[0]
