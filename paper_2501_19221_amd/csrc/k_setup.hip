@@ -2,6 +2,7 @@
 // state layout copies, exact energies (eq. (1) / eq. (2)) and best-of-replica.
 #include "qpa_internal.h"
 
+#include <algorithm>
 #include <type_traits>
 
 #include <math.h>
@@ -448,15 +449,27 @@ __global__ void __launch_bounds__(256) k_copy_state(int64_t n, int64_t R, const 
     }
 }
 
-__global__ void __launch_bounds__(256) k_export_spins(int64_t n, int64_t R, const float *x,
-                                                      int64_t ld_r, int64_t ld_i,
-                                                      int8_t *spins) {
+__device__ __forceinline__ void export_spins_body(int64_t n, int64_t R, const float *x,
+                                                  int64_t ld_r, int64_t ld_i, int8_t *spins) {
     const int64_t total = R * n;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
          k += (int64_t)gridDim.x * blockDim.x) {
         int64_t r = k / n, i = k - r * n;
         spins[k] = (x[r * ld_r + i * ld_i] >= 0.0f) ? (int8_t)1 : (int8_t)-1;
     }
+}
+
+__global__ void __launch_bounds__(256) k_export_spins(int64_t n, int64_t R, const float *x,
+                                                      int64_t ld_r, int64_t ld_i,
+                                                      int8_t *spins) {
+    export_spins_body(n, R, x, ld_r, ld_i, spins);
+}
+
+// Batched scoring: instance blockIdx.y of the task table, the same work per instance as
+// the single-instance kernels (one launch per kind instead of one per instance).
+__global__ void __launch_bounds__(256) k_export_spins_batch(const ScoreTask *__restrict__ tasks) {
+    const ScoreTask &t = tasks[blockIdx.y];
+    export_spins_body(t.n, t.R, t.x, t.ld_r, 1, t.spins);
 }
 
 // ------------------------------------------------------------------ energies
@@ -609,16 +622,16 @@ __global__ void __launch_bounds__(256) k_energy_csr(int64_t n, const int32_t *__
 // split over the lanes; replicas r0 .. r0+ER.  Same partial sums as k_energy_csr (each
 // pair once, exact integers), with 4 rows per block.
 template <typename TW, typename TI>
-__global__ void __launch_bounds__(256) k_energy_csr_wave(int64_t n,
-                                                         const int32_t *__restrict__ rp,
-                                                         const TI *__restrict__ col,
-                                                         const TW *__restrict__ w,
-                                                         const int64_t *__restrict__ b_i64,
-                                                         const int8_t *__restrict__ s, int64_t R,
-                                                         double *__restrict__ partial) {
+__device__ __forceinline__ void energy_csr_wave_body(int64_t n, const int32_t *__restrict__ rp,
+                                                     const TI *__restrict__ col,
+                                                     const TW *__restrict__ w,
+                                                     const int64_t *__restrict__ b_i64,
+                                                     const int8_t *__restrict__ s, int64_t R,
+                                                     double *__restrict__ partial, int64_t bx,
+                                                     int64_t by) {
     const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
-    const int64_t i = (int64_t)blockIdx.x * (256 / WAVE) + wv;
-    const int64_t r0 = (int64_t)blockIdx.y * ER;
+    const int64_t i = bx * (256 / WAVE) + wv;
+    const int64_t r0 = by * ER;
     __shared__ double red[256 / WAVE][ER];
     int64_t di[ER];
 #pragma unroll
@@ -653,9 +666,33 @@ __global__ void __launch_bounds__(256) k_energy_csr_wave(int64_t n,
         if (r < R) {
             double v = 0.0;
             for (int k = 0; k < 256 / WAVE; ++k) v += red[k][q];
-            partial[(int64_t)blockIdx.x * R + r] = v;
+            partial[bx * R + r] = v;
         }
     }
+}
+
+template <typename TW, typename TI>
+__global__ void __launch_bounds__(256) k_energy_csr_wave(int64_t n,
+                                                         const int32_t *__restrict__ rp,
+                                                         const TI *__restrict__ col,
+                                                         const TW *__restrict__ w,
+                                                         const int64_t *__restrict__ b_i64,
+                                                         const int8_t *__restrict__ s, int64_t R,
+                                                         double *__restrict__ partial) {
+    energy_csr_wave_body<TW, TI>(n, rp, col, w, b_i64, s, R, partial, blockIdx.x, blockIdx.y);
+}
+
+// Batched: block x of instance y covers partial block x % nblk and replica group
+// x / nblk (blocks past the instance's nblk * ceil(R / ER) return at once).
+template <typename TW, typename TI>
+__global__ void __launch_bounds__(256) k_energy_csr_wave_batch(const ScoreTask *__restrict__ tasks) {
+    const ScoreTask &t = tasks[blockIdx.y];
+    const int64_t gy = (t.R + ER - 1) / ER;
+    if ((int64_t)blockIdx.x >= t.nblk * gy) return;
+    energy_csr_wave_body<TW, TI>(t.n, t.rp, static_cast<const TI *>(t.col),
+                                 static_cast<const TW *>(t.w), t.b_i64, t.spins, t.R,
+                                 t.partial, (int64_t)blockIdx.x % t.nblk,
+                                 (int64_t)blockIdx.x / t.nblk);
 }
 
 // energy[r] = sum over blocks of partial[b][r] (fixed order), then the QUBO constant.
@@ -664,12 +701,12 @@ __global__ void __launch_bounds__(256) k_energy_csr_wave(int64_t n,
 // One wave per replica: lane l sums partials l, l + 64, ... in order, then a fixed
 // shuffle tree (deterministic; exact int64 sums for integer couplings).
 // twice: the partials sum to 2 H (dense kernel) instead of H.
-__global__ void __launch_bounds__(256) k_energy_finalize(int64_t R, int64_t nblk,
-                                                         const double *__restrict__ partial,
-                                                         int32_t is_int, int32_t is_qubo,
-                                                         int32_t twice, const CanonScalars *sc,
-                                                         int64_t *__restrict__ e_i64,
-                                                         double *__restrict__ e_f64) {
+__device__ __forceinline__ void energy_finalize_body(int64_t R, int64_t nblk,
+                                                     const double *__restrict__ partial,
+                                                     int32_t is_int, int32_t is_qubo,
+                                                     int32_t twice, const CanonScalars *sc,
+                                                     int64_t *__restrict__ e_i64,
+                                                     double *__restrict__ e_f64) {
     const int lane = threadIdx.x & 63;
     const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (r >= R) return;
@@ -692,8 +729,22 @@ __global__ void __launch_bounds__(256) k_energy_finalize(int64_t R, int64_t nblk
     }
 }
 
-__global__ void __launch_bounds__(1024) k_argmin(int64_t R, const int64_t *e_i64,
-                                                 const double *e_f64, int32_t *best) {
+__global__ void __launch_bounds__(256) k_energy_finalize(int64_t R, int64_t nblk,
+                                                         const double *__restrict__ partial,
+                                                         int32_t is_int, int32_t is_qubo,
+                                                         int32_t twice, const CanonScalars *sc,
+                                                         int64_t *__restrict__ e_i64,
+                                                         double *__restrict__ e_f64) {
+    energy_finalize_body(R, nblk, partial, is_int, is_qubo, twice, sc, e_i64, e_f64);
+}
+
+__global__ void __launch_bounds__(256) k_energy_finalize_batch(const ScoreTask *__restrict__ tasks) {
+    const ScoreTask &t = tasks[blockIdx.y];
+    energy_finalize_body(t.R, t.nblk, t.partial, 1, t.is_qubo, 0, t.sc, t.e_i64, t.e_f64);
+}
+
+__device__ __forceinline__ void argmin_body(int64_t R, const int64_t *e_i64,
+                                            const double *e_f64, int32_t *best) {
     __shared__ double sv[1024];
     __shared__ int64_t si[1024];
     __shared__ int64_t sv_i[1024];
@@ -735,6 +786,16 @@ __global__ void __launch_bounds__(1024) k_argmin(int64_t R, const int64_t *e_i64
         __syncthreads();
     }
     if (threadIdx.x == 0) best[0] = (int32_t)si[0];
+}
+
+__global__ void __launch_bounds__(1024) k_argmin(int64_t R, const int64_t *e_i64,
+                                                 const double *e_f64, int32_t *best) {
+    argmin_body(R, e_i64, e_f64, best);
+}
+
+__global__ void __launch_bounds__(1024) k_argmin_batch(const ScoreTask *__restrict__ tasks) {
+    const ScoreTask &t = tasks[blockIdx.y];
+    argmin_body(t.R, t.e_i64, t.e_f64, t.best);
 }
 
 inline unsigned grid1(int64_t total, int block, int64_t cap = 65536) {
@@ -920,6 +981,63 @@ hipError_t launch_argmin(int64_t R, const int64_t *e_i64, const double *e_f64, i
                          hipStream_t st) {
     k_argmin<<<1, 1024, 0, st>>>(R, e_i64, e_f64, best);
     return hipGetLastError();
+}
+
+// Batched scoring launches: instance y of the table in grid row y (at most 65535 rows a
+// launch); every kernel returns from the blocks an instance does not need.
+constexpr int32_t SCORE_ROWS = 65535;
+
+hipError_t launch_export_spins_batch(const ScoreTask *tasks, int32_t ntask, int64_t max_elems,
+                                     hipStream_t st) {
+    for (int32_t c0 = 0; c0 < ntask; c0 += SCORE_ROWS) {
+        const dim3 g(grid1(max_elems, 256, 64), (unsigned)std::min(SCORE_ROWS, ntask - c0));
+        k_export_spins_batch<<<g, 256, 0, st>>>(tasks + c0);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_energy_csr_wave_batch(const ScoreTask *tasks, int32_t ntask,
+                                        qpa_dtype coupling, qpa_dtype index, int64_t max_nblk,
+                                        int64_t max_R, hipStream_t st) {
+    const int64_t max_blocks = max_nblk * ((max_R + ER - 1) / ER);
+    if (max_blocks < 1 || max_blocks > INT32_MAX) return hipErrorInvalidValue;
+    auto run = [&](auto wtag, auto itag) {
+        using TW = decltype(wtag);
+        using TI = decltype(itag);
+        for (int32_t c0 = 0; c0 < ntask; c0 += SCORE_ROWS) {
+            const dim3 g((unsigned)max_blocks, (unsigned)std::min(SCORE_ROWS, ntask - c0));
+            k_energy_csr_wave_batch<TW, TI><<<g, 256, 0, st>>>(tasks + c0);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    auto byw = [&](auto itag) -> hipError_t {
+        switch (coupling) {
+            case QPA_I8: return run((int8_t)0, itag);
+            case QPA_I16: return run((int16_t)0, itag);
+            case QPA_I32: return run((int32_t)0, itag);
+            default: return hipErrorInvalidValue;
+        }
+    };
+    return index == QPA_I16 ? byw((int16_t)0) : byw((int32_t)0);
+}
+
+hipError_t launch_finalize_argmin_batch(const ScoreTask *tasks, int32_t ntask, int64_t max_R,
+                                        hipStream_t st) {
+    for (int32_t c0 = 0; c0 < ntask; c0 += SCORE_ROWS) {
+        const unsigned rows = (unsigned)std::min(SCORE_ROWS, ntask - c0);
+        k_energy_finalize_batch<<<dim3(grid1(max_R * 64, 256, INT64_MAX), rows), 256, 0, st>>>(
+            tasks + c0);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        k_argmin_batch<<<dim3(1, rows), 1024, 0, st>>>(tasks + c0);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace qpa

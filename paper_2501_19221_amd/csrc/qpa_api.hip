@@ -719,7 +719,7 @@ struct BatchPlan {
     std::vector<Plan> inst;          // per-instance single-solve plans (canonical buffers)
     std::vector<size_t> base;        // byte offset of each instance's region
     std::vector<DenseSlot> dense;
-    size_t o_tasks, o_tiles, o_counter, o_lam, total;
+    size_t o_tasks, o_tiles, o_score, o_counter, o_lam, total;
     int32_t ntasks, ntiles_max, max_n;
     int32_t inst_tiles_max;   // most tiles of one dense candidate
 };
@@ -831,6 +831,7 @@ qpa_status make_batch_plan(qpa_ctx *ctx, int32_t count, const qpa_problem *probs
     // filler entries when it is laid out by compute die
     bp.o_tiles = take(sizeof(MfmaTile) *
                       (size_t)std::max(bp.ntiles_max + 2 * XCDS * bp.inst_tiles_max, 1));
+    bp.o_score = take(sizeof(ScoreTask) * (size_t)std::max(count, 1));
     bp.o_counter = take(sizeof(int32_t));
     bp.o_lam = take(sizeof(float) * (size_t)std::max<int32_t>(a.steps, 1));
     bp.total = off;
@@ -1395,6 +1396,57 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
     const qpa_status sj1 = g1.close();
     if (s == QPA_OK) s = sj1;
     if (s != QPA_OK) return s;
+
+    // densified integer instances on the wave-per-row energy kernel are scored by batched
+    // launches (one per kind; the energy kernel once per coupling/index type pair)
+    struct ScoreGroup {
+        qpa_dtype w, i;
+        int32_t first, count;
+        int64_t max_nblk, max_R;
+    };
+    std::vector<ScoreTask> stasks;
+    std::vector<ScoreGroup> sgroups;
+    std::vector<char> batched(count, 0);
+    int64_t score_elems = 0, score_R = 0;
+    for (qpa_dtype wt : {QPA_I8, QPA_I16, QPA_I32})
+        for (qpa_dtype it : {QPA_I16, QPA_I32}) {
+            ScoreGroup g{wt, it, (int32_t)stasks.size(), 0, 0, 0};
+            for (int32_t k = 0; k < count; ++k) {
+                const qpa_problem &p = problems[k];
+                const Plan &pl = bp.inst[k];
+                if (!is_dense[k] || p.coupling_dtype != wt || p.index_dtype != it ||
+                    !csr_rows_by_wave(p) || energy_partial_blocks(p) > pl.eblk)
+                    continue;
+                const DenseSlot &ds = bp.dense[k];
+                char *iw = ws + bp.base[k];
+                const qpa_outputs &o = out[k];
+                ScoreTask t{};
+                t.x = reinterpret_cast<const float *>(ws + ds.o_x);
+                t.ld_r = ds.np;
+                t.n = p.n;
+                t.R = pl.R;
+                t.nblk = energy_partial_blocks(p);
+                t.rp = p.row_ptr;
+                t.col = p.col;
+                t.w = p.weights;
+                t.b_i64 = at<int64_t>(iw, pl.o_bi);
+                t.sc = at<CanonScalars>(iw, pl.o_sc);
+                t.spins = o.spins ? o.spins : at<int8_t>(iw, pl.o_sp);
+                t.partial = at<double>(iw, pl.o_part);
+                t.e_i64 = o.energy_i64 ? o.energy_i64 : at<int64_t>(iw, pl.o_ei);
+                t.e_f64 = o.energy;
+                t.best = o.best;
+                t.is_qubo = p.kind == QPA_KIND_QUBO ? 1 : 0;
+                stasks.push_back(t);
+                batched[k] = 1;
+                ++g.count;
+                g.max_nblk = std::max(g.max_nblk, t.nblk);
+                g.max_R = std::max(g.max_R, t.R);
+                score_elems = std::max(score_elems, t.R * t.n);
+                score_R = std::max(score_R, t.R);
+            }
+            if (g.count) sgroups.push_back(g);
+        }
     // largest instances first so that the tail of each step is made of small tiles; the
     // int8 tiles follow the BF16 ones in the uploaded table
     auto by_size = [](const MfmaTile &a, const MfmaTile &b) { return a.np > b.np; };
@@ -1440,14 +1492,19 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
     for (auto &pr : order) tasks.push_back(pr.second);
     const size_t tbytes = sizeof(BatchTask) * tasks.size();
     const size_t lbytes = sizeof(MfmaTile) * tiles.size();
+    const size_t sbytes = sizeof(ScoreTask) * stasks.size();
     char *hbuf = nullptr;
-    QPA_HIP(hipHostMalloc((void **)&hbuf, std::max<size_t>(tbytes + lbytes, 16)));
+    QPA_HIP(hipHostMalloc((void **)&hbuf, std::max<size_t>(tbytes + lbytes + sbytes, 16)));
     std::copy(tasks.begin(), tasks.end(), reinterpret_cast<BatchTask *>(hbuf));
     std::copy(tiles.begin(), tiles.end(), reinterpret_cast<MfmaTile *>(hbuf + tbytes));
+    std::copy(stasks.begin(), stasks.end(), reinterpret_cast<ScoreTask *>(hbuf + tbytes + lbytes));
     hipError_t ce = hipSuccess;
     if (tbytes) ce = hipMemcpyAsync(ws + bp.o_tasks, hbuf, tbytes, hipMemcpyHostToDevice, st);
     if (ce == hipSuccess && lbytes)
         ce = hipMemcpyAsync(ws + bp.o_tiles, hbuf + tbytes, lbytes, hipMemcpyHostToDevice, st);
+    if (ce == hipSuccess && sbytes)
+        ce = hipMemcpyAsync(ws + bp.o_score, hbuf + tbytes + lbytes, sbytes,
+                            hipMemcpyHostToDevice, st);
     if (ce == hipSuccess) ce = hipStreamSynchronize(st);
     (void)hipHostFree(hbuf);
     if (ce != hipSuccess) return fail(ctx, QPA_E_DEVICE, "task upload: %s", hipGetErrorString(ce));
@@ -1502,6 +1559,15 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
     s = aux_fork(ctx, st);
     if (s != QPA_OK) return s;
     AuxGuard g2{ctx, st};
+    if (!stasks.empty()) {
+        const ScoreTask *dst = reinterpret_cast<const ScoreTask *>(ws + bp.o_score);
+        const int32_t ns = (int32_t)stasks.size();
+        QPA_HIP(launch_export_spins_batch(dst, ns, score_elems, st));
+        for (const ScoreGroup &g : sgroups)
+            QPA_HIP(launch_energy_csr_wave_batch(dst + g.first, g.count, g.w, g.i, g.max_nblk,
+                                                 g.max_R, st));
+        QPA_HIP(launch_finalize_argmin_batch(dst, ns, score_R, st));
+    }
     for (int32_t k = 0; k < count; ++k) {
         hipStream_t ak = ctx->aux[(size_t)k % ctx->aux.size()];
         const Plan &pl = bp.inst[k];
@@ -1513,7 +1579,7 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
             const DenseSlot &ds = bp.dense[k];
             const float *dx = reinterpret_cast<const float *>(ws + ds.o_x);
             const float *dm = reinterpret_cast<const float *>(ws + ds.o_m);
-            QPA_HIP(launch_export_spins(p.n, R, dx, ds.np, 1, spins, ak));
+            if (!batched[k]) QPA_HIP(launch_export_spins(p.n, R, dx, ds.np, 1, spins, ak));
             if (o.x) QPA_HIP(launch_copy_state(p.n, R, dx, ds.np, 1, o.x, p.n, 1, ak));
             if (o.m) QPA_HIP(launch_copy_state(p.n, R, dm, ds.np, 1, o.m, p.n, 1, ak));
         }
@@ -1525,6 +1591,7 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
             if (o.x) QPA_HIP(launch_copy_state(p.n, rg, xg, 1, 64, o.x + g * 64 * p.n, p.n, 1, ak));
             if (o.m) QPA_HIP(launch_copy_state(p.n, rg, mg, 1, 64, o.m + g * 64 * p.n, p.n, 1, ak));
         }
+        if (batched[k]) continue;
         s = score(ctx, p, pl, iw, spins, o.energy, o.energy_i64, o.best, ak);
         if (s != QPA_OK) {
             std::string msg = "instance " + std::to_string(k) + ": " + ctx->err;

@@ -92,6 +92,36 @@ hipError_t launch_energy(const qpa_problem &p, const int64_t *b_i64, const doubl
 hipError_t launch_argmin(int64_t R, const int64_t *e_i64, const double *e_f64, int32_t *best,
                          hipStream_t st);
 
+// Batched scoring of integer CSR instances on the wave-per-row energy kernel: one launch
+// per kind for all instances of a table (device memory), each instance computed exactly
+// as by launch_export_spins + launch_energy + launch_argmin.
+struct ScoreTask {
+    const float *x;              // final state, element (r, i) at x[r * ld_r + i]
+    int64_t ld_r;
+    int64_t n, R;
+    int64_t nblk;                // energy partial blocks, energy_partial_blocks(problem)
+    const int32_t *rp;           // the instance's CSR (index and weight types of the launch)
+    const void *col;
+    const void *w;
+    const int64_t *b_i64;        // canonical integer field
+    const CanonScalars *sc;
+    int8_t *spins;               // [R][n] output
+    double *partial;             // nblk x R
+    int64_t *e_i64;              // R
+    double *e_f64;               // R
+    int32_t *best;               // 1
+    int32_t is_qubo;
+};
+hipError_t launch_export_spins_batch(const ScoreTask *tasks, int32_t ntask, int64_t max_elems,
+                                     hipStream_t st);
+// All tasks of one launch share the coupling and index types; max_nblk and max_R bound
+// the table's nblk and R.
+hipError_t launch_energy_csr_wave_batch(const ScoreTask *tasks, int32_t ntask,
+                                        qpa_dtype coupling, qpa_dtype index, int64_t max_nblk,
+                                        int64_t max_R, hipStream_t st);
+hipError_t launch_finalize_argmin_batch(const ScoreTask *tasks, int32_t ntask, int64_t max_R,
+                                        hipStream_t st);
+
 // ---- dense PA steps ------------------------------------------------------------------
 // Small instances: couplings in LDS, all steps of a replica block in one launch.
 bool dense_resident_fits(int64_t n);
