@@ -638,16 +638,52 @@ __global__ void __launch_bounds__(256) k_csr_to_i8(int64_t n, int64_t np,
     }
 }
 
+// The same matrix written whole, one workgroup per row (rows n .. np-1 zero): the row is
+// cleared and its entries placed in LDS, then stored in 16-byte pieces, so that the
+// matrix needs no separate clear.  np is a multiple of 128 and at most ROWS8_MAX_NP.
+constexpr int64_t ROWS8_MAX_NP = 65536;
+
+template <typename TW, typename TI>
+__global__ void __launch_bounds__(256) k_csr_to_i8_rows(int64_t n, int64_t np,
+                                                        const int32_t *__restrict__ rp,
+                                                        const TI *__restrict__ col,
+                                                        const TW *__restrict__ w,
+                                                        int8_t *__restrict__ J8) {
+    extern __shared__ uint4 row16[];              // np bytes
+    int8_t *row = reinterpret_cast<int8_t *>(row16);
+    const int64_t i = blockIdx.x;
+    const int64_t np16 = np / 16;
+    for (int64_t q = threadIdx.x; q < np16; q += blockDim.x) row16[q] = make_uint4(0, 0, 0, 0);
+    __syncthreads();
+    if (i < n) {
+        for (int64_t k = rp[i] + threadIdx.x; k < rp[i + 1]; k += blockDim.x) {
+            const int64_t j = (int64_t)col[k];
+            if (j != i) row[j] = (int8_t)w[k];
+        }
+    }
+    __syncthreads();
+    uint4 *dst = reinterpret_cast<uint4 *>(J8 + i * np);
+    for (int64_t q = threadIdx.x; q < np16; q += blockDim.x) dst[q] = row16[q];
+}
+
 hipError_t launch_csr_to_i8(const qpa_problem &p, int64_t np, int8_t *J8, hipStream_t st) {
-    hipError_t e = hipMemsetAsync(J8, 0, (size_t)(np * np), st);
-    if (e != hipSuccess) return e;
+    const bool rows = np % 128 == 0 && np >= p.n && np <= ROWS8_MAX_NP;
+    if (!rows) {
+        const hipError_t e = hipMemsetAsync(J8, 0, (size_t)(np * np), st);
+        if (e != hipSuccess) return e;
+    }
     const int64_t g = (p.n + 3) / 4;
     auto run = [&](auto wtag, auto itag) {
         using TW = decltype(wtag);
         using TI = decltype(itag);
-        k_csr_to_i8<TW, TI><<<(unsigned)g, 256, 0, st>>>(
-            p.n, np, p.row_ptr, static_cast<const TI *>(p.col),
-            static_cast<const TW *>(p.weights), J8);
+        if (rows)
+            k_csr_to_i8_rows<TW, TI><<<(unsigned)np, 256, (size_t)np, st>>>(
+                p.n, np, p.row_ptr, static_cast<const TI *>(p.col),
+                static_cast<const TW *>(p.weights), J8);
+        else
+            k_csr_to_i8<TW, TI><<<(unsigned)g, 256, 0, st>>>(
+                p.n, np, p.row_ptr, static_cast<const TI *>(p.col),
+                static_cast<const TW *>(p.weights), J8);
         return hipGetLastError();
     };
     auto byw = [&](auto itag) -> hipError_t {

@@ -172,7 +172,7 @@ __global__ void __launch_bounds__(1024) k_canon_finalize(int64_t n, const double
                                                          const double *row_max,
                                                          const double *row_k,
                                                          const double *parts, int32_t is_int,
-                                                         CanonScalars *sc) {
+                                                         CanonScalars *sc, CanonScalars *mirror) {
     __shared__ double s_abs[1024 / WAVE], s_max[1024 / WAVE], s_k[1024 / WAVE];
     __shared__ int64_t s_ki[1024 / WAVE];
     double a = 0.0, mx = 0.0, kf = 0.0;
@@ -215,7 +215,9 @@ __global__ void __launch_bounds__(1024) k_canon_finalize(int64_t n, const double
         sc->max_abs = M;
         sc->K_f64 = 0.5 * Kf;
         sc->K_i64 = Ki / 2;
-        if (is_int && A >= 16777216.0) atomicOr(&sc->flags, (int32_t)FLAG_RANGE);
+        // the flags of the earlier kernels, read atomically, plus the range bit
+        const int32_t add = (is_int && A >= 16777216.0) ? (int32_t)FLAG_RANGE : 0;
+        const int32_t flags = atomicOr(&sc->flags, add) | add;
         int e = 0;
         if (M > 0.0) {
             e = (int)ceil(log2(M));
@@ -226,6 +228,18 @@ __global__ void __launch_bounds__(1024) k_canon_finalize(int64_t n, const double
         sc->exp2 = e;
         sc->scale = ldexpf(1.0f, e);
         sc->inv_scale = ldexpf(1.0f, -e);
+        if (mirror) {            // a copy in a contiguous array of a batch's instances
+            CanonScalars c;
+            c.K_i64 = Ki / 2;
+            c.K_f64 = 0.5 * Kf;
+            c.scale = ldexpf(1.0f, e);
+            c.inv_scale = ldexpf(1.0f, -e);
+            c.flags = flags;
+            c.exp2 = e;
+            c.max_row = A;
+            c.max_abs = M;
+            *mirror = c;
+        }
     }
 }
 
@@ -457,6 +471,13 @@ __device__ __forceinline__ void export_spins_body(int64_t n, int64_t R, const fl
         int64_t r = k / n, i = k - r * n;
         spins[k] = (x[r * ld_r + i * ld_i] >= 0.0f) ? (int8_t)1 : (int8_t)-1;
     }
+}
+
+__global__ void __launch_bounds__(256) k_pad_f32(int64_t n, int64_t np, const float *src,
+                                                 float *dst) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = i < n ? src[i] : 0.0f;
 }
 
 __global__ void __launch_bounds__(256) k_export_spins(int64_t n, int64_t R, const float *x,
@@ -818,16 +839,19 @@ template <typename F> hipError_t dispatch_q(int32_t dt, F &&f) {
 // One launch for small instances; above CANON_ROWS_PER_PART rows, P <= CANON_PARTS
 // workgroups of rows and a single-workgroup reduction of their partials.
 void canon_reduce(int64_t n, const double *row_abs, const double *row_max, const double *row_k,
-                  double *parts, int32_t is_int, CanonScalars *sc, hipStream_t st) {
+                  double *parts, int32_t is_int, CanonScalars *sc, CanonScalars *mirror,
+                  hipStream_t st) {
     if (n <= CANON_ROWS_PER_PART || parts == nullptr) {
-        k_canon_finalize<<<1, 1024, 0, st>>>(n, row_abs, row_max, row_k, nullptr, is_int, sc);
+        k_canon_finalize<<<1, 1024, 0, st>>>(n, row_abs, row_max, row_k, nullptr, is_int, sc,
+                                             mirror);
         return;
     }
     int64_t P = (n + CANON_ROWS_PER_PART - 1) / CANON_ROWS_PER_PART;
     if (P > CANON_PARTS) P = CANON_PARTS;
     const int64_t rows = (n + P - 1) / P;
     k_canon_part<<<(unsigned)P, 1024, 0, st>>>(n, rows, row_abs, row_max, row_k, parts);
-    k_canon_finalize<<<1, 1024, 0, st>>>(P, nullptr, nullptr, nullptr, parts, is_int, sc);
+    k_canon_finalize<<<1, 1024, 0, st>>>(P, nullptr, nullptr, nullptr, parts, is_int, sc,
+                                         mirror);
 }
 
 }  // namespace
@@ -850,7 +874,7 @@ hipError_t launch_canon_dense(const qpa_problem &p, float *J_f32, uint16_t *Jb, 
             row_max, row_k, sc);
         int64_t nb = (n + 31) / 32;
         k_dense_sym<T><<<dim3((unsigned)nb, (unsigned)nb), 256, 0, st>>>(n, Q, sc);
-        canon_reduce(n, row_abs, row_max, row_k, parts, is_int, sc, st);
+        canon_reduce(n, row_abs, row_max, row_k, parts, is_int, sc, nullptr, st);
         if (Jb) k_dense_bf16<T><<<grid1(npad * npad, 256), 256, 0, st>>>(n, npad, Q, sc, Jb);
         return hipGetLastError();
     });
@@ -859,7 +883,7 @@ hipError_t launch_canon_dense(const qpa_problem &p, float *J_f32, uint16_t *Jb, 
 
 hipError_t launch_canon_csr(const qpa_problem &p, float *b_f32, int64_t *b_i64, double *b_f64,
                             double *row_abs, double *row_max, double *row_k, double *parts,
-                            CanonScalars *sc, hipStream_t st) {
+                            CanonScalars *sc, hipStream_t st, CanonScalars *mirror) {
     const int64_t n = p.n;
     const int32_t is_qubo = p.kind == QPA_KIND_QUBO;
     const int32_t is_int = dtype_is_int(p.coupling_dtype) &&
@@ -879,7 +903,7 @@ hipError_t launch_canon_csr(const qpa_problem &p, float *b_f32, int64_t *b_i64, 
                 n, p.nnz, p.row_ptr, static_cast<const TI *>(p.col),
                 static_cast<const TW *>(p.weights), p.linear, p.linear_dtype, is_qubo, b_f32,
                 b_i64, b_f64, row_abs, row_max, row_k, sc);
-        canon_reduce(n, row_abs, row_max, row_k, parts, is_int, sc, st);
+        canon_reduce(n, row_abs, row_max, row_k, parts, is_int, sc, mirror, st);
         return hipGetLastError();
     };
     return dispatch_q(p.coupling_dtype, [&](auto wtag) {
@@ -902,6 +926,12 @@ hipError_t launch_copy_state(int64_t n, int64_t R, const float *src, int64_t s_l
     if (R * n == 0) return hipSuccess;
     k_copy_state<<<grid1(R * n, 256), 256, 0, st>>>(n, R, src, s_ld_r, s_ld_i, dst, d_ld_r,
                                                     d_ld_i);
+    return hipGetLastError();
+}
+
+hipError_t launch_pad_f32(int64_t n, int64_t np, const float *src, float *dst, hipStream_t st) {
+    if (np <= 0) return hipSuccess;
+    k_pad_f32<<<grid1(np, 256), 256, 0, st>>>(n, np, src, dst);
     return hipGetLastError();
 }
 

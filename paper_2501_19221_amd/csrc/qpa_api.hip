@@ -719,7 +719,7 @@ struct BatchPlan {
     std::vector<Plan> inst;          // per-instance single-solve plans (canonical buffers)
     std::vector<size_t> base;        // byte offset of each instance's region
     std::vector<DenseSlot> dense;
-    size_t o_tasks, o_tiles, o_score, o_counter, o_lam, total;
+    size_t o_tasks, o_tiles, o_score, o_scall, o_counter, o_lam, total;
     int32_t ntasks, ntiles_max, max_n;
     int32_t inst_tiles_max;   // most tiles of one dense candidate
 };
@@ -832,6 +832,7 @@ qpa_status make_batch_plan(qpa_ctx *ctx, int32_t count, const qpa_problem *probs
     bp.o_tiles = take(sizeof(MfmaTile) *
                       (size_t)std::max(bp.ntiles_max + 2 * XCDS * bp.inst_tiles_max, 1));
     bp.o_score = take(sizeof(ScoreTask) * (size_t)std::max(count, 1));
+    bp.o_scall = take(sizeof(CanonScalars) * (size_t)std::max(count, 1));
     bp.o_counter = take(sizeof(int32_t));
     bp.o_lam = take(sizeof(float) * (size_t)std::max<int32_t>(a.steps, 1));
     bp.total = off;
@@ -1283,9 +1284,10 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
     if (s != QPA_OK) return s;
 
     // canonicalise + validate every instance (instances spread over the context's
-    // auxiliary streams: their launches are small and independent), then one read-back of
-    // all the flags
+    // auxiliary streams: their launches are small and independent), each also writing its
+    // scalars into one array, then one read-back of that array
     std::vector<CanonScalars> hsc(count);
+    CanonScalars *scall = reinterpret_cast<CanonScalars *>(ws + bp.o_scall);
     CanonScalars *pinned = nullptr;
     QPA_HIP(hipHostMalloc((void **)&pinned, sizeof(CanonScalars) * (size_t)count));
     s = aux_fork(ctx, st);
@@ -1297,19 +1299,20 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
     s = aux_issue(ctx, count, "canonicalisation", [&](int32_t k, hipStream_t ak) {
         const Plan &pl = bp.inst[k];
         void *iw = ws + bp.base[k];
-        hipError_t e = launch_canon_csr(problems[k], at<float>(iw, pl.o_bf),
-                                        at<int64_t>(iw, pl.o_bi), at<double>(iw, pl.o_bd),
-                                        at<double>(iw, pl.o_rabs), at<double>(iw, pl.o_rmax),
-                                        at<double>(iw, pl.o_rk), at<double>(iw, pl.o_cpart),
-                                        at<CanonScalars>(iw, pl.o_sc), ak);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(&pinned[k], at<CanonScalars>(iw, pl.o_sc), sizeof(CanonScalars),
-                               hipMemcpyDeviceToHost, ak);
-        return e;
+        return launch_canon_csr(problems[k], at<float>(iw, pl.o_bf), at<int64_t>(iw, pl.o_bi),
+                                at<double>(iw, pl.o_bd), at<double>(iw, pl.o_rabs),
+                                at<double>(iw, pl.o_rmax), at<double>(iw, pl.o_rk),
+                                at<double>(iw, pl.o_cpart), at<CanonScalars>(iw, pl.o_sc), ak,
+                                scall + k);
     });
     const qpa_status sj = g0.close();
     if (s == QPA_OK) s = sj;
-    hipError_t se = hipStreamSynchronize(st);
+    hipError_t se = hipSuccess;
+    if (s == QPA_OK)
+        se = hipMemcpyAsync(pinned, scall, sizeof(CanonScalars) * (size_t)count,
+                            hipMemcpyDeviceToHost, st);
+    const hipError_t se2 = hipStreamSynchronize(st);
+    if (se == hipSuccess) se = se2;
     if (s != QPA_OK) {
         (void)hipHostFree(pinned);
         return s;
@@ -1356,10 +1359,7 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
         const CanonScalars *sc = at<CanonScalars>(iw, pl.o_sc);
         hipError_t e = i8 ? launch_csr_to_i8(p, ds.np, reinterpret_cast<int8_t *>(Jb), ak)
                           : launch_csr_to_bf16(p, ds.np, sc, Jb, ak);
-        if (e == hipSuccess) e = hipMemsetAsync(bfp, 0, sizeof(float) * (size_t)ds.np, ak);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(bfp, at<float>(iw, pl.o_bf), sizeof(float) * (size_t)p.n,
-                               hipMemcpyDeviceToDevice, ak);
+        if (e == hipSuccess) e = launch_pad_f32(p.n, ds.np, at<float>(iw, pl.o_bf), bfp, ak);
         if (e == hipSuccess)
             e = launch_init_state(p.n, R, params->seed + (uint64_t)k, params->sigma0, dx, dm,
                                   ds.np, 1, ds.Rp, ds.np, ak);

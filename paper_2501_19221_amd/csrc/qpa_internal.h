@@ -58,9 +58,10 @@ hipError_t launch_canon_dense(const qpa_problem &p, float *J_f32, uint16_t *Jb, 
                               CanonScalars *sc, hipStream_t st);
 
 // Canonicalisation of a CSR problem: b_f32 / b_i64 / b_f64, validation, scalars.
+// mirror (optional): a second copy of the finished scalars (one slot of a batch's array).
 hipError_t launch_canon_csr(const qpa_problem &p, float *b_f32, int64_t *b_i64, double *b_f64,
                             double *row_abs, double *row_max, double *row_k, double *parts,
-                            CanonScalars *sc, hipStream_t st);
+                            CanonScalars *sc, hipStream_t st, CanonScalars *mirror = nullptr);
 
 // x0 / m0 from the counter RNG.  Layout: element (r, i) at x[r * ld_r + i * ld_i].
 hipError_t launch_init_state(int64_t n, int64_t R, uint64_t seed, float sigma0, float *x,
@@ -71,6 +72,9 @@ hipError_t launch_init_state(int64_t n, int64_t R, uint64_t seed, float sigma0, 
 hipError_t launch_copy_state(int64_t n, int64_t R, const float *src, int64_t s_ld_r,
                              int64_t s_ld_i, float *dst, int64_t d_ld_r, int64_t d_ld_i,
                              hipStream_t st);
+
+// dst[i] = src[i] for i < n, 0 for n <= i < np.
+hipError_t launch_pad_f32(int64_t n, int64_t np, const float *src, float *dst, hipStream_t st);
 
 // spins[r*n+i] = sign(x(r,i)) (int8).
 hipError_t launch_export_spins(int64_t n, int64_t R, const float *x, int64_t ld_r,
