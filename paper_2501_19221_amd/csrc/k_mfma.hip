@@ -38,6 +38,8 @@
 //   D (32 x 32): register v of lane l holds row 8*(v/4) + 4*(l/32) + v%4, col l%32.
 #include "qpa_internal.h"
 
+#include <algorithm>
+
 namespace qpa {
 namespace {
 
@@ -644,14 +646,13 @@ __global__ void __launch_bounds__(256) k_csr_to_i8(int64_t n, int64_t np,
 constexpr int64_t ROWS8_MAX_NP = 65536;
 
 template <typename TW, typename TI>
-__global__ void __launch_bounds__(256) k_csr_to_i8_rows(int64_t n, int64_t np,
-                                                        const int32_t *__restrict__ rp,
-                                                        const TI *__restrict__ col,
-                                                        const TW *__restrict__ w,
-                                                        int8_t *__restrict__ J8) {
+__device__ __forceinline__ void csr_to_i8_row(int64_t i, int64_t n, int64_t np,
+                                              const int32_t *__restrict__ rp,
+                                              const TI *__restrict__ col,
+                                              const TW *__restrict__ w,
+                                              int8_t *__restrict__ J8) {
     extern __shared__ uint4 row16[];              // np bytes
     int8_t *row = reinterpret_cast<int8_t *>(row16);
-    const int64_t i = blockIdx.x;
     const int64_t np16 = np / 16;
     for (int64_t q = threadIdx.x; q < np16; q += blockDim.x) row16[q] = make_uint4(0, 0, 0, 0);
     __syncthreads();
@@ -664,6 +665,50 @@ __global__ void __launch_bounds__(256) k_csr_to_i8_rows(int64_t n, int64_t np,
     __syncthreads();
     uint4 *dst = reinterpret_cast<uint4 *>(J8 + i * np);
     for (int64_t q = threadIdx.x; q < np16; q += blockDim.x) dst[q] = row16[q];
+}
+
+template <typename TW, typename TI>
+__global__ void __launch_bounds__(256) k_csr_to_i8_rows(int64_t n, int64_t np,
+                                                        const int32_t *__restrict__ rp,
+                                                        const TI *__restrict__ col,
+                                                        const TW *__restrict__ w,
+                                                        int8_t *__restrict__ J8) {
+    csr_to_i8_row<TW, TI>(blockIdx.x, n, np, rp, col, w, J8);
+}
+
+// Batched: row blockIdx.x of instance blockIdx.y (rows past the instance's np return).
+template <typename TW, typename TI>
+__global__ void __launch_bounds__(256) k_csr_to_i8_rows_batch(const SlotInitTask *__restrict__ tasks) {
+    const SlotInitTask &t = tasks[blockIdx.y];
+    if ((int64_t)blockIdx.x >= t.np) return;
+    csr_to_i8_row<TW, TI>(blockIdx.x, t.n, t.np, t.rp, static_cast<const TI *>(t.col),
+                          static_cast<const TW *>(t.w), t.J8);
+}
+
+hipError_t launch_csr_to_i8_batch(const SlotInitTask *tasks, int32_t ntask, qpa_dtype coupling,
+                                  qpa_dtype index, int64_t max_np, hipStream_t st) {
+    if (max_np < MF_NPAD || max_np % MF_NPAD || max_np > ROWS8_MAX_NP)
+        return hipErrorInvalidValue;
+    auto run = [&](auto wtag, auto itag) {
+        using TW = decltype(wtag);
+        using TI = decltype(itag);
+        for (int32_t c0 = 0; c0 < ntask; c0 += 65535) {
+            const dim3 g((unsigned)max_np, (unsigned)std::min(65535, ntask - c0));
+            k_csr_to_i8_rows_batch<TW, TI><<<g, 256, (size_t)max_np, st>>>(tasks + c0);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    auto byw = [&](auto itag) -> hipError_t {
+        switch (coupling) {
+            case QPA_I8: return run((int8_t)0, itag);
+            case QPA_I16: return run((int16_t)0, itag);
+            case QPA_I32: return run((int32_t)0, itag);
+            default: return hipErrorInvalidValue;
+        }
+    };
+    return index == QPA_I16 ? byw((int16_t)0) : byw((int32_t)0);
 }
 
 hipError_t launch_csr_to_i8(const qpa_problem &p, int64_t np, int8_t *J8, hipStream_t st) {

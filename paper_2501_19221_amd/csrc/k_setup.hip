@@ -417,6 +417,19 @@ __device__ __forceinline__ uint64_t splitmix_output(uint64_t seed, uint64_t k) {
     return z ^ (z >> 31);
 }
 
+// x0 of replica r, variable i (0 in the padding past R or n).
+__device__ __forceinline__ float init_x(uint64_t seed, float sigma0, int64_t n, int64_t R,
+                                        int64_t r, int64_t i) {
+    float xv = 0.0f;
+    if (r < R && i < n) {
+        uint64_t top = splitmix_output(seed, (uint64_t)(r * n + i) + 1u) >> 40;
+        float u = __fmul_rn((float)top, 1.0f / 16777216.0f);
+        float v = __fsub_rn(__fmul_rn(2.0f, u), 1.0f);
+        xv = __fmul_rn(sigma0, v);
+    }
+    return xv;
+}
+
 __global__ void __launch_bounds__(256) k_init_state(int64_t n, int64_t R, uint64_t seed,
                                                     float sigma0, float *__restrict__ x,
                                                     float *__restrict__ m, int64_t ld_r,
@@ -432,15 +445,29 @@ __global__ void __launch_bounds__(256) k_init_state(int64_t n, int64_t R, uint64
             i = k / Rpad;
             r = k - i * Rpad;
         }
-        float xv = 0.0f;
-        if (r < R && i < n) {
-            uint64_t top = splitmix_output(seed, (uint64_t)(r * n + i) + 1u) >> 40;
-            float u = __fmul_rn((float)top, 1.0f / 16777216.0f);
-            float v = __fsub_rn(__fmul_rn(2.0f, u), 1.0f);
-            xv = __fmul_rn(sigma0, v);
-        }
+        const float xv = init_x(seed, sigma0, n, R, r, i);
         x[r * ld_r + i * ld_i] = xv;
         m[r * ld_r + i * ld_i] = 0.0f;
+    }
+}
+
+// Batched set-up of int8 dense slots (instance blockIdx.y of the table): x0 and m0 as
+// k_init_state in the [Rp][np] layout, the byte spins of x0 as the int8 tile kernel
+// reads them (chunk-major: element (r, i) at (i / C) * Rp * C + r * C + i % C, C =
+// MF_NPAD, 0xFF for a negative x), and the field padded to np.
+__global__ void __launch_bounds__(256) k_slot_init_batch(const SlotInitTask *__restrict__ tasks,
+                                                         float sigma0) {
+    const SlotInitTask &t = tasks[blockIdx.y];
+    const int64_t total = t.Rp * t.np;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = k / t.np, i = k - r * t.np;
+        const float xv = init_x(t.seed, sigma0, t.n, t.R, r, i);
+        t.x[k] = xv;
+        t.m[k] = 0.0f;
+        t.s8[(i / MF_NPAD) * t.Rp * MF_NPAD + r * MF_NPAD + i % MF_NPAD] =
+            xv < 0.0f ? (uint8_t)0xFF : (uint8_t)0x01;
+        if (r == 0) t.bfp[i] = i < t.n ? t.bf[i] : 0.0f;
     }
 }
 
@@ -918,6 +945,17 @@ hipError_t launch_init_state(int64_t n, int64_t R, uint64_t seed, float sigma0, 
     k_init_state<<<grid1(Rpad * npad, 256), 256, 0, st>>>(n, R, seed, sigma0, x, m, ld_r, ld_i,
                                                           Rpad, npad);
     return hipGetLastError();
+}
+
+hipError_t launch_slot_init_batch(const SlotInitTask *tasks, int32_t ntask, int64_t max_elems,
+                                  float sigma0, hipStream_t st) {
+    for (int32_t c0 = 0; c0 < ntask; c0 += 65535) {
+        const dim3 g(grid1(max_elems, 256, 256), (unsigned)std::min(65535, ntask - c0));
+        k_slot_init_batch<<<g, 256, 0, st>>>(tasks + c0, sigma0);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_copy_state(int64_t n, int64_t R, const float *src, int64_t s_ld_r,

@@ -719,7 +719,7 @@ struct BatchPlan {
     std::vector<Plan> inst;          // per-instance single-solve plans (canonical buffers)
     std::vector<size_t> base;        // byte offset of each instance's region
     std::vector<DenseSlot> dense;
-    size_t o_tasks, o_tiles, o_score, o_scall, o_counter, o_lam, total;
+    size_t o_tasks, o_tiles, o_score, o_scall, o_slot, o_counter, o_lam, total;
     int32_t ntasks, ntiles_max, max_n;
     int32_t inst_tiles_max;   // most tiles of one dense candidate
 };
@@ -833,6 +833,7 @@ qpa_status make_batch_plan(qpa_ctx *ctx, int32_t count, const qpa_problem *probs
                       (size_t)std::max(bp.ntiles_max + 2 * XCDS * bp.inst_tiles_max, 1));
     bp.o_score = take(sizeof(ScoreTask) * (size_t)std::max(count, 1));
     bp.o_scall = take(sizeof(CanonScalars) * (size_t)std::max(count, 1));
+    bp.o_slot = take(sizeof(SlotInitTask) * (size_t)std::max(count, 1));
     bp.o_counter = take(sizeof(int32_t));
     bp.o_lam = take(sizeof(float) * (size_t)std::max<int32_t>(a.steps, 1));
     bp.total = off;
@@ -1337,6 +1338,15 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
     std::vector<char> is_dense(count, 0);
     std::vector<MfmaTile> tiles, tiles8;
     std::vector<std::vector<MfmaTile>> itiles(count);
+    // int8 slots (np <= 65536) are set up by batched launches below, the others per
+    // instance on the auxiliary streams
+    std::vector<char> slot8(count, 0);
+    for (int32_t k = 0; k < count; ++k) {
+        const DenseSlot &ds = bp.dense[k];
+        if (ds.cand && bp.inst[k].is_int && hsc[k].max_abs <= 127.0 &&
+            problems[k].coupling_dtype != QPA_F32 && ds.np <= 65536)
+            slot8[k] = 1;
+    }
     s = aux_fork(ctx, st);
     if (s != QPA_OK) return s;
     AuxGuard g1{ctx, st};
@@ -1357,17 +1367,20 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
         uint32_t *s0 = reinterpret_cast<uint32_t *>(ws + ds.o_s0);
         uint32_t *s1 = reinterpret_cast<uint32_t *>(ws + ds.o_s1);
         const CanonScalars *sc = at<CanonScalars>(iw, pl.o_sc);
-        hipError_t e = i8 ? launch_csr_to_i8(p, ds.np, reinterpret_cast<int8_t *>(Jb), ak)
-                          : launch_csr_to_bf16(p, ds.np, sc, Jb, ak);
-        if (e == hipSuccess) e = launch_pad_f32(p.n, ds.np, at<float>(iw, pl.o_bf), bfp, ak);
-        if (e == hipSuccess)
-            e = launch_init_state(p.n, R, params->seed + (uint64_t)k, params->sigma0, dx, dm,
-                                  ds.np, 1, ds.Rp, ds.np, ak);
-        if (e == hipSuccess)
-            e = i8 ? launch_mfma_pack_spins_i8(ds.Rp, ds.np, dx,
-                                               reinterpret_cast<uint8_t *>(s0), ak)
-                   : launch_mfma_pack_spins(ds.Rp, ds.np, dx, s0, ak);
-        if (e != hipSuccess) return e;
+        if (!slot8[k]) {        // int8 slots: matrix, field and state by the batched launches
+            hipError_t e = i8 ? launch_csr_to_i8(p, ds.np, reinterpret_cast<int8_t *>(Jb), ak)
+                              : launch_csr_to_bf16(p, ds.np, sc, Jb, ak);
+            if (e == hipSuccess)
+                e = launch_pad_f32(p.n, ds.np, at<float>(iw, pl.o_bf), bfp, ak);
+            if (e == hipSuccess)
+                e = launch_init_state(p.n, R, params->seed + (uint64_t)k, params->sigma0, dx,
+                                      dm, ds.np, 1, ds.Rp, ds.np, ak);
+            if (e == hipSuccess)
+                e = i8 ? launch_mfma_pack_spins_i8(ds.Rp, ds.np, dx,
+                                                   reinterpret_cast<uint8_t *>(s0), ak)
+                       : launch_mfma_pack_spins(ds.Rp, ds.np, dx, s0, ak);
+            if (e != hipSuccess) return e;
+        }
         std::vector<MfmaTile> &tv = itiles[k];
         tv.reserve((size_t)(ds.Rp / MF_BM) * (size_t)(ds.np / MF_BN));
         for (int64_t rb = 0; rb < ds.Rp / MF_BM; ++rb)
@@ -1396,6 +1409,67 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
     const qpa_status sj1 = g1.close();
     if (s == QPA_OK) s = sj1;
     if (s != QPA_OK) return s;
+
+    // batched set-up of the int8 slots: a table uploaded once, the matrix once per
+    // coupling/index type pair, then x0, m0, byte spins and padded field in one launch
+    {
+        std::vector<SlotInitTask> it8;
+        struct SlotGroup {
+            qpa_dtype w, i;
+            int32_t first, count;
+            int64_t max_np;
+        };
+        std::vector<SlotGroup> groups;
+        int64_t max_elems = 0;
+        for (qpa_dtype wt : {QPA_I8, QPA_I16, QPA_I32})
+            for (qpa_dtype xt : {QPA_I16, QPA_I32}) {
+                SlotGroup g{wt, xt, (int32_t)it8.size(), 0, 0};
+                for (int32_t k = 0; k < count; ++k) {
+                    const qpa_problem &p = problems[k];
+                    if (!slot8[k] || p.coupling_dtype != wt || p.index_dtype != xt) continue;
+                    const DenseSlot &ds = bp.dense[k];
+                    const Plan &pl = bp.inst[k];
+                    char *iw = ws + bp.base[k];
+                    SlotInitTask t{};
+                    t.rp = p.row_ptr;
+                    t.col = p.col;
+                    t.w = p.weights;
+                    t.bf = at<float>(iw, pl.o_bf);
+                    t.J8 = reinterpret_cast<int8_t *>(ws + ds.o_Jb);
+                    t.bfp = reinterpret_cast<float *>(ws + ds.o_bfp);
+                    t.x = reinterpret_cast<float *>(ws + ds.o_x);
+                    t.m = reinterpret_cast<float *>(ws + ds.o_m);
+                    t.s8 = reinterpret_cast<uint8_t *>(ws + ds.o_s0);
+                    t.n = p.n;
+                    t.np = ds.np;
+                    t.R = R;
+                    t.Rp = ds.Rp;
+                    t.seed = params->seed + (uint64_t)k;
+                    it8.push_back(t);
+                    ++g.count;
+                    g.max_np = std::max(g.max_np, ds.np);
+                    max_elems = std::max(max_elems, ds.Rp * ds.np);
+                }
+                if (g.count) groups.push_back(g);
+            }
+        if (!it8.empty()) {
+            const size_t bytes = sizeof(SlotInitTask) * it8.size();
+            SlotInitTask *h = nullptr;
+            QPA_HIP(hipHostMalloc((void **)&h, bytes));
+            std::copy(it8.begin(), it8.end(), h);
+            hipError_t e = hipMemcpyAsync(ws + bp.o_slot, h, bytes, hipMemcpyHostToDevice, st);
+            const hipError_t e2 = hipStreamSynchronize(st);
+            (void)hipHostFree(h);
+            if (e == hipSuccess) e = e2;
+            if (e != hipSuccess)
+                return fail(ctx, QPA_E_DEVICE, "slot table upload: %s", hipGetErrorString(e));
+            const SlotInitTask *dt = reinterpret_cast<const SlotInitTask *>(ws + bp.o_slot);
+            for (const SlotGroup &g : groups)
+                QPA_HIP(launch_csr_to_i8_batch(dt + g.first, g.count, g.w, g.i, g.max_np, st));
+            QPA_HIP(launch_slot_init_batch(dt, (int32_t)it8.size(), max_elems, params->sigma0,
+                                           st));
+        }
+    }
 
     // densified integer instances on the wave-per-row energy kernel are scored by batched
     // launches (one per kind; the energy kernel once per coupling/index type pair)

@@ -172,6 +172,27 @@ hipError_t launch_mfma_grouped(const MfmaTile *tiles, int32_t ntiles, int32_t t,
 hipError_t launch_mfma_pack_spins_i8(int64_t Rp, int64_t np, const float *x, uint8_t *s8,
                                      hipStream_t st);
 hipError_t launch_csr_to_i8(const qpa_problem &p, int64_t np, int8_t *J8, hipStream_t st);
+
+// Batched set-up of the int8 dense slots of a batch (instance y of a device table in grid
+// row y): the int8 matrix row by row (all instances of a launch share the coupling and
+// index types; np at most 65536), and x0, m0, byte spins and padded field (each as the
+// single-instance launchers write them).
+struct SlotInitTask {
+    const int32_t *rp;
+    const void *col;
+    const void *w;
+    const float *bf;             // canonical FP32 field (n)
+    int8_t *J8;                  // np x np
+    float *bfp;                  // np
+    float *x, *m;                // [Rp][np]
+    uint8_t *s8;                 // byte spins, Rp * np
+    int64_t n, np, R, Rp;
+    uint64_t seed;
+};
+hipError_t launch_csr_to_i8_batch(const SlotInitTask *tasks, int32_t ntask, qpa_dtype coupling,
+                                  qpa_dtype index, int64_t max_np, hipStream_t st);
+hipError_t launch_slot_init_batch(const SlotInitTask *tasks, int32_t ntask, int64_t max_elems,
+                                  float sigma0, hipStream_t st);
 hipError_t launch_csr_to_bf16(const qpa_problem &p, int64_t np, const CanonScalars *sc,
                               uint16_t *Jb, hipStream_t st);
 
