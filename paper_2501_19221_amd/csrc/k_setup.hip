@@ -118,8 +118,8 @@ __global__ void __launch_bounds__(256) k_dense_sym(int64_t n, const TQ *__restri
 // Large instances reduce the per-row partials in two launches: k_canon_part gives each of
 // P workgroups a contiguous range of rows and writes (max |row|, max |J|, sum K as double,
 // sum K as int64) to parts[4 p ..]; k_canon_finalize then reduces those P values (both in
-// a fixed order, so the scalars are reproducible).
-constexpr int64_t CANON_ROWS_PER_PART = 65536;
+// a fixed order, so the scalars are reproducible); P = ceil(n / CANON_ROWS_PER_PART),
+// at most CANON_PARTS.
 
 __global__ void __launch_bounds__(1024) k_canon_part(int64_t n, int64_t rows,
                                                      const double *row_abs,
@@ -168,11 +168,10 @@ __global__ void __launch_bounds__(1024) k_canon_part(int64_t n, int64_t rows,
 
 // Single block: reduce the per-row partials (or, with `parts`, the P partials of
 // k_canon_part) into the scalars.
-__global__ void __launch_bounds__(1024) k_canon_finalize(int64_t n, const double *row_abs,
-                                                         const double *row_max,
-                                                         const double *row_k,
-                                                         const double *parts, int32_t is_int,
-                                                         CanonScalars *sc, CanonScalars *mirror) {
+__device__ __forceinline__ void canon_finalize_body(int64_t n, const double *row_abs,
+                                                    const double *row_max, const double *row_k,
+                                                    const double *parts, int32_t is_int,
+                                                    CanonScalars *sc, CanonScalars *mirror) {
     __shared__ double s_abs[1024 / WAVE], s_max[1024 / WAVE], s_k[1024 / WAVE];
     __shared__ int64_t s_ki[1024 / WAVE];
     double a = 0.0, mx = 0.0, kf = 0.0;
@@ -241,6 +240,19 @@ __global__ void __launch_bounds__(1024) k_canon_finalize(int64_t n, const double
             *mirror = c;
         }
     }
+}
+
+__global__ void __launch_bounds__(1024) k_canon_finalize(int64_t n, const double *row_abs,
+                                                         const double *row_max,
+                                                         const double *row_k,
+                                                         const double *parts, int32_t is_int,
+                                                         CanonScalars *sc, CanonScalars *mirror) {
+    canon_finalize_body(n, row_abs, row_max, row_k, parts, is_int, sc, mirror);
+}
+
+__global__ void __launch_bounds__(1024) k_canon_finalize_batch(const CanonTask *__restrict__ tasks) {
+    const CanonTask &t = tasks[blockIdx.y];
+    canon_finalize_body(t.n, t.row_abs, t.row_max, t.row_k, nullptr, t.is_int, t.sc, t.mirror);
 }
 
 template <typename TQ>
@@ -333,20 +345,19 @@ __global__ void __launch_bounds__(256) k_csr_rows(int64_t n, int64_t nnz,
 // lanes (the symmetric-partner searches run in parallel).  Outputs as k_csr_rows; every
 // sum is an exact integer, so the order of the reduction does not matter.
 template <typename TW, typename TI>
-__global__ void __launch_bounds__(256) k_csr_rows_wave(int64_t n, int64_t nnz,
-                                                       const int32_t *__restrict__ rp,
-                                                       const TI *__restrict__ col,
-                                                       const TW *__restrict__ w, const void *lin,
-                                                       int32_t lin_dt, int32_t is_qubo,
-                                                       float *__restrict__ b_f32,
-                                                       int64_t *__restrict__ b_i64,
-                                                       double *__restrict__ b_f64,
-                                                       double *__restrict__ row_abs,
-                                                       double *__restrict__ row_max,
-                                                       double *__restrict__ row_k,
-                                                       CanonScalars *sc) {
+__device__ __forceinline__ void csr_rows_wave_body(int64_t i, int64_t n, int64_t nnz,
+                                                   const int32_t *__restrict__ rp,
+                                                   const TI *__restrict__ col,
+                                                   const TW *__restrict__ w, const void *lin,
+                                                   int32_t lin_dt, int32_t is_qubo,
+                                                   float *__restrict__ b_f32,
+                                                   int64_t *__restrict__ b_i64,
+                                                   double *__restrict__ b_f64,
+                                                   double *__restrict__ row_abs,
+                                                   double *__restrict__ row_max,
+                                                   double *__restrict__ row_k,
+                                                   CanonScalars *sc) {
     const int lane = threadIdx.x % WAVE;
-    const int64_t i = (int64_t)blockIdx.x * (256 / WAVE) + threadIdx.x / WAVE;
     if (i >= n) return;                        // uniform per wave
     int32_t flags = 0;
     const int64_t k0 = rp[i], k1 = rp[i + 1];
@@ -406,6 +417,39 @@ __global__ void __launch_bounds__(256) k_csr_rows_wave(int64_t n, int64_t nnz,
     if (row_max) row_max[i] = (double)smax;
     row_k[i] = is_qubo ? ((double)sum + (double)diag + 2.0 * c) : 0.0;
     if (flags) atomicOr(&sc->flags, flags);
+}
+
+template <typename TW, typename TI>
+__global__ void __launch_bounds__(256) k_csr_rows_wave(int64_t n, int64_t nnz,
+                                                       const int32_t *__restrict__ rp,
+                                                       const TI *__restrict__ col,
+                                                       const TW *__restrict__ w, const void *lin,
+                                                       int32_t lin_dt, int32_t is_qubo,
+                                                       float *__restrict__ b_f32,
+                                                       int64_t *__restrict__ b_i64,
+                                                       double *__restrict__ b_f64,
+                                                       double *__restrict__ row_abs,
+                                                       double *__restrict__ row_max,
+                                                       double *__restrict__ row_k,
+                                                       CanonScalars *sc) {
+    csr_rows_wave_body<TW, TI>((int64_t)blockIdx.x * (256 / WAVE) + threadIdx.x / WAVE, n, nnz,
+                               rp, col, w, lin, lin_dt, is_qubo, b_f32, b_i64, b_f64, row_abs,
+                               row_max, row_k, sc);
+}
+
+// Batched canonicalisation (instance blockIdx.y of the table): clear the scalars, the
+// row pass, the finalisation; each as the single-instance kernels do it.
+__global__ void __launch_bounds__(64) k_canon_zero_batch(const CanonTask *__restrict__ tasks) {
+    if (threadIdx.x == 0) *tasks[blockIdx.y].sc = CanonScalars{};
+}
+
+template <typename TW, typename TI>
+__global__ void __launch_bounds__(256) k_csr_rows_wave_batch(const CanonTask *__restrict__ tasks) {
+    const CanonTask &t = tasks[blockIdx.y];
+    csr_rows_wave_body<TW, TI>((int64_t)blockIdx.x * (256 / WAVE) + threadIdx.x / WAVE, t.n,
+                               t.nnz, t.rp, static_cast<const TI *>(t.col),
+                               static_cast<const TW *>(t.w), t.lin, t.lin_dt, t.is_qubo,
+                               t.b_f32, t.b_i64, t.b_f64, t.row_abs, t.row_max, t.row_k, t.sc);
 }
 
 // ------------------------------------------------------------------ initial state
@@ -945,6 +989,34 @@ hipError_t launch_init_state(int64_t n, int64_t R, uint64_t seed, float sigma0, 
     k_init_state<<<grid1(Rpad * npad, 256), 256, 0, st>>>(n, R, seed, sigma0, x, m, ld_r, ld_i,
                                                           Rpad, npad);
     return hipGetLastError();
+}
+
+hipError_t launch_canon_batch(const CanonTask *tasks, int32_t ntask, qpa_dtype coupling,
+                              qpa_dtype index, int64_t max_n, hipStream_t st) {
+    const int64_t gx = (max_n + 3) / 4;
+    if (gx < 1 || gx > INT32_MAX) return hipErrorInvalidValue;
+    auto run = [&](auto wtag, auto itag) {
+        using TW = decltype(wtag);
+        using TI = decltype(itag);
+        for (int32_t c0 = 0; c0 < ntask; c0 += 65535) {
+            const unsigned rows = (unsigned)std::min(65535, ntask - c0);
+            k_canon_zero_batch<<<dim3(1, rows), 64, 0, st>>>(tasks + c0);
+            k_csr_rows_wave_batch<TW, TI><<<dim3((unsigned)gx, rows), 256, 0, st>>>(tasks + c0);
+            k_canon_finalize_batch<<<dim3(1, rows), 1024, 0, st>>>(tasks + c0);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    auto byw = [&](auto itag) -> hipError_t {
+        switch (coupling) {
+            case QPA_I8: return run((int8_t)0, itag);
+            case QPA_I16: return run((int16_t)0, itag);
+            case QPA_I32: return run((int32_t)0, itag);
+            default: return hipErrorInvalidValue;
+        }
+    };
+    return index == QPA_I16 ? byw((int16_t)0) : byw((int32_t)0);
 }
 
 hipError_t launch_slot_init_batch(const SlotInitTask *tasks, int32_t ntask, int64_t max_elems,

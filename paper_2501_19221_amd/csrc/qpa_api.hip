@@ -719,7 +719,7 @@ struct BatchPlan {
     std::vector<Plan> inst;          // per-instance single-solve plans (canonical buffers)
     std::vector<size_t> base;        // byte offset of each instance's region
     std::vector<DenseSlot> dense;
-    size_t o_tasks, o_tiles, o_score, o_scall, o_slot, o_counter, o_lam, total;
+    size_t o_tasks, o_tiles, o_score, o_scall, o_slot, o_canon, o_counter, o_lam, total;
     int32_t ntasks, ntiles_max, max_n;
     int32_t inst_tiles_max;   // most tiles of one dense candidate
 };
@@ -834,6 +834,7 @@ qpa_status make_batch_plan(qpa_ctx *ctx, int32_t count, const qpa_problem *probs
     bp.o_score = take(sizeof(ScoreTask) * (size_t)std::max(count, 1));
     bp.o_scall = take(sizeof(CanonScalars) * (size_t)std::max(count, 1));
     bp.o_slot = take(sizeof(SlotInitTask) * (size_t)std::max(count, 1));
+    bp.o_canon = take(sizeof(CanonTask) * (size_t)std::max(count, 1));
     bp.o_counter = take(sizeof(int32_t));
     bp.o_lam = take(sizeof(float) * (size_t)std::max<int32_t>(a.steps, 1));
     bp.total = off;
@@ -1289,15 +1290,75 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
     // scalars into one array, then one read-back of that array
     std::vector<CanonScalars> hsc(count);
     CanonScalars *scall = reinterpret_cast<CanonScalars *>(ws + bp.o_scall);
+    // integer instances on the wave-per-row pass with a one-launch finalisation are
+    // canonicalised by batched launches from a table (once per coupling/index type pair)
+    struct CanonGroup {
+        qpa_dtype w, i;
+        int32_t first, count;
+        int64_t max_n;
+    };
+    std::vector<CanonTask> ctasks;
+    std::vector<CanonGroup> cgroups;
+    std::vector<char> canon_b(count, 0);
+    for (qpa_dtype wt : {QPA_I8, QPA_I16, QPA_I32})
+        for (qpa_dtype xt : {QPA_I16, QPA_I32}) {
+            CanonGroup g{wt, xt, (int32_t)ctasks.size(), 0, 0};
+            for (int32_t k = 0; k < count; ++k) {
+                const qpa_problem &p = problems[k];
+                if (p.coupling_dtype != wt || p.index_dtype != xt || !csr_rows_by_wave(p) ||
+                    p.n > CANON_ROWS_PER_PART)
+                    continue;
+                const Plan &pl = bp.inst[k];
+                char *iw = ws + bp.base[k];
+                CanonTask t{};
+                t.rp = p.row_ptr;
+                t.col = p.col;
+                t.w = p.weights;
+                t.lin = p.linear;
+                t.lin_dt = p.linear_dtype;
+                t.is_qubo = p.kind == QPA_KIND_QUBO ? 1 : 0;
+                t.is_int = dtype_is_int(p.coupling_dtype) &&
+                           (p.linear == nullptr || dtype_is_int(p.linear_dtype));
+                t.n = p.n;
+                t.nnz = p.nnz;
+                t.b_f32 = at<float>(iw, pl.o_bf);
+                t.b_i64 = at<int64_t>(iw, pl.o_bi);
+                t.b_f64 = at<double>(iw, pl.o_bd);
+                t.row_abs = at<double>(iw, pl.o_rabs);
+                t.row_max = at<double>(iw, pl.o_rmax);
+                t.row_k = at<double>(iw, pl.o_rk);
+                t.sc = at<CanonScalars>(iw, pl.o_sc);
+                t.mirror = scall + k;
+                ctasks.push_back(t);
+                canon_b[k] = 1;
+                ++g.count;
+                g.max_n = std::max(g.max_n, p.n);
+            }
+            if (g.count) cgroups.push_back(g);
+        }
+    // one pinned block: the scalars' read-back, then the table
     CanonScalars *pinned = nullptr;
-    QPA_HIP(hipHostMalloc((void **)&pinned, sizeof(CanonScalars) * (size_t)count));
+    const size_t cbytes = sizeof(CanonTask) * ctasks.size();
+    QPA_HIP(hipHostMalloc((void **)&pinned, sizeof(CanonScalars) * (size_t)count + cbytes));
+    CanonTask *ptab = reinterpret_cast<CanonTask *>(pinned + count);
+    std::copy(ctasks.begin(), ctasks.end(), ptab);
     s = aux_fork(ctx, st);
     if (s != QPA_OK) {
         (void)hipHostFree(pinned);
         return s;
     }
     AuxGuard g0{ctx, st};
-    s = aux_issue(ctx, count, "canonicalisation", [&](int32_t k, hipStream_t ak) {
+    if (!ctasks.empty()) {
+        const CanonTask *dt = reinterpret_cast<const CanonTask *>(ws + bp.o_canon);
+        hipError_t e = hipMemcpyAsync(ws + bp.o_canon, ptab, cbytes, hipMemcpyHostToDevice, st);
+        for (const CanonGroup &g : cgroups)
+            if (e == hipSuccess)
+                e = launch_canon_batch(dt + g.first, g.count, g.w, g.i, g.max_n, st);
+        if (e != hipSuccess)
+            s = fail(ctx, QPA_E_DEVICE, "canonicalisation: %s", hipGetErrorString(e));
+    }
+    if (s == QPA_OK) s = aux_issue(ctx, count, "canonicalisation", [&](int32_t k, hipStream_t ak) {
+        if (canon_b[k]) return hipSuccess;
         const Plan &pl = bp.inst[k];
         void *iw = ws + bp.base[k];
         return launch_canon_csr(problems[k], at<float>(iw, pl.o_bf), at<int64_t>(iw, pl.o_bi),

@@ -52,12 +52,34 @@ inline bool dtype_is_int(int32_t dt) { return dt == QPA_I8 || dt == QPA_I16 || d
 // parts: scratch of 4 * CANON_PARTS doubles for the two-launch reduction of large
 // instances (nullptr: one launch whatever n).
 constexpr int64_t CANON_PARTS = 1024;
+constexpr int64_t CANON_ROWS_PER_PART = 65536;   // one finalising launch up to this n
 hipError_t launch_canon_dense(const qpa_problem &p, float *J_f32, uint16_t *Jb, int64_t npad,
                               float *b_f32, int64_t *b_i64, double *b_f64, double *row_abs,
                               double *row_max, double *row_diag, double *parts,
                               CanonScalars *sc, hipStream_t st);
 
 // Canonicalisation of a CSR problem: b_f32 / b_i64 / b_f64, validation, scalars.
+// Batched canonicalisation of integer CSR instances taking the wave-per-row pass with a
+// single-stage finalisation (n <= CANON_ROWS_PER_PART): instance y of a device table in
+// grid row y; the scalars are cleared, the rows processed and the scalars finalised (and
+// mirrored) exactly as launch_canon_csr does.  All tasks of a launch share the coupling
+// and index types; max_n bounds their n.
+struct CanonTask {
+    const int32_t *rp;
+    const void *col;
+    const void *w;
+    const void *lin;
+    int32_t lin_dt, is_qubo, is_int, pad_;
+    int64_t n, nnz;
+    float *b_f32;
+    int64_t *b_i64;
+    double *b_f64;
+    double *row_abs, *row_max, *row_k;
+    CanonScalars *sc, *mirror;
+};
+hipError_t launch_canon_batch(const CanonTask *tasks, int32_t ntask, qpa_dtype coupling,
+                              qpa_dtype index, int64_t max_n, hipStream_t st);
+
 // mirror (optional): a second copy of the finished scalars (one slot of a batch's array).
 hipError_t launch_canon_csr(const qpa_problem &p, float *b_f32, int64_t *b_i64, double *b_f64,
                             double *row_abs, double *row_max, double *row_k, double *parts,

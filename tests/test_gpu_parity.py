@@ -522,10 +522,12 @@ def test_batch_uneven_instances_bit_exact(q, eng, path):
 
 
 def test_batch_reports_the_failing_instance(q, eng):
-    # An asymmetric instance in the middle of a batch is named in the error; the context
-    # then solves a valid batch to the oracle's bits.
+    # An asymmetric instance in the middle of a batch is named in the error (it has 16 or
+    # more entries per row, the batched canonicalisation's case); the context then solves
+    # a valid batch to the oracle's bits.
     rng = np.random.default_rng(5)
-    insts = [gen.er_qubo(int(n), 0.1, 100, rng) for n in (60, 90, 130, 70, 110, 80, 50)]
+    insts = [gen.er_qubo(int(n), 0.1, 100, rng) for n in (60, 90, 130, 70, 300, 80, 50)]
+    assert insts[4].csr.col.size >= 16 * insts[4].n
     bad = insts[4]
     k0 = int(np.flatnonzero(bad.csr.col[bad.csr.rp[0]:bad.csr.rp[1]] != 0)[0])
     w = bad.csr.w.copy()
