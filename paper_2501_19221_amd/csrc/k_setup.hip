@@ -774,17 +774,82 @@ __global__ void __launch_bounds__(256) k_energy_csr_wave(int64_t n,
     energy_csr_wave_body<TW, TI>(n, rp, col, w, b_i64, s, R, partial, blockIdx.x, blockIdx.y);
 }
 
-// Batched: block x of instance y covers partial block x % nblk and replica group
-// x / nblk (blocks past the instance's nblk * ceil(R / ER) return at once).
-template <typename TW, typename TI>
-__global__ void __launch_bounds__(256) k_energy_csr_wave_batch(const ScoreTask *__restrict__ tasks) {
+// Batched energies of integer CSR instances (n <= EBITS_MAX_N) from bit-packed spins:
+// the same partial sums as the wave-per-row kernel (each pair once, exact integers),
+// over blocks of EB_ROWS rows.  k_spin_words_batch writes each replica's sign bits once
+// (bit i % 64 of word i / 64 set <=> x_i < 0, i.e. spin -1); an energy block stages the
+// words of 64 replicas in LDS as words[i / 64][replica], a wave takes a row with lane =
+// replica and walks the row's entries past the diagonal in pieces of 64 (loaded by the
+// lanes, then broadcast one at a time), so that no spin is fetched from memory per entry.
+__global__ void __launch_bounds__(256) k_spin_words_batch(const ScoreTask *__restrict__ tasks) {
     const ScoreTask &t = tasks[blockIdx.y];
-    const int64_t gy = (t.R + ER - 1) / ER;
-    if ((int64_t)blockIdx.x >= t.nblk * gy) return;
-    energy_csr_wave_body<TW, TI>(t.n, t.rp, static_cast<const TI *>(t.col),
-                                 static_cast<const TW *>(t.w), t.b_i64, t.spins, t.R,
-                                 t.partial, (int64_t)blockIdx.x % t.nblk,
-                                 (int64_t)blockIdx.x / t.nblk);
+    const int64_t nw = (t.n + 63) / 64, total = t.R * nw;
+    const int lane = threadIdx.x & 63;
+    const int64_t step = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t p = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; p < total;
+         p += step) {
+        const int64_t r = p / nw, i = 64 * (p - r * nw) + lane;
+        const uint64_t word = __ballot(i < t.n && t.x[r * t.ld_r + i] < 0.0f);
+        if (lane == 0) t.words[p] = word;
+    }
+}
+
+template <typename TW, typename TI>
+__global__ void __launch_bounds__(256) k_energy_bits_batch(const ScoreTask *__restrict__ tasks) {
+    __shared__ uint64_t words[EBITS_MAX_N / 64][64];
+    __shared__ int64_t red[4][64];
+    const ScoreTask &t = tasks[blockIdx.y];
+    const int64_t n = t.n, R = t.R, nw = (n + 63) / 64;
+    const int64_t i0 = (int64_t)blockIdx.x * EB_ROWS;
+    if (i0 >= n) return;                          // uniform per block
+    const TI *__restrict__ col = static_cast<const TI *>(t.col);
+    const TW *__restrict__ w = static_cast<const TW *>(t.w);
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int64_t r0 = 0; r0 < R; r0 += 64) {
+        __syncthreads();                          // the previous group is no longer read
+        for (int64_t q = threadIdx.x; q < 64 * nw; q += blockDim.x) {
+            const int64_t rr = q / nw, wd = q - rr * nw;
+            words[wd][rr] = r0 + rr < R ? t.words[(r0 + rr) * nw + wd] : 0ull;
+        }
+        __syncthreads();
+        int64_t acc = 0;
+        for (int e = wv; e < EB_ROWS; e += 4) {
+            const int64_t i = i0 + e;
+            if (i >= n) break;
+            // first entry past the diagonal (the columns of a row are sorted)
+            int64_t lo = t.rp[i], hi = t.rp[i + 1];
+            const int64_t k1 = hi;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if ((int64_t)col[mid] <= i) lo = mid + 1;
+                else hi = mid;
+            }
+            int32_t d = 0;
+            for (int64_t kb = lo; kb < k1; kb += 64) {
+                const int cnt = (int)(k1 - kb < 64 ? k1 - kb : 64);
+                int32_t cj = 0, cw = 0;
+                if (lane < cnt) {
+                    cj = (int32_t)col[kb + lane];
+                    cw = (int32_t)w[kb + lane];
+                }
+                for (int c = 0; c < cnt; ++c) {
+                    const int32_t j = __builtin_amdgcn_readlane(cj, c);
+                    const int32_t wj = __builtin_amdgcn_readlane(cw, c);
+                    d += ((words[j >> 6][lane] >> (j & 63)) & 1ull) ? -wj : wj;
+                }
+            }
+            const int64_t v = (int64_t)d + t.b_i64[i];
+            acc += ((words[i >> 6][lane] >> (i & 63)) & 1ull) ? -v : v;
+        }
+        red[wv][lane] = acc;
+        __syncthreads();
+        if (threadIdx.x < 64 && r0 + (int64_t)threadIdx.x < R) {
+            const int q = threadIdx.x;
+            t.partial[(int64_t)blockIdx.x * R + r0 + q] =
+                (double)(red[0][q] + red[1][q] + red[2][q] + red[3][q]);
+        }
+    }
 }
 
 // energy[r] = sum over blocks of partial[b][r] (fixed order), then the QUBO constant.
@@ -1138,17 +1203,21 @@ hipError_t launch_export_spins_batch(const ScoreTask *tasks, int32_t ntask, int6
     return hipSuccess;
 }
 
-hipError_t launch_energy_csr_wave_batch(const ScoreTask *tasks, int32_t ntask,
-                                        qpa_dtype coupling, qpa_dtype index, int64_t max_nblk,
-                                        int64_t max_R, hipStream_t st) {
-    const int64_t max_blocks = max_nblk * ((max_R + ER - 1) / ER);
-    if (max_blocks < 1 || max_blocks > INT32_MAX) return hipErrorInvalidValue;
+int64_t energy_bits_blocks(int64_t n) { return (n + EB_ROWS - 1) / EB_ROWS; }
+
+hipError_t launch_energy_bits_batch(const ScoreTask *tasks, int32_t ntask, qpa_dtype coupling,
+                                    qpa_dtype index, int64_t max_n, int64_t max_words,
+                                    hipStream_t st) {
+    if (max_n < 1 || max_n > EBITS_MAX_N) return hipErrorInvalidValue;
     auto run = [&](auto wtag, auto itag) {
         using TW = decltype(wtag);
         using TI = decltype(itag);
         for (int32_t c0 = 0; c0 < ntask; c0 += SCORE_ROWS) {
-            const dim3 g((unsigned)max_blocks, (unsigned)std::min(SCORE_ROWS, ntask - c0));
-            k_energy_csr_wave_batch<TW, TI><<<g, 256, 0, st>>>(tasks + c0);
+            const unsigned rows = (unsigned)std::min(SCORE_ROWS, ntask - c0);
+            k_spin_words_batch<<<dim3(grid1(max_words * 64, 256, 1024), rows), 256, 0, st>>>(
+                tasks + c0);
+            k_energy_bits_batch<TW, TI>
+                <<<dim3((unsigned)energy_bits_blocks(max_n), rows), 256, 0, st>>>(tasks + c0);
             const hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }

@@ -1532,12 +1532,12 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
         }
     }
 
-    // densified integer instances on the wave-per-row energy kernel are scored by batched
-    // launches (one per kind; the energy kernel once per coupling/index type pair)
+    // densified integer instances (n <= EBITS_MAX_N) are scored by batched launches (one
+    // per kind; the energy kernels once per coupling/index type pair)
     struct ScoreGroup {
         qpa_dtype w, i;
         int32_t first, count;
-        int64_t max_nblk, max_R;
+        int64_t max_n, max_words;
     };
     std::vector<ScoreTask> stasks;
     std::vector<ScoreGroup> sgroups;
@@ -1549,8 +1549,10 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
             for (int32_t k = 0; k < count; ++k) {
                 const qpa_problem &p = problems[k];
                 const Plan &pl = bp.inst[k];
-                if (!is_dense[k] || p.coupling_dtype != wt || p.index_dtype != it ||
-                    !csr_rows_by_wave(p) || energy_partial_blocks(p) > pl.eblk)
+                const bool is_int = dtype_is_int(p.coupling_dtype) &&
+                                    (p.linear == nullptr || dtype_is_int(p.linear_dtype));
+                if (!is_dense[k] || p.coupling_dtype != wt || p.index_dtype != it || !is_int ||
+                    p.n > EBITS_MAX_N || energy_bits_blocks(p.n) > pl.eblk)
                     continue;
                 const DenseSlot &ds = bp.dense[k];
                 char *iw = ws + bp.base[k];
@@ -1560,7 +1562,7 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
                 t.ld_r = ds.np;
                 t.n = p.n;
                 t.R = pl.R;
-                t.nblk = energy_partial_blocks(p);
+                t.nblk = energy_bits_blocks(p.n);
                 t.rp = p.row_ptr;
                 t.col = p.col;
                 t.w = p.weights;
@@ -1571,12 +1573,13 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
                 t.e_i64 = o.energy_i64 ? o.energy_i64 : at<int64_t>(iw, pl.o_ei);
                 t.e_f64 = o.energy;
                 t.best = o.best;
+                t.words = reinterpret_cast<uint64_t *>(ws + ds.o_s1);   // free after the steps
                 t.is_qubo = p.kind == QPA_KIND_QUBO ? 1 : 0;
                 stasks.push_back(t);
                 batched[k] = 1;
                 ++g.count;
-                g.max_nblk = std::max(g.max_nblk, t.nblk);
-                g.max_R = std::max(g.max_R, t.R);
+                g.max_n = std::max(g.max_n, t.n);
+                g.max_words = std::max(g.max_words, t.R * ((t.n + 63) / 64));
                 score_elems = std::max(score_elems, t.R * t.n);
                 score_R = std::max(score_R, t.R);
             }
@@ -1699,8 +1702,8 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
         const int32_t ns = (int32_t)stasks.size();
         QPA_HIP(launch_export_spins_batch(dst, ns, score_elems, st));
         for (const ScoreGroup &g : sgroups)
-            QPA_HIP(launch_energy_csr_wave_batch(dst + g.first, g.count, g.w, g.i, g.max_nblk,
-                                                 g.max_R, st));
+            QPA_HIP(launch_energy_bits_batch(dst + g.first, g.count, g.w, g.i, g.max_n,
+                                             g.max_words, st));
         QPA_HIP(launch_finalize_argmin_batch(dst, ns, score_R, st));
     }
     for (int32_t k = 0; k < count; ++k) {

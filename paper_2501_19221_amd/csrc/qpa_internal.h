@@ -118,14 +118,14 @@ hipError_t launch_energy(const qpa_problem &p, const int64_t *b_i64, const doubl
 hipError_t launch_argmin(int64_t R, const int64_t *e_i64, const double *e_f64, int32_t *best,
                          hipStream_t st);
 
-// Batched scoring of integer CSR instances on the wave-per-row energy kernel: one launch
-// per kind for all instances of a table (device memory), each instance computed exactly
-// as by launch_export_spins + launch_energy + launch_argmin.
+// Batched scoring of integer CSR instances: one launch per kind for all instances of a
+// table (device memory), with the results of launch_export_spins + launch_energy +
+// launch_argmin (the energies are exact integers, whatever the order of their sums).
 struct ScoreTask {
     const float *x;              // final state, element (r, i) at x[r * ld_r + i]
     int64_t ld_r;
     int64_t n, R;
-    int64_t nblk;                // energy partial blocks, energy_partial_blocks(problem)
+    int64_t nblk;                // energy partial blocks, energy_bits_blocks(n)
     const int32_t *rp;           // the instance's CSR (index and weight types of the launch)
     const void *col;
     const void *w;
@@ -136,15 +136,21 @@ struct ScoreTask {
     int64_t *e_i64;              // R
     double *e_f64;               // R
     int32_t *best;               // 1
+    uint64_t *words;             // scratch: R * ceil(n / 64) sign words
     int32_t is_qubo;
 };
+// Energies of a batched scoring table: sign words, then partial sums over blocks of
+// EB_ROWS rows (nblk of a task = energy_bits_blocks(n)); n <= EBITS_MAX_N.
+constexpr int EB_ROWS = 16;
+constexpr int64_t EBITS_MAX_N = 4096;
+int64_t energy_bits_blocks(int64_t n);
 hipError_t launch_export_spins_batch(const ScoreTask *tasks, int32_t ntask, int64_t max_elems,
                                      hipStream_t st);
-// All tasks of one launch share the coupling and index types; max_nblk and max_R bound
-// the table's nblk and R.
-hipError_t launch_energy_csr_wave_batch(const ScoreTask *tasks, int32_t ntask,
-                                        qpa_dtype coupling, qpa_dtype index, int64_t max_nblk,
-                                        int64_t max_R, hipStream_t st);
+// All tasks of one launch share the coupling and index types; max_n and max_words bound
+// the table's n and R * ceil(n / 64).
+hipError_t launch_energy_bits_batch(const ScoreTask *tasks, int32_t ntask, qpa_dtype coupling,
+                                    qpa_dtype index, int64_t max_n, int64_t max_words,
+                                    hipStream_t st);
 hipError_t launch_finalize_argmin_batch(const ScoreTask *tasks, int32_t ntask, int64_t max_R,
                                         hipStream_t st);
 
