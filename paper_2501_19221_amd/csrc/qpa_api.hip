@@ -707,6 +707,7 @@ qpa_status make_rel_plan(qpa_ctx *ctx, const qpa_problem &p, const qpa_params &a
 }
 
 constexpr int64_t BATCH_MAX_N = 4096;
+static_assert(BATCH_MAX_N <= EBITS_MAX_N, "every densified batch instance fits the batched energies");
 
 // Dense matrix-core buffers of a batch instance that may run as BF16 tiles.
 struct DenseSlot {

@@ -548,6 +548,31 @@ def test_batch_reports_the_failing_instance(q, eng):
         assert np.array_equal(host(out["x"]), x) and np.array_equal(host(out["m"]), m), k
 
 
+def test_batch_scoring_size_limits(q, eng):
+    # Dense-forced batch at the largest instance size of a batch (n = 4096, also the
+    # largest of the bit-packed batched energies: 64 sign words per replica in LDS) and a
+    # small one; R = 70 spans two replica groups.  A larger instance is refused.
+    rng = np.random.default_rng(21)
+    insts = [gen.er_qubo(4096, 0.01, 100, rng), gen.er_qubo(300, 0.1, 100, rng)]
+    R, T, eta, alpha, lam0 = 70, 4, 0.0002, 0.8, 200.0
+    p = _params(q, R, T, eta, alpha, lam0, seed=13, flags=q.QPA_BATCH_DENSE)
+    with pytest.raises(q.QpaError) as ei:
+        eng.solve_batch([q.Problem.from_instance(gen.er_qubo(4097, 0.01, 100, rng))], p)
+    assert ei.value.status == q.QPA_E_UNSUPPORTED, str(ei.value)
+    say("batch at the size limit, n=4096/300, R=70")
+    outs = eng.solve_batch([q.Problem.from_instance(i) for i in insts], p, want_state=True)
+    assert (q.qpa_batch_paths(eng.ctx, len(insts)) == q.QPA_PATH_BATCH_DENSE_I8).all()
+    lam = orc.lambda_linear(T, lam0)
+    for k, (inst, out) in enumerate(zip(insts, outs)):
+        x, m, canon = _oracle_instance(inst, R, T, lam, eta, alpha, seed=13 + k)
+        assert np.array_equal(host(out["x"]), x) and np.array_equal(host(out["m"]), m), k
+        s = np.where(x >= 0, 1, -1).astype(np.int8)
+        assert np.array_equal(host(out["spins"]), s), k
+        e = _energies_csr_int(canon, inst.kind, s)
+        assert np.array_equal(host(out["energy_i64"]), e), k
+        assert int(host(out["best"])[0]) == int(np.flatnonzero(e == e.min())[0]), k
+
+
 def test_er512_full_workload_sampled(q, eng):
     wl = WORKLOADS["er512"]
     say("er512 generation")
