@@ -207,6 +207,11 @@ qpa_status qpa_solve(qpa_ctx *ctx, const qpa_problem *problem, const qpa_params 
  *    sums, half the coupling bytes), and every PA step is one grouped matrix-core launch
  *    over the 128x128 tiles of all such instances (one per element type).  Integer
  *    instances give the same bits on every path.
+ * Set-up and scoring run on the context's auxiliary streams (ordered after `stream` and
+ * joined back into it before the call returns), the per-instance parts issued from up to
+ * four host threads of the call's own, the densified integer instances' parts as batched
+ * launches over descriptor tables.  The call synchronises `stream` up to three times
+ * (after the validation of every instance, and after each of two table uploads).
  * Errors name the offending instance in qpa_last_error(). */
 qpa_status qpa_workspace_size_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *problems,
                                     const qpa_params *params, size_t *bytes);
