@@ -357,9 +357,10 @@ def test_csr_float_weights_bit_exact(q, eng, streamed):
 def test_energy_entry_point(q, eng):
     import torch
     rng = np.random.default_rng(11)
-    for inst in [gen.dense_int_qubo(50, seed=3), gen.sk_ising(70, seed=2),
-                 gen.chimera_ising(3, seed=1)]:
-        R = 33
+    # R = 1100: the dense energies' replicas span three blocks of 512 (the last ragged)
+    for inst, R in [(gen.dense_int_qubo(50, seed=3), 33), (gen.sk_ising(70, seed=2), 33),
+                    (gen.chimera_ising(3, seed=1), 33), (gen.dense_int_qubo(40, seed=5), 1100),
+                    (gen.sk_ising(30, seed=6), 1100)]:
         s = (2 * rng.integers(0, 2, (R, inst.n)) - 1).astype(np.int8)
         prob = q.Problem.from_instance(inst)
         say("energy entry point %s n=%d" % (inst.kind, inst.n))
