@@ -70,6 +70,7 @@ def _load():
                                             _P, _F32, _F32, _P]),
             "orc_pa_step_rows_csr_i64": (None, [_I64, _P, _P, _P, _P, _P, _P, _I64, _P, _F32,
                                                 _F32, _F32, _P, _P, _P]),
+            "orc_pa_update_f32": (None, [_I64, _P, _F32, _F32, _F32, _P, _P]),
             "orc_bf16_scale_exponent": (ctypes.c_int32, [_I64, _P]),
             "orc_bf16_quantise": (None, [_I64, _P, ctypes.c_int32, _P]),
             "orc_relaxed_grad_dense_f64": (_F64, [_I64, _P, _P, _I64, _P, _P, _I64, _P, _F64,
@@ -272,6 +273,15 @@ def pa_step_rows_csr_int(rp, col, w, b, x, m, rows, lam_t, eta, alpha):
                                      _ptr(m), len(rows), _ptr(rows), lam_t, eta, alpha,
                                      _ptr(h), _ptr(xo), _ptr(mo))
     return h, xo, mo
+
+
+def pa_update(h, x, m, lam_t, eta, alpha):
+    """The PA update of App. B alone (momentum, position, clip), in place on FP32 x, m
+    from given fields h of the same shape: the update every step function applies."""
+    assert x.dtype == np.float32 and x.flags.c_contiguous and m.flags.c_contiguous
+    assert x.shape == m.shape == np.shape(h)
+    _load().orc_pa_update_f32(x.size, _ptr(_c(h, np.float32)), lam_t, eta, alpha, _ptr(x),
+                              _ptr(m))
 
 
 # ------------------------------------------------------------------------------------

@@ -275,6 +275,13 @@ static void pa_update_row(int64_t n, const float *h, float lam, float eta, float
     }
 }
 
+/* The update alone, for `count` (variable, replica) pairs given their fields h. */
+void orc_pa_update_f32(int64_t count, const float *h, float lam, float eta, float alpha,
+                       float *x, float *m)
+{
+    pa_update_row(count, h, lam, eta, alpha, x, m);
+}
+
 void orc_pa_steps_dense_i64(int64_t n, const int32_t *J, const int64_t *b, int64_t nrep,
                             float *x, float *m, int64_t t0, int64_t t1, const float *lam,
                             float eta, float alpha, float *h_out)

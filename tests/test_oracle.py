@@ -123,6 +123,112 @@ def test_csr_energy_equals_dense_energy(orc):
         assert orc.ising_energy_csr_int(c.rp, c.col, c.w, b, s) == orc.ising_energy_int(D, b, s)
 
 
+def _float_csr(n, p, seed, diag_zeros=False):
+    """Random symmetric float CSR couplings (rows in random entry order, some rows empty),
+    optionally with explicit zero-weight diagonal entries."""
+    rng = np.random.default_rng(seed)
+    D = np.triu(rng.normal(size=(n, n)) * (rng.random((n, n)) < p), 1)
+    D = D + D.T
+    if n > 3:
+        D[2, :] = D[:, 2] = 0.0                      # an empty row
+    rp, col, w = [0], [], []
+    for i in range(n):
+        js = list(np.flatnonzero(D[i]))
+        if diag_zeros and i % 2 == 0:
+            js.append(i)
+        rng.shuffle(js)
+        col += js
+        w += [0.0 if j == i else D[i, j] for j in js]
+        rp.append(len(col))
+    return (D, np.array(rp, np.int64), np.array(col, np.int32), np.array(w, np.float64))
+
+
+def test_float_csr_energy_toy_golden(orc):
+    """The SDK toy model of Sec. V.C stored as CSR: all 8 energies equal the hand-worked
+    values of the golden file."""
+    inst = gen.sdk_toy()
+    rp = np.array([0, 1, 3, 4], np.int64)
+    col = np.array([1, 0, 2, 1], np.int32)
+    w = np.array([-1.0, -1.0, 0.5, 0.5])
+    for s0, s1, s2, H in _rows("sdk_toy_energies.txt"):
+        s = np.array([int(s0), int(s1), int(s2)], np.int8)
+        assert orc.ising_energy_csr_float(rp, col, w, inst.lin, s) == float(H)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_float_csr_energy_by_enumeration(orc, seed):
+    """Eq. (2) on float CSR couplings, every state of n = 10: equals the dense FP64
+    energy of the same matrix, the matrix-form value (1/2) s^T (J s + 2 b) from a float64
+    matrix product, and every single flip changes it by -2 s_k (J s + b)_k.  Explicit
+    zero diagonal entries and empty rows change nothing."""
+    n = 10
+    D, rp, col, w = _float_csr(n, 0.5, seed, diag_zeros=True)
+    b = np.random.default_rng(seed + 10).normal(size=n)
+    states = _all_states(n)
+    E = np.array([orc.ising_energy_csr_float(rp, col, w, b, s) for s in states])
+    sf = states.astype(np.float64)
+    matrix_form = 0.5 * np.einsum("ki,ki->k", sf, sf @ D + 2.0 * b)
+    assert np.allclose(E, matrix_form, rtol=0, atol=1e-12 * np.abs(D).sum())
+    for s, e in zip(states[::37], E[::37]):
+        assert e == pytest.approx(orc.ising_energy_float(D, b, s), abs=1e-12)
+    index = {tuple(s): k for k, s in enumerate(states.tolist())}
+    for k in range(0, len(states), 53):
+        s = states[k]
+        f = D @ s.astype(np.float64) + b
+        for i in range(n):
+            t = s.copy()
+            t[i] = -t[i]
+            assert E[index[tuple(t.tolist())]] - E[k] == pytest.approx(-2 * s[i] * f[i],
+                                                                        abs=1e-11)
+
+
+def test_float_csr_energy_matches_dense_large(orc):
+    """Random float CSR couplings (n = 300): CSR and dense FP64 energies agree."""
+    n = 300
+    D, rp, col, w = _float_csr(n, 0.05, 7)
+    b = np.random.default_rng(8).normal(size=n)
+    rng = np.random.default_rng(9)
+    for _ in range(5):
+        s = (2 * rng.integers(0, 2, n) - 1).astype(np.int8)
+        assert orc.ising_energy_csr_float(rp, col, w, b, s) == pytest.approx(
+            orc.ising_energy_float(D, b, s), abs=1e-9)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_qubo_to_ising_csr_app_a_identity(orc, seed):
+    """App. A for a CSR QUBO with stored diagonal entries, an empty row and a row holding
+    only its diagonal: 2 E(x) = H(s) + K for every x of n = 9, E from the dense QUBO form
+    x^T Q x + c^T x, H from the returned CSR Ising couplings; the output equals the dense
+    canonicalisation of the same matrix."""
+    rng = np.random.default_rng(seed)
+    n = 9
+    Q = np.triu(rng.integers(-7, 8, (n, n)) * (rng.random((n, n)) < 0.6), 0)
+    Q = Q + np.triu(Q, 1).T
+    Q[3, :] = Q[:, 3] = 0                              # empty row
+    Q[5, :] = Q[:, 5] = 0
+    Q[5, 5] = 4                                        # a row with only its diagonal
+    assert np.count_nonzero(np.diag(Q)) >= 3          # diagonal entries are stored
+    c = rng.integers(-5, 6, n)
+    rp, col, w = [0], [], []
+    for i in range(n):
+        js = list(np.flatnonzero(Q[i]))
+        rng.shuffle(js)
+        col += js
+        w += [int(Q[i, j]) for j in js]
+        rp.append(len(col))
+    rp2, col2, w2, b2, K = orc.qubo_to_ising_csr_int(np.array(rp), np.array(col, np.int32),
+                                                      np.array(w, np.int32), c)
+    assert np.all(col2 != np.repeat(np.arange(n), np.diff(rp2)))    # diagonal removed
+    Jd, bd, Kd = orc.qubo_to_ising_int(Q.astype(np.int32), c)
+    assert K == Kd and np.array_equal(b2, bd)
+    assert np.array_equal(gen.CSR(n, rp2, col2, w2).to_dense(np.int64), Jd.astype(np.int64))
+    for s in _all_states(n):
+        x = ((s + 1) // 2).astype(np.int8)
+        E = orc.qubo_energy_int(Q.astype(np.int32), c, x)
+        H = orc.ising_energy_csr_int(rp2, col2, w2, b2, s)
+        assert 2 * E == H + K
+
+
 def test_matrix_form_energy_from_fields(orc):
     """App. C matrix form: H(s) = (1/2) s^T (f + b) with f = J s + b the PA field."""
     inst = gen.dense_int_ising(n=30, seed=3)
@@ -206,6 +312,17 @@ def test_two_spin_hand_worked_steps(orc):
         t = int(step)
         h = orc.pa_steps_dense_int(J, b, x, m, t, t + 1, lam, 0.125, 0.5, want_h=True)
         assert h[0].tolist() == [float(h0), float(h1)]
+        assert m[0].tolist() == [float(m0), float(m1)]
+        assert x[0].tolist() == [float(x0), float(x1)]
+
+
+def test_update_alone_hand_worked(orc):
+    """The update primitive on the hand-worked two-spin fields reproduces both steps of
+    the golden file."""
+    x = np.array([[0.25, -0.5]], np.float32)
+    m = np.zeros_like(x)
+    for step, h0, h1, m0, m1, x0, x1 in _rows("pa_two_spin.txt"):
+        orc.pa_update(np.array([[float(h0), float(h1)]], np.float32), x, m, 0.5, 0.125, 0.5)
         assert m[0].tolist() == [float(m0), float(m1)]
         assert x[0].tolist() == [float(x0), float(x1)]
 
