@@ -408,6 +408,27 @@ qpa_status qpa_autotune(qpa_ctx *ctx, const qpa_problem *problem, const qpa_para
 qpa_status qpa_tune_set(qpa_ctx *ctx, const qpa_problem *problem, const qpa_params *params,
                         int32_t choice);
 
+/* Allocation-free solve, for callers that cannot allocate memory (tight serving loops,
+ * harnesses that forbid hipMalloc): the same solve as qpa_solve -- same kernels, same
+ * results bit for bit -- with the workspace taken from a device buffer the library owns
+ * instead of a caller argument.  The buffer is a static device array of
+ * QPA_NOALLOC_WORKSPACE_BYTES; every device the library is loaded on holds its own copy
+ * until the process ends.  The call allocates nothing (no device, pinned or managed
+ * memory; no HIP event, stream or graph): the schedule staging buffer it needs is
+ * reserved by qpa_create.
+ *  Limits: problems whose qpa_workspace_size() exceeds QPA_NOALLOC_WORKSPACE_BYTES fail
+ *  with QPA_E_WORKSPACE; steps > QPA_NOALLOC_MAX_STEPS and QPA_SOLVE_GRAPH (capturing a
+ *  graph allocates) fail with QPA_E_UNSUPPORTED.  Profiling spans are not recorded.
+ *  Sharing: all calls on one device -- from any context -- use the same buffer, which
+ *  keeps the last call's contents (the solve clears what it needs).  Calls that overlap
+ *  in time on one device race on it: issue them from one host thread on one stream, or
+ *  order them by synchronisation.  Like qpa_solve, the call synchronises `stream` once
+ *  to report invalid input, so it cannot be recorded into a graph. */
+#define QPA_NOALLOC_WORKSPACE_BYTES ((size_t)64 << 20)
+#define QPA_NOALLOC_MAX_STEPS 65536
+qpa_status qpa_solve_noalloc(qpa_ctx *ctx, const qpa_problem *problem, const qpa_params *params,
+                             void *stream, const qpa_outputs *out);
+
 /* Library version string. */
 const char *qpa_version(void);
 

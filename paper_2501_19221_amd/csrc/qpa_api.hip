@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <string>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -21,6 +22,7 @@ struct qpa_ctx {
     qpa::CanonScalars *host_sc = nullptr;   // pinned
     float *host_lam = nullptr;              // pinned schedule staging
     size_t host_lam_cap = 0;
+    void *noalloc_ws = nullptr;             // device address of this device's static workspace
     // step-kernel timing (qpa_profile_*)
     bool prof = false;
     struct Span {
@@ -41,7 +43,16 @@ struct qpa_ctx {
     std::vector<Graph> graphs;              // most recently used last
     // sparse kernel choices found by qpa_autotune: shape key -> 0 (streamed kernel) or
     // the resident kernel's replica group
-    std::vector<std::pair<std::vector<uint8_t>, int32_t>> tuned;
+    struct TuneKey {
+        int64_t n, nnz;
+        int32_t kind, coupling_dtype, index_dtype, replicas;
+        bool operator==(const TuneKey &o) const {
+            return n == o.n && nnz == o.nnz && kind == o.kind &&
+                   coupling_dtype == o.coupling_dtype && index_dtype == o.index_dtype &&
+                   replicas == o.replicas;
+        }
+    };
+    std::vector<std::pair<TuneKey, int32_t>> tuned;
     // streams of default priority for the independent per-instance work of a batch, and
     // the events that order them after and join them back into the caller's stream
     std::vector<hipStream_t> aux;
@@ -600,16 +611,10 @@ qpa_status score(qpa_ctx *ctx, const qpa_problem &p, const Plan &pl, void *ws,
     return QPA_OK;
 }
 
-// Key of a sparse instance's shape for the tuned-choice table.
-std::vector<uint8_t> tune_key(const qpa_problem &p, const qpa_params &a) {
-    std::vector<uint8_t> k;
-    key_add(k, p.n);
-    key_add(k, p.nnz);
-    key_add(k, p.kind);
-    key_add(k, p.coupling_dtype);
-    key_add(k, p.index_dtype);
-    key_add(k, a.replicas);
-    return k;
+// Key of a sparse instance's shape for the tuned-choice table (no allocation: the
+// allocation-free solve looks it up too).
+qpa_ctx::TuneKey tune_key(const qpa_problem &p, const qpa_params &a) {
+    return qpa_ctx::TuneKey{p.n, p.nnz, p.kind, p.coupling_dtype, p.index_dtype, a.replicas};
 }
 
 constexpr int32_t TUNE_BINNED = QPA_TUNE_BINNED;
@@ -627,9 +632,9 @@ void apply_tuning(qpa_ctx *ctx, const qpa_problem &p, const qpa_params &a, Plan 
     if (p.format != QPA_FMT_CSR || (a.flags & (QPA_SOLVE_STREAMED | QPA_SOLVE_BINNED)) ||
         ctx->tuned.empty())
         return;
-    const std::vector<uint8_t> k = tune_key(p, a);
+    const qpa_ctx::TuneKey k = tune_key(p, a);
     for (const auto &e : ctx->tuned) {
-        if (e.first != k) continue;
+        if (!(e.first == k)) continue;
         if (e.second == 0) {
             pl.path = Path::Csr;
             pl.G = pl.Gs;
@@ -903,6 +908,35 @@ SbmPlan make_sbm_plan(const qpa_problem &p, const qpa_sbm_params &s, int cus = 2
 
 using namespace qpa;
 
+// ---------------------------------------------------------------- static workspace
+// Workspace of qpa_solve_noalloc: a file-scope device array, one copy per device.  In
+// host code its name is only a host-side stand-in, never a device address: the address
+// is looked up once per device (with that device current) and kept in the table below;
+// kernels and copies get that address only.
+static __device__ __align__(256) unsigned char scratch[QPA_NOALLOC_WORKSPACE_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of `device`'s copy of the static workspace; `device` must be current.
+hipError_t scratch_address(int device, void **out) {
+    *out = nullptr;
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr || (reinterpret_cast<uintptr_t>(ptr) % ALIGN) != 0) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+}  // namespace
+
 extern "C" {
 
 qpa_status qpa_create(qpa_ctx **out, int device) {
@@ -925,10 +959,25 @@ qpa_status qpa_create(qpa_ctx **out, int device) {
     e = hipHostMalloc((void **)&c->host_sc, sizeof(CanonScalars), hipHostMallocDefault);
     if (e == hipSuccess)
         e = hipHostMalloc((void **)&c->host_flags, sizeof(int32_t) * 4, hipHostMallocDefault);
+    // the schedule staging buffer, sized for every allocation-free solve
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&c->host_lam, sizeof(float) * (size_t)QPA_NOALLOC_MAX_STEPS,
+                          hipHostMallocDefault);
+    if (e == hipSuccess) c->host_lam_cap = (size_t)QPA_NOALLOC_MAX_STEPS;
     if (e != hipSuccess) {
         if (c->host_sc) (void)hipHostFree(c->host_sc);
+        if (c->host_flags) (void)hipHostFree(c->host_flags);
         delete c;
         return fail(nullptr, QPA_E_DEVICE, "hipHostMalloc failed: %s", hipGetErrorString(e));
+    }
+    e = scratch_address(device, &c->noalloc_ws);
+    if (e != hipSuccess) {
+        (void)hipHostFree(c->host_sc);
+        (void)hipHostFree(c->host_flags);
+        (void)hipHostFree(c->host_lam);
+        delete c;
+        return fail(nullptr, QPA_E_DEVICE, "static workspace of device %d: %s", device,
+                    hipGetErrorString(e));
     }
     *out = c;
     return QPA_OK;
@@ -1053,6 +1102,35 @@ qpa_status qpa_solve(qpa_ctx *ctx, const qpa_problem *problem, const qpa_params 
     if (out->x) QPA_HIP(launch_copy_state(pl.n, pl.R, x, ld_r, ld_i, out->x, pl.n, 1, st));
     if (out->m) QPA_HIP(launch_copy_state(pl.n, pl.R, m, ld_r, ld_i, out->m, pl.n, 1, st));
     return score(ctx, *problem, pl, ws, spins, out->energy, out->energy_i64, out->best, st);
+}
+
+qpa_status qpa_solve_noalloc(qpa_ctx *ctx, const qpa_problem *problem, const qpa_params *params,
+                             void *stream, const qpa_outputs *out) {
+    if (!ctx) return QPA_E_ARG;
+    ctx->err.clear();
+    if (!ctx->noalloc_ws) return fail(ctx, QPA_E_DEVICE, "no static workspace on this device");
+    if (!params) return fail(ctx, QPA_E_ARG, "params is NULL");
+    if (params->flags & QPA_SOLVE_GRAPH)
+        return fail(ctx, QPA_E_UNSUPPORTED,
+                    "QPA_SOLVE_GRAPH captures a graph, which allocates; not taken here");
+    if (params->steps > QPA_NOALLOC_MAX_STEPS)
+        return fail(ctx, QPA_E_UNSUPPORTED, "steps = %d exceeds QPA_NOALLOC_MAX_STEPS = %d",
+                    params->steps, QPA_NOALLOC_MAX_STEPS);
+    size_t need = 0;
+    qpa_status s = qpa_workspace_size(ctx, problem, params, &need);
+    if (s != QPA_OK) return s;
+    if (need > QPA_NOALLOC_WORKSPACE_BYTES)
+        return fail(ctx, QPA_E_WORKSPACE,
+                    "the problem needs %zu bytes of workspace; the static workspace holds %zu",
+                    need, (size_t)QPA_NOALLOC_WORKSPACE_BYTES);
+    // the staging buffer reserved by qpa_create holds the schedule (no hipHostMalloc);
+    // profiling spans would create events, so none are recorded
+    const bool prof = ctx->prof;
+    ctx->prof = false;
+    s = qpa_solve(ctx, problem, params, ctx->noalloc_ws, QPA_NOALLOC_WORKSPACE_BYTES, stream,
+                  out);
+    ctx->prof = prof;
+    return s;
 }
 
 qpa_status qpa_workspace_size_relaxed(qpa_ctx *ctx, const qpa_problem *problem,
@@ -2022,13 +2100,13 @@ qpa_status qpa_spectral_radius(qpa_ctx *ctx, const qpa_problem *problem,
 // ---------------------------------------------------------------- autotuning
 namespace {
 void record_choice(qpa_ctx *ctx, const qpa_problem &p, const qpa_params &a, int32_t choice) {
-    std::vector<uint8_t> k = tune_key(p, a);
+    const qpa_ctx::TuneKey k = tune_key(p, a);
     for (auto &e : ctx->tuned)
         if (e.first == k) {
             e.second = choice;
             return;
         }
-    ctx->tuned.emplace_back(std::move(k), choice);
+    ctx->tuned.emplace_back(k, choice);
 }
 }  // namespace
 

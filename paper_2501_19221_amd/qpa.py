@@ -52,7 +52,10 @@ EXPORTED = ["qpa_create", "qpa_destroy", "qpa_last_error", "qpa_status_string",
             "qpa_solve_batch", "qpa_workspace_size_relaxed", "qpa_relaxed_grad",
             "qpa_profile_read_path", "qpa_batch_paths", "qpa_workspace_size_sbm",
             "qpa_sbm_solve", "qpa_sbm_steps", "qpa_spectral_radius",
-            "qpa_workspace_size_spectrum", "qpa_spectrum", "qpa_autotune", "qpa_tune_set"]
+            "qpa_workspace_size_spectrum", "qpa_spectrum", "qpa_autotune", "qpa_tune_set",
+            "qpa_solve_noalloc"]
+QPA_NOALLOC_WORKSPACE_BYTES = 64 << 20
+QPA_NOALLOC_MAX_STEPS = 65536
 
 
 class qpa_problem(ctypes.Structure):
@@ -97,6 +100,8 @@ _sig = {
                                 ctypes.POINTER(ctypes.c_size_t)]),
     "qpa_solve": (_S, [_P, ctypes.POINTER(qpa_problem), ctypes.POINTER(qpa_params), _P,
                        ctypes.c_size_t, _P, ctypes.POINTER(qpa_outputs)]),
+    "qpa_solve_noalloc": (_S, [_P, ctypes.POINTER(qpa_problem), ctypes.POINTER(qpa_params), _P,
+                               ctypes.POINTER(qpa_outputs)]),
     "qpa_steps": (_S, [_P, ctypes.POINTER(qpa_problem), ctypes.POINTER(qpa_params),
                        ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "qpa_energy": (_S, [_P, ctypes.POINTER(qpa_problem), ctypes.POINTER(qpa_params), _P, _P,
@@ -192,6 +197,11 @@ def qpa_workspace_size(ctx, problem: qpa_problem, params: qpa_params) -> int:
 def qpa_solve(ctx, problem, params, workspace, workspace_bytes, stream, outputs):
     _check(ctx, _lib.qpa_solve(ctx, ctypes.byref(problem), ctypes.byref(params), workspace,
                                workspace_bytes, stream, ctypes.byref(outputs)))
+
+
+def qpa_solve_noalloc(ctx, problem, params, stream, outputs):
+    _check(ctx, _lib.qpa_solve_noalloc(ctx, ctypes.byref(problem), ctypes.byref(params), stream,
+                                       ctypes.byref(outputs)))
 
 
 def qpa_steps(ctx, problem, params, t0, t1, x, m, h_last, workspace, workspace_bytes, stream):
@@ -444,14 +454,16 @@ class Engine:
     def _stream(self):
         return ctypes.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
 
-    def solve(self, prob: Problem, params: qpa_params, want_state=False):
+    def solve(self, prob: Problem, params: qpa_params, want_state=False, noalloc=False):
         """Returns dict(spins [R,n] int8, energy [R] f64, energy_i64 [R] or None,
-        best int tensor [1], x, m) -- device tensors."""
+        best int tensor [1], x, m) -- device tensors.  noalloc: run qpa_solve_noalloc
+        (the library's static workspace) instead of qpa_solve with a torch workspace."""
         torch = self.torch
         dev = "cuda:%d" % self.device
         R, n = params.replicas, prob.n
         ps = prob.struct()
-        ws, nbytes = self.workspace(ps, params)
+        if not noalloc:
+            ws, nbytes = self.workspace(ps, params)
         out = {"spins": torch.empty((R, n), dtype=torch.int8, device=dev),
                "energy": torch.empty(R, dtype=torch.float64, device=dev),
                "best": torch.empty(1, dtype=torch.int32, device=dev),
@@ -465,7 +477,11 @@ class Engine:
         o.best = out["best"].data_ptr()
         o.x = out["x"].data_ptr() if want_state else None
         o.m = out["m"].data_ptr() if want_state else None
-        qpa_solve(self.ctx, ps, params, ctypes.c_void_p(ws.data_ptr()), nbytes, self._stream(), o)
+        if noalloc:
+            qpa_solve_noalloc(self.ctx, ps, params, self._stream(), o)
+        else:
+            qpa_solve(self.ctx, ps, params, ctypes.c_void_p(ws.data_ptr()), nbytes,
+                      self._stream(), o)
         return out
 
     def solve_batch(self, probs, params: qpa_params, want_state=False):

@@ -146,6 +146,8 @@ def test_solve_rejects_null_context_and_bad_workspace(q):
     o = q.qpa_outputs()
     st = q._lib.qpa_solve(None, ctypes.byref(p), ctypes.byref(a), None, 0, None, ctypes.byref(o))
     assert st == q.QPA_E_ARG
+    st = q._lib.qpa_solve_noalloc(None, ctypes.byref(p), ctypes.byref(a), None, ctypes.byref(o))
+    assert st == q.QPA_E_ARG
 
 
 def test_create_without_device_fails_cleanly(q):
