@@ -245,9 +245,17 @@ qpa_status qpa_energy(qpa_ctx *ctx, const qpa_problem *problem, const qpa_params
  *   L = scale * sum_r [ (1/2) x_T^T J x_T + b^T x_T ]   over the params->replicas
  *   replicas started as in qpa_solve (scale = 1/replicas gives the mean), (J, b) the
  *   Ising form of the problem (App. A for a QUBO).
- * FP32 state, FP64 accumulation of the gradient sums.  The forward pass keeps (x, m)
- * every ckpt_every steps; the reverse pass recomputes each segment from its checkpoint.
- *  loss, d_eta, d_alpha: device [1] double; d_lambda: device [steps] double.
+ * Per step: f = J x, h = f + b, g = lambda_t x + h, m' = alpha m - eta g, x' = clip(x + m'),
+ * FP32 state (one fused multiply-add per term of J x, ascending columns), FP64
+ * accumulation of the gradient sums in a fixed order (results do not depend on
+ * ckpt_every).  The forward pass keeps (x, m) every ckpt_every steps; the reverse pass
+ * recomputes each segment from its checkpoint, storing the segment's (x, m, J x).
+ * The loss is a continuous, piecewise smooth function of the parameters (clipping makes
+ * kinks); the gradient is that of the smooth piece the parameters lie in, with the clip
+ * derivative taken as 1 on the closed interval [-1, 1].
+ *  loss: device [1] double (required).  d_eta, d_alpha: device [1] double;
+ *  d_lambda: device [steps] double -- all three given, or all NULL for the forward pass
+ *  only (then no checkpoint is kept).
  *  workspace: device buffer of at least qpa_workspace_size_relaxed() bytes.
  * Dense problems use FP32 couplings whatever params->precision says. */
 qpa_status qpa_workspace_size_relaxed(qpa_ctx *ctx, const qpa_problem *problem,
@@ -257,6 +265,24 @@ qpa_status qpa_relaxed_grad(qpa_ctx *ctx, const qpa_problem *problem, const qpa_
                             int32_t ckpt_every, double scale, void *workspace,
                             size_t workspace_bytes, void *stream, double *loss, double *d_eta,
                             double *d_alpha, double *d_lambda);
+
+/* The same for `count` instances sharing params (the loss of the many-instances
+ * protocol of Secs. V and VIII):
+ *   L = scale * sum_k sum_r [ (1/2) x_T^T J_k x_T + b_k^T x_T ],
+ * instance k's replicas started as qpa_solve starts them with seed params->seed + k;
+ * scale = 1 / (replicas * count) gives the mean over every replica of the batch.
+ *  problems: host array of `count` problems (dense or CSR, mixed types allowed).
+ * Every step of the batch is one launch per (coupling, index) type of its CSR instances
+ * plus one tiled product per dense instance.  Errors name the offending instance. */
+qpa_status qpa_workspace_size_relaxed_batch(qpa_ctx *ctx, int32_t count,
+                                            const qpa_problem *problems,
+                                            const qpa_params *params, int32_t ckpt_every,
+                                            size_t *bytes);
+qpa_status qpa_relaxed_grad_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *problems,
+                                  const qpa_params *params, int32_t ckpt_every, double scale,
+                                  void *workspace, size_t workspace_bytes, void *stream,
+                                  double *loss, double *d_eta, double *d_alpha,
+                                  double *d_lambda);
 
 /* Step kernels, as named by the profiling calls and qpa_batch_paths. */
 typedef enum {

@@ -77,6 +77,10 @@ def _load():
                                                   _F64, _F64, _P, _P, _P, _P]),
             "orc_relaxed_grad_csr_f64": (_F64, [_I64, _P, _P, _P, _P, _I64, _P, _P, _I64, _P,
                                                 _F64, _F64, _F64, _P, _P, _P, _P]),
+            "orc_relaxed_grad_dense_f32": (_F64, [_I64, _P, _P, _I64, _P, _I64, _P, _F32,
+                                                  _F32, _F64, _P, _P, _P, _P]),
+            "orc_relaxed_grad_csr_f32": (_F64, [_I64, _P, _P, _P, _P, _I64, _P, _I64, _P,
+                                                _F32, _F32, _F64, _P, _P, _P, _P]),
             "orc_sbm_steps_dense_f32": (None, [_I64, _P, _P, _I64, _P, _P, _I64, _I64, _I64,
                                                _F32, _F32, _F32, _P]),
             "orc_sbm_steps_csr_f32": (None, [_I64, _P, _P, _P, _P, _I64, _P, _P, _I64, _I64,
@@ -335,6 +339,39 @@ def relaxed_grad_csr(rp, col, w, b, x0, T, lam, eta, alpha, norm=None, grads=Tru
         alpha, norm, _ptr(de) if grads else None, _ptr(da) if grads else None,
         _ptr(dl) if grads else None, None)
     return float(L), float(de[0]), float(da[0]), dl
+
+
+def relaxed_grad32_dense(J, b, x0, T, lam, eta, alpha, norm=None, grads=True):
+    """The single-precision pass (state, adjoint vectors and products in FP32, one fused
+    multiply-add per product term in ascending column order; sums in FP64).  Returns
+    (L, d_eta, d_alpha, d_lam[T], x_T [nrep, n] float32)."""
+    J = _c(J, np.float32)
+    x0 = _c(x0, np.float32)
+    nrep, n = x0.shape
+    norm = 1.0 / nrep if norm is None else norm
+    de, da, dl = np.zeros(1), np.zeros(1), np.zeros(T)
+    xT = np.empty((nrep, n), np.float32)
+    L = _load().orc_relaxed_grad_dense_f32(
+        n, _ptr(J), _ptr(_c(b, np.float32)), nrep, _ptr(x0), T, _ptr(_c(lam, np.float32)),
+        float(np.float32(eta)), float(np.float32(alpha)), norm, _ptr(de) if grads else None,
+        _ptr(da) if grads else None, _ptr(dl) if grads else None, _ptr(xT))
+    return float(L), float(de[0]), float(da[0]), dl, xT
+
+
+def relaxed_grad32_csr(rp, col, w, b, x0, T, lam, eta, alpha, norm=None, grads=True):
+    """relaxed_grad32_dense for CSR couplings (entries summed in stored order, which is
+    ascending column order for a valid instance)."""
+    x0 = _c(x0, np.float32)
+    nrep, n = x0.shape
+    norm = 1.0 / nrep if norm is None else norm
+    de, da, dl = np.zeros(1), np.zeros(1), np.zeros(T)
+    xT = np.empty((nrep, n), np.float32)
+    L = _load().orc_relaxed_grad_csr_f32(
+        n, _ptr(_c(rp, np.int64)), _ptr(_c(col, np.int32)), _ptr(_c(w, np.float32)),
+        _ptr(_c(b, np.float32)), nrep, _ptr(x0), T, _ptr(_c(lam, np.float32)),
+        float(np.float32(eta)), float(np.float32(alpha)), norm, _ptr(de) if grads else None,
+        _ptr(da) if grads else None, _ptr(dl) if grads else None, _ptr(xT))
+    return float(L), float(de[0]), float(da[0]), dl, xT
 
 
 # ------------------------------------------------------------------------------------

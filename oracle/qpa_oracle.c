@@ -33,7 +33,9 @@
  * order written (this file is compiled with -ffp-contract=off), integer couplings summed
  * exactly in int64 and then converted, float couplings summed in FP32 in ascending
  * column order.  Energies are exact in int64 for integer instances, FP64 otherwise.
- * The FP64 relaxed forward/adjoint is plain double arithmetic.
+ * The FP64 relaxed forward/adjoint is plain double arithmetic; its FP32 variant rounds
+ * the state, the adjoint vectors and the products (one fused multiply-add per term, in
+ * ascending column order) to single precision.
  *
  * Parity pins live in tests/ (brute force vs naive enumeration, App. A identities,
  * closed forms of the update, planted optima, finite differences for the adjoint,
@@ -568,6 +570,123 @@ double orc_relaxed_grad_csr_f64(int64_t n, const int64_t *rp, const int32_t *col
 {
     return relaxed_grad(1, n, NULL, rp, col, w, b, nrep, x0, m0, T, lam, eta, alpha, norm,
                         d_eta, d_alpha, d_lam, xT);
+}
+
+/* The same relaxed forward pass and adjoint in single precision: state x, m, the
+ * adjoint vectors xbar, mu and the products J v in FP32, every operation rounded
+ * separately in the order written, each product summed with one fused multiply-add per
+ * term in ascending column order (the reading also used for the SBM field); the loss and
+ * the gradient inner products accumulated in FP64.  Per step:
+ *   f = J x;  h = f + b;  g = lambda_t x + h;  m' = alpha m - eta g;  y = x + m';
+ *   x' = clip(y).   Reverse: ybar = xbar [|y| <= 1];  mu = ybar + alpha mu;
+ *   xbar = ybar - eta (lambda_t mu + J mu).
+ * Being piecewise smooth, the loss and its gradient can differ from the FP64 pass by
+ * more than rounding where some |y| falls within rounding of 1 (a clip decided the other
+ * way); the FP64 pass is the reference of the mathematics, this one of the arithmetic. */
+static void matvec32(int fmt, int64_t n, const float *J, const int64_t *rp,
+                     const int32_t *col, const float *w, const float *v, float *out)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        float acc = 0.0f;
+        if (fmt == 0) {
+            for (int64_t j = 0; j < n; ++j) acc = fmaf(J[i * n + j], v[j], acc);
+        } else {
+            for (int64_t k = rp[i]; k < rp[i + 1]; ++k) acc = fmaf(w[k], v[col[k]], acc);
+        }
+        out[i] = acc;
+    }
+}
+
+static double relaxed_grad32(int fmt, int64_t n, const float *J, const int64_t *rp,
+                             const int32_t *col, const float *w, const float *b, int64_t nrep,
+                             const float *x0, int64_t T, const float *lam, float eta,
+                             float alpha, double norm, double *d_eta, double *d_alpha,
+                             double *d_lam, float *xT)
+{
+    float *X = (float *)malloc(sizeof(float) * (size_t)((T + 1) * n));
+    float *M = (float *)malloc(sizeof(float) * (size_t)((T + 1) * n));
+    float *F = (float *)malloc(sizeof(float) * (size_t)((T + 1) * n));
+    float *xbar = (float *)malloc(sizeof(float) * (size_t)n);
+    float *mu = (float *)malloc(sizeof(float) * (size_t)n);
+    float *ybar = (float *)malloc(sizeof(float) * (size_t)n);
+    float *jmu = (float *)malloc(sizeof(float) * (size_t)n);
+    double loss = 0.0;
+    if (d_eta) *d_eta = 0.0;
+    if (d_alpha) *d_alpha = 0.0;
+    if (d_lam) for (int64_t t = 0; t < T; ++t) d_lam[t] = 0.0;
+
+    for (int64_t r = 0; r < nrep; ++r) {
+        memcpy(X, x0 + r * n, sizeof(float) * (size_t)n);
+        memset(M, 0, sizeof(float) * (size_t)n);
+        for (int64_t t = 0; t < T; ++t) {
+            const float *x = X + t * n, *mm = M + t * n;
+            float *f = F + t * n, *xn = X + (t + 1) * n, *mn = M + (t + 1) * n;
+            matvec32(fmt, n, J, rp, col, w, x, f);
+            for (int64_t i = 0; i < n; ++i) {
+                const float h = f[i] + b[i];
+                const float g = lam[t] * x[i] + h;
+                const float mv = alpha * mm[i] - eta * g;
+                const float y = x[i] + mv;
+                mn[i] = mv;
+                xn[i] = y > 1.0f ? 1.0f : (y < -1.0f ? -1.0f : y);
+            }
+        }
+        const float *xt = X + T * n;
+        float *ft = F + T * n;
+        if (xT) memcpy(xT + r * n, xt, sizeof(float) * (size_t)n);
+        matvec32(fmt, n, J, rp, col, w, xt, ft);
+        double e = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            const double xv = xt[i], fv = ft[i], bv = b[i];
+            e += 0.5 * xv * fv + bv * xv;
+            xbar[i] = (float)(norm * (fv + bv));
+            mu[i] = 0.0f;
+        }
+        loss += e * norm;
+        if (!(d_eta || d_alpha || d_lam)) continue;
+        for (int64_t t = T - 1; t >= 0; --t) {
+            const float *x = X + t * n, *mm = M + t * n, *f = F + t * n;
+            double se = 0.0, sa = 0.0, sl = 0.0;
+            for (int64_t i = 0; i < n; ++i) {
+                const float h = f[i] + b[i];
+                const float g = lam[t] * x[i] + h;
+                const float mv = alpha * mm[i] - eta * g;
+                const float y = x[i] + mv;
+                ybar[i] = fabsf(y) <= 1.0f ? xbar[i] : 0.0f;
+                mu[i] = ybar[i] + alpha * mu[i];
+                se += (double)mu[i] * (double)(-g);
+                sa += (double)mu[i] * (double)mm[i];
+                sl += (double)mu[i] * (-(double)eta * (double)x[i]);
+            }
+            if (d_eta) *d_eta += se;
+            if (d_alpha) *d_alpha += sa;
+            if (d_lam) d_lam[t] += sl;
+            matvec32(fmt, n, J, rp, col, w, mu, jmu);
+            for (int64_t i = 0; i < n; ++i)
+                xbar[i] = ybar[i] - eta * (lam[t] * mu[i] + jmu[i]);
+        }
+    }
+    free(X); free(M); free(F); free(xbar); free(mu); free(ybar); free(jmu);
+    return loss;
+}
+
+double orc_relaxed_grad_dense_f32(int64_t n, const float *J, const float *b, int64_t nrep,
+                                  const float *x0, int64_t T, const float *lam, float eta,
+                                  float alpha, double norm, double *d_eta, double *d_alpha,
+                                  double *d_lam, float *xT)
+{
+    return relaxed_grad32(0, n, J, NULL, NULL, NULL, b, nrep, x0, T, lam, eta, alpha, norm,
+                          d_eta, d_alpha, d_lam, xT);
+}
+
+double orc_relaxed_grad_csr_f32(int64_t n, const int64_t *rp, const int32_t *col,
+                                const float *w, const float *b, int64_t nrep, const float *x0,
+                                int64_t T, const float *lam, float eta, float alpha,
+                                double norm, double *d_eta, double *d_alpha, double *d_lam,
+                                float *xT)
+{
+    return relaxed_grad32(1, n, NULL, rp, col, w, b, nrep, x0, T, lam, eta, alpha, norm, d_eta,
+                          d_alpha, d_lam, xT);
 }
 
 /* ---------------------------------------------------------------------------------------

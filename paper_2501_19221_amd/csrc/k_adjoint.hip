@@ -1,198 +1,261 @@
-// Relaxed PA (analog spins in the target part, s := x) and its reverse-mode adjoint.
+// Relaxed PA (analog spins in the target part, s := x) and its reverse-mode adjoint, for
+// one instance or a batch of instances sharing the dynamics parameters.
 //
-// Forward step t (FP32, each operation rounded separately):
-//   f = J x_t;  g = lambda_t x_t + f + b;  m_{t+1} = alpha m_t - eta g;
-//   y_{t+1} = x_t + m_{t+1};  x_{t+1} = clip(y_{t+1}, -1, 1).
-// Loss: L = scale * sum_r [ (1/2) x_T^T J x_T + b^T x_T ]  (scale = 1/replicas for a mean).
+// Forward step t of one element (FP32, each operation rounded separately):
+//   f = (J x_t)_i;  h = f + b_i;  g = lambda_t x + h;  m' = alpha m - eta g;
+//   y = x + m';  x' = clip(y, -1, 1).
+// Loss: L = scale * sum over instances and replicas of [ (1/2) x_T^T J x_T + b^T x_T ].
 // Reverse, with mu_{T+1} = 0 and xbar_T = scale (J x_T + b):
-//   ybar = xbar_{t+1} * [|y_{t+1}| <= 1];   mu = ybar + alpha mu_next;
-//   dL/deta += <mu, -g_t>,  dL/dalpha += <mu, m_t>,  dL/dlambda_t = <mu, -eta x_t>;
-//   xbar_t = ybar - eta (lambda_t mu + J mu).
-// State layout: [R][n] FP32, replica-major.  Products with J: dense couplings through an
-// LDS-tiled FP32 kernel, CSR couplings through a row gather; both sum in ascending column
-// order.  Inner products are accumulated per workgroup in double and written to a
-// per-step partial table, reduced at the end in a fixed order (deterministic).
-#include "qpa_internal.h"
+//   A(t):  ybar = xbar_{t+1} * [|y_{t+1}| <= 1];  mu_{t+1} = ybar + alpha mu_{t+2};
+//          dL/deta += <mu, -g_t>,  dL/dalpha += <mu, m_t>,  dL/dlambda_t = <mu, -eta x_t>
+//   B(t):  xbar_t = ybar - eta (lambda_t mu_{t+1} + J mu_{t+1})
+// A needs only the element's own values; B needs J mu, a product over neighbours.  A step
+// of the reverse pass is one launch that runs B(t) and then A(t-1) on each element ("BA"),
+// with mu double-buffered since neighbours read it; a segment's first step runs A alone
+// and its last B alone, because the state of the step before a segment is recomputed
+// only with the next segment.
+//
+// State: every vector is [rows][Rp] FP32 (replica fastest); instance k of a batch owns the
+// global rows [row0_k, row0_k + n_k).  Replicas r >= R are padding: held at zero and left
+// out of every sum.
+// Products with J: CSR couplings through a gather (a wave = one row and 64 replicas, lane
+// = replica, the row's entries fetched 64 at a time and walked in order, loads of four
+// entries issued together); dense FP32 couplings through the LDS-tiled product shared with
+// the SBM step, with the element work in its epilogue.  Both add one fused multiply-add
+// per term in ascending column order.
+// Inner products are accumulated in FP64 per thread, reduced per workgroup in a fixed
+// order and written to a per-step table of partial sums, which one last launch reduces in
+// a fixed order: results do not depend on the checkpoint interval or on timing.
+#include "fp32_tiled.h"
 
 namespace qpa {
 namespace {
 
-constexpr int TB = 64, TK = 32;
+constexpr int REL_FWD = REL_MODE_FWD, REL_LOSS = REL_MODE_LOSS, REL_A = REL_MODE_A,
+              REL_B = REL_MODE_B, REL_BA = REL_MODE_BA;
 
-// out[r][i] = sum_k J[i][k] v[r][k]   (dense FP32 J, [n][n] row-major)
-__global__ void __launch_bounds__(256) k_dense_apply(int64_t n, int64_t R,
-                                                     const float *__restrict__ J,
-                                                     const float *__restrict__ v,
-                                                     float *__restrict__ out) {
-    __shared__ float As[TK][TB + 1];
-    __shared__ float Bs[TK][TB + 1];
-    const int tid = threadIdx.x;
-    const int tx = tid % 16, ty = tid / 16;
-    const int64_t r0 = (int64_t)blockIdx.y * TB, i0 = (int64_t)blockIdx.x * TB;
-    float acc[4][4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[q][c] = 0.0f;
-    for (int64_t k0 = 0; k0 < n; k0 += TK) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            int idx = tid + e * 256;
-            int row = idx / TK, kk = idx % TK;
-            int64_t k = k0 + kk;
-            int64_t r = r0 + row, i = i0 + row;
-            As[kk][row] = (r < R && k < n) ? v[r * n + k] : 0.0f;
-            Bs[kk][row] = (i < n && k < n) ? J[i * n + k] : 0.0f;
-        }
-        __syncthreads();
-#pragma unroll 8
-        for (int kk = 0; kk < TK; ++kk) {
-            float a[4], bb[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) a[q] = As[kk][4 * ty + q];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) bb[c] = Bs[kk][tx + 16 * c];
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    acc[q][c] = __fadd_rn(acc[q][c], __fmul_rn(a[q], bb[c]));
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        int64_t r = r0 + 4 * ty + q;
-        if (r >= R) continue;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            int64_t i = i0 + tx + 16 * c;
-            if (i < n) out[r * n + i] = acc[q][c];
-        }
-    }
+__device__ __forceinline__ void rel_fwd_point(float f, float bi, float lt, float eta,
+                                              float alpha, float &x, float &m) {
+    const float h = __fadd_rn(f, bi);
+    const float g = __fadd_rn(__fmul_rn(lt, x), h);
+    const float mn = __fsub_rn(__fmul_rn(alpha, m), __fmul_rn(eta, g));
+    x = fminf(1.0f, fmaxf(-1.0f, __fadd_rn(x, mn)));
+    m = mn;
 }
 
-template <typename TW, typename TI>
-__global__ void __launch_bounds__(256) k_csr_apply(int64_t n, int64_t R,
-                                                   const int32_t *__restrict__ rp,
-                                                   const TI *__restrict__ col,
-                                                   const TW *__restrict__ w, int skip_diag,
-                                                   const float *__restrict__ v,
-                                                   float *__restrict__ out) {
-    const int64_t total = R * n;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = q / n, i = q - r * n;
-        const float *vr = v + r * n;
-        float acc = 0.0f;
-        for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
-            const int64_t j = (int64_t)col[k];
-            if (skip_diag && j == i) continue;
-            acc = __fadd_rn(acc, __fmul_rn((float)w[k], vr[j]));
-        }
-        out[q] = acc;
-    }
+// A(t) on one element from its stored state (x_t, m_t, f_t): the same FP32 operations as
+// the forward step rebuild g_t and y_{t+1}.
+__device__ __forceinline__ void rel_a_point(float x, float m, float f, float bi, float lt,
+                                            float eta, float alpha, float xbar_next,
+                                            float mu_next2, float &mu, float &yb, double &se,
+                                            double &sa, double &sl) {
+    const float h = __fadd_rn(f, bi);
+    const float g = __fadd_rn(__fmul_rn(lt, x), h);
+    const float mn = __fsub_rn(__fmul_rn(alpha, m), __fmul_rn(eta, g));
+    const float y = __fadd_rn(x, mn);
+    yb = fabsf(y) <= 1.0f ? xbar_next : 0.0f;
+    mu = __fadd_rn(yb, __fmul_rn(alpha, mu_next2));
+    se += (double)mu * (double)(-g);
+    sa += (double)mu * (double)m;
+    sl += (double)mu * (-(double)eta * (double)x);
 }
 
-// forward update given f = J x (in place on x, m); optionally records y = x + m'.
-__global__ void __launch_bounds__(256) k_rel_update(int64_t n, int64_t R, const float *__restrict__ f,
-                                                    const float *__restrict__ b, float lam,
-                                                    float eta, float alpha, float *__restrict__ x,
-                                                    float *__restrict__ m) {
-    const int64_t total = R * n;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = q % n;
-        const float xv = x[q];
-        float g = __fadd_rn(__fadd_rn(__fmul_rn(lam, xv), f[q]), b[i]);
-        float mn = __fsub_rn(__fmul_rn(alpha, m[q]), __fmul_rn(eta, g));
-        float y = __fadd_rn(xv, mn);
-        x[q] = fminf(1.0f, fmaxf(-1.0f, y));
-        m[q] = mn;
-    }
+__device__ __forceinline__ float rel_b_point(float yb, float mu, float jmu, float lt, float eta) {
+    return __fsub_rn(yb, __fmul_rn(eta, __fadd_rn(__fmul_rn(lt, mu), jmu)));
 }
 
-__device__ __forceinline__ double block_sum(double v, double *sh) {
+__device__ __forceinline__ double rel_wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    return v;
+}
+
+// Fixed-order sum over the workgroup's waves (nw of them), result in thread 0.
+__device__ __forceinline__ double rel_group_sum(double v, double *sh, int nw) {
+    v = rel_wave_sum(v);
     __syncthreads();
-    if (lane == 0) sh[w] = v;
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
     __syncthreads();
     double s = 0.0;
     if (threadIdx.x == 0)
-        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += sh[k];
+        for (int k = 0; k < nw; ++k) s += sh[k];
     return s;
 }
 
-// loss partial: sum (1/2) x f + b x; xbar = scale (f + b)
-__global__ void __launch_bounds__(256) k_rel_loss(int64_t n, int64_t R, const float *__restrict__ x,
-                                                  const float *__restrict__ f,
-                                                  const float *__restrict__ b, double scale,
-                                                  float *__restrict__ xbar,
-                                                  double *__restrict__ part) {
-    __shared__ double sh[4];
-    const int64_t total = R * n;
-    double acc = 0.0;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = q % n;
-        const double xv = x[q], fv = f[q], bv = b[i];
-        acc += 0.5 * xv * fv + bv * xv;
-        xbar[q] = (float)(scale * (fv + bv));
+// Element work of one launch; `acc` is the product (J v)_i when the mode has one.
+template <int MODE>
+__device__ __forceinline__ void rel_element(const RelArgs &a, int64_t idx, bool live, float acc,
+                                            float bi, double &s0, double &s1, double &s2) {
+    if (MODE == REL_FWD) {
+        float x = 0.0f, m = 0.0f;
+        if (live) {
+            x = a.xi[idx];
+            m = a.mi[idx];
+            rel_fwd_point(acc, bi, a.lam[a.t_f], a.eta, a.alpha, x, m);
+        }
+        a.xo[idx] = x;
+        a.mo[idx] = m;
+        if (a.fo) a.fo[idx] = live ? acc : 0.0f;
+    } else if (MODE == REL_LOSS) {
+        float xb = 0.0f;
+        if (live) {
+            const double x = a.xi[idx], f = acc, b = bi;
+            s0 += 0.5 * x * f + b * x;
+            xb = (float)(a.scale * (f + b));
+        }
+        a.xbar[idx] = xb;
+    } else {
+        float xbar_next = 0.0f;
+        if (MODE == REL_A) {
+            xbar_next = a.xbar[idx];
+        } else {
+            // B of the previous launch's step: xbar_t from ybar, mu_{t+1} and J mu_{t+1}
+            const float xb = live ? rel_b_point(a.yb[idx], a.mu_in[idx], acc, a.lam[a.t_f],
+                                                a.eta)
+                                  : 0.0f;
+            if (MODE == REL_B) {
+                a.xbar[idx] = xb;
+                return;
+            }
+            xbar_next = xb;
+        }
+        float mu = 0.0f, yb = 0.0f;
+        if (live)
+            rel_a_point(a.sx[idx], a.sm[idx], a.sf[idx], bi, a.lam[a.t_a], a.eta, a.alpha,
+                        xbar_next, a.mu_in[idx], mu, yb, s0, s1, s2);
+        a.mu_out[idx] = mu;
+        a.yb[idx] = yb;
     }
-    double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = s * scale;
 }
 
-// Reverse part A for step t: from the state (x_t, m_t) and f_t = J x_t, rebuild g_t,
-// m_{t+1}, y_{t+1}; ybar = xbar * [|y| <= 1]; mu = ybar + alpha mu (in place);
-// partial inner products <mu,-g>, <mu,m_t>, <mu,-eta x_t> for this block.
-__global__ void __launch_bounds__(256) k_rel_rev_a(int64_t n, int64_t R,
-                                                   const float *__restrict__ x,
-                                                   const float *__restrict__ m,
-                                                   const float *__restrict__ f,
-                                                   const float *__restrict__ b, float lam,
-                                                   float eta, float alpha,
-                                                   float *__restrict__ xbar,
-                                                   float *__restrict__ mu,
-                                                   double *__restrict__ part /* [3][nblk] */) {
-    __shared__ double sh[4];
-    const int64_t total = R * n;
-    double se = 0.0, sa = 0.0, sl = 0.0;
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = q % n;
-        const float xv = x[q], mv = m[q];
-        float g = __fadd_rn(__fadd_rn(__fmul_rn(lam, xv), f[q]), b[i]);
-        float mn = __fsub_rn(__fmul_rn(alpha, mv), __fmul_rn(eta, g));
-        float y = __fadd_rn(xv, mn);
-        const float yb = fabsf(y) <= 1.0f ? xbar[q] : 0.0f;
-        const float u = __fadd_rn(yb, __fmul_rn(alpha, mu[q]));
-        mu[q] = u;
-        xbar[q] = yb;                                  // holds ybar until part B
-        se += (double)u * (double)(-g);
-        sa += (double)u * (double)mv;
-        sl += (double)u * (double)(-eta * xv);
+// Writes this workgroup's partial sums (thread 0 holds the group sums).
+template <int MODE>
+__device__ __forceinline__ void rel_write_partials(const RelArgs &a, int64_t wg, double s0,
+                                                   double s1, double s2, double *sh, int nw) {
+    if (MODE == REL_FWD || MODE == REL_B) return;
+    const double g0 = rel_group_sum(s0, sh, nw);
+    if (MODE == REL_LOSS) {
+        if (threadIdx.x == 0) a.part[a.slot0 + wg] = g0 * a.scale;
+        return;
     }
-    const double a = block_sum(se, sh);
-    const double c = block_sum(sa, sh);
-    const double d = block_sum(sl, sh);
+    const double g1 = rel_group_sum(s1, sh, nw);
+    const double g2 = rel_group_sum(s2, sh, nw);
     if (threadIdx.x == 0) {
-        part[blockIdx.x] = a;
-        part[gridDim.x + blockIdx.x] = c;
-        part[2 * gridDim.x + blockIdx.x] = d;
+        a.part[a.slot0 + wg] = g0;
+        a.part[a.nblk + a.slot0 + wg] = g1;
+        a.part[2 * a.nblk + a.slot0 + wg] = g2;
     }
 }
 
-// Reverse part B: xbar_t = ybar - eta (lambda_t mu + J mu), with Jmu = J mu.
-__global__ void __launch_bounds__(256) k_rel_rev_b(int64_t count, const float *__restrict__ mu,
-                                                   const float *__restrict__ Jmu, float lam,
-                                                   float eta, float *__restrict__ xbar) {
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < count;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        float inner = __fadd_rn(__fmul_rn(lam, mu[q]), Jmu[q]);
-        xbar[q] = __fsub_rn(xbar[q], __fmul_rn(eta, inner));
+template <typename T> __device__ __forceinline__ float as_weight(T w) { return (float)w; }
+
+// Batched CSR launch (and, with MODE = REL_A, the element-wise pass over the rows of every
+// instance).  Work item q = (row, 64-replica chunk); waves stride over the items in a
+// fixed order.  The instance of a row is found by binary search over item0.
+template <int MODE, typename TW, typename TI>
+__global__ void __launch_bounds__(256) k_rel_rows(const RelInst *__restrict__ insts,
+                                                  int32_t ninst, int64_t items, int32_t C,
+                                                  const RelArgs a) {
+    __shared__ double sh[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    constexpr bool GATHER = MODE != REL_A;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    const int64_t total = items * C;
+    for (int64_t q = (int64_t)blockIdx.x * 4 + wv; q < total; q += (int64_t)gridDim.x * 4) {
+        const int64_t item = q / C;
+        const int c = (int)(q - item * C);
+        int lo = 0, hi = ninst - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (insts[mid].item0 <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        const RelInst &I = insts[lo];
+        const int64_t i = item - I.item0;
+        const int64_t r = (int64_t)c * 64 + lane;
+        const int64_t idx = (I.row0 + i) * a.Rp + r;
+        const bool live = r < a.R;
+        float acc = 0.0f;
+        if (GATHER) {
+            const float *v = (MODE == REL_FWD || MODE == REL_LOSS) ? a.xi : a.mu_in;
+            const float *vb = v + I.row0 * a.Rp + r;
+            const TI *col = static_cast<const TI *>(I.col);
+            const TW *w = static_cast<const TW *>(I.w);
+            const int32_t k0 = I.rp[i], k1 = I.rp[i + 1];
+            for (int32_t kb = k0; kb < k1; kb += 64) {
+                int32_t jj = (int32_t)i;
+                float ww = 0.0f;
+                if (kb + lane < k1) {
+                    jj = (int32_t)col[kb + lane];
+                    ww = as_weight(w[kb + lane]);
+                    // a stored QUBO diagonal is folded into b: weight 0 adds exactly nothing
+                    if (I.skip_diag && jj == (int32_t)i) ww = 0.0f;
+                }
+                const int cnt = min(64, k1 - kb);
+                int e = 0;
+                for (; e + 4 <= cnt; e += 4) {
+                    const int64_t j0 = __builtin_amdgcn_readlane(jj, e);
+                    const int64_t j1 = __builtin_amdgcn_readlane(jj, e + 1);
+                    const int64_t j2 = __builtin_amdgcn_readlane(jj, e + 2);
+                    const int64_t j3 = __builtin_amdgcn_readlane(jj, e + 3);
+                    const float v0 = vb[j0 * a.Rp], v1 = vb[j1 * a.Rp];
+                    const float v2 = vb[j2 * a.Rp], v3 = vb[j3 * a.Rp];
+                    const float w0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ww), e));
+                    const float w1 =
+                        __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ww), e + 1));
+                    const float w2 =
+                        __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ww), e + 2));
+                    const float w3 =
+                        __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ww), e + 3));
+                    acc = __fmaf_rn(w0, v0, acc);
+                    acc = __fmaf_rn(w1, v1, acc);
+                    acc = __fmaf_rn(w2, v2, acc);
+                    acc = __fmaf_rn(w3, v3, acc);
+                }
+                for (; e < cnt; ++e) {
+                    const int64_t j = __builtin_amdgcn_readlane(jj, e);
+                    const float we = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ww), e));
+                    acc = __fmaf_rn(we, vb[j * a.Rp], acc);
+                }
+            }
+        }
+        rel_element<MODE>(a, idx, live, acc, I.b[i], s0, s1, s2);
     }
+    rel_write_partials<MODE>(a, blockIdx.x, s0, s1, s2, sh, 4);
+}
+
+// Epilogue of the dense tiled product for every mode (b, and the state pointers in `a`,
+// already offset to the instance's rows).
+template <int MODE>
+struct RelTileEpilogue {
+    RelArgs a;
+    const float *b;
+    __device__ __forceinline__ void operator()(float (&acc)[8][8], int64_t n, int64_t Rp,
+                                               int64_t i0, int64_t r0, int tx, int ty) const {
+        __shared__ double sh[4];
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const int64_t i = i0 + 64 * (v >> 2) + 4 * tx + (v & 3);
+            if (i >= n) continue;
+            const float bi = b[i];
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int64_t r = r0 + 64 * h + 4 * ty + e;
+                    rel_element<MODE>(a, i * Rp + r, r < a.R, acc[4 * h + e][v], bi, s0, s1,
+                                      s2);
+                }
+        }
+        rel_write_partials<MODE>(a, (int64_t)blockIdx.y * gridDim.x + blockIdx.x, s0, s1, s2,
+                                 sh, 4);
+    }
+};
+
+__global__ void __launch_bounds__(256) k_rel_fill(double *__restrict__ p, int64_t count) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < count;
+         q += (int64_t)gridDim.x * blockDim.x)
+        p[q] = 0.0;
 }
 
 // final reduction of the per-step partial tables (fixed order)
@@ -203,87 +266,117 @@ __global__ void __launch_bounds__(256) k_rel_finish(int32_t T, int32_t nblk,
                                                     double *__restrict__ d_eta,
                                                     double *__restrict__ d_alpha,
                                                     double *__restrict__ d_lam) {
-    for (int32_t t = threadIdx.x; t < T; t += blockDim.x) {
-        const double *p = part_steps + (int64_t)t * 3 * nblk;
-        double l = 0.0;
-        for (int32_t k = 0; k < nblk; ++k) l += p[2 * nblk + k];
-        d_lam[t] = l;
-    }
-    if (threadIdx.x == 0) {
-        double e = 0.0, a = 0.0, L = 0.0;
-        for (int32_t t = 0; t < T; ++t) {
+    if (d_lam)
+        for (int32_t t = threadIdx.x; t < T; t += blockDim.x) {
             const double *p = part_steps + (int64_t)t * 3 * nblk;
-            for (int32_t k = 0; k < nblk; ++k) {
-                e += p[k];
-                a += p[nblk + k];
-            }
+            double l = 0.0;
+            for (int32_t k = 0; k < nblk; ++k) l += p[2 * nblk + k];
+            d_lam[t] = l;
         }
+    if (threadIdx.x == 0) {
+        double L = 0.0;
         for (int32_t k = 0; k < nblk; ++k) L += part_loss[k];
         *loss = L;
-        *d_eta = e;
-        *d_alpha = a;
+        if (d_eta || d_alpha) {
+            double e = 0.0, al = 0.0;
+            for (int32_t t = 0; t < T; ++t) {
+                const double *p = part_steps + (int64_t)t * 3 * nblk;
+                for (int32_t k = 0; k < nblk; ++k) {
+                    e += p[k];
+                    al += p[nblk + k];
+                }
+            }
+            if (d_eta) *d_eta = e;
+            if (d_alpha) *d_alpha = al;
+        }
     }
+}
+
+template <typename F>
+hipError_t rel_by_dtypes(int32_t wdt, int32_t idt, F &&f) {
+    auto byw = [&](auto itag) -> hipError_t {
+        switch (wdt) {
+            case QPA_I8: return f((int8_t)0, itag);
+            case QPA_I16: return f((int16_t)0, itag);
+            case QPA_I32: return f((int32_t)0, itag);
+            default: return f(0.0f, itag);
+        }
+    };
+    return idt == QPA_I16 ? byw((int16_t)0) : byw((int32_t)0);
+}
+
+template <int MODE>
+hipError_t rel_rows_launch(const RelInst *insts, int32_t ninst, int64_t items, int32_t C,
+                           int32_t wdt, int32_t idt, const RelArgs &a, hipStream_t st) {
+    const unsigned g = (unsigned)rel_row_blocks(items, C);
+    if (MODE == REL_A) {
+        k_rel_rows<REL_A, float, int32_t><<<g, 256, 0, st>>>(insts, ninst, items, C, a);
+        return hipGetLastError();
+    }
+    return rel_by_dtypes(wdt, idt, [&](auto wtag, auto itag) {
+        using TW = decltype(wtag);
+        using TI = decltype(itag);
+        k_rel_rows<MODE, TW, TI><<<g, 256, 0, st>>>(insts, ninst, items, C, a);
+        return hipGetLastError();
+    });
+}
+
+template <int MODE>
+hipError_t rel_tile_launch(int64_t n, const float *J, const float *b, const RelArgs &a,
+                           hipStream_t st) {
+    if (a.Rp % SB_BR || n < 1) return hipErrorInvalidValue;
+    dim3 grid((unsigned)((n + SB_BI - 1) / SB_BI), (unsigned)(a.Rp / SB_BR));
+    const RelTileEpilogue<MODE> epi{a, b};
+    const float *q = (MODE == REL_FWD || MODE == REL_LOSS) ? a.xi : a.mu_in;
+    if (n % 4 == 0)
+        k_fp32_tiled_step<true, RelTileEpilogue<MODE>><<<grid, 256, 0, st>>>(n, a.Rp, J, q, epi);
+    else
+        k_fp32_tiled_step<false, RelTileEpilogue<MODE>><<<grid, 256, 0, st>>>(n, a.Rp, J, q, epi);
+    return hipGetLastError();
 }
 
 }  // namespace
 
-int32_t rel_blocks(int64_t count) {
+int64_t rel_row_blocks(int64_t items, int32_t C) {
+    const int64_t waves = items * (int64_t)C;
+    int64_t g = (waves + 3) / 4;
+    if (g > REL_ROW_BLOCKS_MAX) g = REL_ROW_BLOCKS_MAX;
+    return g < 1 ? 1 : g;
+}
+
+int64_t rel_tile_blocks(int64_t n, int64_t Rp) {
+    return ((n + SB_BI - 1) / SB_BI) * (Rp / SB_BR);
+}
+
+hipError_t launch_rel_rows(int32_t mode, const RelInst *insts, int32_t ninst, int64_t items,
+                           int32_t C, int32_t wdt, int32_t idt, const RelArgs &a,
+                           hipStream_t st) {
+    switch (mode) {
+        case REL_FWD: return rel_rows_launch<REL_FWD>(insts, ninst, items, C, wdt, idt, a, st);
+        case REL_LOSS: return rel_rows_launch<REL_LOSS>(insts, ninst, items, C, wdt, idt, a, st);
+        case REL_A: return rel_rows_launch<REL_A>(insts, ninst, items, C, wdt, idt, a, st);
+        case REL_B: return rel_rows_launch<REL_B>(insts, ninst, items, C, wdt, idt, a, st);
+        case REL_BA: return rel_rows_launch<REL_BA>(insts, ninst, items, C, wdt, idt, a, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_rel_tiles(int32_t mode, int64_t n, const float *J, const float *b,
+                            const RelArgs &a, hipStream_t st) {
+    switch (mode) {
+        case REL_FWD: return rel_tile_launch<REL_FWD>(n, J, b, a, st);
+        case REL_LOSS: return rel_tile_launch<REL_LOSS>(n, J, b, a, st);
+        case REL_B: return rel_tile_launch<REL_B>(n, J, b, a, st);
+        case REL_BA: return rel_tile_launch<REL_BA>(n, J, b, a, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_rel_fill(double *p, int64_t count, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
     int64_t g = (count + 255) / 256;
     if (g > 1024) g = 1024;
-    return (int32_t)(g < 1 ? 1 : g);
-}
-
-hipError_t launch_rel_apply(const qpa_problem &p, const float *Jf, bool skip_diag, int64_t R,
-                            const float *v, float *out, hipStream_t st) {
-    const int64_t n = p.n;
-    if (p.format == QPA_FMT_DENSE) {
-        dim3 grid((unsigned)((n + TB - 1) / TB), (unsigned)((R + TB - 1) / TB));
-        k_dense_apply<<<grid, 256, 0, st>>>(n, R, Jf, v, out);
-        return hipGetLastError();
-    }
-    const unsigned g = (unsigned)rel_blocks(R * n);
-    auto run = [&](auto wtag, auto itag) {
-        using TW = decltype(wtag);
-        using TI = decltype(itag);
-        k_csr_apply<TW, TI><<<g, 256, 0, st>>>(n, R, p.row_ptr, static_cast<const TI *>(p.col),
-                                               static_cast<const TW *>(p.weights),
-                                               skip_diag ? 1 : 0, v, out);
-        return hipGetLastError();
-    };
-    auto byw = [&](auto itag) -> hipError_t {
-        switch (p.coupling_dtype) {
-            case QPA_I8: return run((int8_t)0, itag);
-            case QPA_I16: return run((int16_t)0, itag);
-            case QPA_I32: return run((int32_t)0, itag);
-            default: return run(0.0f, itag);
-        }
-    };
-    return p.index_dtype == QPA_I16 ? byw((int16_t)0) : byw((int32_t)0);
-}
-
-hipError_t launch_rel_update(int64_t n, int64_t R, const float *f, const float *b, float lam,
-                             float eta, float alpha, float *x, float *m, hipStream_t st) {
-    k_rel_update<<<rel_blocks(R * n), 256, 0, st>>>(n, R, f, b, lam, eta, alpha, x, m);
-    return hipGetLastError();
-}
-
-hipError_t launch_rel_loss(int64_t n, int64_t R, const float *x, const float *f, const float *b,
-                           double scale, float *xbar, double *part, hipStream_t st) {
-    k_rel_loss<<<rel_blocks(R * n), 256, 0, st>>>(n, R, x, f, b, scale, xbar, part);
-    return hipGetLastError();
-}
-
-hipError_t launch_rel_rev_a(int64_t n, int64_t R, const float *x, const float *m, const float *f,
-                            const float *b, float lam, float eta, float alpha, float *xbar,
-                            float *mu, double *part, hipStream_t st) {
-    k_rel_rev_a<<<rel_blocks(R * n), 256, 0, st>>>(n, R, x, m, f, b, lam, eta, alpha, xbar, mu,
-                                                   part);
-    return hipGetLastError();
-}
-
-hipError_t launch_rel_rev_b(int64_t count, const float *mu, const float *Jmu, float lam,
-                            float eta, float *xbar, hipStream_t st) {
-    k_rel_rev_b<<<rel_blocks(count), 256, 0, st>>>(count, mu, Jmu, lam, eta, xbar);
+    k_rel_fill<<<(unsigned)g, 256, 0, st>>>(p, count);
     return hipGetLastError();
 }
 

@@ -675,36 +675,116 @@ qpa_status prologue(qpa_ctx *ctx, const qpa_problem *problem, const qpa_params *
     return QPA_OK;
 }
 
-// Relaxed-gradient workspace: the FP32 plan's canonical buffers, then checkpoints and
-// the segment buffer of states (x_t, m_t, f_t = J x_t) and the reverse vectors.
+// Relaxed-gradient workspace of a batch (a single instance is a batch of one): each
+// instance's FP32 canonical buffers (no PA state), the instance tables, then the stacked
+// state vectors [rows][Rp], the checkpoints, the stored states of a segment, the reverse
+// vectors and the per-step partial tables.
 struct RelPlan {
-    Plan base;
-    int32_t k, nseg, nblk;
-    size_t o_ckpt, o_seg, o_f, o_xbar, o_mu, o_jmu, o_part, o_ploss, total;
+    std::vector<Plan> inst;
+    std::vector<size_t> base;
+    std::vector<int64_t> row0;
+    int64_t rows = 0, Rp = 0;
+    int32_t C = 0;                 // 64-replica chunks of a row
+    int32_t k = 1, nseg = 0;
+    // partial slots of a step: the element-wise pass over all rows writes slots
+    // [0, nblk_all); a gather step writes each CSR group's blocks and then each dense
+    // instance's tiles, [0, nblk_gather); nblk = the larger of the two
+    int32_t nblk = 0, nblk_all = 0, nblk_gather = 0;
+    struct Group {
+        int32_t wdt, idt, first, count, slot0;
+        int64_t items;
+    };
+    std::vector<Group> groups;     // CSR instances by (coupling, index) type
+    std::vector<int32_t> csr_order;   // instance indices, grouped
+    std::vector<int32_t> dense_slot;  // per instance: first tile slot (-1 for CSR)
+    size_t o_tab_all = 0, o_tab_csr = 0, o_lam = 0, o_x0 = 0, o_x1 = 0, o_m = 0, o_ckpt = 0,
+           o_seg = 0, o_xbar = 0, o_yb = 0, o_mu0 = 0, o_mu1 = 0, o_part = 0, o_ploss = 0,
+           total = 0;
+    size_t vec_bytes() const { return sizeof(float) * (size_t)rows * (size_t)Rp; }
 };
 
-qpa_status make_rel_plan(qpa_ctx *ctx, const qpa_problem &p, const qpa_params &a, int32_t k,
-                         RelPlan &rp) {
+qpa_status make_rel_plan(qpa_ctx *ctx, int32_t count, const qpa_problem *probs,
+                         const qpa_params &a, int32_t k, RelPlan &rp) {
     if (k < 1) return fail(ctx, QPA_E_ARG, "ckpt_every must be >= 1");
+    if (count < 1) return fail(ctx, QPA_E_ARG, "count must be >= 1");
+    if (!probs) return fail(ctx, QPA_E_ARG, "problems is NULL");
     qpa_params a32 = a;
     a32.precision = QPA_PREC_FP32;
-    rp.base = make_plan(p, a32, 0, 0);   // streamed layout: the adjoint kernels use it
-    rp.k = k;
-    rp.nseg = (int32_t)((a.steps + k - 1) / k);
-    const size_t RN = (size_t)a.replicas * (size_t)p.n;
-    rp.nblk = rel_blocks((int64_t)RN);
-    size_t off = rp.base.total;
+    a32.flags = 0;
+    rp.inst.assign(count, Plan{});
+    rp.base.assign(count, 0);
+    rp.row0.assign(count, 0);
+    rp.dense_slot.assign(count, -1);
+    rp.groups.clear();
+    rp.csr_order.clear();
+    rp.rows = 0;
+    bool any_dense = false;
+    size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
         off += align_up(bytes);
         return o;
     };
-    rp.o_ckpt = take(sizeof(float) * 2 * RN * (size_t)(rp.nseg + 1));
-    rp.o_seg = take(sizeof(float) * 3 * RN * (size_t)k);
-    rp.o_f = take(sizeof(float) * RN);
-    rp.o_xbar = take(sizeof(float) * RN);
-    rp.o_mu = take(sizeof(float) * RN);
-    rp.o_jmu = take(sizeof(float) * RN);
+    for (int32_t q = 0; q < count; ++q) {
+        qpa_status s = check_problem(ctx, &probs[q]);
+        if (s != QPA_OK) {
+            std::string msg = "instance " + std::to_string(q) + ": " + ctx->err;
+            return fail(ctx, s, "%s", msg.c_str());
+        }
+        // FP32 couplings: a dense instance gets its canonical FP32 matrix
+        const Plan pl = make_plan(probs[q], a32, 0, 256, false);
+        rp.inst[q] = pl;
+        rp.base[q] = take(pl.total);
+        rp.row0[q] = rp.rows;
+        rp.rows += probs[q].n;
+        any_dense = any_dense || probs[q].format == QPA_FMT_DENSE;
+    }
+    rp.Rp = round_up(a.replicas, any_dense ? 128 : 64);
+    rp.C = (int32_t)(rp.Rp / 64);
+    rp.k = k;
+    rp.nseg = (int32_t)((a.steps + k - 1) / k);
+    // CSR instances grouped by (coupling, index) type, in index order within a group
+    for (int32_t q = 0; q < count; ++q) {
+        if (probs[q].format != QPA_FMT_CSR) continue;
+        const int32_t wdt = probs[q].coupling_dtype, idt = probs[q].index_dtype;
+        bool found = false;
+        for (auto &g : rp.groups) found = found || (g.wdt == wdt && g.idt == idt);
+        if (!found) rp.groups.push_back({wdt, idt, 0, 0, 0, 0});
+    }
+    int32_t slot = 0;
+    for (auto &g : rp.groups) {
+        g.first = (int32_t)rp.csr_order.size();
+        for (int32_t q = 0; q < count; ++q)
+            if (probs[q].format == QPA_FMT_CSR && probs[q].coupling_dtype == g.wdt &&
+                probs[q].index_dtype == g.idt) {
+                rp.csr_order.push_back(q);
+                g.items += probs[q].n;
+            }
+        g.count = (int32_t)rp.csr_order.size() - g.first;
+        g.slot0 = slot;
+        slot += (int32_t)rel_row_blocks(g.items, rp.C);
+    }
+    for (int32_t q = 0; q < count; ++q) {
+        if (probs[q].format != QPA_FMT_DENSE) continue;
+        rp.dense_slot[q] = slot;
+        slot += (int32_t)rel_tile_blocks(probs[q].n, rp.Rp);
+    }
+    rp.nblk_gather = slot;
+    rp.nblk_all = (int32_t)rel_row_blocks(rp.rows, rp.C);
+    rp.nblk = std::max(rp.nblk_gather, rp.nblk_all);
+    const size_t V = rp.vec_bytes();
+    rp.o_tab_all = take(sizeof(RelInst) * (size_t)count);
+    rp.o_tab_csr = take(sizeof(RelInst) * std::max<size_t>(rp.csr_order.size(), 1));
+    rp.o_lam = take(sizeof(float) * (size_t)std::max<int32_t>(a.steps, 1));
+    rp.o_x0 = take(V);
+    rp.o_x1 = take(V);
+    rp.o_m = take(V);
+    rp.o_ckpt = take(V * 2 * (size_t)std::max(rp.nseg, 1));
+    rp.o_seg = take(V * 3 * (size_t)(std::min(k, std::max(a.steps, 1)) + 1));
+    rp.o_xbar = take(V);
+    rp.o_yb = take(V);
+    rp.o_mu0 = take(V);
+    rp.o_mu1 = take(V);
     rp.o_part = take(sizeof(double) * 3 * (size_t)rp.nblk * (size_t)std::max(a.steps, 1));
     rp.o_ploss = take(sizeof(double) * (size_t)rp.nblk);
     rp.total = off;
@@ -1133,104 +1213,278 @@ qpa_status qpa_solve_noalloc(qpa_ctx *ctx, const qpa_problem *problem, const qpa
     return s;
 }
 
-qpa_status qpa_workspace_size_relaxed(qpa_ctx *ctx, const qpa_problem *problem,
-                                      const qpa_params *params, int32_t ckpt_every,
-                                      size_t *bytes) {
-    if (!bytes) return fail(ctx, QPA_E_ARG, "bytes is NULL");
-    qpa_status s = check_problem(ctx, problem);
+}  // extern "C"
+
+namespace qpa {
+namespace {
+
+// The relaxed forward pass, and with gradients the checkpointed reverse pass, of a batch.
+qpa_status relaxed_run(qpa_ctx *ctx, int32_t count, const qpa_problem *probs,
+                       const qpa_params *params, int32_t k, double scale, void *ws,
+                       size_t ws_bytes, hipStream_t st, double *loss, double *d_eta,
+                       double *d_alpha, double *d_lambda) {
+    if (!ctx) return QPA_E_ARG;
+    ctx->err.clear();
+    qpa_status s = check_params(ctx, params);
     if (s != QPA_OK) return s;
-    s = check_params(ctx, params);
+    if (!loss) return fail(ctx, QPA_E_ARG, "loss is required");
+    const bool grads = d_eta || d_alpha || d_lambda;
+    if (grads && (!d_eta || !d_alpha || (params->steps > 0 && !d_lambda)))
+        return fail(ctx, QPA_E_ARG,
+                    "d_eta, d_alpha and d_lambda are all required (or all NULL: loss only)");
+    if (!std::isfinite(scale)) return fail(ctx, QPA_E_ARG, "scale must be finite");
+    RelPlan rp;
+    s = make_rel_plan(ctx, count, probs, *params, k, rp);
+    if (s != QPA_OK) return s;
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) % ALIGN) != 0)
+        return fail(ctx, QPA_E_ARG, "workspace must be non-NULL and %zu-byte aligned", ALIGN);
+    if (ws_bytes < rp.total)
+        return fail(ctx, QPA_E_WORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes,
+                    rp.total);
+    QPA_HIP(hipSetDevice(ctx->device));
+    float *lam = at<float>(ws, rp.o_lam);
+    s = upload_schedule(ctx, *params, lam, st);
+    if (s != QPA_OK) return s;
+    for (int32_t q = 0; q < count; ++q) {
+        s = canonicalise(ctx, probs[q], rp.inst[q], at<char>(ws, rp.base[q]), st);
+        if (s != QPA_OK) {
+            std::string msg = "instance " + std::to_string(q) + ": " + ctx->err;
+            return fail(ctx, s, "%s", msg.c_str());
+        }
+    }
+    // instance tables: every instance (element-wise pass) and the CSR ones by group
+    auto inst_entry = [&](int32_t q, int64_t item0) {
+        const qpa_problem &p = probs[q];
+        RelInst e{};
+        if (p.format == QPA_FMT_CSR) {
+            e.rp = p.row_ptr;
+            e.col = p.col;
+            e.w = p.weights;
+        }
+        e.b = at<float>(at<char>(ws, rp.base[q]), rp.inst[q].o_bf);
+        e.n = p.n;
+        e.row0 = rp.row0[q];
+        e.item0 = item0;
+        e.skip_diag = p.kind == QPA_KIND_QUBO ? 1 : 0;
+        return e;
+    };
+    std::vector<RelInst> tab_all(count), tab_csr(std::max<size_t>(rp.csr_order.size(), 1));
+    for (int32_t q = 0; q < count; ++q) tab_all[q] = inst_entry(q, rp.row0[q]);
+    for (const auto &g : rp.groups) {
+        int64_t item0 = 0;
+        for (int32_t e = g.first; e < g.first + g.count; ++e) {
+            tab_csr[e] = inst_entry(rp.csr_order[e], item0);
+            item0 += probs[rp.csr_order[e]].n;
+        }
+    }
+    RelInst *d_all = at<RelInst>(ws, rp.o_tab_all), *d_csr = at<RelInst>(ws, rp.o_tab_csr);
+    QPA_HIP(hipMemcpyAsync(d_all, tab_all.data(), sizeof(RelInst) * tab_all.size(),
+                           hipMemcpyHostToDevice, st));
+    QPA_HIP(hipMemcpyAsync(d_csr, tab_csr.data(), sizeof(RelInst) * tab_csr.size(),
+                           hipMemcpyHostToDevice, st));
+    // the host tables are read by the copies: wait for them before they go out of scope
+    QPA_HIP(hipStreamSynchronize(st));
+
+    const int64_t Rp = rp.Rp;
+    const int32_t T = params->steps, R = params->replicas;
+    const size_t V = rp.vec_bytes();
+    const size_t VN = (size_t)rp.rows * (size_t)Rp;      // floats per vector
+    float *X[2] = {at<float>(ws, rp.o_x0), at<float>(ws, rp.o_x1)};
+    float *M = at<float>(ws, rp.o_m);
+    float *ckpt = at<float>(ws, rp.o_ckpt), *seg = at<float>(ws, rp.o_seg);
+    float *xbar = at<float>(ws, rp.o_xbar), *yb = at<float>(ws, rp.o_yb);
+    float *MU[2] = {at<float>(ws, rp.o_mu0), at<float>(ws, rp.o_mu1)};
+    double *part = at<double>(ws, rp.o_part), *ploss = at<double>(ws, rp.o_ploss);
+    auto slot_x = [&](int32_t sidx) { return seg + (size_t)3 * VN * (size_t)sidx; };
+    auto slot_m = [&](int32_t sidx) { return slot_x(sidx) + VN; };
+    auto slot_f = [&](int32_t sidx) { return slot_x(sidx) + 2 * VN; };
+
+    RelArgs base{};
+    base.Rp = Rp;
+    base.R = R;
+    base.nblk = rp.nblk;
+    base.lam = lam;
+    base.eta = params->eta;
+    base.alpha = params->alpha;
+    base.scale = scale;
+    // The state pointers of a dense instance's launch point at its first row.
+    auto shifted = [&](const RelArgs &a, int64_t row0) {
+        RelArgs b = a;
+        const int64_t o = row0 * Rp;
+        auto sh = [&](auto *p) { return p ? p + o : p; };
+        b.xi = sh(a.xi);
+        b.mi = sh(a.mi);
+        b.xo = sh(a.xo);
+        b.mo = sh(a.mo);
+        b.fo = sh(a.fo);
+        b.sx = sh(a.sx);
+        b.sm = sh(a.sm);
+        b.sf = sh(a.sf);
+        b.mu_in = sh(a.mu_in);
+        b.mu_out = sh(a.mu_out);
+        b.yb = sh(a.yb);
+        b.xbar = sh(a.xbar);
+        return b;
+    };
+    // One launch mode over every instance: the gather launches of the CSR groups and the
+    // tiled products of the dense instances, each on its own partial slots.
+    auto over_all = [&](int32_t mode, const RelArgs &a) -> qpa_status {
+        for (const auto &g : rp.groups) {
+            RelArgs b = a;
+            b.slot0 = g.slot0;
+            QPA_HIP(launch_rel_rows(mode, d_csr + g.first, g.count, g.items, rp.C, g.wdt, g.idt,
+                                    b, st));
+        }
+        for (int32_t q = 0; q < count; ++q) {
+            if (rp.dense_slot[q] < 0) continue;
+            RelArgs b = shifted(a, rp.row0[q]);
+            b.slot0 = rp.dense_slot[q];
+            const char *wsq = at<char>(ws, rp.base[q]);
+            QPA_HIP(launch_rel_tiles(mode, probs[q].n, at<float>(const_cast<char *>(wsq),
+                                                                 rp.inst[q].o_Jf),
+                                     at<float>(const_cast<char *>(wsq), rp.inst[q].o_bf), b,
+                                     st));
+        }
+        return QPA_OK;
+    };
+    auto fwd = [&](int32_t t, const float *xi, const float *mi, float *xo, float *mo,
+                   float *fo) {
+        RelArgs a = base;
+        a.t_f = t;
+        a.xi = xi;
+        a.mi = mi;
+        a.xo = xo;
+        a.mo = mo;
+        a.fo = fo;
+        return over_all(REL_MODE_FWD, a);
+    };
+
+    // initial state of every instance (seed + instance index), padding replicas zero
+    for (int32_t q = 0; q < count; ++q) {
+        const int64_t o = rp.row0[q] * Rp;
+        QPA_HIP(launch_init_state(probs[q].n, R, params->seed + (uint64_t)q, params->sigma0,
+                                  X[0] + o, M + o, 1, Rp, Rp, probs[q].n, st));
+    }
+    if (grads) QPA_HIP(launch_rel_fill(part, (int64_t)3 * rp.nblk * std::max(T, 1), st));
+    QPA_HIP(launch_rel_fill(ploss, rp.nblk, st));
+    // forward pass, keeping (x, m) at the first step of every segment
+    for (int32_t t = 0; t < T; ++t) {
+        if (grads && t % k == 0) {
+            float *c = ckpt + (size_t)2 * VN * (size_t)(t / k);
+            QPA_HIP(hipMemcpyAsync(c, X[t & 1], V, hipMemcpyDeviceToDevice, st));
+            QPA_HIP(hipMemcpyAsync(c + VN, M, V, hipMemcpyDeviceToDevice, st));
+        }
+        s = fwd(t, X[t & 1], M, X[(t + 1) & 1], M, nullptr);
+        if (s != QPA_OK) return s;
+    }
+    {
+        RelArgs a = base;
+        a.xi = X[T & 1];
+        a.xbar = xbar;
+        a.part = ploss;
+        s = over_all(REL_MODE_LOSS, a);
+        if (s != QPA_OK) return s;
+    }
+    if (grads && T > 0) {
+        QPA_HIP(hipMemsetAsync(MU[0], 0, V, st));    // mu_{T+1} = 0
+        int cur = 0;
+        for (int32_t c = rp.nseg - 1; c >= 0; --c) {
+            const int32_t t0 = c * k, t1 = std::min(T, t0 + k);
+            const float *cp = ckpt + (size_t)2 * VN * (size_t)c;
+            QPA_HIP(hipMemcpyAsync(slot_x(0), cp, V, hipMemcpyDeviceToDevice, st));
+            QPA_HIP(hipMemcpyAsync(slot_m(0), cp + VN, V, hipMemcpyDeviceToDevice, st));
+            for (int32_t t = t0; t < t1; ++t) {
+                const int32_t q = t - t0;
+                s = fwd(t, slot_x(q), slot_m(q), slot_x(q + 1), slot_m(q + 1), slot_f(q));
+                if (s != QPA_OK) return s;
+            }
+            {   // A(t1 - 1) alone, element-wise over all rows
+                RelArgs a = base;
+                a.t_a = t1 - 1;
+                a.sx = slot_x(t1 - 1 - t0);
+                a.sm = slot_m(t1 - 1 - t0);
+                a.sf = slot_f(t1 - 1 - t0);
+                a.xbar = xbar;
+                a.mu_in = MU[cur];
+                a.mu_out = MU[cur ^ 1];
+                a.yb = yb;
+                a.part = part + (size_t)3 * rp.nblk * (size_t)(t1 - 1);
+                a.slot0 = 0;
+                QPA_HIP(launch_rel_rows(REL_MODE_A, d_all, count, rp.rows, rp.C, 0, 0, a, st));
+                cur ^= 1;
+            }
+            for (int32_t t = t1 - 1; t > t0; --t) {    // B(t), then A(t - 1)
+                RelArgs a = base;
+                a.t_f = t;
+                a.t_a = t - 1;
+                a.sx = slot_x(t - 1 - t0);
+                a.sm = slot_m(t - 1 - t0);
+                a.sf = slot_f(t - 1 - t0);
+                a.mu_in = MU[cur];
+                a.mu_out = MU[cur ^ 1];
+                a.yb = yb;
+                a.part = part + (size_t)3 * rp.nblk * (size_t)(t - 1);
+                s = over_all(REL_MODE_BA, a);
+                if (s != QPA_OK) return s;
+                cur ^= 1;
+            }
+            {   // B(t0): xbar_{t0} for the segment before
+                RelArgs a = base;
+                a.t_f = t0;
+                a.mu_in = MU[cur];
+                a.yb = yb;
+                a.xbar = xbar;
+                s = over_all(REL_MODE_B, a);
+                if (s != QPA_OK) return s;
+            }
+        }
+    }
+    QPA_HIP(launch_rel_finish(T, rp.nblk, part, ploss, loss, grads ? d_eta : nullptr,
+                              grads ? d_alpha : nullptr, grads ? d_lambda : nullptr, st));
+    return QPA_OK;
+}
+
+}  // namespace
+}  // namespace qpa
+
+extern "C" {
+
+qpa_status qpa_workspace_size_relaxed_batch(qpa_ctx *ctx, int32_t count,
+                                            const qpa_problem *problems,
+                                            const qpa_params *params, int32_t ckpt_every,
+                                            size_t *bytes) {
+    if (!bytes) return fail(ctx, QPA_E_ARG, "bytes is NULL");
+    qpa_status s = check_params(ctx, params);
     if (s != QPA_OK) return s;
     RelPlan rp;
-    s = make_rel_plan(ctx, *problem, *params, ckpt_every, rp);
+    s = make_rel_plan(ctx, count, problems, *params, ckpt_every, rp);
     if (s != QPA_OK) return s;
     *bytes = rp.total;
     return QPA_OK;
+}
+
+qpa_status qpa_workspace_size_relaxed(qpa_ctx *ctx, const qpa_problem *problem,
+                                      const qpa_params *params, int32_t ckpt_every,
+                                      size_t *bytes) {
+    return qpa_workspace_size_relaxed_batch(ctx, 1, problem, params, ckpt_every, bytes);
+}
+
+qpa_status qpa_relaxed_grad_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *problems,
+                                  const qpa_params *params, int32_t ckpt_every, double scale,
+                                  void *workspace, size_t workspace_bytes, void *stream,
+                                  double *loss, double *d_eta, double *d_alpha,
+                                  double *d_lambda) {
+    return relaxed_run(ctx, count, problems, params, ckpt_every, scale, workspace,
+                       workspace_bytes, static_cast<hipStream_t>(stream), loss, d_eta, d_alpha,
+                       d_lambda);
 }
 
 qpa_status qpa_relaxed_grad(qpa_ctx *ctx, const qpa_problem *problem, const qpa_params *params,
                             int32_t ckpt_every, double scale, void *workspace,
                             size_t workspace_bytes, void *stream, double *loss, double *d_eta,
                             double *d_alpha, double *d_lambda) {
-    if (!ctx) return QPA_E_ARG;
-    ctx->err.clear();
-    qpa_status s = check_problem(ctx, problem);
-    if (s != QPA_OK) return s;
-    s = check_params(ctx, params);
-    if (s != QPA_OK) return s;
-    if (!loss || !d_eta || !d_alpha || (params->steps > 0 && !d_lambda))
-        return fail(ctx, QPA_E_ARG, "loss, d_eta, d_alpha and d_lambda are required");
-    RelPlan rp;
-    s = make_rel_plan(ctx, *problem, *params, ckpt_every, rp);
-    if (s != QPA_OK) return s;
-    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % ALIGN) != 0)
-        return fail(ctx, QPA_E_ARG, "workspace must be non-NULL and %zu-byte aligned", ALIGN);
-    if (workspace_bytes < rp.total)
-        return fail(ctx, QPA_E_WORKSPACE, "workspace has %zu bytes, %zu needed", workspace_bytes,
-                    rp.total);
-    QPA_HIP(hipSetDevice(ctx->device));
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    void *ws = workspace;
-    const Plan &pl = rp.base;
-    const qpa_problem &p = *problem;
-    s = upload_schedule(ctx, *params, at<float>(ws, pl.o_lam), st);
-    if (s != QPA_OK) return s;
-    s = canonicalise(ctx, p, pl, ws, st);
-    if (s != QPA_OK) return s;
-    // the schedule values are needed on the host to pass to the update kernels
-    std::vector<float> lam(params->steps);
-    for (int32_t t = 0; t < params->steps; ++t) lam[t] = ctx->host_lam[t];
-
-    const int64_t n = p.n, R = params->replicas, RN = R * n;
-    const float eta = params->eta, alpha = params->alpha;
-    const float *Jf = pl.o_Jf ? at<float>(ws, pl.o_Jf) : nullptr;
-    const float *bf = at<float>(ws, pl.o_bf);
-    const bool skip = pl.is_qubo;
-    float *ckpt = at<float>(ws, rp.o_ckpt), *seg = at<float>(ws, rp.o_seg);
-    float *f = at<float>(ws, rp.o_f), *xbar = at<float>(ws, rp.o_xbar);
-    float *mu = at<float>(ws, rp.o_mu), *jmu = at<float>(ws, rp.o_jmu);
-    double *part = at<double>(ws, rp.o_part), *ploss = at<double>(ws, rp.o_ploss);
-    float *x = at<float>(ws, pl.o_x), *m = at<float>(ws, pl.o_m);
-    const size_t RNB = sizeof(float) * (size_t)RN;
-    const int32_t T = params->steps, k = rp.k;
-
-    QPA_HIP(launch_init_state(n, R, params->seed, params->sigma0, x, m, n, 1, R, n, st));
-    QPA_HIP(hipMemcpyAsync(ckpt, x, RNB, hipMemcpyDeviceToDevice, st));
-    QPA_HIP(hipMemcpyAsync(ckpt + RN, m, RNB, hipMemcpyDeviceToDevice, st));
-    for (int32_t t = 0; t < T; ++t) {
-        QPA_HIP(launch_rel_apply(p, Jf, skip, R, x, f, st));
-        QPA_HIP(launch_rel_update(n, R, f, bf, lam[t], eta, alpha, x, m, st));
-        if ((t + 1) % k == 0 && (t + 1) < T) {
-            float *c = ckpt + (size_t)2 * RN * (size_t)((t + 1) / k);
-            QPA_HIP(hipMemcpyAsync(c, x, RNB, hipMemcpyDeviceToDevice, st));
-            QPA_HIP(hipMemcpyAsync(c + RN, m, RNB, hipMemcpyDeviceToDevice, st));
-        }
-    }
-    QPA_HIP(launch_rel_apply(p, Jf, skip, R, x, f, st));
-    QPA_HIP(launch_rel_loss(n, R, x, f, bf, scale, xbar, ploss, st));
-    QPA_HIP(hipMemsetAsync(mu, 0, RNB, st));
-    for (int32_t c = rp.nseg - 1; c >= 0; --c) {
-        const int32_t t0 = c * k, t1 = std::min(T, (c + 1) * k);
-        const float *cp = ckpt + (size_t)2 * RN * (size_t)c;
-        QPA_HIP(hipMemcpyAsync(x, cp, RNB, hipMemcpyDeviceToDevice, st));
-        QPA_HIP(hipMemcpyAsync(m, cp + RN, RNB, hipMemcpyDeviceToDevice, st));
-        for (int32_t t = t0; t < t1; ++t) {
-            float *sx = seg + (size_t)3 * RN * (size_t)(t - t0);
-            QPA_HIP(launch_rel_apply(p, Jf, skip, R, x, sx + 2 * RN, st));
-            QPA_HIP(hipMemcpyAsync(sx, x, RNB, hipMemcpyDeviceToDevice, st));
-            QPA_HIP(hipMemcpyAsync(sx + RN, m, RNB, hipMemcpyDeviceToDevice, st));
-            QPA_HIP(launch_rel_update(n, R, sx + 2 * RN, bf, lam[t], eta, alpha, x, m, st));
-        }
-        for (int32_t t = t1 - 1; t >= t0; --t) {
-            const float *sx = seg + (size_t)3 * RN * (size_t)(t - t0);
-            QPA_HIP(launch_rel_rev_a(n, R, sx, sx + RN, sx + 2 * RN, bf, lam[t], eta, alpha, xbar,
-                                     mu, part + (size_t)3 * rp.nblk * (size_t)t, st));
-            QPA_HIP(launch_rel_apply(p, Jf, skip, R, mu, jmu, st));
-            QPA_HIP(launch_rel_rev_b(RN, mu, jmu, lam[t], eta, xbar, st));
-        }
-    }
-    QPA_HIP(launch_rel_finish(T, rp.nblk, part, ploss, loss, d_eta, d_alpha, d_lambda, st));
-    return QPA_OK;
+    return relaxed_run(ctx, 1, problem, params, ckpt_every, scale, workspace, workspace_bytes,
+                       static_cast<hipStream_t>(stream), loss, d_eta, d_alpha, d_lambda);
 }
 
 qpa_status qpa_workspace_size_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *problems,

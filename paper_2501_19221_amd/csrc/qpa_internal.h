@@ -286,18 +286,58 @@ hipError_t launch_bin_step(const BinGeom &g, int64_t n, int64_t nwords, const in
                            float alpha, int cus, hipStream_t st);
 
 // ---- relaxed PA and its adjoint (FP32 state, FP64 inner products) -------------------
-int32_t rel_blocks(int64_t count);
-hipError_t launch_rel_apply(const qpa_problem &p, const float *Jf, bool skip_diag, int64_t R,
-                            const float *v, float *out, hipStream_t st);
-hipError_t launch_rel_update(int64_t n, int64_t R, const float *f, const float *b, float lam,
-                             float eta, float alpha, float *x, float *m, hipStream_t st);
-hipError_t launch_rel_loss(int64_t n, int64_t R, const float *x, const float *f, const float *b,
-                           double scale, float *xbar, double *part, hipStream_t st);
-hipError_t launch_rel_rev_a(int64_t n, int64_t R, const float *x, const float *m, const float *f,
-                            const float *b, float lam, float eta, float alpha, float *xbar,
-                            float *mu, double *part, hipStream_t st);
-hipError_t launch_rel_rev_b(int64_t count, const float *mu, const float *Jmu, float lam,
-                            float eta, float *xbar, hipStream_t st);
+// Every state vector of a relaxed pass is [rows][Rp] FP32 (replica fastest); instance k
+// of a batch owns global rows [row0, row0 + n).  Launch modes (see k_adjoint.hip):
+enum RelModeCode : int32_t { REL_MODE_FWD = 0, REL_MODE_LOSS = 1, REL_MODE_A = 2, REL_MODE_B = 3,
+                             REL_MODE_BA = 4 };
+// One instance of a row launch (a CSR gather, or the element-wise pass over all rows).
+struct RelInst {
+    const int32_t *rp;          // CSR row pointers (NULL: no gather; dense instances)
+    const void *col;
+    const void *w;
+    const float *b;             // canonical Ising field, n floats
+    int64_t n;
+    int64_t row0;               // first global row of the instance
+    int64_t item0;              // first row of the instance among the launch's rows
+    int32_t skip_diag;          // a QUBO: stored diagonal entries are skipped
+    int32_t pad_;
+};
+struct RelArgs {
+    int64_t Rp;
+    int32_t R;
+    int32_t t_f;               // schedule index of the forward step (FWD) or of B (B, BA)
+    int32_t t_a;               // schedule index of A (A, BA)
+    int32_t nblk;              // stride of the three rows of a step's partial table
+    int32_t slot0;             // first partial slot of this launch
+    const float *lam;          // device schedule table
+    float eta, alpha;
+    double scale;
+    const float *xi, *mi;      // FWD, LOSS: state of step t (xi also the product's input)
+    float *xo, *mo, *fo;       // FWD: state of step t+1, f_t (fo optional)
+    const float *sx, *sm, *sf; // A, BA: stored state of the A step
+    const float *mu_in;        // B, BA: mu_{t+1} (product input); A: mu_{t+2} (own)
+    float *mu_out;             // A, BA: mu of the A step
+    float *yb;                 // A, BA: ybar written; B, BA: ybar of B read (own)
+    float *xbar;               // LOSS, B: written; A: xbar_{t+1} read (own)
+    double *part;              // A, BA: partial table of the A step; LOSS: loss partials
+};
+constexpr int64_t REL_ROW_BLOCKS_MAX = 2048;
+// Workgroups of a row launch over `items` rows of C 64-replica chunks (each writes one
+// partial slot), and of the dense tiled product of an n-row instance.
+int64_t rel_row_blocks(int64_t items, int32_t C);
+int64_t rel_tile_blocks(int64_t n, int64_t Rp);
+// Row launch over a device table of instances sharing coupling / index types (wdt, idt;
+// ignored by REL_MODE_A), `items` = the sum of their n.
+hipError_t launch_rel_rows(int32_t mode, const RelInst *insts, int32_t ninst, int64_t items,
+                           int32_t C, int32_t wdt, int32_t idt, const RelArgs &a,
+                           hipStream_t st);
+// Dense instance (FP32 canonical J, n x n) through the tiled product; the state pointers
+// of `a` point at the instance's first row (Rp a multiple of 128).  Not REL_MODE_A.
+hipError_t launch_rel_tiles(int32_t mode, int64_t n, const float *J, const float *b,
+                            const RelArgs &a, hipStream_t st);
+hipError_t launch_rel_fill(double *p, int64_t count, hipStream_t st);
+// loss = sum of the loss partials; d_lam[t] (if non-NULL), d_eta, d_alpha from the
+// per-step tables [T][3][nblk], all in a fixed order.
 hipError_t launch_rel_finish(int32_t T, int32_t nblk, const double *part_steps,
                              const double *part_loss, double *loss, double *d_eta,
                              double *d_alpha, double *d_lam, hipStream_t st);

@@ -53,7 +53,7 @@ EXPORTED = ["qpa_create", "qpa_destroy", "qpa_last_error", "qpa_status_string",
             "qpa_profile_read_path", "qpa_batch_paths", "qpa_workspace_size_sbm",
             "qpa_sbm_solve", "qpa_sbm_steps", "qpa_spectral_radius",
             "qpa_workspace_size_spectrum", "qpa_spectrum", "qpa_autotune", "qpa_tune_set",
-            "qpa_solve_noalloc"]
+            "qpa_solve_noalloc", "qpa_workspace_size_relaxed_batch", "qpa_relaxed_grad_batch"]
 QPA_NOALLOC_WORKSPACE_BYTES = 64 << 20
 QPA_NOALLOC_MAX_STEPS = 65536
 
@@ -118,6 +118,12 @@ _sig = {
     "qpa_relaxed_grad": (_S, [_P, ctypes.POINTER(qpa_problem), ctypes.POINTER(qpa_params),
                               ctypes.c_int32, ctypes.c_double, _P, ctypes.c_size_t, _P, _P, _P,
                               _P, _P]),
+    "qpa_workspace_size_relaxed_batch": (_S, [_P, ctypes.c_int32, ctypes.POINTER(qpa_problem),
+                                              ctypes.POINTER(qpa_params), ctypes.c_int32,
+                                              ctypes.POINTER(ctypes.c_size_t)]),
+    "qpa_relaxed_grad_batch": (_S, [_P, ctypes.c_int32, ctypes.POINTER(qpa_problem),
+                                    ctypes.POINTER(qpa_params), ctypes.c_int32, ctypes.c_double,
+                                    _P, ctypes.c_size_t, _P, _P, _P, _P, _P]),
     "qpa_profile_enable": (_S, [_P, ctypes.c_int32]),
     "qpa_profile_read": (_S, [_P, ctypes.POINTER(ctypes.c_double),
                               ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]),
@@ -241,6 +247,22 @@ def qpa_relaxed_grad(ctx, problem, params, ckpt_every, scale, workspace, workspa
     _check(ctx, _lib.qpa_relaxed_grad(ctx, ctypes.byref(problem), ctypes.byref(params),
                                       ckpt_every, scale, workspace, workspace_bytes, stream,
                                       loss, d_eta, d_alpha, d_lambda))
+
+
+def qpa_workspace_size_relaxed_batch(ctx, problems, params, ckpt_every) -> int:
+    """problems: a ctypes array of qpa_problem."""
+    nbytes = ctypes.c_size_t()
+    _check(ctx, _lib.qpa_workspace_size_relaxed_batch(ctx, len(problems), problems,
+                                                      ctypes.byref(params), ckpt_every,
+                                                      ctypes.byref(nbytes)))
+    return nbytes.value
+
+
+def qpa_relaxed_grad_batch(ctx, problems, params, ckpt_every, scale, workspace,
+                           workspace_bytes, stream, loss, d_eta, d_alpha, d_lambda):
+    _check(ctx, _lib.qpa_relaxed_grad_batch(ctx, len(problems), problems, ctypes.byref(params),
+                                            ckpt_every, scale, workspace, workspace_bytes,
+                                            stream, loss, d_eta, d_alpha, d_lambda))
 
 
 def qpa_profile_enable(ctx, enable: bool):
@@ -513,21 +535,29 @@ class Engine:
                         self._stream(), oa)
         return outs
 
-    def relaxed_grad(self, prob: Problem, params: qpa_params, ckpt_every: int, scale=None):
+    def relaxed_grad(self, prob, params: qpa_params, ckpt_every: int, scale=None,
+                     grads=True):
         """Loss and gradients of the relaxed final energy (device float64 tensors):
-        (loss [1], d_eta [1], d_alpha [1], d_lambda [T])."""
+        (loss [1], d_eta [1], d_alpha [1], d_lambda [T]).  `prob` is one Problem or a list
+        of them (a batch sharing params; instance k starts from seed + k); the default
+        scale is the mean over all replicas of all instances.  grads=False runs the
+        forward pass only and returns (loss, None, None, None)."""
         torch = self.torch
         dev = "cuda:%d" % self.device
-        ps = prob.struct()
-        nbytes = qpa_workspace_size_relaxed(self.ctx, ps, params, ckpt_every)
+        probs = list(prob) if isinstance(prob, (list, tuple)) else [prob]
+        pa = (qpa_problem * len(probs))(*[p.struct() for p in probs])
+        nbytes = qpa_workspace_size_relaxed_batch(self.ctx, pa, params, ckpt_every)
         if self._ws is None or self._ws.numel() < nbytes:
             self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dev)
-        scale = 1.0 / params.replicas if scale is None else scale
+        scale = 1.0 / (params.replicas * len(probs)) if scale is None else scale
         out = [torch.empty(1, dtype=torch.float64, device=dev) for _ in range(3)]
         dl = torch.empty(max(params.steps, 1), dtype=torch.float64, device=dev)
-        qpa_relaxed_grad(self.ctx, ps, params, ckpt_every, scale,
-                         ctypes.c_void_p(self._ws.data_ptr()), nbytes, self._stream(),
-                         _ptr(out[0]), _ptr(out[1]), _ptr(out[2]), _ptr(dl))
+        qpa_relaxed_grad_batch(self.ctx, pa, params, ckpt_every, scale,
+                               ctypes.c_void_p(self._ws.data_ptr()), nbytes, self._stream(),
+                               _ptr(out[0]), _ptr(out[1]) if grads else None,
+                               _ptr(out[2]) if grads else None, _ptr(dl) if grads else None)
+        if not grads:
+            return out[0], None, None, None
         return out[0], out[1], out[2], dl[:params.steps]
 
     def steps(self, prob: Problem, params: qpa_params, t0: int, t1: int, x, m, want_h=False):
@@ -650,9 +680,11 @@ class RelaxedEnergy:
 
     ``RelaxedEnergy.apply(eta, alpha, lam, engine, problem, replicas, sigma0, seed,
     ckpt_every)`` with 0-d float64 tensors eta, alpha and a 1-d float64 tensor lam of
-    length T returns the loss; its backward is the library's hand-written adjoint
-    (qpa_relaxed_grad), so gradients flow into whatever produced eta, alpha and lam
-    (e.g. lam = lambda0 * (1 - t/T))."""
+    length T returns the loss -- the mean over the replicas (and over the instances when
+    `problem` is a list of Problems, instance k starting from seed + k).  Its backward is
+    the library's hand-written adjoint (qpa_relaxed_grad_batch), so gradients flow into
+    whatever produced eta, alpha and lam (e.g. lam = lambda0 * (1 - t/T)); when no input
+    needs a gradient only the forward pass runs."""
 
     @staticmethod
     def _fn():
@@ -665,9 +697,11 @@ class RelaxedEnergy:
                 table = lam.detach().cpu().numpy().astype(np.float32)
                 p = make_params(replicas, T, float(eta), float(alpha), 0.0, sigma0, seed,
                                 QPA_PREC_FP32, lambda_table=table)
-                loss, de, da, dl = engine.relaxed_grad(problem, p, ckpt)
-                ctx.save_for_backward(de.to(eta.device), da.to(alpha.device),
-                                      dl.to(lam.device))
+                grads = any(ctx.needs_input_grad[:3])
+                loss, de, da, dl = engine.relaxed_grad(problem, p, ckpt, grads=grads)
+                if grads:
+                    ctx.save_for_backward(de.to(eta.device), da.to(alpha.device),
+                                          dl.to(lam.device))
                 return loss[0].to(eta.device)
 
             @staticmethod

@@ -1,0 +1,224 @@
+"""The relaxed adjoint (App. B dynamics with analog spins in the target part) at the batch
+workload's shape: ER QUBOs with p = 0.1 and int16 weights in [-100, 100], T = 500 steps,
+a checkpoint every 50, the batch workload's (eta, alpha, lambda0), the mean over every
+replica of a batch of instances.
+
+Two references, both on the GPU's initial states:
+* the oracle's single-precision pass (FP32 state and adjoint vectors, one fused
+  multiply-add per product term in ascending column order, FP64 inner products): the
+  same arithmetic as the GPU, so the trajectories and clip decisions are identical and
+  the loss and gradients agree up to the order of the FP64 sums (1e-12 and 1e-9
+  relative);
+* the oracle's FP64 pass, the reference of the mathematics (pinned to central
+  differences on the CPU): the loss is piecewise smooth, and where some |y| falls
+  within FP32 rounding of 1 a clip is decided the other way, which moves the gradient by
+  more than rounding (about 2e-3 of it at n = 2000).  The GPU must be no farther from
+  it than the FP32 oracle is (plus 1e-6 of the value).
+Differences of the FP32 loss are not used: a step large enough to rise above FP32
+rounding crosses clip kinks (see the CPU test of that property).
+"""
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+import oracle as orc
+from paper_2501_19221_amd import instances as gen
+from paper_2501_19221_amd.configs import WORKLOADS
+
+pytestmark = pytest.mark.gpu
+
+WL = WORKLOADS["er512"]
+T, K = WL.steps, 50
+ETA, ALPHA = float(np.float32(WL.eta)), float(np.float32(WL.alpha))
+
+
+def say(msg):
+    print("[gpu-adjoint] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def q():
+    from paper_2501_19221_amd import qpa
+    return qpa
+
+
+@pytest.fixture(scope="module")
+def eng(q):
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    e = q.Engine(0)
+    yield e
+    e.close()
+
+
+def host(t):
+    return None if t is None else t.detach().cpu().numpy()
+
+
+def _lam():
+    return orc.lambda_linear(T, WL.lambda0)
+
+
+def _params(q, R, seed, lam=None):
+    return q.make_params(R, T, WL.eta, WL.alpha, WL.lambda0, WL.sigma0, seed,
+                         lambda_table=_lam() if lam is None else lam)
+
+
+def _oracle(inst, R, seed, norm):
+    """(FP32 pass, FP64 pass) of the oracle for one instance, each (L, d_eta, d_alpha,
+    d_lambda) scaled by norm."""
+    x0, _ = orc.pa_init(inst.n, R, seed, np.float32(WL.sigma0))
+    lam = _lam()
+    if inst.dense is not None:
+        J, b = inst.dense, inst.lin
+        r32 = orc.relaxed_grad32_dense(J, b, x0, T, lam, ETA, ALPHA, norm=norm)
+        r64 = orc.relaxed_grad_dense(J.astype(np.float64), b.astype(np.float64), x0, T,
+                                     lam.astype(np.float64), ETA, ALPHA, norm=norm)
+        return r32[:4], r64
+    c = inst.csr
+    rp, col, w, b, _ = orc.qubo_to_ising_csr_int(c.rp, c.col, c.w, inst.lin)
+    r32 = orc.relaxed_grad32_csr(rp, col, w, b, x0, T, lam, ETA, ALPHA, norm=norm)
+    r64 = orc.relaxed_grad_csr(rp, col, w.astype(np.float64), b.astype(np.float64), x0, T,
+                               lam.astype(np.float64), ETA, ALPHA, norm=norm)
+    return r32[:4], r64
+
+
+def _sum(parts):
+    """Sum of per-instance (FP32, FP64) oracle results."""
+    def one(rs):
+        return (sum(r[0] for r in rs), sum(r[1] for r in rs), sum(r[2] for r in rs),
+                np.sum([r[3] for r in rs], axis=0))
+    return one([p[0] for p in parts]), one([p[1] for p in parts])
+
+
+def _rel(got, ref):
+    """Differences relative to the reference's magnitude (absolute where it is zero: a
+    fully clipped instance has a gradient of exactly zero)."""
+    L, de, da, dl = got
+    Lo, deo, dao, dlo = ref
+    base = 1.0 - np.arange(T) / T
+    d = lambda a, b: abs(a - b) / (abs(b) if b != 0 else 1.0)
+    return {"loss": d(L, Lo), "d_eta": d(de, deo), "d_alpha": d(da, dao),
+            "d_lambda": float(np.max(np.abs(dl - dlo)) / max(np.max(np.abs(dlo)), 1e-300)
+                              if np.any(dlo) else np.max(np.abs(dl))),
+            "d_lambda0": d(float(np.dot(dl, base)), float(np.dot(dlo, base)))}
+
+
+def _compare(tag, got, refs, nontrivial=True):
+    ref32, ref64 = refs
+    r32, r64, o64 = _rel(got, ref32), _rel(got, ref64), _rel(ref32, ref64)
+    fmt = lambda d: ", ".join("%s %.2e" % kv for kv in d.items())
+    say("%s: loss %.9g, d_eta %.9g, d_alpha %.9g" % (tag, got[0], got[1], got[2]))
+    say("   vs FP32 oracle: %s" % fmt(r32))
+    say("   vs FP64 oracle: %s (FP32 oracle vs FP64: %s)" % (fmt(r64), fmt(o64)))
+    if nontrivial:                                         # a non-trivial gradient is checked
+        assert abs(ref64[1]) > 1.0 and abs(ref64[2]) > 1e-3
+    assert r32["loss"] <= 1e-12
+    for key in ("d_eta", "d_alpha", "d_lambda", "d_lambda0"):
+        assert r32[key] <= 1e-9, key
+        assert r64[key] <= o64[key] + 1e-6, key
+    assert r64["loss"] <= o64["loss"] + 1e-12
+
+
+def _gpu(q, eng, probs, p, k=K, grads=True, scale=None):
+    """(loss, d_eta, d_alpha, d_lambda[T]) on the host; gradients None for grads=False."""
+    L, de, da, dl = eng.relaxed_grad(probs, p, k, scale=scale, grads=grads)
+    if not grads:
+        return float(host(L)[0]), None, None, None
+    return float(host(L)[0]), float(host(de)[0]), float(host(da)[0]), host(dl)
+
+
+def test_batch_of_er_qubos_against_oracle(q, eng):
+    """Three ER QUBOs of n = 100, 1000, 2000 in one batch (16 replicas each): the batch mean
+    against the sum of the oracle's per-instance losses and gradients."""
+    insts = [gen.er_qubo(n, 0.1, 100, np.random.default_rng(40 + n)) for n in (100, 1000, 2000)]
+    R, seed = 16, 7
+    norm = 1.0 / (R * len(insts))
+    with ThreadPoolExecutor(len(insts)) as ex:
+        futs = [ex.submit(_oracle, inst, R, seed + k, norm) for k, inst in enumerate(insts)]
+        probs = [q.Problem.from_instance(i) for i in insts]
+        say("batch of 3 ER QUBOs, R=%d T=%d k=%d" % (R, T, K))
+        got = _gpu(q, eng, probs, _params(q, R, seed))
+        ref = _sum([f.result() for f in futs])
+    _compare("batch n=100,1000,2000", got, ref)
+
+
+def test_single_er_qubo_64_replicas_against_oracle(q, eng):
+    inst = gen.er_qubo(1000, 0.1, 100, np.random.default_rng(3))
+    R, seed = 64, 11
+    with ThreadPoolExecutor(1) as ex:
+        fut = ex.submit(_oracle, inst, R, seed, 1.0 / R)
+        say("ER QUBO n=1000 R=64 T=%d k=%d" % (T, K))
+        got = _gpu(q, eng, q.Problem.from_instance(inst), _params(q, R, seed))
+        ref = fut.result()
+    _compare("n=1000 R=64", got, ref)
+
+
+def test_mixed_dense_and_sparse_batch_against_oracle(q, eng):
+    """A dense SK instance (tiled product, replicas padded to 128) and two ER QUBOs of
+    different index types in one batch."""
+    sk = gen.sk_ising(300, 0.1, seed=8)
+    er1 = gen.er_qubo(500, 0.1, 100, np.random.default_rng(9))
+    er2 = gen.er_qubo(400, 0.1, 100, np.random.default_rng(10), idx_dtype=np.int32)
+    insts = [er1, sk, er2]
+    R, seed = 20, 5
+    norm = 1.0 / (R * len(insts))
+    with ThreadPoolExecutor(len(insts)) as ex:
+        futs = [ex.submit(_oracle, inst, R, seed + k, norm) for k, inst in enumerate(insts)]
+        say("mixed batch (CSR int16, dense SK, CSR int32), R=%d" % R)
+        got = _gpu(q, eng, [q.Problem.from_instance(i) for i in insts], _params(q, R, seed))
+        ref = _sum([f.result() for f in futs])
+    _compare("mixed batch", got, ref)
+
+
+def test_checkpoint_interval_and_forward_only(q, eng):
+    """Bitwise the same loss and gradients for every checkpoint interval; the forward-only
+    call returns the same loss bits."""
+    inst = gen.er_qubo(900, 0.1, 100, np.random.default_rng(21))
+    prob = q.Problem.from_instance(inst)
+    p = _params(q, 64, 2)
+    say("checkpoint intervals 50, 500, 7, 1 at n=900 R=64")
+    ref = _gpu(q, eng, prob, p, 50)
+    for k in (500, 7, 1):
+        got = _gpu(q, eng, prob, p, k)
+        assert got[0] == ref[0] and got[1] == ref[1] and got[2] == ref[2], k
+        assert np.array_equal(got[3], ref[3]), k
+    fwd = _gpu(q, eng, prob, p, 50, grads=False)
+    assert fwd[0] == ref[0] and fwd[1] is None
+
+
+def test_full_batch_workload(q, eng):
+    """All 512 instances of the batch workload (64 replicas, T = 500, k = 50): finite, and
+    equal (up to the order of the final FP64 sums) to the sum of the two halves run as
+    separate batches with their seeds; three sampled instances (smallest, largest, first)
+    run alone with their batch seeds match the oracle."""
+    import time
+    insts = WL.make()
+    cnt, R = len(insts), WL.replicas
+    probs = [q.Problem.from_instance(i) for i in insts]
+    say("er512 relaxed gradient: %d instances, R=%d, T=%d, k=%d" % (cnt, R, T, K))
+    t0 = time.time()
+    full = _gpu(q, eng, probs, _params(q, R, WL.seed), K)
+    say("full batch in %.2f s: loss %.6g d_eta %.6g d_alpha %.6g"
+        % (time.time() - t0, full[0], full[1], full[2]))
+    assert all(np.isfinite(v).all() for v in [full[0], full[1], full[2], full[3]])
+    h = cnt // 2
+    scale = 1.0 / (R * cnt)
+    lo = _gpu(q, eng, probs[:h], _params(q, R, WL.seed), K, scale=scale)
+    hi = _gpu(q, eng, probs[h:], _params(q, R, WL.seed + h), K, scale=scale)
+    for a_, b_, c_ in zip(full, lo, hi):
+        s = np.asarray(b_) + np.asarray(c_)
+        assert np.allclose(a_, s, rtol=1e-9, atol=1e-12 * np.max(np.abs(a_))), (a_, s)
+    ns = np.array([i.n for i in insts])
+    for k in sorted({int(np.argmin(ns)), int(np.argmax(ns)), 0}):
+        inst = insts[k]
+        Rk = 16
+        with ThreadPoolExecutor(1) as ex:
+            fut = ex.submit(_oracle, inst, Rk, WL.seed + k, 1.0 / Rk)
+            got = _gpu(q, eng, probs[k], _params(q, Rk, WL.seed + k))
+            ref = fut.result()
+        _compare("er512 instance %d (n=%d, 16 replicas)" % (k, inst.n), got, ref,
+                 nontrivial=False)

@@ -496,6 +496,119 @@ def test_relaxed_adjoint_vs_finite_differences(orc, fmt):
         assert abs(dl[t] - ft) <= 1e-6 * max(1.0, abs(ft))
 
 
+def _er_ising(orc, n, seed):
+    """An ER QUBO shaped like the batch workload (p = 0.1, int16 weights in [-100, 100]) in
+    its canonical Ising form (App. A), as float64 CSR."""
+    inst = gen.er_qubo(n, 0.1, 100, np.random.default_rng(seed))
+    c = inst.csr
+    rp, col, w, b, _ = orc.qubo_to_ising_csr_int(c.rp, c.col, c.w, inst.lin)
+    return rp, col, w.astype(np.float64), b.astype(np.float64)
+
+
+def test_relaxed_adjoint_at_batch_workload_shape(orc):
+    """The adjoint at the batch workload's dynamics (T = 500, eta = 2e-4, alpha = 0.8,
+    lambda0 = 200) on an ER QUBO with n = 700: central differences with small steps
+    (relative 1e-8 .. 1e-7, where no clip kink falls between the two evaluations) agree
+    with it; most of x is clipped by the end, yet the gradient is far from zero."""
+    rp, col, w, b = _er_ising(orc, 700, 12)
+    R, T, eta, alpha, lam0 = 8, 500, float(np.float32(2e-4)), float(np.float32(0.8)), 200.0
+    base = 1.0 - np.arange(T) / T
+    x0, _ = orc.pa_init(700, R, 1, np.float32(0.1))
+
+    def run(eta_, alpha_, lam_, grads=False):
+        return orc.relaxed_grad_csr(rp, col, w, b, x0, T, lam_, eta_, alpha_, grads=grads)
+
+    L, de, da, dl = run(eta, alpha, lam0 * base, grads=True)
+    dl0 = float(np.dot(dl, base))
+    assert abs(de) > 1e3 and abs(da) > 1.0
+    for h in (1e-8, 1e-7):
+        fe = (run(eta * (1 + h), alpha, lam0 * base)[0]
+              - run(eta * (1 - h), alpha, lam0 * base)[0]) / (2 * h * eta)
+        fa = (run(eta, alpha + h, lam0 * base)[0] - run(eta, alpha - h, lam0 * base)[0]) / (2 * h)
+        fl = (run(eta, alpha, lam0 * (1 + h) * base)[0]
+              - run(eta, alpha, lam0 * (1 - h) * base)[0]) / (2 * h * lam0)
+        assert abs(de - fe) <= 1e-2 * abs(de), (h, de, fe)
+        assert abs(da - fa) <= 1e-2 * abs(da), (h, da, fa)
+        assert abs(dl0 - fl) <= 1e-2 * max(abs(dl0), 1e-3), (h, dl0, fl)
+
+
+def test_relaxed_loss_is_piecewise_smooth_across_clip_kinks(orc):
+    """Where every x ends clipped the relaxed loss is locally constant and its derivative
+    exactly zero; a difference step of 1 % of eta crosses the parameters at which some
+    element changes the step it is clipped at, so the difference quotient there is not the
+    derivative, while small steps recover it.  A smooth case (dense couplings, same
+    dynamics) shows the same convergence: 1 % is off by several per cent, 1e-4 agrees."""
+    inst = gen.chimera_ising(3, seed=22)
+    c = inst.csr
+    R, T = 8, 120
+    eta, alpha = float(np.float32(0.05)), float(np.float32(0.7))
+    lam = orc.lambda_linear(T, 1.5).astype(np.float64)
+    x0, _ = orc.pa_init(inst.n, R, 3, np.float32(0.1))
+    w, b = c.w.astype(np.float64), inst.lin.astype(np.float64)
+
+    def loss(e, a):
+        return orc.relaxed_grad_csr(c.rp, c.col, w, b, x0, T, lam, e, a, grads=False)[0]
+
+    L, de, da, _ = orc.relaxed_grad_csr(c.rp, c.col, w, b, x0, T, lam, eta, alpha)
+    assert de == 0.0 and da == 0.0
+    big = (loss(eta * 1.01, alpha) - loss(eta * 0.99, alpha)) / (0.02 * eta)
+    assert abs(big) > 1.0
+    for h in (1e-4, 1e-6):
+        assert (loss(eta * (1 + h), alpha) - loss(eta * (1 - h), alpha)) == 0.0
+    inst = gen.sk_ising(64, 0.1, seed=21)
+    J = inst.dense.astype(np.float64)
+    xd, _ = orc.pa_init(64, R, 3, np.float32(0.1))
+
+    def dloss(e):
+        return orc.relaxed_grad_dense(J, inst.lin, xd, T, lam, e, alpha, grads=False)[0]
+
+    _, de, _, _ = orc.relaxed_grad_dense(J, inst.lin, xd, T, lam, eta, alpha)
+    fd1 = (dloss(eta * 1.01) - dloss(eta * 0.99)) / (0.02 * eta)
+    fd4 = (dloss(eta * (1 + 1e-4)) - dloss(eta * (1 - 1e-4))) / (2e-4 * eta)
+    assert abs(fd1 - de) > 0.03 * abs(de)
+    assert abs(fd4 - de) < 1e-3 * abs(de)
+
+
+@pytest.mark.parametrize("fmt", ["dense", "csr"])
+def test_relaxed_single_precision_pass_tracks_fp64(orc, fmt):
+    """The single-precision relaxed pass against the FP64 one (itself pinned by finite
+    differences above) on the same smooth case: loss and gradients within 1e-5."""
+    inst = gen.chimera_ising(m=2, seed=3)
+    c = inst.csr
+    n = inst.n
+    b = np.random.default_rng(5).normal(0, 0.3, n)
+    x0, _ = orc.pa_init(n, 4, 3, np.float32(0.2))
+    T, eta, alpha = 60, float(np.float32(0.05)), float(np.float32(0.7))
+    lam = orc.lambda_linear(T, 1.2)
+    if fmt == "dense":
+        D = c.to_dense(np.float64)
+        r32 = orc.relaxed_grad32_dense(D.astype(np.float32), b, x0, T, lam, eta, alpha)
+        r64 = orc.relaxed_grad_dense(D, b.astype(np.float32).astype(np.float64), x0, T,
+                                     lam.astype(np.float64), eta, alpha)
+    else:
+        r32 = orc.relaxed_grad32_csr(c.rp, c.col, c.w, b, x0, T, lam, eta, alpha)
+        r64 = orc.relaxed_grad_csr(c.rp, c.col, c.w.astype(np.float64),
+                                   b.astype(np.float32).astype(np.float64), x0, T,
+                                   lam.astype(np.float64), eta, alpha)
+    assert abs(r32[1]) > 0.1 and abs(r32[2]) > 0.01
+    for a_, b_ in zip(r32[:3], r64[:3]):
+        assert abs(a_ - b_) <= 1e-5 * max(1.0, abs(b_))
+    assert np.max(np.abs(r32[3] - r64[3])) <= 1e-5 * max(1.0, np.max(np.abs(r64[3])))
+
+
+def test_relaxed_single_precision_without_couplings_is_pa(orc):
+    """With J = 0 the single-precision relaxed pass takes the PA steps bit for bit."""
+    n, T = 16, 30
+    b = np.linspace(-1, 1, n).astype(np.float32)
+    x0, _ = orc.pa_init(n, 3, 1, np.float32(0.3))
+    lam = orc.lambda_linear(T, 1.0)
+    *_, xT = orc.relaxed_grad32_dense(np.zeros((n, n), np.float32), b, x0, T, lam, 0.05, 0.5,
+                                      grads=False)
+    x, m = x0.copy(), np.zeros_like(x0)
+    orc.pa_steps_dense_float(np.zeros((n, n), np.float32), b, x, m, 0, T, lam, 0.05, 0.5)
+    assert np.array_equal(xT, x)
+
+
 def test_relaxed_forward_equals_pa_without_couplings(orc):
     """With J = 0 the relaxed (s := x) and binarised dynamics coincide."""
     n, T = 16, 30
