@@ -11,9 +11,11 @@ path is timed once beside it, and both best energies are compared in FP64 ("BF16
 form at matched best energy").
 
     python bench.py [--steps K] [--warmup W]
-                    [--workload sk4096|chimera16|dense20|er512|planted3r|sbm_sk4096|sbm_chimera16]
+                    [--workload sk4096|chimera16|dense20|er512|planted3r|sbm_sk4096|sbm_chimera16
+                                |er512_grad]
 
-The sbm_* workloads time whole Simulated Bifurcation Machine solves (App. B) instead.
+The sbm_* workloads time whole Simulated Bifurcation Machine solves (App. B) instead;
+er512_grad times the relaxed-energy gradient of the whole er512 batch.
 """
 from __future__ import annotations
 
@@ -123,14 +125,50 @@ def measured_peaks(torch):
     return out
 
 
-def cpu_baseline(inst, wl, prec, target_s=15.0):
+# Host threads the CPU baseline may use: the CPUs this process may run on, at most 16 (the
+# host share of one GPU on the measurement machines, whatever the machine's count is).
+HOST_THREADS_MAX = 16
+
+
+def host_cpus():
+    """What the host offers: logical CPUs of the machine, CPUs this process may run on, the
+    threads the baseline uses, and the CPU model name."""
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        allowed = os.cpu_count() or 1
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"machine_cpus": os.cpu_count(), "allowed_cpus": allowed,
+            "threads": max(1, min(HOST_THREADS_MAX, allowed)), "model": model}
+
+
+def _both_rates(rate_fn, target_s):
+    """The oracle on one thread, then on every thread the baseline may use."""
+    hc = host_cpus()
+    one = rate_fn(1, target_s / 2)
+    r = rate_fn(hc["threads"], target_s / 2) if hc["threads"] > 1 else dict(one)
+    r["value_1core"] = one["value"]
+    r["sample_1core"] = "%d replicas x %d steps, %.1f s wall on 1 thread" % (
+        one["reps"], one["steps"], one["seconds"])
+    r["host"] = hc
+    return r
+
+
+def cpu_baseline(inst, wl, prec, target_s=20.0):
     """The CPU oracle (untuned) on a bounded sample of the same workload: a set of replicas
     split over host threads (the oracle releases the GIL), initialised outside the timing,
     run for a number of PA steps chosen from a short probe so that the timed part takes
-    about target_s (steps beyond the schedule's T continue from the state, restarting the
-    schedule)."""
+    about target_s / 2 (steps beyond the schedule's T continue from the state, restarting
+    the schedule); once on one thread and once on every thread the baseline may use."""
     import oracle as orc
-    cores = max(1, min(16, os.cpu_count() or 1))
     n = inst.n
     lam = orc.lambda_linear(wl.steps, wl.lambda0)
     if inst.dense is not None and not np.issubdtype(inst.dense.dtype, np.integer):
@@ -157,7 +195,8 @@ def cpu_baseline(inst, wl, prec, target_s=15.0):
 
         def steps_fn(x, m, t0, t1):
             orc.pa_steps_csr_int(rp, col, w, b, x, m, t0, t1, lam, wl.eta, wl.alpha)
-    r = _oracle_rate(n, wl.replicas, wl.steps, wl.seed, wl.sigma0, steps_fn, cores, target_s)
+    r = _both_rates(lambda cores, ts: _oracle_rate(n, wl.replicas, wl.steps, wl.seed, wl.sigma0,
+                                                   steps_fn, cores, ts), target_s)
     r["sample"] = "%d replicas x %d PA steps of the same instance (%s couplings), " \
                   "%.1f s wall on %d threads" % (r.pop("reps"), r.pop("steps"), kind,
                                                  r.pop("seconds"), r["cores"])
@@ -202,12 +241,11 @@ def _oracle_rate(n, R, T, seed, sigma0, steps_fn, cores, target_s):
             "kind": "oracle", "reps": reps, "steps": steps, "seconds": dt}
 
 
-def cpu_baseline_sbm(inst, swl, target_s=15.0):
+def cpu_baseline_sbm(inst, swl, target_s=20.0):
     """The CPU oracle's SBM steps on a bounded sample of the same workload (see
-    _oracle_rate); c0 = 1 / rho from the oracle's own power method when the workload asks
-    for it."""
+    _oracle_rate), on one thread and on every thread the baseline may use; c0 = 1 / rho
+    from the oracle's own power method when the workload asks for it."""
     import oracle as orc
-    cores = max(1, min(16, os.cpu_count() or 1))
     n = inst.n
     if inst.dense is not None:
         J = np.asarray(inst.dense, np.float32)
@@ -226,7 +264,8 @@ def cpu_baseline_sbm(inst, swl, target_s=15.0):
     else:
         def steps_fn(q, p, t0, t1):
             orc.sbm_steps_csr(rp, col, w, b, q, p, t0, t1, swl.steps, swl.a0, c0, swl.dt)
-    r = _oracle_rate(n, swl.replicas, swl.steps, swl.seed, swl.sigma0, steps_fn, cores, target_s)
+    r = _both_rates(lambda cores, ts: _oracle_rate(n, swl.replicas, swl.steps, swl.seed,
+                                                   swl.sigma0, steps_fn, cores, ts), target_s)
     r["sample"] = "%d replicas x %d SBM steps of the same instance, %.1f s wall on %d " \
                   "threads" % (r.pop("reps"), r.pop("steps"), r.pop("seconds"), r["cores"])
     return r
@@ -342,6 +381,44 @@ def bench_sbm(a, torch, qpa, swl):
     print(json.dumps(res), flush=True)
 
 
+def bench_relaxed(a, torch, qpa, wl, ckpt=50):
+    """One benchmark step = the mean relaxed final energy of the whole batch and its
+    gradient with respect to (eta, alpha, lambda_t): forward pass with a checkpoint every
+    `ckpt` steps, recomputation of each segment and the reverse pass (App. B dynamics with
+    analog spins in the target part)."""
+    log("generating workload %s" % wl.name)
+    insts = wl.make()
+    eng = qpa.Engine(0)
+    probs = [qpa.Problem.from_instance(i) for i in insts]
+    R, T = wl.replicas, wl.steps
+    params = qpa.make_params(R, T, wl.eta, wl.alpha, wl.lambda0, wl.sigma0, wl.seed)
+    torch.cuda.synchronize()
+    for w in range(a.warmup):
+        eng.relaxed_grad(probs, params, ckpt)
+        torch.cuda.synchronize()
+        log("warmup %d done" % w)
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        L, de, da, dl = eng.relaxed_grad(probs, params, ckpt)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n_total = sum(i.n for i in insts)
+    nnz = sum(i.csr.nnz for i in insts)
+    res = {"metric": "relaxed-gradient spin-steps/s (n x replicas x steps / s; forward, "
+                     "recomputation and reverse pass)",
+           "value": n_total * R * T * a.steps / dt, "unit": "spin-steps/s", "n_gpus": 1,
+           "steps": a.steps, "warmup": a.warmup, "ms_per_step": dt / a.steps * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "er512_grad", "description": wl.note, "n": n_total,
+                      "nnz": nnz, "instances": len(insts), "replicas": R, "pa_steps": T,
+                      "checkpoint_every": ckpt, "parallelism": "single GPU"},
+           "loss": float(L.cpu()[0]), "d_eta": float(de.cpu()[0]),
+           "d_alpha": float(da.cpu()[0])}
+    eng.close()
+    print(json.dumps(res), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -359,6 +436,9 @@ def main():
     if a.workload in SBM_WORKLOADS:
         bench_sbm(a, torch, qpa, SBM_WORKLOADS[a.workload])
         return
+    if a.workload == "er512_grad":
+        bench_relaxed(a, torch, qpa, WORKLOADS["er512"])
+        return
     wl = WORKLOADS[a.workload]
     log("generating workload %s" % wl.name)
     made = wl.make()
@@ -372,6 +452,11 @@ def main():
     R, T = wl.replicas, wl.steps
     params = qpa.make_params(R, T, wl.eta, wl.alpha, wl.lambda0, wl.sigma0, wl.seed, pcode)
     tuned = None
+    if batch:
+        # batch path rates measured by the library's batch autotuner (set-up, not timed)
+        dense_bps, sparse_adds = eng.autotune_batch(prob, params, 20)
+        tuned = {"dense_Bps": dense_bps, "sparse_adds_per_s": sparse_adds, "probe_steps": 20}
+        log("autotune_batch: dense %.3g B/s, sparse %.3g adds/s" % (dense_bps, sparse_adds))
     if not batch and insts[0].csr is not None and insts[0].n <= 8192:
         # sparse kernel configuration by the library's autotuner (set-up, not timed)
         choice, ms = eng.autotune(prob, params, 100)
@@ -518,10 +603,13 @@ def main():
     if prec == "bf16" and not a.no_fp32_form:
         # the same solve with FP32 couplings; when BF16's best energy is worse, BF16 is
         # rerun with twice the replicas (and its cost counted) until it matches
+        # (each form: one warm-up solve, then FORM_SOLVES timed solves)
+        FORM_SOLVES = 3
         p32 = qpa.make_params(R, T, wl.eta, wl.alpha, wl.lambda0, wl.sigma0, wl.seed,
                               qpa.QPA_PREC_FP32)
         log("FP32 form")
-        d32, o32, _, _, _ = run_solves(eng, qpa, torch, insts, prob, p32, 1, 0, False)
+        d32, o32, _, _, _ = run_solves(eng, qpa, torch, insts, prob, p32, FORM_SOLVES, 1, False)
+        d32 /= FORM_SOLVES
         ef = float(o32["energy"].cpu().numpy().min())
         eb = float(out["energy"].cpu().numpy().min())
         t_bf = dt / a.steps
@@ -531,14 +619,18 @@ def main():
             log("BF16 with %d replicas" % reps)
             pb = qpa.make_params(reps, T, wl.eta, wl.alpha, wl.lambda0, wl.sigma0, wl.seed,
                                  qpa.QPA_PREC_BF16)
-            tb, ob, _, _, _ = run_solves(eng, qpa, torch, insts, prob, pb, 1, 0, False)
-            t_bf = tb
+            tb, ob, _, _, _ = run_solves(eng, qpa, torch, insts, prob, pb, FORM_SOLVES, 1, False)
+            t_bf = tb / FORM_SOLVES
             eb = float(ob["energy"].cpu().numpy().min())
+        matched = bool(eb <= ef + 1e-6 * abs(ef))
         res["fp32_form"] = {"value": n_total * R * T / d32, "unit": "spin-updates/s",
-                            "seconds_per_solve": d32, "best_energy": ef,
-                            "bf16_best_energy": eb, "bf16_replicas_to_match": reps,
-                            "matched": bool(eb <= ef + 1e-6 * abs(ef)),
-                            "bf16_speedup_at_matched_energy": d32 / t_bf}
+                            "seconds_per_solve": d32, "solves_timed": FORM_SOLVES,
+                            "best_energy": ef, "bf16_best_energy": eb,
+                            "bf16_replicas_to_match": reps, "matched": matched,
+                            "bf16_seconds_per_solve_at_match": t_bf,
+                            "bf16_value_at_matched_energy": n_total * reps * T / t_bf,
+                            "bf16_speedup_at_matched_energy": d32 / t_bf,
+                            "bf16_speedup_at_config_replicas": d32 / (dt / a.steps)}
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle)")
         res["cpu_baseline"] = cpu_baseline(inst0, wl, prec)

@@ -134,7 +134,9 @@ typedef struct {
  * QPA_SOLVE_STREAMED. */
 #define QPA_SOLVE_BINNED 16
 
-/* Path choice of qpa_solve_batch (params.flags; qpa_solve requires 0).  By default
+/* Path choice of qpa_solve_batch (params.flags, optionally or-ed with QPA_SOLVE_GRAPH:
+ * the per-step loop of the dense tiles is then captured once as a HIP graph and replayed,
+ * as for qpa_solve; qpa_solve requires neither value).  By default
  * every instance whose couplings are exact in BF16 (integer weights with |w| <= 256,
  * or any weights when precision is QPA_PREC_BF16) runs as dense matrix-core tiles when
  * a cost model finds that cheaper than the sparse kernel; the others run sparse. */
@@ -426,6 +428,22 @@ qpa_status qpa_spectrum(qpa_ctx *ctx, int64_t n, int32_t R, const int8_t *spins,
 qpa_status qpa_autotune(qpa_ctx *ctx, const qpa_problem *problem, const qpa_params *params,
                         int32_t probe_steps, void *workspace, size_t workspace_bytes,
                         void *stream, int32_t *choice, double *ms);
+
+/* Measure the two paths of qpa_solve_batch on this device for `count` instances: the
+ * batch is solved for probe_steps steps with every BF16-exact instance forced dense, then
+ * with every instance forced sparse (a warm-up run before each timed one), and the
+ * step-kernel time of each path gives its rate -- dense tiles in bytes per second,
+ * counting 2 bytes per coupling of the padded matrix plus 16 per variable and replica
+ * (x and m read and written), sparse tasks in coupling adds per second (stored entries
+ * times replicas).  The context keeps the rates; later qpa_workspace_size_batch and
+ * qpa_solve_batch calls on it choose each instance's path with them (before any
+ * measurement, built-in estimates are used).
+ *  rates (host, optional, 2 doubles): the rates now in effect [dense B/s, sparse adds/s].
+ * The tuner allocates the probe's workspace and outputs itself and frees them before it
+ * returns; `stream` is synchronised. */
+qpa_status qpa_autotune_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *problems,
+                              const qpa_params *params, int32_t probe_steps, void *stream,
+                              double *rates);
 
 /* Record a sparse kernel choice for this shape by hand (0 = streamed, the resident
  * kernel's replica group 1, 2, 4 or 8, or QPA_TUNE_BINNED, where it applies), as

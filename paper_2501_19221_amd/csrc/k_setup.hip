@@ -777,7 +777,7 @@ __global__ void __launch_bounds__(256) k_energy_csr_wave(int64_t n,
 // Batched energies of integer CSR instances (n <= EBITS_MAX_N) from bit-packed spins:
 // the same partial sums as the wave-per-row kernel (each pair once, exact integers),
 // over blocks of EB_ROWS rows.  k_spin_words_batch writes each replica's sign bits once
-// (bit i % 64 of word i / 64 set <=> x_i < 0, i.e. spin -1); an energy block stages the
+// (bit i % 64 of word i / 64 set <=> not x_i >= 0, i.e. spin -1); an energy block stages the
 // words of 64 replicas in LDS as words[i / 64][replica], a wave takes a row with lane =
 // replica and walks the row's entries past the diagonal in pieces of 64 (loaded by the
 // lanes, then broadcast one at a time), so that no spin is fetched from memory per entry.
@@ -789,14 +789,17 @@ __global__ void __launch_bounds__(256) k_spin_words_batch(const ScoreTask *__res
     for (int64_t p = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; p < total;
          p += step) {
         const int64_t r = p / nw, i = 64 * (p - r * nw) + lane;
-        const uint64_t word = __ballot(i < t.n && t.x[r * t.ld_r + i] < 0.0f);
+        // spin -1 exactly where the export writes -1: not (x >= 0)
+        const uint64_t word = __ballot(i < t.n && !(t.x[r * t.ld_r + i] >= 0.0f));
         if (lane == 0) t.words[p] = word;
     }
 }
 
 template <typename TW, typename TI>
 __global__ void __launch_bounds__(256) k_energy_bits_batch(const ScoreTask *__restrict__ tasks) {
-    __shared__ uint64_t words[EBITS_MAX_N / 64][64];
+    // rows padded by one word: the staging writes (consecutive threads on consecutive
+    // rows) then fall in different banks
+    __shared__ uint64_t words[EBITS_MAX_N / 64][64 + 1];
     __shared__ int64_t red[4][64];
     const ScoreTask &t = tasks[blockIdx.y];
     const int64_t n = t.n, R = t.R, nw = (n + 63) / 64;

@@ -53,6 +53,10 @@ struct qpa_ctx {
         }
     };
     std::vector<std::pair<TuneKey, int32_t>> tuned;
+    // batch path rates measured by qpa_autotune_batch (0: the built-in estimates):
+    // dense tiles in bytes per second (2 bytes per coupling plus 16 per variable and
+    // replica, whatever the tile element type), sparse tasks in coupling adds per second
+    double batch_dense_Bps = 0.0, batch_sparse_adds = 0.0;
     // streams of default priority for the independent per-instance work of a batch, and
     // the events that order them after and join them back into the caller's stream
     std::vector<hipStream_t> aux;
@@ -304,8 +308,11 @@ qpa_status check_params(qpa_ctx *ctx, const qpa_params *a) {
 qpa_status check_batch_params(qpa_ctx *ctx, const qpa_params *a) {
     if (!a) return fail(ctx, QPA_E_ARG, "params is NULL");
     qpa_params b = *a;
-    if (b.flags != 0 && b.flags != QPA_BATCH_SPARSE && b.flags != QPA_BATCH_DENSE)
-        return fail(ctx, QPA_E_ARG, "params.flags must be 0, QPA_BATCH_SPARSE or QPA_BATCH_DENSE");
+    const int32_t path = b.flags & ~QPA_SOLVE_GRAPH;
+    if (path != 0 && path != QPA_BATCH_SPARSE && path != QPA_BATCH_DENSE)
+        return fail(ctx, QPA_E_ARG,
+                    "params.flags must be 0, QPA_BATCH_SPARSE or QPA_BATCH_DENSE, optionally "
+                    "or-ed with QPA_SOLVE_GRAPH");
     b.flags = 0;
     return check_params(ctx, &b);
 }
@@ -836,13 +843,24 @@ std::vector<MfmaTile> by_compute_die(const std::vector<MfmaTile> &in) {
     return out;
 }
 
-// Cost model of one PA step of one instance on the two batch paths, in seconds, with
-// rates measured on MI355X: the CSR task kernel sustains about 0.3e12 signed coupling
-// adds per second; the grouped matrix-core step streams BF16 couplings and FP32 state at
-// about 3e12 bytes per second.
-double csr_step_cost(int64_t nnz, int64_t R) { return (double)nnz * (double)R / 0.3e12; }
-double dense_step_cost(int64_t np, int64_t R) {
-    return ((double)np * (double)np * 2.0 + 16.0 * (double)R * (double)np) / 3.0e12;
+// Cost model of one PA step of one instance on the two batch paths, in seconds: work
+// over a rate.  The rates are the context's, measured by qpa_autotune_batch on this
+// device for the caller's instances; before any measurement, estimates from earlier
+// measurements on MI355X (the sparse task kernel about 0.3e12 signed coupling adds per
+// second, the grouped matrix-core step about 3e12 bytes per second).
+constexpr double SPARSE_ADDS_DEFAULT = 0.3e12, DENSE_BPS_DEFAULT = 3.0e12;
+double csr_step_work(int64_t nnz, int64_t R) { return (double)nnz * (double)R; }
+double dense_step_work(int64_t np, int64_t R) {
+    return (double)np * (double)np * 2.0 + 16.0 * (double)R * (double)np;
+}
+double csr_step_cost(const qpa_ctx *ctx, int64_t nnz, int64_t R) {
+    const double r = ctx && ctx->batch_sparse_adds > 0.0 ? ctx->batch_sparse_adds
+                                                        : SPARSE_ADDS_DEFAULT;
+    return csr_step_work(nnz, R) / r;
+}
+double dense_step_cost(const qpa_ctx *ctx, int64_t np, int64_t R) {
+    const double r = ctx && ctx->batch_dense_Bps > 0.0 ? ctx->batch_dense_Bps : DENSE_BPS_DEFAULT;
+    return dense_step_work(np, R) / r;
 }
 
 // Per instance: the canonical buffers, energy scratch and [groups][n][64] state of a CSR
@@ -883,9 +901,10 @@ qpa_status make_batch_plan(qpa_ctx *ctx, int32_t count, const qpa_problem *probs
         DenseSlot ds;
         const bool exact_ok = pl.is_int || a.precision == QPA_PREC_BF16;
         const int64_t np = round_up(probs[k].n, MF_NPAD), Rp = round_up(a.replicas, MF_BM);
-        const bool cheaper =
-            dense_step_cost(np, a.replicas) < csr_step_cost(probs[k].nnz, a.replicas);
-        if (exact_ok && a.flags != QPA_BATCH_SPARSE && (cheaper || a.flags == QPA_BATCH_DENSE)) {
+        const bool cheaper = dense_step_cost(ctx, np, a.replicas) <
+                             csr_step_cost(ctx, probs[k].nnz, a.replicas);
+        const int32_t force = a.flags & (QPA_BATCH_SPARSE | QPA_BATCH_DENSE);
+        if (exact_ok && force != QPA_BATCH_SPARSE && (cheaper || force == QPA_BATCH_DENSE)) {
             ds.cand = true;
             ds.np = np;
             ds.Rp = Rp;
@@ -1989,12 +2008,33 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
             QPA_HIP(hipEventRecord(sp.a, st));
         }
         const MfmaTile *dt16 = reinterpret_cast<const MfmaTile *>(ws + bp.o_tiles);
-        for (int32_t t = 0; t < params->steps; ++t) {
-            QPA_HIP(launch_mfma_grouped(dt16, ntiles16, t, dlam, params->eta, params->alpha,
-                                        false, st));
-            QPA_HIP(launch_mfma_grouped(dt16 + ntiles16, ntiles8, t, dlam, params->eta,
-                                        params->alpha, true, st));
+        auto loop = [&](hipStream_t s_) -> qpa_status {
+            for (int32_t t = 0; t < params->steps; ++t) {
+                QPA_HIP(launch_mfma_grouped(dt16, ntiles16, t, dlam, params->eta, params->alpha,
+                                            false, s_));
+                QPA_HIP(launch_mfma_grouped(dt16 + ntiles16, ntiles8, t, dlam, params->eta,
+                                            params->alpha, true, s_));
+            }
+            return QPA_OK;
+        };
+        if (params->flags & QPA_SOLVE_GRAPH) {
+            // the step loop's launches read only these host values (the tile table and
+            // the schedule are device data written before the replay)
+            std::vector<uint8_t> key;
+            key_add(key, (int32_t)2);
+            key_add(key, ws);
+            key_add(key, bp.o_tiles);
+            key_add(key, bp.o_lam);
+            key_add(key, ntiles16);
+            key_add(key, ntiles8);
+            key_add(key, params->steps);
+            key_add(key, params->eta);
+            key_add(key, params->alpha);
+            s = run_graph(ctx, std::move(key), st, loop);
+        } else {
+            s = loop(st);
         }
+        if (s != QPA_OK) return s;
         if (ctx->prof) {
             QPA_HIP(hipEventRecord(sp.b, st));
             sp.launches = (int64_t)params->steps * ((ntiles16 > 0) + (ntiles8 > 0));
@@ -2441,6 +2481,85 @@ qpa_status qpa_autotune(qpa_ctx *ctx, const qpa_problem *problem, const qpa_para
     if (s != QPA_OK) return s;
     record_choice(ctx, *problem, *params, pick);
     *choice = pick;
+    return QPA_OK;
+}
+
+qpa_status qpa_autotune_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *problems,
+                              const qpa_params *params, int32_t probe_steps, void *stream,
+                              double *rates) {
+    if (!ctx) return QPA_E_ARG;
+    ctx->err.clear();
+    qpa_status s = check_batch_params(ctx, params);
+    if (s != QPA_OK) return s;
+    if (probe_steps < 1) return fail(ctx, QPA_E_ARG, "probe_steps must be >= 1");
+    if (count < 1 || !problems) return fail(ctx, QPA_E_ARG, "count must be >= 1, problems non-NULL");
+    QPA_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    qpa_params a = *params;
+    a.steps = probe_steps;
+    a.lambda_table = nullptr;                 // the schedule's values do not change the cost
+    const int64_t R = a.replicas;
+    double measured[2] = {0.0, 0.0};
+    const int32_t force[2] = {QPA_BATCH_DENSE, QPA_BATCH_SPARSE};
+    const bool prof = ctx->prof;
+    for (int f = 0; f < 2 && s == QPA_OK; ++f) {
+        a.flags = force[f];
+        BatchPlan bp;
+        s = make_batch_plan(ctx, count, problems, a, bp);
+        if (s != QPA_OK) break;
+        // a workspace and outputs of the tuner's own for the probe solves
+        const size_t obytes = align_up(sizeof(double) * (size_t)R + sizeof(int32_t));
+        void *buf = nullptr;
+        hipError_t e = hipMalloc(&buf, bp.total + obytes * (size_t)count);
+        if (e != hipSuccess) {
+            s = fail(ctx, QPA_E_DEVICE, "autotune_batch: %s", hipGetErrorString(e));
+            break;
+        }
+        std::vector<qpa_outputs> outs(count);
+        for (int32_t k = 0; k < count; ++k) {
+            char *o = static_cast<char *>(buf) + bp.total + obytes * (size_t)k;
+            outs[k] = qpa_outputs{};
+            outs[k].energy = reinterpret_cast<double *>(o);
+            outs[k].best = reinterpret_cast<int32_t *>(o + sizeof(double) * (size_t)R);
+        }
+        double ms = 0.0;
+        int64_t launches = 0;
+        const int32_t path = f == 0 ? QPA_PATH_BATCH_DENSE : QPA_PATH_BATCH_SPARSE;
+        for (int rep = 0; rep < 2 && s == QPA_OK; ++rep) {      // the first run warms up
+            ctx->prof = rep == 1;
+            double d0 = 0.0;
+            int64_t l0 = 0;
+            if (rep == 1) (void)qpa_profile_read_path(ctx, QPA_PATH_ALL, &d0, &l0, 1);
+            s = qpa_solve_batch(ctx, count, problems, &a, buf, bp.total, stream, outs.data());
+            if (s == QPA_OK && rep == 1) {
+                e = hipStreamSynchronize(st);
+                if (e != hipSuccess) s = fail(ctx, QPA_E_DEVICE, "%s", hipGetErrorString(e));
+                else s = qpa_profile_read_path(ctx, path, &ms, &launches, 1);
+            }
+        }
+        ctx->prof = prof;
+        // the work of the instances that took the path, over its step-kernel time
+        double work = 0.0;
+        for (int32_t k = 0; k < count && s == QPA_OK; ++k) {
+            const int32_t pk = ctx->batch_paths[k];
+            if (f == 0 && (pk == QPA_PATH_BATCH_DENSE || pk == QPA_PATH_BATCH_DENSE_I8))
+                work += dense_step_work(round_up(problems[k].n, MF_NPAD), R);
+            if (f == 1 && pk == QPA_PATH_BATCH_SPARSE)
+                work += csr_step_work(problems[k].nnz, R);
+        }
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(buf);
+        if (s == QPA_OK && ms > 0.0 && work > 0.0)
+            measured[f] = work * (double)probe_steps / (ms / 1e3);
+    }
+    ctx->prof = prof;
+    if (s != QPA_OK) return s;
+    if (measured[0] > 0.0) ctx->batch_dense_Bps = measured[0];
+    if (measured[1] > 0.0) ctx->batch_sparse_adds = measured[1];
+    if (rates) {
+        rates[0] = ctx->batch_dense_Bps > 0.0 ? ctx->batch_dense_Bps : DENSE_BPS_DEFAULT;
+        rates[1] = ctx->batch_sparse_adds > 0.0 ? ctx->batch_sparse_adds : SPARSE_ADDS_DEFAULT;
+    }
     return QPA_OK;
 }
 

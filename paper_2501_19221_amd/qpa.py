@@ -53,7 +53,8 @@ EXPORTED = ["qpa_create", "qpa_destroy", "qpa_last_error", "qpa_status_string",
             "qpa_profile_read_path", "qpa_batch_paths", "qpa_workspace_size_sbm",
             "qpa_sbm_solve", "qpa_sbm_steps", "qpa_spectral_radius",
             "qpa_workspace_size_spectrum", "qpa_spectrum", "qpa_autotune", "qpa_tune_set",
-            "qpa_solve_noalloc", "qpa_workspace_size_relaxed_batch", "qpa_relaxed_grad_batch"]
+            "qpa_solve_noalloc", "qpa_workspace_size_relaxed_batch", "qpa_relaxed_grad_batch",
+            "qpa_autotune_batch"]
 QPA_NOALLOC_WORKSPACE_BYTES = 64 << 20
 QPA_NOALLOC_MAX_STEPS = 65536
 
@@ -145,6 +146,9 @@ _sig = {
                           ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
     "qpa_tune_set": (_S, [_P, ctypes.POINTER(qpa_problem), ctypes.POINTER(qpa_params),
                           ctypes.c_int32]),
+    "qpa_autotune_batch": (_S, [_P, ctypes.c_int32, ctypes.POINTER(qpa_problem),
+                                ctypes.POINTER(qpa_params), ctypes.c_int32, _P,
+                                ctypes.POINTER(ctypes.c_double)]),
     "qpa_workspace_size_spectrum": (_S, [_P, ctypes.c_int64, ctypes.c_int32,
                                          ctypes.POINTER(ctypes.c_size_t)]),
     "qpa_spectrum": (_S, [_P, ctypes.c_int64, ctypes.c_int32, _P, _P, ctypes.c_int32,
@@ -323,6 +327,14 @@ def qpa_autotune(ctx, problem, params, probe_steps, workspace, workspace_bytes, 
     _check(ctx, _lib.qpa_autotune(ctx, ctypes.byref(problem), ctypes.byref(params), probe_steps,
                                   workspace, workspace_bytes, stream, ctypes.byref(choice), ms))
     return choice.value, list(ms)
+
+
+def qpa_autotune_batch(ctx, problems, params, probe_steps, stream):
+    """Returns the batch path rates now in effect: (dense bytes/s, sparse adds/s)."""
+    rates = (ctypes.c_double * 2)()
+    _check(ctx, _lib.qpa_autotune_batch(ctx, len(problems), problems, ctypes.byref(params),
+                                        probe_steps, stream, rates))
+    return rates[0], rates[1]
 
 
 def qpa_tune_set(ctx, problem, params, choice):
@@ -635,6 +647,12 @@ class Engine:
 
     def tune_set(self, prob: Problem, params: qpa_params, choice):
         qpa_tune_set(self.ctx, prob.struct(), params, choice)
+
+    def autotune_batch(self, probs, params: qpa_params, probe_steps=20):
+        """Measure both batch paths for these instances; the context keeps the rates.
+        Returns (dense bytes/s, sparse adds/s)."""
+        pa = (qpa_problem * len(probs))(*[p.struct() for p in probs])
+        return qpa_autotune_batch(self.ctx, pa, params, probe_steps, self._stream())
 
     def spectrum(self, spins, energy, k, flags=0):
         """Low-energy spectrum of device samples spins [R,n] int8 / energy [R] float64:

@@ -522,6 +522,38 @@ def test_batch_uneven_instances_bit_exact(q, eng, path):
         assert int(host(out["best"])[0]) == int(np.flatnonzero(e == e.min())[0]), k
 
 
+def test_batch_autotune_measures_rates_and_chooses_by_them(q, eng):
+    """qpa_autotune_batch measures both paths on the device; afterwards every instance
+    takes the path the cost model gives with the measured rates (dense when BF16-exact and
+    (2 np^2 + 16 R np) / dense rate < nnz R / sparse rate), and the results are the
+    oracle's bits."""
+    rng = np.random.default_rng(17)
+    insts = [gen.er_qubo(int(n), 0.1, 100, rng) for n in (60, 200, 350)]
+    insts += [gen.chimera_ising(4, seed=3), gen.er_qubo(600, 0.004, 100, rng),
+              gen.er_qubo(200, 0.1, 300, rng)]
+    R, T, eta, alpha, lam0 = 64, 40, 0.0002, 0.8, 200.0
+    probs = [q.Problem.from_instance(i) for i in insts]
+    p = _params(q, R, T, eta, alpha, lam0, seed=9)
+    say("batch autotune")
+    dense_bps, sparse_adds = eng.autotune_batch(probs, p, probe_steps=20)
+    say("measured rates: dense %.3g B/s, sparse %.3g adds/s" % (dense_bps, sparse_adds))
+    assert 1e10 < dense_bps < 2e13 and 1e9 < sparse_adds < 4e13
+    outs = eng.solve_batch(probs, p, want_state=True)
+    paths = q.qpa_batch_paths(eng.ctx, len(insts))
+    for k, inst in enumerate(insts):
+        np_ = -(-inst.n // 128) * 128
+        dense_cost = (2.0 * np_ * np_ + 16.0 * R * np_) / dense_bps
+        sparse_cost = inst.csr.nnz * R / sparse_adds
+        exact = int(np.abs(inst.csr.w).max(initial=0)) <= 256
+        want_dense = exact and dense_cost < sparse_cost
+        assert (paths[k] != q.QPA_PATH_BATCH_SPARSE) == want_dense, (k, paths[k])
+    assert paths[-1] == q.QPA_PATH_BATCH_SPARSE
+    lam = orc.lambda_linear(T, lam0)
+    for k, (inst, out) in enumerate(zip(insts, outs)):
+        x, m, _ = _oracle_instance(inst, R, T, lam, eta, alpha, seed=9 + k)
+        assert np.array_equal(host(out["x"]), x) and np.array_equal(host(out["m"]), m), k
+
+
 def test_batch_reports_the_failing_instance(q, eng):
     # An asymmetric instance in the middle of a batch is named in the error (it has 16 or
     # more entries per row, the batched canonicalisation's case); the context then solves
@@ -749,6 +781,38 @@ def test_graph_step_loop_matches_plain_launches(q, eng, which):
         # eager work between the replays
         eng.energy(prob, _params(q, R, T, 0.05, 0.8, 3.0, prec=prec), out["spins"])
         torch.cuda.synchronize()
+
+
+def test_graph_batch_step_loop_matches_plain_launches(q, eng):
+    """qpa_solve_batch with QPA_SOLVE_GRAPH: the captured per-step loop of the dense tiles
+    (int8 and BF16 tiles in one batch, beside a sparse instance) replayed three times with
+    eager work in between, then replayed for a second batch of the same shapes but other
+    couplings, gives the bits of the plain launches every time."""
+    import torch
+
+    def batch(seed):
+        rng = np.random.default_rng(seed)
+        return [gen.er_qubo(180, 0.1, 100, rng), gen.er_qubo(300, 0.1, 200, rng),
+                gen.er_qubo(260, 0.1, 300, rng)]          # the last is never densified
+    R, T, eta, alpha, lam0 = 70, 30, 0.0002, 0.8, 200.0
+    for seed in (1, 2):
+        probs = [q.Problem.from_instance(i) for i in batch(seed)]
+        say("graph batch step loop, batch seed %d" % seed)
+        ref = eng.solve_batch(probs, _params(q, R, T, eta, alpha, lam0, seed=4,
+                                             flags=q.QPA_BATCH_DENSE), want_state=True)
+        paths = q.qpa_batch_paths(eng.ctx, len(probs))
+        assert list(paths) == [q.QPA_PATH_BATCH_DENSE_I8, q.QPA_PATH_BATCH_DENSE,
+                               q.QPA_PATH_BATCH_SPARSE]
+        pg = _params(q, R, T, eta, alpha, lam0, seed=4,
+                     flags=q.QPA_BATCH_DENSE | q.QPA_SOLVE_GRAPH)
+        for rep in range(3 if seed == 1 else 1):
+            outs = eng.solve_batch(probs, pg, want_state=True)
+            torch.cuda.synchronize()
+            for a_, b_ in zip(outs, ref):
+                for key in ("x", "m", "energy_i64", "best"):
+                    assert np.array_equal(host(a_[key]), host(b_[key])), (seed, rep, key)
+            eng.energy(probs[0], _params(q, R, T, eta, alpha, lam0), outs[0]["spins"])
+            torch.cuda.synchronize()
 
 
 def test_graph_steps_split_equals_oracle(q, eng):
