@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="sk4096")
+    ap.add_argument("--precision", choices=["bf16", "fp32"], default=None,
+                    help="dense field arithmetic instead of the workload's own (e.g. the "
+                         "FP32 form of sk4096 alone)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32-form", action="store_true")
     ap.add_argument("--no-measured-peaks", action="store_true")
@@ -444,7 +447,7 @@ def main():
     made = wl.make()
     batch = isinstance(made, list)
     insts = made if batch else [made]
-    prec = wl.precision
+    prec = a.precision or wl.precision
     eng = qpa.Engine(0)
     probs = [qpa.Problem.from_instance(i) for i in insts]
     prob = probs if batch else probs[0]
@@ -531,7 +534,7 @@ def main():
         else:
             roof = {"bound": "alu", "peak": PEAK_FP32_TFLOPS,
                     "kernel": ("k_dense_wave" if n <= 64 else "k_dense_resident")
-                    if per_solve_launches <= 1.0 else "k_dense_tiled_step"}
+                    if per_solve_launches <= 1.0 else "k_fp32_tiled_step"}
         roof.update({"achieved": achieved, "unit": "TFLOP/s", "per_launch": what})
         e = out["energy"].cpu().numpy()
         extra = {"best_energy": float(e.min()), "best_replica": int(out["best"].cpu()[0])}

@@ -258,36 +258,43 @@ __global__ void __launch_bounds__(256) k_rel_fill(double *__restrict__ p, int64_
         p[q] = 0.0;
 }
 
-// final reduction of the per-step partial tables (fixed order)
+// Final reduction of the per-step partial tables, in a fixed order: thread t sums the
+// slots of steps t, t + 256, ... (d_lambda_t, and the step's d_eta and d_alpha terms,
+// which it leaves in the step's first slots), then thread 0 sums the steps in order.
 __global__ void __launch_bounds__(256) k_rel_finish(int32_t T, int32_t nblk,
-                                                    const double *__restrict__ part_steps,
+                                                    double *__restrict__ part_steps,
                                                     const double *__restrict__ part_loss,
                                                     double *__restrict__ loss,
                                                     double *__restrict__ d_eta,
                                                     double *__restrict__ d_alpha,
                                                     double *__restrict__ d_lam) {
-    if (d_lam)
+    const bool grads = d_eta || d_alpha || d_lam;
+    if (grads)
         for (int32_t t = threadIdx.x; t < T; t += blockDim.x) {
-            const double *p = part_steps + (int64_t)t * 3 * nblk;
-            double l = 0.0;
-            for (int32_t k = 0; k < nblk; ++k) l += p[2 * nblk + k];
-            d_lam[t] = l;
+            double *p = part_steps + (int64_t)t * 3 * nblk;
+            double e = 0.0, a = 0.0, l = 0.0;
+            for (int32_t k = 0; k < nblk; ++k) {
+                e += p[k];
+                a += p[nblk + k];
+                l += p[2 * nblk + k];
+            }
+            p[0] = e;
+            p[nblk] = a;
+            if (d_lam) d_lam[t] = l;
         }
+    __syncthreads();
     if (threadIdx.x == 0) {
         double L = 0.0;
         for (int32_t k = 0; k < nblk; ++k) L += part_loss[k];
         *loss = L;
-        if (d_eta || d_alpha) {
-            double e = 0.0, al = 0.0;
+        if (grads) {
+            double e = 0.0, a = 0.0;
             for (int32_t t = 0; t < T; ++t) {
-                const double *p = part_steps + (int64_t)t * 3 * nblk;
-                for (int32_t k = 0; k < nblk; ++k) {
-                    e += p[k];
-                    al += p[nblk + k];
-                }
+                e += part_steps[(int64_t)t * 3 * nblk];
+                a += part_steps[(int64_t)t * 3 * nblk + nblk];
             }
             if (d_eta) *d_eta = e;
-            if (d_alpha) *d_alpha = al;
+            if (d_alpha) *d_alpha = a;
         }
     }
 }
@@ -380,7 +387,7 @@ hipError_t launch_rel_fill(double *p, int64_t count, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_rel_finish(int32_t T, int32_t nblk, const double *part_steps,
+hipError_t launch_rel_finish(int32_t T, int32_t nblk, double *part_steps,
                              const double *part_loss, double *loss, double *d_eta,
                              double *d_alpha, double *d_lam, hipStream_t st) {
     k_rel_finish<<<1, 256, 0, st>>>(T, nblk, part_steps, part_loss, loss, d_eta, d_alpha, d_lam);

@@ -1104,7 +1104,10 @@ const char *qpa_last_error(const qpa_ctx *ctx) {
 }
 
 const char *qpa_status_string(qpa_status s) {
-    switch (s) {
+    // a C caller may pass any int: read the bits as an int, not as the enumeration
+    int v = 0;
+    memcpy(&v, &s, sizeof(v));
+    switch (v) {
         case QPA_OK: return "QPA_OK";
         case QPA_E_ARG: return "QPA_E_ARG";
         case QPA_E_SHAPE: return "QPA_E_SHAPE";

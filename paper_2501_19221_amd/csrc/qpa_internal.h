@@ -337,8 +337,8 @@ hipError_t launch_rel_tiles(int32_t mode, int64_t n, const float *J, const float
                             const RelArgs &a, hipStream_t st);
 hipError_t launch_rel_fill(double *p, int64_t count, hipStream_t st);
 // loss = sum of the loss partials; d_lam[t] (if non-NULL), d_eta, d_alpha from the
-// per-step tables [T][3][nblk], all in a fixed order.
-hipError_t launch_rel_finish(int32_t T, int32_t nblk, const double *part_steps,
+// per-step tables [T][3][nblk] (overwritten), all in a fixed order.
+hipError_t launch_rel_finish(int32_t T, int32_t nblk, double *part_steps,
                              const double *part_loss, double *loss, double *d_eta,
                              double *d_alpha, double *d_lam, hipStream_t st);
 

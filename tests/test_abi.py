@@ -232,3 +232,23 @@ def test_spectrum_workspace_and_limits(q):
                                               ctypes.byref(n)) == q.QPA_E_UNSUPPORTED
     assert q._lib.qpa_workspace_size_spectrum(None, 0, 10, ctypes.byref(n)) == q.QPA_E_SHAPE
     assert q._lib.qpa_workspace_size_spectrum(None, 10, 0, ctypes.byref(n)) == q.QPA_E_ARG
+
+
+def test_host_code_under_sanitizers():
+    """The library's host code built with AddressSanitizer and UndefinedBehaviorSanitizer
+    (device code unchanged) runs tests/sanitized_host_checks.py -- validation and planning
+    of every entry point -- without a finding."""
+    import subprocess
+    import sys
+    from paper_2501_19221_amd import build
+    lib = build.build(sanitize=True)
+    rt = build.sanitizer_runtime()
+    assert os.path.exists(rt), rt
+    env = dict(os.environ)
+    env["LD_PRELOAD"] = rt
+    env["ASAN_OPTIONS"] = "detect_leaks=0:abort_on_error=1"
+    env["UBSAN_OPTIONS"] = "print_stacktrace=1:halt_on_error=1"
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "tests", "sanitized_host_checks.py"),
+                        lib], env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, r.stdout[-3000:] + r.stderr[-3000:]
+    assert "sanitized host checks ok" in r.stdout
