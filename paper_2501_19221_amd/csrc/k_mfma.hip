@@ -148,27 +148,31 @@ __device__ __forceinline__ void matrix_step(uint8_t *lds, const Tile &tl, int nc
     const int wr = (wave >> 1) & 1, wc = wave & 1;
     const int half = lane >> 5, l32 = lane & 31;
     // J: load u (0..3) of wave w fills LDS rows 16w + 4u + lane/16 at position lane % 16,
-    // which holds piece (lane % 16) ^ (row % 16) of that row.
-    const uint16_t *gJ[4];
+    // which holds piece (lane % 16) ^ (row % 16) of that row.  Addresses are a
+    // wave-uniform base plus 32-bit lane offsets (fewer registers than 64-bit pointers).
+    const uint16_t *Jw = Jb + (I0 + 16 * wave) * np;
+    uint32_t oJ[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-        const int row = 16 * wave + 4 * u + (lane >> 4);
-        gJ[u] = Jb + (I0 + row) * np + 8 * ((lane & 15) ^ (row & 15));
+        const int r = 4 * u + (lane >> 4);         // row - 16 w, and row % 16 == r % 16
+        oJ[u] = (uint32_t)r * (uint32_t)np + 8u * (uint32_t)((lane & 15) ^ (r & 15));
     }
     // spins: the load of wave w fills bytes 1024w + 16 lane of the 8 KiB block of the
     // tile's replicas (64 bytes per replica, in replica order): row 16w + lane/4,
     // position lane % 4, which holds piece (lane - row / 4) % 4
-    const int srow = 16 * wave + (lane >> 2);
-    const uint32_t *gS = s_cur + (R0 + srow) * 16 + 4 * (((lane & 3) - (srow >> 2)) & 3);
+    const uint32_t *Sw = s_cur + (R0 + 16 * wave) * 16;
+    const uint32_t oS = (uint32_t)(lane >> 2) * 16u +
+                        4u * (uint32_t)(((lane & 3) - ((lane >> 4) & 3)) & 3);
     const int64_t sstride = tl.Rp * 16;            // u32 words between consecutive chunks
     auto stage = [&](int kc, int st) {
         kc = kc < nchunk ? kc : nchunk - 1;        // past the end: reload the last chunk
         uint8_t *dst = lds + st * STG;
+        const uint16_t *jc = Jw + (int64_t)kc * KC;
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-            __builtin_amdgcn_global_load_lds(gJ[u] + (int64_t)kc * KC,
+            __builtin_amdgcn_global_load_lds(jc + oJ[u],
                                              (lds_void *)(dst + (4 * wave + u) * 1024), 16, 0, 0);
-        __builtin_amdgcn_global_load_lds(gS + (int64_t)kc * sstride,
+        __builtin_amdgcn_global_load_lds(Sw + (int64_t)kc * sstride + oS,
                                          (lds_void *)(dst + JSTG + 1024 * wave), 16, 0, 0);
     };
 
@@ -181,14 +185,8 @@ __device__ __forceinline__ void matrix_step(uint8_t *lds, const Tile &tl, int nc
 #pragma unroll
             for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
 
-#pragma unroll
-    for (int s = 0; s < NST - 1; ++s) stage(s, s);
-    for (int c = 0; c < nchunk; ++c) {
-        // this wave's loads of chunk c have landed (the NST-2 younger chunks may not);
-        // after the barrier every wave's have, and every wave is done with the stage of
-        // chunk c-1, which is refilled next
-        wait_barrier<(NST - 2) * LOADS_PER_CHUNK>();
-        stage(c + NST - 1, (c + NST - 1) % NST);
+    // the products of chunk c from its stage
+    auto multiply = [&](int c) {
         const uint8_t *src = lds + (c % NST) * STG;
         // this lane's 4 pair words (k steps 4 kh .. 4 kh + 3 of its half) per replica
         // fragment: piece 2 half + kh of the replica's 64 bytes
@@ -219,6 +217,16 @@ __device__ __forceinline__ void matrix_step(uint8_t *lds, const Tile &tl, int nc
                     acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
                         a[i], __builtin_bit_cast(bf16x8, bq[j]), acc[i][j], 0, 0, 0);
         }
+    };
+#pragma unroll
+    for (int s = 0; s < NST - 1; ++s) stage(s, s);
+    for (int c = 0; c < nchunk; ++c) {
+        // this wave's loads of chunk c have landed (the NST-2 younger chunks may not);
+        // after the barrier every wave's have, and every wave is done with the stage of
+        // chunk c-1, which is refilled next
+        wait_barrier<(NST - 2) * LOADS_PER_CHUNK>();
+        stage(c + NST - 1, (c + NST - 1) % NST);
+        multiply(c);
     }
     wait_barrier<0>();     // the trailing (redundant) loads have landed in every wave and
                            // every stage read is done: the stages can take the sums
