@@ -508,6 +508,16 @@ def main():
                 "instances": int((~dense).sum()),
                 "per_launch": "sum(nnz)*R*T = %.4g signed coupling adds (sparse instances, "
                               "all steps, one launch)" % ops}
+        if "dense" in roofs:
+            # the same step counted as the streamed CSR form would move it: int16 index and
+            # weight per stored entry, row pointers, x and m read and written, byte spins
+            # written and read -- the bytes the batch workload's scope states
+            csr_b = float(sum(4.0 * i.csr.nnz + 4.0 * (i.n + 1) + 18.0 * R * i.n
+                              for i in insts))
+            rd = roofs["dense"]
+            rd["csr_form_bytes_per_step"] = csr_b
+            rd["frac_on_csr_form_bytes"] = csr_b / (rd["ms"] / 1e3 / rd["launches"]) / 1e9 / \
+                PEAK_HBM_GBS
         main_path = max(roofs, key=lambda k: roofs[k]["ms"])
         roof = dict(roofs[main_path])
         avg_launch_s = roof.pop("ms") / 1e3 / roof["launches"]
