@@ -478,26 +478,37 @@ def main():
     inst0 = insts[0]
     if batch:
         paths = qpa.qpa_batch_paths(eng.ctx, len(insts))
-        dense = (paths == qpa.QPA_PATH_BATCH_DENSE) | (paths == qpa.QPA_PATH_BATCH_DENSE_I8)
+        grouped = (qpa.QPA_PATH_BATCH_DENSE, qpa.QPA_PATH_BATCH_DENSE_I8,
+                   qpa.QPA_PATH_BATCH_SPARSE_I8)
+        dense = np.isin(paths, grouped)
         roofs = {}
         if qpa.QPA_PATH_BATCH_DENSE in per_path:
             pm, pl = per_path[qpa.QPA_PATH_BATCH_DENSE]
+            # one step: the couplings read once (BF16: 2 bytes per element, int8 rows: 1 byte
+            # per element, int8 entry lists: 4 bytes per nonzero), x and m read and written
+            jb, kinds = 0.0, set()
+            for i, pth in zip(insts, paths):
+                if pth not in grouped:
+                    continue
+                kinds.add(int(pth))
+                if pth == qpa.QPA_PATH_BATCH_SPARSE_I8:
+                    jb += 4.0 * np.count_nonzero(i.csr.w)
+                else:
+                    jb += (1.0 if pth == qpa.QPA_PATH_BATCH_DENSE_I8 else 2.0) * i.n * i.n
             nd = np.array([i.n for i, d in zip(insts, dense) if d], np.float64)
-            esz = np.array([1.0 if pth == qpa.QPA_PATH_BATCH_DENSE_I8 else 2.0
-                            for pth, d in zip(paths, dense) if d])
-            # one step: the coupling matrix (int8 or BF16) read once, x and m read and written
-            byts = float(np.sum(esz * nd * nd + 16.0 * R * nd))
-            # launches per step: one per element type present
-            pl = pl / max(1, int(np.any(esz == 1.0)) + int(np.any(esz == 2.0)))
+            byts = float(jb + np.sum(16.0 * R * nd))
+            pl = pl / max(1, len(kinds))          # launches per step: one per tile kind present
             roofs["dense"] = {
                 "bound": "hbm", "achieved": byts / (pm / 1e3 / pl) / 1e9, "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "kernel": "k_mfma_grouped", "ms": pm, "launches": pl,
                 "instances": int(dense.sum()),
-                "per_launch": "sum over dense instances of n^2 (int8 couplings) or 2n^2 "
-                              "(BF16) + 16nR (x, m read and written) = %.4g B (one PA step "
-                              "of every replica of every dense instance; 'launch' = the "
-                              "grouped launches of one step)" % byts,
-                "int8_instances": int(np.sum(paths == qpa.QPA_PATH_BATCH_DENSE_I8))}
+                "per_launch": "sum over the grouped instances of their couplings (2n^2 BF16, "
+                              "n^2 int8 rows, 4 bytes per nonzero as int8 entry lists) + 16nR "
+                              "(x, m read and written) = %.4g B (one PA step of every replica "
+                              "of every grouped instance; 'launch' = the grouped launches of "
+                              "one step)" % byts,
+                "int8_instances": int(np.sum(paths == qpa.QPA_PATH_BATCH_DENSE_I8)),
+                "int8_entry_list_instances": int(np.sum(paths == qpa.QPA_PATH_BATCH_SPARSE_I8))}
         if qpa.QPA_PATH_BATCH_SPARSE in per_path:
             pm, pl = per_path[qpa.QPA_PATH_BATCH_SPARSE]
             nnz = sum(i.csr.nnz for i, d in zip(insts, dense) if not d)

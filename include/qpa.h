@@ -302,7 +302,11 @@ typedef enum {
     QPA_PATH_BATCH_DENSE_I8 = 10, /* qpa_batch_paths: grouped matrix-core step with int8
                                     couplings (integer |w| <= 127); timed under
                                     QPA_PATH_BATCH_DENSE                           */
-    QPA_PATH_CSR_BINNED = 11     /* sparse, two streaming passes per step (binned)  */
+    QPA_PATH_CSR_BINNED = 11,    /* sparse, two streaming passes per step (binned)  */
+    QPA_PATH_BATCH_SPARSE_I8 = 12 /* qpa_batch_paths: grouped matrix-core step with int8
+                                    couplings kept as lists of their nonzeros (at most
+                                    384 in every 16 x 128 block of the padded matrix);
+                                    timed under QPA_PATH_BATCH_DENSE                */
 } qpa_path;
 
 /* Measurement of the PA-step kernels.  While enabled (enable != 0), every qpa_solve,
@@ -320,9 +324,10 @@ qpa_status qpa_profile_read(qpa_ctx *ctx, double *step_ms, int64_t *step_launche
 qpa_status qpa_profile_read_path(qpa_ctx *ctx, int32_t path, double *step_ms,
                                  int64_t *step_launches, int32_t reset);
 
-/* The path (QPA_PATH_BATCH_SPARSE, QPA_PATH_BATCH_DENSE or QPA_PATH_BATCH_DENSE_I8) that
- * each instance of the last successful qpa_solve_batch on this context took; `count` must
- * equal that call's count.  paths: host array of `count` int32. */
+/* The path (QPA_PATH_BATCH_SPARSE, QPA_PATH_BATCH_DENSE, QPA_PATH_BATCH_DENSE_I8 or
+ * QPA_PATH_BATCH_SPARSE_I8) that each instance of the last successful qpa_solve_batch on
+ * this context took; `count` must equal that call's count.  paths: host array of `count`
+ * int32. */
 qpa_status qpa_batch_paths(const qpa_ctx *ctx, int32_t count, int32_t *paths);
 
 /* ---------------------------------------------------------------------------------

@@ -17,7 +17,7 @@ QPA_BATCH_SPARSE, QPA_BATCH_DENSE = 1, 2
 QPA_PATH_ALL, QPA_PATH_DENSE_RESIDENT, QPA_PATH_DENSE_TILED, QPA_PATH_DENSE_MFMA, QPA_PATH_CSR, \
     QPA_PATH_BATCH_SPARSE, QPA_PATH_BATCH_DENSE, QPA_PATH_CSR_RESIDENT, QPA_PATH_SBM_DENSE, \
     QPA_PATH_SBM_CSR, QPA_PATH_SBM_CSR_RESIDENT, QPA_PATH_BATCH_DENSE_I8, \
-    QPA_PATH_CSR_BINNED = range(-1, 12)
+    QPA_PATH_CSR_BINNED, QPA_PATH_BATCH_SPARSE_I8 = range(-1, 13)
 QPA_SOLVE_STREAMED = 4
 QPA_SOLVE_GRAPH = 8
 QPA_SOLVE_BINNED = 16

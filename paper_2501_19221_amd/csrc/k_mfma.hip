@@ -134,6 +134,8 @@ struct Tile {
     const float *b;
     float scale;
     float *x, *m;
+    const uint32_t *E = nullptr;     // sparse int8 tiles: entries and block offsets
+    const int32_t *O = nullptr;
 };
 
 // ---- matrix waves: the reduction of one step, left in LDS as raw sums --------------
@@ -255,6 +257,9 @@ __device__ __forceinline__ void matrix_step(uint8_t *lds, const Tile &tl, int nc
 // 16w + 8u + lane/8, position lane % 8 holding piece (lane % 8) ^ (row % 8)) and two of
 // spins (replica rows likewise) per wave; four k steps of 32 (wave kh takes 2 kh and
 // 2 kh + 1); the operand of k step q and lane half h is piece 2 q + h of the row.
+// SPARSE: the coupling half of every stage is written by the state waves from the
+// tile's entry lists (state_load_sparse); the matrix waves load only the spins.
+template <bool SPARSE>
 __device__ __forceinline__ void matrix_step_i8(uint8_t *lds, const Tile &tl, int nchunk,
                                                const uint8_t *__restrict__ s_cur, int wave,
                                                int lane) {
@@ -273,19 +278,31 @@ __device__ __forceinline__ void matrix_step_i8(uint8_t *lds, const Tile &tl, int
         gS[u] = s_cur + (R0 + row) * KC + 16 * piece;
     }
     const int64_t sstride = tl.Rp * KC;            // bytes between consecutive spin chunks
+    // Replica rows 64..127 of a tile with no live replica there (fewer than 65 live rows,
+    // e.g. 64 replicas padded to 128) are neither loaded (waves 4..7) nor multiplied (the
+    // waves of wr = 1): rows are independent, and padding rows are never stored.
+    const bool upper = tl.R0 + 64 < tl.rlive;
+    const bool spins_here = wave < 4 || upper, rows_here = wr == 0 || upper;
     auto stage = [&](int kc, int st) {
         kc = kc < nchunk ? kc : nchunk - 1;        // past the end: reload the last chunk
         uint8_t *dst = lds + st * STG8;
+        if (!SPARSE) {
 #pragma unroll
-        for (int u = 0; u < 2; ++u)
-            __builtin_amdgcn_global_load_lds(gJ[u] + (int64_t)kc * KC,
-                                             (lds_void *)(dst + (2 * wave + u) * 1024), 16, 0, 0);
+            for (int u = 0; u < 2; ++u)
+                __builtin_amdgcn_global_load_lds(gJ[u] + (int64_t)kc * KC,
+                                                 (lds_void *)(dst + (2 * wave + u) * 1024), 16, 0,
+                                                 0);
+        }
+        if (spins_here) {
 #pragma unroll
-        for (int u = 0; u < 2; ++u)
-            __builtin_amdgcn_global_load_lds(gS[u] + (int64_t)kc * sstride,
-                                             (lds_void *)(dst + JSTG8 + (2 * wave + u) * 1024),
-                                             16, 0, 0);
+            for (int u = 0; u < 2; ++u)
+                __builtin_amdgcn_global_load_lds(gS[u] + (int64_t)kc * sstride,
+                                                 (lds_void *)(dst + JSTG8 + (2 * wave + u) * 1024),
+                                                 16, 0, 0);
+        }
     };
+    // loads per chunk of this wave: 2 of J rows (dense only), 2 of spins (if spins_here)
+    constexpr int LJ = SPARSE ? 0 : 2;
     i32x16 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -296,10 +313,15 @@ __device__ __forceinline__ void matrix_step_i8(uint8_t *lds, const Tile &tl, int
 
 #pragma unroll
     for (int s = 0; s < NST8 - 1; ++s) stage(s, s);
+    static_assert(LOADS_PER_CHUNK8 == 4, "2 J pieces + 2 spin pieces");
     for (int c = 0; c < nchunk; ++c) {
-        wait_barrier<(NST8 - 2) * LOADS_PER_CHUNK8>();
+        if (spins_here)
+            wait_barrier<(NST8 - 2) * (LJ + 2)>();
+        else
+            wait_barrier<(NST8 - 2) * LJ>();
         stage(c + NST8 - 1, (c + NST8 - 1) % NST8);
         const uint8_t *src = lds + (c % NST8) * STG8;
+        if (rows_here) {
 #pragma unroll
         for (int qq = 0; qq < 2; ++qq) {
             const int piece = 2 * (2 * kh + qq) + half;
@@ -321,6 +343,7 @@ __device__ __forceinline__ void matrix_step_i8(uint8_t *lds, const Tile &tl, int
                 for (int j = 0; j < 2; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], bq[j], acc[i][j], 0,
                                                                       0, 0);
+        }
         }
     }
     wait_barrier<0>();
@@ -389,6 +412,135 @@ __device__ __forceinline__ void state_load(StateRegs &st, const Tile &tl, int nc
     for (; passed < nchunk; ++passed) barrier();   // the remaining chunks
 }
 
+// ---- state waves of sparse int8 tiles: they also write the coupling half of the stages
+// State wave g (0..7) owns rows 16g .. 16g + 15 of the 128 x 128 coupling block of every
+// chunk: it clears its 2 KiB of the stage and writes the nonzeros of its block there, one
+// byte store per entry (the entry holds its staging position and weight).  The entries of
+// chunk c + NST8 - 2 are placed after the barrier of chunk c, into the stage of chunk
+// c - 2 (free since the barrier of chunk c - 1); the chunks before the first barrier are
+// placed by a prologue.  Entry loads run three chunks ahead (three register sets used in
+// turn), so that their latency is hidden behind three chunk periods as the matrix waves'
+// loads are.  Loads and stores are issued without per-lane branches, so that each wait
+// for a register set covers that set only: lanes past a block's end load and store its
+// last entry again (the same byte with the same value), loads past the last chunk reload
+// it.  A block has at most I8S_BLOCK_MAX entries (I8S_EPL per lane).
+struct EntryRegs {
+    uint32_t e[I8S_EPL];
+    int32_t cnt;
+};
+
+// The table's pointers are generic; these views make the offsets scalar loads (uniform,
+// read-only during the launch) and the entries, x and m global loads, which count on the
+// vector-memory counter only (generic loads also count on the counter that the LDS
+// barriers wait for).
+typedef __attribute__((address_space(4))) const int32_t c_i32;
+typedef __attribute__((address_space(1))) const uint32_t g_u32;
+typedef __attribute__((address_space(1))) const float g_f32;
+
+__device__ __forceinline__ void entries_load(EntryRegs &er, const Tile &tl, int kc, int nchunk,
+                                             int g, int lane) {
+    kc = kc < nchunk ? kc : nchunk - 1;
+    const int64_t blk = ((tl.I0 / KC) * (tl.np / KC) + kc) * 8 + g;
+    const c_i32 *O = (const c_i32 *)tl.O;
+    const int32_t beg = O[blk];
+    er.cnt = O[blk + 1] - beg;
+    // an empty block reads the word at its start, which lies inside the coupling buffer
+    // (the entries end at least a quarter of the buffer before its end); it is not placed
+    const g_u32 *src = (const g_u32 *)tl.E + beg;
+    const int32_t last = max(er.cnt - 1, 0);
+#pragma unroll
+    for (int j = 0; j < I8S_EPL; ++j) er.e[j] = src[min(lane + 64 * j, last)];
+}
+
+// Clears this wave's 2 KiB of the stage and writes its entries there.  Positions are taken
+// within the wave's own rows (an entry of row group g already lies there), so that the
+// words an empty block loaded write zeros into cleared bytes of the same rows.
+__device__ __forceinline__ void entries_place(const EntryRegs &er, uint8_t *stage, int g,
+                                              int lane) {
+    uint8_t *rg = stage + 2048 * g;
+    *reinterpret_cast<u32x4 *>(rg + 16 * lane) = (u32x4){0u, 0u, 0u, 0u};
+    *reinterpret_cast<u32x4 *>(rg + 1024 + 16 * lane) = (u32x4){0u, 0u, 0u, 0u};
+    const uint32_t keep = er.cnt > 0 ? 0xFFFFFFFFu : 0u;
+#pragma unroll
+    for (int j = 0; j < I8S_EPL; ++j)
+        rg[er.e[j] & 0x7FFu] = (uint8_t)((er.e[j] & keep) >> 16);
+}
+
+// The LDS stores of this wave are complete, then the workgroup barrier.
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+constexpr int I8S_AHEAD = 3;                     // chunks of entries in flight
+static_assert(NST8 - 2 >= 1, "a chunk is placed at least one barrier before it is used");
+
+// One chunk barrier of the state waves: then the entries held in er (chunk c + NST8 - 2)
+// are placed and er is reloaded with the chunk I8S_AHEAD further on.  Past the last chunk
+// the reloaded last chunk is placed again, into the stage of chunk c - 2, which no later
+// chunk of the loop uses (they take the stages of chunks c + 1, c + 2 at most); the first
+// barrier after the loop waits for these stores, before the stages take the sums.  No
+// branch: the waits for one register set cover that set only.
+__device__ __forceinline__ void sparse_chunk(EntryRegs &er, const Tile &tl, int c, int nchunk,
+                                             uint8_t *lds, int g, int lane) {
+    lds_barrier();
+    const int kc = c + NST8 - 2;
+    entries_place(er, lds + (kc % NST8) * STG8, g, lane);
+    entries_load(er, tl, kc + I8S_AHEAD, nchunk, g, lane);
+}
+
+// x, m of rows E0 .. E1 - 1 of this thread (padding rows are not read).
+template <int E0, int E1>
+__device__ __forceinline__ void xm_load(StateRegs &st, const Tile &tl, int t) {
+    const int col = t & (BN - 1);
+    const int rsub = __builtin_amdgcn_readfirstlane(t >> 7);
+    const g_f32 *xr = (const g_f32 *)tl.x + (tl.R0 + 4 * E0 + rsub) * tl.np + tl.I0;
+    const g_f32 *mr = (const g_f32 *)tl.m + (tl.R0 + 4 * E0 + rsub) * tl.np + tl.I0;
+#pragma unroll
+    for (int e = E0; e < E1; ++e) {
+        const bool live = tl.R0 + 4 * e + rsub < tl.rlive;
+        st.xv[e] = live ? xr[col] : 0.0f;
+        st.mv[e] = live ? mr[col] : 0.0f;
+        xr = next_rows(xr, 4 * tl.np);
+        mr = next_rows(mr, 4 * tl.np);
+    }
+}
+
+// state_load for sparse int8 tiles: the prologue's chunks are placed and the entries of
+// the next three chunks loaded; the first three chunk barriers (peeled) each also issue a
+// third of the x, m loads, after that chunk's entry loads, so that no wait for entries
+// waits for x, m loads issued just before them (loads complete in issue order); then the
+// steady loop.  Executes nchunk barriers.
+__device__ __forceinline__ void state_load_sparse(StateRegs &st, const Tile &tl, int nchunk,
+                                                  int t, uint8_t *lds, int g, int lane) {
+    static_assert(I8S_AHEAD == 3 && SR == 32, "three register sets, 32 rows per thread");
+    EntryRegs r0, r1, r2;
+    // the prologue's chunks (past the last chunk: the last again, into stages no chunk uses)
+#pragma unroll
+    for (int c = 0; c < NST8 - 2; ++c) {
+        entries_load(r0, tl, c, nchunk, g, lane);
+        entries_place(r0, lds + c * STG8, g, lane);
+    }
+    // r0, r1, r2 take chunks NST8 - 2 + 3j, + 1 + 3j, + 2 + 3j in turn
+    entries_load(r0, tl, NST8 - 2, nchunk, g, lane);
+    entries_load(r1, tl, NST8 - 1, nchunk, g, lane);
+    entries_load(r2, tl, NST8, nchunk, g, lane);
+    if (nchunk > 0) sparse_chunk(r0, tl, 0, nchunk, lds, g, lane);
+    xm_load<0, 11>(st, tl, t);
+    if (nchunk > 1) sparse_chunk(r1, tl, 1, nchunk, lds, g, lane);
+    xm_load<11, 22>(st, tl, t);
+    if (nchunk > 2) sparse_chunk(r2, tl, 2, nchunk, lds, g, lane);
+    xm_load<22, 32>(st, tl, t);
+    st.bi = ((const g_f32 *)tl.b)[tl.I0 + (t & (BN - 1))];
+    int c = 3;
+    for (; c + 3 <= nchunk; c += 3) {
+        sparse_chunk(r0, tl, c, nchunk, lds, g, lane);
+        sparse_chunk(r1, tl, c + 1, nchunk, lds, g, lane);
+        sparse_chunk(r2, tl, c + 2, nchunk, lds, g, lane);
+    }
+    if (c < nchunk) sparse_chunk(r0, tl, c, nchunk, lds, g, lane);
+    if (c + 1 < nchunk) sparse_chunk(r1, tl, c + 1, nchunk, lds, g, lane);
+}
+
 // Waits for the loads of state_load, once, so that later stores wait for nothing.
 __device__ __forceinline__ void state_collect(StateRegs &st) {
 #pragma unroll
@@ -421,10 +573,13 @@ __device__ __forceinline__ void state_update(StateRegs &st, const Tile &tl, cons
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int e = 8 * g + u;
-                const bool live = tl.R0 + 4 * e + rsub < tl.rlive;
-                const float h = __fadd_rn(__fmul_rn(hv[u], tl.scale), st.bi);
-                pa_update(h, lt, eta, alpha, st.xv[e], st.mv[e]);
-                srow[(int64_t)4 * e * KC] = (live && st.xv[e] < 0.0f) ? (uint8_t)0xFF : (uint8_t)0x01;
+                // padding rows (uniform per wave) are not updated and their spins are not
+                // written: no live row reads them
+                if (tl.R0 + 4 * e + rsub < tl.rlive) {
+                    const float h = __fadd_rn(__fmul_rn(hv[u], tl.scale), st.bi);
+                    pa_update(h, lt, eta, alpha, st.xv[e], st.mv[e]);
+                    srow[(int64_t)4 * e * KC] = st.xv[e] < 0.0f ? (uint8_t)0xFF : (uint8_t)0x01;
+                }
             }
         }
     } else {
@@ -500,20 +655,26 @@ __device__ __forceinline__ void state_store(const StateRegs &st, const Tile &tl,
 }
 
 // One PA step of one tile: matrix and state waves side by side.
-template <bool I8, bool NT>
+template <int KIND, bool NT>
 __device__ __forceinline__ void mfma_tile_step(uint8_t *lds, const Tile &tl,
                                                const uint32_t *__restrict__ s_cur,
                                                uint32_t *__restrict__ s_nxt,
                                                float *__restrict__ h_last, float lt, float eta,
                                                float alpha) {
+    constexpr bool I8 = KIND != GK_BF16;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nchunk = (int)(tl.np / KC);
     if (wave >= MW) {
         const int t = tid - MW * 64;
         StateRegs st;
-        state_load(st, tl, nchunk, t);
-        barrier();                                     // stages drained
+        if (KIND == GK_I8_SPARSE) {
+            state_load_sparse(st, tl, nchunk, t, lds, wave - MW, lane);
+            lds_barrier();                             // stages drained (and written)
+        } else {
+            state_load(st, tl, nchunk, t);
+            barrier();                                 // stages drained
+        }
         barrier();                                     // partial sums stored
         barrier();                                     // field sums in LDS
         state_collect(st);
@@ -522,8 +683,12 @@ __device__ __forceinline__ void mfma_tile_step(uint8_t *lds, const Tile &tl,
         state_store<NT>(st, tl, t);
         return;
     }
-    if (I8)
-        matrix_step_i8(lds, tl, nchunk, reinterpret_cast<const uint8_t *>(s_cur), wave, lane);
+    if (KIND == GK_I8_SPARSE)
+        matrix_step_i8<true>(lds, tl, nchunk, reinterpret_cast<const uint8_t *>(s_cur), wave,
+                             lane);
+    else if (KIND == GK_I8)
+        matrix_step_i8<false>(lds, tl, nchunk, reinterpret_cast<const uint8_t *>(s_cur), wave,
+                              lane);
     else
         matrix_step(lds, tl, nchunk, s_cur, wave, lane);
 }
@@ -537,13 +702,14 @@ __global__ void __launch_bounds__(THREADS, 1) k_mfma_step(
     __shared__ __attribute__((aligned(16))) uint8_t lds[LDS_BYTES];
     const Tile tl{np, Rp, (int64_t)blockIdx.x * BN, (int64_t)blockIdx.y * BM, rlive, Jb, b,
                   sc->scale, x, m};
-    mfma_tile_step<false, true>(lds, tl, s_cur, s_nxt, h_last, lam[t], eta, alpha);
+    mfma_tile_step<GK_BF16, true>(lds, tl, s_cur, s_nxt, h_last, lam[t], eta, alpha);
 }
 
 // Many instances in one launch: block k runs tile k of the table.  Each tile points at
 // its instance's couplings, bias, state and the two spin buffers (picked by step parity).
-// I8: int8 couplings and byte spins (unscaled sums).
-template <bool I8>
+// KIND: GK_BF16, or int8 couplings and byte spins (unscaled sums) read as dense rows
+// (GK_I8) or as entry lists (GK_I8_SPARSE).
+template <int KIND>
 __global__ void __launch_bounds__(THREADS, 1) k_mfma_grouped(const MfmaTile *__restrict__ tiles,
                                                              int t, const float *__restrict__ lam,
                                                              float eta, float alpha) {
@@ -553,8 +719,8 @@ __global__ void __launch_bounds__(THREADS, 1) k_mfma_grouped(const MfmaTile *__r
     const uint32_t *cur = (t & 1) ? mt.s1 : mt.s0;
     uint32_t *nxt = (t & 1) ? mt.s0 : mt.s1;
     const Tile tl{mt.np, mt.Rp, mt.I0, mt.R0, mt.rlive, mt.Jb, mt.b,
-                  I8 ? 1.0f : mt.sc->scale, mt.x, mt.m};
-    mfma_tile_step<I8, false>(lds, tl, cur, nxt, nullptr, lam[t], eta, alpha);
+                  KIND != GK_BF16 ? 1.0f : mt.sc->scale, mt.x, mt.m, mt.E, mt.O};
+    mfma_tile_step<KIND, false>(lds, tl, cur, nxt, nullptr, lam[t], eta, alpha);
 }
 
 // Byte spins of the signs of x (chunk-major, 128 bytes per replica and chunk).
@@ -587,7 +753,143 @@ __global__ void __launch_bounds__(256) k_mfma_pack(int64_t Rp, int64_t np,
     }
 }
 
+// ---- sparse int8 tiles: entry lists of the 16 x 128 blocks of J8 ------------------------
+// One wave per block: lane l covers row 16 g + l / 4 of the row tile, columns
+// 32 (l % 4) .. 32 (l % 4) + 31 of the chunk.
+__device__ __forceinline__ void i8s_block(const I8sTask &tk, int64_t blk, int lane,
+                                          const int8_t *&src, int &row, int &k0) {
+    const int64_t nch = tk.np / KC;
+    const int64_t ib = blk / (nch * 8), kc = (blk / 8) % nch, g = blk % 8;
+    row = 16 * (int)g + (lane >> 2);
+    k0 = 32 * (lane & 3);
+    src = tk.J8 + (ib * KC + row) * tk.np + kc * KC + k0;
+}
+
+__device__ __forceinline__ int nonzero_bytes(uint32_t v) {
+    int c = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) c += ((v >> (8 * b)) & 0xFFu) != 0u;
+    return c;
+}
+
+__global__ void __launch_bounds__(256) k_i8s_count(const I8sTask *__restrict__ tasks) {
+    const I8sTask tk = tasks[blockIdx.y];
+    const int64_t blk = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (blk >= i8s_blocks(tk.np)) return;                 // whole waves leave together
+    const int8_t *src;
+    int row, k0;
+    i8s_block(tk, blk, lane, src, row, k0);
+    const u32x4 v0 = *reinterpret_cast<const u32x4 *>(src);
+    const u32x4 v1 = *reinterpret_cast<const u32x4 *>(src + 16);
+    int c = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) c += nonzero_bytes(v0[q]) + nonzero_bytes(v1[q]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+    if (lane == 0) tk.cnt[blk] = c;
+}
+
+// Counts -> exclusive offsets in place (nblk + 1 values, the last the total), and the
+// largest block and the total into stats.  One workgroup per task.
+__global__ void __launch_bounds__(1024) k_i8s_scan(const I8sTask *__restrict__ tasks) {
+    __shared__ int32_t part[1024], mx[1024];
+    const I8sTask tk = tasks[blockIdx.x];
+    const int64_t nblk = i8s_blocks(tk.np);
+    const int t = threadIdx.x;
+    const int64_t per = (nblk + 1023) / 1024;
+    const int64_t a = std::min<int64_t>(nblk, t * per), b = std::min<int64_t>(nblk, a + per);
+    int32_t s = 0, m = 0;
+    for (int64_t i = a; i < b; ++i) {
+        s += tk.cnt[i];
+        m = max(m, tk.cnt[i]);
+    }
+    part[t] = s;
+    mx[t] = m;
+    __syncthreads();
+    if (t == 0) {                 // 1024 partial sums in order: exact and deterministic
+        int32_t run = 0, mm = 0;
+        for (int i = 0; i < 1024; ++i) {
+            const int32_t v = part[i];
+            part[i] = run;
+            run += v;
+            mm = max(mm, mx[i]);
+        }
+        tk.stats[0] = mm;
+        tk.stats[1] = run;
+        tk.cnt[nblk] = run;
+    }
+    __syncthreads();
+    int32_t run = part[t];
+    for (int64_t i = a; i < b; ++i) {
+        const int32_t v = tk.cnt[i];
+        tk.cnt[i] = run;
+        run += v;
+    }
+}
+
+// The entries of every block (tasks whose largest block exceeds I8S_BLOCK_MAX keep their
+// dense rows and are skipped).  Within a block the entries follow (row, column) order.
+__global__ void __launch_bounds__(256) k_i8s_fill(const I8sTask *__restrict__ tasks) {
+    const I8sTask tk = tasks[blockIdx.y];
+    const int64_t blk = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (blk >= i8s_blocks(tk.np) || tk.stats[0] > I8S_BLOCK_MAX) return;
+    const int8_t *src;
+    int row, k0;
+    i8s_block(tk, blk, lane, src, row, k0);
+    const u32x4 v0 = *reinterpret_cast<const u32x4 *>(src);
+    const u32x4 v1 = *reinterpret_cast<const u32x4 *>(src + 16);
+    int c = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) c += nonzero_bytes(v0[q]) + nonzero_bytes(v1[q]);
+    int incl = c;                                     // inclusive prefix over the lanes
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    uint32_t *dst = tk.E + tk.cnt[blk] + (incl - c);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const uint32_t v = q < 4 ? v0[q] : v1[q - 4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const uint32_t w = (v >> (8 * b)) & 0xFFu;
+            if (w != 0u) {
+                const int k = k0 + 4 * q + b;
+                const uint32_t pos = (uint32_t)(row * KC + 16 * ((k >> 4) ^ (row & 7)) + (k & 15));
+                *dst++ = (w << 16) | pos;
+            }
+        }
+    }
+}
+
 }  // namespace
+
+hipError_t launch_i8s_count(const I8sTask *tasks, int32_t ntask, int64_t max_np,
+                            hipStream_t st) {
+    if (ntask <= 0) return hipSuccess;
+    const int64_t bx = (i8s_blocks(max_np) + 3) / 4;
+    if (bx <= 0 || bx > INT32_MAX || ntask > 65535) return hipErrorInvalidValue;
+    k_i8s_count<<<dim3((unsigned)bx, (unsigned)ntask), 256, 0, st>>>(tasks);
+    return hipGetLastError();
+}
+
+hipError_t launch_i8s_scan(const I8sTask *tasks, int32_t ntask, hipStream_t st) {
+    if (ntask <= 0) return hipSuccess;
+    k_i8s_scan<<<(unsigned)ntask, 1024, 0, st>>>(tasks);
+    return hipGetLastError();
+}
+
+hipError_t launch_i8s_fill(const I8sTask *tasks, int32_t ntask, int64_t max_np,
+                           hipStream_t st) {
+    if (ntask <= 0) return hipSuccess;
+    const int64_t bx = (i8s_blocks(max_np) + 3) / 4;
+    if (bx <= 0 || bx > INT32_MAX || ntask > 65535) return hipErrorInvalidValue;
+    k_i8s_fill<<<dim3((unsigned)bx, (unsigned)ntask), 256, 0, st>>>(tasks);
+    return hipGetLastError();
+}
 
 hipError_t launch_mfma_pack_spins(int64_t Rp, int64_t np, const float *x, uint32_t *sbits,
                                   hipStream_t st) {
@@ -611,13 +913,16 @@ hipError_t launch_mfma_step(int64_t Rp, int64_t np, int64_t rlive, const uint16_
 }
 
 hipError_t launch_mfma_grouped(const MfmaTile *tiles, int32_t ntiles, int32_t t,
-                               const float *lam, float eta, float alpha, bool i8,
+                               const float *lam, float eta, float alpha, GroupKind kind,
                                hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
-    if (i8)
-        k_mfma_grouped<true><<<(unsigned)ntiles, THREADS, 0, st>>>(tiles, t, lam, eta, alpha);
+    if (kind == GK_I8_SPARSE)
+        k_mfma_grouped<GK_I8_SPARSE><<<(unsigned)ntiles, THREADS, 0, st>>>(tiles, t, lam, eta,
+                                                                          alpha);
+    else if (kind == GK_I8)
+        k_mfma_grouped<GK_I8><<<(unsigned)ntiles, THREADS, 0, st>>>(tiles, t, lam, eta, alpha);
     else
-        k_mfma_grouped<false><<<(unsigned)ntiles, THREADS, 0, st>>>(tiles, t, lam, eta, alpha);
+        k_mfma_grouped<GK_BF16><<<(unsigned)ntiles, THREADS, 0, st>>>(tiles, t, lam, eta, alpha);
     return hipGetLastError();
 }
 

@@ -812,7 +812,8 @@ struct BatchPlan {
     std::vector<Plan> inst;          // per-instance single-solve plans (canonical buffers)
     std::vector<size_t> base;        // byte offset of each instance's region
     std::vector<DenseSlot> dense;
-    size_t o_tasks, o_tiles, o_score, o_scall, o_slot, o_canon, o_counter, o_lam, total;
+    size_t o_tasks, o_tiles, o_score, o_scall, o_slot, o_canon, o_counter, o_lam, o_i8s_tab,
+        o_i8s_stats, total;
     int32_t ntasks, ntiles_max, max_n;
     int32_t inst_tiles_max;   // most tiles of one dense candidate
 };
@@ -847,20 +848,27 @@ std::vector<MfmaTile> by_compute_die(const std::vector<MfmaTile> &in) {
 // over a rate.  The rates are the context's, measured by qpa_autotune_batch on this
 // device for the caller's instances; before any measurement, estimates from earlier
 // measurements on MI355X (the sparse task kernel about 0.3e12 signed coupling adds per
-// second, the grouped matrix-core step about 3e12 bytes per second).
+// second, the grouped matrix-core step about 3e12 bytes per second).  The grouped step's
+// work is its memory traffic: the couplings (2 bytes per element in BF16, or 4 bytes per
+// stored entry for integer couplings sparse enough for entry lists: at most a tenth of
+// the padded matrix is assumed here, the exact test runs on the device) and x, m.
 constexpr double SPARSE_ADDS_DEFAULT = 0.3e12, DENSE_BPS_DEFAULT = 3.0e12;
 double csr_step_work(int64_t nnz, int64_t R) { return (double)nnz * (double)R; }
-double dense_step_work(int64_t np, int64_t R) {
-    return (double)np * (double)np * 2.0 + 16.0 * (double)R * (double)np;
+double dense_step_work(int64_t np, int64_t R, int64_t nnz = -1) {
+    const double J = nnz >= 0 ? 4.0 * (double)nnz : (double)np * (double)np * 2.0;
+    return J + 16.0 * (double)R * (double)np;
+}
+bool likely_sparse_i8(const qpa_problem &p, int64_t np) {
+    return dtype_is_int(p.coupling_dtype) && (double)p.nnz <= 0.1 * (double)np * (double)np;
 }
 double csr_step_cost(const qpa_ctx *ctx, int64_t nnz, int64_t R) {
     const double r = ctx && ctx->batch_sparse_adds > 0.0 ? ctx->batch_sparse_adds
                                                         : SPARSE_ADDS_DEFAULT;
     return csr_step_work(nnz, R) / r;
 }
-double dense_step_cost(const qpa_ctx *ctx, int64_t np, int64_t R) {
+double dense_step_cost(const qpa_ctx *ctx, int64_t np, int64_t R, int64_t nnz = -1) {
     const double r = ctx && ctx->batch_dense_Bps > 0.0 ? ctx->batch_dense_Bps : DENSE_BPS_DEFAULT;
-    return dense_step_work(np, R) / r;
+    return dense_step_work(np, R, nnz) / r;
 }
 
 // Per instance: the canonical buffers, energy scratch and [groups][n][64] state of a CSR
@@ -901,8 +909,9 @@ qpa_status make_batch_plan(qpa_ctx *ctx, int32_t count, const qpa_problem *probs
         DenseSlot ds;
         const bool exact_ok = pl.is_int || a.precision == QPA_PREC_BF16;
         const int64_t np = round_up(probs[k].n, MF_NPAD), Rp = round_up(a.replicas, MF_BM);
-        const bool cheaper = dense_step_cost(ctx, np, a.replicas) <
-                             csr_step_cost(ctx, probs[k].nnz, a.replicas);
+        const bool cheaper =
+            dense_step_cost(ctx, np, a.replicas, likely_sparse_i8(probs[k], np) ? probs[k].nnz : -1) <
+            csr_step_cost(ctx, probs[k].nnz, a.replicas);
         const int32_t force = a.flags & (QPA_BATCH_SPARSE | QPA_BATCH_DENSE);
         if (exact_ok && force != QPA_BATCH_SPARSE && (cheaper || force == QPA_BATCH_DENSE)) {
             ds.cand = true;
@@ -932,16 +941,18 @@ qpa_status make_batch_plan(qpa_ctx *ctx, int32_t count, const qpa_problem *probs
         return o;
     };
     bp.o_tasks = take(sizeof(BatchTask) * (size_t)bp.ntasks);
-    // each of the two tile lists (BF16, int8) may gain up to XCDS * inst_tiles_max
-    // filler entries when it is laid out by compute die
+    // each of the three tile lists (BF16, int8, sparse int8) may gain up to
+    // XCDS * inst_tiles_max filler entries when it is laid out by compute die
     bp.o_tiles = take(sizeof(MfmaTile) *
-                      (size_t)std::max(bp.ntiles_max + 2 * XCDS * bp.inst_tiles_max, 1));
+                      (size_t)std::max(bp.ntiles_max + 3 * XCDS * bp.inst_tiles_max, 1));
     bp.o_score = take(sizeof(ScoreTask) * (size_t)std::max(count, 1));
     bp.o_scall = take(sizeof(CanonScalars) * (size_t)std::max(count, 1));
     bp.o_slot = take(sizeof(SlotInitTask) * (size_t)std::max(count, 1));
     bp.o_canon = take(sizeof(CanonTask) * (size_t)std::max(count, 1));
     bp.o_counter = take(sizeof(int32_t));
     bp.o_lam = take(sizeof(float) * (size_t)std::max<int32_t>(a.steps, 1));
+    bp.o_i8s_tab = take(sizeof(I8sTask) * (size_t)std::max(count, 1));
+    bp.o_i8s_stats = take(2 * sizeof(int32_t) * (size_t)std::max(count, 1));
     bp.total = off;
     return QPA_OK;
 }
@@ -1818,10 +1829,6 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
             }
         return hipSuccess;
     });
-    for (int32_t k = 0; k < count && s == QPA_OK; ++k) {
-        std::vector<MfmaTile> &dst = is_dense[k] == 2 ? tiles8 : tiles;
-        dst.insert(dst.end(), itiles[k].begin(), itiles[k].end());
-    }
     const qpa_status sj1 = g1.close();
     if (s == QPA_OK) s = sj1;
     if (s != QPA_OK) return s;
@@ -1887,6 +1894,73 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
         }
     }
 
+    // int8 slots whose 16 x 128 blocks hold at most I8S_BLOCK_MAX nonzeros run as sparse
+    // int8 tiles: their entry lists go into the second half of the slot's coupling buffer
+    // (J8 takes np^2 of its 2 np^2 bytes; offsets, then entries)
+    {
+        std::vector<I8sTask> ts;
+        std::vector<int32_t> who;
+        int64_t max_np = 0;
+        for (int32_t k = 0; k < count; ++k) {
+            if (is_dense[k] != 2) continue;
+            const DenseSlot &ds = bp.dense[k];
+            char *jb = ws + ds.o_Jb;
+            const size_t np2 = (size_t)(ds.np * ds.np);
+            const size_t o_cnt = align_up(np2);
+            const size_t o_e = o_cnt + align_up(sizeof(int32_t) * (size_t)(i8s_blocks(ds.np) + 1));
+            I8sTask t{};
+            t.J8 = reinterpret_cast<const int8_t *>(jb);
+            t.cnt = reinterpret_cast<int32_t *>(jb + o_cnt);
+            t.E = reinterpret_cast<uint32_t *>(jb + o_e);
+            t.stats = reinterpret_cast<int32_t *>(ws + bp.o_i8s_stats) + 2 * ts.size();
+            t.np = ds.np;
+            ts.push_back(t);
+            who.push_back(k);
+            max_np = std::max(max_np, ds.np);
+        }
+        if (!ts.empty()) {
+            const size_t tb = sizeof(I8sTask) * ts.size(), sb = 2 * sizeof(int32_t) * ts.size();
+            char *h = nullptr;
+            QPA_HIP(hipHostMalloc((void **)&h, tb + sb));
+            std::copy(ts.begin(), ts.end(), reinterpret_cast<I8sTask *>(h));
+            const I8sTask *dt = reinterpret_cast<const I8sTask *>(ws + bp.o_i8s_tab);
+            const int32_t nt = (int32_t)ts.size();
+            hipError_t e = hipMemcpyAsync(ws + bp.o_i8s_tab, h, tb, hipMemcpyHostToDevice, st);
+            if (e == hipSuccess) e = launch_i8s_count(dt, nt, max_np, st);
+            if (e == hipSuccess) e = launch_i8s_scan(dt, nt, st);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(h + tb, ws + bp.o_i8s_stats, sb, hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = launch_i8s_fill(dt, nt, max_np, st);
+            const hipError_t e2 = hipStreamSynchronize(st);
+            if (e == hipSuccess) e = e2;
+            std::vector<int32_t> stats(2 * ts.size());
+            std::copy(reinterpret_cast<int32_t *>(h + tb),
+                      reinterpret_cast<int32_t *>(h + tb) + 2 * ts.size(), stats.begin());
+            (void)hipHostFree(h);
+            if (e != hipSuccess)
+                return fail(ctx, QPA_E_DEVICE, "sparse int8 tiles: %s", hipGetErrorString(e));
+            for (size_t j = 0; j < ts.size(); ++j) {
+                if (stats[2 * j] > I8S_BLOCK_MAX) continue;
+                const int32_t k = who[j];
+                const DenseSlot &ds = bp.dense[k];
+                const size_t room = 2 * (size_t)(ds.np * ds.np) -
+                                    (size_t)(reinterpret_cast<char *>(ts[j].E) - (ws + ds.o_Jb));
+                if ((size_t)stats[2 * j + 1] * sizeof(uint32_t) > room)
+                    return fail(ctx, QPA_E_DEVICE, "instance %d: sparse int8 entries overflow", k);
+                is_dense[k] = 3;
+                for (MfmaTile &tl : itiles[k]) {
+                    tl.E = ts[j].E;
+                    tl.O = ts[j].cnt;
+                }
+            }
+        }
+    }
+    std::vector<MfmaTile> tiles8s;
+    for (int32_t k = 0; k < count; ++k) {
+        std::vector<MfmaTile> &dst = is_dense[k] == 3 ? tiles8s : is_dense[k] == 2 ? tiles8 : tiles;
+        dst.insert(dst.end(), itiles[k].begin(), itiles[k].end());
+    }
+
     // densified integer instances (n <= EBITS_MAX_N) are scored by batched launches (one
     // per kind; the energy kernels once per coupling/index type pair)
     struct ScoreGroup {
@@ -1945,10 +2019,14 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
     auto by_size = [](const MfmaTile &a, const MfmaTile &b) { return a.np > b.np; };
     std::stable_sort(tiles.begin(), tiles.end(), by_size);
     std::stable_sort(tiles8.begin(), tiles8.end(), by_size);
+    std::stable_sort(tiles8s.begin(), tiles8s.end(), by_size);
     tiles = by_compute_die(tiles);
     tiles8 = by_compute_die(tiles8);
-    const int32_t ntiles16 = (int32_t)tiles.size(), ntiles8 = (int32_t)tiles8.size();
+    tiles8s = by_compute_die(tiles8s);
+    const int32_t ntiles16 = (int32_t)tiles.size(), ntiles8 = (int32_t)tiles8.size(),
+                  ntiles8s = (int32_t)tiles8s.size();
     tiles.insert(tiles.end(), tiles8.begin(), tiles8.end());
+    tiles.insert(tiles.end(), tiles8s.begin(), tiles8s.end());
 
     // task table of the CSR instances, largest (most stored entries) first
     std::vector<std::pair<int64_t, BatchTask>> order;
@@ -2014,9 +2092,11 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
         auto loop = [&](hipStream_t s_) -> qpa_status {
             for (int32_t t = 0; t < params->steps; ++t) {
                 QPA_HIP(launch_mfma_grouped(dt16, ntiles16, t, dlam, params->eta, params->alpha,
-                                            false, s_));
+                                            GK_BF16, s_));
                 QPA_HIP(launch_mfma_grouped(dt16 + ntiles16, ntiles8, t, dlam, params->eta,
-                                            params->alpha, true, s_));
+                                            params->alpha, GK_I8, s_));
+                QPA_HIP(launch_mfma_grouped(dt16 + ntiles16 + ntiles8, ntiles8s, t, dlam,
+                                            params->eta, params->alpha, GK_I8_SPARSE, s_));
             }
             return QPA_OK;
         };
@@ -2030,6 +2110,7 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
             key_add(key, bp.o_lam);
             key_add(key, ntiles16);
             key_add(key, ntiles8);
+            key_add(key, ntiles8s);
             key_add(key, params->steps);
             key_add(key, params->eta);
             key_add(key, params->alpha);
@@ -2040,7 +2121,7 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
         if (s != QPA_OK) return s;
         if (ctx->prof) {
             QPA_HIP(hipEventRecord(sp.b, st));
-            sp.launches = (int64_t)params->steps * ((ntiles16 > 0) + (ntiles8 > 0));
+            sp.launches = (int64_t)params->steps * ((ntiles16 > 0) + (ntiles8 > 0) + (ntiles8s > 0));
             sp.path = QPA_PATH_BATCH_DENSE;
             ctx->spans.push_back(sp);
         }
@@ -2117,7 +2198,9 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
     ctx->batch_paths.assign(count, QPA_PATH_BATCH_SPARSE);
     for (int32_t k = 0; k < count; ++k)
         if (is_dense[k])
-            ctx->batch_paths[k] = is_dense[k] == 2 ? QPA_PATH_BATCH_DENSE_I8 : QPA_PATH_BATCH_DENSE;
+            ctx->batch_paths[k] = is_dense[k] == 3   ? QPA_PATH_BATCH_SPARSE_I8
+                                  : is_dense[k] == 2 ? QPA_PATH_BATCH_DENSE_I8
+                                                     : QPA_PATH_BATCH_DENSE;
     return QPA_OK;
 }
 
@@ -2547,6 +2630,8 @@ qpa_status qpa_autotune_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *pr
             const int32_t pk = ctx->batch_paths[k];
             if (f == 0 && (pk == QPA_PATH_BATCH_DENSE || pk == QPA_PATH_BATCH_DENSE_I8))
                 work += dense_step_work(round_up(problems[k].n, MF_NPAD), R);
+            if (f == 0 && pk == QPA_PATH_BATCH_SPARSE_I8)
+                work += dense_step_work(round_up(problems[k].n, MF_NPAD), R, problems[k].nnz);
             if (f == 1 && pk == QPA_PATH_BATCH_SPARSE)
                 work += csr_step_work(problems[k].nnz, R);
         }

@@ -190,12 +190,42 @@ struct MfmaTile {
     const CanonScalars *sc;
     uint32_t *s0, *s1;       // spin-bit buffers: step t reads s0 if t is even, else s1
     float *x, *m;            // [Rp][np] state of the instance
+    const uint32_t *E;       // sparse int8 tiles: nonzero entries (see below)
+    const int32_t *O;        // sparse int8 tiles: entry offsets per block, nblk + 1
     int64_t np, Rp, I0, R0, rlive;
 };
-// i8: tiles of integer instances with |J| <= 127 (int8 couplings, byte spins).
+// Kinds of grouped tiles: BF16 couplings; int8 couplings (integer |J| <= 127) read as
+// dense rows; int8 couplings read as lists of their nonzero entries.
+enum GroupKind : int { GK_BF16 = 0, GK_I8 = 1, GK_I8_SPARSE = 2 };
 hipError_t launch_mfma_grouped(const MfmaTile *tiles, int32_t ntiles, int32_t t,
-                               const float *lam, float eta, float alpha, bool i8,
+                               const float *lam, float eta, float alpha, GroupKind kind,
                                hipStream_t st);
+
+// Sparse int8 tiles.  The int8 matrix J8 [np][np] is cut into blocks of 16 rows by 128
+// columns, ordered (row tile of 128, column chunk of 128, row group of 16 within the row
+// tile): block index ((I0 / 128) * (np / 128) + kc) * 8 + g.  Each nonzero of a block is
+// one 32-bit entry: bits 0..13 its byte position in the 128 x 128 staging block of the
+// step kernel (row r = I0-relative row, column k: 128 r + 16 ((k / 16) ^ (r % 8)) +
+// k % 16), bits 16..23 the int8 weight.  O[blk] .. O[blk + 1] are the entries of a
+// block.  A block may hold at most I8S_BLOCK_MAX entries (the step kernel prefetches that
+// many per row group); denser instances keep the dense int8 rows.
+constexpr int I8S_EPL = 6;                       // entries per lane of a row-group wave
+constexpr int32_t I8S_BLOCK_MAX = 64 * I8S_EPL;  // entries per block of 16 x 128
+__host__ __device__ inline int64_t i8s_blocks(int64_t np) { return (np / 128) * (np / 128) * 8; }
+struct I8sTask {
+    const int8_t *J8;        // [np][np]
+    int32_t *cnt;            // nblk + 1 counts, then offsets (in place)
+    uint32_t *E;             // entries
+    int32_t *stats;          // [0]: largest block count, [1]: total entries
+    int64_t np;
+};
+// count: entries of every block and the per-instance largest block and total;
+// scan: counts -> offsets (exclusive, nblk + 1 values); fill: the entries.
+hipError_t launch_i8s_count(const I8sTask *tasks, int32_t ntask, int64_t max_np,
+                            hipStream_t st);
+hipError_t launch_i8s_scan(const I8sTask *tasks, int32_t ntask, hipStream_t st);
+hipError_t launch_i8s_fill(const I8sTask *tasks, int32_t ntask, int64_t max_np,
+                           hipStream_t st);
 // Byte spins (chunk-major, Rp * np bytes) and the int8 couplings of a CSR instance.
 hipError_t launch_mfma_pack_spins_i8(int64_t Rp, int64_t np, const float *x, uint8_t *s8,
                                      hipStream_t st);

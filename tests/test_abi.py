@@ -182,7 +182,7 @@ def _ws_batch(q, probs, a):
 
 def test_batch_path_flags(q):
     # a dense-friendly instance (n=1000, 10% of pairs) and a very sparse one
-    probs = [_fake_csr(q, 1000, 100_000), _fake_csr(q, 1000, 2_000)]
+    probs = [_fake_csr(q, 1000, 100_000), _fake_csr(q, 1000, 200)]
     sizes = {}
     for name, fl in [("auto", 0), ("sparse", q.QPA_BATCH_SPARSE), ("dense", q.QPA_BATCH_DENSE)]:
         a = q.make_params(64, 10, 0.1, 0.8, 4.0, flags=fl)

@@ -484,17 +484,21 @@ def _oracle_instance(inst, R, T, lam, eta, alpha, seed, r0=0):
     return x, m, canon
 
 
+@pytest.mark.parametrize("R", [70, 40])
 @pytest.mark.parametrize("path", ["auto", "sparse", "dense"])
-def test_batch_uneven_instances_bit_exact(q, eng, path):
+def test_batch_uneven_instances_bit_exact(q, eng, path, R):
     # Both batch paths give the oracle's bits on integer instances.  The last instance has
     # couplings up to 300 (not exact in BF16), so it stays sparse even when dense is forced.
+    # R = 70: a full and a partial group of 64 (sparse kernel), live replicas in both halves
+    # of the matrix-core tile; R = 40: only the first half of the tile is live.
     rng = np.random.default_rng(7)
     insts = [gen.er_qubo(int(n), 0.1, 100, rng) for n in rng.integers(30, 400, size=9)]
+    insts.append(gen.er_qubo(200, 0.5, 100, rng))       # too dense for int8 entry lists
     insts.append(gen.chimera_ising(3, seed=5))          # an Ising instance in the same batch
     insts.append(gen.er_qubo(400, 0.005, 100, rng))     # sparse enough for the sparse kernel
     insts.append(gen.er_qubo(250, 0.1, 200, rng))       # |w| up to 200: BF16 tiles, not int8
     insts.append(gen.er_qubo(300, 0.2, 300, rng))
-    R, T, eta, alpha, lam0 = 70, 60, 0.0002, 0.8, 200.0  # 70 replicas: a full and a partial group
+    T, eta, alpha, lam0 = 60, 0.0002, 0.8, 200.0
     probs = [q.Problem.from_instance(i) for i in insts]
     flags = {"auto": 0, "sparse": q.QPA_BATCH_SPARSE, "dense": q.QPA_BATCH_DENSE}[path]
     p = _params(q, R, T, eta, alpha, lam0, seed=11, flags=flags)
@@ -505,11 +509,16 @@ def test_batch_uneven_instances_bit_exact(q, eng, path):
     if path == "sparse":
         assert (paths == q.QPA_PATH_BATCH_SPARSE).all()
     elif path == "dense":
-        assert (paths[:-2] == q.QPA_PATH_BATCH_DENSE_I8).all()   # |w| <= 127: int8 tiles
+        # |w| <= 127: int8 tiles, as entry lists where every 16 x 128 block is sparse enough
+        assert (paths[:9] == q.QPA_PATH_BATCH_SPARSE_I8).all()
+        assert paths[9] == q.QPA_PATH_BATCH_DENSE_I8             # half of all pairs
+        assert (paths[10:12] == q.QPA_PATH_BATCH_SPARSE_I8).all()
         assert paths[-2] == q.QPA_PATH_BATCH_DENSE               # |w| <= 200: BF16 tiles
     else:                                                  # the cost model mixes both
-        assert paths[0] == q.QPA_PATH_BATCH_DENSE_I8        # n=379, 10% of pairs
-        assert paths[-3] == q.QPA_PATH_BATCH_SPARSE         # n=400, 0.5% of pairs
+        assert paths[0] == q.QPA_PATH_BATCH_SPARSE_I8       # n=379, 10% of pairs
+        assert paths[9] == q.QPA_PATH_BATCH_DENSE_I8        # n=200, 50% of pairs
+        if R == 70:                                        # (near the break-even at 40)
+            assert paths[-3] == q.QPA_PATH_BATCH_SPARSE     # n=400, 0.5% of pairs
     lam = orc.lambda_linear(T, lam0)
     for k, (inst, out) in enumerate(zip(insts, outs)):
         x, m, canon = _oracle_instance(inst, R, T, lam, eta, alpha, seed=11 + k)
@@ -525,8 +534,9 @@ def test_batch_uneven_instances_bit_exact(q, eng, path):
 def test_batch_autotune_measures_rates_and_chooses_by_them(q, eng):
     """qpa_autotune_batch measures both paths on the device; afterwards every instance
     takes the path the cost model gives with the measured rates (dense when BF16-exact and
-    (2 np^2 + 16 R np) / dense rate < nnz R / sparse rate), and the results are the
-    oracle's bits."""
+    (J bytes + 16 R np) / dense rate < nnz R / sparse rate, J bytes 4 nnz for integer
+    couplings with nnz <= np^2 / 10, else 2 np^2), and the results are the oracle's
+    bits."""
     rng = np.random.default_rng(17)
     insts = [gen.er_qubo(int(n), 0.1, 100, rng) for n in (60, 200, 350)]
     insts += [gen.chimera_ising(4, seed=3), gen.er_qubo(600, 0.004, 100, rng),
@@ -542,7 +552,8 @@ def test_batch_autotune_measures_rates_and_chooses_by_them(q, eng):
     paths = q.qpa_batch_paths(eng.ctx, len(insts))
     for k, inst in enumerate(insts):
         np_ = -(-inst.n // 128) * 128
-        dense_cost = (2.0 * np_ * np_ + 16.0 * R * np_) / dense_bps
+        jb = 4.0 * inst.csr.nnz if inst.csr.nnz <= 0.1 * np_ * np_ else 2.0 * np_ * np_
+        dense_cost = (jb + 16.0 * R * np_) / dense_bps
         sparse_cost = inst.csr.nnz * R / sparse_adds
         exact = int(np.abs(inst.csr.w).max(initial=0)) <= 256
         want_dense = exact and dense_cost < sparse_cost
@@ -583,10 +594,13 @@ def test_batch_reports_the_failing_instance(q, eng):
 
 def test_batch_scoring_size_limits(q, eng):
     # Dense-forced batch at the largest instance size of a batch (n = 4096, also the
-    # largest of the bit-packed batched energies: 64 sign words per replica in LDS) and a
-    # small one; R = 70 spans two replica groups.  A larger instance is refused.
+    # largest of the bit-packed batched energies: 64 sign words per replica in LDS; int8
+    # entry lists over 32 chunks), a small one, and one too dense for entry lists (int8
+    # rows over 8 chunks, more than the 5 stages); R = 70 spans two replica groups.  A
+    # larger instance is refused.
     rng = np.random.default_rng(21)
-    insts = [gen.er_qubo(4096, 0.01, 100, rng), gen.er_qubo(300, 0.1, 100, rng)]
+    insts = [gen.er_qubo(4096, 0.01, 100, rng), gen.er_qubo(300, 0.1, 100, rng),
+             gen.er_qubo(1000, 0.3, 100, rng)]
     R, T, eta, alpha, lam0 = 70, 4, 0.0002, 0.8, 200.0
     p = _params(q, R, T, eta, alpha, lam0, seed=13, flags=q.QPA_BATCH_DENSE)
     with pytest.raises(q.QpaError) as ei:
@@ -594,7 +608,8 @@ def test_batch_scoring_size_limits(q, eng):
     assert ei.value.status == q.QPA_E_UNSUPPORTED, str(ei.value)
     say("batch at the size limit, n=4096/300, R=70")
     outs = eng.solve_batch([q.Problem.from_instance(i) for i in insts], p, want_state=True)
-    assert (q.qpa_batch_paths(eng.ctx, len(insts)) == q.QPA_PATH_BATCH_DENSE_I8).all()
+    assert list(q.qpa_batch_paths(eng.ctx, len(insts))) == [
+        q.QPA_PATH_BATCH_SPARSE_I8, q.QPA_PATH_BATCH_SPARSE_I8, q.QPA_PATH_BATCH_DENSE_I8]
     lam = orc.lambda_linear(T, lam0)
     for k, (inst, out) in enumerate(zip(insts, outs)):
         x, m, canon = _oracle_instance(inst, R, T, lam, eta, alpha, seed=13 + k)
@@ -614,6 +629,7 @@ def test_er512_full_workload_sampled(q, eng):
     p = _params(q, wl.replicas, wl.steps, wl.eta, wl.alpha, wl.lambda0, seed=wl.seed)
     say("er512 full workload solve")
     outs = eng.solve_batch(probs, p, want_state=True)
+    assert (q.qpa_batch_paths(eng.ctx, len(insts)) == q.QPA_PATH_BATCH_SPARSE_I8).all()
     lam = orc.lambda_linear(wl.steps, wl.lambda0)
     sizes = np.array([i.n for i in insts])
     for k in [int(np.argmin(sizes)), int(np.argmax(sizes)), 137]:
@@ -785,14 +801,15 @@ def test_graph_step_loop_matches_plain_launches(q, eng, which):
 
 def test_graph_batch_step_loop_matches_plain_launches(q, eng):
     """qpa_solve_batch with QPA_SOLVE_GRAPH: the captured per-step loop of the dense tiles
-    (int8 and BF16 tiles in one batch, beside a sparse instance) replayed three times with
-    eager work in between, then replayed for a second batch of the same shapes but other
-    couplings, gives the bits of the plain launches every time."""
+    (int8 entry-list, int8 and BF16 tiles in one batch, beside a sparse instance) replayed
+    three times with eager work in between, then replayed for a second batch of the same
+    shapes but other couplings, gives the bits of the plain launches every time."""
     import torch
 
     def batch(seed):
         rng = np.random.default_rng(seed)
-        return [gen.er_qubo(180, 0.1, 100, rng), gen.er_qubo(300, 0.1, 200, rng),
+        return [gen.er_qubo(180, 0.1, 100, rng), gen.er_qubo(200, 0.4, 100, rng),
+                gen.er_qubo(300, 0.1, 200, rng),
                 gen.er_qubo(260, 0.1, 300, rng)]          # the last is never densified
     R, T, eta, alpha, lam0 = 70, 30, 0.0002, 0.8, 200.0
     for seed in (1, 2):
@@ -801,8 +818,8 @@ def test_graph_batch_step_loop_matches_plain_launches(q, eng):
         ref = eng.solve_batch(probs, _params(q, R, T, eta, alpha, lam0, seed=4,
                                              flags=q.QPA_BATCH_DENSE), want_state=True)
         paths = q.qpa_batch_paths(eng.ctx, len(probs))
-        assert list(paths) == [q.QPA_PATH_BATCH_DENSE_I8, q.QPA_PATH_BATCH_DENSE,
-                               q.QPA_PATH_BATCH_SPARSE]
+        assert list(paths) == [q.QPA_PATH_BATCH_SPARSE_I8, q.QPA_PATH_BATCH_DENSE_I8,
+                               q.QPA_PATH_BATCH_DENSE, q.QPA_PATH_BATCH_SPARSE]
         pg = _params(q, R, T, eta, alpha, lam0, seed=4,
                      flags=q.QPA_BATCH_DENSE | q.QPA_SOLVE_GRAPH)
         for rep in range(3 if seed == 1 else 1):
