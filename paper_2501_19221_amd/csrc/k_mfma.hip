@@ -70,6 +70,7 @@ constexpr int THREADS = 1024;                // 8 matrix waves + 8 state waves
 constexpr int MW = 8;                        // matrix waves
 constexpr int SR = BM / 4;                   // rows per state thread
 static_assert(LDS_BYTES >= BM * HS * 4, "the field handoff reuses the stages");
+static_assert(LDS_BYTES >= 2 * BM * HS * 4, "the int8 handoff's two partial-sum buffers too");
 static_assert(LDS_BYTES <= 160 * 1024, "LDS of one workgroup");
 static_assert(MF_NPAD % KC == 0, "np must be a multiple of the chunk");
 
@@ -347,25 +348,23 @@ __device__ __forceinline__ void matrix_step_i8(uint8_t *lds, const Tile &tl, int
         }
     }
     wait_barrier<0>();
-    // exact integer sums (rows are validated below 2^24) go to the state waves as floats
+    // the two k halves' exact int32 partial sums go to two handoff buffers (the state
+    // waves add them; rows are validated below 2^24), in one pass and one barrier; waves
+    // whose rows are all padding write nothing
+    if (rows_here) {
+        int32_t *hp0 = reinterpret_cast<int32_t *>(hs) + kh * (BM * HS);
 #pragma unroll
-    for (int pass = 0; pass < 2; ++pass) {
-        if (kh == pass) {
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j)
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
-#pragma unroll
-                    for (int v = 0; v < 16; ++v) {
-                        const int row = 64 * wr + 32 * i + 8 * (v >> 2) + 4 * half + (v & 3);
-                        const int col = 64 * wc + 32 * j + l32;
-                        float *hp = hs + row * HS + col;
-                        const float f = (float)acc[i][j][v];
-                        *hp = pass == 0 ? f : *hp + f;
-                    }
-        }
-        wait_barrier<0>();
+                for (int v = 0; v < 16; ++v) {
+                    const int row = 64 * wr + 32 * i + 8 * (v >> 2) + 4 * half + (v & 3);
+                    const int col = 64 * wc + 32 * j + l32;
+                    hp0[row * HS + col] = acc[i][j][v];
+                }
     }
+    wait_barrier<0>();
 }
 
 // ---- state waves: thread t (0..511) owns column t % 128 of rows 4e + t / 128 ---------
@@ -514,12 +513,15 @@ __device__ __forceinline__ void state_load_sparse(StateRegs &st, const Tile &tl,
                                                   int t, uint8_t *lds, int g, int lane) {
     static_assert(I8S_AHEAD == 3 && SR == 32, "three register sets, 32 rows per thread");
     EntryRegs r0, r1, r2;
-    // the prologue's chunks (past the last chunk: the last again, into stages no chunk uses)
-#pragma unroll
-    for (int c = 0; c < NST8 - 2; ++c) {
-        entries_load(r0, tl, c, nchunk, g, lane);
-        entries_place(r0, lds + c * STG8, g, lane);
-    }
+    // the prologue's chunks, loaded together (past the last chunk: the last again, into
+    // stages no chunk uses)
+    static_assert(NST8 - 2 == 3, "the prologue's chunks take the three register sets");
+    entries_load(r0, tl, 0, nchunk, g, lane);
+    entries_load(r1, tl, 1, nchunk, g, lane);
+    entries_load(r2, tl, 2, nchunk, g, lane);
+    entries_place(r0, lds, g, lane);
+    entries_place(r1, lds + STG8, g, lane);
+    entries_place(r2, lds + 2 * STG8, g, lane);
     // r0, r1, r2 take chunks NST8 - 2 + 3j, + 1 + 3j, + 2 + 3j in turn
     entries_load(r0, tl, NST8 - 2, nchunk, g, lane);
     entries_load(r1, tl, NST8 - 1, nchunk, g, lane);
@@ -565,18 +567,24 @@ __device__ __forceinline__ void state_update(StateRegs &st, const Tile &tl, cons
         // spins as bytes: row r of chunk I0/128 at (chunk * Rp + r) * 128 + col
         uint8_t *srow = reinterpret_cast<uint8_t *>(s_nxt) +
                         ((tl.I0 / KC) * tl.Rp + tl.R0 + rsub) * KC + col;
+        // field = sum of the two k halves' int32 partials (exact), unscaled
+        const int32_t *h0 = reinterpret_cast<const int32_t *>(hs), *h1 = h0 + BM * HS;
 #pragma unroll
         for (int g = 0; g < SR / 8; ++g) {
-            float hv[8];
+            // padding rows (uniform per wave) are not read, not updated and their spins are
+            // not written: no live row reads them
+            if (tl.R0 + 4 * (8 * g) + rsub >= tl.rlive) continue;
+            int32_t hv[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) hv[u] = hs[(4 * (8 * g + u) + rsub) * HS + col];
+            for (int u = 0; u < 8; ++u) {
+                const int k = (4 * (8 * g + u) + rsub) * HS + col;
+                hv[u] = h0[k] + h1[k];
+            }
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int e = 8 * g + u;
-                // padding rows (uniform per wave) are not updated and their spins are not
-                // written: no live row reads them
                 if (tl.R0 + 4 * e + rsub < tl.rlive) {
-                    const float h = __fadd_rn(__fmul_rn(hv[u], tl.scale), st.bi);
+                    const float h = __fadd_rn((float)hv[u], st.bi);
                     pa_update(h, lt, eta, alpha, st.xv[e], st.mv[e]);
                     srow[(int64_t)4 * e * KC] = st.xv[e] < 0.0f ? (uint8_t)0xFF : (uint8_t)0x01;
                 }
@@ -619,7 +627,7 @@ __device__ __forceinline__ void state_update(StateRegs &st, const Tile &tl, cons
         }
     }
     }
-    if (h_last) {
+    if (!I8 && h_last) {           // (the grouped int8 tiles store no last field)
         float *hr = h_last + (tl.R0 + rsub) * tl.np + tl.I0;
 #pragma unroll
         for (int e = 0; e < SR; ++e) {
@@ -675,7 +683,7 @@ __device__ __forceinline__ void mfma_tile_step(uint8_t *lds, const Tile &tl,
             state_load(st, tl, nchunk, t);
             barrier();                                 // stages drained
         }
-        barrier();                                     // partial sums stored
+        if (!I8) barrier();                            // BF16: first k half's sums stored
         barrier();                                     // field sums in LDS
         state_collect(st);
         state_update<I8>(st, tl, reinterpret_cast<const float *>(lds), s_nxt, h_last, t,
