@@ -21,8 +21,8 @@
 // chunk publishes a stage and frees the one that is loaded next; the state waves take
 // part in every barrier and issue no loads in between, so that the matrix waves' waits
 // count their own loads only.  After the loop the raw sums go to the state waves
-// through LDS (128 x 128 FP32, rows padded to 136 so that the two halves of a wave's
-// stores use different banks).
+// through LDS, one 128 x 128 FP32 buffer per k half (rows padded to 136 so that the two
+// halves of a wave's stores use different banks), added by the state waves.
 //
 // Spins ("pair words", chunk-major): for replica r and chunk kc (variables 128 kc ..
 // 128 kc + 127) there are 16 u32 words at (kc * Rp + r) * 16.  Word 8 h + q covers the
@@ -233,24 +233,20 @@ __device__ __forceinline__ void matrix_step(uint8_t *lds, const Tile &tl, int nc
     }
     wait_barrier<0>();     // the trailing (redundant) loads have landed in every wave and
                            // every stage read is done: the stages can take the sums
-    // the first k half stores its sums, the second adds its own
+    // each k half stores its sums into its own buffer (the state waves add the two, first
+    // half + second half), in one pass
+    float *hp0 = hs + kh * (BM * HS);
 #pragma unroll
-    for (int pass = 0; pass < 2; ++pass) {
-        if (kh == pass) {
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
-#pragma unroll
-                    for (int v = 0; v < 16; ++v) {
-                        const int row = 64 * wr + 32 * i + 8 * (v >> 2) + 4 * half + (v & 3);
-                        const int col = 64 * wc + 32 * j + l32;
-                        float *hp = hs + row * HS + col;
-                        *hp = pass == 0 ? acc[i][j][v] : *hp + acc[i][j][v];
-                    }
-        }
-        wait_barrier<0>();  // pass 0: partial sums stored; pass 1: field sums complete
-    }
+            for (int v = 0; v < 16; ++v) {
+                const int row = 64 * wr + 32 * i + 8 * (v >> 2) + 4 * half + (v & 3);
+                const int col = 64 * wc + 32 * j + l32;
+                hp0[row * HS + col] = acc[i][j][v];
+            }
+    wait_barrier<0>();      // partial sums stored
 }
 
 // ---- matrix waves, int8 couplings ---------------------------------------------------
@@ -597,7 +593,10 @@ __device__ __forceinline__ void state_update(StateRegs &st, const Tile &tl, cons
     for (int g = 0; g < SR / 8; ++g) {
         float hv[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) hv[u] = hs[(4 * (8 * g + u) + rsub) * HS + col];
+        for (int u = 0; u < 8; ++u) {
+            const int k = (4 * (8 * g + u) + rsub) * HS + col;
+            hv[u] = hs[k] + hs[BM * HS + k];          // first k half + second k half
+        }
         uint64_t bal[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -632,7 +631,10 @@ __device__ __forceinline__ void state_update(StateRegs &st, const Tile &tl, cons
 #pragma unroll
         for (int e = 0; e < SR; ++e) {
             if (tl.R0 + 4 * e + rsub < tl.rlive)
-                hr[col] = __fadd_rn(__fmul_rn(hs[(4 * e + rsub) * HS + col], tl.scale), st.bi);
+                hr[col] = __fadd_rn(__fmul_rn(hs[(4 * e + rsub) * HS + col] +
+                                                  hs[BM * HS + (4 * e + rsub) * HS + col],
+                                              tl.scale),
+                                    st.bi);
             hr = next_rows(hr, 4 * tl.np);
         }
     }
@@ -683,8 +685,7 @@ __device__ __forceinline__ void mfma_tile_step(uint8_t *lds, const Tile &tl,
             state_load(st, tl, nchunk, t);
             barrier();                                 // stages drained
         }
-        if (!I8) barrier();                            // BF16: first k half's sums stored
-        barrier();                                     // field sums in LDS
+        barrier();                                     // partial sums stored
         state_collect(st);
         state_update<I8>(st, tl, reinterpret_cast<const float *>(lds), s_nxt, h_last, t,
                             wave, lane, lt, eta, alpha);
