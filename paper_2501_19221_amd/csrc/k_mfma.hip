@@ -56,21 +56,26 @@ constexpr int SSTG = BM * 64;                // spin words of a stage: 128 rows 
 constexpr int STG = JSTG + SSTG;
 constexpr int NST = 4;                       // stages
 constexpr int LDS_BYTES = NST * STG;
-// Integer couplings with |J| <= 127 (exact in int8): J rows of 128 bytes, spins one byte
-// per (replica, variable) (+1 = 0x01, -1 = 0xFF), chunk-major like the pair words (128
-// bytes per replica and chunk), v_mfma_i32_32x32x32_i8 with exact int32 sums.
-constexpr int JSTG8 = BN * KC;               // 128 rows x 128 bytes
-constexpr int SSTG8 = BM * KC;               // 128 replicas x 128 bytes
+// Integer couplings with |J| <= 127 (exact in int8) run on tiles of 64 replicas x 256
+// variables (see the int8 section below): J rows of 128 bytes per chunk, spins one byte per
+// (replica, variable) (+1 = 0x01, -1 = 0xFF), chunk-major (128 bytes per replica and
+// chunk), v_mfma_i32_32x32x32_i8 with exact int32 sums.
+constexpr int BM8 = MF_BM8, BN8 = MF_BN8;    // 64 replicas x 256 variables
+constexpr int JSTG8 = BN8 * KC;              // 256 rows x 128 bytes
+constexpr int SSTG8 = BM8 * KC;              // 64 replicas x 128 bytes
 constexpr int STG8 = JSTG8 + SSTG8;
-constexpr int NST8 = 5;
+constexpr int NST8 = 4;
+constexpr int HS8 = BN8 + 8;                 // row stride of the int8 handoff (int32)
+constexpr int SR8 = BM8 / 2;                 // rows per state thread of an int8 tile
 static_assert(NST8 * STG8 <= LDS_BYTES, "int8 stages fit the same LDS");
-constexpr int LOADS_PER_CHUNK8 = 4;          // per matrix wave: 2 J pieces + 2 spin pieces
+static_assert(2 * BM8 * HS8 * 4 <= LDS_BYTES, "the int8 handoff's two partial-sum buffers");
+static_assert(BN8 % KC == 0 && BN8 / 16 == 16, "16 row groups of 16 per int8 tile");
 constexpr int HS = BN + 8;                   // row stride of the field handoff (floats)
 constexpr int THREADS = 1024;                // 8 matrix waves + 8 state waves
 constexpr int MW = 8;                        // matrix waves
 constexpr int SR = BM / 4;                   // rows per state thread
 static_assert(LDS_BYTES >= BM * HS * 4, "the field handoff reuses the stages");
-static_assert(LDS_BYTES >= 2 * BM * HS * 4, "the int8 handoff's two partial-sum buffers too");
+static_assert(LDS_BYTES >= 2 * BM * HS * 4, "the two k halves' handoff buffers");
 static_assert(LDS_BYTES <= 160 * 1024, "LDS of one workgroup");
 static_assert(MF_NPAD % KC == 0, "np must be a multiple of the chunk");
 
@@ -249,120 +254,6 @@ __device__ __forceinline__ void matrix_step(uint8_t *lds, const Tile &tl, int nc
     wait_barrier<0>();      // partial sums stored
 }
 
-// ---- matrix waves, int8 couplings ---------------------------------------------------
-// As matrix_step with J and spins as bytes: per chunk two 1 KiB loads of J (rows
-// 16w + 8u + lane/8, position lane % 8 holding piece (lane % 8) ^ (row % 8)) and two of
-// spins (replica rows likewise) per wave; four k steps of 32 (wave kh takes 2 kh and
-// 2 kh + 1); the operand of k step q and lane half h is piece 2 q + h of the row.
-// SPARSE: the coupling half of every stage is written by the state waves from the
-// tile's entry lists (state_load_sparse); the matrix waves load only the spins.
-template <bool SPARSE>
-__device__ __forceinline__ void matrix_step_i8(uint8_t *lds, const Tile &tl, int nchunk,
-                                               const uint8_t *__restrict__ s_cur, int wave,
-                                               int lane) {
-    const int64_t np = tl.np, I0 = tl.I0, R0 = tl.R0;
-    const uint8_t *__restrict__ J8 = reinterpret_cast<const uint8_t *>(tl.Jb);
-    float *hs = reinterpret_cast<float *>(lds);
-    const int kh = wave >> 2;                      // k steps 2 kh, 2 kh + 1 of a chunk
-    const int wr = (wave >> 1) & 1, wc = wave & 1;
-    const int half = lane >> 5, l32 = lane & 31;
-    const uint8_t *gJ[2], *gS[2];
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-        const int row = 16 * wave + 8 * u + (lane >> 3);
-        const int piece = (lane & 7) ^ (row & 7);
-        gJ[u] = J8 + (I0 + row) * np + 16 * piece;
-        gS[u] = s_cur + (R0 + row) * KC + 16 * piece;
-    }
-    const int64_t sstride = tl.Rp * KC;            // bytes between consecutive spin chunks
-    // Replica rows 64..127 of a tile with no live replica there (fewer than 65 live rows,
-    // e.g. 64 replicas padded to 128) are neither loaded (waves 4..7) nor multiplied (the
-    // waves of wr = 1): rows are independent, and padding rows are never stored.
-    const bool upper = tl.R0 + 64 < tl.rlive;
-    const bool spins_here = wave < 4 || upper, rows_here = wr == 0 || upper;
-    auto stage = [&](int kc, int st) {
-        kc = kc < nchunk ? kc : nchunk - 1;        // past the end: reload the last chunk
-        uint8_t *dst = lds + st * STG8;
-        if (!SPARSE) {
-#pragma unroll
-            for (int u = 0; u < 2; ++u)
-                __builtin_amdgcn_global_load_lds(gJ[u] + (int64_t)kc * KC,
-                                                 (lds_void *)(dst + (2 * wave + u) * 1024), 16, 0,
-                                                 0);
-        }
-        if (spins_here) {
-#pragma unroll
-            for (int u = 0; u < 2; ++u)
-                __builtin_amdgcn_global_load_lds(gS[u] + (int64_t)kc * sstride,
-                                                 (lds_void *)(dst + JSTG8 + (2 * wave + u) * 1024),
-                                                 16, 0, 0);
-        }
-    };
-    // loads per chunk of this wave: 2 of J rows (dense only), 2 of spins (if spins_here)
-    constexpr int LJ = SPARSE ? 0 : 2;
-    i32x16 acc[2][2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) acc[i][j][v] = 0;
-
-#pragma unroll
-    for (int s = 0; s < NST8 - 1; ++s) stage(s, s);
-    static_assert(LOADS_PER_CHUNK8 == 4, "2 J pieces + 2 spin pieces");
-    for (int c = 0; c < nchunk; ++c) {
-        if (spins_here)
-            wait_barrier<(NST8 - 2) * (LJ + 2)>();
-        else
-            wait_barrier<(NST8 - 2) * LJ>();
-        stage(c + NST8 - 1, (c + NST8 - 1) % NST8);
-        const uint8_t *src = lds + (c % NST8) * STG8;
-        if (rows_here) {
-#pragma unroll
-        for (int qq = 0; qq < 2; ++qq) {
-            const int piece = 2 * (2 * kh + qq) + half;
-            i32x4 a[2], bq[2];
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const int row = 64 * wr + 32 * i + l32;
-                a[i] = *reinterpret_cast<const i32x4 *>(src + JSTG8 + row * KC +
-                                                        16 * (piece ^ (row & 7)));
-            }
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int row = 64 * wc + 32 * j + l32;
-                bq[j] = *reinterpret_cast<const i32x4 *>(src + row * KC + 16 * (piece ^ (row & 7)));
-            }
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], bq[j], acc[i][j], 0,
-                                                                      0, 0);
-        }
-        }
-    }
-    wait_barrier<0>();
-    // the two k halves' exact int32 partial sums go to two handoff buffers (the state
-    // waves add them; rows are validated below 2^24), in one pass and one barrier; waves
-    // whose rows are all padding write nothing
-    if (rows_here) {
-        int32_t *hp0 = reinterpret_cast<int32_t *>(hs) + kh * (BM * HS);
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-#pragma unroll
-                for (int v = 0; v < 16; ++v) {
-                    const int row = 64 * wr + 32 * i + 8 * (v >> 2) + 4 * half + (v & 3);
-                    const int col = 64 * wc + 32 * j + l32;
-                    hp0[row * HS + col] = acc[i][j][v];
-                }
-    }
-    wait_barrier<0>();
-}
-
 // ---- state waves: thread t (0..511) owns column t % 128 of rows 4e + t / 128 ---------
 // Row pointers are wave-uniform and advanced one row pair at a time through an opaque
 // step, so that the compiler computes each address when it is used instead of holding
@@ -407,138 +298,6 @@ __device__ __forceinline__ void state_load(StateRegs &st, const Tile &tl, int nc
     for (; passed < nchunk; ++passed) barrier();   // the remaining chunks
 }
 
-// ---- state waves of sparse int8 tiles: they also write the coupling half of the stages
-// State wave g (0..7) owns rows 16g .. 16g + 15 of the 128 x 128 coupling block of every
-// chunk: it clears its 2 KiB of the stage and writes the nonzeros of its block there, one
-// byte store per entry (the entry holds its staging position and weight).  The entries of
-// chunk c + NST8 - 2 are placed after the barrier of chunk c, into the stage of chunk
-// c - 2 (free since the barrier of chunk c - 1); the chunks before the first barrier are
-// placed by a prologue.  Entry loads run three chunks ahead (three register sets used in
-// turn), so that their latency is hidden behind three chunk periods as the matrix waves'
-// loads are.  Loads and stores are issued without per-lane branches, so that each wait
-// for a register set covers that set only: lanes past a block's end load and store its
-// last entry again (the same byte with the same value), loads past the last chunk reload
-// it.  A block has at most I8S_BLOCK_MAX entries (I8S_EPL per lane).
-struct EntryRegs {
-    uint32_t e[I8S_EPL];
-    int32_t cnt;
-};
-
-// The table's pointers are generic; these views make the offsets scalar loads (uniform,
-// read-only during the launch) and the entries, x and m global loads, which count on the
-// vector-memory counter only (generic loads also count on the counter that the LDS
-// barriers wait for).
-typedef __attribute__((address_space(4))) const int32_t c_i32;
-typedef __attribute__((address_space(1))) const uint32_t g_u32;
-typedef __attribute__((address_space(1))) const float g_f32;
-
-__device__ __forceinline__ void entries_load(EntryRegs &er, const Tile &tl, int kc, int nchunk,
-                                             int g, int lane) {
-    kc = kc < nchunk ? kc : nchunk - 1;
-    const int64_t blk = ((tl.I0 / KC) * (tl.np / KC) + kc) * 8 + g;
-    const c_i32 *O = (const c_i32 *)tl.O;
-    const int32_t beg = O[blk];
-    er.cnt = O[blk + 1] - beg;
-    // an empty block reads the word at its start, which lies inside the coupling buffer
-    // (the entries end at least a quarter of the buffer before its end); it is not placed
-    const g_u32 *src = (const g_u32 *)tl.E + beg;
-    const int32_t last = max(er.cnt - 1, 0);
-#pragma unroll
-    for (int j = 0; j < I8S_EPL; ++j) er.e[j] = src[min(lane + 64 * j, last)];
-}
-
-// Clears this wave's 2 KiB of the stage and writes its entries there.  Positions are taken
-// within the wave's own rows (an entry of row group g already lies there), so that the
-// words an empty block loaded write zeros into cleared bytes of the same rows.
-__device__ __forceinline__ void entries_place(const EntryRegs &er, uint8_t *stage, int g,
-                                              int lane) {
-    uint8_t *rg = stage + 2048 * g;
-    *reinterpret_cast<u32x4 *>(rg + 16 * lane) = (u32x4){0u, 0u, 0u, 0u};
-    *reinterpret_cast<u32x4 *>(rg + 1024 + 16 * lane) = (u32x4){0u, 0u, 0u, 0u};
-    const uint32_t keep = er.cnt > 0 ? 0xFFFFFFFFu : 0u;
-#pragma unroll
-    for (int j = 0; j < I8S_EPL; ++j)
-        rg[er.e[j] & 0x7FFu] = (uint8_t)((er.e[j] & keep) >> 16);
-}
-
-// The LDS stores of this wave are complete, then the workgroup barrier.
-__device__ __forceinline__ void lds_barrier() {
-    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-}
-
-constexpr int I8S_AHEAD = 3;                     // chunks of entries in flight
-static_assert(NST8 - 2 >= 1, "a chunk is placed at least one barrier before it is used");
-
-// One chunk barrier of the state waves: then the entries held in er (chunk c + NST8 - 2)
-// are placed and er is reloaded with the chunk I8S_AHEAD further on.  Past the last chunk
-// the reloaded last chunk is placed again, into the stage of chunk c - 2, which no later
-// chunk of the loop uses (they take the stages of chunks c + 1, c + 2 at most); the first
-// barrier after the loop waits for these stores, before the stages take the sums.  No
-// branch: the waits for one register set cover that set only.
-__device__ __forceinline__ void sparse_chunk(EntryRegs &er, const Tile &tl, int c, int nchunk,
-                                             uint8_t *lds, int g, int lane) {
-    lds_barrier();
-    const int kc = c + NST8 - 2;
-    entries_place(er, lds + (kc % NST8) * STG8, g, lane);
-    entries_load(er, tl, kc + I8S_AHEAD, nchunk, g, lane);
-}
-
-// x, m of rows E0 .. E1 - 1 of this thread (padding rows are not read).
-template <int E0, int E1>
-__device__ __forceinline__ void xm_load(StateRegs &st, const Tile &tl, int t) {
-    const int col = t & (BN - 1);
-    const int rsub = __builtin_amdgcn_readfirstlane(t >> 7);
-    const g_f32 *xr = (const g_f32 *)tl.x + (tl.R0 + 4 * E0 + rsub) * tl.np + tl.I0;
-    const g_f32 *mr = (const g_f32 *)tl.m + (tl.R0 + 4 * E0 + rsub) * tl.np + tl.I0;
-#pragma unroll
-    for (int e = E0; e < E1; ++e) {
-        const bool live = tl.R0 + 4 * e + rsub < tl.rlive;
-        st.xv[e] = live ? xr[col] : 0.0f;
-        st.mv[e] = live ? mr[col] : 0.0f;
-        xr = next_rows(xr, 4 * tl.np);
-        mr = next_rows(mr, 4 * tl.np);
-    }
-}
-
-// state_load for sparse int8 tiles: the prologue's chunks are placed and the entries of
-// the next three chunks loaded; the first three chunk barriers (peeled) each also issue a
-// third of the x, m loads, after that chunk's entry loads, so that no wait for entries
-// waits for x, m loads issued just before them (loads complete in issue order); then the
-// steady loop.  Executes nchunk barriers.
-__device__ __forceinline__ void state_load_sparse(StateRegs &st, const Tile &tl, int nchunk,
-                                                  int t, uint8_t *lds, int g, int lane) {
-    static_assert(I8S_AHEAD == 3 && SR == 32, "three register sets, 32 rows per thread");
-    EntryRegs r0, r1, r2;
-    // the prologue's chunks, loaded together (past the last chunk: the last again, into
-    // stages no chunk uses)
-    static_assert(NST8 - 2 == 3, "the prologue's chunks take the three register sets");
-    entries_load(r0, tl, 0, nchunk, g, lane);
-    entries_load(r1, tl, 1, nchunk, g, lane);
-    entries_load(r2, tl, 2, nchunk, g, lane);
-    entries_place(r0, lds, g, lane);
-    entries_place(r1, lds + STG8, g, lane);
-    entries_place(r2, lds + 2 * STG8, g, lane);
-    // r0, r1, r2 take chunks NST8 - 2 + 3j, + 1 + 3j, + 2 + 3j in turn
-    entries_load(r0, tl, NST8 - 2, nchunk, g, lane);
-    entries_load(r1, tl, NST8 - 1, nchunk, g, lane);
-    entries_load(r2, tl, NST8, nchunk, g, lane);
-    if (nchunk > 0) sparse_chunk(r0, tl, 0, nchunk, lds, g, lane);
-    xm_load<0, 11>(st, tl, t);
-    if (nchunk > 1) sparse_chunk(r1, tl, 1, nchunk, lds, g, lane);
-    xm_load<11, 22>(st, tl, t);
-    if (nchunk > 2) sparse_chunk(r2, tl, 2, nchunk, lds, g, lane);
-    xm_load<22, 32>(st, tl, t);
-    st.bi = ((const g_f32 *)tl.b)[tl.I0 + (t & (BN - 1))];
-    int c = 3;
-    for (; c + 3 <= nchunk; c += 3) {
-        sparse_chunk(r0, tl, c, nchunk, lds, g, lane);
-        sparse_chunk(r1, tl, c + 1, nchunk, lds, g, lane);
-        sparse_chunk(r2, tl, c + 2, nchunk, lds, g, lane);
-    }
-    if (c < nchunk) sparse_chunk(r0, tl, c, nchunk, lds, g, lane);
-    if (c + 1 < nchunk) sparse_chunk(r1, tl, c + 1, nchunk, lds, g, lane);
-}
-
 // Waits for the loads of state_load, once, so that later stores wait for nothing.
 __device__ __forceinline__ void state_collect(StateRegs &st) {
 #pragma unroll
@@ -552,41 +311,13 @@ __device__ __forceinline__ void state_collect(StateRegs &st) {
 // the loop lanes 0..15 turn them into 16-byte stores (the even (ln = 0) or odd (ln = 1)
 // bytes of their row).  With h_last the fields are stored by a second pass.  Executes no
 // barrier.
-template <bool I8>
 __device__ __forceinline__ void state_update(StateRegs &st, const Tile &tl, const float *hs,
                                              uint32_t *__restrict__ s_nxt,
                                              float *__restrict__ h_last, int t, int wave,
                                              int lane, float lt, float eta, float alpha) {
     const int col = t & (BN - 1);
     const int rsub = __builtin_amdgcn_readfirstlane(t >> 7);
-    if (I8) {
-        // spins as bytes: row r of chunk I0/128 at (chunk * Rp + r) * 128 + col
-        uint8_t *srow = reinterpret_cast<uint8_t *>(s_nxt) +
-                        ((tl.I0 / KC) * tl.Rp + tl.R0 + rsub) * KC + col;
-        // field = sum of the two k halves' int32 partials (exact), unscaled
-        const int32_t *h0 = reinterpret_cast<const int32_t *>(hs), *h1 = h0 + BM * HS;
-#pragma unroll
-        for (int g = 0; g < SR / 8; ++g) {
-            // padding rows (uniform per wave) are not read, not updated and their spins are
-            // not written: no live row reads them
-            if (tl.R0 + 4 * (8 * g) + rsub >= tl.rlive) continue;
-            int32_t hv[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int k = (4 * (8 * g + u) + rsub) * HS + col;
-                hv[u] = h0[k] + h1[k];
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int e = 8 * g + u;
-                if (tl.R0 + 4 * e + rsub < tl.rlive) {
-                    const float h = __fadd_rn((float)hv[u], st.bi);
-                    pa_update(h, lt, eta, alpha, st.xv[e], st.mv[e]);
-                    srow[(int64_t)4 * e * KC] = st.xv[e] < 0.0f ? (uint8_t)0xFF : (uint8_t)0x01;
-                }
-            }
-        }
-    } else {
+    {
     const int u_mine = (lane >> 1) & 7;
     uint64_t mine[SR / 8];
 #pragma unroll
@@ -626,7 +357,7 @@ __device__ __forceinline__ void state_update(StateRegs &st, const Tile &tl, cons
         }
     }
     }
-    if (!I8 && h_last) {           // (the grouped int8 tiles store no last field)
+    if (h_last) {
         float *hr = h_last + (tl.R0 + rsub) * tl.np + tl.I0;
 #pragma unroll
         for (int e = 0; e < SR; ++e) {
@@ -664,42 +395,29 @@ __device__ __forceinline__ void state_store(const StateRegs &st, const Tile &tl,
     }
 }
 
-// One PA step of one tile: matrix and state waves side by side.
-template <int KIND, bool NT>
+// One PA step of one BF16 tile: matrix and state waves side by side.
+template <bool NT>
 __device__ __forceinline__ void mfma_tile_step(uint8_t *lds, const Tile &tl,
                                                const uint32_t *__restrict__ s_cur,
                                                uint32_t *__restrict__ s_nxt,
                                                float *__restrict__ h_last, float lt, float eta,
                                                float alpha) {
-    constexpr bool I8 = KIND != GK_BF16;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nchunk = (int)(tl.np / KC);
     if (wave >= MW) {
         const int t = tid - MW * 64;
         StateRegs st;
-        if (KIND == GK_I8_SPARSE) {
-            state_load_sparse(st, tl, nchunk, t, lds, wave - MW, lane);
-            lds_barrier();                             // stages drained (and written)
-        } else {
-            state_load(st, tl, nchunk, t);
-            barrier();                                 // stages drained
-        }
+        state_load(st, tl, nchunk, t);
+        barrier();                                     // stages drained
         barrier();                                     // partial sums stored
         state_collect(st);
-        state_update<I8>(st, tl, reinterpret_cast<const float *>(lds), s_nxt, h_last, t,
-                            wave, lane, lt, eta, alpha);
+        state_update(st, tl, reinterpret_cast<const float *>(lds), s_nxt, h_last, t, wave, lane,
+                     lt, eta, alpha);
         state_store<NT>(st, tl, t);
         return;
     }
-    if (KIND == GK_I8_SPARSE)
-        matrix_step_i8<true>(lds, tl, nchunk, reinterpret_cast<const uint8_t *>(s_cur), wave,
-                             lane);
-    else if (KIND == GK_I8)
-        matrix_step_i8<false>(lds, tl, nchunk, reinterpret_cast<const uint8_t *>(s_cur), wave,
-                              lane);
-    else
-        matrix_step(lds, tl, nchunk, s_cur, wave, lane);
+    matrix_step(lds, tl, nchunk, s_cur, wave, lane);
 }
 
 __global__ void __launch_bounds__(THREADS, 1) k_mfma_step(
@@ -711,14 +429,11 @@ __global__ void __launch_bounds__(THREADS, 1) k_mfma_step(
     __shared__ __attribute__((aligned(16))) uint8_t lds[LDS_BYTES];
     const Tile tl{np, Rp, (int64_t)blockIdx.x * BN, (int64_t)blockIdx.y * BM, rlive, Jb, b,
                   sc->scale, x, m};
-    mfma_tile_step<GK_BF16, true>(lds, tl, s_cur, s_nxt, h_last, lam[t], eta, alpha);
+    mfma_tile_step<true>(lds, tl, s_cur, s_nxt, h_last, lam[t], eta, alpha);
 }
 
 // Many instances in one launch: block k runs tile k of the table.  Each tile points at
 // its instance's couplings, bias, state and the two spin buffers (picked by step parity).
-// KIND: GK_BF16, or int8 couplings and byte spins (unscaled sums) read as dense rows
-// (GK_I8) or as entry lists (GK_I8_SPARSE).
-template <int KIND>
 __global__ void __launch_bounds__(THREADS, 1) k_mfma_grouped(const MfmaTile *__restrict__ tiles,
                                                              int t, const float *__restrict__ lam,
                                                              float eta, float alpha) {
@@ -727,9 +442,335 @@ __global__ void __launch_bounds__(THREADS, 1) k_mfma_grouped(const MfmaTile *__r
     if (mt.np == 0) return;      // filler entry of the compute-die-ordered table
     const uint32_t *cur = (t & 1) ? mt.s1 : mt.s0;
     uint32_t *nxt = (t & 1) ? mt.s0 : mt.s1;
-    const Tile tl{mt.np, mt.Rp, mt.I0, mt.R0, mt.rlive, mt.Jb, mt.b,
-                  KIND != GK_BF16 ? 1.0f : mt.sc->scale, mt.x, mt.m, mt.E, mt.O};
-    mfma_tile_step<KIND, false>(lds, tl, cur, nxt, nullptr, lam[t], eta, alpha);
+    const Tile tl{mt.np, mt.Rp, mt.I0, mt.R0, mt.rlive, mt.Jb, mt.b, mt.sc->scale, mt.x, mt.m};
+    mfma_tile_step<false>(lds, tl, cur, nxt, nullptr, lam[t], eta, alpha);
+}
+
+// ---- int8 tiles of a batch: 64 replicas x 256 variables ---------------------------------
+// For integer couplings with |J| <= 127 a workgroup owns 64 replicas (R0 .. R0 + 63) and
+// 256 variables (I0 .. I0 + 255) of an instance; every tile row is a replica (with 64
+// replicas per instance, as in the batch workload, no row is padding), and one tile does
+// the work of two 128 x 128 tiles with one set of fixed costs.  Per chunk of 128 reduction
+// variables a stage holds the 256 x 128 int8 block of J (rows of 128 bytes, the 16-byte
+// piece p of row r at position p ^ (r % 8)) and the 64 x 128 byte spins of the tile's
+// replicas (same layout); NST8 = 4 stages.
+//   * matrix waves: wave w takes columns 64 (w % 4) .. + 63 and k steps 2 (w / 4),
+//     2 (w / 4) + 1 of every chunk (32 each), 2 x 2 accumulators of 32 x 32
+//     (v_mfma_i32_32x32x32_i8); they load the spins of every stage (one 1 KiB direct
+//     load each: rows 8w .. 8w + 7) and, for dense rows, the couplings (four: rows
+//     32w .. 32w + 31);
+//   * state waves: thread t owns column t % 256 of rows 2e + t / 256 (32 rows); for
+//     entry-list tiles, state wave g also writes the couplings of row groups 2g and 2g + 1
+//     (16 rows each) of every stage: it clears their 2 KiB and stores each entry's weight
+//     byte at its position (entries of chunk c placed after the barrier of chunk c - 2
+//     into the stage of chunk c - 4, loaded three chunks ahead into three register sets
+//     used in turn; lanes past a block's end repeat its last entry, the same byte with the
+//     same value, so that no load or store sits behind a per-lane branch and each wait
+//     for a register set covers that set only).
+// After the reduction the two k halves' exact int32 partial sums go through two LDS
+// buffers (rows padded to 264 words), added by the state waves, which then run the PA
+// update and store x, m and the byte spins of their live rows (rows at or past rlive,
+// uniform per wave, are skipped).  Barriers per tile: nchunk + 2 in both roles.
+
+// The table's pointers are generic; these views make the offsets scalar loads (uniform,
+// read-only during the launch) and the entries global loads, which count on the
+// vector-memory counter only (generic loads also count on the counter that the LDS
+// barriers wait for).
+typedef __attribute__((address_space(4))) const int32_t c_i32;
+typedef __attribute__((address_space(1))) const uint32_t g_u32;
+typedef __attribute__((address_space(1))) const float g_f32;
+typedef __attribute__((address_space(1))) float g_f32w;
+typedef __attribute__((address_space(1))) uint8_t g_u8w;
+
+// The LDS stores of this wave are complete, then the workgroup barrier.
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+template <bool SPARSE>
+__device__ __forceinline__ void matrix_tile8(uint8_t *lds, const Tile &tl, int nchunk,
+                                             const uint8_t *__restrict__ s_cur, int wave,
+                                             int lane) {
+    const int64_t np = tl.np;
+    const int kh = wave >> 2, wc = wave & 3;
+    const int half = lane >> 5, l32 = lane & 31;
+    // wave-uniform bases plus 32-bit lane offsets (fewer registers than 64-bit pointers):
+    // load u of the couplings fills rows 32w + 8u + lane / 8, that of the spins rows
+    // 8w + lane / 8, each at position lane % 8 (piece (lane % 8) ^ (row % 8))
+    const uint8_t *Jw = reinterpret_cast<const uint8_t *>(tl.Jb) + (tl.I0 + 32 * wave) * np;
+    const uint8_t *Sw = s_cur + (tl.R0 + 8 * wave) * KC;
+    const int r8 = lane >> 3;
+    const uint32_t piece = (uint32_t)((lane & 7) ^ r8);
+    uint32_t oJ[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) oJ[u] = (uint32_t)(8 * u + r8) * (uint32_t)np + 16u * piece;
+    const uint32_t oS = (uint32_t)r8 * (uint32_t)KC + 16u * piece;
+    const int64_t sstride = tl.Rp * KC;            // bytes between consecutive spin chunks
+    auto stage = [&](int kc, int st) {
+        kc = kc < nchunk ? kc : nchunk - 1;        // past the end: reload the last chunk
+        uint8_t *dst = lds + st * STG8;
+        if (!SPARSE) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                __builtin_amdgcn_global_load_lds(Jw + (int64_t)kc * KC + oJ[u],
+                                                 (lds_void *)(dst + (4 * wave + u) * 1024), 16, 0,
+                                                 0);
+        }
+        __builtin_amdgcn_global_load_lds(Sw + (int64_t)kc * sstride + oS,
+                                         (lds_void *)(dst + JSTG8 + wave * 1024), 16, 0, 0);
+    };
+    constexpr int LOADS = SPARSE ? 1 : 5;          // per chunk and wave
+    i32x16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[i][j][v] = 0;
+#pragma unroll
+    for (int s = 0; s < NST8 - 1; ++s) stage(s, s);
+    for (int c = 0; c < nchunk; ++c) {
+        // this wave's loads of chunk c have landed (NST8 - 2 younger chunks may not)
+        wait_barrier<(NST8 - 2) * LOADS>();
+        stage(c + NST8 - 1, (c + NST8 - 1) % NST8);
+        const uint8_t *src = lds + (c % NST8) * STG8;
+#pragma unroll
+        for (int qq = 0; qq < 2; ++qq) {
+            const int pc = 2 * (2 * kh + qq) + half;
+            i32x4 a[2], bq[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int row = 32 * i + l32;
+                a[i] = *reinterpret_cast<const i32x4 *>(src + JSTG8 + row * KC +
+                                                        16 * (pc ^ (row & 7)));
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int row = 64 * wc + 32 * j + l32;
+                bq[j] = *reinterpret_cast<const i32x4 *>(src + row * KC + 16 * (pc ^ (row & 7)));
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[i], bq[j], acc[i][j], 0,
+                                                                      0, 0);
+        }
+    }
+    wait_barrier<0>();     // every load has landed and every stage read is done
+    // the two k halves' exact int32 partial sums, one buffer each
+    int32_t *hp = reinterpret_cast<int32_t *>(lds) + kh * (BM8 * HS8);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int row = 32 * i + 8 * (v >> 2) + 4 * half + (v & 3);
+                const int col = 64 * wc + 32 * j + l32;
+                hp[row * HS8 + col] = acc[i][j][v];
+            }
+    wait_barrier<0>();     // partial sums stored
+}
+
+// Entries of one 16 x 128 block (I8S_EPL per lane).
+struct EntryRegs {
+    uint32_t e[I8S_EPL];
+    int32_t cnt;
+};
+
+// Row group gg (0..15) of the tile, chunk kc (past the last chunk: the last again).  The
+// block belongs to the 128-row tile I0 / 128 + gg / 8 of the entry-list layout.
+__device__ __forceinline__ void entries_load(EntryRegs &er, const Tile &tl, int kc, int nchunk,
+                                             int gg, int lane) {
+    kc = kc < nchunk ? kc : nchunk - 1;
+    const int64_t blk = ((tl.I0 / KC + (gg >> 3)) * (tl.np / KC) + kc) * 8 + (gg & 7);
+    const c_i32 *O = (const c_i32 *)tl.O;
+    const int32_t beg = O[blk];
+    er.cnt = O[blk + 1] - beg;
+    // an empty block reads the word at its start, which lies inside the coupling buffer
+    // (the entries end at least a quarter of the buffer before its end); it is not placed
+    const g_u32 *src = (const g_u32 *)tl.E + beg;
+    const int32_t last = max(er.cnt - 1, 0);
+#pragma unroll
+    for (int j = 0; j < I8S_EPL; ++j) er.e[j] = src[min(lane + 64 * j, last)];
+}
+
+// Clears row group gg's 2 KiB of the stage and writes its entries there.  An entry's
+// position within its 16 rows is its low 11 bits (the rows of its block); the words an
+// empty block loaded write zeros into cleared bytes of the same rows.
+__device__ __forceinline__ void entries_place(const EntryRegs &er, uint8_t *stage, int gg,
+                                              int lane) {
+    uint8_t *rg = stage + 2048 * gg;
+    *reinterpret_cast<u32x4 *>(rg + 16 * lane) = (u32x4){0u, 0u, 0u, 0u};
+    *reinterpret_cast<u32x4 *>(rg + 1024 + 16 * lane) = (u32x4){0u, 0u, 0u, 0u};
+    const uint32_t keep = er.cnt > 0 ? 0xFFFFFFFFu : 0u;
+#pragma unroll
+    for (int j = 0; j < I8S_EPL; ++j)
+        rg[er.e[j] & 0x7FFu] = (uint8_t)((er.e[j] & keep) >> 16);
+}
+
+// The two row groups (2g, 2g + 1) of a state wave.
+struct EntryPair {
+    EntryRegs a, b;
+};
+
+__device__ __forceinline__ void pair_load(EntryPair &p, const Tile &tl, int kc, int nchunk,
+                                          int g, int lane) {
+    entries_load(p.a, tl, kc, nchunk, 2 * g, lane);
+    entries_load(p.b, tl, kc, nchunk, 2 * g + 1, lane);
+}
+
+__device__ __forceinline__ void pair_place(const EntryPair &p, uint8_t *stage, int g, int lane) {
+    entries_place(p.a, stage, 2 * g, lane);
+    entries_place(p.b, stage, 2 * g + 1, lane);
+}
+
+struct StateRegs8 {
+    float xv[SR8], mv[SR8];
+    float bi;
+};
+
+// x, m of rows 2e + t / 256, E0 <= e < E1, of this thread (rows at or past rlive are not
+// read).
+template <int E0, int E1>
+__device__ __forceinline__ void xm_load8(StateRegs8 &st, const Tile &tl, int t) {
+    const int col = t & (BN8 - 1);
+    const int rsub = __builtin_amdgcn_readfirstlane(t >> 8);
+    const g_f32 *xr = (const g_f32 *)tl.x + (tl.R0 + 2 * E0 + rsub) * tl.np + tl.I0;
+    const g_f32 *mr = (const g_f32 *)tl.m + (tl.R0 + 2 * E0 + rsub) * tl.np + tl.I0;
+#pragma unroll
+    for (int e = E0; e < E1; ++e) {
+        const bool live = tl.R0 + 2 * e + rsub < tl.rlive;
+        st.xv[e] = live ? xr[col] : 0.0f;
+        st.mv[e] = live ? mr[col] : 0.0f;
+        xr = next_rows(xr, 2 * tl.np);
+        mr = next_rows(mr, 2 * tl.np);
+    }
+}
+
+// One chunk barrier of a placing state wave: then the entries held in p (chunk c + 2) go
+// into the stage of chunk c - 2 (free since the barrier of chunk c - 1) and p is reloaded
+// with the chunk three further on.  Past the last chunk the reloaded last chunk is placed
+// again, into a stage that no later chunk of the loop uses (they take those of c + 1 at
+// most); the barrier after the loop waits for these stores.  No branch, so that the waits
+// for one register set cover that set only.
+__device__ __forceinline__ void place_step(EntryPair &p, const Tile &tl, int c, int nchunk,
+                                           uint8_t *lds, int g, int lane) {
+    lds_barrier();
+    const int kc = c + NST8 - 2;
+    pair_place(p, lds + (kc % NST8) * STG8, g, lane);
+    pair_load(p, tl, kc + 3, nchunk, g, lane);
+}
+
+// State waves of an int8 tile, up to the partial sums: x, m and b loaded, and for
+// entry-list tiles the couplings of every chunk placed.  Executes nchunk barriers.
+template <bool SPARSE>
+__device__ __forceinline__ void state_load8(StateRegs8 &st, const Tile &tl, int nchunk, int t,
+                                            uint8_t *lds, int g, int lane) {
+    static_assert(SR8 == 32 && NST8 == 4, "the load pattern below");
+    const int col = t & (BN8 - 1);
+    if (!SPARSE) {
+        xm_load8<0, SR8>(st, tl, t);
+        st.bi = ((const g_f32 *)tl.b)[tl.I0 + col];
+        for (int c = 0; c < nchunk; ++c) barrier();
+        return;
+    }
+    // the prologue's two chunks (past the last chunk: the last again, into stages no chunk
+    // uses), then the next three chunks' entries; x and m follow in three groups after the
+    // first three chunks' entry loads, since loads complete in issue order and a wait for
+    // entries would otherwise wait for them
+    EntryPair p0, p1, p2;
+    pair_load(p0, tl, 0, nchunk, g, lane);
+    pair_load(p1, tl, 1, nchunk, g, lane);
+    pair_place(p0, lds, g, lane);
+    pair_place(p1, lds + STG8, g, lane);
+    pair_load(p0, tl, 2, nchunk, g, lane);
+    pair_load(p1, tl, 3, nchunk, g, lane);
+    pair_load(p2, tl, 4, nchunk, g, lane);
+    if (nchunk > 0) place_step(p0, tl, 0, nchunk, lds, g, lane);
+    xm_load8<0, 11>(st, tl, t);
+    if (nchunk > 1) place_step(p1, tl, 1, nchunk, lds, g, lane);
+    xm_load8<11, 22>(st, tl, t);
+    if (nchunk > 2) place_step(p2, tl, 2, nchunk, lds, g, lane);
+    xm_load8<22, 32>(st, tl, t);
+    st.bi = ((const g_f32 *)tl.b)[tl.I0 + col];
+    int c = 3;
+    for (; c + 3 <= nchunk; c += 3) {
+        place_step(p0, tl, c, nchunk, lds, g, lane);
+        place_step(p1, tl, c + 1, nchunk, lds, g, lane);
+        place_step(p2, tl, c + 2, nchunk, lds, g, lane);
+    }
+    if (c < nchunk) place_step(p0, tl, c, nchunk, lds, g, lane);
+    if (c + 1 < nchunk) place_step(p1, tl, c + 1, nchunk, lds, g, lane);
+}
+
+// One PA step of one int8 tile.
+template <bool SPARSE>
+__device__ __forceinline__ void tile8_step(uint8_t *lds, const Tile &tl,
+                                           const uint8_t *__restrict__ s_cur,
+                                           uint8_t *__restrict__ s_nxt, float lt, float eta,
+                                           float alpha) {
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nchunk = (int)(tl.np / KC);
+    if (wave < MW) {
+        matrix_tile8<SPARSE>(lds, tl, nchunk, s_cur, wave, lane);
+        return;
+    }
+    const int t = tid - MW * 64;
+    const int col = t & (BN8 - 1);
+    const int rsub = __builtin_amdgcn_readfirstlane(t >> 8);
+    StateRegs8 st;
+    state_load8<SPARSE>(st, tl, nchunk, t, lds, wave - MW, lane);
+    lds_barrier();                                     // stages drained (and written)
+    barrier();                                         // partial sums stored
+#pragma unroll
+    for (int e = 0; e < SR8; ++e) asm volatile("" ::"v"(st.xv[e]), "v"(st.mv[e]));
+    asm volatile("" ::"v"(st.bi));
+    // field = sum of the two k halves' int32 partials (exact), unscaled; rows at or past
+    // rlive (uniform per wave) are not read, not updated and their spins not written
+    const int32_t *h0 = reinterpret_cast<const int32_t *>(lds), *h1 = h0 + BM8 * HS8;
+    // spins as bytes: row r of chunk (I0 + col) / 128 at (chunk * Rp + r) * 128 + col % 128
+    g_u8w *srow = (g_u8w *)s_nxt + (((tl.I0 + col) / KC) * tl.Rp + tl.R0 + rsub) * KC +
+                  (col & (KC - 1));
+    g_f32w *xr = (g_f32w *)tl.x + (tl.R0 + rsub) * tl.np + tl.I0 + col;
+    g_f32w *mr = (g_f32w *)tl.m + (tl.R0 + rsub) * tl.np + tl.I0 + col;
+#pragma unroll
+    for (int g = 0; g < SR8 / 8; ++g) {
+        if (tl.R0 + 2 * (8 * g) + rsub >= tl.rlive) continue;
+        int32_t hv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = (2 * (8 * g + u) + rsub) * HS8 + col;
+            hv[u] = h0[k] + h1[k];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = 8 * g + u;
+            if (tl.R0 + 2 * e + rsub < tl.rlive) {
+                const float h = __fadd_rn((float)hv[u], st.bi);
+                pa_update(h, lt, eta, alpha, st.xv[e], st.mv[e]);
+                srow[(int64_t)2 * e * KC] = st.xv[e] < 0.0f ? (uint8_t)0xFF : (uint8_t)0x01;
+                xr[(int64_t)2 * e * tl.np] = st.xv[e];
+                mr[(int64_t)2 * e * tl.np] = st.mv[e];
+            }
+        }
+    }
+}
+
+template <bool SPARSE>
+__global__ void __launch_bounds__(THREADS, 1) k_mfma_grouped8(const MfmaTile *__restrict__ tiles,
+                                                              int t, const float *__restrict__ lam,
+                                                              float eta, float alpha) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds[LDS_BYTES];
+    const MfmaTile mt = tiles[blockIdx.x];
+    if (mt.np == 0) return;      // filler entry of the compute-die-ordered table
+    const uint8_t *cur = reinterpret_cast<const uint8_t *>((t & 1) ? mt.s1 : mt.s0);
+    uint8_t *nxt = reinterpret_cast<uint8_t *>((t & 1) ? mt.s0 : mt.s1);
+    const Tile tl{mt.np, mt.Rp, mt.I0, mt.R0, mt.rlive, mt.Jb, mt.b, 1.0f, mt.x, mt.m,
+                  mt.E, mt.O};
+    tile8_step<SPARSE>(lds, tl, cur, nxt, lam[t], eta, alpha);
 }
 
 // Byte spins of the signs of x (chunk-major, 128 bytes per replica and chunk).
@@ -926,12 +967,11 @@ hipError_t launch_mfma_grouped(const MfmaTile *tiles, int32_t ntiles, int32_t t,
                                hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
     if (kind == GK_I8_SPARSE)
-        k_mfma_grouped<GK_I8_SPARSE><<<(unsigned)ntiles, THREADS, 0, st>>>(tiles, t, lam, eta,
-                                                                          alpha);
+        k_mfma_grouped8<true><<<(unsigned)ntiles, THREADS, 0, st>>>(tiles, t, lam, eta, alpha);
     else if (kind == GK_I8)
-        k_mfma_grouped<GK_I8><<<(unsigned)ntiles, THREADS, 0, st>>>(tiles, t, lam, eta, alpha);
+        k_mfma_grouped8<false><<<(unsigned)ntiles, THREADS, 0, st>>>(tiles, t, lam, eta, alpha);
     else
-        k_mfma_grouped<GK_BF16><<<(unsigned)ntiles, THREADS, 0, st>>>(tiles, t, lam, eta, alpha);
+        k_mfma_grouped<<<(unsigned)ntiles, THREADS, 0, st>>>(tiles, t, lam, eta, alpha);
     return hipGetLastError();
 }
 

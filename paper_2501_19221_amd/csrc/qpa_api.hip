@@ -908,7 +908,8 @@ qpa_status make_batch_plan(qpa_ctx *ctx, int32_t count, const qpa_problem *probs
         // device) or BF16 requested, and cheaper by the cost model
         DenseSlot ds;
         const bool exact_ok = pl.is_int || a.precision == QPA_PREC_BF16;
-        const int64_t np = round_up(probs[k].n, MF_NPAD), Rp = round_up(a.replicas, MF_BM);
+        // np a multiple of the int8 tiles' 256 variables (BF16 tiles take 128)
+        const int64_t np = round_up(probs[k].n, MF_BN8), Rp = round_up(a.replicas, MF_BM);
         const bool cheaper =
             dense_step_cost(ctx, np, a.replicas, likely_sparse_i8(probs[k], np) ? probs[k].nnz : -1) <
             csr_step_cost(ctx, probs[k].nnz, a.replicas);
@@ -1809,9 +1810,13 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
             if (e != hipSuccess) return e;
         }
         std::vector<MfmaTile> &tv = itiles[k];
-        tv.reserve((size_t)(ds.Rp / MF_BM) * (size_t)(ds.np / MF_BN));
-        for (int64_t rb = 0; rb < ds.Rp / MF_BM; ++rb)
-            for (int64_t ib = 0; ib < ds.np / MF_BN; ++ib) {
+        // BF16: tiles of 128 replicas x 128 variables over the padded replicas; int8: 64 x
+        // 256 over the replicas up to R (a tile past them would hold padding only)
+        const int64_t bm = i8 ? MF_BM8 : MF_BM, bn = i8 ? MF_BN8 : MF_BN;
+        const int64_t nrb = i8 ? (R + MF_BM8 - 1) / MF_BM8 : ds.Rp / MF_BM;
+        tv.reserve((size_t)nrb * (size_t)(ds.np / bn));
+        for (int64_t rb = 0; rb < nrb; ++rb)
+            for (int64_t ib = 0; ib < ds.np / bn; ++ib) {
                 MfmaTile tl{};
                 tl.Jb = Jb;
                 tl.b = bfp;
@@ -1822,8 +1827,8 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
                 tl.m = dm;
                 tl.np = ds.np;
                 tl.Rp = ds.Rp;
-                tl.I0 = ib * MF_BN;
-                tl.R0 = rb * MF_BM;
+                tl.I0 = ib * bn;
+                tl.R0 = rb * bm;
                 tl.rlive = R;
                 tv.push_back(tl);
             }
@@ -2629,9 +2634,9 @@ qpa_status qpa_autotune_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *pr
         for (int32_t k = 0; k < count && s == QPA_OK; ++k) {
             const int32_t pk = ctx->batch_paths[k];
             if (f == 0 && (pk == QPA_PATH_BATCH_DENSE || pk == QPA_PATH_BATCH_DENSE_I8))
-                work += dense_step_work(round_up(problems[k].n, MF_NPAD), R);
+                work += dense_step_work(round_up(problems[k].n, MF_BN8), R);
             if (f == 0 && pk == QPA_PATH_BATCH_SPARSE_I8)
-                work += dense_step_work(round_up(problems[k].n, MF_NPAD), R, problems[k].nnz);
+                work += dense_step_work(round_up(problems[k].n, MF_BN8), R, problems[k].nnz);
             if (f == 1 && pk == QPA_PATH_BATCH_SPARSE)
                 work += csr_step_work(problems[k].nnz, R);
         }

@@ -177,6 +177,8 @@ hipError_t launch_sign_f32(int64_t count, const float *x, float *s, hipStream_t 
 constexpr int MF_BM = 128;   // replicas per tile
 constexpr int MF_BN = 128;   // variables per tile
 constexpr int MF_NPAD = 128; // np is a multiple of this (the reduction chunk)
+// Tiles of the grouped int8 step: 64 replicas x 256 variables (np a multiple of 256).
+constexpr int MF_BM8 = 64, MF_BN8 = 256;
 hipError_t launch_mfma_pack_spins(int64_t Rp, int64_t np, const float *x, uint32_t *sbits,
                                   hipStream_t st);
 hipError_t launch_mfma_step(int64_t Rp, int64_t np, int64_t rlive, const uint16_t *Jb,
