@@ -18,10 +18,10 @@
 // State: every vector is [rows][Rp] FP32 (replica fastest); instance k of a batch owns the
 // global rows [row0_k, row0_k + n_k).  Replicas r >= R are padding: held at zero and left
 // out of every sum.
-// Products with J: CSR couplings through a gather (a wave = one row and 64 replicas, lane
-// = replica, the row's entries fetched 64 at a time and walked in order, loads of four
-// entries issued together); dense FP32 couplings through the LDS-tiled product shared with
-// the SBM step, with the element work in its epilogue.  Both add one fused multiply-add
+// Products with J: CSR couplings through row launches over blocks of 64 rows, the input
+// vector staged through LDS (a wave = four rows and 64 replicas, lane = replica, each
+// row's entries walked in order); dense FP32 couplings through the LDS-tiled product
+// shared with the SBM step, with the element work in its epilogue.  Both add one fused multiply-add
 // per term in ascending column order.
 // Inner products are accumulated in FP64 per thread, reduced per workgroup in a fixed
 // order and written to a per-step table of partial sums, which one last launch reduces in
@@ -148,79 +148,211 @@ __device__ __forceinline__ void rel_write_partials(const RelArgs &a, int64_t wg,
 
 template <typename T> __device__ __forceinline__ float as_weight(T w) { return (float)w; }
 
-// Batched CSR launch (and, with MODE = REL_A, the element-wise pass over the rows of every
-// instance).  Work item q = (row, 64-replica chunk); waves stride over the items in a
-// fixed order.  The instance of a row is found by binary search over item0.
+// Row launches: the CSR product with its input staged through LDS (the gather modes), and
+// the element-wise pass (REL_A) over every instance's rows with the same work items, so
+// that a step's partial sums are grouped alike whichever launch computes them.  Work item
+// = (block of 64 consecutive rows of one instance, 64-replica chunk c); a workgroup of 16
+// waves takes items b, b + G, ... in order.  Wave w owns rows 4w .. 4w + 3 of the block
+// (lane = replica) and keeps their running sums; the input vector (x or mu of the
+// instance, the chunk's 64 replicas) goes through LDS 256 columns at a time (64 KiB, two
+// buffers: the next columns load while these are used), and each row walks its entries
+// whose column falls in the staged range, in ascending order, one fused multiply-add per
+// term (the order of the definition), while each staged value serves all 64 rows of the
+// block instead of one gather per entry.  A row's entries come in windows of 64 (lane k =
+// entry k past the row's cursor).  At the start of a range the number of each row's
+// entries in it is counted from the window at hand; the windows past them (all four rows)
+// are loaded into a second register set before any row is walked, so that they are in
+// flight during the walks, and they are converted only when the next range counts them.
+// The loads are issued without per-lane branches and are younger than the staging loads
+// of the next range, so that the barrier before it waits for the staging only.
+typedef __attribute__((address_space(3))) void lds_void;
+constexpr int GR_THREADS = 1024, GR_WAVES = GR_THREADS / 64, GR_RPW = 4;
+constexpr int GR_ROWS = GR_WAVES * GR_RPW;       // 64 rows per block
+constexpr int GR_CW = 256;                       // staged columns
+static_assert(GR_ROWS == 64, "blocks of 64 rows");
+
+typedef const __attribute__((address_space(1))) int32_t *gr_i32;
+
+// A row's window as loaded (raw column and weight of entry cursor + lane; lanes past the
+// row's end hold some stored entry of the instance); converted when it is used, so that
+// its loads stay in flight until then.
+template <typename TW, typename TI> struct GrWin {
+    TI j[GR_RPW];
+    TW w[GR_RPW];
+};
+
 template <int MODE, typename TW, typename TI>
-__global__ void __launch_bounds__(256) k_rel_rows(const RelInst *__restrict__ insts,
-                                                  int32_t ninst, int64_t items, int32_t C,
-                                                  const RelArgs a) {
-    __shared__ double sh[4];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+__global__ void __launch_bounds__(GR_THREADS) k_rel_gather(const RelInst *__restrict__ insts,
+                                                           int32_t ninst, int64_t blocks,
+                                                           int32_t C, const RelArgs a) {
     constexpr bool GATHER = MODE != REL_A;
+    typedef const __attribute__((address_space(1))) TW *gw_t;
+    typedef const __attribute__((address_space(1))) TI *gi_t;
+    __shared__ __attribute__((aligned(16))) float vs[GATHER ? 2 : 1][GATHER ? GR_CW * 64 : 1];
+    __shared__ double sh[GR_WAVES];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    const int64_t total = items * C;
-    for (int64_t q = (int64_t)blockIdx.x * 4 + wv; q < total; q += (int64_t)gridDim.x * 4) {
-        const int64_t item = q / C;
-        const int c = (int)(q - item * C);
+    const int64_t total = blocks * C;
+    for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+        const int64_t blk = it / C;
+        const int c = (int)(it - blk * C);
         int lo = 0, hi = ninst - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (insts[mid].item0 <= item) lo = mid;
+            if (insts[mid].blk0 <= blk) lo = mid;
             else hi = mid - 1;
         }
+        // the instance's fields, read once (a staging load may write memory as far as the
+        // compiler knows, which would otherwise make it read them again)
         const RelInst &I = insts[lo];
-        const int64_t i = item - I.item0;
-        const int64_t r = (int64_t)c * 64 + lane;
-        const int64_t idx = (I.row0 + i) * a.Rp + r;
-        const bool live = r < a.R;
-        float acc = 0.0f;
+        const int64_t n = I.n;
+        const int64_t i0 = (blk - I.blk0) * GR_ROWS + GR_RPW * wv;
+        float acc[GR_RPW];
+#pragma unroll
+        for (int u = 0; u < GR_RPW; ++u) acc[u] = 0.0f;
         if (GATHER) {
-            const float *v = (MODE == REL_FWD || MODE == REL_LOSS) ? a.xi : a.mu_in;
-            const float *vb = v + I.row0 * a.Rp + r;
-            const TI *col = static_cast<const TI *>(I.col);
-            const TW *w = static_cast<const TW *>(I.w);
-            const int32_t k0 = I.rp[i], k1 = I.rp[i + 1];
-            for (int32_t kb = k0; kb < k1; kb += 64) {
-                int32_t jj = (int32_t)i;
-                float ww = 0.0f;
-                if (kb + lane < k1) {
-                    jj = (int32_t)col[kb + lane];
-                    ww = as_weight(w[kb + lane]);
-                    // a stored QUBO diagonal is folded into b: weight 0 adds exactly nothing
-                    if (I.skip_diag && jj == (int32_t)i) ww = 0.0f;
+            const gr_i32 rp = (gr_i32)I.rp;
+            const int32_t rp0 = rp[0];
+            // (an instance without stored entries has nothing to gather: uniform per item)
+            if (rp[n] > rp0) {
+                const float *v = ((MODE == REL_FWD || MODE == REL_LOSS) ? a.xi : a.mu_in) +
+                                 I.row0 * a.Rp + (int64_t)c * 64;
+                const gi_t col = (gi_t)I.col;
+                const gw_t w = (gw_t)I.w;
+                const bool skip = I.skip_diag != 0;
+                // staging of columns 256 q .. 256 q + 255 (past n: column n - 1 again,
+                // unused): thread t moves 4 x 16 bytes, element e = 1024 u + t = column
+                // e / 16, floats 4 (e % 16) .. + 3; a wave's destinations are contiguous
+                auto stage = [&](int q, int buf) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int e = 1024 * u + (int)threadIdx.x;
+                        int64_t j = (int64_t)q * GR_CW + (e >> 4);
+                        j = j < n ? j : n - 1;
+                        __builtin_amdgcn_global_load_lds(
+                            v + j * a.Rp + 4 * (e & 15),
+                            (lds_void *)(&vs[buf][0] + 4 * (1024 * u + 64 * wv)), 16, 0, 0);
+                    }
+                    // the window loads that follow stay younger than these
+                    asm volatile("" ::: "memory");
+                };
+                int32_t kc[GR_RPW], ke[GR_RPW];
+#pragma unroll
+                for (int u = 0; u < GR_RPW; ++u) {
+                    const int64_t i = i0 + u;
+                    kc[u] = i < n ? rp[i] : rp0;
+                    ke[u] = i < n ? rp[i + 1] : rp0;
                 }
-                const int cnt = min(64, k1 - kb);
-                int e = 0;
-                for (; e + 4 <= cnt; e += 4) {
-                    const int64_t j0 = __builtin_amdgcn_readlane(jj, e);
-                    const int64_t j1 = __builtin_amdgcn_readlane(jj, e + 1);
-                    const int64_t j2 = __builtin_amdgcn_readlane(jj, e + 2);
-                    const int64_t j3 = __builtin_amdgcn_readlane(jj, e + 3);
-                    const float v0 = vb[j0 * a.Rp], v1 = vb[j1 * a.Rp];
-                    const float v2 = vb[j2 * a.Rp], v3 = vb[j3 * a.Rp];
-                    const float w0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ww), e));
-                    const float w1 =
-                        __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ww), e + 1));
-                    const float w2 =
-                        __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ww), e + 2));
-                    const float w3 =
-                        __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ww), e + 3));
-                    acc = __fmaf_rn(w0, v0, acc);
-                    acc = __fmaf_rn(w1, v1, acc);
-                    acc = __fmaf_rn(w2, v2, acc);
-                    acc = __fmaf_rn(w3, v3, acc);
+                // row u's window from its cursor kc[u] (two loads, no branch)
+                auto load = [&](GrWin<TW, TI> &W, int u) {
+                    const int32_t kk = min(kc[u] + lane, max(ke[u] - 1, rp0));
+                    W.j[u] = col[kk];
+                    W.w[u] = w[kk];
+                };
+                // its entries as columns (past the row's end: one no range reaches) and
+                // weights (a stored QUBO diagonal is folded into b: weight 0 adds nothing)
+                auto cols = [&](const GrWin<TW, TI> &W, int u) {
+                    return kc[u] + lane < ke[u] ? (int32_t)W.j[u] : INT32_MAX;
+                };
+                auto weights = [&](const GrWin<TW, TI> &W, int u) {
+                    const float wf = as_weight(W.w[u]);
+                    return skip && (int64_t)W.j[u] == i0 + u ? 0.0f : wf;
+                };
+                auto walk = [&](int32_t jl, float wl, int u, int cnt, int32_t base,
+                                const float *src) {
+                    int e = 0;
+                    const int wi = __float_as_int(wl);
+                    for (; e + 4 <= cnt; e += 4) {
+                        const int32_t j0 = __builtin_amdgcn_readlane(jl, e) - base;
+                        const int32_t j1 = __builtin_amdgcn_readlane(jl, e + 1) - base;
+                        const int32_t j2 = __builtin_amdgcn_readlane(jl, e + 2) - base;
+                        const int32_t j3 = __builtin_amdgcn_readlane(jl, e + 3) - base;
+                        const float v0 = src[64 * j0], v1 = src[64 * j1];
+                        const float v2 = src[64 * j2], v3 = src[64 * j3];
+                        acc[u] = __fmaf_rn(__int_as_float(__builtin_amdgcn_readlane(wi, e)),
+                                           v0, acc[u]);
+                        acc[u] = __fmaf_rn(
+                            __int_as_float(__builtin_amdgcn_readlane(wi, e + 1)), v1, acc[u]);
+                        acc[u] = __fmaf_rn(
+                            __int_as_float(__builtin_amdgcn_readlane(wi, e + 2)), v2, acc[u]);
+                        acc[u] = __fmaf_rn(
+                            __int_as_float(__builtin_amdgcn_readlane(wi, e + 3)), v3, acc[u]);
+                    }
+                    for (; e < cnt; ++e) {
+                        const int32_t j = __builtin_amdgcn_readlane(jl, e) - base;
+                        acc[u] = __fmaf_rn(__int_as_float(__builtin_amdgcn_readlane(wi, e)),
+                                           src[64 * j], acc[u]);
+                    }
+                };
+                const int nq = (int)((n + GR_CW - 1) / GR_CW);
+                GrWin<TW, TI> A, B;
+#pragma unroll
+                for (int u = 0; u < GR_RPW; ++u) load(A, u);
+                stage(0, 0);
+                asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+                // range q: load Y (the windows past this range's entries of every row),
+                // then walk X (the windows at the cursors before)
+                auto range = [&](int q, GrWin<TW, TI> &X, GrWin<TW, TI> &Y) {
+                    // every wave's staging of q has landed (the 8 window loads since are
+                    // younger), and every wave is done with the buffer q + 1 takes
+                    if (q > 0)
+                        asm volatile("s_waitcnt vmcnt(8) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+                    const int32_t base = q * GR_CW, bound = base + GR_CW;
+                    int32_t jl[GR_RPW];
+                    float wl[GR_RPW];
+                    int cnt[GR_RPW];
+#pragma unroll
+                    for (int u = 0; u < GR_RPW; ++u) {
+                        jl[u] = cols(X, u);
+                        wl[u] = weights(X, u);
+                        cnt[u] = __popcll(__ballot(jl[u] < bound));
+                    }
+                    if (q + 1 < nq) stage(q + 1, (q + 1) & 1);
+                    const float *src = &vs[q & 1][0] + lane;
+#pragma unroll
+                    for (int u = 0; u < GR_RPW; ++u) {
+                        kc[u] += cnt[u];
+                        load(Y, u);
+                    }
+#pragma unroll
+                    for (int u = 0; u < GR_RPW; ++u) {
+                        walk(jl[u], wl[u], u, cnt[u], base, src);
+                        if (cnt[u] == 64) {
+                            // more of the row's entries in this range (rare): walk on from
+                            // Y, which starts at the cursor, and reload it after them
+                            for (;;) {
+                                const int32_t j2 = cols(Y, u);
+                                const int c2 = __popcll(__ballot(j2 < bound));
+                                walk(j2, weights(Y, u), u, c2, base, src);
+                                kc[u] += c2;
+                                load(Y, u);
+                                if (c2 < 64) break;
+                            }
+                        }
+                    }
+                };
+                int q = 0;
+                for (; q + 2 <= nq; q += 2) {
+                    range(q, A, B);
+                    range(q + 1, B, A);
                 }
-                for (; e < cnt; ++e) {
-                    const int64_t j = __builtin_amdgcn_readlane(jj, e);
-                    const float we = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ww), e));
-                    acc = __fmaf_rn(we, vb[j * a.Rp], acc);
-                }
+                if (q < nq) range(q, A, B);
+                // every wave is done with the staging buffers before the next item loads
+                // them
+                __syncthreads();
             }
         }
-        rel_element<MODE>(a, idx, live, acc, I.b[i], s0, s1, s2);
+        const int64_t r = (int64_t)c * 64 + lane;
+#pragma unroll
+        for (int u = 0; u < GR_RPW; ++u) {
+            const int64_t i = i0 + u;
+            if (i < n)
+                rel_element<MODE>(a, (I.row0 + i) * a.Rp + r, r < a.R, acc[u], I.b[i], s0, s1,
+                                  s2);
+        }
     }
-    rel_write_partials<MODE>(a, blockIdx.x, s0, s1, s2, sh, 4);
+    rel_write_partials<MODE>(a, blockIdx.x, s0, s1, s2, sh, GR_WAVES);
 }
 
 // Epilogue of the dense tiled product for every mode (b, and the state pointers in `a`,
@@ -313,17 +445,17 @@ hipError_t rel_by_dtypes(int32_t wdt, int32_t idt, F &&f) {
 }
 
 template <int MODE>
-hipError_t rel_rows_launch(const RelInst *insts, int32_t ninst, int64_t items, int32_t C,
-                           int32_t wdt, int32_t idt, const RelArgs &a, hipStream_t st) {
-    const unsigned g = (unsigned)rel_row_blocks(items, C);
+hipError_t rel_gather_launch(const RelInst *insts, int32_t ninst, int64_t blocks, int32_t C,
+                             int32_t wdt, int32_t idt, const RelArgs &a, hipStream_t st) {
+    const unsigned g = (unsigned)rel_gather_blocks(blocks, C);
     if (MODE == REL_A) {
-        k_rel_rows<REL_A, float, int32_t><<<g, 256, 0, st>>>(insts, ninst, items, C, a);
+        k_rel_gather<REL_A, float, int32_t><<<g, GR_THREADS, 0, st>>>(insts, ninst, blocks, C, a);
         return hipGetLastError();
     }
     return rel_by_dtypes(wdt, idt, [&](auto wtag, auto itag) {
         using TW = decltype(wtag);
         using TI = decltype(itag);
-        k_rel_rows<MODE, TW, TI><<<g, 256, 0, st>>>(insts, ninst, items, C, a);
+        k_rel_gather<MODE, TW, TI><<<g, GR_THREADS, 0, st>>>(insts, ninst, blocks, C, a);
         return hipGetLastError();
     });
 }
@@ -344,28 +476,27 @@ hipError_t rel_tile_launch(int64_t n, const float *J, const float *b, const RelA
 
 }  // namespace
 
-int64_t rel_row_blocks(int64_t items, int32_t C) {
-    const int64_t waves = items * (int64_t)C;
-    int64_t g = (waves + 3) / 4;
-    if (g > REL_ROW_BLOCKS_MAX) g = REL_ROW_BLOCKS_MAX;
+int64_t rel_gather_blocks(int64_t blocks, int32_t C) {
+    int64_t g = blocks * (int64_t)C;
+    if (g > REL_GATHER_BLOCKS_MAX) g = REL_GATHER_BLOCKS_MAX;
     return g < 1 ? 1 : g;
+}
+
+hipError_t launch_rel_gather(int32_t mode, const RelInst *insts, int32_t ninst, int64_t blocks,
+                             int32_t C, int32_t wdt, int32_t idt, const RelArgs &a,
+                             hipStream_t st) {
+    switch (mode) {
+        case REL_FWD: return rel_gather_launch<REL_FWD>(insts, ninst, blocks, C, wdt, idt, a, st);
+        case REL_LOSS: return rel_gather_launch<REL_LOSS>(insts, ninst, blocks, C, wdt, idt, a, st);
+        case REL_A: return rel_gather_launch<REL_A>(insts, ninst, blocks, C, wdt, idt, a, st);
+        case REL_B: return rel_gather_launch<REL_B>(insts, ninst, blocks, C, wdt, idt, a, st);
+        case REL_BA: return rel_gather_launch<REL_BA>(insts, ninst, blocks, C, wdt, idt, a, st);
+    }
+    return hipErrorInvalidValue;
 }
 
 int64_t rel_tile_blocks(int64_t n, int64_t Rp) {
     return ((n + SB_BI - 1) / SB_BI) * (Rp / SB_BR);
-}
-
-hipError_t launch_rel_rows(int32_t mode, const RelInst *insts, int32_t ninst, int64_t items,
-                           int32_t C, int32_t wdt, int32_t idt, const RelArgs &a,
-                           hipStream_t st) {
-    switch (mode) {
-        case REL_FWD: return rel_rows_launch<REL_FWD>(insts, ninst, items, C, wdt, idt, a, st);
-        case REL_LOSS: return rel_rows_launch<REL_LOSS>(insts, ninst, items, C, wdt, idt, a, st);
-        case REL_A: return rel_rows_launch<REL_A>(insts, ninst, items, C, wdt, idt, a, st);
-        case REL_B: return rel_rows_launch<REL_B>(insts, ninst, items, C, wdt, idt, a, st);
-        case REL_BA: return rel_rows_launch<REL_BA>(insts, ninst, items, C, wdt, idt, a, st);
-    }
-    return hipErrorInvalidValue;
 }
 
 hipError_t launch_rel_tiles(int32_t mode, int64_t n, const float *J, const float *b,

@@ -691,6 +691,7 @@ struct RelPlan {
     std::vector<size_t> base;
     std::vector<int64_t> row0;
     int64_t rows = 0, Rp = 0;
+    int64_t blocks_all = 0;        // blocks of 64 rows over every instance
     int32_t C = 0;                 // 64-replica chunks of a row
     int32_t k = 1, nseg = 0;
     // partial slots of a step: the element-wise pass over all rows writes slots
@@ -699,7 +700,7 @@ struct RelPlan {
     int32_t nblk = 0, nblk_all = 0, nblk_gather = 0;
     struct Group {
         int32_t wdt, idt, first, count, slot0;
-        int64_t items;
+        int64_t items, blocks;     // rows, and blocks of 64 rows (the gather's work items)
     };
     std::vector<Group> groups;     // CSR instances by (coupling, index) type
     std::vector<int32_t> csr_order;   // instance indices, grouped
@@ -756,7 +757,7 @@ qpa_status make_rel_plan(qpa_ctx *ctx, int32_t count, const qpa_problem *probs,
         const int32_t wdt = probs[q].coupling_dtype, idt = probs[q].index_dtype;
         bool found = false;
         for (auto &g : rp.groups) found = found || (g.wdt == wdt && g.idt == idt);
-        if (!found) rp.groups.push_back({wdt, idt, 0, 0, 0, 0});
+        if (!found) rp.groups.push_back({wdt, idt, 0, 0, 0, 0, 0});
     }
     int32_t slot = 0;
     for (auto &g : rp.groups) {
@@ -766,10 +767,11 @@ qpa_status make_rel_plan(qpa_ctx *ctx, int32_t count, const qpa_problem *probs,
                 probs[q].index_dtype == g.idt) {
                 rp.csr_order.push_back(q);
                 g.items += probs[q].n;
+                g.blocks += (probs[q].n + 63) / 64;
             }
         g.count = (int32_t)rp.csr_order.size() - g.first;
         g.slot0 = slot;
-        slot += (int32_t)rel_row_blocks(g.items, rp.C);
+        slot += (int32_t)rel_gather_blocks(g.blocks, rp.C);
     }
     for (int32_t q = 0; q < count; ++q) {
         if (probs[q].format != QPA_FMT_DENSE) continue;
@@ -777,7 +779,9 @@ qpa_status make_rel_plan(qpa_ctx *ctx, int32_t count, const qpa_problem *probs,
         slot += (int32_t)rel_tile_blocks(probs[q].n, rp.Rp);
     }
     rp.nblk_gather = slot;
-    rp.nblk_all = (int32_t)rel_row_blocks(rp.rows, rp.C);
+    rp.blocks_all = 0;
+    for (int32_t q = 0; q < count; ++q) rp.blocks_all += (probs[q].n + 63) / 64;
+    rp.nblk_all = (int32_t)rel_gather_blocks(rp.blocks_all, rp.C);
     rp.nblk = std::max(rp.nblk_gather, rp.nblk_all);
     const size_t V = rp.vec_bytes();
     rp.o_tab_all = take(sizeof(RelInst) * (size_t)count);
@@ -1287,7 +1291,7 @@ qpa_status relaxed_run(qpa_ctx *ctx, int32_t count, const qpa_problem *probs,
         }
     }
     // instance tables: every instance (element-wise pass) and the CSR ones by group
-    auto inst_entry = [&](int32_t q, int64_t item0) {
+    auto inst_entry = [&](int32_t q, int64_t item0, int64_t blk0) {
         const qpa_problem &p = probs[q];
         RelInst e{};
         if (p.format == QPA_FMT_CSR) {
@@ -1299,16 +1303,22 @@ qpa_status relaxed_run(qpa_ctx *ctx, int32_t count, const qpa_problem *probs,
         e.n = p.n;
         e.row0 = rp.row0[q];
         e.item0 = item0;
+        e.blk0 = blk0;
         e.skip_diag = p.kind == QPA_KIND_QUBO ? 1 : 0;
         return e;
     };
     std::vector<RelInst> tab_all(count), tab_csr(std::max<size_t>(rp.csr_order.size(), 1));
-    for (int32_t q = 0; q < count; ++q) tab_all[q] = inst_entry(q, rp.row0[q]);
+    int64_t blk_all = 0;
+    for (int32_t q = 0; q < count; ++q) {
+        tab_all[q] = inst_entry(q, rp.row0[q], blk_all);
+        blk_all += (probs[q].n + 63) / 64;
+    }
     for (const auto &g : rp.groups) {
-        int64_t item0 = 0;
+        int64_t item0 = 0, blk0 = 0;
         for (int32_t e = g.first; e < g.first + g.count; ++e) {
-            tab_csr[e] = inst_entry(rp.csr_order[e], item0);
+            tab_csr[e] = inst_entry(rp.csr_order[e], item0, blk0);
             item0 += probs[rp.csr_order[e]].n;
+            blk0 += (probs[rp.csr_order[e]].n + 63) / 64;
         }
     }
     RelInst *d_all = at<RelInst>(ws, rp.o_tab_all), *d_csr = at<RelInst>(ws, rp.o_tab_csr);
@@ -1366,8 +1376,8 @@ qpa_status relaxed_run(qpa_ctx *ctx, int32_t count, const qpa_problem *probs,
         for (const auto &g : rp.groups) {
             RelArgs b = a;
             b.slot0 = g.slot0;
-            QPA_HIP(launch_rel_rows(mode, d_csr + g.first, g.count, g.items, rp.C, g.wdt, g.idt,
-                                    b, st));
+            QPA_HIP(launch_rel_gather(mode, d_csr + g.first, g.count, g.blocks, rp.C, g.wdt,
+                                      g.idt, b, st));
         }
         for (int32_t q = 0; q < count; ++q) {
             if (rp.dense_slot[q] < 0) continue;
@@ -1444,7 +1454,8 @@ qpa_status relaxed_run(qpa_ctx *ctx, int32_t count, const qpa_problem *probs,
                 a.yb = yb;
                 a.part = part + (size_t)3 * rp.nblk * (size_t)(t1 - 1);
                 a.slot0 = 0;
-                QPA_HIP(launch_rel_rows(REL_MODE_A, d_all, count, rp.rows, rp.C, 0, 0, a, st));
+                QPA_HIP(launch_rel_gather(REL_MODE_A, d_all, count, rp.blocks_all, rp.C, 0, 0,
+                                          a, st));
                 cur ^= 1;
             }
             for (int32_t t = t1 - 1; t > t0; --t) {    // B(t), then A(t - 1)

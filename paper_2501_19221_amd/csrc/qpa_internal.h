@@ -331,6 +331,7 @@ struct RelInst {
     int64_t n;
     int64_t row0;               // first global row of the instance
     int64_t item0;              // first row of the instance among the launch's rows
+    int64_t blk0;               // first 64-row block of the instance among the launch's
     int32_t skip_diag;          // a QUBO: stored diagonal entries are skipped
     int32_t pad_;
 };
@@ -353,16 +354,18 @@ struct RelArgs {
     float *xbar;               // LOSS, B: written; A: xbar_{t+1} read (own)
     double *part;              // A, BA: partial table of the A step; LOSS: loss partials
 };
-constexpr int64_t REL_ROW_BLOCKS_MAX = 2048;
-// Workgroups of a row launch over `items` rows of C 64-replica chunks (each writes one
-// partial slot), and of the dense tiled product of an n-row instance.
-int64_t rel_row_blocks(int64_t items, int32_t C);
+// Workgroups of the dense tiled product of an n-row instance.
 int64_t rel_tile_blocks(int64_t n, int64_t Rp);
-// Row launch over a device table of instances sharing coupling / index types (wdt, idt;
-// ignored by REL_MODE_A), `items` = the sum of their n.
-hipError_t launch_rel_rows(int32_t mode, const RelInst *insts, int32_t ninst, int64_t items,
-                           int32_t C, int32_t wdt, int32_t idt, const RelArgs &a,
-                           hipStream_t st);
+// Row launches over a device table of instances sharing coupling / index types (wdt, idt;
+// ignored by REL_MODE_A), in blocks of 64 rows: the CSR product modes (FWD, LOSS, B, BA)
+// with the product's input staged through LDS, and the element-wise REL_MODE_A over the
+// rows of every instance; `blocks` = the sum of ceil(n / 64) over the table's instances;
+// rel_gather_blocks = the launch's workgroups (each writes one partial slot).
+constexpr int64_t REL_GATHER_BLOCKS_MAX = 1024;
+int64_t rel_gather_blocks(int64_t blocks, int32_t C);
+hipError_t launch_rel_gather(int32_t mode, const RelInst *insts, int32_t ninst, int64_t blocks,
+                             int32_t C, int32_t wdt, int32_t idt, const RelArgs &a,
+                             hipStream_t st);
 // Dense instance (FP32 canonical J, n x n) through the tiled product; the state pointers
 // of `a` point at the instance's first row (Rp a multiple of 128).  Not REL_MODE_A.
 hipError_t launch_rel_tiles(int32_t mode, int64_t n, const float *J, const float *b,
