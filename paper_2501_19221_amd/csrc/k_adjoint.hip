@@ -27,6 +27,7 @@
 // order and written to a per-step table of partial sums, which one last launch reduces in
 // a fixed order: results do not depend on the checkpoint interval or on timing.
 #include "fp32_tiled.h"
+#include <type_traits>
 
 namespace qpa {
 namespace {
@@ -223,16 +224,19 @@ __global__ void __launch_bounds__(GR_THREADS) k_rel_gather(const RelInst *__rest
                 const bool skip = I.skip_diag != 0;
                 // staging of columns 256 q .. 256 q + 255 (past n: column n - 1 again,
                 // unused): thread t moves 4 x 16 bytes, element e = 1024 u + t = column
-                // e / 16, floats 4 (e % 16) .. + 3; a wave's destinations are contiguous
+                // e / 16 of the range, floats 4 (e % 16) .. + 3; a wave's destinations are
+                // contiguous.  Addresses are the range's uniform base plus 32-bit offsets.
+                const uint32_t rp4 = (uint32_t)a.Rp;
                 auto stage = [&](int q, int buf) {
+                    const float *vq = v + (int64_t)q * GR_CW * a.Rp;
+                    const uint32_t lim = (uint32_t)min((int64_t)GR_CW - 1, n - 1 - (int64_t)q * GR_CW);
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
-                        const int e = 1024 * u + (int)threadIdx.x;
-                        int64_t j = (int64_t)q * GR_CW + (e >> 4);
-                        j = j < n ? j : n - 1;
+                        const uint32_t e = 1024u * u + threadIdx.x;
+                        const uint32_t o = __umul24(min(e >> 4, lim), rp4) + 4u * (e & 15u);
                         __builtin_amdgcn_global_load_lds(
-                            v + j * a.Rp + 4 * (e & 15),
-                            (lds_void *)(&vs[buf][0] + 4 * (1024 * u + 64 * wv)), 16, 0, 0);
+                            vq + o, (lds_void *)(&vs[buf][0] + 4 * (1024 * u + 64 * wv)), 16, 0,
+                            0);
                     }
                     // the window loads that follow stay younger than these
                     asm volatile("" ::: "memory");
@@ -285,6 +289,39 @@ __global__ void __launch_bounds__(GR_THREADS) k_rel_gather(const RelInst *__rest
                                            src[64 * j], acc[u]);
                     }
                 };
+                // Integer weights of 8 or 16 bits: the float of such a weight has its low 8
+                // bits zero, which then carry the entry's column within the staged range,
+                // so that one read of the window word gives both (the column on the scalar
+                // unit, the weight as it is).
+                constexpr bool PACK = std::is_integral<TW>::value && sizeof(TW) <= 2;
+                auto pack = [&](int32_t jl, float wl, int32_t base) {
+                    return (__float_as_int(wl) & ~0xFF) | ((jl - base) & 0xFF);
+                };
+                auto walkp = [&](int32_t pk, int u, int cnt, const float *src) {
+                    int e = 0;
+                    for (; e + 4 <= cnt; e += 4) {
+                        const int32_t p0 = __builtin_amdgcn_readlane(pk, e);
+                        const int32_t p1 = __builtin_amdgcn_readlane(pk, e + 1);
+                        const int32_t p2 = __builtin_amdgcn_readlane(pk, e + 2);
+                        const int32_t p3 = __builtin_amdgcn_readlane(pk, e + 3);
+                        const float v0 = src[64 * (p0 & 0xFF)], v1 = src[64 * (p1 & 0xFF)];
+                        const float v2 = src[64 * (p2 & 0xFF)], v3 = src[64 * (p3 & 0xFF)];
+                        acc[u] = __fmaf_rn(__int_as_float(p0 & ~0xFF), v0, acc[u]);
+                        acc[u] = __fmaf_rn(__int_as_float(p1 & ~0xFF), v1, acc[u]);
+                        acc[u] = __fmaf_rn(__int_as_float(p2 & ~0xFF), v2, acc[u]);
+                        acc[u] = __fmaf_rn(__int_as_float(p3 & ~0xFF), v3, acc[u]);
+                    }
+                    for (; e < cnt; ++e) {
+                        const int32_t p = __builtin_amdgcn_readlane(pk, e);
+                        acc[u] = __fmaf_rn(__int_as_float(p & ~0xFF), src[64 * (p & 0xFF)],
+                                           acc[u]);
+                    }
+                };
+                auto walk_any = [&](int32_t jl, float wl, int u, int cnt, int32_t base,
+                                    const float *src) {
+                    if (PACK) walkp(pack(jl, wl, base), u, cnt, src);
+                    else walk(jl, wl, u, cnt, base, src);
+                };
                 const int nq = (int)((n + GR_CW - 1) / GR_CW);
                 GrWin<TW, TI> A, B;
 #pragma unroll
@@ -317,14 +354,14 @@ __global__ void __launch_bounds__(GR_THREADS) k_rel_gather(const RelInst *__rest
                     }
 #pragma unroll
                     for (int u = 0; u < GR_RPW; ++u) {
-                        walk(jl[u], wl[u], u, cnt[u], base, src);
+                        walk_any(jl[u], wl[u], u, cnt[u], base, src);
                         if (cnt[u] == 64) {
                             // more of the row's entries in this range (rare): walk on from
                             // Y, which starts at the cursor, and reload it after them
                             for (;;) {
                                 const int32_t j2 = cols(Y, u);
                                 const int c2 = __popcll(__ballot(j2 < bound));
-                                walk(j2, weights(Y, u), u, c2, base, src);
+                                walk_any(j2, weights(Y, u), u, c2, base, src);
                                 kc[u] += c2;
                                 load(Y, u);
                                 if (c2 < 64) break;
