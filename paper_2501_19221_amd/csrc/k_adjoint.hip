@@ -153,10 +153,10 @@ template <typename T> __device__ __forceinline__ float as_weight(T w) { return (
 // the element-wise pass (REL_A) over every instance's rows with the same work items, so
 // that a step's partial sums are grouped alike whichever launch computes them.  Work item
 // = (block of 64 consecutive rows of one instance, 64-replica chunk c); a workgroup of 16
-// waves takes items b, b + G, ... in order.  Wave w owns rows 4w .. 4w + 3 of the block
+// waves takes its items in the order below.  Wave w owns rows 4w .. 4w + 3 of the block
 // (lane = replica) and keeps their running sums; the input vector (x or mu of the
-// instance, the chunk's 64 replicas) goes through LDS 256 columns at a time (64 KiB, two
-// buffers: the next columns load while these are used), and each row walks its entries
+// instance, the chunk's 64 replicas) goes through LDS 128 columns at a time (two buffers
+// of 32 KiB: the next columns load while these are used), and each row walks its entries
 // whose column falls in the staged range, in ascending order, one fused multiply-add per
 // term (the order of the definition), while each staged value serves all 64 rows of the
 // block instead of one gather per entry.  A row's entries come in windows of 64 (lane k =
@@ -169,7 +169,7 @@ template <typename T> __device__ __forceinline__ float as_weight(T w) { return (
 typedef __attribute__((address_space(3))) void lds_void;
 constexpr int GR_THREADS = 1024, GR_WAVES = GR_THREADS / 64, GR_RPW = 4;
 constexpr int GR_ROWS = GR_WAVES * GR_RPW;       // 64 rows per block
-constexpr int GR_CW = 256;                       // staged columns
+constexpr int GR_CW = 128;                       // staged columns per range
 static_assert(GR_ROWS == 64, "blocks of 64 rows");
 
 typedef const __attribute__((address_space(1))) int32_t *gr_i32;
@@ -182,8 +182,11 @@ template <typename TW, typename TI> struct GrWin {
     TW w[GR_RPW];
 };
 
+// Two workgroups per CU (64 KiB of LDS each, 8 waves per SIMD): the walks are bound by
+// the latency of their LDS reads, which the second workgroup's waves hide.
 template <int MODE, typename TW, typename TI>
-__global__ void __launch_bounds__(GR_THREADS) k_rel_gather(const RelInst *__restrict__ insts,
+__global__ void __launch_bounds__(GR_THREADS)
+    __attribute__((amdgpu_waves_per_eu(8))) k_rel_gather(const RelInst *__restrict__ insts,
                                                            int32_t ninst, int64_t blocks,
                                                            int32_t C, const RelArgs a) {
     constexpr bool GATHER = MODE != REL_A;
@@ -195,7 +198,14 @@ __global__ void __launch_bounds__(GR_THREADS) k_rel_gather(const RelInst *__rest
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     const int64_t total = blocks * C;
-    for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+    // items in chunks of P = (workgroups / 8) consecutive ones, chunk k on compute die
+    // k mod 8 (workgroup b runs on die b mod 8): the items a die runs at a time are
+    // neighbouring blocks, mostly of one instance, whose input vector its L2 then holds
+    // for all of them instead of every die fetching every instance's
+    const int64_t P = gridDim.x >> 3;
+    const int64_t die = blockIdx.x & 7, slot = blockIdx.x >> 3;
+    for (int64_t k = die; k * P + slot < total; k += 8) {
+        const int64_t it = k * P + slot;
         const int64_t blk = it / C;
         const int c = (int)(it - blk * C);
         int lo = 0, hi = ninst - 1;
@@ -222,16 +232,18 @@ __global__ void __launch_bounds__(GR_THREADS) k_rel_gather(const RelInst *__rest
                 const gi_t col = (gi_t)I.col;
                 const gw_t w = (gw_t)I.w;
                 const bool skip = I.skip_diag != 0;
-                // staging of columns 256 q .. 256 q + 255 (past n: column n - 1 again,
-                // unused): thread t moves 4 x 16 bytes, element e = 1024 u + t = column
-                // e / 16 of the range, floats 4 (e % 16) .. + 3; a wave's destinations are
-                // contiguous.  Addresses are the range's uniform base plus 32-bit offsets.
+                // staging of columns GR_CW q .. GR_CW q + GR_CW - 1 (past n: column n - 1
+                // again, unused): thread t moves GR_CW / 64 pieces of 16 bytes, element
+                // e = 1024 u + t = column e / 16 of the range, floats 4 (e % 16) .. + 3; a
+                // wave's destinations are contiguous.  Addresses are the range's uniform
+                // base plus 32-bit offsets.
                 const uint32_t rp4 = (uint32_t)a.Rp;
                 auto stage = [&](int q, int buf) {
                     const float *vq = v + (int64_t)q * GR_CW * a.Rp;
-                    const uint32_t lim = (uint32_t)min((int64_t)GR_CW - 1, n - 1 - (int64_t)q * GR_CW);
+                    const uint32_t lim =
+                        (uint32_t)min((int64_t)GR_CW - 1, n - 1 - (int64_t)q * GR_CW);
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
+                    for (int u = 0; u < GR_CW / 64; ++u) {
                         const uint32_t e = 1024u * u + threadIdx.x;
                         const uint32_t o = __umul24(min(e >> 4, lim), rp4) + 4u * (e & 15u);
                         __builtin_amdgcn_global_load_lds(
@@ -485,6 +497,7 @@ template <int MODE>
 hipError_t rel_gather_launch(const RelInst *insts, int32_t ninst, int64_t blocks, int32_t C,
                              int32_t wdt, int32_t idt, const RelArgs &a, hipStream_t st) {
     const unsigned g = (unsigned)rel_gather_blocks(blocks, C);
+    if (g % 8) return hipErrorInvalidValue;       // the item order assumes whole dies
     if (MODE == REL_A) {
         k_rel_gather<REL_A, float, int32_t><<<g, GR_THREADS, 0, st>>>(insts, ninst, blocks, C, a);
         return hipGetLastError();
@@ -514,9 +527,9 @@ hipError_t rel_tile_launch(int64_t n, const float *J, const float *b, const RelA
 }  // namespace
 
 int64_t rel_gather_blocks(int64_t blocks, int32_t C) {
-    int64_t g = blocks * (int64_t)C;
+    int64_t g = (blocks * (int64_t)C + 7) / 8 * 8;          // a multiple of the 8 dies
     if (g > REL_GATHER_BLOCKS_MAX) g = REL_GATHER_BLOCKS_MAX;
-    return g < 1 ? 1 : g;
+    return g < 8 ? 8 : g;
 }
 
 hipError_t launch_rel_gather(int32_t mode, const RelInst *insts, int32_t ninst, int64_t blocks,

@@ -361,7 +361,7 @@ int64_t rel_tile_blocks(int64_t n, int64_t Rp);
 // with the product's input staged through LDS, and the element-wise REL_MODE_A over the
 // rows of every instance; `blocks` = the sum of ceil(n / 64) over the table's instances;
 // rel_gather_blocks = the launch's workgroups (each writes one partial slot).
-constexpr int64_t REL_GATHER_BLOCKS_MAX = 1024;
+constexpr int64_t REL_GATHER_BLOCKS_MAX = 512;     // two resident workgroups per CU
 int64_t rel_gather_blocks(int64_t blocks, int32_t C);
 hipError_t launch_rel_gather(int32_t mode, const RelInst *insts, int32_t ninst, int64_t blocks,
                              int32_t C, int32_t wdt, int32_t idt, const RelArgs &a,
