@@ -309,8 +309,7 @@ __global__ void __launch_bounds__(GR_THREADS)
                 auto pack = [&](int32_t jl, float wl, int32_t base) {
                     return (__float_as_int(wl) & ~0xFF) | ((jl - base) & 0xFF);
                 };
-                auto walkp = [&](int32_t pk, int u, int cnt, const float *src) {
-                    int e = 0;
+                auto walkp = [&](int32_t pk, int u, int e, int cnt, const float *src) {
                     for (; e + 4 <= cnt; e += 4) {
                         const int32_t p0 = __builtin_amdgcn_readlane(pk, e);
                         const int32_t p1 = __builtin_amdgcn_readlane(pk, e + 1);
@@ -329,9 +328,35 @@ __global__ void __launch_bounds__(GR_THREADS)
                                            acc[u]);
                     }
                 };
+                // rows u and u + 1 together over their common first entries (eight reads in
+                // flight, two independent sums), then each alone
+                auto walkp2 = [&](int32_t pa, int32_t pb, int u, int ca, int cb,
+                                  const float *src) {
+                    const int cm = min(ca, cb);
+                    int e = 0;
+                    for (; e + 4 <= cm; e += 4) {
+                        int32_t p[8];
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            p[k] = __builtin_amdgcn_readlane(pa, e + k);
+                            p[4 + k] = __builtin_amdgcn_readlane(pb, e + k);
+                        }
+                        float vv[8];
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) vv[k] = src[64 * (p[k] & 0xFF)];
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            acc[u] = __fmaf_rn(__int_as_float(p[k] & ~0xFF), vv[k], acc[u]);
+                            acc[u + 1] =
+                                __fmaf_rn(__int_as_float(p[4 + k] & ~0xFF), vv[4 + k], acc[u + 1]);
+                        }
+                    }
+                    walkp(pa, u, e, ca, src);
+                    walkp(pb, u + 1, e, cb, src);
+                };
                 auto walk_any = [&](int32_t jl, float wl, int u, int cnt, int32_t base,
                                     const float *src) {
-                    if (PACK) walkp(pack(jl, wl, base), u, cnt, src);
+                    if (PACK) walkp(pack(jl, wl, base), u, 0, cnt, src);
                     else walk(jl, wl, u, cnt, base, src);
                 };
                 const int nq = (int)((n + GR_CW - 1) / GR_CW);
@@ -364,9 +389,15 @@ __global__ void __launch_bounds__(GR_THREADS)
                         kc[u] += cnt[u];
                         load(Y, u);
                     }
+                    if (PACK) {
+#pragma unroll
+                        for (int u = 0; u < GR_RPW; u += 2)
+                            walkp2(pack(jl[u], wl[u], base), pack(jl[u + 1], wl[u + 1], base), u,
+                                   cnt[u], cnt[u + 1], src);
+                    }
 #pragma unroll
                     for (int u = 0; u < GR_RPW; ++u) {
-                        walk_any(jl[u], wl[u], u, cnt[u], base, src);
+                        if (!PACK) walk_any(jl[u], wl[u], u, cnt[u], base, src);
                         if (cnt[u] == 64) {
                             // more of the row's entries in this range (rare): walk on from
                             // Y, which starts at the cursor, and reload it after them
