@@ -174,6 +174,26 @@ def test_mixed_dense_and_sparse_batch_against_oracle(q, eng):
     _compare("mixed batch", got, ref)
 
 
+def test_two_replica_chunks_with_int16_and_int8_weights(q, eng):
+    """100 replicas (two chunks of 64, the second with 36 live replicas) on ER QUBOs whose
+    weights are int16, and the same graph with its weights stored as int8 (a launch group
+    of its own): the batch mean against the sum of the oracle's per-instance results."""
+    import dataclasses
+    base = gen.er_qubo(700, 0.1, 100, np.random.default_rng(31))
+    narrow = dataclasses.replace(
+        base, csr=gen.CSR(base.n, base.csr.rp, base.csr.col, base.csr.w.astype(np.int8)))
+    other = gen.er_qubo(300, 0.1, 100, np.random.default_rng(32))
+    insts = [base, narrow, other]
+    R, seed = 100, 13
+    norm = 1.0 / (R * len(insts))
+    with ThreadPoolExecutor(len(insts)) as ex:
+        futs = [ex.submit(_oracle, inst, R, seed + k, norm) for k, inst in enumerate(insts)]
+        say("two replica chunks, int16 and int8 weights, R=%d" % R)
+        got = _gpu(q, eng, [q.Problem.from_instance(i) for i in insts], _params(q, R, seed))
+        ref = _sum([f.result() for f in futs])
+    _compare("R=100, int16 + int8", got, ref)
+
+
 def test_checkpoint_interval_and_forward_only(q, eng):
     """Bitwise the same loss and gradients for every checkpoint interval; the forward-only
     call returns the same loss bits."""
