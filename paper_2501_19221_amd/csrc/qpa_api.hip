@@ -851,12 +851,12 @@ std::vector<MfmaTile> by_compute_die(const std::vector<MfmaTile> &in) {
 // Cost model of one PA step of one instance on the two batch paths, in seconds: work
 // over a rate.  The rates are the context's, measured by qpa_autotune_batch on this
 // device for the caller's instances; before any measurement, estimates from earlier
-// measurements on MI355X (the sparse task kernel about 0.3e12 signed coupling adds per
+// measurements on MI355X (the sparse task kernel about 1e12 signed coupling adds per
 // second, the grouped matrix-core step about 3e12 bytes per second).  The grouped step's
 // work is its memory traffic: the couplings (2 bytes per element in BF16, or 4 bytes per
 // stored entry for integer couplings sparse enough for entry lists: at most a tenth of
 // the padded matrix is assumed here, the exact test runs on the device) and x, m.
-constexpr double SPARSE_ADDS_DEFAULT = 0.3e12, DENSE_BPS_DEFAULT = 3.0e12;
+constexpr double SPARSE_ADDS_DEFAULT = 1.0e12, DENSE_BPS_DEFAULT = 3.0e12;
 double csr_step_work(int64_t nnz, int64_t R) { return (double)nnz * (double)R; }
 double dense_step_work(int64_t np, int64_t R, int64_t nnz = -1) {
     const double J = nnz >= 0 ? 4.0 * (double)nnz : (double)np * (double)np * 2.0;

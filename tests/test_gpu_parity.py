@@ -517,8 +517,7 @@ def test_batch_uneven_instances_bit_exact(q, eng, path, R):
     else:                                                  # the cost model mixes both
         assert paths[0] == q.QPA_PATH_BATCH_SPARSE_I8       # n=379, 10% of pairs
         assert paths[9] == q.QPA_PATH_BATCH_DENSE_I8        # n=200, 50% of pairs
-        if R == 70:                                        # (near the break-even at 40)
-            assert paths[-3] == q.QPA_PATH_BATCH_SPARSE     # n=400, 0.5% of pairs
+        assert paths[-3] == q.QPA_PATH_BATCH_SPARSE         # n=400, 0.5% of pairs
     lam = orc.lambda_linear(T, lam0)
     for k, (inst, out) in enumerate(zip(insts, outs)):
         x, m, canon = _oracle_instance(inst, R, T, lam, eta, alpha, seed=11 + k)
