@@ -204,11 +204,13 @@ qpa_status qpa_solve(qpa_ctx *ctx, const qpa_problem *problem, const qpa_params 
  *  - sparse: tasks (instance, group of 64 replicas), sorted by stored entries, largest
  *    first, taken by the workgroups of one persistent launch from an atomic counter;
  *    no workgroup waits on another;
- *  - dense: the couplings are expanded once into a BF16 matrix (exact, see above), or an
- *    int8 matrix for integer weights with |w| <= 127 (v_mfma_i32_32x32x32_i8, exact int32
- *    sums, half the coupling bytes), and every PA step is one grouped matrix-core launch
- *    over the 128x128 tiles of all such instances (one per element type).  Integer
- *    instances give the same bits on every path.
+ *  - dense: the couplings are expanded once into a BF16 matrix (exact, see above), or for
+ *    integer weights with |w| <= 127 into int8 (v_mfma_i32_32x32x32_i8, exact int32 sums):
+ *    a dense int8 matrix, or, where every 16x128 block is sparse enough, per-block lists
+ *    of its nonzeros that the step kernel places into LDS (QPA_PATH_BATCH_SPARSE_I8); every
+ *    PA step is one grouped matrix-core launch per kind over the tiles of all such
+ *    instances (BF16: 128 replicas x 128 variables; int8: 64 x 256).  Integer instances
+ *    give the same bits on every path.
  * Set-up and scoring run on the context's auxiliary streams (ordered after `stream` and
  * joined back into it before the call returns), the per-instance parts issued from up to
  * four host threads of the call's own, the densified integer instances' parts as batched
@@ -438,9 +440,9 @@ qpa_status qpa_autotune(qpa_ctx *ctx, const qpa_problem *problem, const qpa_para
  * batch is solved for probe_steps steps with every BF16-exact instance forced dense, then
  * with every instance forced sparse (a warm-up run before each timed one), and the
  * step-kernel time of each path gives its rate -- dense tiles in bytes per second,
- * counting 2 bytes per coupling of the padded matrix plus 16 per variable and replica
- * (x and m read and written), sparse tasks in coupling adds per second (stored entries
- * times replicas).  The context keeps the rates; later qpa_workspace_size_batch and
+ * counting 2 bytes per coupling of the padded matrix (4 per stored entry for the int8
+ * entry lists) plus 16 per variable and replica (x and m read and written), sparse tasks
+ * in coupling adds per second (stored entries times replicas).  The context keeps the rates; later qpa_workspace_size_batch and
  * qpa_solve_batch calls on it choose each instance's path with them (before any
  * measurement, built-in estimates are used).
  *  rates (host, optional, 2 doubles): the rates now in effect [dense B/s, sparse adds/s].
