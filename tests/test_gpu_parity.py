@@ -530,6 +530,39 @@ def test_batch_uneven_instances_bit_exact(q, eng, path, R):
         assert int(host(out["best"])[0]) == int(np.flatnonzero(e == e.min())[0]), k
 
 
+def _float_chimera(m, seed):
+    """A Chimera Ising instance with Gaussian float couplings and fields on its graph."""
+    inst = gen.chimera_ising(m, seed=seed)
+    rng = np.random.default_rng(seed)
+    c = inst.csr
+    D = c.to_dense(np.int32).astype(np.float32)
+    W = np.triu(rng.standard_normal(D.shape).astype(np.float32) * (D != 0), 1)
+    W = W + W.T
+    rows, cols = np.nonzero(D)
+    inst.csr = gen.CSR(inst.n, c.rp, c.col, W[rows, cols].astype(np.float32))
+    inst.lin = rng.standard_normal(inst.n).astype(np.float32) * 0.3
+    return inst
+
+
+def test_batch_float_couplings_on_the_sparse_kernel(q, eng):
+    """Float couplings are not exact in BF16, so a batch sends them to the sparse task
+    kernel (FP32 sums of +-w in row order): the oracle's bits, next to an integer instance,
+    with a full and a partial group of 64 replicas."""
+    insts = [_float_chimera(3, 41), gen.chimera_ising(2, seed=42), _float_chimera(2, 43)]
+    R, T, eta, alpha, lam0 = 70, 60, 0.1, 0.8, 2.0
+    probs = [q.Problem.from_instance(i) for i in insts]
+    p = _params(q, R, T, eta, alpha, lam0, seed=21)
+    say("batch with float couplings, R=%d T=%d" % (R, T))
+    outs = eng.solve_batch(probs, p, want_state=True)
+    paths = q.qpa_batch_paths(eng.ctx, len(insts))
+    assert paths[0] == q.QPA_PATH_BATCH_SPARSE and paths[2] == q.QPA_PATH_BATCH_SPARSE
+    lam = orc.lambda_linear(T, lam0)
+    for k, (inst, out) in enumerate(zip(insts, outs)):
+        x, m, _ = _oracle_instance(inst, R, T, lam, eta, alpha, seed=21 + k)
+        assert np.array_equal(host(out["x"]), x), k
+        assert np.array_equal(host(out["m"]), m), k
+
+
 def test_batch_autotune_measures_rates_and_chooses_by_them(q, eng):
     """qpa_autotune_batch measures both paths on the device; afterwards every instance
     takes the path the cost model gives with the measured rates (dense when BF16-exact and
