@@ -425,7 +425,7 @@ def bench_relaxed(a, torch, qpa, wl, ckpt=50):
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py measures one GPU only: this build runs the whole solve on a single "
+        print("bench.py measures one GPU only: the library runs the whole solve on a single "
               "MI355X (replica/variable sharding across GPUs is a design note, not code). "
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)

@@ -55,7 +55,7 @@ typedef enum {
                             /* FP32 fields would no longer be exact                   */
     QPA_E_WORKSPACE = 5,    /* workspace smaller than qpa_workspace_size()            */
     QPA_E_DEVICE = 6,       /* a HIP call failed                                      */
-    QPA_E_UNSUPPORTED = 7   /* valid request outside what this build implements       */
+    QPA_E_UNSUPPORTED = 7   /* valid request outside what this library implements     */
 } qpa_status;
 
 typedef enum { QPA_KIND_QUBO = 0, QPA_KIND_ISING = 1 } qpa_kind;
