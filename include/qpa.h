@@ -193,6 +193,32 @@ qpa_status qpa_solve(qpa_ctx *ctx, const qpa_problem *problem, const qpa_params 
                      void *workspace, size_t workspace_bytes, void *stream,
                      const qpa_outputs *out);
 
+/* Best state over the trajectory (Sec. VIII: the solver evolves many states and reports
+ * the best one found, which need not be where a replica ends).  Device outputs, each
+ * required:
+ *  best_energy [R] double: the lowest objective value (as in qpa_outputs.energy) among
+ *              the replica's sampled states;
+ *  best_step   [R] int32: the number of steps completed at that state (the earliest on
+ *              ties);
+ *  best_spins  [R*n] int8: that state's spins, row-major by replica. */
+typedef struct {
+    double *best_energy;
+    int32_t *best_step;
+    int8_t *best_spins;
+} qpa_track_outputs;
+
+/* qpa_solve that also keeps each replica's best state: the steps run in segments of
+ * `every` (>= 1) steps, and the state after each segment -- after steps every, 2 every,
+ * ..., and after the last step (the initial state when steps == 0) -- is scored exactly
+ * like the final one.  The dynamics are those of qpa_solve (a split run gives the same
+ * bits), so `out` receives exactly what qpa_solve gives; the cost is one scoring per
+ * segment.  workspace: qpa_workspace_size() bytes, as for qpa_solve.
+ *  Errors: every < 1, or a missing output -> QPA_E_ARG. */
+qpa_status qpa_solve_track(qpa_ctx *ctx, const qpa_problem *problem,
+                           const qpa_params *params, int32_t every, void *workspace,
+                           size_t workspace_bytes, void *stream, const qpa_outputs *out,
+                           const qpa_track_outputs *track);
+
 /* Solve `count` independent sparse instances together (the batch shares params).
  * Instance k is solved exactly as qpa_solve would solve it alone with seed
  * params->seed + k; its outputs go to out[k].

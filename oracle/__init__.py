@@ -425,6 +425,34 @@ def solve_csr_int(rp, col, w, lin, R, T, lam, eta, alpha, seed, sigma0, r0=0):
     return OracleResult(x, m, s, e, _argmin_first(e))
 
 
+def track_best(x, m, T, every, step, energy):
+    """Best sampled state of a PA trajectory (Sec. VIII: many states are evolved and the
+    best one found is what the solver reports, not necessarily where a replica ends).
+    step(x, m, t0, t1) advances the state in place through steps t0 .. t1-1; energy(s)
+    gives the objective of spins s [R, n].  The state after each segment of `every` steps
+    and after step T (the initial state when T == 0) is binarised (+1 where x >= 0) and
+    scored; per replica the lowest energy is kept, the earliest state on ties.
+    Returns (best_energy [R], best_step [R] int32, best_spins [R, n] int8)."""
+    best_e = best_t = best_s = None
+    t0 = 0
+    while True:
+        t1 = min(t0 + every, T)
+        if t1 > t0:
+            step(x, m, t0, t1)
+        s = _sign(x)
+        e = np.asarray(energy(s))
+        if best_e is None:
+            best_e, best_t, best_s = e.copy(), np.full(len(e), t1, np.int32), s.copy()
+        else:
+            better = e < best_e
+            best_e = np.where(better, e, best_e)
+            best_t[better] = t1
+            best_s[better] = s[better]
+        t0 = t1
+        if t0 >= T:
+            return best_e, best_t, best_s
+
+
 def qubo_to_ising_csr_int(rp, col, w, c):
     """App. A for a CSR QUBO with integer weights: J = the off-diagonal entries,
     b_i = (sum of row i, diagonal included) + c_i, K = (1/2) 1^T Q 1 + (1/2) tr Q + 1^T c."""

@@ -33,7 +33,7 @@ EXPORTED = ["qpa_create", "qpa_destroy", "qpa_last_error", "qpa_status_string",
             "qpa_sbm_solve", "qpa_sbm_steps", "qpa_spectral_radius",
             "qpa_workspace_size_spectrum", "qpa_spectrum", "qpa_autotune", "qpa_tune_set",
             "qpa_solve_noalloc", "qpa_workspace_size_relaxed_batch", "qpa_relaxed_grad_batch",
-            "qpa_autotune_batch"]
+            "qpa_autotune_batch", "qpa_solve_track"]
 QPA_NOALLOC_WORKSPACE_BYTES = 64 << 20
 QPA_NOALLOC_MAX_STEPS = 65536
 
@@ -61,6 +61,11 @@ class qpa_outputs(ctypes.Structure):
                 ("x", ctypes.c_void_p), ("m", ctypes.c_void_p)]
 
 
+class qpa_track_outputs(ctypes.Structure):
+    _fields_ = [("best_energy", ctypes.c_void_p), ("best_step", ctypes.c_void_p),
+                ("best_spins", ctypes.c_void_p)]
+
+
 class qpa_sbm_params(ctypes.Structure):
     _fields_ = [("replicas", ctypes.c_int32), ("steps", ctypes.c_int32),
                 ("a0", ctypes.c_float), ("c0", ctypes.c_float), ("dt", ctypes.c_float),
@@ -82,6 +87,9 @@ _sig = {
                        ctypes.c_size_t, _P, ctypes.POINTER(qpa_outputs)]),
     "qpa_solve_noalloc": (_S, [_P, ctypes.POINTER(qpa_problem), ctypes.POINTER(qpa_params), _P,
                                ctypes.POINTER(qpa_outputs)]),
+    "qpa_solve_track": (_S, [_P, ctypes.POINTER(qpa_problem), ctypes.POINTER(qpa_params),
+                             ctypes.c_int32, _P, ctypes.c_size_t, _P, ctypes.POINTER(qpa_outputs),
+                             ctypes.POINTER(qpa_track_outputs)]),
     "qpa_steps": (_S, [_P, ctypes.POINTER(qpa_problem), ctypes.POINTER(qpa_params),
                        ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "qpa_energy": (_S, [_P, ctypes.POINTER(qpa_problem), ctypes.POINTER(qpa_params), _P, _P,

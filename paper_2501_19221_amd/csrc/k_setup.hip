@@ -993,6 +993,30 @@ void canon_reduce(int64_t n, const double *row_abs, const double *row_max, const
                                          mirror);
 }
 
+// Best state over the trajectory: workgroup r compares replica r's energy of the state
+// after `t` steps with its best so far (the first sample is always taken; a tie keeps the
+// earlier state) and, when lower, copies the state's spins, then the energy and step.
+__global__ void __launch_bounds__(256) k_track_best(int64_t n, const double *__restrict__ energy,
+                                                    const int8_t *__restrict__ spins, int32_t t,
+                                                    int32_t first, double *__restrict__ best_e,
+                                                    int32_t *__restrict__ best_t,
+                                                    int8_t *__restrict__ best_s) {
+    const int64_t r = blockIdx.x;
+    const double e = energy[r];
+    // one decision for the workgroup, taken before anything of the replica is written
+    __shared__ int take;
+    if (threadIdx.x == 0) take = first || e < best_e[r];
+    __syncthreads();
+    if (!take) return;
+    const int8_t *src = spins + r * n;
+    int8_t *dst = best_s + r * n;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+    if (threadIdx.x == 0) {
+        best_e[r] = e;
+        best_t[r] = t;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_canon_dense(const qpa_problem &p, float *J_f32, uint16_t *Jb, int64_t npad,
@@ -1188,6 +1212,15 @@ hipError_t launch_energy(const qpa_problem &p, const int64_t *b_i64, const doubl
 hipError_t launch_argmin(int64_t R, const int64_t *e_i64, const double *e_f64, int32_t *best,
                          hipStream_t st) {
     k_argmin<<<1, 1024, 0, st>>>(R, e_i64, e_f64, best);
+    return hipGetLastError();
+}
+
+hipError_t launch_track_best(int64_t n, int64_t R, const double *energy, const int8_t *spins,
+                             int32_t t, bool first, double *best_e, int32_t *best_t,
+                             int8_t *best_s, hipStream_t st) {
+    if (R < 1 || R > INT32_MAX || n < 1) return hipErrorInvalidValue;
+    k_track_best<<<(unsigned)R, 256, 0, st>>>(n, energy, spins, t, first ? 1 : 0, best_e, best_t,
+                                              best_s);
     return hipGetLastError();
 }
 

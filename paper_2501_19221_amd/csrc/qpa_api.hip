@@ -1222,6 +1222,56 @@ qpa_status qpa_solve(qpa_ctx *ctx, const qpa_problem *problem, const qpa_params 
     return score(ctx, *problem, pl, ws, spins, out->energy, out->energy_i64, out->best, st);
 }
 
+qpa_status qpa_solve_track(qpa_ctx *ctx, const qpa_problem *problem,
+                           const qpa_params *params, int32_t every, void *workspace,
+                           size_t workspace_bytes, void *stream, const qpa_outputs *out,
+                           const qpa_track_outputs *track) {
+    Plan pl;
+    qpa_status s = prologue(ctx, problem, params, workspace, workspace_bytes, pl);
+    if (s != QPA_OK) return s;
+    if (!out || !out->energy || !out->best)
+        return fail(ctx, QPA_E_ARG, "outputs.energy and outputs.best are required");
+    if (!track || !track->best_energy || !track->best_step || !track->best_spins)
+        return fail(ctx, QPA_E_ARG,
+                    "track.best_energy, track.best_step and track.best_spins are required");
+    if (every < 1) return fail(ctx, QPA_E_ARG, "every must be >= 1 (got %d)", every);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    void *ws = workspace;
+    s = upload_schedule(ctx, *params, at<float>(ws, pl.o_lam), st);
+    if (s != QPA_OK) return s;
+    s = canonicalise(ctx, *problem, pl, ws, st);
+    if (s != QPA_OK) return s;
+    int64_t ld_r, ld_i;
+    state_strides(pl, ld_r, ld_i);
+    float *x = at<float>(ws, pl.o_x), *m = at<float>(ws, pl.o_m);
+    QPA_HIP(launch_init_state(pl.n, pl.R, params->seed, params->sigma0, x, m, ld_r, ld_i, pl.Rp,
+                              pl.np, st));
+    int8_t *spins = out->spins ? out->spins : at<int8_t>(ws, pl.o_sp);
+    // segments of `every` steps (a split run gives the bits of an uninterrupted one); the
+    // state after each is scored like the final one and offered to the track
+    const int32_t T = params->steps;
+    int32_t t0 = 0;
+    bool first = true;
+    do {
+        const int32_t t1 = (int32_t)std::min<int64_t>((int64_t)t0 + every, T);
+        if (t1 > t0) {
+            s = run_steps(ctx, *problem, *params, pl, ws, t0, t1, false, st);
+            if (s != QPA_OK) return s;
+        }
+        QPA_HIP(launch_export_spins(pl.n, pl.R, x, ld_r, ld_i, spins, st));
+        s = score(ctx, *problem, pl, ws, spins, out->energy, out->energy_i64,
+                  t1 == T ? out->best : nullptr, st);
+        if (s != QPA_OK) return s;
+        QPA_HIP(launch_track_best(pl.n, pl.R, out->energy, spins, t1, first, track->best_energy,
+                                  track->best_step, track->best_spins, st));
+        first = false;
+        t0 = t1;
+    } while (t0 < T);
+    if (out->x) QPA_HIP(launch_copy_state(pl.n, pl.R, x, ld_r, ld_i, out->x, pl.n, 1, st));
+    if (out->m) QPA_HIP(launch_copy_state(pl.n, pl.R, m, ld_r, ld_i, out->m, pl.n, 1, st));
+    return QPA_OK;
+}
+
 qpa_status qpa_solve_noalloc(qpa_ctx *ctx, const qpa_problem *problem, const qpa_params *params,
                              void *stream, const qpa_outputs *out) {
     if (!ctx) return QPA_E_ARG;

@@ -117,6 +117,11 @@ hipError_t launch_energy(const qpa_problem &p, const int64_t *b_i64, const doubl
 // best[0] = lowest r with minimal energy.
 hipError_t launch_argmin(int64_t R, const int64_t *e_i64, const double *e_f64, int32_t *best,
                          hipStream_t st);
+// Per replica: keep the state after `t` steps when its energy is below the best so far
+// (always on the first sample): its spins [R][n], energy and step.
+hipError_t launch_track_best(int64_t n, int64_t R, const double *energy, const int8_t *spins,
+                             int32_t t, bool first, double *best_e, int32_t *best_t,
+                             int8_t *best_s, hipStream_t st);
 
 // Batched scoring of integer CSR instances: one launch per kind for all instances of a
 // table (device memory), with the results of launch_export_spins + launch_energy +

@@ -86,6 +86,13 @@ def qpa_solve_noalloc(ctx, problem, params, stream, outputs):
                                        ctypes.byref(outputs)))
 
 
+def qpa_solve_track(ctx, problem, params, every, workspace, workspace_bytes, stream, outputs,
+                    track):
+    _check(ctx, _lib.qpa_solve_track(ctx, ctypes.byref(problem), ctypes.byref(params), every,
+                                     workspace, workspace_bytes, stream, ctypes.byref(outputs),
+                                     ctypes.byref(track)))
+
+
 def qpa_steps(ctx, problem, params, t0, t1, x, m, h_last, workspace, workspace_bytes, stream):
     _check(ctx, _lib.qpa_steps(ctx, ctypes.byref(problem), ctypes.byref(params), t0, t1, x, m,
                                h_last, workspace, workspace_bytes, stream))
@@ -388,6 +395,38 @@ class Engine:
         else:
             qpa_solve(self.ctx, ps, params, ctypes.c_void_p(ws.data_ptr()), nbytes,
                       self._stream(), o)
+        return out
+
+    def solve_track(self, prob: Problem, params: qpa_params, every: int, want_state=False):
+        """qpa_solve_track: the solve() outputs plus each replica's best sampled state --
+        best_energy [R] f64, best_step [R] int32, best_spins [R,n] int8 (device tensors)."""
+        torch = self.torch
+        dev = "cuda:%d" % self.device
+        R, n = params.replicas, prob.n
+        ps = prob.struct()
+        ws, nbytes = self.workspace(ps, params)
+        out = {"spins": torch.empty((R, n), dtype=torch.int8, device=dev),
+               "energy": torch.empty(R, dtype=torch.float64, device=dev),
+               "best": torch.empty(1, dtype=torch.int32, device=dev),
+               "energy_i64": torch.empty(R, dtype=torch.int64, device=dev),
+               "x": torch.empty((R, n), dtype=torch.float32, device=dev) if want_state else None,
+               "m": torch.empty((R, n), dtype=torch.float32, device=dev) if want_state else None,
+               "best_energy": torch.empty(R, dtype=torch.float64, device=dev),
+               "best_step": torch.empty(R, dtype=torch.int32, device=dev),
+               "best_spins": torch.empty((R, n), dtype=torch.int8, device=dev)}
+        o = qpa_outputs()
+        o.spins = out["spins"].data_ptr()
+        o.energy = out["energy"].data_ptr()
+        o.energy_i64 = out["energy_i64"].data_ptr()
+        o.best = out["best"].data_ptr()
+        o.x = out["x"].data_ptr() if want_state else None
+        o.m = out["m"].data_ptr() if want_state else None
+        tr = qpa_track_outputs()
+        tr.best_energy = out["best_energy"].data_ptr()
+        tr.best_step = out["best_step"].data_ptr()
+        tr.best_spins = out["best_spins"].data_ptr()
+        qpa_solve_track(self.ctx, ps, params, int(every), ctypes.c_void_p(ws.data_ptr()), nbytes,
+                        self._stream(), o, tr)
         return out
 
     def solve_batch(self, probs, params: qpa_params, want_state=False):

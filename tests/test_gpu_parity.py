@@ -353,6 +353,71 @@ def test_csr_float_weights_bit_exact(q, eng, streamed):
     assert np.array_equal(host(out["x"]), x) and np.array_equal(host(out["m"]), m)
 
 
+# ------------------------------------------------------------------ best state over the trajectory
+@pytest.mark.parametrize("case", ["csr_ising", "csr_qubo", "dense_bf16"])
+def test_solve_track_matches_oracle(q, eng, case):
+    """qpa_solve_track: each replica's best sampled state (after every `every` steps and
+    after the last) is the oracle's -- exact integer energies, the step, the spins -- and
+    the final outputs are qpa_solve's."""
+    if case == "csr_ising":
+        inst, R, T, every, prec = gen.chimera_ising(3, seed=12), 20, 120, 10, "fp32"
+    elif case == "csr_qubo":
+        inst, R, T, every, prec = gen.er_qubo(150, 0.1, 100, np.random.default_rng(13)), 70, 90, 7, "fp32"
+    else:
+        inst, R, T, every, prec = gen.dense_int_ising(300, -20, 20, seed=14), 130, 60, 8, "bf16"
+    eta, alpha, lam0, seed = 0.05, 0.8, 3.0, 6
+    prob = q.Problem.from_instance(inst)
+    p = _params(q, R, T, eta, alpha, lam0, seed=seed, prec=prec)
+    say("solve_track %s n=%d R=%d T=%d every=%d" % (case, inst.n, R, T, every))
+    out = eng.solve_track(prob, p, every, want_state=True)
+    ref = eng.solve(prob, p, want_state=True)
+    for key in ("x", "m", "spins", "energy_i64", "best"):
+        assert np.array_equal(host(out[key]), host(ref[key])), key
+    lam = orc.lambda_linear(T, lam0)
+    x, m = orc.pa_init(inst.n, R, seed, np.float32(0.1))
+    if inst.dense is not None:
+        J, b = inst.dense, inst.lin
+        step = lambda x_, m_, t0, t1: orc.pa_steps_dense_int(J, b, x_, m_, t0, t1, lam, eta, alpha)
+        energy = lambda s_: np.array([orc.ising_energy_int(J, b, s_[r]) for r in range(R)])
+    else:
+        c = inst.csr
+        canon = (orc.qubo_to_ising_csr_int(c.rp, c.col, c.w, inst.lin) if inst.kind == "qubo"
+                 else (c.rp, c.col, c.w, inst.lin, 0))
+        step = lambda x_, m_, t0, t1: orc.pa_steps_csr_int(canon[0], canon[1], canon[2],
+                                                           canon[3], x_, m_, t0, t1, lam, eta,
+                                                           alpha)
+        energy = lambda s_: _energies_csr_int(canon, inst.kind, s_)
+    be, bt, bs = orc.track_best(x, m, T, every, step, energy)
+    assert np.array_equal(host(out["best_energy"]), be.astype(np.float64))
+    assert np.array_equal(host(out["best_step"]), bt)
+    assert np.array_equal(host(out["best_spins"]), bs)
+    assert (bt < T).any()                    # some replica's best is not its final state
+
+
+def test_solve_track_argument_errors(q, eng):
+    """every < 1 and missing track outputs are rejected before any work."""
+    import ctypes
+    inst = gen.chimera_ising(2, seed=1)
+    prob = q.Problem.from_instance(inst)
+    p = _params(q, 4, 10, 0.1, 0.8, 2.0)
+    say("solve_track argument errors")
+    for every in (0, -3):
+        with pytest.raises(q.QpaError) as ei:
+            eng.solve_track(prob, p, every)
+        assert ei.value.status == q.QPA_E_ARG, str(ei.value)
+    ps = prob.struct()
+    ws, nbytes = eng.workspace(ps, p)
+    out = eng.solve(prob, p)
+    o = q.qpa_outputs()
+    o.energy = out["energy"].data_ptr()
+    o.best = out["best"].data_ptr()
+    tr = q.qpa_track_outputs()                      # all three outputs missing
+    with pytest.raises(q.QpaError) as ei:
+        q.qpa_solve_track(eng.ctx, ps, p, 5, ctypes.c_void_p(ws.data_ptr()), nbytes,
+                          eng._stream(), o, tr)
+    assert ei.value.status == q.QPA_E_ARG, str(ei.value)
+
+
 # ------------------------------------------------------------------ energies, resume, errors
 def test_energy_entry_point(q, eng):
     import torch

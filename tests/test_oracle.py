@@ -822,3 +822,54 @@ def test_spectrum_invariants_and_ties(orc):
     assert st.tolist() == [[-1, 1], [1, -1], [1, 1]]
     assert E.tolist() == [-2.0, -2.0, 0.0] and cnt.tolist() == [2, 2, 2]
     assert first.tolist() == [1, 2, 0]
+
+
+# ------------------------------------------------------------------ best state over a trajectory
+def _track_setup(orc, seed, R, T):
+    inst = gen.chimera_ising(2, seed=seed)
+    c = inst.csr
+    lam = orc.lambda_linear(T, 2.0)
+    step = lambda x, m, t0, t1: orc.pa_steps_csr_int(c.rp, c.col, c.w, inst.lin, x, m, t0, t1,
+                                                     lam, 0.1, 0.8)
+    energy = lambda s: np.array([orc.ising_energy_csr_int(c.rp, c.col, c.w, inst.lin, s[r])
+                                 for r in range(len(s))], np.int64)
+    x0, m0 = orc.pa_init(inst.n, R, seed + 1, np.float32(0.1))
+    return inst, lam, step, energy, x0, m0
+
+
+def test_track_best_single_segment_is_the_final_state(orc):
+    """One segment (every >= T) samples only the final state: the solve's final energies
+    and spins, at step T."""
+    R, T = 6, 40
+    inst, lam, step, energy, x0, m0 = _track_setup(orc, 3, R, T)
+    c = inst.csr
+    fin = orc.solve_csr_int(c.rp, c.col, c.w, inst.lin, R, T, lam, 0.1, 0.8, 4, np.float32(0.1))
+    for every in (T, T + 5, 10 ** 6):
+        be, bt, bs = orc.track_best(x0.copy(), m0.copy(), T, every, step, energy)
+        assert np.array_equal(be, fin.energy) and (bt == T).all()
+        assert np.array_equal(bs, fin.spins)
+
+
+def test_track_best_is_the_first_minimum_over_the_sampled_history(orc):
+    """Against the whole history recorded one step at a time: per replica the lowest
+    energy among the sampled states (after every `every` steps and after the last), the
+    earliest on ties, with that state's spins; T = 0 samples the initial state."""
+    R, T = 8, 30
+    _, _, step, energy, x0, m0 = _track_setup(orc, 7, R, T)
+    x, m = x0.copy(), m0.copy()
+    hist_s = [np.where(x >= 0, 1, -1).astype(np.int8)]
+    for t in range(1, T + 1):
+        step(x, m, t - 1, t)
+        hist_s.append(np.where(x >= 0, 1, -1).astype(np.int8))
+    hist_e = [energy(s) for s in hist_s]
+    for every in (1, 3, 7):
+        samples = [t for t in range(1, T + 1) if t % every == 0 or t == T]
+        E = np.array([hist_e[t] for t in samples])            # [samples, R]
+        k = E.argmin(axis=0)                                  # first minimum per replica
+        be, bt, bs = orc.track_best(x0.copy(), m0.copy(), T, every, step, energy)
+        assert np.array_equal(be, E[k, np.arange(R)])
+        assert np.array_equal(bt, [samples[k[r]] for r in range(R)])
+        assert np.array_equal(bs, np.array([hist_s[samples[k[r]]][r] for r in range(R)]))
+        assert len(set(bt)) > 1                               # not all at one step
+    be, bt, bs = orc.track_best(x0.copy(), m0.copy(), 0, 5, step, energy)
+    assert np.array_equal(be, hist_e[0]) and (bt == 0).all() and np.array_equal(bs, hist_s[0])
