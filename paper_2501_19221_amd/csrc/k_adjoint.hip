@@ -155,8 +155,9 @@ template <typename T> __device__ __forceinline__ float as_weight(T w) { return (
 // = (block of 64 consecutive rows of one instance, 64-replica chunk c); a workgroup of 16
 // waves takes its items in the order below.  Wave w owns rows 4w .. 4w + 3 of the block
 // (lane = replica) and keeps their running sums; the input vector (x or mu of the
-// instance, the chunk's 64 replicas) goes through LDS 128 columns at a time (two buffers
-// of 32 KiB: the next columns load while these are used), and each row walks its entries
+// instance, the chunk's 64 replicas) goes through LDS 256 columns at a time (one buffer of
+// 64 KiB: a range is staged, then walked; the other workgroup on the compute unit walks
+// while this one stages), and each row walks its entries
 // whose column falls in the staged range, in ascending order, one fused multiply-add per
 // term (the order of the definition), while each staged value serves all 64 rows of the
 // block instead of one gather per entry.  A row's entries come in windows of 64 (lane k =
@@ -164,12 +165,11 @@ template <typename T> __device__ __forceinline__ float as_weight(T w) { return (
 // entries in it is counted from the window at hand; the windows past them (all four rows)
 // are loaded into a second register set before any row is walked, so that they are in
 // flight during the walks, and they are converted only when the next range counts them.
-// The loads are issued without per-lane branches and are younger than the staging loads
-// of the next range, so that the barrier before it waits for the staging only.
+// The loads are issued without per-lane branches.
 typedef __attribute__((address_space(3))) void lds_void;
 constexpr int GR_THREADS = 1024, GR_WAVES = GR_THREADS / 64, GR_RPW = 4;
 constexpr int GR_ROWS = GR_WAVES * GR_RPW;       // 64 rows per block
-constexpr int GR_CW = 128;                       // staged columns per range
+constexpr int GR_CW = 256;                       // staged columns per range
 static_assert(GR_ROWS == 64, "blocks of 64 rows");
 
 typedef const __attribute__((address_space(1))) int32_t *gr_i32;
@@ -183,7 +183,8 @@ template <typename TW, typename TI> struct GrWin {
 };
 
 // Two workgroups per CU (64 KiB of LDS each, 8 waves per SIMD): the walks are bound by
-// the latency of their LDS reads, which the second workgroup's waves hide.
+// the latency of their LDS reads, which the second workgroup's waves hide, as they hide
+// each range's staging.
 template <int MODE, typename TW, typename TI>
 __global__ void __launch_bounds__(GR_THREADS)
     __attribute__((amdgpu_waves_per_eu(8))) k_rel_gather(const RelInst *__restrict__ insts,
@@ -192,7 +193,7 @@ __global__ void __launch_bounds__(GR_THREADS)
     constexpr bool GATHER = MODE != REL_A;
     typedef const __attribute__((address_space(1))) TW *gw_t;
     typedef const __attribute__((address_space(1))) TI *gi_t;
-    __shared__ __attribute__((aligned(16))) float vs[GATHER ? 2 : 1][GATHER ? GR_CW * 64 : 1];
+    __shared__ __attribute__((aligned(16))) float vs[GATHER ? GR_CW * 64 : 1];
     __shared__ double sh[GR_WAVES];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -238,7 +239,7 @@ __global__ void __launch_bounds__(GR_THREADS)
                 // wave's destinations are contiguous.  Addresses are the range's uniform
                 // base plus 32-bit offsets.
                 const uint32_t rp4 = (uint32_t)a.Rp;
-                auto stage = [&](int q, int buf) {
+                auto stage = [&](int q) {
                     const float *vq = v + (int64_t)q * GR_CW * a.Rp;
                     const uint32_t lim =
                         (uint32_t)min((int64_t)GR_CW - 1, n - 1 - (int64_t)q * GR_CW);
@@ -247,11 +248,8 @@ __global__ void __launch_bounds__(GR_THREADS)
                         const uint32_t e = 1024u * u + threadIdx.x;
                         const uint32_t o = __umul24(min(e >> 4, lim), rp4) + 4u * (e & 15u);
                         __builtin_amdgcn_global_load_lds(
-                            vq + o, (lds_void *)(&vs[buf][0] + 4 * (1024 * u + 64 * wv)), 16, 0,
-                            0);
+                            vq + o, (lds_void *)(vs + 4 * (1024 * u + 64 * wv)), 16, 0, 0);
                     }
-                    // the window loads that follow stay younger than these
-                    asm volatile("" ::: "memory");
                 };
                 int32_t kc[GR_RPW], ke[GR_RPW];
 #pragma unroll
@@ -363,15 +361,14 @@ __global__ void __launch_bounds__(GR_THREADS)
                 GrWin<TW, TI> A, B;
 #pragma unroll
                 for (int u = 0; u < GR_RPW; ++u) load(A, u);
-                stage(0, 0);
-                asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
                 // range q: load Y (the windows past this range's entries of every row),
                 // then walk X (the windows at the cursors before)
                 auto range = [&](int q, GrWin<TW, TI> &X, GrWin<TW, TI> &Y) {
-                    // every wave's staging of q has landed (the 8 window loads since are
-                    // younger), and every wave is done with the buffer q + 1 takes
-                    if (q > 0)
-                        asm volatile("s_waitcnt vmcnt(8) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+                    // every wave is done with range q - 1, then the buffer takes range q
+                    // and every wave's part has landed
+                    if (q > 0) asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+                    stage(q);
+                    asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
                     const int32_t base = q * GR_CW, bound = base + GR_CW;
                     int32_t jl[GR_RPW];
                     float wl[GR_RPW];
@@ -382,8 +379,7 @@ __global__ void __launch_bounds__(GR_THREADS)
                         wl[u] = weights(X, u);
                         cnt[u] = __popcll(__ballot(jl[u] < bound));
                     }
-                    if (q + 1 < nq) stage(q + 1, (q + 1) & 1);
-                    const float *src = &vs[q & 1][0] + lane;
+                    const float *src = vs + lane;
 #pragma unroll
                     for (int u = 0; u < GR_RPW; ++u) {
                         kc[u] += cnt[u];
