@@ -304,32 +304,51 @@ __global__ void __launch_bounds__(GR_THREADS)
                 // so that one read of the window word gives both (the column on the scalar
                 // unit, the weight as it is).
                 constexpr bool PACK = std::is_integral<TW>::value && sizeof(TW) <= 2;
-                auto pack = [&](int32_t jl, float wl, int32_t base) {
+                // Two forms of the word: 8-bit weights' floats have their low 16 bits zero
+                // too, which then carry the column's byte offset in the staged range as it is
+                // (one AND on the scalar unit instead of a shift and an AND); other 8- or
+                // 16-bit weights carry the column index in their low 8 bits.  W16 (a
+                // compile-time tag) selects the form.
+                auto pack = [&](int32_t jl, float wl, int32_t base, auto w16) {
+                    if (decltype(w16)::value)
+                        return (__float_as_int(wl) & (int32_t)0xFFFF0000) |
+                               (((jl - base) & 0xFF) << 8);
                     return (__float_as_int(wl) & ~0xFF) | ((jl - base) & 0xFF);
                 };
-                auto walkp = [&](int32_t pk, int u, int e, int cnt, const float *src) {
+                auto offs = [](int32_t p, auto w16) -> int32_t {
+                    return decltype(w16)::value ? (p & 0xFF00) : ((p & 0xFF) << 8);
+                };
+                auto wgt = [](int32_t p, auto w16) -> float {
+                    return __int_as_float(decltype(w16)::value ? (p & (int32_t)0xFFFF0000)
+                                                               : (p & ~0xFF));
+                };
+                // the staged value of a word's column for this lane's replica
+                auto val = [&](const float *src, int32_t p, auto w16) {
+                    return *reinterpret_cast<const float *>(
+                        reinterpret_cast<const char *>(src) + offs(p, w16));
+                };
+                auto walkp = [&](int32_t pk, int u, int e, int cnt, const float *src, auto w16) {
                     for (; e + 4 <= cnt; e += 4) {
                         const int32_t p0 = __builtin_amdgcn_readlane(pk, e);
                         const int32_t p1 = __builtin_amdgcn_readlane(pk, e + 1);
                         const int32_t p2 = __builtin_amdgcn_readlane(pk, e + 2);
                         const int32_t p3 = __builtin_amdgcn_readlane(pk, e + 3);
-                        const float v0 = src[64 * (p0 & 0xFF)], v1 = src[64 * (p1 & 0xFF)];
-                        const float v2 = src[64 * (p2 & 0xFF)], v3 = src[64 * (p3 & 0xFF)];
-                        acc[u] = __fmaf_rn(__int_as_float(p0 & ~0xFF), v0, acc[u]);
-                        acc[u] = __fmaf_rn(__int_as_float(p1 & ~0xFF), v1, acc[u]);
-                        acc[u] = __fmaf_rn(__int_as_float(p2 & ~0xFF), v2, acc[u]);
-                        acc[u] = __fmaf_rn(__int_as_float(p3 & ~0xFF), v3, acc[u]);
+                        const float v0 = val(src, p0, w16), v1 = val(src, p1, w16);
+                        const float v2 = val(src, p2, w16), v3 = val(src, p3, w16);
+                        acc[u] = __fmaf_rn(wgt(p0, w16), v0, acc[u]);
+                        acc[u] = __fmaf_rn(wgt(p1, w16), v1, acc[u]);
+                        acc[u] = __fmaf_rn(wgt(p2, w16), v2, acc[u]);
+                        acc[u] = __fmaf_rn(wgt(p3, w16), v3, acc[u]);
                     }
                     for (; e < cnt; ++e) {
                         const int32_t p = __builtin_amdgcn_readlane(pk, e);
-                        acc[u] = __fmaf_rn(__int_as_float(p & ~0xFF), src[64 * (p & 0xFF)],
-                                           acc[u]);
+                        acc[u] = __fmaf_rn(wgt(p, w16), val(src, p, w16), acc[u]);
                     }
                 };
                 // rows u and u + 1 together over their common first entries (eight reads in
                 // flight, two independent sums), then each alone
                 auto walkp2 = [&](int32_t pa, int32_t pb, int u, int ca, int cb,
-                                  const float *src) {
+                                  const float *src, auto w16) {
                     const int cm = min(ca, cb);
                     int e = 0;
                     for (; e + 4 <= cm; e += 4) {
@@ -341,20 +360,20 @@ __global__ void __launch_bounds__(GR_THREADS)
                         }
                         float vv[8];
 #pragma unroll
-                        for (int k = 0; k < 8; ++k) vv[k] = src[64 * (p[k] & 0xFF)];
+                        for (int k = 0; k < 8; ++k) vv[k] = val(src, p[k], w16);
 #pragma unroll
                         for (int k = 0; k < 4; ++k) {
-                            acc[u] = __fmaf_rn(__int_as_float(p[k] & ~0xFF), vv[k], acc[u]);
-                            acc[u + 1] =
-                                __fmaf_rn(__int_as_float(p[4 + k] & ~0xFF), vv[4 + k], acc[u + 1]);
+                            acc[u] = __fmaf_rn(wgt(p[k], w16), vv[k], acc[u]);
+                            acc[u + 1] = __fmaf_rn(wgt(p[4 + k], w16), vv[4 + k], acc[u + 1]);
                         }
                     }
-                    walkp(pa, u, e, ca, src);
-                    walkp(pb, u + 1, e, cb, src);
+                    walkp(pa, u, e, ca, src, w16);
+                    walkp(pb, u + 1, e, cb, src, w16);
                 };
                 auto walk_any = [&](int32_t jl, float wl, int u, int cnt, int32_t base,
                                     const float *src) {
-                    if (PACK) walkp(pack(jl, wl, base), u, 0, cnt, src);
+                    if (PACK) walkp(pack(jl, wl, base, std::false_type{}), u, 0, cnt, src,
+                                    std::false_type{});
                     else walk(jl, wl, u, cnt, base, src);
                 };
                 const int nq = (int)((n + GR_CW - 1) / GR_CW);
@@ -386,10 +405,25 @@ __global__ void __launch_bounds__(GR_THREADS)
                         load(Y, u);
                     }
                     if (PACK) {
+                        // the 16-bit form when every weight of the four windows fits it
+                        bool w16 = true;
 #pragma unroll
-                        for (int u = 0; u < GR_RPW; u += 2)
-                            walkp2(pack(jl[u], wl[u], base), pack(jl[u + 1], wl[u + 1], base), u,
-                                   cnt[u], cnt[u + 1], src);
+                        for (int u = 0; u < GR_RPW; ++u)
+                            w16 = w16 && __ballot(kc[u] - cnt[u] + lane < ke[u] &&
+                                                  fabsf(wl[u]) > 255.0f) == 0;
+                        if (w16) {
+#pragma unroll
+                            for (int u = 0; u < GR_RPW; u += 2)
+                                walkp2(pack(jl[u], wl[u], base, std::true_type{}),
+                                       pack(jl[u + 1], wl[u + 1], base, std::true_type{}), u,
+                                       cnt[u], cnt[u + 1], src, std::true_type{});
+                        } else {
+#pragma unroll
+                            for (int u = 0; u < GR_RPW; u += 2)
+                                walkp2(pack(jl[u], wl[u], base, std::false_type{}),
+                                       pack(jl[u + 1], wl[u + 1], base, std::false_type{}), u,
+                                       cnt[u], cnt[u + 1], src, std::false_type{});
+                        }
                     }
 #pragma unroll
                     for (int u = 0; u < GR_RPW; ++u) {

@@ -194,6 +194,21 @@ def test_two_replica_chunks_with_int16_and_int8_weights(q, eng):
     _compare("R=100, int16 + int8", got, ref)
 
 
+def test_wide_int16_weights_against_oracle(q, eng):
+    """int16 weights up to 1000 (windows holding weights above 255 take the packed form
+    with an 8-bit column index) next to a narrow-weight instance, 40 replicas."""
+    insts = [gen.er_qubo(400, 0.1, 1000, np.random.default_rng(51)),
+             gen.er_qubo(260, 0.1, 100, np.random.default_rng(52))]
+    R, seed = 40, 17
+    norm = 1.0 / (R * len(insts))
+    with ThreadPoolExecutor(len(insts)) as ex:
+        futs = [ex.submit(_oracle, inst, R, seed + k, norm) for k, inst in enumerate(insts)]
+        say("int16 weights up to 1000 next to narrow ones, R=%d" % R)
+        got = _gpu(q, eng, [q.Problem.from_instance(i) for i in insts], _params(q, R, seed))
+        ref = _sum([f.result() for f in futs])
+    _compare("wide int16 weights", got, ref, nontrivial=False)
+
+
 def test_checkpoint_interval_and_forward_only(q, eng):
     """Bitwise the same loss and gradients for every checkpoint interval; the forward-only
     call returns the same loss bits."""
