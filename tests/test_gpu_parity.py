@@ -628,6 +628,41 @@ def test_batch_float_couplings_on_the_sparse_kernel(q, eng):
         assert np.array_equal(host(out["m"]), m), k
 
 
+def _with_diagonal(inst, rng, lo=-20, hi=20):
+    """The CSR QUBO with Q_ii drawn in [lo, hi] stored as entries (App. A folds them into b)."""
+    c, n = inst.csr, inst.n
+    d = c.to_dense(np.int32)
+    d[np.arange(n), np.arange(n)] = rng.integers(lo, hi + 1, n)
+    rows, cols = np.nonzero(d)
+    rp = np.zeros(n + 1, np.int64)
+    np.cumsum(np.bincount(rows, minlength=n), out=rp[1:])
+    inst.csr = gen.CSR(n, rp.astype(np.int32), cols.astype(c.col.dtype),
+                       d[rows, cols].astype(c.w.dtype))
+    return inst
+
+
+def test_batch_sparse_kernel_with_stored_diagonals(q, eng):
+    """QUBOs with stored diagonal entries on the sparse task kernel (the diagonal adds
+    nothing to the field there: it is folded into b), a full and a partial replica group:
+    the oracle's bits."""
+    rng = np.random.default_rng(61)
+    insts = [_with_diagonal(gen.er_qubo(int(n), 0.1, 100, rng), rng) for n in (90, 333)]
+    insts.append(_with_diagonal(gen.er_qubo(150, 0.05, 100, rng, idx_dtype=np.int32), rng))
+    R, T, eta, alpha, lam0 = 70, 50, 0.0002, 0.8, 200.0
+    probs = [q.Problem.from_instance(i) for i in insts]
+    p = _params(q, R, T, eta, alpha, lam0, seed=31, flags=q.QPA_BATCH_SPARSE)
+    say("batch with stored diagonals on the sparse kernel, R=%d T=%d" % (R, T))
+    outs = eng.solve_batch(probs, p, want_state=True)
+    assert (q.qpa_batch_paths(eng.ctx, len(insts)) == q.QPA_PATH_BATCH_SPARSE).all()
+    lam = orc.lambda_linear(T, lam0)
+    for k, (inst, out) in enumerate(zip(insts, outs)):
+        x, m, canon = _oracle_instance(inst, R, T, lam, eta, alpha, seed=31 + k)
+        assert np.array_equal(host(out["x"]), x), k
+        assert np.array_equal(host(out["m"]), m), k
+        s = np.where(x >= 0, 1, -1).astype(np.int8)
+        assert np.array_equal(host(out["energy_i64"]), _energies_csr_int(canon, "qubo", s)), k
+
+
 def test_batch_autotune_measures_rates_and_chooses_by_them(q, eng):
     """qpa_autotune_batch measures both paths on the device; afterwards every instance
     takes the path the cost model gives with the measured rates (dense when BF16-exact and
