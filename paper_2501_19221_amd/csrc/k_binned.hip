@@ -326,6 +326,8 @@ __global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(8))) k_
     __syncthreads();
     // fused update of the bin's (row, replica) pairs; state index = row * G + replica.
     // UQ pairs per thread per round: every load of a round is issued before its stores.
+    // x and m stream through once per step (gigabytes, far beyond the caches): their
+    // loads and stores are non-temporal, leaving the caches to the entry records.
     constexpr int UQ = 4;
     static_assert((BIN_WORDS / BT) % UQ == 0, "rounds must cover the bin exactly");
     const int64_t q0 = bin * SUMS;
@@ -341,8 +343,8 @@ __global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(8))) k_
             xv[u] = mv[u] = 0.0f;
             cr[u] = 0;
             if (live[u]) {
-                xv[u] = x[gi];
-                mv[u] = m[gi];
+                xv[u] = __builtin_nontemporal_load(&x[gi]);
+                mv[u] = __builtin_nontemporal_load(&m[gi]);
                 cr[u] = crow[gi >> shiftG];
             }
         }
@@ -355,8 +357,8 @@ __global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(8))) k_
                 const int32_t A = (int32_t)((acc[q / L] >> (LW * (q % L))) & LMASK);
                 const float h = (float)(cr[u] - 2 * A);
                 pa_update(h, lt, eta, alpha, xv[u], mv[u]);
-                x[gi] = xv[u];
-                m[gi] = mv[u];
+                __builtin_nontemporal_store(xv[u], &x[gi]);
+                __builtin_nontemporal_store(mv[u], &m[gi]);
                 if (h_last) h_last[gi] = h;
                 neg = xv[u] < 0.0f;
             }
