@@ -632,7 +632,8 @@ struct StateRegs8 {
 };
 
 // x, m of rows 2e + t / 256, E0 <= e < E1, of this thread (rows at or past rlive are not
-// read).
+// read).  The state of a batch step (all instances', with the couplings and spins far more
+// than the caches hold between steps) is read and written non-temporally.
 template <int E0, int E1>
 __device__ __forceinline__ void xm_load8(StateRegs8 &st, const Tile &tl, int t) {
     const int col = t & (BN8 - 1);
@@ -642,8 +643,8 @@ __device__ __forceinline__ void xm_load8(StateRegs8 &st, const Tile &tl, int t) 
 #pragma unroll
     for (int e = E0; e < E1; ++e) {
         const bool live = tl.R0 + 2 * e + rsub < tl.rlive;
-        st.xv[e] = live ? xr[col] : 0.0f;
-        st.mv[e] = live ? mr[col] : 0.0f;
+        st.xv[e] = live ? __builtin_nontemporal_load(&xr[col]) : 0.0f;
+        st.mv[e] = live ? __builtin_nontemporal_load(&mr[col]) : 0.0f;
         xr = next_rows(xr, 2 * tl.np);
         mr = next_rows(mr, 2 * tl.np);
     }
@@ -752,8 +753,8 @@ __device__ __forceinline__ void tile8_step(uint8_t *lds, const Tile &tl,
                 const float h = __fadd_rn((float)hv[u], st.bi);
                 pa_update(h, lt, eta, alpha, st.xv[e], st.mv[e]);
                 srow[(int64_t)2 * e * KC] = st.xv[e] < 0.0f ? (uint8_t)0xFF : (uint8_t)0x01;
-                xr[(int64_t)2 * e * tl.np] = st.xv[e];
-                mr[(int64_t)2 * e * tl.np] = st.mv[e];
+                __builtin_nontemporal_store(st.xv[e], &xr[(int64_t)2 * e * tl.np]);
+                __builtin_nontemporal_store(st.mv[e], &mr[(int64_t)2 * e * tl.np]);
             }
         }
     }
