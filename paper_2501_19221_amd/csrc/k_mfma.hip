@@ -273,7 +273,9 @@ struct StateRegs {
 // few elements before each), so that this traffic shares the memory system with the
 // chunk loads instead of delaying the first chunks.  Rows past rlive are padding: they
 // are not read and take zeros.  Row pointers are wave-uniform, so that each load is a
-// scalar base plus the lane's column.  Executes nchunk barriers.
+// scalar base plus the lane's column.  Executes nchunk barriers.  NTL: non-temporal loads
+// (the grouped batch step).
+template <bool NTL>
 __device__ __forceinline__ void state_load(StateRegs &st, const Tile &tl, int nchunk, int t) {
     const int col = t & (BN - 1);
     const int rsub = __builtin_amdgcn_readfirstlane(t >> 7);
@@ -289,8 +291,8 @@ __device__ __forceinline__ void state_load(StateRegs &st, const Tile &tl, int nc
         }
         // padding rows (uniform per wave) are not read: they start from zero each step
         const bool live = tl.R0 + 4 * e + rsub < tl.rlive;
-        st.xv[e] = live ? xr[col] : 0.0f;
-        st.mv[e] = live ? mr[col] : 0.0f;
+        st.xv[e] = live ? (NTL ? __builtin_nontemporal_load(&xr[col]) : xr[col]) : 0.0f;
+        st.mv[e] = live ? (NTL ? __builtin_nontemporal_load(&mr[col]) : mr[col]) : 0.0f;
         xr = next_rows(xr, 4 * tl.np);
         mr = next_rows(mr, 4 * tl.np);
     }
@@ -371,8 +373,9 @@ __device__ __forceinline__ void state_update(StateRegs &st, const Tile &tl, cons
     }
 }
 
-// NT: non-temporal stores (measured: 1.6 % faster for the single-instance step, 1.5 %
-// slower for the grouped batch step, whose next step finds more of x, m in the caches).
+// NT: non-temporal stores.  Measured: 1.6 % faster for the single-instance step; for the
+// grouped batch step (a batch's state, couplings and spins are more than the caches hold
+// between steps) non-temporal stores and loads (NTL in state_load) together 6 % faster.
 template <bool NT>
 __device__ __forceinline__ void state_store(const StateRegs &st, const Tile &tl, int t) {
     const int col = t & (BN - 1);
@@ -396,7 +399,7 @@ __device__ __forceinline__ void state_store(const StateRegs &st, const Tile &tl,
 }
 
 // One PA step of one BF16 tile: matrix and state waves side by side.
-template <bool NT>
+template <bool NT, bool NTL = false>
 __device__ __forceinline__ void mfma_tile_step(uint8_t *lds, const Tile &tl,
                                                const uint32_t *__restrict__ s_cur,
                                                uint32_t *__restrict__ s_nxt,
@@ -408,7 +411,7 @@ __device__ __forceinline__ void mfma_tile_step(uint8_t *lds, const Tile &tl,
     if (wave >= MW) {
         const int t = tid - MW * 64;
         StateRegs st;
-        state_load(st, tl, nchunk, t);
+        state_load<NTL>(st, tl, nchunk, t);
         barrier();                                     // stages drained
         barrier();                                     // partial sums stored
         state_collect(st);
@@ -443,7 +446,7 @@ __global__ void __launch_bounds__(THREADS, 1) k_mfma_grouped(const MfmaTile *__r
     const uint32_t *cur = (t & 1) ? mt.s1 : mt.s0;
     uint32_t *nxt = (t & 1) ? mt.s0 : mt.s1;
     const Tile tl{mt.np, mt.Rp, mt.I0, mt.R0, mt.rlive, mt.Jb, mt.b, mt.sc->scale, mt.x, mt.m};
-    mfma_tile_step<false>(lds, tl, cur, nxt, nullptr, lam[t], eta, alpha);
+    mfma_tile_step<true, true>(lds, tl, cur, nxt, nullptr, lam[t], eta, alpha);
 }
 
 // ---- int8 tiles of a batch: 64 replicas x 256 variables ---------------------------------
