@@ -2147,6 +2147,38 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
     if (ce != hipSuccess) return fail(ctx, QPA_E_DEVICE, "task upload: %s", hipGetErrorString(ce));
 
     const float *dlam = reinterpret_cast<const float *>(ws + bp.o_lam);
+    // The sparse task kernel (a few workgroups for all steps, instances disjoint from the
+    // tiles') runs beside the grouped tile launches: forked onto an auxiliary stream before
+    // the step loop and joined back before the scoring.
+    const bool beside = !tasks.empty() && !tiles.empty() && params->steps > 0;
+    AuxGuard gt{ctx, st, beside};
+    if (beside) {
+        s = aux_fork(ctx, st);
+        if (s != QPA_OK) return s;
+    }
+    if (!tasks.empty()) {
+        hipStream_t ts = beside ? ctx->aux[0] : st;
+        int cus = 0;
+        QPA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+        const int32_t ntask = (int32_t)tasks.size();
+        const int32_t blocks = (int32_t)std::min<int64_t>(ntask, (int64_t)cus * 4);
+        qpa_ctx::Span sp{};
+        if (ctx->prof) {
+            QPA_HIP(take_event(ctx, &sp.a));
+            QPA_HIP(take_event(ctx, &sp.b));
+            QPA_HIP(hipEventRecord(sp.a, ts));
+        }
+        QPA_HIP(launch_csr_batch(reinterpret_cast<const BatchTask *>(ws + bp.o_tasks), ntask,
+                                 reinterpret_cast<int32_t *>(ws + bp.o_counter), blocks,
+                                 params->steps, dlam, params->eta, params->alpha, params->sigma0,
+                                 bp.max_n, ts));
+        if (ctx->prof) {
+            QPA_HIP(hipEventRecord(sp.b, ts));
+            sp.launches = 1;
+            sp.path = QPA_PATH_BATCH_SPARSE;
+            ctx->spans.push_back(sp);
+        }
+    }
     if (!tiles.empty() && params->steps > 0) {
         qpa_ctx::Span sp{};
         if (ctx->prof) {
@@ -2192,27 +2224,9 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
             ctx->spans.push_back(sp);
         }
     }
-    if (!tasks.empty()) {
-        int cus = 0;
-        QPA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
-        const int32_t ntask = (int32_t)tasks.size();
-        const int32_t blocks = (int32_t)std::min<int64_t>(ntask, (int64_t)cus * 4);
-        qpa_ctx::Span sp{};
-        if (ctx->prof) {
-            QPA_HIP(take_event(ctx, &sp.a));
-            QPA_HIP(take_event(ctx, &sp.b));
-            QPA_HIP(hipEventRecord(sp.a, st));
-        }
-        QPA_HIP(launch_csr_batch(reinterpret_cast<const BatchTask *>(ws + bp.o_tasks), ntask,
-                                 reinterpret_cast<int32_t *>(ws + bp.o_counter), blocks,
-                                 params->steps, dlam, params->eta, params->alpha, params->sigma0,
-                                 bp.max_n, st));
-        if (ctx->prof) {
-            QPA_HIP(hipEventRecord(sp.b, st));
-            sp.launches = 1;
-            sp.path = QPA_PATH_BATCH_SPARSE;
-            ctx->spans.push_back(sp);
-        }
+    if (beside) {
+        s = gt.close();
+        if (s != QPA_OK) return s;
     }
 
     // per instance: spins, optional state, exact energies, best replica (instances spread
