@@ -22,6 +22,8 @@ struct qpa_ctx {
     qpa::CanonScalars *host_sc = nullptr;   // pinned
     float *host_lam = nullptr;              // pinned schedule staging
     size_t host_lam_cap = 0;
+    char *host_stage = nullptr;             // pinned, the batch solve's table uploads and
+    size_t host_stage_cap = 0;              // read-backs (grown, kept until qpa_destroy)
     void *noalloc_ws = nullptr;             // device address of this device's static workspace
     // step-kernel timing (qpa_profile_*)
     bool prof = false;
@@ -319,6 +321,23 @@ qpa_status check_batch_params(qpa_ctx *ctx, const qpa_params *a) {
 
 template <typename T> T *at(void *ws, size_t off) {
     return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
+}
+
+// The context's pinned staging block, at least `bytes` long.  Callers synchronise the
+// stream a copy from or into it was issued on before they return, so every call finds it
+// idle.
+qpa_status host_stage(qpa_ctx *ctx, size_t bytes, char **out) {
+    bytes = std::max<size_t>(bytes, 16);
+    if (ctx->host_stage_cap < bytes) {
+        const size_t cap = std::max(bytes, 2 * ctx->host_stage_cap);
+        if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
+        ctx->host_stage = nullptr;
+        ctx->host_stage_cap = 0;
+        QPA_HIP(hipHostMalloc((void **)&ctx->host_stage, cap));
+        ctx->host_stage_cap = cap;
+    }
+    *out = ctx->host_stage;
+    return QPA_OK;
 }
 
 // Schedule table (host, FP32, rounded as written) -> pinned staging -> workspace.
@@ -1105,6 +1124,7 @@ void qpa_destroy(qpa_ctx *ctx) {
     if (ctx->host_sc) (void)hipHostFree(ctx->host_sc);
     if (ctx->host_flags) (void)hipHostFree(ctx->host_flags);
     if (ctx->host_lam) (void)hipHostFree(ctx->host_lam);
+    if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
     for (auto &sp : ctx->spans) {
         (void)hipEventDestroy(sp.a);
         (void)hipEventDestroy(sp.b);
@@ -1765,16 +1785,15 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
             if (g.count) cgroups.push_back(g);
         }
     // one pinned block: the scalars' read-back, then the table
-    CanonScalars *pinned = nullptr;
     const size_t cbytes = sizeof(CanonTask) * ctasks.size();
-    QPA_HIP(hipHostMalloc((void **)&pinned, sizeof(CanonScalars) * (size_t)count + cbytes));
+    char *stage = nullptr;
+    s = host_stage(ctx, sizeof(CanonScalars) * (size_t)count + cbytes, &stage);
+    if (s != QPA_OK) return s;
+    CanonScalars *pinned = reinterpret_cast<CanonScalars *>(stage);
     CanonTask *ptab = reinterpret_cast<CanonTask *>(pinned + count);
     std::copy(ctasks.begin(), ctasks.end(), ptab);
     s = aux_fork(ctx, st);
-    if (s != QPA_OK) {
-        (void)hipHostFree(pinned);
-        return s;
-    }
+    if (s != QPA_OK) return s;
     AuxGuard g0{ctx, st};
     if (!ctasks.empty()) {
         const CanonTask *dt = reinterpret_cast<const CanonTask *>(ws + bp.o_canon);
@@ -1803,12 +1822,8 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
                             hipMemcpyDeviceToHost, st);
     const hipError_t se2 = hipStreamSynchronize(st);
     if (se == hipSuccess) se = se2;
-    if (s != QPA_OK) {
-        (void)hipHostFree(pinned);
-        return s;
-    }
+    if (s != QPA_OK) return s;
     for (int32_t k = 0; k < count; ++k) hsc[k] = pinned[k];
-    (void)hipHostFree(pinned);
     if (se != hipSuccess)
         return fail(ctx, QPA_E_DEVICE, "synchronise failed: %s", hipGetErrorString(se));
     for (int32_t k = 0; k < count; ++k) {
@@ -2131,7 +2146,8 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
     const size_t lbytes = sizeof(MfmaTile) * tiles.size();
     const size_t sbytes = sizeof(ScoreTask) * stasks.size();
     char *hbuf = nullptr;
-    QPA_HIP(hipHostMalloc((void **)&hbuf, std::max<size_t>(tbytes + lbytes + sbytes, 16)));
+    s = host_stage(ctx, tbytes + lbytes + sbytes, &hbuf);
+    if (s != QPA_OK) return s;
     std::copy(tasks.begin(), tasks.end(), reinterpret_cast<BatchTask *>(hbuf));
     std::copy(tiles.begin(), tiles.end(), reinterpret_cast<MfmaTile *>(hbuf + tbytes));
     std::copy(stasks.begin(), stasks.end(), reinterpret_cast<ScoreTask *>(hbuf + tbytes + lbytes));
@@ -2142,8 +2158,8 @@ qpa_status qpa_solve_batch(qpa_ctx *ctx, int32_t count, const qpa_problem *probl
     if (ce == hipSuccess && sbytes)
         ce = hipMemcpyAsync(ws + bp.o_score, hbuf + tbytes + lbytes, sbytes,
                             hipMemcpyHostToDevice, st);
-    if (ce == hipSuccess) ce = hipStreamSynchronize(st);
-    (void)hipHostFree(hbuf);
+    const hipError_t ce2 = hipStreamSynchronize(st);     // the staging block is idle again
+    if (ce == hipSuccess) ce = ce2;
     if (ce != hipSuccess) return fail(ctx, QPA_E_DEVICE, "task upload: %s", hipGetErrorString(ce));
 
     const float *dlam = reinterpret_cast<const float *>(ws + bp.o_lam);
