@@ -237,6 +237,8 @@ qpa_status qpa_solve_track(qpa_ctx *ctx, const qpa_problem *problem,
  *    PA step is one grouped matrix-core launch per kind over the tiles of all such
  *    instances (BF16: 128 replicas x 128 variables; int8: 64 x 256).  Integer instances
  *    give the same bits on every path.
+ * When a batch uses both paths, the sparse launch runs on an auxiliary stream beside the
+ * dense step loop (disjoint instances) and is joined back before the scoring.
  * Set-up and scoring run on the context's auxiliary streams (ordered after `stream` and
  * joined back into it before the call returns), the per-instance parts issued from up to
  * four host threads of the call's own, the densified integer instances' parts as batched
