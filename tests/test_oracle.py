@@ -758,6 +758,18 @@ def test_power_method_matches_eigvalsh(orc):
         assert orc.spectral_radius_power(M, 3000, 1) == pytest.approx(rho, rel=1e-6)
 
 
+def test_power_start_vector_is_the_first_replicas_draw(orc):
+    """The power method starts from 2u - 1 with u the top 24 bits of SplitMix64 outputs
+    1..n, the same draw as replica 0's initial state at sigma0 = 1 (float64 here, FP32
+    there; 2u - 1 is exact in both); every entry lies in [-1, 1) on the 2^-23 grid."""
+    for n, seed in ((1, 0), (37, 5), (1000, 2**64 - 1)):
+        v = orc.power_start_vector(n, seed)
+        x, _ = orc.pa_init(n, 1, seed, 1.0)
+        np.testing.assert_array_equal(v, x[0].astype(np.float64))
+        assert np.all(v >= -1.0) and np.all(v < 1.0)
+        assert np.array_equal(v * 2.0**23, np.round(v * 2.0**23))
+
+
 def test_sbm_field_terms_are_fused_multiply_adds(orc):
     """The SBM field sums J_ij q_j with one rounding per term (fused multiply-add), in
     ascending j: with J_01 = -1, J_02 = 1 + 2^-12 and q = (0, 1, 1 + 2^-12) the exact
