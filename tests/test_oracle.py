@@ -407,6 +407,41 @@ def test_csr_and_dense_trajectories_identical(orc):
     assert np.array_equal(x1, x3)
 
 
+def test_float_csr_steps_equal_dense_float_steps(orc):
+    """Float couplings: the CSR and dense PA steps sum the same nonzero terms in ascending
+    column order (the dense one adds signed zeros besides, which change no sum), so their
+    states agree bit for bit; a reordered or regrouped sum, or a bias added first, would not."""
+    rng = np.random.default_rng(11)
+    n, R, T = 50, 5, 40
+    J = rng.normal(size=(n, n)).astype(np.float32)
+    J = np.triu(J, 1) * (rng.random((n, n)) < 0.2)
+    J = (J + J.T).astype(np.float32)
+    b = rng.normal(scale=0.3, size=n).astype(np.float32)
+    rows, cols = np.nonzero(J)
+    rp = np.zeros(n + 1, np.int64)
+    np.add.at(rp, rows + 1, 1)
+    rp = np.cumsum(rp)
+    lam = orc.lambda_linear(T, 2.0)
+    x1, m1 = orc.pa_init(n, R, 7, np.float32(0.1))
+    x2, m2 = x1.copy(), m1.copy()
+    h1 = orc.pa_steps_dense_float(J, b, x1, m1, 0, T, lam, 0.05, 0.8, want_h=True)
+    h2 = orc.pa_steps_csr_float(rp, cols.astype(np.int32), J[rows, cols], b, x2, m2, 0, T,
+                                lam, 0.05, 0.8, want_h=True)
+    assert np.array_equal(h1, h2) and np.array_equal(x1, x2) and np.array_equal(m1, m2)
+    # one more step: its field is the FP32 sum of the nonzero terms in ascending column
+    # order, then the bias, written out here term by term
+    sp = np.where(x1 >= 0, np.float32(1), np.float32(-1))
+    lam1 = np.array([0.5], np.float32)
+    h3 = orc.pa_steps_csr_float(rp, cols.astype(np.int32), J[rows, cols], b, x2, m2, 0, 1,
+                                lam1, 0.05, 0.8, want_h=True)
+    for r in range(R):
+        for i in range(n):
+            acc = np.float32(0.0)
+            for j in np.nonzero(J[i])[0]:
+                acc = np.float32(acc + np.float32(J[i, j] * sp[r, j]))
+            assert h3[r, i] == np.float32(acc + b[i])
+
+
 def test_step_rows_matches_full_step(orc):
     inst = gen.planted_3regular(200, seed=4)
     c = inst.csr
