@@ -78,6 +78,25 @@ def test_app_a_identity_by_enumeration(orc, seed):
         assert 2 * E == H + K
 
 
+def test_app_a_identity_float_by_enumeration(orc):
+    """The float canonicalisation keeps 2 E(x) = H(s) + K for real couplings: E = x^T Q x +
+    c^T x and H = sum_{i<j} J_ij s_i s_j + b^T s evaluated here with numpy in float64, for
+    all 2^8 states of a symmetric Q with a nonzero diagonal."""
+    rng = np.random.default_rng(4)
+    n = 8
+    Q = rng.normal(size=(n, n))
+    Q = (Q + Q.T) / 2
+    c = rng.normal(size=n)
+    J, b, K = orc.qubo_to_ising_float(Q, c)
+    assert np.all(np.diag(J) == 0) and np.allclose(J, J.T)
+    for s in _all_states(n):
+        sf = s.astype(np.float64)
+        x = (sf + 1) / 2
+        E = x @ Q @ x + c @ x
+        H = sum(J[i, j] * sf[i] * sf[j] for i in range(n) for j in range(i + 1, n)) + b @ sf
+        assert 2 * E == pytest.approx(H + K, abs=1e-9)
+
+
 def test_app_a_printed_constant_sign(orc):
     """App. A with c = 0: h_i = sum_j Q_ij, J = offdiag(Q), C = sum_{i<j} Q_ij + tr Q.
     Enumeration shows Q(x) = H/2 + C/2; the printed relation has -C/2."""
