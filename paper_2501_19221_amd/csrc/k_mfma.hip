@@ -593,10 +593,13 @@ __device__ __forceinline__ void entries_load(EntryRegs &er, const Tile &tl, int 
     er.cnt = O[blk + 1] - beg;
     // an empty block reads the word at its start, which lies inside the coupling buffer
     // (the entries end at least a quarter of the buffer before its end); it is not placed
+    // each block is read once per step and a batch's lists, state and spins are far more
+    // than the caches hold between steps: non-temporal loads
     const g_u32 *src = (const g_u32 *)tl.E + beg;
     const int32_t last = max(er.cnt - 1, 0);
 #pragma unroll
-    for (int j = 0; j < I8S_EPL; ++j) er.e[j] = src[min(lane + 64 * j, last)];
+    for (int j = 0; j < I8S_EPL; ++j)
+        er.e[j] = __builtin_nontemporal_load(&src[min(lane + 64 * j, last)]);
 }
 
 // Clears row group gg's 2 KiB of the stage and writes its entries there.  An entry's
